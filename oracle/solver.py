@@ -1,0 +1,98 @@
+"""Matrix-free PCG and one LM step for the oracle (test infrastructure only).
+
+Written in the order of Alg. 1 (one LM step with a matrix-free preconditioned
+CG solver) of arXiv 2504.12905, in FP64 numpy over the C++ oracle's operator
+products. Readings of the paper that this code fixes:
+
+* sign: with r = I_hat - I (eq. 7) and (J^T J + lam I) dbeta = J^T r (eq. 8),
+  the descent update is beta - eta * x (Alg. 1 writes "+"); see ``lm_step``;
+* "for i = 0 to PCG_iters" runs exactly ``iters`` operator products;
+* the loop stops early (keeping x) if p^T A p <= 0 or r^T z has collapsed;
+* learning rate (Sec. 4.5, Supp. D): eta = 0.05 for the first 10 LM
+  iterations, afterwards min(0.2, 1 / max |x_dc|) with x_dc the DC colour
+  coefficients of the solution (so the largest colour change is at most 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import Oracle
+from .sampling import sample_uniform
+
+
+def pcg(apply_A, b: np.ndarray, m_inv: np.ndarray, iters: int):
+    """Alg. 1, PCG part: solve A x = b from x0 = 0 with Jacobi preconditioner m_inv.
+
+    Returns (x, residual norms ||r_i|| for i = 0..done, number of products)."""
+    r = b.copy()                       # r0 = J^T r   (the right-hand side)
+    z = m_inv * r                      # z0 = M^-1 r0
+    p = z.copy()                       # p0 = z0
+    x = np.zeros_like(b)               # x0 = 0
+    rz = float(r @ z)
+    rz0 = rz
+    norms = [float(np.linalg.norm(r))]
+    done = 0
+    for _ in range(iters):
+        u = apply_A(p)                 # u = (J^T J + lam I) p
+        done += 1
+        pu = float(p @ u)
+        if not (pu > 0.0) or not (rz > 1e-30 * rz0):
+            break
+        alpha = rz / pu
+        x = x + alpha * p
+        r = r - alpha * u
+        z = m_inv * r
+        rz_new = float(r @ z)
+        beta = rz_new / rz
+        p = z + beta * p
+        rz = rz_new
+        norms.append(float(np.linalg.norm(r)))
+    return x, np.array(norms), done
+
+
+def learning_rate(x: np.ndarray, n: int, it: int, cap: float = 0.2, warm: float = 0.05,
+                  warm_iters: int = 10) -> float:
+    """Sec. 4.5 / Supp. D: bound the largest DC-colour change of eta*x by 1."""
+    if it < warm_iters:
+        return warm
+    m = float(np.max(np.abs(x[11 * n: 14 * n]))) if n else 0.0
+    return cap if m == 0.0 else min(cap, 1.0 / m)
+
+
+def gather_targets(targets: np.ndarray, orc: Oracle) -> np.ndarray:
+    """Target colours [S, 3] at the oracle's sampled pixels; targets is [V, H, W, 3]."""
+    v, x, y = orc.pixel_coords()
+    return targets[v, y, x].astype(np.float64)
+
+
+def lm_step(n, sh_degree, beta, cams_all, targets_all, view_ids, width, height, k, seed, it, lam,
+            cg_iters, d=None, opts=None):
+    """Alg. 1 for one LM iteration. Returns (beta_next float32, info dict)."""
+    view_ids = np.asarray(view_ids, dtype=np.int64)
+    cams = cams_all[view_ids]                                   # getBatch (view sampling)
+    orc = Oracle(n, sh_degree, beta, cams, width, height, opts)  # splatting: project + bin
+    if k >= 256:
+        orc.set_samples(256)
+    else:
+        pix, w = sample_uniform(seed, it, view_ids, orc.T, k)
+        orc.set_samples(k, pix, w)
+    fwd = orc.render()
+    res = fwd["C"] - gather_targets(targets_all[view_ids], orc)  # r = I_hat - I  (eq. 7)
+    wts = orc.weights()
+    b = orc.vjp(wts[:, None] * res)                             # r0 = J^T W r
+    D = orc.diag()                                              # diag(J^T W J)
+    dd = np.ones(orc.P) if d is None else np.asarray(d, np.float64)
+    m_inv = 1.0 / (D + lam * dd)                                # M^-1 = 1 / diag(J^T W J + lam d)
+    x, norms, done = pcg(lambda p: orc.gn(p, lam, dd), b, m_inv, cg_iters)
+    eta = learning_rate(x, n, it)
+    beta_next = (beta.astype(np.float64) - eta * x).astype(np.float32)
+    info = dict(loss_sampled=float(np.sum(wts[:, None] * res ** 2)), b=b, diag=D, x=x, eta=eta,
+                cg_norms=norms, cg_done=done, residual=res, weights=wts)
+    return beta_next, info
+
+
+def full_loss(n, sh_degree, beta, cams, targets, width, height, opts=None) -> float:
+    """Sum of squared residuals over every pixel and channel of the given views (eq. 6, unnormalised)."""
+    orc = Oracle(n, sh_degree, beta, cams, width, height, opts)
+    img = orc.render_image()
+    return float(np.sum((img - targets) ** 2))

@@ -1,0 +1,122 @@
+"""Pins of the oracle's alpha-blended render (eq. 3, Alg. 2) by closed forms and brute force."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2504_12905_amd import synth
+from test_oracle_geometry import axis_camera, one_gaussian_scene
+
+
+def test_single_gaussian_closed_form():
+    f, W = 40.0, 32
+    sigma, o_logit = 0.1, 0.7
+    rgb = np.array([0.9, 0.3, 0.1])
+    n, beta = one_gaussian_scene([0, 0, 0], [math.log(sigma)] * 3, [1, 0, 0, 0], o_logit, rgb)
+    orc = Oracle(n, 0, beta, axis_camera(f, W, W), W, W)
+    img = orc.render_image()[0]
+    s2 = (f * sigma / 3.0) ** 2 + 0.3
+    r = math.ceil(3 * math.sqrt(s2))
+    op = 1 / (1 + math.exp(-o_logit))
+    ys, xs = np.mgrid[0:W, 0:W]
+    d2 = (xs + 0.5 - W / 2) ** 2 + (ys + 0.5 - W / 2) ** 2
+    a = np.minimum(op * np.exp(-0.5 * d2 / s2), 0.99)
+    a[a < 1 / 255] = 0.0
+    # tiles outside the 3-sigma rectangle are not rendered
+    tx0, tx1 = math.floor((W / 2 - r) / 16), math.floor((W / 2 + r) / 16)
+    in_rect = ((xs // 16 >= tx0) & (xs // 16 <= tx1) & (ys // 16 >= tx0) & (ys // 16 <= tx1))
+    ref = (a * in_rect)[..., None] * rgb
+    np.testing.assert_allclose(img, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_two_gaussians_over_operator():
+    f, W = 40.0, 32
+    rgb1, rgb2 = np.array([1.0, 0.0, 0.2]), np.array([0.1, 0.8, 0.3])
+    n, beta = one_gaussian_scene([[0, 0, 0], [0.01, -0.02, 0.5]], [math.log(0.1)] * 3, [1, 0, 0, 0],
+                                 0.3, [0, 0, 0])
+    K = 1
+    sh = beta[synth.seg(n, "sh", 0)].reshape(K, 3, n)
+    sh[0, :, 0] = (rgb1 - 0.5) / 0.28209479177387814
+    sh[0, :, 1] = (rgb2 - 0.5) / 0.28209479177387814
+    beta[synth.seg(n, "sh", 0)] = sh.reshape(-1)
+    orc = Oracle(n, 0, beta, axis_camera(f, W, W), W, W)
+    img = orc.render_image()[0]
+    pr = orc.projection()["rec"][0]
+
+    def alpha(rec, x, y):
+        dx, dy = rec[0] - x, rec[1] - y
+        s = -0.5 * (rec[2] * dx * dx + rec[4] * dy * dy) - rec[3] * dx * dy
+        a = min(0.99, rec[5] * math.exp(s))
+        return 0.0 if a < 1 / 255 else a
+
+    for (x, y) in [(15, 15), (16, 17), (13, 18), (18, 12)]:
+        a1, a2 = alpha(pr[0], x + 0.5, y + 0.5), alpha(pr[1], x + 0.5, y + 0.5)
+        ref = rgb1 * a1 + rgb2 * a2 * (1 - a1)
+        np.testing.assert_allclose(img[y, x], ref, rtol=1e-12)
+
+
+def test_transmittance_stop_three_layers():
+    """Opacity 0.95 centred on a pixel: T 1 -> 0.05 -> 0.0025 -> 1.25e-4; a fourth
+    layer would take T to 6.25e-6 < 1e-4, so exactly three layers are blended."""
+    f, W = 32.0, 32
+    depths = [3.0, 3.1, 3.2, 3.3]
+    # camera at z = -3: a mean at world z has depth z + 3; centre on pixel (16, 16)
+    means = [[0.5 * (d) / f, 0.5 * (d) / f, d - 3.0] for d in depths]
+    n, beta = one_gaussian_scene(means, [math.log(0.2)] * 3, [1, 0, 0, 0], math.log(19.0), [0.8, 0.6, 0.4])
+    orc = Oracle(n, 0, beta, axis_camera(f, W, W), W, W)
+    orc.set_samples(256)
+    out = orc.render()
+    v, x, y = orc.pixel_coords()
+    i = int(np.where((x == 16) & (y == 16))[0][0])
+    assert out["n_contrib"][i] == 3
+    assert out["T"][i] == pytest.approx(0.05 ** 3, rel=1e-9)
+    np.testing.assert_allclose(out["C"][i], np.array([0.8, 0.6, 0.4]) * (1 - 0.05 ** 3), rtol=1e-9)
+
+
+def brute_force_pixel(rec, order, x, y):
+    T, Cc = 1.0, np.zeros(3)
+    for g in order:
+        r = rec[g]
+        dx, dy = r[0] - x, r[1] - y
+        s = -0.5 * (r[2] * dx * dx + r[4] * dy * dy) - r[3] * dx * dy
+        if s > 0:
+            continue
+        a = min(0.99, r[5] * math.exp(s))
+        if a < 1 / 255:
+            continue
+        if T * (1 - a) < 1e-4:
+            break
+        Cc += r[6:9] * a * T
+        T *= 1 - a
+    return Cc, T
+
+
+def test_tile_render_matches_brute_force_pixels():
+    w = synth.config0()
+    orc = Oracle(w.n, 0, w.beta_gt, w.cams, w.width, w.height)
+    pr = orc.projection()
+    img = orc.render_image()
+    rng = np.random.default_rng(3)
+    for _ in range(60):
+        v, x, y = rng.integers(0, orc.V), rng.integers(0, w.width), rng.integers(0, w.height)
+        tx, ty = x // 16, y // 16
+        members = [g for g in range(orc.n) if pr["visible"][v, g]
+                   and pr["rect"][v, g, 0] <= tx < pr["rect"][v, g, 2]
+                   and pr["rect"][v, g, 1] <= ty < pr["rect"][v, g, 3]]
+        members.sort(key=lambda g: (pr["depth"][v, g], g))
+        ref, _ = brute_force_pixel(pr["rec"][v], members, x + 0.5, y + 0.5)
+        np.testing.assert_allclose(img[v, y, x], ref, rtol=1e-12, atol=1e-15)
+
+
+def test_samples_select_pixels():
+    w = synth.config0()
+    orc = Oracle(w.n, 0, w.beta_gt, w.cams, w.width, w.height)
+    full = orc.render_image()
+    rng = np.random.default_rng(0)
+    k = 13
+    pix = np.stack([np.sort(rng.choice(256, k, replace=False)) for _ in range(orc.V * orc.T)])
+    orc.set_samples(k, pix, np.full(pix.shape, 256 / k, np.float32))
+    out = orc.render()
+    v, x, y = orc.pixel_coords()
+    np.testing.assert_array_equal(out["C"], full[v, y, x])
