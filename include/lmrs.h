@@ -1,0 +1,221 @@
+/*
+ * lmrs.h -- C ABI of the MI355X (gfx950) library for the Gauss-Newton hot path
+ * of matrix-free Levenberg-Marquardt with residual sampling for 3D Gaussian
+ * Splatting (Pehlivan et al., "Matrix-free Second-order Optimization of
+ * Gaussian Splats with Residual Sampling", arXiv 2504.12905).
+ *
+ * The operator at the centre is the sampled, damped Gauss-Newton matrix
+ *     A = J^T W J + lambda diag(d)                      (Sec. 4.1 eq. 8, Sec. 4.4 eq. 14)
+ * where J is the Jacobian of the residuals r = I_hat - I (eq. 7) of the
+ * alpha-blended render (Sec. 3 eq. 3) with respect to all Gaussian parameters,
+ * evaluated at the sampled pixels, and W = diag(w) repeats each sampled
+ * pixel's importance weight over its 3 colour channels (eq. 12-14).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Memory.  Every pointer marked "device" is HBM owned by the caller; the
+ *   library never allocates, frees or retains device memory, and keeps no
+ *   state between calls. Host structs are read during the call only.
+ * Streams. `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   Work is enqueued and the call returns, except lmrs_bin_tiles and
+ *   lmrs_lm_step, which wait for the tile-instance count (see there).
+ * Errors.  Arguments are checked on the host before anything is enqueued; a
+ *   failed check returns a negative status and enqueues nothing.
+ *   lmrs_last_error() gives a message for the calling thread. A fault inside
+ *   a kernel surfaces as LMRS_EHIP from a later call or stream sync.
+ * Outputs are overwritten, never accumulated.
+ *
+ * Parameter vector beta (float32, P = n (11 + 3K), K = (sh_degree+1)^2),
+ * component-major segments (all Gaussians' first component, then the next):
+ *     [0n,3n) mean xyz | [3n,6n) log-scale xyz | [6n,10n) quaternion wxyz
+ *     (normalised inside) | [10n,11n) opacity logit | [11n + (3k+c) n] SH
+ *     coefficient k of colour channel c.
+ * These are the per-Gaussian opacity, colour, mean, scale and rotation of
+ * Sec. 4.1; colour is 0.5 + sum_k Y_k(dir) f_k with the real SH basis of
+ * degree <= 3 (degree 0 is the paper's Lambertian setting, Sec. 3).
+ *
+ * Cameras: lmrs_camera rows, world-to-camera R (row-major) and t, pinhole
+ * fx fy cx cy; x right, y down, z forward; pixel (i, j) has centre
+ * (i + 0.5, j + 0.5). Images are split in 16x16 tiles (Supp. A); width and
+ * height must be multiples of 16. T = (width/16)(height/16) tiles per view,
+ * tile id = ty * (width/16) + tx, pixel-in-tile index = 16 * (y%16) + (x%16).
+ *
+ * Sampled pixels (Sec. 4.4, stratified per tile): k per tile, sample index
+ * i = (v * T + t) * k + j for view v, tile t, slot j; S = V T k.
+ */
+#ifndef LMRS_H
+#define LMRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lmrs_status;
+#define LMRS_OK 0
+#define LMRS_EINVAL (-1)       /* bad argument (message in lmrs_last_error) */
+#define LMRS_ECAPACITY (-2)    /* tile-instance buffer too small; count written */
+#define LMRS_EWORKSPACE (-3)   /* workspace smaller than lmrs_workspace_bytes */
+#define LMRS_EHIP (-4)         /* HIP runtime error */
+
+/* Floats per screen record: u v A B C opacity r g b | depth radius 0 (Sec. 3 eq. 3). */
+#define LMRS_REC 12
+
+typedef struct lmrs_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+} lmrs_camera;
+
+/* Rasteriser constants. The paper follows 3DGS for these (Supp. A) and states
+ * none; the defaults used throughout are alpha_min 1/255, alpha_max 0.99,
+ * t_min 1e-4, lowpass 0.3 px^2, znear 0.2, cutoff 3 sigmas, black background. */
+typedef struct lmrs_render_opts {
+  float alpha_min;  /* a Gaussian with alpha below this is skipped            */
+  float alpha_max;  /* alpha is capped here; a capped alpha has no derivative  */
+  float t_min;      /* blending stops before the Gaussian taking T below this  */
+  float lowpass;    /* added to the 2-D covariance diagonal (px^2)             */
+  float znear;      /* Gaussians with camera depth <= znear are culled          */
+  float cutoff;     /* footprint radius = ceil(cutoff * sqrt(lambda_max))       */
+  float bg[3];      /* background colour added with the final transmittance    */
+} lmrs_render_opts;
+
+/* One view batch at one parameter vector. All pointers are device memory
+ * owned by the caller; which call reads or writes each field is listed. */
+typedef struct lmrs_frame {
+  int32_t n;              /* Gaussians                                          */
+  int32_t sh_degree;      /* 0..3                                               */
+  int32_t n_views;        /* V, views in this batch                            */
+  int32_t width, height;  /* pixels per view, multiples of 16                   */
+  int32_t k;              /* samples per tile, 1..256                           */
+  const float* beta;      /* [P] parameters                     (read by all)   */
+  const lmrs_camera* cams;/* [>= max view id + 1] cameras       (project, lm)   */
+  const int32_t* view_ids;/* [V] camera index of batch view v, or NULL = v      */
+  float* rec;             /* [V][n][LMRS_REC] screen records    (project: out)  */
+  int32_t* rect;          /* [V][n][4] tile rect x0 y0 x1 y1, end exclusive;
+                             empty (x0 == x1) when culled        (project: out)  */
+  int64_t* tile_start;    /* [V*T + 1] list offsets into ids    (bin: out)      */
+  int32_t* ids;           /* [capacity] Gaussian ids per tile    (bin: out)      */
+  int64_t capacity;       /* entries available in ids                            */
+  int64_t* n_instances;   /* [1] total list entries             (bin: out)      */
+  uint8_t* pix;           /* [V][T][k] pixel-in-tile indices, or NULL = all 256
+                             pixels in order (k must be 256)    (lm: out)       */
+  float* w;               /* [V][T][k] weights, or NULL = 1      (lm: out)       */
+  float* color;           /* [S][3] rendered colour             (render: out)   */
+  float* trans;           /* [S] final transmittance            (render: out)   */
+  int32_t* last;          /* [S] list position of the last blended Gaussian,
+                             -1 if none                          (render: out)   */
+} lmrs_frame;
+
+/* Operation codes for lmrs_workspace_bytes. */
+#define LMRS_OP_BIN 1
+#define LMRS_OP_JVP 2
+#define LMRS_OP_VJP 3
+#define LMRS_OP_GN 4
+#define LMRS_OP_DIAG 5
+#define LMRS_OP_PCG 6
+#define LMRS_OP_LM 7
+
+/* Learning-rate and solver settings of one LM step (Alg. 1; Sec. 4.5; Supp. D). */
+typedef struct lmrs_lm_params {
+  int32_t iter;         /* LM iteration index (schedule, sampler counter)      */
+  int32_t cg_iters;     /* GN products in the PCG loop                          */
+  float lambda;         /* fixed damping (Sec. 4.1)                             */
+  float eta_cap;        /* learning-rate cap (0.2)                              */
+  float eta_warm;       /* fixed learning rate of the first iterations (0.05)  */
+  int32_t warm_iters;   /* number of such iterations (10)                       */
+  uint64_t seed;        /* residual-sampler seed                                */
+} lmrs_lm_params;
+
+/* Slots of the device report written by lmrs_pcg / lmrs_lm_step. */
+#define LMRS_REPORT_FLOATS 8
+#define LMRS_REP_LOSS 0        /* sampled weighted loss sum_i w_i |r_i|^2        */
+#define LMRS_REP_ETA 1         /* learning rate applied                           */
+#define LMRS_REP_XDC_MAX 2     /* max |x| over the DC colour coefficients         */
+#define LMRS_REP_CG_DONE 3     /* PCG iterations that updated x                  */
+#define LMRS_REP_R0 4          /* ||r_0|| = ||b||                                 */
+#define LMRS_REP_RN 5          /* ||r|| after the last iteration                  */
+#define LMRS_REP_BX 6          /* b^T x (> 0 for a descent step)                  */
+#define LMRS_REP_INST 7        /* tile-list entries of this step                  */
+
+const char* lmrs_status_str(lmrs_status s);
+const char* lmrs_last_error(void);
+
+/* Scratch bytes that call `op` needs for frame `f` (uses n, sh_degree,
+ * n_views, width, height, k and capacity). Pass a buffer of at least this
+ * size as (ws, ws_bytes); its contents need not be initialised. */
+size_t lmrs_workspace_bytes(int32_t op, const lmrs_frame* f);
+
+/* a1. Projection (Sec. 3 eq. 1-3, EWA splatting): for every batch view v and
+ * Gaussian g, rec[v][g] = (u, v, conic A B C, opacity sigmoid(logit),
+ * rgb = 0.5 + sum_k Y_k(dir) f_k, FP32 depth key, radius) and rect[v][g].
+ * Reads beta, cams, view_ids; writes rec, rect. */
+lmrs_status lmrs_project(const lmrs_frame* f, const lmrs_render_opts* o, void* stream);
+
+/* a2. Tile binning and depth sort (Sec. 3: projected Gaussians are sorted by
+ * depth; Supp. A: 16x16 tiles). For each view and tile, ids of the Gaussians
+ * whose rect holds the tile, ascending depth key, ties by ascending id.
+ * Reads rect and rec; writes n_instances, tile_start and ids. Waits for the
+ * instance count; if it exceeds capacity returns LMRS_ECAPACITY with
+ * *n_instances (device) holding the count needed and ids untouched. */
+lmrs_status lmrs_bin_tiles(const lmrs_frame* f, void* ws, size_t ws_bytes, void* stream);
+
+/* a3. Forward render of the sampled pixels (Sec. 3 eq. 3; Supp. A Alg. 2):
+ * front-to-back blending of each pixel's tile list. Writes color (with
+ * background), trans (final T) and last. */
+lmrs_status lmrs_render(const lmrs_frame* f, const lmrs_render_opts* o, void* stream);
+
+/* J p at every sampled pixel (Sec. 4.2; Supp. A "Jv kernel", Alg. 3):
+ * forward-mode derivative of the rendered colour along p, with the discrete
+ * decisions of lmrs_render (lists, skips, last) held fixed.
+ * p: device [P]; jp: device [S][3]. Needs rec, rect, lists and render outputs. */
+lmrs_status lmrs_jvp(const lmrs_frame* f, const lmrs_render_opts* o, const float* p, float* jp,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* J^T u (Supp. A "J^T v kernel"): u device [S][3] (no weights applied),
+ * out device [P]. Same state as lmrs_jvp. */
+lmrs_status lmrs_vjp(const lmrs_frame* f, const lmrs_render_opts* o, const float* u, float* out,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* a6. Gauss-Newton product out = J^T W J p + lambda d.p (Alg. 1 line "u =
+ * (J^T J + lambda I) p"; eq. 8, eq. 14), W from f->w. d: device [P] or NULL
+ * (all ones, the paper's lambda I). p, out: device [P], must not alias. */
+lmrs_status lmrs_gn_product(const lmrs_frame* f, const lmrs_render_opts* o, const float* p,
+                            float lambda, const float* d, float* out, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* a5. diag(J^T W J) (Alg. 1 preconditioner; Supp. A "Diag(J^T J) kernel"),
+ * exact: per (view, Gaussian) the weighted Gram matrix of the screen-record
+ * derivatives, then contracted with the record Jacobian. out: device [P]. */
+lmrs_status lmrs_gn_diag(const lmrs_frame* f, const lmrs_render_opts* o, float* out, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* a5 + a7. Matrix-free PCG of Alg. 1 from x0 = 0: Jacobi preconditioner
+ * 1 / (diag(J^T W J) + lambda d), exactly `iters` GN products; x stops
+ * changing if p^T A p <= 0 or r^T z collapses. b, x: device [P].
+ * report: device [LMRS_REPORT_FLOATS] or NULL (slots CG_DONE, R0, RN, BX). */
+lmrs_status lmrs_pcg(const lmrs_frame* f, const lmrs_render_opts* o, const float* b, float lambda,
+                     const float* d, int32_t iters, float* x, float* report, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* a1-a8. One LM iteration of Alg. 1 on the batch views f->view_ids:
+ * project, bin, sample k pixels per tile (Sec. 4.4; uniform without
+ * replacement by Philox4x32-10 keys, weight 256/k; k = 256 takes every
+ * pixel with weight 1), render, residuals r = C - I against targets
+ * (device [*][height][width][3], indexed by camera id), b = J^T W r,
+ * Jacobi-PCG, learning rate (Sec. 4.5: eta_warm for iter < warm_iters, else
+ * min(eta_cap, 1 / max |x_dc|)) and the descent update beta <- beta - eta x.
+ * f->beta must equal beta; f->pix and f->w receive the samples. Waits for the
+ * instance count like lmrs_bin_tiles (LMRS_ECAPACITY leaves beta unchanged).
+ * report: device [LMRS_REPORT_FLOATS] or NULL. */
+lmrs_status lmrs_lm_step(lmrs_frame* f, float* beta, const float* targets, const float* d,
+                         const lmrs_lm_params* prm, const lmrs_render_opts* o, float* report,
+                         void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMRS_H */

@@ -1,0 +1,401 @@
+// C ABI of liblmrs (see include/lmrs.h for the contract of every call).
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace lmrs {
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lmrs_status fail(lmrs_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+lmrs_status hip_check(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LMRS_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return LMRS_OK;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr int kRedDoubles = 2 * kRedBlocks + 64;
+
+// Bump allocator over the caller's workspace; the same sequence of take()
+// calls sizes the workspace (base == nullptr) and carves it.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+struct Scratch {
+  float* tan = nullptr;
+  float* grad2d = nullptr;
+  float* gram = nullptr;
+  float* diag = nullptr;
+  float *r = nullptr, *z = nullptr, *p = nullptr, *u = nullptr, *minv = nullptr;
+  float* b = nullptr;
+  float* x = nullptr;
+  float* wr = nullptr;
+  double* sc = nullptr;
+  double* red = nullptr;
+  BinScratch bin{};
+};
+
+// Workspace layout of each operation.
+Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
+  Scratch s;
+  const int64_t P = (int64_t)d.n * d.pg;
+  const int64_t VN = (int64_t)d.V * d.n;
+  const bool need_bin = op == LMRS_OP_BIN || op == LMRS_OP_LM;
+  const bool need_tan = op == LMRS_OP_JVP || op == LMRS_OP_GN || op == LMRS_OP_PCG || op == LMRS_OP_LM;
+  const bool need_grad = op == LMRS_OP_VJP || op == LMRS_OP_GN || op == LMRS_OP_PCG || op == LMRS_OP_LM;
+  const bool need_gram = op == LMRS_OP_DIAG || op == LMRS_OP_PCG || op == LMRS_OP_LM;
+  const bool need_pcg = op == LMRS_OP_PCG || op == LMRS_OP_LM;
+  if (need_bin) {
+    s.bin.counts = c.take<int32_t>((size_t)d.V * d.T);
+    s.bin.keys = c.take<uint64_t>((size_t)capacity);
+    s.bin.tmp = c.take<uint64_t>((size_t)capacity);
+  }
+  if (need_tan) s.tan = c.take<float>((size_t)VN * LMRS_REC);
+  if (need_grad) s.grad2d = c.take<float>((size_t)VN * 9);
+  if (need_gram) s.gram = c.take<float>((size_t)VN * kGram);
+  if (need_pcg) {
+    s.diag = c.take<float>(P);
+    s.r = c.take<float>(P);
+    s.z = c.take<float>(P);
+    s.p = c.take<float>(P);
+    s.u = c.take<float>(P);
+    s.minv = c.take<float>(P);
+    s.sc = c.take<double>(16);
+  }
+  if (op == LMRS_OP_LM) {
+    s.b = c.take<float>(P);
+    s.x = c.take<float>(P);
+    s.wr = c.take<float>((size_t)d.S * 3);
+  }
+  s.red = c.take<double>(kRedDoubles);
+  return s;
+}
+
+lmrs_status check_frame(const lmrs_frame* f, bool need_samples_k = true) {
+  if (!f) return fail(LMRS_EINVAL, "frame is NULL");
+  if (f->n <= 0) return fail(LMRS_EINVAL, "n = %d must be positive", f->n);
+  if (f->sh_degree < 0 || f->sh_degree > 3) return fail(LMRS_EINVAL, "sh_degree = %d not in 0..3", f->sh_degree);
+  if (f->n_views <= 0) return fail(LMRS_EINVAL, "n_views = %d must be positive", f->n_views);
+  if (f->width <= 0 || f->height <= 0 || f->width % kTile || f->height % kTile)
+    return fail(LMRS_EINVAL, "image %dx%d must be positive multiples of 16", f->width, f->height);
+  if (need_samples_k) {
+    if (f->k < 1 || f->k > 256) return fail(LMRS_EINVAL, "k = %d not in 1..256", f->k);
+    if (!f->pix && f->k != 256) return fail(LMRS_EINVAL, "pix is NULL but k = %d != 256", f->k);
+  }
+  if (!f->beta) return fail(LMRS_EINVAL, "beta is NULL");
+  const int64_t tiles = (int64_t)f->n_views * (f->width / kTile) * (f->height / kTile);
+  if (tiles > 0x7fffffffLL) return fail(LMRS_EINVAL, "too many tiles");
+  return LMRS_OK;
+}
+
+lmrs_status need(const void* p, const char* name) {
+  return p ? LMRS_OK : fail(LMRS_EINVAL, "%s is NULL", name);
+}
+
+lmrs_status check_ws(int op, const lmrs_frame* f, void* ws, size_t ws_bytes) {
+  const size_t req = lmrs_workspace_bytes(op, f);
+  if (ws_bytes < req || (!ws && req > 0))
+    return fail(LMRS_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, req);
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+    return fail(LMRS_EWORKSPACE, "workspace must be 256-byte aligned");
+  return LMRS_OK;
+}
+
+lmrs_status check_render_state(const lmrs_frame* f) {
+  lmrs_status st;
+  if ((st = need(f->rec, "rec")) || (st = need(f->rect, "rect")) || (st = need(f->tile_start, "tile_start")) ||
+      (st = need(f->ids, "ids")) || (st = need(f->cams, "cams")))
+    return st;
+  return LMRS_OK;
+}
+
+lmrs_status check_deriv_state(const lmrs_frame* f) {
+  lmrs_status st = check_render_state(f);
+  if (st) return st;
+  if ((st = need(f->trans, "trans")) || (st = need(f->last, "last"))) return st;
+  return LMRS_OK;
+}
+
+#define LMRS_TRY(x)              \
+  do {                           \
+    const lmrs_status _s = (x);  \
+    if (_s != LMRS_OK) return _s; \
+  } while (0)
+
+// J^T W J p + lambda d p into out (tangent, fused splat, chain).
+void gn_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* p,
+                 float lambda, const float* dvec, float* out, const Scratch& s, hipStream_t st) {
+  launch_tangent(f, d, o, p, s.tan, st);
+  launch_fill(s.grad2d, (int64_t)d.V * d.n * 9, 0.f, st);
+  launch_deriv(3, f, d, o, s.tan, nullptr, nullptr, s.grad2d, st);
+  launch_chain_vjp(f, d, o, s.grad2d, p, lambda, dvec, out, st);
+}
+
+void vjp_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* u,
+                  float* out, const Scratch& s, hipStream_t st) {
+  launch_fill(s.grad2d, (int64_t)d.V * d.n * 9, 0.f, st);
+  launch_deriv(2, f, d, o, nullptr, u, nullptr, s.grad2d, st);
+  launch_chain_vjp(f, d, o, s.grad2d, nullptr, 0.f, nullptr, out, st);
+}
+
+void diag_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* out,
+                   const Scratch& s, hipStream_t st) {
+  launch_fill(s.gram, (int64_t)d.V * d.n * kGram, 0.f, st);
+  launch_gram(f, d, o, s.gram, st);
+  launch_chain_diag(f, d, o, s.gram, out, st);
+}
+
+void pcg_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* b,
+                  float lambda, const float* dvec, int iters, float* x, float* report, const Scratch& s,
+                  hipStream_t st) {
+  const int64_t P = (int64_t)d.n * d.pg;
+  diag_sequence(f, d, o, s.diag, s, st);
+  PcgState ps{x, s.r, s.z, s.p, s.u, s.minv, s.sc, s.red};
+  launch_pcg_init(b, s.diag, lambda, dvec, P, ps, st);
+  for (int it = 0; it < iters; ++it) {
+    gn_sequence(f, d, o, s.p, lambda, dvec, s.u, s, st);
+    launch_pcg_update(P, ps, st);
+    launch_pcg_direction(P, ps, st);
+  }
+  if (report) launch_pcg_report(b, P, ps, report, st);
+}
+
+// count, wait for the total, then emit and sort.
+lmrs_status bin_sequence(const lmrs_frame* f, const FrameDims& d, const Scratch& s, hipStream_t st,
+                         int64_t* total_out = nullptr) {
+  launch_bin_count(f, d, s.bin, st);
+  int64_t total = 0;
+  if (hipMemcpyAsync(&total, f->n_instances, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return hip_check("bin count");
+  LMRS_TRY(hip_check("bin count"));
+  if (total > f->capacity)
+    return fail(LMRS_ECAPACITY, "%lld tile-list entries needed, capacity %lld", (long long)total,
+                (long long)f->capacity);
+  if (total_out) *total_out = total;
+  launch_bin_emit_sort(f, d, s.bin, st);
+  return hip_check("bin sort");
+}
+
+}  // namespace
+
+FrameDims dims_of(const lmrs_frame* f) {
+  FrameDims d;
+  d.n = f->n;
+  d.deg = f->sh_degree;
+  d.pg = 11 + 3 * (f->sh_degree + 1) * (f->sh_degree + 1);
+  d.V = f->n_views;
+  d.W = f->width;
+  d.H = f->height;
+  d.TX = f->width / kTile;
+  d.TY = f->height / kTile;
+  d.T = d.TX * d.TY;
+  d.k = f->k;
+  d.S = (int64_t)d.V * d.T * d.k;
+  return d;
+}
+
+}  // namespace lmrs
+
+using namespace lmrs;
+
+extern "C" {
+
+const char* lmrs_status_str(lmrs_status s) {
+  switch (s) {
+    case LMRS_OK: return "ok";
+    case LMRS_EINVAL: return "invalid argument";
+    case LMRS_ECAPACITY: return "tile-list capacity exceeded";
+    case LMRS_EWORKSPACE: return "workspace too small";
+    case LMRS_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* lmrs_last_error(void) { return g_err; }
+
+size_t lmrs_workspace_bytes(int32_t op, const lmrs_frame* f) {
+  if (!f || f->n <= 0 || f->n_views <= 0 || f->width <= 0 || f->height <= 0) return 0;
+  FrameDims d = dims_of(f);
+  if (d.k < 1) d.k = 1;
+  d.S = (int64_t)d.V * d.T * d.k;
+  Carver c(nullptr);
+  carve(op, d, f->capacity > 0 ? f->capacity : 0, c);
+  return c.used;
+}
+
+lmrs_status lmrs_project(const lmrs_frame* f, const lmrs_render_opts* o, void* stream) {
+  LMRS_TRY(check_frame(f, false));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(need(f->cams, "cams"));
+  LMRS_TRY(need(f->rec, "rec"));
+  LMRS_TRY(need(f->rect, "rect"));
+  launch_project(f, dims_of(f), *o, (hipStream_t)stream);
+  return hip_check("lmrs_project");
+}
+
+lmrs_status lmrs_bin_tiles(const lmrs_frame* f, void* ws, size_t ws_bytes, void* stream) {
+  LMRS_TRY(check_frame(f, false));
+  LMRS_TRY(need(f->rec, "rec"));
+  LMRS_TRY(need(f->rect, "rect"));
+  LMRS_TRY(need(f->tile_start, "tile_start"));
+  LMRS_TRY(need(f->n_instances, "n_instances"));
+  if (f->capacity > 0) LMRS_TRY(need(f->ids, "ids"));
+  LMRS_TRY(check_ws(LMRS_OP_BIN, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_BIN, d, f->capacity, c);
+  return bin_sequence(f, d, s, (hipStream_t)stream);
+}
+
+lmrs_status lmrs_render(const lmrs_frame* f, const lmrs_render_opts* o, void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_render_state(f));
+  LMRS_TRY(need(f->color, "color"));
+  LMRS_TRY(need(f->trans, "trans"));
+  LMRS_TRY(need(f->last, "last"));
+  launch_render(f, dims_of(f), *o, (hipStream_t)stream);
+  return hip_check("lmrs_render");
+}
+
+lmrs_status lmrs_jvp(const lmrs_frame* f, const lmrs_render_opts* o, const float* p, float* jp, void* ws,
+                     size_t ws_bytes, void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_deriv_state(f));
+  LMRS_TRY(need(p, "p"));
+  LMRS_TRY(need(jp, "jp"));
+  LMRS_TRY(check_ws(LMRS_OP_JVP, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_JVP, d, f->capacity, c);
+  hipStream_t st = (hipStream_t)stream;
+  launch_tangent(f, d, *o, p, s.tan, st);
+  launch_deriv(1, f, d, *o, s.tan, nullptr, jp, nullptr, st);
+  return hip_check("lmrs_jvp");
+}
+
+lmrs_status lmrs_vjp(const lmrs_frame* f, const lmrs_render_opts* o, const float* u, float* out, void* ws,
+                     size_t ws_bytes, void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_deriv_state(f));
+  LMRS_TRY(need(u, "u"));
+  LMRS_TRY(need(out, "out"));
+  LMRS_TRY(check_ws(LMRS_OP_VJP, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_VJP, d, f->capacity, c);
+  vjp_sequence(f, d, *o, u, out, s, (hipStream_t)stream);
+  return hip_check("lmrs_vjp");
+}
+
+lmrs_status lmrs_gn_product(const lmrs_frame* f, const lmrs_render_opts* o, const float* p, float lambda,
+                            const float* dvec, float* out, void* ws, size_t ws_bytes, void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_deriv_state(f));
+  LMRS_TRY(need(p, "p"));
+  LMRS_TRY(need(out, "out"));
+  if (p == out) return fail(LMRS_EINVAL, "p and out must not alias");
+  LMRS_TRY(check_ws(LMRS_OP_GN, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_GN, d, f->capacity, c);
+  gn_sequence(f, d, *o, p, lambda, dvec, out, s, (hipStream_t)stream);
+  return hip_check("lmrs_gn_product");
+}
+
+lmrs_status lmrs_gn_diag(const lmrs_frame* f, const lmrs_render_opts* o, float* out, void* ws,
+                         size_t ws_bytes, void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_deriv_state(f));
+  LMRS_TRY(need(out, "out"));
+  LMRS_TRY(check_ws(LMRS_OP_DIAG, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_DIAG, d, f->capacity, c);
+  diag_sequence(f, d, *o, out, s, (hipStream_t)stream);
+  return hip_check("lmrs_gn_diag");
+}
+
+lmrs_status lmrs_pcg(const lmrs_frame* f, const lmrs_render_opts* o, const float* b, float lambda,
+                     const float* dvec, int32_t iters, float* x, float* report, void* ws, size_t ws_bytes,
+                     void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_deriv_state(f));
+  LMRS_TRY(need(b, "b"));
+  LMRS_TRY(need(x, "x"));
+  if (iters < 0) return fail(LMRS_EINVAL, "iters = %d must be >= 0", iters);
+  if (!(lambda >= 0.f)) return fail(LMRS_EINVAL, "lambda must be >= 0");
+  LMRS_TRY(check_ws(LMRS_OP_PCG, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_PCG, d, f->capacity, c);
+  pcg_sequence(f, d, *o, b, lambda, dvec, iters, x, report, s, (hipStream_t)stream);
+  return hip_check("lmrs_pcg");
+}
+
+lmrs_status lmrs_lm_step(lmrs_frame* f, float* beta, const float* targets, const float* dvec,
+                         const lmrs_lm_params* prm, const lmrs_render_opts* o, float* report, void* ws,
+                         size_t ws_bytes, void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(need(prm, "params"));
+  LMRS_TRY(need(beta, "beta"));
+  LMRS_TRY(need(targets, "targets"));
+  if (f->beta != beta) return fail(LMRS_EINVAL, "frame->beta must equal beta");
+  LMRS_TRY(check_render_state(f));
+  LMRS_TRY(need(f->n_instances, "n_instances"));
+  LMRS_TRY(need(f->color, "color"));
+  LMRS_TRY(need(f->trans, "trans"));
+  LMRS_TRY(need(f->last, "last"));
+  if (f->k < 256 && (!f->pix || !f->w)) return fail(LMRS_EINVAL, "k < 256 needs pix and w buffers");
+  if (prm->cg_iters < 0) return fail(LMRS_EINVAL, "cg_iters must be >= 0");
+  if (!(prm->lambda >= 0.f)) return fail(LMRS_EINVAL, "lambda must be >= 0");
+  LMRS_TRY(check_ws(LMRS_OP_LM, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_LM, d, f->capacity, c);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t P = (int64_t)d.n * d.pg;
+  launch_project(f, d, *o, st);
+  int64_t total = 0;
+  LMRS_TRY(bin_sequence(f, d, s, st, &total));
+  if (f->pix) launch_sample_uniform(f, d, prm->seed, prm->iter, st);
+  launch_render(f, d, *o, st);
+  launch_residual(f, d, targets, s.wr, s.red, report, st);
+  vjp_sequence(f, d, *o, s.wr, s.b, s, st);
+  pcg_sequence(f, d, *o, s.b, prm->lambda, dvec, prm->cg_iters, s.x, report, s, st);
+  launch_lm_update(beta, s.x, d.n, P, *prm, s.red, report, st);
+  if (report) launch_fill(report + LMRS_REP_INST, 1, (float)total, st);
+  return hip_check("lmrs_lm_step");
+}
+
+}  // extern "C"

@@ -1,0 +1,361 @@
+// Device-side building blocks shared by the lmrs kernels (gfx950, wave64).
+//
+// * dualf: (value, derivative) pairs for forward-mode differentiation, the
+//   dual numbers of the paper's J p kernel (Supp. A, Alg. 3);
+// * the real spherical-harmonic colour basis of degree <= 3;
+// * projection of one Gaussian into one view (Sec. 3, eq. 1-3, EWA splatting):
+//   templated on the scalar so the same code gives the record (float) and its
+//   tangent (dualf), plus the hand-written adjoint used by J^T u;
+// * the per-pixel opacity test shared by every splat kernel;
+// * wave64 scans and reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lmrs.h"
+
+namespace lmrs {
+
+constexpr int kTile = 16;
+constexpr int kWave = 64;
+constexpr int kMaxPg = 11 + 3 * 16;  // parameters per Gaussian at SH degree 3
+constexpr int kGram = 32;            // Gram entries kept per (view, Gaussian)
+
+// ------------------------------------------------------------------ duals
+struct dualf {
+  float v, d;
+  __device__ __forceinline__ dualf() : v(0.f), d(0.f) {}
+  __device__ __forceinline__ dualf(float a) : v(a), d(0.f) {}  // NOLINT
+  __device__ __forceinline__ dualf(float a, float b) : v(a), d(b) {}
+};
+__device__ __forceinline__ dualf operator+(dualf a, dualf b) { return dualf(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ dualf operator-(dualf a, dualf b) { return dualf(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ dualf operator-(dualf a) { return dualf(-a.v, -a.d); }
+__device__ __forceinline__ dualf operator*(dualf a, dualf b) {
+  return dualf(a.v * b.v, a.v * b.d + a.d * b.v);
+}
+__device__ __forceinline__ dualf operator/(dualf a, dualf b) {
+  const float r = 1.f / b.v;
+  const float q = a.v * r;
+  return dualf(q, (a.d - q * b.d) * r);
+}
+__device__ __forceinline__ float tval(float x) { return x; }
+__device__ __forceinline__ float tval(dualf x) { return x.v; }
+__device__ __forceinline__ float texp(float x) { return expf(x); }
+__device__ __forceinline__ dualf texp(dualf x) {
+  const float e = expf(x.v);
+  return dualf(e, e * x.d);
+}
+__device__ __forceinline__ float trsqrt(float x) { return 1.f / sqrtf(x); }
+__device__ __forceinline__ dualf trsqrt(dualf x) {
+  const float r = 1.f / sqrtf(x.v);
+  return dualf(r, -0.5f * r * r * r * x.d);
+}
+
+// --------------------------------------------------------------- SH basis
+// Real spherical harmonics, index l*l + l + m: Y_{l,0} = Y_l^0,
+// Y_{l,m} = sqrt(2) Re Y_l^m, Y_{l,-m} = sqrt(2) Im Y_l^m (m > 0), with the
+// Condon-Shortley phase in Y_l^m, written as polynomials of a unit direction.
+template <class T>
+__device__ __forceinline__ void sh_eval(int deg, T x, T y, T z, T* Y) {
+  Y[0] = T(0.28209479177387814f);
+  if (deg < 1) return;
+  Y[1] = T(-0.48860251190291987f) * y;
+  Y[2] = T(0.48860251190291987f) * z;
+  Y[3] = T(-0.48860251190291987f) * x;
+  if (deg < 2) return;
+  const T xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = T(1.0925484305920792f) * x * y;
+  Y[5] = T(-1.0925484305920792f) * y * z;
+  Y[6] = T(0.31539156525252005f) * (T(2.f) * zz - xx - yy);
+  Y[7] = T(-1.0925484305920792f) * x * z;
+  Y[8] = T(0.5462742152960396f) * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = T(-0.5900435899266435f) * y * (T(3.f) * xx - yy);
+  Y[10] = T(2.890611442640554f) * x * y * z;
+  Y[11] = T(-0.4570457994644658f) * y * (T(4.f) * zz - xx - yy);
+  Y[12] = T(0.3731763325901154f) * z * (T(2.f) * zz - T(3.f) * xx - T(3.f) * yy);
+  Y[13] = T(-0.4570457994644658f) * x * (T(4.f) * zz - xx - yy);
+  Y[14] = T(1.445305721320277f) * z * (xx - yy);
+  Y[15] = T(-0.5900435899266435f) * x * (xx - T(3.f) * yy);
+}
+
+// --------------------------------------------------------------- cameras
+struct CamView {
+  lmrs_camera c;
+  float pos[3];  // camera centre -R^T t
+};
+
+__device__ __forceinline__ CamView load_cam(const lmrs_camera* cams, const int32_t* view_ids, int v) {
+  CamView cv;
+  cv.c = cams[view_ids ? view_ids[v] : v];
+  for (int i = 0; i < 3; ++i)
+    cv.pos[i] = -(cv.c.R[i] * cv.c.t[0] + cv.c.R[3 + i] * cv.c.t[1] + cv.c.R[6 + i] * cv.c.t[2]);
+  return cv;
+}
+
+// Camera-space mean and projected centre in FP32 with a fixed operation
+// order (these values decide list membership and depth order).
+__device__ __forceinline__ void decision_point(const lmrs_camera& c, float mx, float my, float mz,
+                                               float* tc, float* u, float* v) {
+  for (int i = 0; i < 3; ++i) {
+    float acc = c.t[i];
+    acc = __fmaf_rn(c.R[3 * i + 0], mx, acc);
+    acc = __fmaf_rn(c.R[3 * i + 1], my, acc);
+    acc = __fmaf_rn(c.R[3 * i + 2], mz, acc);
+    tc[i] = acc;
+  }
+  *u = __fmaf_rn(c.fx, __fdiv_rn(tc[0], tc[2]), c.cx);
+  *v = __fmaf_rn(c.fy, __fdiv_rn(tc[1], tc[2]), c.cy);
+}
+
+// Load the P_g parameters of Gaussian g (component-major beta).
+template <class T>
+__device__ __forceinline__ void load_params(const float* beta, int n, int g, int pg, T* prm) {
+  for (int j = 0; j < pg; ++j) prm[j] = T(beta[(size_t)j * n + g]);
+}
+
+// ----------------------------------------------------------- projection
+// Screen record (u, v, A, B, C, opacity, r, g, b) of one Gaussian in one view.
+// Sigma = R S S^T R^T (eq. 2); Sigma_2D = J W Sigma W^T J^T + lowpass I with
+// J the pinhole Jacobian at the camera-space mean, computed as K K^T with
+// K = J W R S; the conic is Sigma_2D^-1. Colour 0.5 + sum_k Y_k(dir) f_k,
+// dir the unit vector from the camera centre to the mean.
+template <class T>
+__device__ __forceinline__ void proj_core(const T* prm, int deg, const CamView& cv, float lowpass,
+                                          T* rec, float* a_out, float* b_out, float* c_out) {
+  const lmrs_camera& c = cv.c;
+  const T mx = prm[0], my = prm[1], mz = prm[2];
+  const T tx = T(c.R[0]) * mx + T(c.R[1]) * my + T(c.R[2]) * mz + T(c.t[0]);
+  const T ty = T(c.R[3]) * mx + T(c.R[4]) * my + T(c.R[5]) * mz + T(c.t[1]);
+  const T tz = T(c.R[6]) * mx + T(c.R[7]) * my + T(c.R[8]) * mz + T(c.t[2]);
+  const T iz = T(1.f) / tz;
+  const T inv = trsqrt(prm[6] * prm[6] + prm[7] * prm[7] + prm[8] * prm[8] + prm[9] * prm[9]);
+  const T w = prm[6] * inv, x = prm[7] * inv, y = prm[8] * inv, z = prm[9] * inv;
+  const T R[9] = {T(1.f) - T(2.f) * (y * y + z * z), T(2.f) * (x * y - w * z), T(2.f) * (x * z + w * y),
+                  T(2.f) * (x * y + w * z), T(1.f) - T(2.f) * (x * x + z * z), T(2.f) * (y * z - w * x),
+                  T(2.f) * (x * z - w * y), T(2.f) * (y * z + w * x), T(1.f) - T(2.f) * (x * x + y * y)};
+  const T s[3] = {texp(prm[3]), texp(prm[4]), texp(prm[5])};
+  const T J00 = T(c.fx) * iz, J02 = -(T(c.fx) * tx * iz * iz);
+  const T J11 = T(c.fy) * iz, J12 = -(T(c.fy) * ty * iz * iz);
+  T Tm[6];
+  for (int j = 0; j < 3; ++j) {
+    Tm[j] = J00 * T(c.R[j]) + J02 * T(c.R[6 + j]);
+    Tm[3 + j] = J11 * T(c.R[3 + j]) + J12 * T(c.R[6 + j]);
+  }
+  T K[6];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j)
+      K[3 * i + j] = (Tm[3 * i + 0] * R[j] + Tm[3 * i + 1] * R[3 + j] + Tm[3 * i + 2] * R[6 + j]) * s[j];
+  const T a = K[0] * K[0] + K[1] * K[1] + K[2] * K[2] + T(lowpass);
+  const T b = K[0] * K[3] + K[1] * K[4] + K[2] * K[5];
+  const T cc = K[3] * K[3] + K[4] * K[4] + K[5] * K[5] + T(lowpass);
+  const T idet = T(1.f) / (a * cc - b * b);
+  rec[0] = T(c.fx) * tx * iz + T(c.cx);
+  rec[1] = T(c.fy) * ty * iz + T(c.cy);
+  rec[2] = cc * idet;
+  rec[3] = -(b * idet);
+  rec[4] = a * idet;
+  rec[5] = T(1.f) / (T(1.f) + texp(-prm[10]));
+  T dx = mx - T(cv.pos[0]), dy = my - T(cv.pos[1]), dz = mz - T(cv.pos[2]);
+  const T dinv = trsqrt(dx * dx + dy * dy + dz * dz);
+  dx = dx * dinv; dy = dy * dinv; dz = dz * dinv;
+  T Y[16];
+  sh_eval(deg, dx, dy, dz, Y);
+  const int K2 = (deg + 1) * (deg + 1);
+  for (int ch = 0; ch < 3; ++ch) {
+    T acc = T(0.5f);
+    for (int k = 0; k < K2; ++k) acc = acc + Y[k] * prm[11 + 3 * k + ch];
+    rec[6 + ch] = acc;
+  }
+  if (a_out) { *a_out = tval(a); *b_out = tval(b); *c_out = tval(cc); }
+}
+
+// Adjoint of proj_core: gp[j] += sum_q grec[q] d rec_q / d prm_j.
+__device__ __forceinline__ void proj_vjp(const float* prm, int deg, const CamView& cv, float lowpass,
+                                         const float* gr, float* gp) {
+  const lmrs_camera& c = cv.c;
+  const float mx = prm[0], my = prm[1], mz = prm[2];
+  const float tx = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
+  const float ty = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
+  const float tz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
+  const float iz = 1.f / tz, iz2 = iz * iz, iz3 = iz2 * iz;
+  const float inv = 1.f / sqrtf(prm[6] * prm[6] + prm[7] * prm[7] + prm[8] * prm[8] + prm[9] * prm[9]);
+  const float w = prm[6] * inv, x = prm[7] * inv, y = prm[8] * inv, z = prm[9] * inv;
+  const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+                      2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+                      2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
+  const float s[3] = {expf(prm[3]), expf(prm[4]), expf(prm[5])};
+  const float J00 = c.fx * iz, J02 = -c.fx * tx * iz2, J11 = c.fy * iz, J12 = -c.fy * ty * iz2;
+  float Tm[6];
+  for (int j = 0; j < 3; ++j) {
+    Tm[j] = J00 * c.R[j] + J02 * c.R[6 + j];
+    Tm[3 + j] = J11 * c.R[3 + j] + J12 * c.R[6 + j];
+  }
+  float M[9];
+  for (int l = 0; l < 3; ++l)
+    for (int j = 0; j < 3; ++j) M[3 * l + j] = R[3 * l + j] * s[j];
+  float K[6];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j)
+      K[3 * i + j] = Tm[3 * i] * M[j] + Tm[3 * i + 1] * M[3 + j] + Tm[3 * i + 2] * M[6 + j];
+  const float a = K[0] * K[0] + K[1] * K[1] + K[2] * K[2] + lowpass;
+  const float b = K[0] * K[3] + K[1] * K[4] + K[2] * K[5];
+  const float cc = K[3] * K[3] + K[4] * K[4] + K[5] * K[5] + lowpass;
+  const float idet = 1.f / (a * cc - b * b), id2 = idet * idet;
+  const float gu = gr[0], gv = gr[1], gA = gr[2], gB = gr[3], gC = gr[4], go = gr[5];
+  // conic (A, B, C) = (c, -b, a) / (a c - b^2)
+  const float ga = (-cc * cc * gA + b * cc * gB - b * b * gC) * id2;
+  const float gb = (2.f * b * cc * gA - (a * cc + b * b) * gB + 2.f * a * b * gC) * id2;
+  const float gc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
+  float gK[6];
+  for (int j = 0; j < 3; ++j) {
+    gK[j] = 2.f * ga * K[j] + gb * K[3 + j];
+    gK[3 + j] = 2.f * gc * K[3 + j] + gb * K[j];
+  }
+  // K = Tm M
+  float gTm[6];
+  for (int i = 0; i < 2; ++i)
+    for (int l = 0; l < 3; ++l)
+      gTm[3 * i + l] = gK[3 * i] * M[3 * l] + gK[3 * i + 1] * M[3 * l + 1] + gK[3 * i + 2] * M[3 * l + 2];
+  float gR[9], gs[3] = {0.f, 0.f, 0.f};
+  for (int l = 0; l < 3; ++l)
+    for (int j = 0; j < 3; ++j) {
+      const float gM = Tm[l] * gK[j] + Tm[3 + l] * gK[3 + j];
+      gR[3 * l + j] = gM * s[j];
+      gs[j] += gM * R[3 * l + j];
+    }
+  for (int j = 0; j < 3; ++j) gp[3 + j] += gs[j] * s[j];
+  // Tm = J W
+  float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
+  for (int j = 0; j < 3; ++j) {
+    gJ00 += gTm[j] * c.R[j];
+    gJ02 += gTm[j] * c.R[6 + j];
+    gJ11 += gTm[3 + j] * c.R[3 + j];
+    gJ12 += gTm[3 + j] * c.R[6 + j];
+  }
+  const float gtx = -gJ02 * c.fx * iz2 + gu * c.fx * iz;
+  const float gty = -gJ12 * c.fy * iz2 + gv * c.fy * iz;
+  const float gtz = -gJ00 * c.fx * iz2 + 2.f * gJ02 * c.fx * tx * iz3 - gJ11 * c.fy * iz2 +
+                    2.f * gJ12 * c.fy * ty * iz3 - gu * c.fx * tx * iz2 - gv * c.fy * ty * iz2;
+  float gm[3];
+  for (int i = 0; i < 3; ++i) gm[i] = c.R[i] * gtx + c.R[3 + i] * gty + c.R[6 + i] * gtz;
+  // rotation of the normalised quaternion
+  const float gw = 2.f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+  const float gx = 2.f * (y * gR[1] + z * gR[2] + y * gR[3] - 2.f * x * gR[4] - w * gR[5] + z * gR[6] +
+                          w * gR[7] - 2.f * x * gR[8]);
+  const float gy = 2.f * (-2.f * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
+                          z * gR[7] - 2.f * y * gR[8]);
+  const float gz = 2.f * (-2.f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.f * z * gR[4] +
+                          y * gR[5] + x * gR[6] + y * gR[7]);
+  const float dq = w * gw + x * gx + y * gy + z * gz;
+  gp[6] += (gw - w * dq) * inv;
+  gp[7] += (gx - x * dq) * inv;
+  gp[8] += (gy - y * dq) * inv;
+  gp[9] += (gz - z * dq) * inv;
+  // opacity
+  const float op = 1.f / (1.f + expf(-prm[10]));
+  gp[10] += go * op * (1.f - op);
+  // colour
+  float dx = mx - cv.pos[0], dy = my - cv.pos[1], dz = mz - cv.pos[2];
+  const float dinv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+  dx *= dinv; dy *= dinv; dz *= dinv;
+  const int K2 = (deg + 1) * (deg + 1);
+  float Y[16];
+  sh_eval(deg, dx, dy, dz, Y);
+  for (int k = 0; k < K2; ++k)
+    for (int ch = 0; ch < 3; ++ch) gp[11 + 3 * k + ch] += gr[6 + ch] * Y[k];
+  if (deg > 0) {
+    // d/d dir of sum_k gamma_k Y_k(dir), gamma_k = sum_c grgb_c f_kc, one dual pass per axis
+    float gamma[16];
+    for (int k = 0; k < K2; ++k)
+      gamma[k] = gr[6] * prm[11 + 3 * k] + gr[7] * prm[12 + 3 * k] + gr[8] * prm[13 + 3 * k];
+    float gd[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      dualf Yd[16];
+      sh_eval(deg, dualf(dx, ax == 0 ? 1.f : 0.f), dualf(dy, ax == 1 ? 1.f : 0.f),
+              dualf(dz, ax == 2 ? 1.f : 0.f), Yd);
+      float acc = 0.f;
+      for (int k = 1; k < K2; ++k) acc += gamma[k] * Yd[k].d;
+      gd[ax] = acc;
+    }
+    const float dd = dx * gd[0] + dy * gd[1] + dz * gd[2];
+    gm[0] += (gd[0] - dx * dd) * dinv;
+    gm[1] += (gd[1] - dy * dd) * dinv;
+    gm[2] += (gd[2] - dz * dd) * dinv;
+  }
+  gp[0] += gm[0];
+  gp[1] += gm[1];
+  gp[2] += gm[2];
+}
+
+// --------------------------------------------------- per-pixel opacity test
+// Exponent and opacity of one (pixel, Gaussian) pair, evaluated identically in
+// every splat kernel so that skip decisions agree between render, J p, J^T u
+// and the diagonal. Returns the alpha before capping in *raw.
+struct Alpha {
+  float dx, dy, es, a;
+  bool inc, capped;
+};
+
+__device__ __forceinline__ Alpha pair_alpha(float u, float v, float A, float B, float C, float o,
+                                            float xc, float yc, const lmrs_render_opts& op) {
+#pragma clang fp contract(off)
+  Alpha r;
+  r.dx = u - xc;
+  r.dy = v - yc;
+  const float s = -0.5f * (A * r.dx * r.dx + C * r.dy * r.dy) - B * r.dx * r.dy;
+  r.es = __expf(s);
+  const float raw = o * r.es;
+  r.capped = raw > op.alpha_max;
+  r.a = r.capped ? op.alpha_max : raw;
+  r.inc = (s <= 0.f) && (r.a >= op.alpha_min);
+  if (!r.inc) r.a = 0.f;
+  return r;
+}
+
+// ---------------------------------------------------- wave64 collectives
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
+}
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) x = max(x, __shfl_xor(x, d, kWave));
+  return x;
+}
+__device__ __forceinline__ float incl_prod(float x, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const float y = __shfl_up(x, d, kWave);
+    if (lane >= d) x *= y;
+  }
+  return x;
+}
+__device__ __forceinline__ float incl_sum(float x, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const float y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+// sum over lanes >= this lane
+__device__ __forceinline__ float suffix_sum(float x, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const float y = __shfl_down(x, d, kWave);
+    if (lane + d < kWave) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ float bcast(float x, int src) { return __shfl(x, src, kWave); }
+
+// Upper-triangle index of (i, j), i <= j < 5, in a 5x5 symmetric block.
+__host__ __device__ constexpr int sym5(int i, int j) { return i * 5 - i * (i - 1) / 2 + (j - i); }
+
+}  // namespace lmrs

@@ -1,0 +1,180 @@
+// Tile binning and depth sort (Sec. 3: Gaussians are sorted by depth before
+// blending; Supp. A: 16x16 tiles).
+//
+// 1. count: every visible (view, Gaussian) adds 1 to each tile of its rect.
+// 2. scan: exclusive prefix sum over the V*T counts -> tile_start (int64),
+//    total -> n_instances; counts are reset to serve as per-tile cursors.
+// 3. emit: each (view, Gaussian) writes the 64-bit key (depth bits << 32 | id)
+//    into a free slot of each of its tiles' segments. Depths are > znear > 0,
+//    so their IEEE bits order like the values; the id breaks ties.
+// 4. sort: one workgroup per tile sorts its segment. Segments of up to 4096
+//    keys are sorted in LDS by a bitonic network; longer ones sort 4096-key
+//    runs in LDS and then merge runs pairwise in HBM, each key placed at
+//    (its index in its run) + (number of smaller keys in the partner run),
+//    found by binary search (keys are unique within a tile).
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace lmrs {
+
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortChunk = 4096;
+
+__global__ __launch_bounds__(256) void count_kernel(const int4* __restrict__ rect, int n, int TX, int T,
+                                                    int32_t* __restrict__ counts) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int v = blockIdx.y;
+  if (g >= n) return;
+  const int4 rc = rect[(size_t)v * n + g];
+  for (int ty = rc.y; ty < rc.w; ++ty)
+    for (int tx = rc.x; tx < rc.z; ++tx) atomicAdd(&counts[(size_t)v * T + ty * TX + tx], 1);
+}
+
+// Single workgroup of 1024 threads scans `m` counts.
+__global__ __launch_bounds__(1024) void scan_kernel(int32_t* __restrict__ counts, int64_t m,
+                                                    int64_t* __restrict__ tile_start,
+                                                    int64_t* __restrict__ total) {
+  __shared__ int64_t s_part[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (m + 1023) / 1024;
+  const int64_t a = tid * per, b = min(m, a + per);
+  int64_t acc = 0;
+  for (int64_t i = a; i < b; ++i) acc += counts[i];
+  s_part[tid] = acc;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan of the partials
+    int64_t y = tid >= d ? s_part[tid - d] : 0;
+    __syncthreads();
+    s_part[tid] += y;
+    __syncthreads();
+  }
+  int64_t run = s_part[tid] - acc;
+  for (int64_t i = a; i < b; ++i) {
+    tile_start[i] = run;
+    run += counts[i];
+    counts[i] = 0;
+  }
+  if (tid == 1023) {
+    tile_start[m] = s_part[1023];
+    *total = s_part[1023];
+  }
+}
+
+__global__ __launch_bounds__(256) void emit_kernel(const int4* __restrict__ rect,
+                                                   const float* __restrict__ rec, int n, int TX, int T,
+                                                   const int64_t* __restrict__ tile_start,
+                                                   int32_t* __restrict__ cursor,
+                                                   uint64_t* __restrict__ keys) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int v = blockIdx.y;
+  if (g >= n) return;
+  const size_t vg = (size_t)v * n + g;
+  const int4 rc = rect[vg];
+  if (rc.x >= rc.z) return;
+  const uint32_t dbits = __float_as_uint(rec[vg * LMRS_REC + 9]);
+  const uint64_t key = ((uint64_t)dbits << 32) | (uint32_t)g;
+  for (int ty = rc.y; ty < rc.w; ++ty)
+    for (int tx = rc.x; tx < rc.z; ++tx) {
+      const size_t tile = (size_t)v * T + ty * TX + tx;
+      const int slot = atomicAdd(&cursor[tile], 1);
+      keys[tile_start[tile] + slot] = key;
+    }
+}
+
+// Bitonic sort of s[0..m) in LDS, m a power of two.
+__device__ void lds_bitonic(uint64_t* s, int m) {
+  for (int size = 2; size <= m; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < (m >> 1); i += kSortThreads) {
+        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t x = s[lo], y = s[hi];
+        if ((x > y) == up) {
+          s[lo] = y;
+          s[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+}
+
+// Sort keys[a, a+len) of one chunk through LDS; result to dst (may equal src).
+__device__ void sort_chunk(const uint64_t* src, uint64_t* dst, int len, uint64_t* s) {
+  int m = 1;
+  while (m < len) m <<= 1;
+  for (int i = threadIdx.x; i < m; i += kSortThreads) s[i] = i < len ? src[i] : ~0ull;
+  __syncthreads();
+  lds_bitonic(s, m);
+  for (int i = threadIdx.x; i < len; i += kSortThreads) dst[i] = s[i];
+  __syncthreads();
+}
+
+__device__ int64_t count_less(const uint64_t* x, int64_t len, uint64_t key) {
+  int64_t lo = 0, hi = len;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (x[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kSortThreads) void sort_kernel(const int64_t* __restrict__ tile_start,
+                                                            uint64_t* __restrict__ keys,
+                                                            uint64_t* __restrict__ tmp,
+                                                            int32_t* __restrict__ ids) {
+  __shared__ uint64_t s[kSortChunk];
+  const int64_t a = tile_start[blockIdx.x];
+  const int64_t len = tile_start[blockIdx.x + 1] - a;
+  if (len == 0) return;
+  uint64_t* src = keys + a;
+  uint64_t* dst = tmp + a;
+  if (len <= kSortChunk) {
+    sort_chunk(src, src, (int)len, s);
+  } else {
+    for (int64_t c = 0; c < len; c += kSortChunk)
+      sort_chunk(src + c, src + c, (int)min<int64_t>(kSortChunk, len - c), s);
+    for (int64_t run = kSortChunk; run < len; run <<= 1) {
+      for (int64_t i = threadIdx.x; i < len; i += kSortThreads) {
+        const int64_t pair = i / (2 * run), base = pair * 2 * run;
+        const int64_t alen = min(run, len - base);
+        const int64_t blen = max<int64_t>(0, min(run, len - base - run));
+        const uint64_t key = src[i];
+        int64_t pos;
+        if (i - base < run) {
+          pos = (i - base) + count_less(src + base + run, blen, key);
+        } else {
+          pos = (i - base - run) + count_less(src + base, alen, key);
+        }
+        dst[base + pos] = key;
+      }
+      __syncthreads();
+      uint64_t* t = src;
+      src = dst;
+      dst = t;
+    }
+  }
+  for (int64_t i = threadIdx.x; i < len; i += kSortThreads) ids[a + i] = (int32_t)(src[i] & 0xffffffffu);
+}
+
+}  // namespace
+
+void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
+  const int64_t m = (int64_t)d.V * d.T;
+  (void)hipMemsetAsync(b.counts, 0, m * sizeof(int32_t), s);
+  dim3 grid((d.n + 255) / 256, d.V);
+  count_kernel<<<grid, 256, 0, s>>>(reinterpret_cast<const int4*>(f->rect), d.n, d.TX, d.T, b.counts);
+  scan_kernel<<<1, 1024, 0, s>>>(b.counts, m, f->tile_start, f->n_instances);
+}
+
+void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
+  dim3 grid((d.n + 255) / 256, d.V);
+  emit_kernel<<<grid, 256, 0, s>>>(reinterpret_cast<const int4*>(f->rect), f->rec, d.n, d.TX, d.T,
+                                   f->tile_start, b.counts, b.keys);
+  sort_kernel<<<(unsigned)((int64_t)d.V * d.T), kSortThreads, 0, s>>>(f->tile_start, b.keys, b.tmp,
+                                                                     f->ids);
+}
+
+}  // namespace lmrs

@@ -1,0 +1,358 @@
+// Solver-side kernels: stratified residual sampling (Sec. 4.4), residuals
+// (eq. 7), the vector recurrences of the matrix-free PCG loop (Alg. 1) and the
+// learning-rate rule with the parameter update (Sec. 4.5).
+//
+// Reductions are two-stage and deterministic: kRedBlocks partial sums in FP64,
+// then one workgroup sums them. PCG scalars stay in device memory, so a PCG
+// iteration is a fixed sequence of launches with no host round trip.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace lmrs {
+
+namespace {
+
+// Philox4x32-10 (Salmon et al., SC 2011): 10 rounds of two 32x32->64
+// multiplies with key bumps by the Weyl constants.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// One workgroup of 256 lanes per (view, tile): lane p draws the key of pixel p
+// from counter (p, tile, camera id, iteration); the k pixels with the smallest
+// (key, p) are taken, listed in ascending pixel order, each with weight 256/k.
+__global__ __launch_bounds__(256) void sample_kernel(const int32_t* __restrict__ view_ids, int T, int k,
+                                                     uint32_t seed_lo, uint32_t seed_hi, uint32_t iter,
+                                                     uint8_t* __restrict__ pix, float* __restrict__ w) {
+  __shared__ uint64_t s[256];
+  __shared__ int s_sel[256];
+  const int p = threadIdx.x;
+  const int64_t tile_lin = blockIdx.x;
+  const int v = (int)(tile_lin / T), t = (int)(tile_lin % T);
+  const uint32_t cam = (uint32_t)(view_ids ? view_ids[v] : v);
+  const uint4 r = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)t, cam, iter), seed_lo, seed_hi);
+  s[p] = ((uint64_t)r.x << 8) | (uint64_t)p;
+  __syncthreads();
+  for (int size = 2; size <= 256; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (p < 128) {
+        const int lo = 2 * stride * (p / stride) + (p % stride), hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t x = s[lo], y = s[hi];
+        if ((x > y) == up) {
+          s[lo] = y;
+          s[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  s_sel[p] = 0;
+  __syncthreads();
+  if (p < k) s_sel[(int)(s[p] & 0xff)] = 1;
+  __syncthreads();
+  if (s_sel[p]) {
+    int pos = 0;
+    for (int q = 0; q < p; ++q) pos += s_sel[q];
+    pix[tile_lin * k + pos] = (uint8_t)p;
+    w[tile_lin * k + pos] = 256.f / (float)k;
+  }
+}
+
+// wr = w * (C - I) at every sampled pixel; partial sums of w |C - I|^2.
+__global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__ color,
+                                                       const float* __restrict__ targets,
+                                                       const uint8_t* __restrict__ pix,
+                                                       const float* __restrict__ wts,
+                                                       const int32_t* __restrict__ view_ids, int T,
+                                                       int TX, int W, int H, int k, int64_t S,
+                                                       float* __restrict__ wr, double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < S; i += (int64_t)gridDim.x * 256) {
+    const int64_t tile_lin = i / k;
+    const int j = (int)(i % k);
+    const int v = (int)(tile_lin / T), t = (int)(tile_lin % T);
+    const int p = pix ? (int)pix[i] : j;
+    const int x = (t % TX) * kTile + (p & 15), y = (t / TX) * kTile + (p >> 4);
+    const int cam = view_ids ? view_ids[v] : v;
+    const float* tg = targets + (((int64_t)cam * H + y) * W + x) * 3;
+    const float wi = wts ? wts[i] : 1.f;
+    for (int c = 0; c < 3; ++c) {
+      const float r = color[3 * i + c] - tg[c];
+      wr[3 * i + c] = wi * r;
+      acc += (double)wi * r * r;
+    }
+  }
+  s_red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) s_red[threadIdx.x] += s_red[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = s_red[0];
+}
+
+__device__ __forceinline__ double block_sum(double x, double* s_red) {
+  s_red[threadIdx.x] = x;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) s_red[threadIdx.x] += s_red[threadIdx.x + d];
+    __syncthreads();
+  }
+  const double r = s_red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void dot_partial_kernel(const float* __restrict__ a,
+                                                          const float* __restrict__ b, int64_t n,
+                                                          double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    acc += (double)a[i] * (double)b[i];
+  const double r = block_sum(acc, s_red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// out[o] = sum of partials[o * stride + 0 .. count), for `outs` outputs.
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ partials, int count,
+                                                       int outs, int stride, double* __restrict__ out) {
+  __shared__ double s_red[256];
+  for (int o = 0; o < outs; ++o) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += 256) acc += partials[o * stride + i];
+    const double r = block_sum(acc, s_red);
+    if (threadIdx.x == 0) out[o] = r;
+  }
+}
+
+// Report slot writer: report[slot] = (float)value[0].
+__global__ void report_kernel(const double* __restrict__ value, float* __restrict__ report, int slot) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) report[slot] = (float)value[0];
+}
+
+// PCG scalar slots.
+enum : int {
+  kRZ = 0,      // r_i^T z_i
+  kRZ0 = 1,     // r_0^T z_0
+  kPU = 2,      // p_i^T u
+  kRZNew = 3,   // r_{i+1}^T z_{i+1}
+  kRR = 4,      // r^T r
+  kAlpha = 5,
+  kBeta = 6,
+  kStop = 7,
+  kDone = 8,
+  kRR0 = 9,
+  kScalars = 16
+};
+
+__global__ __launch_bounds__(256) void pcg_init_kernel(const float* __restrict__ b,
+                                                       const float* __restrict__ diag, float lambda,
+                                                       const float* __restrict__ dvec, int64_t P,
+                                                       float* __restrict__ x, float* __restrict__ r,
+                                                       float* __restrict__ z, float* __restrict__ p,
+                                                       float* __restrict__ minv, double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  double rz = 0.0, rr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
+    const float m = 1.f / (diag[i] + lambda * (dvec ? dvec[i] : 1.f));
+    const float bi = b[i];
+    minv[i] = m;
+    x[i] = 0.f;
+    r[i] = bi;
+    const float zi = m * bi;
+    z[i] = zi;
+    p[i] = zi;
+    rz += (double)bi * zi;
+    rr += (double)bi * bi;
+  }
+  const double a = block_sum(rz, s_red);
+  const double c = block_sum(rr, s_red);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = a;
+    partials[kRedBlocks + blockIdx.x] = c;
+  }
+}
+
+__global__ void pcg_init_scalars_kernel(double* __restrict__ sc) {
+  if (threadIdx.x == 0) {
+    sc[kRZ0] = sc[kRZ];
+    sc[kRR0] = sc[kRR];
+    sc[kStop] = 0.0;
+    sc[kDone] = 0.0;
+    sc[kAlpha] = 0.0;
+    sc[kBeta] = 0.0;
+  }
+}
+
+// alpha = r^T z / p^T u (0 once stopped); x += alpha p; r -= alpha u; z = M^-1 r.
+__global__ __launch_bounds__(256) void pcg_update_kernel(int64_t P, const double* __restrict__ sc,
+                                                         float* __restrict__ x, float* __restrict__ r,
+                                                         float* __restrict__ z, const float* __restrict__ p,
+                                                         const float* __restrict__ u,
+                                                         const float* __restrict__ minv,
+                                                         double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  const double rz = sc[kRZ], pu = sc[kPU];
+  const bool go = sc[kStop] == 0.0 && pu > 0.0 && rz > 1e-30 * sc[kRZ0];
+  const float alpha = go ? (float)(rz / pu) : 0.f;
+  double rz1 = 0.0, rr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
+    float ri = r[i];
+    if (go) {
+      x[i] += alpha * p[i];
+      ri -= alpha * u[i];
+      r[i] = ri;
+    }
+    const float zi = minv[i] * ri;
+    z[i] = zi;
+    rz1 += (double)ri * zi;
+    rr += (double)ri * ri;
+  }
+  const double a = block_sum(rz1, s_red);
+  const double c = block_sum(rr, s_red);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = a;
+    partials[kRedBlocks + blockIdx.x] = c;
+  }
+}
+
+// After pcg_update's reductions (kRZNew, kRR): beta and the stop flag.
+__global__ void pcg_scalar_kernel(double* __restrict__ sc) {
+  if (threadIdx.x != 0) return;
+  const double rz = sc[kRZ], pu = sc[kPU];
+  const bool go = sc[kStop] == 0.0 && pu > 0.0 && rz > 1e-30 * sc[kRZ0];
+  if (go) {
+    sc[kBeta] = sc[kRZNew] / rz;
+    sc[kRZ] = sc[kRZNew];
+    sc[kDone] += 1.0;
+  } else {
+    sc[kStop] = 1.0;
+    sc[kBeta] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void pcg_dir_kernel(int64_t P, const double* __restrict__ sc,
+                                                      const float* __restrict__ z, float* __restrict__ p) {
+  if (sc[kStop] != 0.0) return;
+  const float beta = (float)sc[kBeta];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void pcg_report_kernel(const double* __restrict__ sc, const double* __restrict__ bx,
+                                  float* __restrict__ report) {
+  if (threadIdx.x != 0) return;
+  report[LMRS_REP_CG_DONE] = (float)sc[kDone];
+  report[LMRS_REP_R0] = (float)sqrt(sc[kRR0]);
+  report[LMRS_REP_RN] = (float)sqrt(sc[kRR]);
+  report[LMRS_REP_BX] = (float)bx[0];
+}
+
+// max |x| over the DC colour coefficients, partial per block.
+__global__ __launch_bounds__(256) void absmax_partial_kernel(const float* __restrict__ x, int64_t n,
+                                                             double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    m = fmax(m, (double)fabsf(x[i]));
+  s_red[threadIdx.x] = m;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) s_red[threadIdx.x] = fmax(s_red[threadIdx.x], s_red[threadIdx.x + d]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = s_red[0];
+}
+
+__global__ void lr_kernel(const double* __restrict__ partials, int count, lmrs_lm_params prm,
+                          double* __restrict__ eta_out, float* __restrict__ report) {
+  if (threadIdx.x != 0) return;
+  double m = 0.0;
+  for (int i = 0; i < count; ++i) m = fmax(m, partials[i]);
+  double eta;
+  if (prm.iter < prm.warm_iters) eta = prm.eta_warm;
+  else eta = m > 0.0 ? fmin((double)prm.eta_cap, 1.0 / m) : (double)prm.eta_cap;
+  *eta_out = eta;
+  if (report) {
+    report[LMRS_REP_ETA] = (float)eta;
+    report[LMRS_REP_XDC_MAX] = (float)m;
+  }
+}
+
+__global__ __launch_bounds__(256) void lm_apply_kernel(float* __restrict__ beta, const float* __restrict__ x,
+                                                       int64_t P, const double* __restrict__ eta) {
+  const float e = (float)eta[0];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256)
+    beta[i] -= e * x[i];
+}
+
+}  // namespace
+
+void launch_sample_uniform(const lmrs_frame* f, const FrameDims& d, uint64_t seed, int iter, hipStream_t s) {
+  sample_kernel<<<(unsigned)((int64_t)d.V * d.T), 256, 0, s>>>(
+      f->view_ids, d.T, d.k, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)iter, f->pix,
+      f->w);
+}
+
+void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targets, float* wr,
+                     double* partials, float* report, hipStream_t s) {
+  residual_kernel<<<kRedBlocks, 256, 0, s>>>(f->color, targets, f->pix, f->w, f->view_ids, d.T, d.TX,
+                                             d.W, d.H, d.k, d.S, wr, partials);
+  finalize_kernel<<<1, 256, 0, s>>>(partials, kRedBlocks, 1, kRedBlocks, partials + 2 * kRedBlocks);
+  if (report) report_kernel<<<1, 64, 0, s>>>(partials + 2 * kRedBlocks, report, LMRS_REP_LOSS);
+}
+
+void launch_dot(const float* a, const float* b, int64_t n, double* partials, double* out, hipStream_t s) {
+  dot_partial_kernel<<<kRedBlocks, 256, 0, s>>>(a, b, n, partials);
+  finalize_kernel<<<1, 256, 0, s>>>(partials, kRedBlocks, 1, kRedBlocks, out);
+}
+
+void launch_pcg_init(const float* b, const float* diag, float lambda, const float* dvec, int64_t P,
+                     PcgState st, hipStream_t s) {
+  pcg_init_kernel<<<kRedBlocks, 256, 0, s>>>(b, diag, lambda, dvec, P, st.x, st.r, st.z, st.p, st.minv,
+                                             st.partials);
+  // rz -> sc[kRZ], rr -> sc[kRR]
+  finalize_kernel<<<1, 256, 0, s>>>(st.partials, kRedBlocks, 1, kRedBlocks, st.sc + kRZ);
+  finalize_kernel<<<1, 256, 0, s>>>(st.partials + kRedBlocks, kRedBlocks, 1, kRedBlocks, st.sc + kRR);
+  pcg_init_scalars_kernel<<<1, 64, 0, s>>>(st.sc);
+}
+
+void launch_pcg_update(int64_t P, PcgState st, hipStream_t s) {
+  // p^T u first
+  dot_partial_kernel<<<kRedBlocks, 256, 0, s>>>(st.p, st.u, P, st.partials);
+  finalize_kernel<<<1, 256, 0, s>>>(st.partials, kRedBlocks, 1, kRedBlocks, st.sc + kPU);
+  pcg_update_kernel<<<kRedBlocks, 256, 0, s>>>(P, st.sc, st.x, st.r, st.z, st.p, st.u, st.minv,
+                                               st.partials);
+  finalize_kernel<<<1, 256, 0, s>>>(st.partials, kRedBlocks, 1, kRedBlocks, st.sc + kRZNew);
+  finalize_kernel<<<1, 256, 0, s>>>(st.partials + kRedBlocks, kRedBlocks, 1, kRedBlocks, st.sc + kRR);
+  pcg_scalar_kernel<<<1, 64, 0, s>>>(st.sc);
+}
+
+void launch_pcg_direction(int64_t P, PcgState st, hipStream_t s) {
+  pcg_dir_kernel<<<kRedBlocks, 256, 0, s>>>(P, st.sc, st.z, st.p);
+}
+
+void launch_pcg_report(const float* b, int64_t P, PcgState st, float* report, hipStream_t s) {
+  launch_dot(b, st.x, P, st.partials, st.sc + 10, s);
+  pcg_report_kernel<<<1, 64, 0, s>>>(st.sc, st.sc + 10, report);
+}
+
+void launch_lm_update(float* beta, const float* x, int n, int64_t P, const lmrs_lm_params& prm,
+                      double* partials, float* report, hipStream_t s) {
+  absmax_partial_kernel<<<kRedBlocks, 256, 0, s>>>(x + (int64_t)11 * n, (int64_t)3 * n, partials);
+  lr_kernel<<<1, 64, 0, s>>>(partials, kRedBlocks, prm, partials + kRedBlocks, report);
+  lm_apply_kernel<<<kRedBlocks, 256, 0, s>>>(beta, x, P, partials + kRedBlocks);
+}
+
+}  // namespace lmrs

@@ -1,0 +1,68 @@
+// Host-side launchers of the lmrs kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lmrs.h"
+
+namespace lmrs {
+
+// Geometry shared by the splat kernels of one frame.
+struct FrameDims {
+  int n, deg, pg, V, W, H, TX, TY, T, k;
+  int64_t S;  // sampled pixels V*T*k
+};
+
+FrameDims dims_of(const lmrs_frame* f);
+
+// projection side (kernels_project.hip)
+void launch_project(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s);
+void launch_tangent(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* p,
+                    float* tan, hipStream_t s);
+void launch_chain_vjp(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
+                      const float* grad2d, const float* p, float lambda, const float* dvec, float* out,
+                      hipStream_t s);
+void launch_chain_diag(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
+                       const float* gram, float* out, hipStream_t s);
+void launch_fill(float* x, int64_t count, float value, hipStream_t s);
+
+// binning (kernels_bin.hip)
+struct BinScratch {
+  int32_t* counts;  // [V*T]
+  uint64_t* keys;   // [capacity]
+  uint64_t* tmp;    // [capacity]
+};
+void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s);
+void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s);
+
+// splatting (kernels_splat.hip)
+void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s);
+// mode: 1 = J p only (writes jp), 2 = J^T u only (reads u), 3 = fused GN (J^T W J p)
+void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
+                  const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s);
+void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* gram,
+                 hipStream_t s);
+
+// solver side (kernels_solver.hip)
+constexpr int kRedBlocks = 512;  // partial sums per reduction
+void launch_sample_uniform(const lmrs_frame* f, const FrameDims& d, uint64_t seed, int iter,
+                           hipStream_t s);
+void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targets, float* wr,
+                     double* partials, float* report, hipStream_t s);
+void launch_dot(const float* a, const float* b, int64_t n, double* partials, double* out, hipStream_t s);
+// PCG state in device memory
+struct PcgState {
+  float *x, *r, *z, *p, *u, *minv;
+  double* sc;        // scalars: see kernels_solver.hip
+  double* partials;  // [2 * kRedBlocks]
+};
+void launch_pcg_init(const float* b, const float* diag, float lambda, const float* dvec, int64_t P,
+                     PcgState st, hipStream_t s);
+void launch_pcg_update(int64_t P, PcgState st, hipStream_t s);
+void launch_pcg_direction(int64_t P, PcgState st, hipStream_t s);
+void launch_pcg_report(const float* b, int64_t P, PcgState st, float* report, hipStream_t s);
+void launch_lm_update(float* beta, const float* x, int n, int64_t P, const lmrs_lm_params& prm,
+                      double* partials, float* report, hipStream_t s);
+
+}  // namespace lmrs

@@ -1,0 +1,293 @@
+"""Python binding of liblmrs (argument marshalling only).
+
+Every call forwards device pointers of torch tensors and the current HIP stream
+to the C ABI declared in include/lmrs.h; all arithmetic runs in the library's
+HIP kernels. Importing this module raises if the library has not been built:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblmrs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"liblmrs.so not built at {LIB_PATH}: run __graft_entry__.build() first")
+
+_lib = C.CDLL(LIB_PATH)
+
+LMRS_OK, LMRS_EINVAL, LMRS_ECAPACITY, LMRS_EWORKSPACE, LMRS_EHIP = 0, -1, -2, -3, -4
+LMRS_REC = 12
+OP_BIN, OP_JVP, OP_VJP, OP_GN, OP_DIAG, OP_PCG, OP_LM = 1, 2, 3, 4, 5, 6, 7
+REPORT_FLOATS = 8
+REP = dict(loss=0, eta=1, xdc_max=2, cg_done=3, r0=4, rn=5, bx=6, instances=7)
+
+
+class LmrsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.lmrs_last_error().decode()
+        super().__init__(f"{where}: {_lib.lmrs_status_str(status).decode()} ({msg})")
+        self.status = status
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
+                ("lowpass", C.c_float), ("znear", C.c_float), ("cutoff", C.c_float),
+                ("bg", C.c_float * 3)]
+
+
+def default_opts(**kw) -> RenderOpts:
+    o = RenderOpts(1.0 / 255.0, 0.99, 1e-4, 0.3, 0.2, 3.0, (C.c_float * 3)(0.0, 0.0, 0.0))
+    for k, v in kw.items():
+        if k == "bg":
+            o.bg = (C.c_float * 3)(*v)
+        else:
+            setattr(o, k, v)
+    return o
+
+
+class _Frame(C.Structure):
+    _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("n_views", C.c_int32),
+                ("width", C.c_int32), ("height", C.c_int32), ("k", C.c_int32),
+                ("beta", C.c_void_p), ("cams", C.c_void_p), ("view_ids", C.c_void_p),
+                ("rec", C.c_void_p), ("rect", C.c_void_p), ("tile_start", C.c_void_p),
+                ("ids", C.c_void_p), ("capacity", C.c_int64), ("n_instances", C.c_void_p),
+                ("pix", C.c_void_p), ("w", C.c_void_p), ("color", C.c_void_p),
+                ("trans", C.c_void_p), ("last", C.c_void_p)]
+
+
+class LmParams(C.Structure):
+    _fields_ = [("iter", C.c_int32), ("cg_iters", C.c_int32), ("lam", C.c_float),
+                ("eta_cap", C.c_float), ("eta_warm", C.c_float), ("warm_iters", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+_vp, _i32, _f32, _sz = C.c_void_p, C.c_int32, C.c_float, C.c_size_t
+_FP = C.POINTER(_Frame)
+_lib.lmrs_status_str.restype = C.c_char_p
+_lib.lmrs_status_str.argtypes = [_i32]
+_lib.lmrs_last_error.restype = C.c_char_p
+_lib.lmrs_workspace_bytes.restype = _sz
+_lib.lmrs_workspace_bytes.argtypes = [_i32, _FP]
+_lib.lmrs_project.argtypes = [_FP, _vp, _vp]
+_lib.lmrs_bin_tiles.argtypes = [_FP, _vp, _sz, _vp]
+_lib.lmrs_render.argtypes = [_FP, _vp, _vp]
+_lib.lmrs_jvp.argtypes = [_FP, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.lmrs_vjp.argtypes = [_FP, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.lmrs_gn_product.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]
+_lib.lmrs_gn_diag.argtypes = [_FP, _vp, _vp, _vp, _sz, _vp]
+_lib.lmrs_pcg.argtypes = [_FP, _vp, _vp, _f32, _vp, _i32, _vp, _vp, _vp, _sz, _vp]
+_lib.lmrs_lm_step.argtypes = [_FP, _vp, _vp, _vp, C.POINTER(LmParams), _vp, _vp, _vp, _sz, _vp]
+for _name in ("lmrs_project", "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp",
+              "lmrs_gn_product", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step"):
+    getattr(_lib, _name).restype = _i32
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check(status: int, where: str):
+    if status != LMRS_OK:
+        raise LmrsError(status, where)
+
+
+@dataclass
+class Frame:
+    """Device buffers of one view batch (see lmrs_frame in include/lmrs.h).
+
+    beta: float32 [P]; cams: float32 [V_total, 16]; view_ids: int32 [V] or None
+    (batch view v is camera v); k: samples per tile (256 = all pixels).
+    """
+    n: int
+    sh_degree: int
+    beta: torch.Tensor
+    cams: torch.Tensor
+    width: int
+    height: int
+    n_views: int
+    view_ids: torch.Tensor | None = None
+    k: int = 256
+    sampled: bool = False          # allocate pix / w (needed when k < 256)
+    capacity: int = 0
+    tensors: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        dev = self.beta.device
+        V, n = self.n_views, self.n
+        self.TX, self.TY = self.width // 16, self.height // 16
+        self.T = self.TX * self.TY
+        self.P = n * (11 + 3 * (self.sh_degree + 1) ** 2)
+        assert self.beta.dtype == torch.float32 and self.beta.numel() == self.P and self.beta.is_contiguous()
+        assert self.cams.dtype == torch.float32 and self.cams.shape[-1] == 16
+        if self.view_ids is not None:
+            assert self.view_ids.dtype == torch.int32 and self.view_ids.numel() == V
+        t = self.tensors
+        t["rec"] = torch.empty((V, n, LMRS_REC), dtype=torch.float32, device=dev)
+        t["rect"] = torch.empty((V, n, 4), dtype=torch.int32, device=dev)
+        t["tile_start"] = torch.zeros(V * self.T + 1, dtype=torch.int64, device=dev)
+        t["n_instances"] = torch.zeros(1, dtype=torch.int64, device=dev)
+        t["ids"] = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
+        self.set_k(self.k, self.sampled or self.k < 256)
+
+    def set_k(self, k: int, sampled: bool):
+        dev = self.beta.device
+        self.k, self.sampled = int(k), bool(sampled)
+        S = self.n_views * self.T * self.k
+        t = self.tensors
+        if self.sampled:
+            t["pix"] = torch.empty((self.n_views, self.T, self.k), dtype=torch.uint8, device=dev)
+            t["w"] = torch.empty((self.n_views, self.T, self.k), dtype=torch.float32, device=dev)
+        else:
+            t["pix"], t["w"] = None, None
+        t["color"] = torch.empty((S, 3), dtype=torch.float32, device=dev)
+        t["trans"] = torch.empty(S, dtype=torch.float32, device=dev)
+        t["last"] = torch.empty(S, dtype=torch.int32, device=dev)
+
+    @property
+    def S(self) -> int:
+        return self.n_views * self.T * self.k
+
+    def __getattr__(self, name):
+        t = self.__dict__.get("tensors", {})
+        if name in t:
+            return t[name]
+        raise AttributeError(name)
+
+    def struct(self) -> _Frame:
+        t = self.tensors
+        return _Frame(self.n, self.sh_degree, self.n_views, self.width, self.height, self.k,
+                      self.beta.data_ptr(), self.cams.data_ptr(),
+                      None if self.view_ids is None else self.view_ids.data_ptr(),
+                      t["rec"].data_ptr(), t["rect"].data_ptr(), t["tile_start"].data_ptr(),
+                      t["ids"].data_ptr(), self.capacity, t["n_instances"].data_ptr(),
+                      None if t["pix"] is None else t["pix"].data_ptr(),
+                      None if t["w"] is None else t["w"].data_ptr(),
+                      t["color"].data_ptr(), t["trans"].data_ptr(), t["last"].data_ptr())
+
+    def grow_ids(self, needed: int):
+        self.capacity = int(needed * 1.25) + 1024
+        self.tensors["ids"] = torch.empty(self.capacity, dtype=torch.int32, device=self.beta.device)
+
+
+def workspace(op: int, frame: Frame) -> torch.Tensor:
+    fs = frame.struct()
+    nbytes = int(_lib.lmrs_workspace_bytes(op, C.byref(fs)))
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=frame.beta.device)
+
+
+def lmrs_project(frame: Frame, opts: RenderOpts | None = None, stream=None):
+    opts = opts or default_opts()
+    fs = frame.struct()
+    _check(_lib.lmrs_project(C.byref(fs), C.byref(opts), _stream(stream)), "lmrs_project")
+
+
+def lmrs_bin_tiles(frame: Frame, stream=None) -> int:
+    """Bins; grows the id buffer and retries when the capacity is exceeded."""
+    for _ in range(2):
+        fs = frame.struct()
+        ws = workspace(OP_BIN, frame)
+        st = _lib.lmrs_bin_tiles(C.byref(fs), _ptr(ws), ws.numel(), _stream(stream))
+        if st == LMRS_ECAPACITY:
+            frame.grow_ids(int(frame.n_instances.item()))
+            continue
+        _check(st, "lmrs_bin_tiles")
+        return int(frame.n_instances.item())
+    raise LmrsError(LMRS_ECAPACITY, "lmrs_bin_tiles")
+
+
+def lmrs_render(frame: Frame, opts: RenderOpts | None = None, stream=None):
+    opts = opts or default_opts()
+    fs = frame.struct()
+    _check(_lib.lmrs_render(C.byref(fs), C.byref(opts), _stream(stream)), "lmrs_render")
+
+
+def lmrs_jvp(frame: Frame, p: torch.Tensor, out: torch.Tensor | None = None, opts=None, stream=None):
+    opts = opts or default_opts()
+    out = out if out is not None else torch.empty((frame.S, 3), dtype=torch.float32, device=p.device)
+    ws = workspace(OP_JVP, frame)
+    fs = frame.struct()
+    _check(_lib.lmrs_jvp(C.byref(fs), C.byref(opts), _ptr(p), _ptr(out), _ptr(ws), ws.numel(),
+                         _stream(stream)), "lmrs_jvp")
+    return out
+
+
+def lmrs_vjp(frame: Frame, u: torch.Tensor, out: torch.Tensor | None = None, opts=None, stream=None):
+    opts = opts or default_opts()
+    out = out if out is not None else torch.empty(frame.P, dtype=torch.float32, device=u.device)
+    ws = workspace(OP_VJP, frame)
+    fs = frame.struct()
+    _check(_lib.lmrs_vjp(C.byref(fs), C.byref(opts), _ptr(u), _ptr(out), _ptr(ws), ws.numel(),
+                         _stream(stream)), "lmrs_vjp")
+    return out
+
+
+def lmrs_gn_product(frame: Frame, p: torch.Tensor, lam: float, d: torch.Tensor | None = None,
+                    out: torch.Tensor | None = None, opts=None, stream=None, ws: torch.Tensor | None = None):
+    opts = opts or default_opts()
+    out = out if out is not None else torch.empty(frame.P, dtype=torch.float32, device=p.device)
+    ws = ws if ws is not None else workspace(OP_GN, frame)
+    fs = frame.struct()
+    _check(_lib.lmrs_gn_product(C.byref(fs), C.byref(opts), _ptr(p), float(lam), _ptr(d), _ptr(out),
+                                _ptr(ws), ws.numel(), _stream(stream)), "lmrs_gn_product")
+    return out
+
+
+def lmrs_gn_diag(frame: Frame, out: torch.Tensor | None = None, opts=None, stream=None):
+    opts = opts or default_opts()
+    out = out if out is not None else torch.empty(frame.P, dtype=torch.float32, device=frame.beta.device)
+    ws = workspace(OP_DIAG, frame)
+    fs = frame.struct()
+    _check(_lib.lmrs_gn_diag(C.byref(fs), C.byref(opts), _ptr(out), _ptr(ws), ws.numel(),
+                             _stream(stream)), "lmrs_gn_diag")
+    return out
+
+
+def lmrs_pcg(frame: Frame, b: torch.Tensor, lam: float, iters: int, d: torch.Tensor | None = None,
+             x: torch.Tensor | None = None, report: torch.Tensor | None = None, opts=None, stream=None):
+    opts = opts or default_opts()
+    x = x if x is not None else torch.empty(frame.P, dtype=torch.float32, device=b.device)
+    ws = workspace(OP_PCG, frame)
+    fs = frame.struct()
+    _check(_lib.lmrs_pcg(C.byref(fs), C.byref(opts), _ptr(b), float(lam), _ptr(d), int(iters), _ptr(x),
+                         _ptr(report), _ptr(ws), ws.numel(), _stream(stream)), "lmrs_pcg")
+    return x
+
+
+def lmrs_lm_step(frame: Frame, targets: torch.Tensor, params: LmParams, d: torch.Tensor | None = None,
+                 report: torch.Tensor | None = None, opts=None, stream=None, ws: torch.Tensor | None = None):
+    """One LM iteration in place on frame.beta; grows the id buffer and retries on overflow."""
+    opts = opts or default_opts()
+    for _ in range(3):
+        fs = frame.struct()
+        w = ws if (ws is not None and ws.numel() >= _lib.lmrs_workspace_bytes(OP_LM, C.byref(fs))) \
+            else workspace(OP_LM, frame)
+        st = _lib.lmrs_lm_step(C.byref(fs), _ptr(frame.beta), _ptr(targets), _ptr(d), C.byref(params),
+                               C.byref(opts), _ptr(report), _ptr(w), w.numel(), _stream(stream))
+        if st == LMRS_ECAPACITY:
+            frame.grow_ids(int(frame.n_instances.item()))
+            continue
+        _check(st, "lmrs_lm_step")
+        return
+    raise LmrsError(LMRS_ECAPACITY, "lmrs_lm_step")
+
+
+def lm_params(iter: int, cg_iters: int, lam: float, seed: int = 0, eta_cap: float = 0.2,
+              eta_warm: float = 0.05, warm_iters: int = 10) -> LmParams:
+    return LmParams(int(iter), int(cg_iters), float(lam), float(eta_cap), float(eta_warm), int(warm_iters),
+                    int(seed))
+
+
+EXPORTS = ("lmrs_status_str", "lmrs_last_error", "lmrs_workspace_bytes", "lmrs_project", "lmrs_bin_tiles",
+           "lmrs_render", "lmrs_jvp", "lmrs_vjp", "lmrs_gn_product", "lmrs_gn_diag", "lmrs_pcg",
+           "lmrs_lm_step")

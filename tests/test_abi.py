@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI: the library loads, exports every call that
+include/lmrs.h declares, sizes workspaces consistently and rejects bad
+arguments before enqueuing anything (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lmrs.h")
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2504_12905_amd import lmrs
+    return lmrs
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:lmrs_status|size_t|const char\*)\s+(lmrs_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_eight_hot_path_calls():
+    names = declared_functions()
+    for n in ("lmrs_project", "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp", "lmrs_gn_product",
+              "lmrs_pcg", "lmrs_lm_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(M):
+    lib = C.CDLL(M.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(M.EXPORTS)
+
+
+def frame(M, **kw):
+    f = M._Frame()
+    f.n, f.sh_degree, f.n_views, f.width, f.height, f.k, f.capacity = 1000, 3, 8, 800, 800, 26, 10 ** 6
+    for k, v in kw.items():
+        setattr(f, k, v)
+    return f
+
+
+def test_workspace_sizes(M):
+    ws = lambda op, **kw: M._lib.lmrs_workspace_bytes(op, C.byref(frame(M, **kw)))
+    assert ws(M.OP_GN) >= 8 * 1000 * (12 + 9) * 4
+    assert ws(M.OP_PCG) > ws(M.OP_GN) > ws(M.OP_JVP)
+    assert ws(M.OP_LM) > ws(M.OP_PCG)
+    assert ws(M.OP_BIN, capacity=2 * 10 ** 6) > ws(M.OP_BIN)
+    assert all(ws(op) % 256 == 0 for op in range(1, 8))
+    assert M._lib.lmrs_workspace_bytes(M.OP_GN, None) == 0
+
+
+@pytest.mark.parametrize("bad", [dict(n=0), dict(sh_degree=4), dict(width=100), dict(n_views=0),
+                                 dict(k=0), dict(k=300)])
+def test_invalid_frames_rejected_on_host(M, bad):
+    f = frame(M, **bad)
+    f.beta = 1  # never dereferenced: validation fails first
+    opts = M.default_opts()
+    st = M._lib.lmrs_render(C.byref(f), C.byref(opts), None)
+    assert st == M.LMRS_EINVAL
+    assert M._lib.lmrs_last_error()
+
+
+def test_missing_buffers_and_small_workspace_rejected(M):
+    f = frame(M)
+    f.beta = 1
+    opts = M.default_opts()
+    assert M._lib.lmrs_render(C.byref(f), C.byref(opts), None) == M.LMRS_EINVAL  # pix NULL with k=26
+    f.k = 256
+    assert M._lib.lmrs_render(C.byref(f), C.byref(opts), None) == M.LMRS_EINVAL  # rec NULL
+    assert b"rec" in M._lib.lmrs_last_error()
+    for name in ("rec", "rect", "tile_start", "ids", "cams", "trans", "last"):
+        setattr(f, name, 256)
+    st = M._lib.lmrs_gn_product(C.byref(f), C.byref(opts), 256, C.c_float(0.1), None, 512, 256, 16, None)
+    assert st == M.LMRS_EWORKSPACE
+    assert M._lib.lmrs_status_str(st) == b"workspace too small"

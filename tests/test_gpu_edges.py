@@ -1,0 +1,68 @@
+"""GPU edge cases against the oracle: culled scenes, a single Gaussian, one
+sample per tile, a tile list longer than one LDS sort chunk (merge path) and
+empty tiles."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, compare_lists, gpu_frame, lib, lists_of, log, np_, oracle_for, rel
+from oracle.sampling import sample_uniform
+from paper_2504_12905_amd import synth
+from test_oracle_geometry import axis_camera, one_gaussian_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def check_all(name, n, deg, beta, cams, W, H, k=256, pix=None, wts=None, lam=0.05):
+    log(f"[edge] {name}")
+    fr = gpu_frame(n, deg, beta, cams, W, H, k, pix, wts)
+    orc = oracle_for(n, deg, beta, cams, W, H, k, pix, wts)
+    gts, gids = lists_of(fr)
+    ots, oids = orc.lists()
+    assert compare_lists(gts, gids, ots, oids, orc.projection()["margin"], orc.T) == 0
+    ref = orc.render()
+    assert rel(np_(fr.color), ref["C"]) < 1e-4 or np.linalg.norm(ref["C"]) == 0
+    p = np.random.default_rng(0).normal(size=orc.P).astype(np.float32)
+    out = np_(lib().lmrs_gn_product(fr, torch.tensor(p, device=DEV), lam))
+    e = rel(out, orc.gn(p, lam))
+    log(f"  lists {oids.size}  gn rel {e:.2e}")
+    assert e < 1e-4
+    return fr, orc
+
+
+def test_everything_culled():
+    # all Gaussians behind the camera or off-screen: empty lists, background render, out = lam p
+    n, beta = one_gaussian_scene([[0, 0, -3.5], [50, 0, 0], [0, 0, -3.0]], [math.log(0.1)] * 3,
+                                 [1, 0, 0, 0], 0.0, [0.5, 0.5, 0.5])
+    fr, orc = check_all("culled", n, 0, beta, axis_camera(40.0, 32, 32), 32, 32)
+    assert int(fr.n_instances.item()) == 0
+    assert np.all(np_(fr.last) == -1) and np.all(np_(fr.trans) == 1.0)
+
+
+def test_single_gaussian_sh2():
+    rng = np.random.default_rng(0)
+    n, beta = one_gaussian_scene([0.05, -0.02, 0.1], [-2.0, -2.3, -1.9], [0.9, 0.1, -0.3, 0.2], 0.4,
+                                 [0.7, 0.2, 0.4], sh_degree=2, sh_rest=rng.normal(0, 0.1, size=(8, 3, 1)))
+    check_all("single-sh2", n, 2, beta, axis_camera(60.0, 48, 48), 48, 48)
+
+
+def test_one_sample_per_tile():
+    w = synth.config0()
+    pix, wts = sample_uniform(4, 2, np.arange(4), 16, 1)
+    check_all("cfg0-k1", w.n, 0, w.beta_init, w.cams, w.width, w.height, 1, pix, wts)
+
+
+def test_long_tile_list_merge_path():
+    # 6000 small Gaussians in front of one tile: the tile list exceeds the 4096-key LDS sort chunk
+    rng = np.random.default_rng(7)
+    n, f = 6000, 120.0
+    zc = rng.uniform(2.0, 4.0, n)                 # camera depth
+    u, v = rng.uniform(35.0, 45.0, n), rng.uniform(35.0, 45.0, n)   # inside tile (2, 2) with margin
+    mu = np.stack([(u - 32.0) * zc / f, (v - 32.0) * zc / f, zc - 3.0], 1)
+    n, beta = one_gaussian_scene(mu, [math.log(0.004)] * 3, [1, 0, 0, 0], -1.0, [0.3, 0.6, 0.9])
+    beta[synth.seg(n, "log_scale")] += rng.normal(0, 0.1, size=3 * n)
+    fr, orc = check_all("long-list", n, 0, beta, axis_camera(f, 64, 64), 64, 64)
+    ts = np_(fr.tile_start)
+    assert np.diff(ts).max() > 4096
