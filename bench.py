@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark: Gauss-Newton products per second inside LM steps on one MI355X.
+
+Workload (object-scale fit, FP32): 100k Gaussians in the unit ball, SH degree 3,
+64 cameras of 800x800 on a radius-4 sphere. Each LM step samples 8 views and
+10 % of the pixels of every 16x16 tile (26 per tile, uniform, Philox keys),
+runs 8 CG iterations (8 GN products) and updates the parameters. A timed
+"step" is one full LM step through the C ABI: projection, binning, sampling,
+render, residuals, b = J^T W r, diagonal, PCG with 8 GN products, learning
+rate and update. `value` = GN products completed per second of LM stepping
+(8 per step), with all inputs resident in HBM.
+
+Also measured: the GN product on its own (HIP events on the library's stream,
+per launch), the roofline position of its dominant kernel (the fused splat
+kernel), and the FP64 CPU oracle's GN-product rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GN products (J^T J p)/sec at 100k Gaussians vs plain; served fits/sec + p99"
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+SPLAT_SOURCE = os.path.join(ROOT, "paper_2504_12905_amd", "csrc", "kernels_splat.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gn_splat_traffic_cfg1.txt")
+
+# Algorithmic bytes of the fused splat kernel (one GN product):
+#   per traversed (tile, list entry): list id 4 B + screen record 36 B + its
+#   tangent 36 B read, screen gradient 36 B written;
+#   per sampled pixel: pixel index 1 B, weight 4 B, final transmittance 4 B,
+#   last blended position 4 B.
+BYTES_PER_ENTRY = 4 + 36 + 36 + 36
+BYTES_PER_PIXEL = 1 + 4 + 4 + 4
+# Algorithmic FP32 operations per (sampled pixel, list entry) pair walked:
+# opacity test 14 (offsets 2, quadratic form 7, exp 1, scale 1, compares 3),
+# exponent tangent 17, alpha tangent 3, transmittance and its tangent 5,
+# colour tangent 12, reverse transmittance 2, blended-behind term 6,
+# alpha adjoint 4, screen-gradient accumulation 24.
+FLOPS_PER_PAIR = 14 + 17 + 3 + 5 + 12 + 14 + 2 + 6 + 4 + 24
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def render_targets(L, torch, w, beta_gt, cams, dev):
+    """Render every camera of the workload at full resolution (setup, untimed)."""
+    V_all = cams.shape[0]
+    H, W = w.height, w.width
+    targets = torch.empty((V_all, H, W, 3), dtype=torch.float32, device=dev)
+    TX = W // 16
+    for a in range(0, V_all, 8):
+        ids = torch.arange(a, min(a + 8, V_all), dtype=torch.int32, device=dev)
+        fr = L.Frame(w.n, w.sh_degree, beta_gt, cams, W, H, ids.numel(), view_ids=ids, k=256)
+        L.lmrs_project(fr)
+        L.lmrs_bin_tiles(fr)
+        L.lmrs_render(fr)
+        T = fr.T
+        col = fr.color.view(ids.numel(), T, 256, 3)
+        t = torch.arange(T, device=dev)
+        p = torch.arange(256, device=dev)
+        y = ((t // TX) * 16)[:, None] + (p // 16)[None, :]
+        x = ((t % TX) * 16)[:, None] + (p % 16)[None, :]
+        for v in range(ids.numel()):
+            targets[a + v, y, x] = col[v]
+    torch.cuda.synchronize()
+    return targets
+
+
+def traffic_from_profile(kernel_hash: str):
+    """HBM bytes per launch of the fused splat kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, beta, cams_np, view_ids, pix, wts, lam, budget_s=20.0):
+    """FP64 oracle GN products/s on a bounded sample: one of the step's views
+    (same samples, same parameters), scaled to the full 8-view product."""
+    from oracle import Oracle, num_threads
+    v0 = int(view_ids[0])
+    orc = Oracle(w.n, w.sh_degree, beta, cams_np[[v0]], w.width, w.height)
+    orc.set_samples(pix.shape[-1], pix[:1], wts[:1])
+    p = np.random.default_rng(0).normal(size=orc.P)
+    t0 = time.perf_counter()
+    orc.gn(p, lam)                       # first call also builds the record Jacobians it reuses
+    first = time.perf_counter() - t0
+    times = []
+    while sum(times) + first < budget_s and len(times) < 5:
+        t0 = time.perf_counter()
+        orc.gn(p, lam)
+        times.append(time.perf_counter() - t0)
+    t1 = float(np.median(times))
+    V = len(view_ids)
+    return {"value": 1.0 / (V * t1), "unit": "GN products/s", "cores": num_threads(), "kind": "oracle",
+            "sample": f"1 of the {V} batch views (camera {v0}), same 26 samples/tile and parameters; "
+                      f"median of {len(times)} GN products after a warm-up ({first:.1f} s, builds the "
+                      f"record Jacobians), time x {V} = one full product",
+            "seconds_per_view_product": t1}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--gn-reps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--n", type=int, default=100_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
+              "(view sharding, one all-reduce per GN product) is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2504_12905_amd import lmrs as L
+    from paper_2504_12905_amd import synth
+
+    dev = "cuda:0"
+    w = synth.config1(n=args.n)
+    cams = torch.tensor(w.cams, device=dev)
+    beta_gt = torch.tensor(w.beta_gt, device=dev)
+    log(f"[bench] {w.name}: rendering {w.cams.shape[0]} targets")
+    targets = render_targets(L, torch, w, beta_gt, cams, dev)
+    del beta_gt
+    V, k = w.views_per_step, w.samples_per_tile
+    beta = torch.tensor(w.beta_init, device=dev)
+    view_ids = torch.zeros(V, dtype=torch.int32, device=dev)
+    fr = L.Frame(w.n, w.sh_degree, beta, cams, w.width, w.height, V, view_ids=view_ids, k=k, sampled=True)
+    rep = torch.zeros(L.REPORT_FLOATS, device=dev)
+    rng = np.random.default_rng(w.seed)
+    ws = None
+
+    def step(it):
+        view_ids.copy_(torch.tensor(rng.choice(w.cams.shape[0], V, replace=False).astype(np.int32)))
+        # the binding allocates a larger workspace itself if the tile lists outgrow ws
+        L.lmrs_lm_step(fr, targets, L.lm_params(it, w.cg_iters, w.lam, seed=w.seed), report=rep, ws=ws)
+
+    log(f"[bench] warmup {args.warmup} LM steps")
+    it = 0
+    for _ in range(args.warmup):
+        step(it)
+        it += 1
+    torch.cuda.synchronize()
+    # grow the workspace once for the largest instance count seen, outside the timed region
+    ws = torch.empty(int(L._lib.lmrs_workspace_bytes(L.OP_LM, L.C.byref(fr.struct())) * 1.1) + 4096,
+                     dtype=torch.uint8, device=dev)
+    log(f"[bench] timing {args.steps} LM steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(it)
+        it += 1
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    products = w.cg_iters * args.steps
+    value = products / el
+    r = rep.cpu().numpy()
+    log(f"[bench] {el / args.steps * 1e3:.2f} ms/LM step, {value:.1f} GN products/s; last step: loss "
+        f"{r[0]:.4e} eta {r[1]:.3f} instances {r[7]:.0f}")
+
+    # --- the GN product on its own, at the current parameters and the last step's samples
+    L.lmrs_project(fr)
+    L.lmrs_bin_tiles(fr)
+    L.lmrs_render(fr)
+    torch.cuda.synchronize()
+    p = torch.randn(fr.P, generator=torch.Generator(device="cpu").manual_seed(0)).to(dev)
+    out = torch.empty_like(p)
+    gws = L.workspace(L.OP_GN, fr)
+    for _ in range(3):
+        L.lmrs_gn_product(fr, p, w.lam, out=out, ws=gws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.gn_reps):
+        L.lmrs_gn_product(fr, p, w.lam, out=out, ws=gws)
+    e1.record(stream)
+    e1.synchronize()
+    gn_ms = e0.elapsed_time(e1) / args.gn_reps
+    phases = np.zeros(4)
+    for _ in range(args.gn_reps):
+        phases += np.array(L.lmrs_gn_product_timed(fr, p, w.lam, out=out, ws=gws)[1])
+    phases /= args.gn_reps
+    log(f"[bench] GN product {gn_ms:.3f} ms (tangent {phases[0]:.3f}, fill {phases[1]:.3f}, "
+        f"fused splat {phases[2]:.3f}, chain {phases[3]:.3f})")
+
+    # --- algorithmic work of the fused splat kernel in this launch
+    last = fr.last.view(V * fr.T, k).to(torch.int64)
+    entries = int((last.max(dim=1).values + 1).clamp(min=0).sum().item())
+    pairs = int((last + 1).clamp(min=0).sum().item())
+    S = fr.S
+    b_alg = entries * BYTES_PER_ENTRY + S * BYTES_PER_PIXEL
+    f_alg = pairs * FLOPS_PER_PAIR
+    t_splat = phases[2] * 1e-3
+    gbs = b_alg / t_splat / 1e9
+    tflops = f_alg / t_splat / 1e12
+    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tflops / FP32_VECTOR_PEAK_TFLOPS
+    kernel_hash = hashlib.sha256(open(SPLAT_SOURCE, "rb").read()).hexdigest()
+    traffic = traffic_from_profile(kernel_hash)
+    bound_alu = alu_frac > hbm_frac
+    roofline = {
+        "kernel": "deriv_kernel<3> (fused J p / weight / J^T u splat of lmrs_gn_product)",
+        "bound": "alu" if bound_alu else "hbm",
+        "achieved": round(tflops if bound_alu else gbs, 4),
+        "peak": FP32_VECTOR_PEAK_TFLOPS if bound_alu else HBM_PEAK_GBS,
+        "unit": "TFLOP/s" if bound_alu else "GB/s",
+        "frac": round(alu_frac if bound_alu else hbm_frac, 6),
+        "traffic": traffic,
+        "hbm_gbs": round(gbs, 3), "hbm_frac": round(hbm_frac, 6),
+        "alu_tflops": round(tflops, 4), "alu_frac": round(alu_frac, 6),
+        "algorithmic_bytes": b_alg, "algorithmic_flops": f_alg,
+        "traversed_entries": entries, "pixel_entry_pairs": pairs, "sampled_pixels": S,
+        "ms_per_launch": round(phases[2], 4),
+    }
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline (bounded sample)")
+        cpu = cpu_baseline(w, fr.beta.cpu().numpy(), w.cams, view_ids.cpu().numpy(), fr.pix.cpu().numpy(),
+                           fr.w.cpu().numpy(), w.lam)
+        log(f"[bench] oracle {cpu['value']:.4f} GN products/s on {cpu['cores']} threads")
+
+    res = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GN products/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "gaussians": w.n, "sh_degree": w.sh_degree,
+                   "views_per_step": V, "views_total": int(w.cams.shape[0]), "resolution": [w.width, w.height],
+                   "samples_per_tile": k, "cg_iters": w.cg_iters, "lambda": w.lam,
+                   "gn_product_ms_isolated": round(gn_ms, 4),
+                   "gn_products_per_s_isolated": round(1e3 / gn_ms, 2),
+                   "gn_phase_ms": [round(x, 4) for x in phases]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

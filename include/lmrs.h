@@ -179,12 +179,23 @@ lmrs_status lmrs_jvp(const lmrs_frame* f, const lmrs_render_opts* o, const float
 lmrs_status lmrs_vjp(const lmrs_frame* f, const lmrs_render_opts* o, const float* u, float* out,
                      void* ws, size_t ws_bytes, void* stream);
 
-/* a6. Gauss-Newton product out = J^T W J p + lambda d.p (Alg. 1 line "u =
- * (J^T J + lambda I) p"; eq. 8, eq. 14), W from f->w. d: device [P] or NULL
+/* a6. Gauss-Newton product out = J^T W J p + lambda d.p, the operator product
+ * inside the PCG loop of Alg. 1 (eq. 8 with the sampled Hessian of eq. 14),
+ * W from f->w. d: device [P] or NULL
  * (all ones, the paper's lambda I). p, out: device [P], must not alias. */
 lmrs_status lmrs_gn_product(const lmrs_frame* f, const lmrs_render_opts* o, const float* p,
                             float lambda, const float* d, float* out, void* ws, size_t ws_bytes,
                             void* stream);
+
+/* Measurement variant of lmrs_gn_product: the same four launches (tangent
+ * projection, fused splat, zero fill, reverse chain) with HIP events
+ * recorded on `stream` between them; waits for the last event and writes
+ * the elapsed milliseconds of each launch to ms[4] (host):
+ * ms[0] tangent, ms[1] fill, ms[2] fused splat, ms[3] chain. For profiling
+ * and benchmarks; the result in out is identical to lmrs_gn_product's. */
+lmrs_status lmrs_gn_product_timed(const lmrs_frame* f, const lmrs_render_opts* o, const float* p,
+                                  float lambda, const float* d, float* out, void* ws, size_t ws_bytes,
+                                  void* stream, float* ms);
 
 /* a5. diag(J^T W J) (Alg. 1 preconditioner; Supp. A "Diag(J^T J) kernel"),
  * exact: per (view, Gaussian) the weighted Gram matrix of the screen-record

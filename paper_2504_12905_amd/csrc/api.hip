@@ -330,6 +330,42 @@ lmrs_status lmrs_gn_product(const lmrs_frame* f, const lmrs_render_opts* o, cons
   return hip_check("lmrs_gn_product");
 }
 
+lmrs_status lmrs_gn_product_timed(const lmrs_frame* f, const lmrs_render_opts* o, const float* p,
+                                  float lambda, const float* dvec, float* out, void* ws, size_t ws_bytes,
+                                  void* stream, float* ms) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_deriv_state(f));
+  LMRS_TRY(need(p, "p"));
+  LMRS_TRY(need(out, "out"));
+  LMRS_TRY(need(ms, "ms"));
+  if (p == out) return fail(LMRS_EINVAL, "p and out must not alias");
+  LMRS_TRY(check_ws(LMRS_OP_GN, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_GN, d, f->capacity, c);
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t ev[5];
+  for (int i = 0; i < 5; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) return hip_check("hipEventCreate");
+  (void)hipEventRecord(ev[0], st);
+  launch_tangent(f, d, *o, p, s.tan, st);
+  (void)hipEventRecord(ev[1], st);
+  launch_fill(s.grad2d, (int64_t)d.V * d.n * 9, 0.f, st);
+  (void)hipEventRecord(ev[2], st);
+  launch_deriv(3, f, d, *o, s.tan, nullptr, nullptr, s.grad2d, st);
+  (void)hipEventRecord(ev[3], st);
+  launch_chain_vjp(f, d, *o, s.grad2d, p, lambda, dvec, out, st);
+  (void)hipEventRecord(ev[4], st);
+  lmrs_status status = LMRS_OK;
+  if (hipEventSynchronize(ev[4]) != hipSuccess) status = hip_check("hipEventSynchronize");
+  for (int i = 0; i < 4 && status == LMRS_OK; ++i)
+    if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess) status = hip_check("hipEventElapsedTime");
+  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+  if (status != LMRS_OK) return status;
+  return hip_check("lmrs_gn_product_timed");
+}
+
 lmrs_status lmrs_gn_diag(const lmrs_frame* f, const lmrs_render_opts* o, float* out, void* ws,
                          size_t ws_bytes, void* stream) {
   LMRS_TRY(check_frame(f));

@@ -80,11 +80,12 @@ _lib.lmrs_render.argtypes = [_FP, _vp, _vp]
 _lib.lmrs_jvp.argtypes = [_FP, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_vjp.argtypes = [_FP, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_gn_product.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]
+_lib.lmrs_gn_product_timed.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp, _vp]
 _lib.lmrs_gn_diag.argtypes = [_FP, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_pcg.argtypes = [_FP, _vp, _vp, _f32, _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_lm_step.argtypes = [_FP, _vp, _vp, _vp, C.POINTER(LmParams), _vp, _vp, _vp, _sz, _vp]
 for _name in ("lmrs_project", "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp",
-              "lmrs_gn_product", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step"):
+              "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -243,6 +244,20 @@ def lmrs_gn_product(frame: Frame, p: torch.Tensor, lam: float, d: torch.Tensor |
     return out
 
 
+def lmrs_gn_product_timed(frame: Frame, p: torch.Tensor, lam: float, d: torch.Tensor | None = None,
+                          out: torch.Tensor | None = None, opts=None, stream=None,
+                          ws: torch.Tensor | None = None):
+    """Returns (out, [ms tangent, ms fill, ms fused splat, ms chain])."""
+    opts = opts or default_opts()
+    out = out if out is not None else torch.empty(frame.P, dtype=torch.float32, device=p.device)
+    ws = ws if ws is not None else workspace(OP_GN, frame)
+    ms = (C.c_float * 4)()
+    fs = frame.struct()
+    _check(_lib.lmrs_gn_product_timed(C.byref(fs), C.byref(opts), _ptr(p), float(lam), _ptr(d), _ptr(out),
+                                      _ptr(ws), ws.numel(), _stream(stream), ms), "lmrs_gn_product_timed")
+    return out, [float(x) for x in ms]
+
+
 def lmrs_gn_diag(frame: Frame, out: torch.Tensor | None = None, opts=None, stream=None):
     opts = opts or default_opts()
     out = out if out is not None else torch.empty(frame.P, dtype=torch.float32, device=frame.beta.device)
@@ -289,5 +304,6 @@ def lm_params(iter: int, cg_iters: int, lam: float, seed: int = 0, eta_cap: floa
 
 
 EXPORTS = ("lmrs_status_str", "lmrs_last_error", "lmrs_workspace_bytes", "lmrs_project", "lmrs_bin_tiles",
-           "lmrs_render", "lmrs_jvp", "lmrs_vjp", "lmrs_gn_product", "lmrs_gn_diag", "lmrs_pcg",
+           "lmrs_render", "lmrs_jvp", "lmrs_vjp", "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_diag",
+           "lmrs_pcg",
            "lmrs_lm_step")
