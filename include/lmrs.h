@@ -37,7 +37,7 @@
  * Cameras: lmrs_camera rows, world-to-camera R (row-major) and t, pinhole
  * fx fy cx cy; x right, y down, z forward; pixel (i, j) has centre
  * (i + 0.5, j + 0.5). Images are split in 16x16 tiles (Supp. A); width and
- * height must be multiples of 16. T = (width/16)(height/16) tiles per view,
+ * height must be multiples of 16, with at most 16384 tiles per view. T = (width/16)(height/16) tiles per view,
  * tile id = ty * (width/16) + tx, pixel-in-tile index = 16 * (y%16) + (x%16).
  *
  * Sampled pixels (Sec. 4.4, stratified per tile): k per tile, sample index
@@ -188,7 +188,7 @@ lmrs_status lmrs_gn_product(const lmrs_frame* f, const lmrs_render_opts* o, cons
                             void* stream);
 
 /* Measurement variant of lmrs_gn_product: the same four launches (tangent
- * projection, fused splat, zero fill, reverse chain) with HIP events
+ * projection, zero fill, fused splat, reverse chain) with HIP events
  * recorded on `stream` between them; waits for the last event and writes
  * the elapsed milliseconds of each launch to ms[4] (host):
  * ms[0] tangent, ms[1] fill, ms[2] fused splat, ms[3] chain. For profiling

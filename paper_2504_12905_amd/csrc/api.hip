@@ -70,6 +70,7 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
   const bool need_pcg = op == LMRS_OP_PCG || op == LMRS_OP_LM;
   if (need_bin) {
     s.bin.counts = c.take<int32_t>((size_t)d.V * d.T);
+    s.bin.chunk_hist = c.take<int32_t>((size_t)d.V * bin_chunks(d.n) * d.T);
     s.bin.keys = c.take<uint64_t>((size_t)capacity);
     s.bin.tmp = c.take<uint64_t>((size_t)capacity);
   }
@@ -108,6 +109,8 @@ lmrs_status check_frame(const lmrs_frame* f, bool need_samples_k = true) {
   if (!f->beta) return fail(LMRS_EINVAL, "beta is NULL");
   const int64_t tiles = (int64_t)f->n_views * (f->width / kTile) * (f->height / kTile);
   if (tiles > 0x7fffffffLL) return fail(LMRS_EINVAL, "too many tiles");
+  if ((int64_t)(f->width / kTile) * (f->height / kTile) > kMaxTilesPerView)
+    return fail(LMRS_EINVAL, "%d x %d image has more than %d tiles", f->width, f->height, kMaxTilesPerView);
   return LMRS_OK;
 }
 

@@ -19,7 +19,6 @@ namespace lmrs {
 
 constexpr int kTile = 16;
 constexpr int kWave = 64;
-constexpr int kMaxPg = 11 + 3 * 16;  // parameters per Gaussian at SH degree 3
 constexpr int kGram = 32;            // Gram entries kept per (view, Gaussian)
 
 // ------------------------------------------------------------------ duals
@@ -54,31 +53,40 @@ __device__ __forceinline__ dualf trsqrt(dualf x) {
 }
 
 // --------------------------------------------------------------- SH basis
+template <int DEG>
+struct ShDims {
+  static constexpr int K = (DEG + 1) * (DEG + 1);  // coefficients per channel
+  static constexpr int PG = 11 + 3 * K;            // parameters per Gaussian
+};
+
 // Real spherical harmonics, index l*l + l + m: Y_{l,0} = Y_l^0,
 // Y_{l,m} = sqrt(2) Re Y_l^m, Y_{l,-m} = sqrt(2) Im Y_l^m (m > 0), with the
 // Condon-Shortley phase in Y_l^m, written as polynomials of a unit direction.
-template <class T>
-__device__ __forceinline__ void sh_eval(int deg, T x, T y, T z, T* Y) {
+template <int DEG, class T>
+__device__ __forceinline__ void sh_eval(T x, T y, T z, T* Y) {
   Y[0] = T(0.28209479177387814f);
-  if (deg < 1) return;
-  Y[1] = T(-0.48860251190291987f) * y;
-  Y[2] = T(0.48860251190291987f) * z;
-  Y[3] = T(-0.48860251190291987f) * x;
-  if (deg < 2) return;
-  const T xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = T(1.0925484305920792f) * x * y;
-  Y[5] = T(-1.0925484305920792f) * y * z;
-  Y[6] = T(0.31539156525252005f) * (T(2.f) * zz - xx - yy);
-  Y[7] = T(-1.0925484305920792f) * x * z;
-  Y[8] = T(0.5462742152960396f) * (xx - yy);
-  if (deg < 3) return;
-  Y[9] = T(-0.5900435899266435f) * y * (T(3.f) * xx - yy);
-  Y[10] = T(2.890611442640554f) * x * y * z;
-  Y[11] = T(-0.4570457994644658f) * y * (T(4.f) * zz - xx - yy);
-  Y[12] = T(0.3731763325901154f) * z * (T(2.f) * zz - T(3.f) * xx - T(3.f) * yy);
-  Y[13] = T(-0.4570457994644658f) * x * (T(4.f) * zz - xx - yy);
-  Y[14] = T(1.445305721320277f) * z * (xx - yy);
-  Y[15] = T(-0.5900435899266435f) * x * (xx - T(3.f) * yy);
+  if constexpr (DEG >= 1) {
+    Y[1] = T(-0.48860251190291987f) * y;
+    Y[2] = T(0.48860251190291987f) * z;
+    Y[3] = T(-0.48860251190291987f) * x;
+  }
+  if constexpr (DEG >= 2) {
+    const T xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = T(1.0925484305920792f) * x * y;
+    Y[5] = T(-1.0925484305920792f) * y * z;
+    Y[6] = T(0.31539156525252005f) * (T(2.f) * zz - xx - yy);
+    Y[7] = T(-1.0925484305920792f) * x * z;
+    Y[8] = T(0.5462742152960396f) * (xx - yy);
+    if constexpr (DEG >= 3) {
+      Y[9] = T(-0.5900435899266435f) * y * (T(3.f) * xx - yy);
+      Y[10] = T(2.890611442640554f) * x * y * z;
+      Y[11] = T(-0.4570457994644658f) * y * (T(4.f) * zz - xx - yy);
+      Y[12] = T(0.3731763325901154f) * z * (T(2.f) * zz - T(3.f) * xx - T(3.f) * yy);
+      Y[13] = T(-0.4570457994644658f) * x * (T(4.f) * zz - xx - yy);
+      Y[14] = T(1.445305721320277f) * z * (xx - yy);
+      Y[15] = T(-0.5900435899266435f) * x * (xx - T(3.f) * yy);
+    }
+  }
 }
 
 // --------------------------------------------------------------- cameras
@@ -110,21 +118,22 @@ __device__ __forceinline__ void decision_point(const lmrs_camera& c, float mx, f
   *v = __fmaf_rn(c.fy, __fdiv_rn(tc[1], tc[2]), c.cy);
 }
 
-// Load the P_g parameters of Gaussian g (component-major beta).
-template <class T>
-__device__ __forceinline__ void load_params(const float* beta, int n, int g, int pg, T* prm) {
-  for (int j = 0; j < pg; ++j) prm[j] = T(beta[(size_t)j * n + g]);
+// Load the PG parameters of Gaussian g (component-major beta).
+template <int PG, class T>
+__device__ __forceinline__ void load_params(const float* beta, int n, int g, T* prm) {
+#pragma unroll
+  for (int j = 0; j < PG; ++j) prm[j] = T(beta[(size_t)j * n + g]);
 }
 
 // ----------------------------------------------------------- projection
-// Screen record (u, v, A, B, C, opacity, r, g, b) of one Gaussian in one view.
-// Sigma = R S S^T R^T (eq. 2); Sigma_2D = J W Sigma W^T J^T + lowpass I with
-// J the pinhole Jacobian at the camera-space mean, computed as K K^T with
-// K = J W R S; the conic is Sigma_2D^-1. Colour 0.5 + sum_k Y_k(dir) f_k,
-// dir the unit vector from the camera centre to the mean.
+// Geometry of the screen record, (u, v, A, B, C), from mean, log-scale and
+// quaternion (prm[0..10)). Sigma = R S S^T R^T (eq. 2); Sigma_2D =
+// J W Sigma W^T J^T + lowpass I with J the pinhole Jacobian at the
+// camera-space mean, computed as K K^T with K = J W R S; the conic is
+// Sigma_2D^-1.
 template <class T>
-__device__ __forceinline__ void proj_core(const T* prm, int deg, const CamView& cv, float lowpass,
-                                          T* rec, float* a_out, float* b_out, float* c_out) {
+__device__ __forceinline__ void proj_geom(const T* prm, const CamView& cv, float lowpass, T* rec,
+                                          float* a_out, float* b_out, float* c_out) {
   const lmrs_camera& c = cv.c;
   const T mx = prm[0], my = prm[1], mz = prm[2];
   const T tx = T(c.R[0]) * mx + T(c.R[1]) * my + T(c.R[2]) * mz + T(c.t[0]);
@@ -140,12 +149,15 @@ __device__ __forceinline__ void proj_core(const T* prm, int deg, const CamView& 
   const T J00 = T(c.fx) * iz, J02 = -(T(c.fx) * tx * iz * iz);
   const T J11 = T(c.fy) * iz, J12 = -(T(c.fy) * ty * iz * iz);
   T Tm[6];
+#pragma unroll
   for (int j = 0; j < 3; ++j) {
     Tm[j] = J00 * T(c.R[j]) + J02 * T(c.R[6 + j]);
     Tm[3 + j] = J11 * T(c.R[3 + j]) + J12 * T(c.R[6 + j]);
   }
   T K[6];
+#pragma unroll
   for (int i = 0; i < 2; ++i)
+#pragma unroll
     for (int j = 0; j < 3; ++j)
       K[3 * i + j] = (Tm[3 * i + 0] * R[j] + Tm[3 * i + 1] * R[3 + j] + Tm[3 * i + 2] * R[6 + j]) * s[j];
   const T a = K[0] * K[0] + K[1] * K[1] + K[2] * K[2] + T(lowpass);
@@ -157,24 +169,73 @@ __device__ __forceinline__ void proj_core(const T* prm, int deg, const CamView& 
   rec[2] = cc * idet;
   rec[3] = -(b * idet);
   rec[4] = a * idet;
-  rec[5] = T(1.f) / (T(1.f) + texp(-prm[10]));
-  T dx = mx - T(cv.pos[0]), dy = my - T(cv.pos[1]), dz = mz - T(cv.pos[2]);
-  const T dinv = trsqrt(dx * dx + dy * dy + dz * dz);
-  dx = dx * dinv; dy = dy * dinv; dz = dz * dinv;
-  T Y[16];
-  sh_eval(deg, dx, dy, dz, Y);
-  const int K2 = (deg + 1) * (deg + 1);
-  for (int ch = 0; ch < 3; ++ch) {
-    T acc = T(0.5f);
-    for (int k = 0; k < K2; ++k) acc = acc + Y[k] * prm[11 + 3 * k + ch];
-    rec[6 + ch] = acc;
-  }
   if (a_out) { *a_out = tval(a); *b_out = tval(b); *c_out = tval(cc); }
 }
 
+// Unit direction from the camera centre to the mean.
+template <class T>
+__device__ __forceinline__ void view_dir(const T* prm, const CamView& cv, T* d) {
+  T dx = prm[0] - T(cv.pos[0]), dy = prm[1] - T(cv.pos[1]), dz = prm[2] - T(cv.pos[2]);
+  const T dinv = trsqrt(dx * dx + dy * dy + dz * dz);
+  d[0] = dx * dinv; d[1] = dy * dinv; d[2] = dz * dinv;
+}
+
+// View-dependent colour 0.5 + sum_k Y_k(dir) f_k (prm[11 + 3k + c] = f_kc).
+template <int DEG, class T>
+__device__ __forceinline__ void proj_color(const T* prm, const CamView& cv, T* rgb) {
+  constexpr int K = ShDims<DEG>::K;
+  T d[3];
+  view_dir(prm, cv, d);
+  T Y[K];
+  sh_eval<DEG>(d[0], d[1], d[2], Y);
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    T acc = T(0.5f);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = acc + Y[k] * prm[11 + 3 * k + ch];
+    rgb[ch] = acc;
+  }
+}
+
+// Screen record (u, v, A, B, C, opacity, r, g, b) of one Gaussian in one view.
+template <int DEG, class T>
+__device__ __forceinline__ void proj_core(const T* prm, const CamView& cv, float lowpass, T* rec, float* a_out,
+                                          float* b_out, float* c_out) {
+  proj_geom(prm, cv, lowpass, rec, a_out, b_out, c_out);
+  rec[5] = T(1.f) / (T(1.f) + texp(-prm[10]));
+  proj_color<DEG>(prm, cv, rec + 6);
+}
+
+// d rgb / d mean (3x3, [channel][axis]) through the view direction, by one
+// dual pass of the SH basis per axis.
+template <int DEG>
+__device__ __forceinline__ void color_mean_jacobian(const float* prm, const CamView& cv, float* drgb) {
+  constexpr int K = ShDims<DEG>::K;
+  float dx = prm[0] - cv.pos[0], dy = prm[1] - cv.pos[1], dz = prm[2] - cv.pos[2];
+  const float dinv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+  dx *= dinv; dy *= dinv; dz *= dinv;
+  const float dd[3] = {dx, dy, dz};
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    // tangent of the unit direction along mean axis ax: (e_ax - d d_ax) / |dir|
+    dualf Yd[K];
+    sh_eval<DEG>(dualf(dx, ((ax == 0) - dx * dd[ax]) * dinv), dualf(dy, ((ax == 1) - dy * dd[ax]) * dinv),
+                 dualf(dz, ((ax == 2) - dz * dd[ax]) * dinv), Yd);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 1; k < K; ++k) acc += Yd[k].d * prm[11 + 3 * k + ch];
+      drgb[3 * ch + ax] = acc;
+    }
+  }
+}
+
 // Adjoint of proj_core: gp[j] += sum_q grec[q] d rec_q / d prm_j.
-__device__ __forceinline__ void proj_vjp(const float* prm, int deg, const CamView& cv, float lowpass,
-                                         const float* gr, float* gp) {
+template <int DEG>
+__device__ __forceinline__ void proj_vjp(const float* prm, const CamView& cv, float lowpass, const float* gr,
+                                         float* gp) {
+  constexpr int K2 = ShDims<DEG>::K;
   const lmrs_camera& c = cv.c;
   const float mx = prm[0], my = prm[1], mz = prm[2];
   const float tx = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
@@ -189,15 +250,20 @@ __device__ __forceinline__ void proj_vjp(const float* prm, int deg, const CamVie
   const float s[3] = {expf(prm[3]), expf(prm[4]), expf(prm[5])};
   const float J00 = c.fx * iz, J02 = -c.fx * tx * iz2, J11 = c.fy * iz, J12 = -c.fy * ty * iz2;
   float Tm[6];
+#pragma unroll
   for (int j = 0; j < 3; ++j) {
     Tm[j] = J00 * c.R[j] + J02 * c.R[6 + j];
     Tm[3 + j] = J11 * c.R[3 + j] + J12 * c.R[6 + j];
   }
   float M[9];
+#pragma unroll
   for (int l = 0; l < 3; ++l)
+#pragma unroll
     for (int j = 0; j < 3; ++j) M[3 * l + j] = R[3 * l + j] * s[j];
   float K[6];
+#pragma unroll
   for (int i = 0; i < 2; ++i)
+#pragma unroll
     for (int j = 0; j < 3; ++j)
       K[3 * i + j] = Tm[3 * i] * M[j] + Tm[3 * i + 1] * M[3 + j] + Tm[3 * i + 2] * M[6 + j];
   const float a = K[0] * K[0] + K[1] * K[1] + K[2] * K[2] + lowpass;
@@ -210,25 +276,32 @@ __device__ __forceinline__ void proj_vjp(const float* prm, int deg, const CamVie
   const float gb = (2.f * b * cc * gA - (a * cc + b * b) * gB + 2.f * a * b * gC) * id2;
   const float gc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
   float gK[6];
+#pragma unroll
   for (int j = 0; j < 3; ++j) {
     gK[j] = 2.f * ga * K[j] + gb * K[3 + j];
     gK[3 + j] = 2.f * gc * K[3 + j] + gb * K[j];
   }
   // K = Tm M
   float gTm[6];
+#pragma unroll
   for (int i = 0; i < 2; ++i)
+#pragma unroll
     for (int l = 0; l < 3; ++l)
       gTm[3 * i + l] = gK[3 * i] * M[3 * l] + gK[3 * i + 1] * M[3 * l + 1] + gK[3 * i + 2] * M[3 * l + 2];
   float gR[9], gs[3] = {0.f, 0.f, 0.f};
+#pragma unroll
   for (int l = 0; l < 3; ++l)
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
       const float gM = Tm[l] * gK[j] + Tm[3 + l] * gK[3 + j];
       gR[3 * l + j] = gM * s[j];
       gs[j] += gM * R[3 * l + j];
     }
+#pragma unroll
   for (int j = 0; j < 3; ++j) gp[3 + j] += gs[j] * s[j];
   // Tm = J W
   float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
+#pragma unroll
   for (int j = 0; j < 3; ++j) {
     gJ00 += gTm[j] * c.R[j];
     gJ02 += gTm[j] * c.R[6 + j];
@@ -240,6 +313,7 @@ __device__ __forceinline__ void proj_vjp(const float* prm, int deg, const CamVie
   const float gtz = -gJ00 * c.fx * iz2 + 2.f * gJ02 * c.fx * tx * iz3 - gJ11 * c.fy * iz2 +
                     2.f * gJ12 * c.fy * ty * iz3 - gu * c.fx * tx * iz2 - gv * c.fy * ty * iz2;
   float gm[3];
+#pragma unroll
   for (int i = 0; i < 3; ++i) gm[i] = c.R[i] * gtx + c.R[3 + i] * gty + c.R[6 + i] * gtz;
   // rotation of the normalised quaternion
   const float gw = 2.f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
@@ -257,33 +331,20 @@ __device__ __forceinline__ void proj_vjp(const float* prm, int deg, const CamVie
   // opacity
   const float op = 1.f / (1.f + expf(-prm[10]));
   gp[10] += go * op * (1.f - op);
-  // colour
-  float dx = mx - cv.pos[0], dy = my - cv.pos[1], dz = mz - cv.pos[2];
-  const float dinv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
-  dx *= dinv; dy *= dinv; dz *= dinv;
-  const int K2 = (deg + 1) * (deg + 1);
-  float Y[16];
-  sh_eval(deg, dx, dy, dz, Y);
+  // colour: d/d f_kc = Y_k(dir); d/d mean through the direction
+  float d[3];
+  view_dir(prm, cv, d);
+  float Y[K2];
+  sh_eval<DEG>(d[0], d[1], d[2], Y);
+#pragma unroll
   for (int k = 0; k < K2; ++k)
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) gp[11 + 3 * k + ch] += gr[6 + ch] * Y[k];
-  if (deg > 0) {
-    // d/d dir of sum_k gamma_k Y_k(dir), gamma_k = sum_c grgb_c f_kc, one dual pass per axis
-    float gamma[16];
-    for (int k = 0; k < K2; ++k)
-      gamma[k] = gr[6] * prm[11 + 3 * k] + gr[7] * prm[12 + 3 * k] + gr[8] * prm[13 + 3 * k];
-    float gd[3];
-    for (int ax = 0; ax < 3; ++ax) {
-      dualf Yd[16];
-      sh_eval(deg, dualf(dx, ax == 0 ? 1.f : 0.f), dualf(dy, ax == 1 ? 1.f : 0.f),
-              dualf(dz, ax == 2 ? 1.f : 0.f), Yd);
-      float acc = 0.f;
-      for (int k = 1; k < K2; ++k) acc += gamma[k] * Yd[k].d;
-      gd[ax] = acc;
-    }
-    const float dd = dx * gd[0] + dy * gd[1] + dz * gd[2];
-    gm[0] += (gd[0] - dx * dd) * dinv;
-    gm[1] += (gd[1] - dy * dd) * dinv;
-    gm[2] += (gd[2] - dz * dd) * dinv;
+  if constexpr (DEG > 0) {
+    float J[9];
+    color_mean_jacobian<DEG>(prm, cv, J);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) gm[ax] += gr[6] * J[ax] + gr[7] * J[3 + ax] + gr[8] * J[6 + ax];
   }
   gp[0] += gm[0];
   gp[1] += gm[1];

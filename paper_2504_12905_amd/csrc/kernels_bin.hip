@@ -1,13 +1,20 @@
 // Tile binning and depth sort (Sec. 3: Gaussians are sorted by depth before
 // blending; Supp. A: 16x16 tiles).
 //
-// 1. count: every visible (view, Gaussian) adds 1 to each tile of its rect.
-// 2. scan: exclusive prefix sum over the V*T counts -> tile_start (int64),
-//    total -> n_instances; counts are reset to serve as per-tile cursors.
-// 3. emit: each (view, Gaussian) writes the 64-bit key (depth bits << 32 | id)
-//    into a free slot of each of its tiles' segments. Depths are > znear > 0,
-//    so their IEEE bits order like the values; the id breaks ties.
-// 4. sort: one workgroup per tile sorts its segment. Segments of up to 4096
+// Gaussians of one view are processed in chunks of kChunk by one workgroup,
+// which keeps a histogram / cursor over all tiles of the view in LDS, so the
+// only atomics are LDS atomics inside a workgroup (a single hot tile can hold
+// thousands of entries; global atomics on it serialise across the chip).
+// 1. hist: per (view, chunk) count of the chunk's Gaussians per tile.
+// 2. column scan: per (view, tile), the chunks' counts become running offsets
+//    and the tile total is formed.
+// 3. scan: exclusive prefix sum over the V*T totals -> tile_start (int64),
+//    total -> n_instances.
+// 4. emit: each (view, Gaussian) writes the 64-bit key (depth bits << 32 | id)
+//    into its tiles' segments at (tile start + chunk offset + LDS cursor).
+//    Depths are > znear > 0, so their IEEE bits order like the values; the id
+//    breaks ties.
+// 5. sort: one workgroup per tile sorts its segment. Segments of up to 4096
 //    keys are sorted in LDS by a bitonic network; longer ones sort 4096-key
 //    runs in LDS and then merge runs pairwise in HBM, each key placed at
 //    (its index in its run) + (number of smaller keys in the partner run),
@@ -21,15 +28,42 @@ namespace {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortChunk = 4096;
+constexpr int kChunk = 8192;  // Gaussians per binning workgroup
 
-__global__ __launch_bounds__(256) void count_kernel(const int4* __restrict__ rect, int n, int TX, int T,
-                                                    int32_t* __restrict__ counts) {
-  const int g = blockIdx.x * 256 + threadIdx.x;
-  const int v = blockIdx.y;
-  if (g >= n) return;
-  const int4 rc = rect[(size_t)v * n + g];
-  for (int ty = rc.y; ty < rc.w; ++ty)
-    for (int tx = rc.x; tx < rc.z; ++tx) atomicAdd(&counts[(size_t)v * T + ty * TX + tx], 1);
+constexpr int kBinThreads = 1024;
+
+__global__ __launch_bounds__(kBinThreads) void hist_kernel(const int4* __restrict__ rect, int n, int TX, int T,
+                                                            int n_chunks, int32_t* __restrict__ chunk_hist) {
+  extern __shared__ int32_t s_hist[];
+  const int chunk = blockIdx.x, v = blockIdx.y;
+  for (int t = threadIdx.x; t < T; t += kBinThreads) s_hist[t] = 0;
+  __syncthreads();
+  const int g0 = chunk * kChunk;
+  const int g1 = min(n, g0 + kChunk);
+  for (int g = g0 + (int)threadIdx.x; g < g1; g += kBinThreads) {
+    const int4 rc = rect[(size_t)v * n + g];
+    for (int ty = rc.y; ty < rc.w; ++ty)
+      for (int tx = rc.x; tx < rc.z; ++tx) atomicAdd(&s_hist[ty * TX + tx], 1);
+  }
+  __syncthreads();
+  int32_t* dst = chunk_hist + ((size_t)v * n_chunks + chunk) * T;
+  for (int t = threadIdx.x; t < T; t += kBinThreads) dst[t] = s_hist[t];
+}
+
+// Per (view, tile): chunk counts -> running offsets; tile total -> counts.
+__global__ __launch_bounds__(256) void colscan_kernel(int32_t* __restrict__ chunk_hist, int V, int T,
+                                                      int n_chunks, int32_t* __restrict__ counts) {
+  const int64_t vt = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (vt >= (int64_t)V * T) return;
+  const int v = (int)(vt / T), t = (int)(vt % T);
+  int32_t run = 0;
+  for (int c = 0; c < n_chunks; ++c) {
+    int32_t* h = chunk_hist + ((size_t)v * n_chunks + c) * T + t;
+    const int32_t x = *h;
+    *h = run;
+    run += x;
+  }
+  counts[vt] = run;
 }
 
 // Single workgroup of 1024 threads scans `m` counts.
@@ -62,25 +96,32 @@ __global__ __launch_bounds__(1024) void scan_kernel(int32_t* __restrict__ counts
   }
 }
 
-__global__ __launch_bounds__(256) void emit_kernel(const int4* __restrict__ rect,
-                                                   const float* __restrict__ rec, int n, int TX, int T,
-                                                   const int64_t* __restrict__ tile_start,
-                                                   int32_t* __restrict__ cursor,
-                                                   uint64_t* __restrict__ keys) {
-  const int g = blockIdx.x * 256 + threadIdx.x;
-  const int v = blockIdx.y;
-  if (g >= n) return;
-  const size_t vg = (size_t)v * n + g;
-  const int4 rc = rect[vg];
-  if (rc.x >= rc.z) return;
-  const uint32_t dbits = __float_as_uint(rec[vg * LMRS_REC + 9]);
-  const uint64_t key = ((uint64_t)dbits << 32) | (uint32_t)g;
-  for (int ty = rc.y; ty < rc.w; ++ty)
-    for (int tx = rc.x; tx < rc.z; ++tx) {
-      const size_t tile = (size_t)v * T + ty * TX + tx;
-      const int slot = atomicAdd(&cursor[tile], 1);
-      keys[tile_start[tile] + slot] = key;
-    }
+__global__ __launch_bounds__(kBinThreads) void emit_kernel(const int4* __restrict__ rect,
+                                                            const float* __restrict__ rec, int n, int TX, int T,
+                                                            int n_chunks, const int32_t* __restrict__ chunk_hist,
+                                                            const int64_t* __restrict__ tile_start,
+                                                            uint64_t* __restrict__ keys) {
+  extern __shared__ int32_t s_cur[];
+  const int chunk = blockIdx.x, v = blockIdx.y;
+  const int32_t* off = chunk_hist + ((size_t)v * n_chunks + chunk) * T;
+  for (int t = threadIdx.x; t < T; t += kBinThreads) s_cur[t] = off[t];
+  __syncthreads();
+  const int64_t* ts = tile_start + (size_t)v * T;
+  const int g0 = chunk * kChunk;
+  const int g1 = min(n, g0 + kChunk);
+  for (int g = g0 + (int)threadIdx.x; g < g1; g += kBinThreads) {
+    const size_t vg = (size_t)v * n + g;
+    const int4 rc = rect[vg];
+    if (rc.x >= rc.z) continue;
+    const uint32_t dbits = __float_as_uint(rec[vg * LMRS_REC + 9]);
+    const uint64_t key = ((uint64_t)dbits << 32) | (uint32_t)g;
+    for (int ty = rc.y; ty < rc.w; ++ty)
+      for (int tx = rc.x; tx < rc.z; ++tx) {
+        const int t = ty * TX + tx;
+        const int slot = atomicAdd(&s_cur[t], 1);
+        keys[ts[t] + slot] = key;
+      }
+  }
 }
 
 // Bitonic sort of s[0..m) in LDS, m a power of two.
@@ -161,18 +202,23 @@ __global__ __launch_bounds__(kSortThreads) void sort_kernel(const int64_t* __res
 
 }  // namespace
 
+int bin_chunks(int n) { return (n + kChunk - 1) / kChunk; }
+
 void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
+  const int nc = bin_chunks(d.n);
+  const size_t lds = (size_t)d.T * sizeof(int32_t);
+  hist_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), d.n, d.TX, d.T,
+                                                      nc, b.chunk_hist);
   const int64_t m = (int64_t)d.V * d.T;
-  (void)hipMemsetAsync(b.counts, 0, m * sizeof(int32_t), s);
-  dim3 grid((d.n + 255) / 256, d.V);
-  count_kernel<<<grid, 256, 0, s>>>(reinterpret_cast<const int4*>(f->rect), d.n, d.TX, d.T, b.counts);
+  colscan_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(b.chunk_hist, d.V, d.T, nc, b.counts);
   scan_kernel<<<1, 1024, 0, s>>>(b.counts, m, f->tile_start, f->n_instances);
 }
 
 void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
-  dim3 grid((d.n + 255) / 256, d.V);
-  emit_kernel<<<grid, 256, 0, s>>>(reinterpret_cast<const int4*>(f->rect), f->rec, d.n, d.TX, d.T,
-                                   f->tile_start, b.counts, b.keys);
+  const int nc = bin_chunks(d.n);
+  const size_t lds = (size_t)d.T * sizeof(int32_t);
+  emit_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), f->rec, d.n, d.TX,
+                                                      d.T, nc, b.chunk_hist, f->tile_start, b.keys);
   sort_kernel<<<(unsigned)((int64_t)d.V * d.T), kSortThreads, 0, s>>>(f->tile_start, b.keys, b.tmp,
                                                                      f->ids);
 }

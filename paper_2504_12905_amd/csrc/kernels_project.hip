@@ -15,11 +15,13 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__global__ __launch_bounds__(kBlock) void project_kernel(const float* __restrict__ beta, int n, int deg,
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void project_kernel(const float* __restrict__ beta, int n,
                                                          const lmrs_camera* __restrict__ cams,
                                                          const int32_t* __restrict__ view_ids, int TX,
                                                          int TY, lmrs_render_opts o,
                                                          float* __restrict__ rec, int4* __restrict__ rect) {
+  constexpr int PG = ShDims<DEG>::PG;
   const int g = blockIdx.x * kBlock + threadIdx.x;
   const int v = blockIdx.y;
   if (g >= n) return;
@@ -32,11 +34,10 @@ __global__ __launch_bounds__(kBlock) void project_kernel(const float* __restrict
   float r[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float radius = 0.f;
   if (tc[2] > o.znear && isfinite(u) && isfinite(vv)) {
-    float prm[kMaxPg];
-    const int pg = 11 + 3 * (deg + 1) * (deg + 1);
-    load_params(beta, n, g, pg, prm);
+    float prm[PG];
+    load_params<PG>(beta, n, g, prm);
     float a, b, c;
-    proj_core(prm, deg, cv, o.lowpass, r, &a, &b, &c);
+    proj_core<DEG>(prm, cv, o.lowpass, r, &a, &b, &c);
     r[0] = u;
     r[1] = vv;
     const float lam = 0.5f * (a + c) + sqrtf(0.25f * (a - c) * (a - c) + b * b);
@@ -61,12 +62,14 @@ __global__ __launch_bounds__(kBlock) void project_kernel(const float* __restrict
 }
 
 // Tangent of the screen record along direction p (forward mode).
+template <int DEG>
 __global__ __launch_bounds__(kBlock) void tangent_kernel(const float* __restrict__ beta,
-                                                         const float* __restrict__ p, int n, int deg,
+                                                         const float* __restrict__ p, int n,
                                                          const lmrs_camera* __restrict__ cams,
                                                          const int32_t* __restrict__ view_ids,
                                                          const int4* __restrict__ rect, float lowpass,
                                                          float* __restrict__ tan) {
+  constexpr int PG = ShDims<DEG>::PG;
   const int g = blockIdx.x * kBlock + threadIdx.x;
   const int v = blockIdx.y;
   if (g >= n) return;
@@ -78,39 +81,43 @@ __global__ __launch_bounds__(kBlock) void tangent_kernel(const float* __restrict
     return;
   }
   const CamView cv = load_cam(cams, view_ids, v);
-  const int pg = 11 + 3 * (deg + 1) * (deg + 1);
-  dualf prm[kMaxPg];
-  for (int j = 0; j < pg; ++j) prm[j] = dualf(beta[(size_t)j * n + g], p[(size_t)j * n + g]);
+  dualf prm[PG];
+#pragma unroll
+  for (int j = 0; j < PG; ++j) prm[j] = dualf(beta[(size_t)j * n + g], p[(size_t)j * n + g]);
   dualf r[9];
-  proj_core(prm, deg, cv, lowpass, r, nullptr, nullptr, nullptr);
+  proj_core<DEG>(prm, cv, lowpass, r, nullptr, nullptr, nullptr);
   out[0] = make_float4(r[0].d, r[1].d, r[2].d, r[3].d);
   out[1] = make_float4(r[4].d, r[5].d, r[6].d, r[7].d);
   out[2] = make_float4(r[8].d, 0.f, 0.f, 0.f);
 }
 
 // out[beta_g] = sum_v (d rec_vg / d beta_g)^T grad2d[v][:][g]  (+ lambda d p)
+template <int DEG>
 __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
-    const float* __restrict__ beta, int n, int deg, int V, const lmrs_camera* __restrict__ cams,
+    const float* __restrict__ beta, int n, int V, const lmrs_camera* __restrict__ cams,
     const int32_t* __restrict__ view_ids, float lowpass, const float* __restrict__ grad2d,
     const float* __restrict__ p, float lambda, const float* __restrict__ dvec, float* __restrict__ out) {
+  constexpr int PG = ShDims<DEG>::PG;
   const int g = blockIdx.x * kBlock + threadIdx.x;
   if (g >= n) return;
-  const int pg = 11 + 3 * (deg + 1) * (deg + 1);
-  float prm[kMaxPg], gp[kMaxPg];
-  load_params(beta, n, g, pg, prm);
-  for (int j = 0; j < pg; ++j) gp[j] = 0.f;
+  float prm[PG], gp[PG];
+  load_params<PG>(beta, n, g, prm);
+#pragma unroll
+  for (int j = 0; j < PG; ++j) gp[j] = 0.f;
   for (int v = 0; v < V; ++v) {
     float gr[9];
     bool any = false;
+#pragma unroll
     for (int q = 0; q < 9; ++q) {
       gr[q] = grad2d[((size_t)v * 9 + q) * n + g];
       any |= gr[q] != 0.f;
     }
     if (!any) continue;
     const CamView cv = load_cam(cams, view_ids, v);
-    proj_vjp(prm, deg, cv, lowpass, gr, gp);
+    proj_vjp<DEG>(prm, cv, lowpass, gr, gp);
   }
-  for (int j = 0; j < pg; ++j) {
+#pragma unroll
+  for (int j = 0; j < PG; ++j) {
     const size_t idx = (size_t)j * n + g;
     float val = gp[j];
     if (p) val += lambda * (dvec ? dvec[idx] : 1.f) * p[idx];
@@ -122,56 +129,77 @@ __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
 // derivatives: D_j = col_j^T G col_j, col_j = d rec / d beta_j. Gram layout per
 // (view, Gaussian): [0,15) geometry (u v A B C) upper triangle, [15,30)
 // geometry x colour channel (3 k + c), 30 colour (same for all channels),
-// 31 opacity.
+// 31 opacity. Geometric columns (mean, log-scale, quaternion) come from one
+// dual pass each of the geometric projection; the mean's colour rows from
+// the SH basis derivative; opacity and SH columns have closed forms.
+template <int DEG>
 __global__ __launch_bounds__(kBlock) void chain_diag_kernel(
-    const float* __restrict__ beta, int n, int deg, int V, const lmrs_camera* __restrict__ cams,
+    const float* __restrict__ beta, int n, int V, const lmrs_camera* __restrict__ cams,
     const int32_t* __restrict__ view_ids, float lowpass, const float* __restrict__ gram,
     float* __restrict__ out) {
+  constexpr int K2 = ShDims<DEG>::K;
+  constexpr int PG = ShDims<DEG>::PG;
   const int g = blockIdx.x * kBlock + threadIdx.x;
   if (g >= n) return;
-  const int K2 = (deg + 1) * (deg + 1);
-  const int pg = 11 + 3 * K2;
-  float prm[kMaxPg], D[kMaxPg];
-  load_params(beta, n, g, pg, prm);
-  for (int j = 0; j < pg; ++j) D[j] = 0.f;
+  float prm[PG], D[PG];
+  load_params<PG>(beta, n, g, prm);
+#pragma unroll
+  for (int j = 0; j < PG; ++j) D[j] = 0.f;
   const float op = 1.f / (1.f + expf(-prm[10]));
   const float dop = op * (1.f - op);
   for (int v = 0; v < V; ++v) {
     float G[kGram];
     bool any = false;
+#pragma unroll
     for (int e = 0; e < kGram; ++e) {
       G[e] = gram[((size_t)v * kGram + e) * n + g];
       any |= G[e] != 0.f;
     }
     if (!any) continue;
     const CamView cv = load_cam(cams, view_ids, v);
-    // geometric parameters: mean (3), log-scale (3), quaternion (4)
+    float Jc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if constexpr (DEG > 0) color_mean_jacobian<DEG>(prm, cv, Jc);
+#pragma unroll
     for (int j = 0; j < 10; ++j) {
-      dualf dp[kMaxPg];
-      for (int i = 0; i < pg; ++i) dp[i] = dualf(prm[i], i == j ? 1.f : 0.f);
-      dualf r[9];
-      proj_core(dp, deg, cv, lowpass, r, nullptr, nullptr, nullptr);
-      float col[9];
-      for (int q = 0; q < 9; ++q) col[q] = r[q].d;
+      dualf dp[10];
+#pragma unroll
+      for (int i = 0; i < 10; ++i) dp[i] = dualf(prm[i], i == j ? 1.f : 0.f);
+      dualf r[5];
+      proj_geom(dp, cv, lowpass, r, nullptr, nullptr, nullptr);
+      float col[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) col[q] = r[q].d;
+      float crgb[3] = {0.f, 0.f, 0.f};
+      if (j < 3) {
+        crgb[0] = Jc[j];
+        crgb[1] = Jc[3 + j];
+        crgb[2] = Jc[6 + j];
+      }
       float acc = 0.f;
+#pragma unroll
       for (int a = 0; a < 5; ++a) {
         acc += G[sym5(a, a)] * col[a] * col[a];
+#pragma unroll
         for (int b = a + 1; b < 5; ++b) acc += 2.f * G[sym5(a, b)] * col[a] * col[b];
-        for (int c = 0; c < 3; ++c) acc += 2.f * G[15 + 3 * a + c] * col[a] * col[6 + c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc += 2.f * G[15 + 3 * a + c] * col[a] * crgb[c];
       }
-      for (int c = 0; c < 3; ++c) acc += G[30] * col[6 + c] * col[6 + c];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc += G[30] * crgb[c] * crgb[c];
       D[j] += acc;
     }
     D[10] += dop * dop * G[31];
-    // colour coefficients: d rgb_c / d f_kc = Y_k(dir)
-    float dx = prm[0] - cv.pos[0], dy = prm[1] - cv.pos[1], dz = prm[2] - cv.pos[2];
-    const float dinv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
-    float Y[16];
-    sh_eval(deg, dx * dinv, dy * dinv, dz * dinv, Y);
+    float d[3];
+    view_dir(prm, cv, d);
+    float Y[K2];
+    sh_eval<DEG>(d[0], d[1], d[2], Y);
+#pragma unroll
     for (int k = 0; k < K2; ++k)
+#pragma unroll
       for (int c = 0; c < 3; ++c) D[11 + 3 * k + c] += Y[k] * Y[k] * G[30];
   }
-  for (int j = 0; j < pg; ++j) out[(size_t)j * n + g] = D[j];
+#pragma unroll
+  for (int j = 0; j < PG; ++j) out[(size_t)j * n + g] = D[j];
 }
 
 __global__ void fill_kernel(float* __restrict__ x, int64_t count, float value) {
@@ -183,28 +211,48 @@ __global__ void fill_kernel(float* __restrict__ x, int64_t count, float value) {
 
 void launch_project(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
   dim3 grid((d.n + kBlock - 1) / kBlock, d.V);
-  project_kernel<<<grid, kBlock, 0, s>>>(f->beta, d.n, d.deg, f->cams, f->view_ids, d.TX, d.TY, o,
-                                         f->rec, reinterpret_cast<int4*>(f->rect));
+  auto* rect = reinterpret_cast<int4*>(f->rect);
+  switch (d.deg) {
+    case 0: project_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, f->cams, f->view_ids, d.TX, d.TY, o, f->rec, rect); break;
+    case 1: project_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, f->cams, f->view_ids, d.TX, d.TY, o, f->rec, rect); break;
+    case 2: project_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, f->cams, f->view_ids, d.TX, d.TY, o, f->rec, rect); break;
+    default: project_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, f->cams, f->view_ids, d.TX, d.TY, o, f->rec, rect); break;
+  }
 }
 
 void launch_tangent(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* p,
                     float* tan, hipStream_t s) {
   dim3 grid((d.n + kBlock - 1) / kBlock, d.V);
-  tangent_kernel<<<grid, kBlock, 0, s>>>(f->beta, p, d.n, d.deg, f->cams, f->view_ids,
-                                         reinterpret_cast<const int4*>(f->rect), o.lowpass, tan);
+  auto* rect = reinterpret_cast<const int4*>(f->rect);
+  switch (d.deg) {
+    case 0: tangent_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, f->cams, f->view_ids, rect, o.lowpass, tan); break;
+    case 1: tangent_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, f->cams, f->view_ids, rect, o.lowpass, tan); break;
+    case 2: tangent_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, f->cams, f->view_ids, rect, o.lowpass, tan); break;
+    default: tangent_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, f->cams, f->view_ids, rect, o.lowpass, tan); break;
+  }
 }
 
 void launch_chain_vjp(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                       const float* grad2d, const float* p, float lambda, const float* dvec, float* out,
                       hipStream_t s) {
-  chain_vjp_kernel<<<(d.n + kBlock - 1) / kBlock, kBlock, 0, s>>>(
-      f->beta, d.n, d.deg, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out);
+  const unsigned grid = (d.n + kBlock - 1) / kBlock;
+  switch (d.deg) {
+    case 0: chain_vjp_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out); break;
+    case 1: chain_vjp_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out); break;
+    case 2: chain_vjp_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out); break;
+    default: chain_vjp_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out); break;
+  }
 }
 
 void launch_chain_diag(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                        const float* gram, float* out, hipStream_t s) {
-  chain_diag_kernel<<<(d.n + kBlock - 1) / kBlock, kBlock, 0, s>>>(f->beta, d.n, d.deg, d.V, f->cams,
-                                                                    f->view_ids, o.lowpass, gram, out);
+  const unsigned grid = (d.n + kBlock - 1) / kBlock;
+  switch (d.deg) {
+    case 0: chain_diag_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, out); break;
+    case 1: chain_diag_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, out); break;
+    case 2: chain_diag_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, out); break;
+    default: chain_diag_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, out); break;
+  }
 }
 
 void launch_fill(float* x, int64_t count, float value, hipStream_t s) {

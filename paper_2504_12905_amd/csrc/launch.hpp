@@ -29,10 +29,13 @@ void launch_fill(float* x, int64_t count, float value, hipStream_t s);
 
 // binning (kernels_bin.hip)
 struct BinScratch {
-  int32_t* counts;  // [V*T]
-  uint64_t* keys;   // [capacity]
-  uint64_t* tmp;    // [capacity]
+  int32_t* counts;      // [V*T]
+  int32_t* chunk_hist;  // [V][bin_chunks(n)][T]
+  uint64_t* keys;       // [capacity]
+  uint64_t* tmp;        // [capacity]
 };
+constexpr int kMaxTilesPerView = 16384;  // LDS histogram of one view's tiles (64 KB)
+int bin_chunks(int n);
 void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s);
 void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s);
 
