@@ -377,44 +377,56 @@ __device__ __forceinline__ Alpha pair_alpha(float u, float v, float A, float B, 
 }
 
 // ---------------------------------------------------- wave64 collectives
+// Scans across the 64 lanes of a wave from DPP: row shifts by 1, 2, 4, 8
+// within each row of 16 lanes (these fold into v_add_f32_dpp), then the
+// row-15 and row-31 broadcasts carry the row totals to the later rows. They
+// must be called with all 64 lanes active.
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+namespace dpp {
+constexpr int kRowShr = 0x110;     // row_shr:n = kRowShr + n
+constexpr int kRowBcast15 = 0x142; // lane 15 of each row to the next row
+constexpr int kRowBcast31 = 0x143; // lane 31 to rows 2 and 3
+}  // namespace dpp
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_mov(float old, float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROW_MASK,
+                                                    0xf, false));
+}
+__device__ __forceinline__ float readlane(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ int readlane(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
+// reg with lane `lane` replaced by the wave-uniform `value`
+__device__ __forceinline__ float writelane(float reg, float value, int lane) {
+  return lane_id() == lane ? value : reg;
+}
+__device__ __forceinline__ int writelane(int reg, int value, int lane) { return lane_id() == lane ? value : reg; }
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uniform(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// Inclusive prefix sum over lanes 0..lane.
+__device__ __forceinline__ float scan_add(float x) {
+  x += dpp_mov<dpp::kRowShr + 1>(0.f, x);
+  x += dpp_mov<dpp::kRowShr + 2>(0.f, x);
+  x += dpp_mov<dpp::kRowShr + 4>(0.f, x);
+  x += dpp_mov<dpp::kRowShr + 8>(0.f, x);
+  x += dpp_mov<dpp::kRowBcast15, 0xa>(0.f, x);
+  x += dpp_mov<dpp::kRowBcast31, 0xc>(0.f, x);
   return x;
 }
+
+// Sum over all 64 lanes (wave-uniform).
+__device__ __forceinline__ float wave_total(float x) { return readlane(scan_add(x), kWave - 1); }
+
 __device__ __forceinline__ int wave_max_i(int x) {
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) x = max(x, __shfl_xor(x, d, kWave));
   return x;
 }
-__device__ __forceinline__ float incl_prod(float x, int lane) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const float y = __shfl_up(x, d, kWave);
-    if (lane >= d) x *= y;
-  }
-  return x;
-}
-__device__ __forceinline__ float incl_sum(float x, int lane) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const float y = __shfl_up(x, d, kWave);
-    if (lane >= d) x += y;
-  }
-  return x;
-}
-// sum over lanes >= this lane
-__device__ __forceinline__ float suffix_sum(float x, int lane) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const float y = __shfl_down(x, d, kWave);
-    if (lane + d < kWave) x += y;
-  }
-  return x;
-}
-__device__ __forceinline__ float bcast(float x, int src) { return __shfl(x, src, kWave); }
 
 // Upper-triangle index of (i, j), i <= j < 5, in a 5x5 symmetric block.
 __host__ __device__ constexpr int sym5(int i, int j) { return i * 5 - i * (i - 1) / 2 + (j - i); }

@@ -9,14 +9,18 @@
 // gradient. Here the lanes own list entries instead: a chunk of 64 entries
 // of the tile's depth-sorted list is loaded, one record per lane, and the
 // wave walks the tile's sampled pixels one after another. For each pixel
-// the transmittance in front of every entry is an exclusive prefix product
-// of (1 - alpha) across the lanes, carried from chunk to chunk; J p needs one
-// more prefix sum for its derivative; J^T u walks the chunks back to front
-// and needs a suffix sum for the colour blended behind each entry. Each lane
-// then holds its Gaussian's screen-space gradient summed over all pixels of
-// the tile and issues one atomic add per component: no per-Gaussian
-// cross-lane reduction. A pixel's loop stops at its last blended entry
-// (`last` from the render), so work follows the actual blend depth per pixel.
+// the transmittance in front of every entry is 2^(prefix sum of
+// log2(1 - alpha)) across the lanes (a DPP scan), carried from chunk to
+// chunk; J p needs one more prefix sum for its derivative. J^T u walks the
+// chunks back to front with the lane order reversed inside a chunk, so the
+// colour blended behind an entry and the transmittance product behind it are
+// prefix sums as well. Each lane then holds its Gaussian's screen-space
+// gradient summed over all pixels of the tile and issues one atomic add per
+// component: no per-Gaussian cross-lane reduction. A pixel's loop stops at
+// its last blended entry (`last` from the render), so work follows the
+// actual blend depth per pixel. Per-pixel state lives in lane registers
+// (pixel 64 s + l in slot s of lane l) and is read and written with
+// readlane / writelane.
 //
 // Discrete decisions (list, opacity skip, cap, stop position) come from the
 // render and are recomputed bit-identically by pair_alpha().
@@ -64,7 +68,39 @@ __device__ __forceinline__ RecF load_rec(const float* rec, size_t vg) {
   return RecF{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
 }
 
+// Pixel 64 s + l of a tile lives in slot s of lane l.
+template <int NS>
+struct PixelRegs {
+  float xc[NS], yc[NS], w[NS];
+  int last[NS];
+};
+
+template <int NS>
+__device__ __forceinline__ int load_pixel_regs(const uint8_t* pix, const float* wts, const int32_t* lastv, int k,
+                                               const TileCtx& c, PixelRegs<NS>& pr) {
+  int lmax = -1;
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int j = s * kWave + lane;
+    pr.xc[s] = pr.yc[s] = 0.f;
+    pr.w[s] = 0.f;
+    pr.last[s] = -1;
+    if (j < k) {
+      const int64_t i = c.tile_lin * k + j;
+      pixel_center(pix, k, c, j, &pr.xc[s], &pr.yc[s]);
+      pr.w[s] = wts ? wts[i] : 1.f;
+      if (lastv) pr.last[s] = lastv[i];
+      lmax = max(lmax, pr.last[s]);
+    }
+  }
+  return uniform(wave_max_i(lmax));
+}
+
+__device__ __forceinline__ float log2_om(bool inc, float a) { return inc ? __log2f(1.f - a) : 0.f; }
+
 // ------------------------------------------------------------------ render
+template <int NS>
 __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__ rec,
                                                        const int64_t* __restrict__ tile_start,
                                                        const int32_t* __restrict__ ids,
@@ -72,65 +108,75 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
                                                        int TX, int k, lmrs_render_opts o,
                                                        float* __restrict__ color, float* __restrict__ trans,
                                                        int32_t* __restrict__ last) {
-  __shared__ float s_xc[kMaxK], s_yc[kMaxK], s_T[kMaxK], s_C[3 * kMaxK];
-  __shared__ int s_last[kMaxK], s_done[kMaxK];
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX);
-  for (int j = lane; j < k; j += kWave) {
-    pixel_center(pix, k, c, j, &s_xc[j], &s_yc[j]);
-    s_T[j] = 1.f;
-    s_C[3 * j] = s_C[3 * j + 1] = s_C[3 * j + 2] = 0.f;
-    s_last[j] = -1;
-    s_done[j] = 0;
+  PixelRegs<NS> pr;
+  load_pixel_regs<NS>(pix, nullptr, nullptr, k, c, pr);
+  float sT[NS], sC0[NS], sC1[NS], sC2[NS];
+  int sLast[NS], sDone[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    sT[s] = 1.f;
+    sC0[s] = sC1[s] = sC2[s] = 0.f;
+    sLast[s] = -1;
+    sDone[s] = 0;
   }
-  __syncthreads();
+  const float log_tmin = __log2f(o.t_min);
   int remaining = k;
-  for (int64_t c0 = 0; c0 < c.len && remaining > 0; c0 += kWave) {
+  for (int c0 = 0; c0 < c.len && remaining > 0; c0 += kWave) {
     const bool valid = c0 + lane < c.len;
     RecF r{};
     if (valid) r = load_rec(rec, (size_t)c.v * n + ids[c.start + c0 + lane]);
-    for (int j = 0; j < k; ++j) {
-      if (s_done[j]) continue;
-      const Alpha al = pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, s_xc[j], s_yc[j], o);
-      const bool inc = valid && al.inc;
-      const float a = inc ? al.a : 0.f;
-      const float ip = incl_prod(1.f - a, lane);
-      float ep = __shfl_up(ip, 1, kWave);
-      if (lane == 0) ep = 1.f;
-      const float Tc = s_T[j];
-      const uint64_t stop = __ballot(inc && Tc * ip < o.t_min);
-      const int f = stop ? __ffsll((unsigned long long)stop) - 1 : kWave;
-      const bool ok = inc && lane < f;
-      const float wgt = ok ? a * Tc * ep : 0.f;
-      const float cr = wave_sum(wgt * r.r), cg = wave_sum(wgt * r.g), cb = wave_sum(wgt * r.b);
-      const uint64_t okm = __ballot(ok);
-      const float Tnext = f < kWave ? Tc * bcast(ep, f) : Tc * bcast(ip, kWave - 1);
-      if (lane == 0) {
-        s_C[3 * j] += cr;
-        s_C[3 * j + 1] += cg;
-        s_C[3 * j + 2] += cb;
-        if (okm) s_last[j] = (int)c0 + 63 - __clzll((long long)okm);
-        s_T[j] = Tnext;
-        if (f < kWave) s_done[j] = 1;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int cnt = min(kWave, k - s * kWave);
+      for (int l = 0; l < cnt; ++l) {
+        if (readlane(sDone[s], l)) continue;
+        const Alpha al = pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+        const bool inc = valid && al.inc;
+        const float a = inc ? al.a : 0.f;
+        const float lg = log2_om(inc, a);
+        const float Linc = scan_add(lg);
+        const float Tc = readlane(sT[s], l);
+        const float lTc = __log2f(Tc);
+        // first entry whose blending would take T below t_min
+        const uint64_t stop = __ballot(inc && lTc + Linc < log_tmin);
+        const int f = stop ? __ffsll((unsigned long long)stop) - 1 : kWave;
+        const bool ok = inc && lane < f;
+        const float Tex = Tc * __builtin_amdgcn_exp2f(Linc - lg);
+        const float wgt = ok ? a * Tex : 0.f;
+        const float cr = wave_total(wgt * r.r), cg = wave_total(wgt * r.g), cb = wave_total(wgt * r.b);
+        const uint64_t okm = __ballot(ok);
+        const float Tnext = f < kWave ? readlane(Tex, f) : Tc * __builtin_amdgcn_exp2f(readlane(Linc, kWave - 1));
+        sT[s] = writelane(sT[s], Tnext, l);
+        sC0[s] = writelane(sC0[s], readlane(sC0[s], l) + cr, l);
+        sC1[s] = writelane(sC1[s], readlane(sC1[s], l) + cg, l);
+        sC2[s] = writelane(sC2[s], readlane(sC2[s], l) + cb, l);
+        if (okm) sLast[s] = writelane(sLast[s], c0 + 63 - __clzll((long long)okm), l);
+        if (f < kWave) {
+          sDone[s] = writelane(sDone[s], 1, l);
+          --remaining;
+        }
       }
-      if (f < kWave) --remaining;
     }
   }
-  __syncthreads();
-  for (int j = lane; j < k; j += kWave) {
-    const int64_t i = c.tile_lin * k + j;
-    const float Tf = s_T[j];
-    color[3 * i] = s_C[3 * j] + Tf * o.bg[0];
-    color[3 * i + 1] = s_C[3 * j + 1] + Tf * o.bg[1];
-    color[3 * i + 2] = s_C[3 * j + 2] + Tf * o.bg[2];
-    trans[i] = Tf;
-    last[i] = s_last[j];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int j = s * kWave + lane;
+    if (j < k) {
+      const int64_t i = c.tile_lin * k + j;
+      color[3 * i] = sC0[s] + sT[s] * o.bg[0];
+      color[3 * i + 1] = sC1[s] + sT[s] * o.bg[1];
+      color[3 * i + 2] = sC2[s] + sT[s] * o.bg[2];
+      trans[i] = sT[s];
+      last[i] = sLast[s];
+    }
   }
 }
 
 // ----------------------------------------------------- J p, J^T u, fused GN
 // MODE 1: jp = J p.  MODE 2: grad2d += J^T u.  MODE 3: grad2d += J^T W J p.
-template <int MODE>
+template <int MODE, int NS>
 __global__ __launch_bounds__(kWave) void deriv_kernel(
     const float* __restrict__ rec, const float* __restrict__ tan, const int64_t* __restrict__ tile_start,
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
@@ -139,30 +185,22 @@ __global__ __launch_bounds__(kWave) void deriv_kernel(
     float* __restrict__ grad2d) {
   constexpr bool FWD = MODE != 2;
   constexpr bool REV = MODE != 1;
-  __shared__ float s_xc[kMaxK], s_yc[kMaxK], s_a[kMaxK], s_b[kMaxK], s_u[3 * kMaxK];
-  __shared__ int s_last[kMaxK];
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX);
-  int lmax = -1;
-  for (int j = lane; j < k; j += kWave) {
-    const int64_t i = c.tile_lin * k + j;
-    pixel_center(pix, k, c, j, &s_xc[j], &s_yc[j]);
-    s_last[j] = lastv[i];
-    lmax = max(lmax, s_last[j]);
-  }
-  lmax = wave_max_i(lmax);
-  __syncthreads();
+  PixelRegs<NS> pr;
+  const int lmax = load_pixel_regs<NS>(pix, wts, lastv, k, c, pr);
+  // forward: a = T in front of the chunk, b = its tangent, u0..u2 = d colour
+  // reverse: a = T behind the chunk range already walked, b = u . (colour behind + T_final bg), u = weights
+  float sa[NS], sb[NS], su0[NS], su1[NS], su2[NS];
 
   if (FWD) {
-    // s_a = T carried in front of the chunk, s_b = its derivative, s_u = d colour
-    for (int j = lane; j < k; j += kWave) {
-      s_a[j] = 1.f;
-      s_b[j] = 0.f;
-      s_u[3 * j] = s_u[3 * j + 1] = s_u[3 * j + 2] = 0.f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      sa[s] = 1.f;
+      sb[s] = su0[s] = su1[s] = su2[s] = 0.f;
     }
-    __syncthreads();
-    for (int64_t c0 = 0; c0 <= lmax; c0 += kWave) {
-      const int64_t e = c0 + lane;
+    for (int c0 = 0; c0 <= lmax; c0 += kWave) {
+      const int e = c0 + lane;
       const bool valid = e < c.len;
       RecF r{}, dr{};
       if (valid) {
@@ -170,91 +208,92 @@ __global__ __launch_bounds__(kWave) void deriv_kernel(
         r = load_rec(rec, vg);
         dr = load_rec(tan, vg);
       }
-      for (int j = 0; j < k; ++j) {
-        const int lj = s_last[j];
-        if (c0 > lj) continue;
-        const Alpha al = pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, s_xc[j], s_yc[j], o);
-        const bool inc = valid && e <= lj && al.inc;
-        float a = 0.f, da = 0.f;
-        if (inc) {
-          a = al.a;
-          if (!al.capped) {
-            const float ds = -(r.A * al.dx * dr.u + r.C * al.dy * dr.v) -
-                             0.5f * (dr.A * al.dx * al.dx + dr.C * al.dy * al.dy) - dr.B * al.dx * al.dy -
-                             r.B * (dr.u * al.dy + al.dx * dr.v);
-            da = al.es * (dr.o + r.o * ds);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int cnt = min(kWave, k - s * kWave);
+        for (int l = 0; l < cnt; ++l) {
+          const int lj = readlane(pr.last[s], l);
+          if (c0 > lj) continue;
+          const Alpha al =
+              pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+          const bool inc = valid && e <= lj && al.inc;
+          float a = 0.f, da = 0.f;
+          if (inc) {
+            a = al.a;
+            if (!al.capped) {
+              const float ds = -(r.A * al.dx * dr.u + r.C * al.dy * dr.v) -
+                               0.5f * (dr.A * al.dx * al.dx + dr.C * al.dy * al.dy) -
+                               dr.B * al.dx * al.dy - r.B * (dr.u * al.dy + al.dx * dr.v);
+              da = al.es * (dr.o + r.o * ds);
+            }
           }
-        }
-        const float om = 1.f - a;
-        const float ip = incl_prod(om, lane);
-        float ep = __shfl_up(ip, 1, kWave);
-        const float q = inc ? -da / om : 0.f;
-        const float iq = incl_sum(q, lane);
-        float eq = __shfl_up(iq, 1, kWave);
-        if (lane == 0) {
-          ep = 1.f;
-          eq = 0.f;
-        }
-        const float Tc = s_a[j], dTc = s_b[j];
-        const float Tn = Tc * ep;
-        const float dTn = ep * (dTc + Tc * eq);
-        float cr = 0.f, cg = 0.f, cb = 0.f;
-        if (inc) {
-          const float aT = a * Tn, gT = da * Tn + a * dTn;
-          cr = dr.r * aT + r.r * gT;
-          cg = dr.g * aT + r.g * gT;
-          cb = dr.b * aT + r.b * gT;
-        }
-        cr = wave_sum(cr);
-        cg = wave_sum(cg);
-        cb = wave_sum(cb);
-        const float tp = bcast(ip, kWave - 1), tq = bcast(iq, kWave - 1);
-        if (lane == 0) {
-          s_u[3 * j] += cr;
-          s_u[3 * j + 1] += cg;
-          s_u[3 * j + 2] += cb;
-          s_b[j] = tp * (dTc + Tc * tq);
-          s_a[j] = Tc * tp;
+          const float lg = log2_om(inc, a);
+          const float q = inc ? -da * __builtin_amdgcn_rcpf(1.f - a) : 0.f;
+          const float Linc = scan_add(lg);
+          const float Qinc = scan_add(q);
+          const float Tc = readlane(sa[s], l), dTc = readlane(sb[s], l);
+          const float pin = __builtin_amdgcn_exp2f(Linc - lg);  // product of (1 - alpha) in front, within the chunk
+          const float Tn = Tc * pin;
+          const float dTn = pin * (dTc + Tc * (Qinc - q));
+          float cr = 0.f, cg = 0.f, cb = 0.f;
+          if (inc) {
+            const float aT = a * Tn, gT = da * Tn + a * dTn;
+            cr = dr.r * aT + r.r * gT;
+            cg = dr.g * aT + r.g * gT;
+            cb = dr.b * aT + r.b * gT;
+          }
+          cr = wave_total(cr);
+          cg = wave_total(cg);
+          cb = wave_total(cb);
+          const float tp = __builtin_amdgcn_exp2f(readlane(Linc, kWave - 1)), tq = readlane(Qinc, kWave - 1);
+          su0[s] = writelane(su0[s], readlane(su0[s], l) + cr, l);
+          su1[s] = writelane(su1[s], readlane(su1[s], l) + cg, l);
+          su2[s] = writelane(su2[s], readlane(su2[s], l) + cb, l);
+          sa[s] = writelane(sa[s], Tc * tp, l);
+          sb[s] = writelane(sb[s], tp * (dTc + Tc * tq), l);
         }
       }
     }
-    __syncthreads();
-    for (int j = lane; j < k; j += kWave) {
-      const int64_t i = c.tile_lin * k + j;
-      float d0 = s_u[3 * j] + o.bg[0] * s_b[j];
-      float d1 = s_u[3 * j + 1] + o.bg[1] * s_b[j];
-      float d2 = s_u[3 * j + 2] + o.bg[2] * s_b[j];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int j = s * kWave + lane;
+      const float d0 = su0[s] + o.bg[0] * sb[s], d1 = su1[s] + o.bg[1] * sb[s], d2 = su2[s] + o.bg[2] * sb[s];
       if (MODE == 1) {
-        jp_out[3 * i] = d0;
-        jp_out[3 * i + 1] = d1;
-        jp_out[3 * i + 2] = d2;
+        if (j < k) {
+          const int64_t i = c.tile_lin * k + j;
+          jp_out[3 * i] = d0;
+          jp_out[3 * i + 1] = d1;
+          jp_out[3 * i + 2] = d2;
+        }
       } else {
-        const float wj = wts ? wts[i] : 1.f;
-        s_u[3 * j] = wj * d0;
-        s_u[3 * j + 1] = wj * d1;
-        s_u[3 * j + 2] = wj * d2;
+        su0[s] = pr.w[s] * d0;
+        su1[s] = pr.w[s] * d1;
+        su2[s] = pr.w[s] * d2;
       }
     }
-    __syncthreads();
   }
 
   if (REV) {
-    // s_a = T behind the chunk range already walked, s_b = u . (colour behind + T_final bg)
-    for (int j = lane; j < k; j += kWave) {
-      const int64_t i = c.tile_lin * k + j;
-      if (!FWD) {
-        s_u[3 * j] = u_in[3 * i];
-        s_u[3 * j + 1] = u_in[3 * i + 1];
-        s_u[3 * j + 2] = u_in[3 * i + 2];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int j = s * kWave + lane;
+      if (j < k) {
+        const int64_t i = c.tile_lin * k + j;
+        if (!FWD) {
+          su0[s] = u_in[3 * i];
+          su1[s] = u_in[3 * i + 1];
+          su2[s] = u_in[3 * i + 2];
+        }
+        sa[s] = trans[i];
+      } else {
+        if (!FWD) su0[s] = su1[s] = su2[s] = 0.f;
+        sa[s] = 0.f;
       }
-      const float Tf = trans[i];
-      s_a[j] = Tf;
-      s_b[j] = Tf * (s_u[3 * j] * o.bg[0] + s_u[3 * j + 1] * o.bg[1] + s_u[3 * j + 2] * o.bg[2]);
+      sb[s] = sa[s] * (su0[s] * o.bg[0] + su1[s] * o.bg[1] + su2[s] * o.bg[2]);
     }
-    __syncthreads();
     if (lmax < 0) return;
-    for (int64_t c0 = (lmax / kWave) * kWave; c0 >= 0; c0 -= kWave) {
-      const int64_t e = c0 + lane;
+    for (int c0 = (lmax / kWave) * kWave; c0 >= 0; c0 -= kWave) {
+      const int e = c0 + (kWave - 1 - lane);  // reversed: lane 0 holds the chunk's deepest entry
       const bool valid = e < c.len;
       RecF r{};
       int id = 0;
@@ -263,43 +302,44 @@ __global__ __launch_bounds__(kWave) void deriv_kernel(
         r = load_rec(rec, (size_t)c.v * n + id);
       }
       float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      for (int j = 0; j < k; ++j) {
-        const int lj = s_last[j];
-        if (c0 > lj) continue;
-        const Alpha al = pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, s_xc[j], s_yc[j], o);
-        const bool inc = valid && e <= lj && al.inc;
-        const float a = inc ? al.a : 0.f;
-        const float om = 1.f - a;
-        const float ip = incl_prod(om, lane);
-        float ep = __shfl_up(ip, 1, kWave);
-        if (lane == 0) ep = 1.f;
-        const float Tin = s_a[j] / bcast(ip, kWave - 1);
-        const float Tn = Tin * ep;
-        const float u0 = s_u[3 * j], u1 = s_u[3 * j + 1], u2 = s_u[3 * j + 2];
-        const float urgb = u0 * r.r + u1 * r.g + u2 * r.b;
-        const float term = inc ? urgb * a * Tn : 0.f;
-        const float sinc = suffix_sum(term, lane);
-        if (inc) {
-          const float aT = a * Tn;
-          g[6] += u0 * aT;
-          g[7] += u1 * aT;
-          g[8] += u2 * aT;
-          if (!al.capped) {
-            const float behind = s_b[j] + (sinc - term);
-            const float ga = Tn * urgb - behind / om;
-            const float gs = ga * a;
-            g[5] += ga * al.es;
-            g[0] -= gs * (r.A * al.dx + r.B * al.dy);
-            g[1] -= gs * (r.B * al.dx + r.C * al.dy);
-            g[2] -= 0.5f * gs * al.dx * al.dx;
-            g[3] -= gs * al.dx * al.dy;
-            g[4] -= 0.5f * gs * al.dy * al.dy;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int cnt = min(kWave, k - s * kWave);
+        for (int l = 0; l < cnt; ++l) {
+          const int lj = readlane(pr.last[s], l);
+          if (c0 > lj) continue;
+          const Alpha al =
+              pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+          const bool inc = valid && e <= lj && al.inc;
+          const float a = inc ? al.a : 0.f;
+          const float lg = log2_om(inc, a);
+          const float Linc = scan_add(lg);  // over this entry and the ones behind it in the chunk
+          const float Tafter = readlane(sa[s], l);
+          const float Tn = Tafter * __builtin_amdgcn_exp2f(-Linc);
+          const float u0 = readlane(su0[s], l), u1 = readlane(su1[s], l), u2 = readlane(su2[s], l);
+          const float urgb = u0 * r.r + u1 * r.g + u2 * r.b;
+          const float term = inc ? urgb * a * Tn : 0.f;
+          const float Sinc = scan_add(term);
+          const float S = readlane(sb[s], l);
+          if (inc) {
+            const float aT = a * Tn;
+            g[6] += u0 * aT;
+            g[7] += u1 * aT;
+            g[8] += u2 * aT;
+            if (!al.capped) {
+              const float behind = S + (Sinc - term);
+              const float ga = Tn * urgb - behind * __builtin_amdgcn_rcpf(1.f - a);
+              const float gs = ga * a;
+              g[5] += ga * al.es;
+              g[0] -= gs * (r.A * al.dx + r.B * al.dy);
+              g[1] -= gs * (r.B * al.dx + r.C * al.dy);
+              g[2] -= 0.5f * gs * al.dx * al.dx;
+              g[3] -= gs * al.dx * al.dy;
+              g[4] -= 0.5f * gs * al.dy * al.dy;
+            }
           }
-        }
-        const float tot = bcast(sinc, 0);
-        if (lane == 0) {
-          s_a[j] = Tin;
-          s_b[j] += tot;
+          sa[s] = writelane(sa[s], Tafter * __builtin_amdgcn_exp2f(-readlane(Linc, kWave - 1)), l);
+          sb[s] = writelane(sb[s], S + readlane(Sinc, kWave - 1), l);
         }
       }
       if (valid) {
@@ -314,7 +354,9 @@ __global__ __launch_bounds__(kWave) void deriv_kernel(
 
 // --------------------------------------------------------------- Gram
 // Per (view, Gaussian) weighted Gram of d C_c / d rec over the tile's pixels
-// and channels: geometry block, geometry x colour, colour, opacity.
+// and channels: geometry block, geometry x colour, colour, opacity. Walks
+// like the reverse pass of deriv_kernel, with one "colour behind" per channel.
+template <int NS>
 __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ rec,
                                                      const int64_t* __restrict__ tile_start,
                                                      const int32_t* __restrict__ ids,
@@ -324,26 +366,22 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
                                                      const int32_t* __restrict__ lastv, int n, int T,
                                                      int TX, int k, lmrs_render_opts o,
                                                      float* __restrict__ gram) {
-  __shared__ float s_xc[kMaxK], s_yc[kMaxK], s_T[kMaxK], s_S[3 * kMaxK], s_w[kMaxK];
-  __shared__ int s_last[kMaxK];
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX);
-  int lmax = -1;
-  for (int j = lane; j < k; j += kWave) {
-    const int64_t i = c.tile_lin * k + j;
-    pixel_center(pix, k, c, j, &s_xc[j], &s_yc[j]);
-    s_last[j] = lastv[i];
-    lmax = max(lmax, s_last[j]);
-    const float Tf = trans[i];
-    s_T[j] = Tf;
-    for (int ch = 0; ch < 3; ++ch) s_S[3 * j + ch] = Tf * o.bg[ch];
-    s_w[j] = wts ? wts[i] : 1.f;
+  PixelRegs<NS> pr;
+  const int lmax = load_pixel_regs<NS>(pix, wts, lastv, k, c, pr);
+  float sT[NS], sS0[NS], sS1[NS], sS2[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int j = s * kWave + lane;
+    sT[s] = j < k ? trans[c.tile_lin * k + j] : 0.f;
+    sS0[s] = sT[s] * o.bg[0];
+    sS1[s] = sT[s] * o.bg[1];
+    sS2[s] = sT[s] * o.bg[2];
   }
-  lmax = wave_max_i(lmax);
-  __syncthreads();
   if (lmax < 0) return;
-  for (int64_t c0 = (lmax / kWave) * kWave; c0 >= 0; c0 -= kWave) {
-    const int64_t e = c0 + lane;
+  for (int c0 = (lmax / kWave) * kWave; c0 >= 0; c0 -= kWave) {
+    const int e = c0 + (kWave - 1 - lane);
     const bool valid = e < c.len;
     RecF r{};
     int id = 0;
@@ -354,48 +392,53 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
     float G[kGram];
     for (int q = 0; q < kGram; ++q) G[q] = 0.f;
     const float rgb[3] = {r.r, r.g, r.b};
-    for (int j = 0; j < k; ++j) {
-      const int lj = s_last[j];
-      if (c0 > lj) continue;
-      const Alpha al = pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, s_xc[j], s_yc[j], o);
-      const bool inc = valid && e <= lj && al.inc;
-      const float a = inc ? al.a : 0.f;
-      const float om = 1.f - a;
-      const float ip = incl_prod(om, lane);
-      float ep = __shfl_up(ip, 1, kWave);
-      if (lane == 0) ep = 1.f;
-      const float Tin = s_T[j] / bcast(ip, kWave - 1);
-      const float Tn = Tin * ep;
-      float behind[3], tot[3];
-      for (int ch = 0; ch < 3; ++ch) {
-        const float term = inc ? rgb[ch] * a * Tn : 0.f;
-        const float sinc = suffix_sum(term, lane);
-        behind[ch] = s_S[3 * j + ch] + (sinc - term);
-        tot[ch] = bcast(sinc, 0);
-      }
-      if (inc) {
-        const float wj = s_w[j];
-        const float aT = a * Tn;
-        G[30] += wj * aT * aT;
-        if (!al.capped) {
-          float ga[3], sga2 = 0.f;
-          for (int ch = 0; ch < 3; ++ch) {
-            ga[ch] = Tn * rgb[ch] - behind[ch] / om;
-            sga2 += ga[ch] * ga[ch];
-          }
-          const float h[5] = {-(r.A * al.dx + r.B * al.dy), -(r.B * al.dx + r.C * al.dy),
-                              -0.5f * al.dx * al.dx, -al.dx * al.dy, -0.5f * al.dy * al.dy};
-          const float fg = wj * a * a * sga2;
-          for (int p = 0; p < 5; ++p) {
-            for (int q = p; q < 5; ++q) G[sym5(p, q)] += fg * h[p] * h[q];
-            for (int ch = 0; ch < 3; ++ch) G[15 + 3 * p + ch] += wj * ga[ch] * a * h[p] * aT;
-          }
-          G[31] += wj * sga2 * al.es * al.es;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int cnt = min(kWave, k - s * kWave);
+      for (int l = 0; l < cnt; ++l) {
+        const int lj = readlane(pr.last[s], l);
+        if (c0 > lj) continue;
+        const Alpha al =
+            pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+        const bool inc = valid && e <= lj && al.inc;
+        const float a = inc ? al.a : 0.f;
+        const float lg = log2_om(inc, a);
+        const float Linc = scan_add(lg);
+        const float Tafter = readlane(sT[s], l);
+        const float Tn = Tafter * __builtin_amdgcn_exp2f(-Linc);
+        const float S[3] = {readlane(sS0[s], l), readlane(sS1[s], l), readlane(sS2[s], l)};
+        float behind[3], tot[3];
+        for (int ch = 0; ch < 3; ++ch) {
+          const float term = inc ? rgb[ch] * a * Tn : 0.f;
+          const float Sinc = scan_add(term);
+          behind[ch] = S[ch] + (Sinc - term);
+          tot[ch] = readlane(Sinc, kWave - 1);
         }
-      }
-      if (lane == 0) {
-        s_T[j] = Tin;
-        for (int ch = 0; ch < 3; ++ch) s_S[3 * j + ch] += tot[ch];
+        if (inc) {
+          const float wj = readlane(pr.w[s], l);
+          const float aT = a * Tn;
+          G[30] += wj * aT * aT;
+          if (!al.capped) {
+            float ga[3], sga2 = 0.f;
+            const float iom = __builtin_amdgcn_rcpf(1.f - a);
+            for (int ch = 0; ch < 3; ++ch) {
+              ga[ch] = Tn * rgb[ch] - behind[ch] * iom;
+              sga2 += ga[ch] * ga[ch];
+            }
+            const float h[5] = {-(r.A * al.dx + r.B * al.dy), -(r.B * al.dx + r.C * al.dy),
+                                -0.5f * al.dx * al.dx, -al.dx * al.dy, -0.5f * al.dy * al.dy};
+            const float fg = wj * a * a * sga2;
+            for (int p = 0; p < 5; ++p) {
+              for (int q = p; q < 5; ++q) G[sym5(p, q)] += fg * h[p] * h[q];
+              for (int ch = 0; ch < 3; ++ch) G[15 + 3 * p + ch] += wj * ga[ch] * a * h[p] * aT;
+            }
+            G[31] += wj * sga2 * al.es * al.es;
+          }
+        }
+        sT[s] = writelane(sT[s], Tafter * __builtin_amdgcn_exp2f(-readlane(Linc, kWave - 1)), l);
+        sS0[s] = writelane(sS0[s], S[0] + tot[0], l);
+        sS1[s] = writelane(sS1[s], S[1] + tot[1], l);
+        sS2[s] = writelane(sS2[s], S[2] + tot[2], l);
       }
     }
     if (valid) {
@@ -410,9 +453,13 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
 }  // namespace
 
 void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
-  const int64_t tiles = (int64_t)d.V * d.T;
-  render_kernel<<<(unsigned)tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX,
-                                                  d.k, o, f->color, f->trans, f->last);
+  const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
+  if (d.k <= kWave)
+    render_kernel<1><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k, o,
+                                                 f->color, f->trans, f->last);
+  else
+    render_kernel<4><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k, o,
+                                                 f->color, f->trans, f->last);
 }
 
 void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
@@ -421,17 +468,29 @@ void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_
 #define LMRS_DERIV_ARGS                                                                              \
   f->rec, tan, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T, d.TX, d.k, o, u, jp, \
       grad2d
-  if (mode == 1) deriv_kernel<1><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
-  else if (mode == 2) deriv_kernel<2><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
-  else deriv_kernel<3><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+  const bool small = d.k <= kWave;
+  if (mode == 1) {
+    if (small) deriv_kernel<1, 1><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    else deriv_kernel<1, 4><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+  } else if (mode == 2) {
+    if (small) deriv_kernel<2, 1><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    else deriv_kernel<2, 4><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+  } else {
+    if (small) deriv_kernel<3, 1><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    else deriv_kernel<3, 4><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+  }
 #undef LMRS_DERIV_ARGS
 }
 
 void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* gram,
                  hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
-  gram_kernel<<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last,
-                                      d.n, d.T, d.TX, d.k, o, gram);
+  if (d.k <= kWave)
+    gram_kernel<1><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last,
+                                               d.n, d.T, d.TX, d.k, o, gram);
+  else
+    gram_kernel<4><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last,
+                                               d.n, d.T, d.TX, d.k, o, gram);
 }
 
 }  // namespace lmrs
