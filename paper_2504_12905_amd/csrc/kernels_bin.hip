@@ -16,9 +16,10 @@
 //    breaks ties.
 // 5. sort: one workgroup per tile sorts its segment. Segments of up to 4096
 //    keys are sorted in LDS by a bitonic network; longer ones sort 4096-key
-//    runs in LDS and then merge runs pairwise in HBM, each key placed at
-//    (its index in its run) + (number of smaller keys in the partner run),
-//    found by binary search (keys are unique within a tile).
+//    runs in LDS and then merge runs pairwise in HBM by merge path: each
+//    thread takes an equal share of the output, finds where that share
+//    starts in the two runs by one binary search along the merge path, and
+//    merges its share sequentially (keys are unique within a tile).
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -153,13 +154,24 @@ __device__ void sort_chunk(const uint64_t* src, uint64_t* dst, int len, uint64_t
   __syncthreads();
 }
 
-__device__ int64_t count_less(const uint64_t* x, int64_t len, uint64_t key) {
-  int64_t lo = 0, hi = len;
+// Merge sorted runs A[0, na) and B[0, nb) into out[0, na + nb).
+__device__ void merge_path(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb, uint64_t* out) {
+  const int64_t total = na + nb;
+  const int64_t per = (total + kSortThreads - 1) / kSortThreads;
+  const int64_t d0 = min(total, (int64_t)threadIdx.x * per);
+  const int64_t d1 = min(total, d0 + per);
+  if (d0 >= d1) return;
+  // number of A elements among the first d0 outputs
+  int64_t lo = max<int64_t>(0, d0 - nb), hi = min(d0, na);
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if (x[mid] < key) lo = mid + 1; else hi = mid;
+    if (A[mid] < B[d0 - 1 - mid]) lo = mid + 1; else hi = mid;
   }
-  return lo;
+  int64_t i = lo, j = d0 - lo;
+  for (int64_t d = d0; d < d1; ++d) {
+    const bool take_a = j >= nb || (i < na && A[i] < B[j]);
+    out[d] = take_a ? A[i++] : B[j++];
+  }
 }
 
 __global__ __launch_bounds__(kSortThreads) void sort_kernel(const int64_t* __restrict__ tile_start,
@@ -178,18 +190,10 @@ __global__ __launch_bounds__(kSortThreads) void sort_kernel(const int64_t* __res
     for (int64_t c = 0; c < len; c += kSortChunk)
       sort_chunk(src + c, src + c, (int)min<int64_t>(kSortChunk, len - c), s);
     for (int64_t run = kSortChunk; run < len; run <<= 1) {
-      for (int64_t i = threadIdx.x; i < len; i += kSortThreads) {
-        const int64_t pair = i / (2 * run), base = pair * 2 * run;
-        const int64_t alen = min(run, len - base);
-        const int64_t blen = max<int64_t>(0, min(run, len - base - run));
-        const uint64_t key = src[i];
-        int64_t pos;
-        if (i - base < run) {
-          pos = (i - base) + count_less(src + base + run, blen, key);
-        } else {
-          pos = (i - base - run) + count_less(src + base, alen, key);
-        }
-        dst[base + pos] = key;
+      for (int64_t base = 0; base < len; base += 2 * run) {
+        const int64_t na = min(run, len - base);
+        const int64_t nb = max<int64_t>(0, min(run, len - base - run));
+        merge_path(src + base, na, src + base + na, nb, dst + base);
       }
       __syncthreads();
       uint64_t* t = src;
