@@ -51,7 +51,7 @@ def lib():
         L.or_get_lists.argtypes = [vp, vp, vp]
         L.or_set_samples.argtypes = [vp, i32, vp, vp]
         L.or_set_tile_mask.argtypes = [vp, vp]
-        L.or_render.argtypes = [vp] * 6
+        L.or_render.argtypes = [vp] * 7
         L.or_jvp.argtypes = [vp, vp, vp]
         L.or_vjp.argtypes = [vp, vp, vp]
         L.or_vjp_screen.argtypes = [vp, vp, vp]
@@ -163,8 +163,16 @@ class Oracle:
         last = np.zeros(S, np.int32)
         nc = np.zeros(S, np.int32)
         tr = np.zeros(S, np.uint64)
-        lib().or_render(self.h, _p(Cc), _p(T), _p(last), _p(nc), _p(tr))
-        return dict(C=Cc, T=T, last=last, n_contrib=nc, trace=tr)
+        mg = np.zeros(S)
+        lib().or_render(self.h, _p(Cc), _p(T), _p(last), _p(nc), _p(tr), _p(mg))
+        return dict(C=Cc, T=T, last=last, n_contrib=nc, trace=tr, margin=mg)
+
+    def decided(self, tau: float = 1e-4) -> np.ndarray:
+        """Sampled pixels whose discrete decisions (exponent sign, alpha floor and
+        cap, transmittance stop) all lie farther than tau (relative) from their
+        thresholds. Below that, FP32 and FP64 arithmetic may decide differently
+        and the pixel's colour derivative is not unique at FP32 precision."""
+        return self.render()["margin"] >= tau
 
     def render_image(self) -> np.ndarray:
         """Full images [V, H, W, 3] (uses all pixels; resets the sample set)."""

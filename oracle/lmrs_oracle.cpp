@@ -228,6 +228,7 @@ struct PixelOut {
   int last;        // position in the tile list of the last blended Gaussian, -1 if none
   int n_contrib;   // number of blended Gaussians
   uint64_t trace;  // hash of the discrete decisions taken along the walk
+  double margin;   // smallest relative distance of a decision to its threshold
 };
 
 template <class S>
@@ -238,12 +239,18 @@ void render_pixel(const Rec<S>* const* recs, const int* list, int len, double xc
   int last = -1, nc = 0;
   uint64_t h = 1469598103934665603ull;
   auto mix = [&h](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+  // Decision margins: |s| for the s > 0 test, |alpha - threshold| / threshold
+  // for the alpha floor and cap, |T (1 - alpha) - t_min| / t_min for the stop.
+  double margin = 1e30;
   for (int i = 0; i < len; ++i) {
     const Rec<S>& r = *recs[i];
     S dx = r.u - S(xc), dy = r.v - S(yc);
     S s = S(-0.5) * (r.A * dx * dx + r.C * dy * dy) - r.B * dx * dy;
+    margin = std::min(margin, std::fabs(re(s)));
     if (re(s) > 0.0) continue;
     S a = r.o * exp(s);
+    margin = std::min(margin, std::fabs(re(a) - op.alpha_min) / op.alpha_min);
+    margin = std::min(margin, std::fabs(re(a) - op.alpha_max) / op.alpha_max);
     bool capped = false;
     if (re(a) > op.alpha_max) {
       a = S(op.alpha_max);
@@ -251,6 +258,7 @@ void render_pixel(const Rec<S>* const* recs, const int* list, int len, double xc
     }
     if (re(a) < op.alpha_min) continue;
     S Tn = T * (S(1.0) - a);
+    margin = std::min(margin, std::fabs(re(Tn) - op.t_min) / op.t_min);
     if (re(Tn) < op.t_min) {
       mix(0xffffffffull);
       break;
@@ -266,6 +274,7 @@ void render_pixel(const Rec<S>* const* recs, const int* list, int len, double xc
   po.last = last;
   po.n_contrib = nc;
   po.trace = h;
+  po.margin = margin;
 }
 
 // ------------------------------------------------------------------ problem
@@ -467,7 +476,7 @@ void tile_recs(const Problem& pb, const std::vector<Rec<S>>& recs, int v, int t,
 
 template <class S>
 void walk_all(const Problem& pb, const std::vector<Rec<S>>& recs, double* C, double* Cdu, double* T,
-              int* last, int* ncontrib, uint64_t* trace) {
+              int* last, int* ncontrib, uint64_t* trace, double* margin = nullptr) {
 #pragma omp parallel
   {
     std::vector<const Rec<S>*> ptrs;
@@ -492,6 +501,7 @@ void walk_all(const Problem& pb, const std::vector<Rec<S>>& recs, double* C, dou
         if (last) last[i] = po.last;
         if (ncontrib) ncontrib[i] = po.n_contrib;
         if (trace) trace[i] = po.trace;
+        if (margin) margin[i] = po.margin;
       }
     }
   }
@@ -696,9 +706,9 @@ void or_set_tile_mask(void* h, const uint8_t* mask) {
   if (mask) pb.tile_mask.assign(mask, mask + (size_t)pb.V * pb.T); else pb.tile_mask.clear();
 }
 
-void or_render(void* h, double* C, double* T, int* last, int* ncontrib, uint64_t* trace) {
+void or_render(void* h, double* C, double* T, int* last, int* ncontrib, uint64_t* trace, double* margin) {
   Problem& pb = *static_cast<Problem*>(h);
-  walk_all<double>(pb, pb.rec, C, nullptr, T, last, ncontrib, trace);
+  walk_all<double>(pb, pb.rec, C, nullptr, T, last, ncontrib, trace, margin);
 }
 
 // J p at every sampled pixel (3 channels), by dual numbers.

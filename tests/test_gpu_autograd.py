@@ -1,0 +1,175 @@
+"""The render behind torch.autograd (LmrsRender): forward, the hand-written
+backward (reverse pass) and the forward-mode rule (dual-number tangent pass),
+checked against the FP64 oracle's exact derivatives, its central finite
+differences (h = 1e-3) and the adjoint identity.
+
+Directions p_k = g/||g||, g ~ N(0, I). Per-pixel derivative comparisons skip
+pixels with a discrete decision (exponent sign, alpha floor or cap,
+transmittance stop) within 1e-4 of its threshold, where FP32 and FP64 may
+decide differently (about 0.1 % of pixels; reported). The 256-direction sweep and the finite
+differences run on a 20k-Gaussian SH-3 scene (4 views, 256x256, all pixels);
+the 200k-Gaussian, 16-view 512x512 configuration runs the same calls with the
+oracle restricted to a subset of tiles."""
+import numpy as np
+import pytest
+import torch
+import torch.autograd.forward_ad as fwAD
+
+from gpu_util import DEV, log, np_, rel
+from oracle import Oracle
+from paper_2504_12905_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def views_of(cams, W, H):
+    from paper_2504_12905_amd.autograd import Views
+    return Views(torch.tensor(cams, device=DEV), W, H)
+
+
+def to_samples(img: np.ndarray, orc: Oracle) -> np.ndarray:
+    """[V, H, W, 3] image -> oracle sample order [S, 3] (all pixels)."""
+    v, x, y = orc.pixel_coords()
+    return img[v, y, x]
+
+
+@pytest.fixture(scope="module")
+def medium():
+    n, deg, W = 20000, 3, 256
+    gt = synth.make_scene(n, deg, 9, means="ball")
+    beta = synth.perturb_init(gt, n, deg, 9)
+    cams = synth.sphere_cameras(4, 4.0, W, W, 60.0, 9)
+    orc = Oracle(n, deg, beta, cams, W, W)
+    orc.set_samples(256)
+    target = np.random.default_rng(9).uniform(0, 1, size=(4, W, W, 3)).astype(np.float32)
+    return n, deg, beta, cams, W, orc, target
+
+
+def test_forward_matches_oracle(medium):
+    from paper_2504_12905_amd.autograd import LmrsRender
+    n, deg, beta, cams, W, orc, target = medium
+    img = np_(LmrsRender.apply(torch.tensor(beta, device=DEV), n, deg, views_of(cams, W, W)))
+    e = rel(to_samples(img, orc), orc.render()["C"])
+    log(f"  forward rel {e:.2e}")
+    assert e < 1e-4
+
+
+def test_backward_matches_oracle_gradient(medium):
+    from paper_2504_12905_amd.autograd import pack, render
+    n, deg, beta, cams, W, orc, target = medium
+    b = torch.tensor(beta, device=DEV)
+    K = (deg + 1) ** 2
+    groups = [b[0:3 * n].view(3, n).t(), b[3 * n:6 * n].view(3, n).t(), b[6 * n:10 * n].view(4, n).t(),
+              b[10 * n:11 * n], b[11 * n:].view(K * 3, n).t().reshape(n, K, 3)]
+    leaves = [g.detach().clone().requires_grad_(True) for g in groups]
+    assert torch.equal(pack(*leaves).detach(), b)
+    img = render(*leaves, views_of(cams, W, W))
+    loss = 0.5 * ((img - torch.tensor(target, device=DEV)) ** 2).sum()
+    grads = torch.autograd.grad(loss, leaves)
+    g_gpu = np_(pack(*grads))
+    r = orc.render()["C"] - to_samples(target, orc)
+    g_ref = orc.vjp(r)
+    e = rel(g_gpu, g_ref)
+    log(f"  gradient of 1/2 |r|^2 rel {e:.2e}")
+    assert e < 1e-4
+
+
+def gpu_jvp(beta_t: torch.Tensor, p: torch.Tensor, n, deg, views):
+    from paper_2504_12905_amd.autograd import LmrsRender
+    with fwAD.dual_level():
+        out = LmrsRender.apply(fwAD.make_dual(beta_t, p), n, deg, views)
+        return fwAD.unpack_dual(out).tangent
+
+
+def test_forward_ad_256_directions_vs_oracle_dual(medium):
+    n, deg, beta, cams, W, orc, target = medium
+    b = torch.tensor(beta, device=DEV)
+    views = views_of(cams, W, W)
+    rng = np.random.default_rng(10)
+    ok = orc.decided()
+    worst = 0.0
+    for k in range(256):
+        g = rng.normal(size=orc.P)
+        p = (g / np.linalg.norm(g)).astype(np.float32)
+        jp = np_(gpu_jvp(b, torch.tensor(p, device=DEV), n, deg, views))
+        worst = max(worst, rel(to_samples(jp, orc)[ok], orc.jvp(p)[ok]))
+    log(f"  forward-mode, 256 directions: worst rel {worst:.2e} ({1 - ok.mean():.4%} pixels within 1e-4 "
+        "of a decision threshold excluded)")
+    assert worst < 1e-4 and ok.mean() > 0.99
+
+
+def test_jvp_vs_oracle_central_differences(medium):
+    """Central differences of the FP64 render (h = 1e-3) along 32 directions,
+    on pixels whose discrete decisions are the same at beta - h p, beta and
+    beta + h p."""
+    n, deg, beta, cams, W, orc, target = medium
+    b = torch.tensor(beta, device=DEV)
+    views = views_of(cams, W, W)
+    base = orc.render()
+    h = 1e-3
+    rng = np.random.default_rng(11)
+    worst, excluded = 0.0, []
+    for k in range(32):
+        g = rng.normal(size=orc.P)
+        p = g / np.linalg.norm(g)
+        outs = []
+        for s in (1.0, -1.0):
+            o = Oracle(n, deg, beta.astype(np.float64) + s * h * p, cams, W, W)
+            o.set_samples(256)
+            outs.append(o.render())
+        same = (outs[0]["trace"] == base["trace"]) & (outs[1]["trace"] == base["trace"]) & orc.decided()
+        excluded.append(1.0 - same.mean())
+        fd = (outs[0]["C"] - outs[1]["C"]) / (2 * h)
+        jp = to_samples(np_(gpu_jvp(b, torch.tensor(p.astype(np.float32), device=DEV), n, deg, views)), orc)
+        worst = max(worst, rel(jp[same], fd[same]))
+    log(f"  32 FD directions: worst rel {worst:.2e}; kink pixels excluded {np.mean(excluded):.4%}")
+    assert np.mean(excluded) < 0.05
+    assert worst < 1e-3
+
+
+def test_adjoint_identity_autograd(medium):
+    from paper_2504_12905_amd.autograd import LmrsRender
+    n, deg, beta, cams, W, orc, target = medium
+    views = views_of(cams, W, W)
+    gen = torch.Generator(device="cpu").manual_seed(12)
+    for _ in range(4):
+        b = torch.tensor(beta, device=DEV).requires_grad_(True)
+        p = torch.randn(orc.P, generator=gen).to(DEV)
+        u = torch.randn(4, W, W, 3, generator=gen).to(DEV)
+        img = LmrsRender.apply(b, n, deg, views)
+        (jtu,) = torch.autograd.grad(img, b, u)
+        jp = gpu_jvp(b.detach(), p, n, deg, views)
+        lhs = float((jp.double() * u.double()).sum())
+        rhs = float((p.double() * jtu.double()).sum())
+        assert abs(lhs - rhs) <= 1e-5 * abs(lhs), (lhs, rhs)
+
+
+def test_config3_full_size():
+    """200k Gaussians, SH 3, 16 views 512x512: forward, backward and
+    forward-mode on the GPU; oracle comparison on 48 tiles per view."""
+    from paper_2504_12905_amd.autograd import LmrsRender
+    w = synth.config3()
+    W = w.width
+    views = views_of(w.cams, W, W)
+    b = torch.tensor(w.beta_init, device=DEV).requires_grad_(True)
+    img = LmrsRender.apply(b, w.n, w.sh_degree, views)
+    u = torch.randn(img.shape, generator=torch.Generator(device="cpu").manual_seed(13)).to(DEV)
+    (jtu,) = torch.autograd.grad(img, b, u)
+    p = torch.randn(b.shape, generator=torch.Generator(device="cpu").manual_seed(14)).to(DEV)
+    jp = gpu_jvp(b.detach(), p, w.n, w.sh_degree, views)
+    lhs, rhs = float((jp.double() * u.double()).sum()), float((p.double() * jtu.double()).sum())
+    log(f"  config3 <Jp,u>={lhs:.8e} <p,J^T u>={rhs:.8e}")
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    orc = Oracle(w.n, w.sh_degree, w.beta_init, w.cams, W, W)
+    orc.set_samples(256)
+    mask = np.zeros(orc.V * orc.T, np.uint8)
+    rng = np.random.default_rng(15)
+    ts, _ = orc.lists()
+    busy = np.flatnonzero(np.diff(ts) > 0)
+    mask[rng.choice(busy, min(48 * orc.V, busy.size), replace=False)] = 1
+    orc.set_tile_mask(mask)
+    on = np.repeat(mask.astype(bool), 256) & orc.decided()
+    e_f = rel(to_samples(np_(img), orc)[on], orc.render()["C"][on])
+    e_j = rel(to_samples(np_(jp), orc)[on], orc.jvp(np_(p).astype(np.float64))[on])
+    log(f"  config3 forward rel {e_f:.2e}, forward-mode rel {e_j:.2e} on {mask.sum()} tiles")
+    assert e_f < 1e-4 and e_j < 1e-4

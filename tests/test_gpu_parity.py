@@ -3,7 +3,9 @@
 Bar (FP32 path vs FP64 oracle, norm-wise relative error ||a-b||/||b||):
 * tile lists and depth order: bit-exact (exceptions only for a footprint radius
   within 1e-4 of an integer, reported);
-* projection, render, J p, J^T u, GN product, diagonal: <= 1e-4;
+* projection, render, J p, J^T u, GN product, diagonal: <= 1e-4 (J p per pixel on
+  the pixels whose skip / cap / stop decisions are farther than 1e-4 from their
+  thresholds, the rest having no unique derivative at FP32 precision);
 * PCG solution: <= 1e-3 (FP32 CG recurrences drift from FP64 over iterations);
 * sampler: bit-exact.
 """
@@ -95,8 +97,9 @@ def test_jvp(case):
     p = rng.normal(size=case.P).astype(np.float32)
     jp = np_(lib().lmrs_jvp(case.fr, torch.tensor(p, device=DEV)))
     ref = case.orc.jvp(p)
-    log(f"  jvp rel {rel(jp, ref):.2e}")
-    assert rel(jp, ref) < TOL
+    ok = case.orc.decided()
+    log(f"  jvp rel {rel(jp[ok], ref[ok]):.2e} on decided pixels ({1 - ok.mean():.4%} within 1e-4 of a threshold)")
+    assert rel(jp[ok], ref[ok]) < TOL
 
 
 def test_vjp(case):

@@ -120,3 +120,23 @@ def test_samples_select_pixels():
     out = orc.render()
     v, x, y = orc.pixel_coords()
     np.testing.assert_array_equal(out["C"], full[v, y, x])
+
+
+def test_decision_margin_flags_threshold_pixels():
+    """A pixel whose alpha sits 1e-6 (relative) above the 1/255 floor is not
+    decided at tau = 1e-4; with alpha 0.006 it is."""
+    f, W = 40.0, 32
+    sigma = 0.1
+    s2 = (f * sigma / 3.0) ** 2 + 0.3
+    x, y = 20, 16                        # pixel centre (20.5, 16.5), Gaussian at (16, 16)
+    d2 = (x + 0.5 - W / 2) ** 2 + (y + 0.5 - W / 2) ** 2
+    g = math.exp(-0.5 * d2 / s2)
+    for target, expect in [((1 + 1e-6) / 255.0, False), (0.006, True)]:
+        op = target / g
+        n, beta = one_gaussian_scene([0, 0, 0], [math.log(sigma)] * 3, [1, 0, 0, 0], math.log(op / (1 - op)),
+                                     [0.5, 0.5, 0.5])
+        orc = Oracle(n, 0, beta, axis_camera(f, W, W), W, W)
+        orc.set_samples(256)
+        v, xs, ys = orc.pixel_coords()
+        i = int(np.flatnonzero((xs == x) & (ys == y))[0])
+        assert bool(orc.decided()[i]) is expect
