@@ -12,7 +12,8 @@ rate and update. `value` = GN products completed per second of LM stepping
 
 Also measured: the GN product on its own (HIP events on the library's stream,
 per launch), the roofline position of its dominant kernel (the fused splat
-kernel), and the FP64 CPU oracle's GN-product rate on a bounded sample.
+kernel), the unfused J p -> J^T u comparator, and the FP64 CPU oracle timed on
+the same GN product (its result also gives the parity of the timed product).
 """
 from __future__ import annotations
 
@@ -95,29 +96,97 @@ def traffic_from_profile(kernel_hash: str):
         return None
 
 
-def cpu_baseline(w, beta, cams_np, view_ids, pix, wts, lam, budget_s=20.0):
-    """FP64 oracle GN products/s on a bounded sample: one of the step's views
-    (same samples, same parameters), scaled to the full 8-view product."""
+def cpu_baseline(w, beta, cams_np, view_ids, pix, wts, lam, p, budget_s=20.0):
+    """FP64 oracle GN products/s on the same product the GPU timed: all batch
+    views, the same samples, parameters and direction p. The first call also
+    builds the record Jacobians the later calls reuse (reported apart); then
+    products are repeated until about `budget_s` seconds of CPU work."""
     from oracle import Oracle, num_threads
-    v0 = int(view_ids[0])
-    orc = Oracle(w.n, w.sh_degree, beta, cams_np[[v0]], w.width, w.height)
-    orc.set_samples(pix.shape[-1], pix[:1], wts[:1])
-    p = np.random.default_rng(0).normal(size=orc.P)
+    orc = Oracle(w.n, w.sh_degree, beta, cams_np[view_ids], w.width, w.height)
+    orc.set_samples(pix.shape[-1], pix, wts)
+    pd = p.astype(np.float64)
     t0 = time.perf_counter()
-    orc.gn(p, lam)                       # first call also builds the record Jacobians it reuses
+    ref = orc.gn(pd, lam)
     first = time.perf_counter() - t0
     times = []
-    while sum(times) + first < budget_s and len(times) < 5:
+    while (not times or sum(times) + first < budget_s) and len(times) < 500:
         t0 = time.perf_counter()
-        orc.gn(p, lam)
+        orc.gn(pd, lam)
         times.append(time.perf_counter() - t0)
     t1 = float(np.median(times))
     V = len(view_ids)
-    return {"value": 1.0 / (V * t1), "unit": "GN products/s", "cores": num_threads(), "kind": "oracle",
-            "sample": f"1 of the {V} batch views (camera {v0}), same 26 samples/tile and parameters; "
-                      f"median of {len(times)} GN products after a warm-up ({first:.1f} s, builds the "
-                      f"record Jacobians), time x {V} = one full product",
-            "seconds_per_view_product": t1}
+    return {"value": round(1.0 / t1, 4), "unit": "GN products/s", "cores": num_threads(), "kind": "oracle",
+            "sample": f"the full GN product of one LM step ({V} views, {pix.shape[-1]} samples/tile, same "
+                      f"parameters and p as the GPU's timed product); median of {len(times)} products after "
+                      f"a first call of {first:.1f} s that also builds the record Jacobians",
+            "seconds_per_product": round(t1, 4)}, ref
+
+
+def copy_calibration(torch, dev, mib=1024, reps=3):
+    """Plain device copies of a known size (the HBM-counter calibration
+    kernel of the traffic pass): reads and writes mib MiB each."""
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def summarize_traffic(fetch_dir: str, write_dir: str, copy_mib: int, command: str, copy_reps: int = 3) -> str:
+    """Per-launch HBM bytes of the fused splat kernel from two rocprofv3 --pmc
+    runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by the
+    ratio of the known copy size to what the same counter reads for the plain
+    copy kernel of the same run. Writes TRAFFIC_FILE and returns its text."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        vals = {}
+        for f in files:
+            for row in csv.DictReader(open(f)):
+                if row.get("Counter_Name") != counter:
+                    continue
+                vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+        return vals
+
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        vals = per_kernel(d, counter)
+        splat = [x for k, v in vals.items() if "deriv_kernel<3" in k for x in v]
+        # the calibration copies are the largest dispatches of the runtime's
+        # device-to-device copy kernel in the run (reps of the same size)
+        copy = sorted(x for k, v in vals.items() if "copyBuffer" in k for x in v)[-copy_reps:]
+        if not splat or not copy:
+            raise SystemExit(f"{counter}: kernels found: {sorted(vals)[:20]}")
+        splat_kib = float(np.median(splat))
+        copy_kib = float(np.median(copy))
+        scale = copy_mib * 1024.0 / copy_kib
+        out[counter] = (splat_kib, copy_kib, scale)
+    fetch = out["FETCH_SIZE"][0] * out["FETCH_SIZE"][2] * 1024
+    write = out["WRITE_SIZE"][0] * out["WRITE_SIZE"][2] * 1024
+    kernel_hash = hashlib.sha256(open(SPLAT_SOURCE, "rb").read()).hexdigest()
+    text = (f"# HBM traffic of the fused splat kernel deriv_kernel<3> (one GN product),\n"
+            f"# 100k-Gaussian object-scale workload (8 views 800x800, 26 samples/tile).\n"
+            f"# Commands (one counter per run, from the repository root):\n"
+            f"#   {command}\n"
+            f"# Counter values are KiB per dispatch (median over the GN products of the run);\n"
+            f"# each is scaled by (known copy size / the same counter for a {copy_mib} MiB device copy).\n"
+            f"fetch_kib_splat: {out['FETCH_SIZE'][0]:.1f}\n"
+            f"fetch_kib_copy_{copy_mib}MiB: {out['FETCH_SIZE'][1]:.1f}\n"
+            f"fetch_scale: {out['FETCH_SIZE'][2]:.4f}\n"
+            f"write_kib_splat: {out['WRITE_SIZE'][0]:.1f}\n"
+            f"write_kib_copy_{copy_mib}MiB: {out['WRITE_SIZE'][1]:.1f}\n"
+            f"write_scale: {out['WRITE_SIZE'][2]:.4f}\n"
+            f"hbm_bytes_per_launch: {fetch + write:.0f}\n"
+            f"kernel_source_sha256: {kernel_hash}\n")
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write(text)
+    return text
 
 
 def main():
@@ -125,10 +194,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--gn-reps", type=int, default=20)
+    ap.add_argument("--gn-reps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run MIB-MiB device copies before the GN timing (HBM-counter calibration)")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the splat traffic summary from two rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--traffic-command", default="", help="command line recorded in the traffic summary")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        print(summarize_traffic(*args.summarize_traffic, args.calibrate_copy or 1024, args.traffic_command))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
               "(view sharding, one all-reduce per GN product) is described in DESIGN.md", file=sys.stderr)
@@ -190,23 +268,38 @@ def main():
     p = torch.randn(fr.P, generator=torch.Generator(device="cpu").manual_seed(0)).to(dev)
     out = torch.empty_like(p)
     gws = L.workspace(L.OP_GN, fr)
-    for _ in range(3):
+    if args.calibrate_copy:
+        copy_calibration(torch, dev, args.calibrate_copy)
+    for _ in range(5):
         L.lmrs_gn_product(fr, p, w.lam, out=out, ws=gws)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.gn_reps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        L.lmrs_gn_product(fr, p, w.lam, out=out, ws=gws)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    per_call = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    gn_ms = float(np.median(per_call))
+    phases = np.array([L.lmrs_gn_product_timed(fr, p, w.lam, out=out, ws=gws)[1] for _ in range(args.gn_reps)])
+    phase_ms = np.median(phases, axis=0)
+    log(f"[bench] GN product median {gn_ms:.3f} ms over {args.gn_reps} calls (tangent {phase_ms[0]:.3f}, "
+        f"fill {phase_ms[1]:.3f}, fused splat {phase_ms[2]:.3f}, chain {phase_ms[3]:.3f})")
+    # the unfused comparator: J p to HBM, weights, then J^T u (same state)
+    wts = fr.w.view(-1, 1)
+    jp = torch.empty((fr.S, 3), dtype=torch.float32, device=dev)
+    jtu = torch.empty_like(p)
+    for _ in range(3):
+        L.lmrs_vjp(fr, L.lmrs_jvp(fr, p, out=jp).mul_(wts), out=jtu)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.gn_reps):
-        L.lmrs_gn_product(fr, p, w.lam, out=out, ws=gws)
+        L.lmrs_vjp(fr, L.lmrs_jvp(fr, p, out=jp).mul_(wts), out=jtu)
     e1.record(stream)
     e1.synchronize()
-    gn_ms = e0.elapsed_time(e1) / args.gn_reps
-    phases = np.zeros(4)
-    for _ in range(args.gn_reps):
-        phases += np.array(L.lmrs_gn_product_timed(fr, p, w.lam, out=out, ws=gws)[1])
-    phases /= args.gn_reps
-    log(f"[bench] GN product {gn_ms:.3f} ms (tangent {phases[0]:.3f}, fill {phases[1]:.3f}, "
-        f"fused splat {phases[2]:.3f}, chain {phases[3]:.3f})")
+    unfused_ms = e0.elapsed_time(e1) / args.gn_reps
+    out_gpu = out.double().cpu().numpy()
 
     # --- algorithmic work of the fused splat kernel in this launch
     last = fr.last.view(V * fr.T, k).to(torch.int64)
@@ -215,7 +308,7 @@ def main():
     S = fr.S
     b_alg = entries * BYTES_PER_ENTRY + S * BYTES_PER_PIXEL
     f_alg = pairs * FLOPS_PER_PAIR
-    t_splat = phases[2] * 1e-3
+    t_splat = phase_ms[2] * 1e-3
     gbs = b_alg / t_splat / 1e9
     tflops = f_alg / t_splat / 1e12
     hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tflops / FP32_VECTOR_PEAK_TFLOPS
@@ -234,15 +327,17 @@ def main():
         "alu_tflops": round(tflops, 4), "alu_frac": round(alu_frac, 6),
         "algorithmic_bytes": b_alg, "algorithmic_flops": f_alg,
         "traversed_entries": entries, "pixel_entry_pairs": pairs, "sampled_pixels": S,
-        "ms_per_launch": round(phases[2], 4),
+        "ms_per_launch": round(float(phase_ms[2]), 4),
     }
 
-    cpu = None
+    cpu, parity = None, None
     if not args.no_cpu:
-        log("[bench] CPU oracle baseline (bounded sample)")
-        cpu = cpu_baseline(w, fr.beta.cpu().numpy(), w.cams, view_ids.cpu().numpy(), fr.pix.cpu().numpy(),
-                           fr.w.cpu().numpy(), w.lam)
-        log(f"[bench] oracle {cpu['value']:.4f} GN products/s on {cpu['cores']} threads")
+        log("[bench] CPU oracle baseline (the same GN product in FP64)")
+        cpu, ref = cpu_baseline(w, fr.beta.cpu().numpy(), w.cams, view_ids.cpu().numpy(), fr.pix.cpu().numpy(),
+                                fr.w.cpu().numpy(), w.lam, p.cpu().numpy(), args.cpu_budget)
+        parity = float(np.linalg.norm(out_gpu - ref) / np.linalg.norm(ref))
+        log(f"[bench] oracle {cpu['value']:.4f} GN products/s on {cpu['cores']} threads; "
+            f"GPU vs oracle rel {parity:.2e}")
 
     res = {
         "metric": METRIC, "value": round(value, 3), "unit": "GN products/s", "n_gpus": 1,
@@ -252,9 +347,11 @@ def main():
         "config": {"workload": w.name, "gaussians": w.n, "sh_degree": w.sh_degree,
                    "views_per_step": V, "views_total": int(w.cams.shape[0]), "resolution": [w.width, w.height],
                    "samples_per_tile": k, "cg_iters": w.cg_iters, "lambda": w.lam,
-                   "gn_product_ms_isolated": round(gn_ms, 4),
+                   "gn_product_ms_median": round(gn_ms, 4),
                    "gn_products_per_s_isolated": round(1e3 / gn_ms, 2),
-                   "gn_phase_ms": [round(x, 4) for x in phases]},
+                   "gn_phase_ms_median": [round(float(x), 4) for x in phase_ms],
+                   "gn_unfused_jvp_vjp_ms": round(unfused_ms, 4),
+                   "gn_parity_rel_vs_oracle": parity},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
