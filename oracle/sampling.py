@@ -11,6 +11,10 @@ generator, so the oracle and the GPU draw identical keys from the same
 Pixel p of tile t in camera c at LM iteration it gets the first 32-bit output
 word of Philox(counter = (p, t, c, it), key = (seed_lo, seed_hi)); the k pixels
 with the smallest (word, p) are taken and listed in ascending pixel order.
+
+The residual-weighted sampler (Supp. E, q_residual) draws k pixels per tile
+with replacement from the softmax of the pixels' residual magnitudes inside
+the tile; see ``sample_residual``.
 """
 from __future__ import annotations
 
@@ -59,3 +63,50 @@ def sample_uniform(seed: int, it: int, cam_ids, n_tiles: int, k: int):
     chosen = np.sort(np.argsort(order_key, axis=-1, kind="stable")[..., :k], axis=-1)
     w = np.full(chosen.shape, 256.0 / k, dtype=np.float32)
     return chosen.astype(np.uint8), w
+
+
+def draw_uniforms(seed: int, it: int, cam_ids, n_tiles: int, k: int) -> np.ndarray:
+    """float64 [V, T, k] in [0, 1): draw j of tile t in camera c at LM iteration
+    it is the first Philox4x32-10 word of counter (256 + j, t, c, it) (counters
+    0..255 belong to the uniform sampler's pixel keys), cut to its top 24 bits
+    and scaled by 2^-24, so the value is exact in FP32 as well."""
+    cam_ids = np.asarray(cam_ids, dtype=np.uint32)
+    V = cam_ids.size
+    ctr = np.zeros((V, n_tiles, k, 4), dtype=np.uint32)
+    ctr[..., 0] = 256 + np.arange(k, dtype=np.uint32)[None, None, :]
+    ctr[..., 1] = np.arange(n_tiles, dtype=np.uint32)[None, :, None]
+    ctr[..., 2] = cam_ids[:, None, None]
+    ctr[..., 3] = np.uint32(it)
+    word = philox4x32_10(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))[..., 0]
+    return (word >> np.uint32(8)).astype(np.float64) * 2.0 ** -24
+
+
+def sample_residual(seed: int, it: int, cam_ids, n_tiles: int, k: int, scores: np.ndarray):
+    """Residual-weighted stratified sampling (Supp. E, q_residual, eq. 16),
+    restricted to each 16x16 tile (Sec. 4.4): inside a tile pixel p has
+    probability q(p) = exp(s_p) / sum_q exp(s_q), with s_p = |r_p| the pixel's
+    residual magnitude (scores, [V, T, 256]); k independent draws per tile, with
+    replacement, each weighted 1 / (k q(p)) so that the weighted sum over the
+    draws estimates the tile's sum (eq. 11, 12).
+
+    Draw j takes the pixel whose interval [Q_{p-1}, Q_p) of the cumulative
+    distribution Q_p = q(0) + ... + q(p) holds the draw's uniform number.
+    Returns (pix uint8 [V, T, k] in draw order, w float64 [V, T, k],
+    margin float64 [V, T, k] = distance of the uniform number to the nearer
+    end of its interval, the room the decision has for rounding)."""
+    s = np.asarray(scores, dtype=np.float64)
+    e = np.exp(s - s.max(axis=-1, keepdims=True))         # softmax numerator (shift-invariant)
+    q = e / e.sum(axis=-1, keepdims=True)
+    Q = np.cumsum(q, axis=-1)
+    Q[..., -1] = 1.0
+    u = draw_uniforms(seed, it, cam_ids, n_tiles, k)
+    # smallest p with Q_p > u = the number of p with Q_p <= u (Q is non-decreasing)
+    pix = np.empty(u.shape, dtype=np.int64)
+    for v in range(u.shape[0]):
+        pix[v] = (Q[v][:, None, :] <= u[v][:, :, None]).sum(axis=-1)
+    pix = np.minimum(pix, 255)
+    qp = np.take_along_axis(q, pix, axis=-1)
+    hi = np.take_along_axis(Q, pix, axis=-1)
+    lo = hi - qp
+    margin = np.minimum(u - lo, hi - u)
+    return pix.astype(np.uint8), 1.0 / (k * qp), margin

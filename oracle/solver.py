@@ -10,14 +10,17 @@ products. Readings of the paper that this code fixes:
 * the loop stops early (keeping x) if p^T A p <= 0 or r^T z has collapsed;
 * learning rate (Sec. 4.5, Supp. D): eta = 0.05 for the first 10 LM
   iterations, afterwards min(0.2, 1 / max |x_dc|) with x_dc the DC colour
-  coefficients of the solution (so the largest colour change is at most 1).
+  coefficients of the solution (so the largest colour change is at most 1);
+* residual-weighted sampling (Supp. E, q_residual): the distribution comes
+  from a render of every pixel of the batch views at the current parameters,
+  with |r_p| = |r_p,R| + |r_p,G| + |r_p,B|; see ``residual_scores``.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import Oracle
-from .sampling import sample_uniform
+from .sampling import sample_residual, sample_uniform
 
 
 def pcg(apply_A, b: np.ndarray, m_inv: np.ndarray, iters: int):
@@ -65,13 +68,30 @@ def gather_targets(targets: np.ndarray, orc: Oracle) -> np.ndarray:
     return targets[v, y, x].astype(np.float64)
 
 
+def residual_scores(orc: Oracle, targets: np.ndarray) -> np.ndarray:
+    """|r_p| = sum over channels of |I_hat_p - I_p| at every pixel of the
+    oracle's views (targets [V, H, W, 3] of those views), as [V, T, 256] in
+    tile-major pixel order. Leaves the oracle sampling every pixel."""
+    orc.set_samples(256)
+    res = orc.render()["C"] - gather_targets(targets, orc)
+    return np.abs(res).sum(axis=1).reshape(orc.V, orc.T, 256)
+
+
 def lm_step(n, sh_degree, beta, cams_all, targets_all, view_ids, width, height, k, seed, it, lam,
-            cg_iters, d=None, opts=None):
-    """Alg. 1 for one LM iteration. Returns (beta_next float32, info dict)."""
+            cg_iters, d=None, opts=None, sampler="uniform"):
+    """Alg. 1 for one LM iteration. Returns (beta_next float32, info dict).
+
+    sampler: "uniform" (Sec. 4.4; k = 256 takes every pixel) or "residual"
+    (Supp. E q_residual, k draws per tile with replacement)."""
     view_ids = np.asarray(view_ids, dtype=np.int64)
     cams = cams_all[view_ids]                                   # getBatch (view sampling)
     orc = Oracle(n, sh_degree, beta, cams, width, height, opts)  # splatting: project + bin
-    if k >= 256:
+    margin = None
+    if sampler == "residual":
+        scores = residual_scores(orc, targets_all[view_ids])
+        pix, w, margin = sample_residual(seed, it, view_ids, orc.T, k, scores)
+        orc.set_samples(k, pix, w)
+    elif k >= 256:
         orc.set_samples(256)
     else:
         pix, w = sample_uniform(seed, it, view_ids, orc.T, k)
@@ -87,7 +107,8 @@ def lm_step(n, sh_degree, beta, cams_all, targets_all, view_ids, width, height, 
     eta = learning_rate(x, n, it)
     beta_next = (beta.astype(np.float64) - eta * x).astype(np.float32)
     info = dict(loss_sampled=float(np.sum(wts[:, None] * res ** 2)), b=b, diag=D, x=x, eta=eta,
-                cg_norms=norms, cg_done=done, residual=res, weights=wts)
+                cg_norms=norms, cg_done=done, residual=res, weights=wts, samples=orc.pix,
+                sample_margin=margin)
     return beta_next, info
 
 

@@ -160,3 +160,28 @@ def test_lm_step_with_sampling_descends(cfg0_targets):
                          w.lam, 6)
     assert np.all(info["weights"] == 4.0)
     assert full_loss(w.n, 0, beta, w.cams, tg, w.width, w.height) < l0
+
+
+def test_residual_scores_follow_tile_major_pixel_order(cfg0_targets):
+    """scores[v, t, p] is the L1 residual of image pixel (x, y) with
+    t = (y // 16) * (W / 16) + x // 16 and p = 16 (y % 16) + x % 16."""
+    from oracle.solver import residual_scores
+    w, tg = cfg0_targets
+    orc = Oracle(w.n, 0, w.beta_init, w.cams, w.width, w.height)
+    sc = residual_scores(orc, tg)
+    img = orc.render_image()
+    ref = np.abs(img - tg).sum(axis=-1)                      # [V, H, W]
+    TX = w.width // 16
+    for (v, y, x) in [(0, 0, 0), (1, 17, 5), (3, 63, 63), (2, 40, 22)]:
+        t, p = (y // 16) * TX + x // 16, 16 * (y % 16) + x % 16
+        assert sc[v, t, p] == pytest.approx(ref[v, y, x], rel=1e-12, abs=1e-15)
+
+
+def test_lm_step_with_residual_sampling_descends(cfg0_targets):
+    w, tg = cfg0_targets
+    l0 = full_loss(w.n, 0, w.beta_init, w.cams, tg, w.width, w.height)
+    beta, info = lm_step(w.n, 0, w.beta_init, w.cams, tg, np.arange(4), w.width, w.height, 32, 3, 0,
+                         w.lam, 6, sampler="residual")
+    assert float(info["b"] @ info["x"]) > 0
+    assert info["weights"].min() > 0
+    assert full_loss(w.n, 0, beta, w.cams, tg, w.width, w.height) < l0
