@@ -96,14 +96,17 @@ def traffic_from_profile(kernel_hash: str):
         return None
 
 
-def cpu_baseline(w, beta, cams_np, view_ids, pix, wts, lam, p, budget_s=20.0):
-    """FP64 oracle GN products/s on the same product the GPU timed: all batch
-    views, the same samples, parameters and direction p. The first call also
+def cpu_baseline(w, beta, cams_np, view_ids, pix, wts, lam, p, budget_s=20.0, n_views=None):
+    """FP64 oracle GN products/s on the same product the GPU timed: the batch
+    views (or the first n_views of them, the time then scaled to the whole
+    batch), the same samples, parameters and direction p. The first call also
     builds the record Jacobians the later calls reuse (reported apart); then
     products are repeated until about `budget_s` seconds of CPU work."""
     from oracle import Oracle, num_threads
-    orc = Oracle(w.n, w.sh_degree, beta, cams_np[view_ids], w.width, w.height)
-    orc.set_samples(pix.shape[-1], pix, wts)
+    V = len(view_ids)
+    nv = V if n_views is None else n_views
+    orc = Oracle(w.n, w.sh_degree, beta, cams_np[view_ids[:nv]], w.width, w.height)
+    orc.set_samples(pix.shape[-1], pix[:nv], wts[:nv])
     pd = p.astype(np.float64)
     t0 = time.perf_counter()
     ref = orc.gn(pd, lam)
@@ -113,13 +116,14 @@ def cpu_baseline(w, beta, cams_np, view_ids, pix, wts, lam, p, budget_s=20.0):
         t0 = time.perf_counter()
         orc.gn(pd, lam)
         times.append(time.perf_counter() - t0)
-    t1 = float(np.median(times))
-    V = len(view_ids)
+    t1 = float(np.median(times)) * V / nv
+    part = (f"the full GN product of one LM step ({V} views" if nv == V else
+            f"the GN product restricted to {nv} of the {V} batch views, time scaled by {V}/{nv} ({nv} views")
     return {"value": round(1.0 / t1, 4), "unit": "GN products/s", "cores": num_threads(), "kind": "oracle",
-            "sample": f"the full GN product of one LM step ({V} views, {pix.shape[-1]} samples/tile, same "
-                      f"parameters and p as the GPU's timed product); median of {len(times)} products after "
-                      f"a first call of {first:.1f} s that also builds the record Jacobians",
-            "seconds_per_product": round(t1, 4)}, ref
+            "sample": f"{part}, {pix.shape[-1]} samples/tile, same parameters and p as the GPU's timed "
+                      f"product); median of {len(times)} products after a first call of {first:.1f} s that "
+                      f"also builds the record Jacobians",
+            "seconds_per_product": round(t1, 4)}, (ref if nv == V else None)
 
 
 def copy_calibration(torch, dev, mib=1024, reps=3):
@@ -189,6 +193,43 @@ def summarize_traffic(fetch_dir: str, write_dir: str, copy_mib: int, command: st
     return text
 
 
+def lm_breakdown(L, torch, fr, targets, w, sampler, it, gn_ms):
+    """Wall milliseconds of each stage of one LM step, each run on its own
+    through the C ABI at the current parameters (synchronised before and
+    after, so launch overheads are included); the PCG vector work is the PCG
+    call minus its diagonal and GN products."""
+    dev = fr.beta.device
+
+    def wall(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    out = {"project": wall(lambda: L.lmrs_project(fr)), "bin": wall(lambda: L.lmrs_bin_tiles(fr))}
+    if sampler == L.SAMPLER_RESIDUAL:
+        scores = torch.empty((fr.n_views, fr.T, 256), dtype=torch.float32, device=dev)
+        out["full render (residual scores)"] = wall(lambda: L.lmrs_residual_scores(fr, targets, out=scores))
+        out["sample"] = wall(lambda: L.lmrs_sample(fr, sampler, w.seed, it, scores))
+    else:
+        out["sample"] = wall(lambda: L.lmrs_sample(fr, sampler, w.seed, it))
+    out["render"] = wall(lambda: L.lmrs_render(fr))
+    u = torch.randn((fr.S, 3), generator=torch.Generator(device="cpu").manual_seed(1)).to(dev)
+    b = torch.empty(fr.P, dtype=torch.float32, device=dev)
+    L.lmrs_vjp(fr, u, out=b)
+    out["b = J^T W r"] = wall(lambda: L.lmrs_vjp(fr, u, out=b))
+    dg = torch.empty_like(b)
+    L.lmrs_gn_diag(fr, out=dg)
+    out["diag"] = wall(lambda: L.lmrs_gn_diag(fr, out=dg))
+    out[f"{w.cg_iters} GN products"] = w.cg_iters * gn_ms
+    x = torch.empty_like(b)
+    L.lmrs_pcg(fr, b, w.lam, w.cg_iters, x=x)
+    pcg = wall(lambda: L.lmrs_pcg(fr, b, w.lam, w.cg_iters, x=x))
+    out["PCG vector work"] = max(0.0, pcg - out["diag"] - w.cg_iters * gn_ms)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,7 +237,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--gn-reps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--n", type=int, default=None, help="Gaussians (default: the workload's)")
+    ap.add_argument("--workload", choices=["cfg1", "cfg2"], default="cfg1",
+                    help="cfg1: 100k-Gaussian object-scale fit (default); cfg2: 1.5M-Gaussian "
+                         "unbounded-scene fit with residual-weighted sampling")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run MIB-MiB device copies before the GN timing (HBM-counter calibration)")
@@ -218,7 +262,12 @@ def main():
     from paper_2504_12905_amd import synth
 
     dev = "cuda:0"
-    w = synth.config1(n=args.n)
+    if args.workload == "cfg1":
+        w = synth.config1(**({} if args.n is None else {"n": args.n}))
+        sampler = L.SAMPLER_UNIFORM
+    else:
+        w = synth.config2(**({} if args.n is None else {"n": args.n}))
+        sampler = L.SAMPLER_RESIDUAL
     cams = torch.tensor(w.cams, device=dev)
     beta_gt = torch.tensor(w.beta_gt, device=dev)
     log(f"[bench] {w.name}: rendering {w.cams.shape[0]} targets")
@@ -235,7 +284,8 @@ def main():
     def step(it):
         view_ids.copy_(torch.tensor(rng.choice(w.cams.shape[0], V, replace=False).astype(np.int32)))
         # the binding allocates a larger workspace itself if the tile lists outgrow ws
-        L.lmrs_lm_step(fr, targets, L.lm_params(it, w.cg_iters, w.lam, seed=w.seed), report=rep, ws=ws)
+        L.lmrs_lm_step(fr, targets, L.lm_params(it, w.cg_iters, w.lam, seed=w.seed, sampler=sampler), report=rep,
+                       ws=ws)
 
     log(f"[bench] warmup {args.warmup} LM steps")
     it = 0
@@ -301,6 +351,9 @@ def main():
     unfused_ms = e0.elapsed_time(e1) / args.gn_reps
     out_gpu = out.double().cpu().numpy()
 
+    breakdown = lm_breakdown(L, torch, fr, targets, w, sampler, it, gn_ms)
+    log("[bench] LM-step stages (ms, each run alone): " + ", ".join(f"{k} {v:.2f}" for k, v in breakdown.items()))
+
     # --- algorithmic work of the fused splat kernel in this launch
     last = fr.last.view(V * fr.T, k).to(torch.int64)
     entries = int((last.max(dim=1).values + 1).clamp(min=0).sum().item())
@@ -334,10 +387,12 @@ def main():
     if not args.no_cpu:
         log("[bench] CPU oracle baseline (the same GN product in FP64)")
         cpu, ref = cpu_baseline(w, fr.beta.cpu().numpy(), w.cams, view_ids.cpu().numpy(), fr.pix.cpu().numpy(),
-                                fr.w.cpu().numpy(), w.lam, p.cpu().numpy(), args.cpu_budget)
-        parity = float(np.linalg.norm(out_gpu - ref) / np.linalg.norm(ref))
+                                fr.w.cpu().numpy(), w.lam, p.cpu().numpy(), args.cpu_budget,
+                                n_views=None if args.workload == "cfg1" else 2)
+        if ref is not None:
+            parity = float(np.linalg.norm(out_gpu - ref) / np.linalg.norm(ref))
         log(f"[bench] oracle {cpu['value']:.4f} GN products/s on {cpu['cores']} threads; "
-            f"GPU vs oracle rel {parity:.2e}")
+            f"GPU vs oracle rel {parity}")
 
     res = {
         "metric": METRIC, "value": round(value, 3), "unit": "GN products/s", "n_gpus": 1,
@@ -351,7 +406,9 @@ def main():
                    "gn_products_per_s_isolated": round(1e3 / gn_ms, 2),
                    "gn_phase_ms_median": [round(float(x), 4) for x in phase_ms],
                    "gn_unfused_jvp_vjp_ms": round(unfused_ms, 4),
-                   "gn_parity_rel_vs_oracle": parity},
+                   "gn_parity_rel_vs_oracle": parity,
+                   "sampler": "residual" if sampler == L.SAMPLER_RESIDUAL else "uniform",
+                   "lm_step_stage_ms": {k: round(v, 3) for k, v in breakdown.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -127,7 +127,13 @@ typedef struct lmrs_lm_params {
   float eta_warm;       /* fixed learning rate of the first iterations (0.05)  */
   int32_t warm_iters;   /* number of such iterations (10)                       */
   uint64_t seed;        /* residual-sampler seed                                */
+  int32_t sampler;      /* LMRS_SAMPLER_UNIFORM or LMRS_SAMPLER_RESIDUAL        */
 } lmrs_lm_params;
+
+/* Pixel samplers (lmrs_sample, lmrs_lm_params.sampler). */
+#define LMRS_SAMPLER_UNIFORM 0   /* Sec. 4.4: k distinct pixels per tile        */
+#define LMRS_SAMPLER_RESIDUAL 1  /* Supp. E q_residual: k draws per tile with
+                                    replacement from the softmax of |r|         */
 
 /* Slots of the device report written by lmrs_pcg / lmrs_lm_step. */
 #define LMRS_REPORT_FLOATS 8
@@ -211,10 +217,35 @@ lmrs_status lmrs_pcg(const lmrs_frame* f, const lmrs_render_opts* o, const float
                      const float* d, int32_t iters, float* x, float* report, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* Residual magnitudes for the residual-weighted sampler (Supp. E, eq. 16):
+ * renders every pixel of the batch views (as lmrs_render with k = 256) and
+ * writes scores[(v * T + t) * 256 + p] = |C_R - I_R| + |C_G - I_G| + |C_B - I_B|,
+ * C with background, I from targets (device [*][height][width][3], indexed
+ * by camera id f->view_ids[v]). Needs rec, rect and the tile lists; f->k,
+ * f->pix and the render outputs are not used. scores: device [V][T][256]. */
+lmrs_status lmrs_residual_scores(const lmrs_frame* f, const lmrs_render_opts* o, const float* targets,
+                                 float* scores, void* stream);
+
+/* a4. Stratified pixel sampling (Sec. 4.4), writes f->pix and f->w
+ * ([V][T][k], device; both must be non-NULL).
+ * LMRS_SAMPLER_UNIFORM: k distinct pixels per tile, the k smallest
+ *   (Philox4x32-10 word of counter (p, tile, camera id, iter), p) with
+ *   key = seed, in ascending pixel order; weight 256/k.
+ * LMRS_SAMPLER_RESIDUAL (Supp. E q_residual): inside each tile
+ *   q(p) = exp(s_p) / sum exp(s), s = scores (lmrs_residual_scores); draw j
+ *   takes u_j = (top 24 bits of the first Philox word of counter
+ *   (256 + j, tile, camera id, iter)) * 2^-24 and the smallest p whose
+ *   running sum of q in pixel order exceeds u_j; k draws with replacement
+ *   in draw order, weight 1 / (k q(p)). scores is ignored by the uniform
+ *   sampler and may be NULL there. Unknown sampler: LMRS_EINVAL. */
+lmrs_status lmrs_sample(const lmrs_frame* f, int32_t sampler, uint64_t seed, int32_t iter, const float* scores,
+                        void* stream);
+
 /* a1-a8. One LM iteration of Alg. 1 on the batch views f->view_ids:
- * project, bin, sample k pixels per tile (Sec. 4.4; uniform without
- * replacement by Philox4x32-10 keys, weight 256/k; k = 256 takes every
- * pixel with weight 1), render, residuals r = C - I against targets
+ * project, bin, sample k pixels per tile (prm->sampler, as lmrs_sample;
+ * the residual sampler first renders every pixel for its scores; with the
+ * uniform sampler and f->pix NULL, k = 256 takes every pixel with weight 1),
+ * render, residuals r = C - I against targets
  * (device [*][height][width][3], indexed by camera id), b = J^T W r,
  * Jacobi-PCG, learning rate (Sec. 4.5: eta_warm for iter < warm_iters, else
  * min(eta_cap, 1 / max |x_dc|)) and the descent update beta <- beta - eta x.

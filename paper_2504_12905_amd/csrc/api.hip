@@ -53,6 +53,7 @@ struct Scratch {
   float* b = nullptr;
   float* x = nullptr;
   float* wr = nullptr;
+  float* scores = nullptr;
   double* sc = nullptr;
   double* red = nullptr;
   BinScratch bin{};
@@ -90,6 +91,7 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
     s.b = c.take<float>(P);
     s.x = c.take<float>(P);
     s.wr = c.take<float>((size_t)d.S * 3);
+    s.scores = c.take<float>((size_t)d.V * d.T * 256);
   }
   s.red = c.take<double>(kRedDoubles);
   return s;
@@ -401,6 +403,34 @@ lmrs_status lmrs_pcg(const lmrs_frame* f, const lmrs_render_opts* o, const float
   return hip_check("lmrs_pcg");
 }
 
+lmrs_status lmrs_residual_scores(const lmrs_frame* f, const lmrs_render_opts* o, const float* targets,
+                                 float* scores, void* stream) {
+  LMRS_TRY(check_frame(f, false));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_render_state(f));
+  LMRS_TRY(need(targets, "targets"));
+  LMRS_TRY(need(scores, "scores"));
+  launch_render_scores(f, dims_of(f), *o, targets, scores, (hipStream_t)stream);
+  return hip_check("lmrs_residual_scores");
+}
+
+lmrs_status lmrs_sample(const lmrs_frame* f, int32_t sampler, uint64_t seed, int32_t iter, const float* scores,
+                        void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(f->pix, "pix"));
+  LMRS_TRY(need(f->w, "w"));
+  const FrameDims d = dims_of(f);
+  if (sampler == LMRS_SAMPLER_UNIFORM) {
+    launch_sample_uniform(f, d, seed, iter, (hipStream_t)stream);
+  } else if (sampler == LMRS_SAMPLER_RESIDUAL) {
+    LMRS_TRY(need(scores, "scores"));
+    launch_sample_residual(f, d, scores, seed, iter, (hipStream_t)stream);
+  } else {
+    return fail(LMRS_EINVAL, "unknown sampler %d", sampler);
+  }
+  return hip_check("lmrs_sample");
+}
+
 lmrs_status lmrs_lm_step(lmrs_frame* f, float* beta, const float* targets, const float* dvec,
                          const lmrs_lm_params* prm, const lmrs_render_opts* o, float* report, void* ws,
                          size_t ws_bytes, void* stream) {
@@ -416,6 +446,10 @@ lmrs_status lmrs_lm_step(lmrs_frame* f, float* beta, const float* targets, const
   LMRS_TRY(need(f->trans, "trans"));
   LMRS_TRY(need(f->last, "last"));
   if (f->k < 256 && (!f->pix || !f->w)) return fail(LMRS_EINVAL, "k < 256 needs pix and w buffers");
+  if (prm->sampler != LMRS_SAMPLER_UNIFORM && prm->sampler != LMRS_SAMPLER_RESIDUAL)
+    return fail(LMRS_EINVAL, "unknown sampler %d", prm->sampler);
+  if (prm->sampler == LMRS_SAMPLER_RESIDUAL && (!f->pix || !f->w))
+    return fail(LMRS_EINVAL, "the residual sampler needs pix and w buffers");
   if (prm->cg_iters < 0) return fail(LMRS_EINVAL, "cg_iters must be >= 0");
   if (!(prm->lambda >= 0.f)) return fail(LMRS_EINVAL, "lambda must be >= 0");
   LMRS_TRY(check_ws(LMRS_OP_LM, f, ws, ws_bytes));
@@ -427,7 +461,12 @@ lmrs_status lmrs_lm_step(lmrs_frame* f, float* beta, const float* targets, const
   launch_project(f, d, *o, st);
   int64_t total = 0;
   LMRS_TRY(bin_sequence(f, d, s, st, &total));
-  if (f->pix) launch_sample_uniform(f, d, prm->seed, prm->iter, st);
+  if (prm->sampler == LMRS_SAMPLER_RESIDUAL) {
+    launch_render_scores(f, d, *o, targets, s.scores, st);
+    launch_sample_residual(f, d, s.scores, prm->seed, prm->iter, st);
+  } else if (f->pix) {
+    launch_sample_uniform(f, d, prm->seed, prm->iter, st);
+  }
   launch_render(f, d, *o, st);
   launch_residual(f, d, targets, s.wr, s.red, report, st);
   vjp_sequence(f, d, *o, s.wr, s.b, s, st);

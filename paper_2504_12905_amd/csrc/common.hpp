@@ -427,6 +427,11 @@ __device__ __forceinline__ int wave_max_i(int x) {
   for (int d = 32; d > 0; d >>= 1) x = max(x, __shfl_xor(x, d, kWave));
   return x;
 }
+__device__ __forceinline__ float wave_max_f(float x) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) x = fmaxf(x, __shfl_xor(x, d, kWave));
+  return x;
+}
 
 // Upper-triangle index of (i, j), i <= j < 5, in a 5x5 symmetric block.
 __host__ __device__ constexpr int sym5(int i, int j) { return i * 5 - i * (i - 1) / 2 + (j - i); }

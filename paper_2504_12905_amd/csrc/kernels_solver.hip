@@ -67,6 +67,56 @@ __global__ __launch_bounds__(256) void sample_kernel(const int32_t* __restrict__
   }
 }
 
+// Residual-weighted sampling (Supp. E, q_residual) inside each tile: pixel p
+// has probability q(p) = e_p / Z with e_p = exp(s_p - max s), Z = sum e_p and
+// s_p the pixel's residual magnitude. One workgroup of 256 lanes per (view,
+// tile); lane p computes e_p, one lane forms the running sums Q_p = e_0 + ...
+// + e_p in pixel order (so Q is non-decreasing), and lane j < k takes draw j:
+// the 24-bit uniform u_j from the first Philox word of counter
+// (256 + j, tile, camera id, iteration), then the smallest p with
+// Q_p > u_j Z, weight 1 / (k q(p)) = Z / (k e_p). Draws are with
+// replacement and listed in draw order.
+__global__ __launch_bounds__(256) void sample_residual_kernel(const float* __restrict__ scores,
+                                                              const int32_t* __restrict__ view_ids, int T,
+                                                              int k, uint32_t seed_lo, uint32_t seed_hi,
+                                                              uint32_t iter, uint8_t* __restrict__ pix,
+                                                              float* __restrict__ w) {
+  __shared__ float s_e[256];
+  __shared__ float s_q[256];
+  __shared__ float s_m[4];
+  const int p = threadIdx.x;
+  const int64_t tile_lin = blockIdx.x;
+  const int v = (int)(tile_lin / T), t = (int)(tile_lin % T);
+  const float sp = scores[tile_lin * 256 + p];
+  const float wm = wave_max_f(sp);
+  if (lane_id() == 0) s_m[p / kWave] = wm;
+  __syncthreads();
+  const float m = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
+  const float e = expf(sp - m);
+  s_e[p] = e;
+  __syncthreads();
+  if (p == 0) {
+    float acc = 0.f;
+    for (int q = 0; q < 256; ++q) {
+      acc += s_e[q];
+      s_q[q] = acc;
+    }
+  }
+  __syncthreads();
+  if (p >= k) return;
+  const uint32_t cam = (uint32_t)(view_ids ? view_ids[v] : v);
+  const uint4 r = philox4x32_10(make_uint4(256u + (uint32_t)p, (uint32_t)t, cam, iter), seed_lo, seed_hi);
+  const float Z = s_q[255];
+  const float target = (float)(r.x >> 8) * 0x1p-24f * Z;
+  int lo = 0, hi = 255;  // smallest index with s_q > target; index 255 if none
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (s_q[mid] > target) hi = mid; else lo = mid + 1;
+  }
+  pix[tile_lin * k + p] = (uint8_t)lo;
+  w[tile_lin * k + p] = Z / ((float)k * s_e[lo]);
+}
+
 // wr = w * (C - I) at every sampled pixel; partial sums of w |C - I|^2.
 __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__ color,
                                                        const float* __restrict__ targets,
@@ -303,6 +353,13 @@ void launch_sample_uniform(const lmrs_frame* f, const FrameDims& d, uint64_t see
   sample_kernel<<<(unsigned)((int64_t)d.V * d.T), 256, 0, s>>>(
       f->view_ids, d.T, d.k, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)iter, f->pix,
       f->w);
+}
+
+void launch_sample_residual(const lmrs_frame* f, const FrameDims& d, const float* scores, uint64_t seed,
+                            int iter, hipStream_t s) {
+  sample_residual_kernel<<<(unsigned)((int64_t)d.V * d.T), 256, 0, s>>>(
+      scores, f->view_ids, d.T, d.k, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)iter,
+      f->pix, f->w);
 }
 
 void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targets, float* wr,

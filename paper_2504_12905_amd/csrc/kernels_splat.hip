@@ -100,14 +100,25 @@ __device__ __forceinline__ int load_pixel_regs(const uint8_t* pix, const float* 
 __device__ __forceinline__ float log2_om(bool inc, float a) { return inc ? __log2f(1.f - a) : 0.f; }
 
 // ------------------------------------------------------------------ render
-template <int NS>
+// SCORE = false: colour (with background), final transmittance and last
+// blended position of every sampled pixel. SCORE = true (every pixel, k = 256):
+// only the pixel's residual magnitude |C_R - I_R| + |C_G - I_G| + |C_B - I_B|
+// against the target image of its camera, for the residual-weighted sampler.
+struct ScoreOut {
+  const float* targets;     // [cameras][H][W][3]
+  const int32_t* view_ids;  // [V] or NULL
+  int W, H;
+  float* score;             // [V][T][256]
+};
+
+template <int NS, bool SCORE>
 __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__ rec,
                                                        const int64_t* __restrict__ tile_start,
                                                        const int32_t* __restrict__ ids,
                                                        const uint8_t* __restrict__ pix, int n, int T,
                                                        int TX, int k, lmrs_render_opts o,
                                                        float* __restrict__ color, float* __restrict__ trans,
-                                                       int32_t* __restrict__ last) {
+                                                       int32_t* __restrict__ last, ScoreOut so) {
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX);
   PixelRegs<NS> pr;
@@ -160,16 +171,27 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
       }
     }
   }
+  const int cam = SCORE ? (so.view_ids ? so.view_ids[c.v] : c.v) : 0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int j = s * kWave + lane;
     if (j < k) {
       const int64_t i = c.tile_lin * k + j;
-      color[3 * i] = sC0[s] + sT[s] * o.bg[0];
-      color[3 * i + 1] = sC1[s] + sT[s] * o.bg[1];
-      color[3 * i + 2] = sC2[s] + sT[s] * o.bg[2];
-      trans[i] = sT[s];
-      last[i] = sLast[s];
+      const float c0 = sC0[s] + sT[s] * o.bg[0];
+      const float c1 = sC1[s] + sT[s] * o.bg[1];
+      const float c2 = sC2[s] + sT[s] * o.bg[2];
+      if (SCORE) {
+        const int p = pix ? (int)pix[i] : j;
+        const int x = (c.t % TX) * kTile + (p & 15), y = (c.t / TX) * kTile + (p >> 4);
+        const float* tg = so.targets + (((int64_t)cam * so.H + y) * so.W + x) * 3;
+        so.score[i] = (fabsf(c0 - tg[0]) + fabsf(c1 - tg[1])) + fabsf(c2 - tg[2]);
+      } else {
+        color[3 * i] = c0;
+        color[3 * i + 1] = c1;
+        color[3 * i + 2] = c2;
+        trans[i] = sT[s];
+        last[i] = sLast[s];
+      }
     }
   }
 }
@@ -454,12 +476,21 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
 
 void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
+  const ScoreOut none{nullptr, nullptr, 0, 0, nullptr};
   if (d.k <= kWave)
-    render_kernel<1><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k, o,
-                                                 f->color, f->trans, f->last);
+    render_kernel<1, false><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k,
+                                                    o, f->color, f->trans, f->last, none);
   else
-    render_kernel<4><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k, o,
-                                                 f->color, f->trans, f->last);
+    render_kernel<4, false><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k,
+                                                    o, f->color, f->trans, f->last, none);
+}
+
+void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
+                          const float* targets, float* scores, hipStream_t s) {
+  const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
+  const ScoreOut so{targets, f->view_ids, d.W, d.H, scores};
+  render_kernel<4, true><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, nullptr, d.n, d.T, d.TX, 256, o,
+                                                 nullptr, nullptr, nullptr, so);
 }
 
 void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,

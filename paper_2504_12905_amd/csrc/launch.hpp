@@ -41,6 +41,9 @@ void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b,
 
 // splatting (kernels_splat.hip)
 void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s);
+// every pixel of the batch views: scores[V][T][256] = sum_c |C_c - I_c| against targets
+void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
+                          const float* targets, float* scores, hipStream_t s);
 // mode: 1 = J p only (writes jp), 2 = J^T u only (reads u), 3 = fused GN (J^T W J p)
 void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                   const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s);
@@ -51,6 +54,8 @@ void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts
 constexpr int kRedBlocks = 512;  // partial sums per reduction
 void launch_sample_uniform(const lmrs_frame* f, const FrameDims& d, uint64_t seed, int iter,
                            hipStream_t s);
+void launch_sample_residual(const lmrs_frame* f, const FrameDims& d, const float* scores, uint64_t seed,
+                            int iter, hipStream_t s);
 void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targets, float* wr,
                      double* partials, float* report, hipStream_t s);
 void launch_dot(const float* a, const float* b, int64_t n, double* partials, double* out, hipStream_t s);

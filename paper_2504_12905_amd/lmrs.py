@@ -25,6 +25,7 @@ LMRS_OK, LMRS_EINVAL, LMRS_ECAPACITY, LMRS_EWORKSPACE, LMRS_EHIP = 0, -1, -2, -3
 LMRS_REC = 12
 OP_BIN, OP_JVP, OP_VJP, OP_GN, OP_DIAG, OP_PCG, OP_LM = 1, 2, 3, 4, 5, 6, 7
 REPORT_FLOATS = 8
+SAMPLER_UNIFORM, SAMPLER_RESIDUAL = 0, 1
 REP = dict(loss=0, eta=1, xdc_max=2, cg_done=3, r0=4, rn=5, bx=6, instances=7)
 
 
@@ -64,7 +65,7 @@ class _Frame(C.Structure):
 class LmParams(C.Structure):
     _fields_ = [("iter", C.c_int32), ("cg_iters", C.c_int32), ("lam", C.c_float),
                 ("eta_cap", C.c_float), ("eta_warm", C.c_float), ("warm_iters", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("sampler", C.c_int32)]
 
 
 _vp, _i32, _f32, _sz = C.c_void_p, C.c_int32, C.c_float, C.c_size_t
@@ -84,8 +85,11 @@ _lib.lmrs_gn_product_timed.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, 
 _lib.lmrs_gn_diag.argtypes = [_FP, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_pcg.argtypes = [_FP, _vp, _vp, _f32, _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_lm_step.argtypes = [_FP, _vp, _vp, _vp, C.POINTER(LmParams), _vp, _vp, _vp, _sz, _vp]
+_lib.lmrs_residual_scores.argtypes = [_FP, _vp, _vp, _vp, _vp]
+_lib.lmrs_sample.argtypes = [_FP, _i32, C.c_uint64, _i32, _vp, _vp]
 for _name in ("lmrs_project", "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp",
-              "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step"):
+              "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step",
+              "lmrs_residual_scores", "lmrs_sample"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -279,6 +283,30 @@ def lmrs_pcg(frame: Frame, b: torch.Tensor, lam: float, iters: int, d: torch.Ten
     return x
 
 
+def lmrs_residual_scores(frame: Frame, targets: torch.Tensor, out: torch.Tensor | None = None, opts=None,
+                         stream=None) -> torch.Tensor:
+    """[V, T, 256] residual magnitudes of every pixel (needs project + bin)."""
+    opts = opts or default_opts()
+    assert targets.dtype == torch.float32 and targets.is_contiguous()
+    out = out if out is not None else torch.empty((frame.n_views, frame.T, 256), dtype=torch.float32,
+                                                  device=frame.beta.device)
+    fs = frame.struct()
+    _check(_lib.lmrs_residual_scores(C.byref(fs), C.byref(opts), _ptr(targets), _ptr(out), _stream(stream)),
+           "lmrs_residual_scores")
+    return out
+
+
+def lmrs_sample(frame: Frame, sampler: int, seed: int, iter: int, scores: torch.Tensor | None = None,
+                stream=None):
+    """Fills frame.pix / frame.w (frame must be sampled)."""
+    if scores is not None:
+        assert scores.dtype == torch.float32 and scores.is_contiguous()
+        assert scores.numel() == frame.n_views * frame.T * 256
+    fs = frame.struct()
+    _check(_lib.lmrs_sample(C.byref(fs), int(sampler), int(seed), int(iter), _ptr(scores), _stream(stream)),
+           "lmrs_sample")
+
+
 def lmrs_lm_step(frame: Frame, targets: torch.Tensor, params: LmParams, d: torch.Tensor | None = None,
                  report: torch.Tensor | None = None, opts=None, stream=None, ws: torch.Tensor | None = None):
     """One LM iteration in place on frame.beta; grows the id buffer and retries on overflow."""
@@ -298,12 +326,11 @@ def lmrs_lm_step(frame: Frame, targets: torch.Tensor, params: LmParams, d: torch
 
 
 def lm_params(iter: int, cg_iters: int, lam: float, seed: int = 0, eta_cap: float = 0.2,
-              eta_warm: float = 0.05, warm_iters: int = 10) -> LmParams:
+              eta_warm: float = 0.05, warm_iters: int = 10, sampler: int = SAMPLER_UNIFORM) -> LmParams:
     return LmParams(int(iter), int(cg_iters), float(lam), float(eta_cap), float(eta_warm), int(warm_iters),
-                    int(seed))
+                    int(seed), int(sampler))
 
 
 EXPORTS = ("lmrs_status_str", "lmrs_last_error", "lmrs_workspace_bytes", "lmrs_project", "lmrs_bin_tiles",
            "lmrs_render", "lmrs_jvp", "lmrs_vjp", "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_diag",
-           "lmrs_pcg",
-           "lmrs_lm_step")
+           "lmrs_pcg", "lmrs_lm_step", "lmrs_residual_scores", "lmrs_sample")
