@@ -230,6 +230,53 @@ def lm_breakdown(L, torch, fr, targets, w, sampler, it, gn_ms):
     return out
 
 
+def serving_main(args):
+    """Served fits/s and p50/p99 latency on a Poisson stream of fit requests,
+    against the plain sequential solver on the same GPU."""
+    import torch
+
+    from paper_2504_12905_amd import serving, synth
+
+    stream = synth.request_stream(args.requests, args.rate, seed=0)
+    reqs = [serving.FitRequest.from_stream(d) for d in stream]
+    if args.lm_iters:
+        for r in reqs:
+            r.lm_iters = args.lm_iters
+    log(f"[serve] preparing {len(reqs)} requests on the host")
+    probs = [serving.make_problem(r) for r in reqs]
+    budget = int(args.hbm_budget_gb * 2 ** 30)
+    # warm the library's kernels once (code-object loading) outside both runs
+    serving.run_sequential([serving.make_problem(serving.FitRequest(seed=999, n=2000, sh_degree=3, n_views=4,
+                                                                    res=256, lm_iters=2))])
+    log("[serve] sequential plain solves")
+    seq = serving.run_sequential(probs)
+    s_seq = serving.summarize(seq, probs)
+    log(f"[serve] sequential: {s_seq}")
+    log(f"[serve] continuous batching, {args.slots} slots, budget {args.hbm_budget_gb} GiB")
+    srv = serving.Server(budget, max_slots=args.slots, use_graphs=not args.no_graphs)
+    for p in probs:
+        srv.submit(p.req, p)
+    got = srv.run_until_idle()
+    s_srv = serving.summarize(got, probs)
+    log(f"[serve] served: {s_srv}")
+    dpsnr = max(abs(got[i].final_psnr - seq[i].final_psnr) for i in got)
+    dbeta = max(float(np.linalg.norm(got[i].beta - seq[i].beta) / np.linalg.norm(seq[i].beta)) for i in got)
+    torch.cuda.synchronize()
+    res = {
+        "metric": "served fits/s (continuous batching) vs sequential plain solves", "value": round(s_srv["fits_per_s"], 4),
+        "unit": "fits/s", "n_gpus": 1, "steps": len(reqs), "warmup": 0,
+        "ms_per_step": round(1e3 / s_srv["fits_per_s"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"fit-request stream: {len(reqs)} requests, Poisson {args.rate} req/s",
+                   "lm_iters": reqs[0].lm_iters, "cg_iters": reqs[0].cg_iters, "slots": args.slots,
+                   "hbm_budget_gib": args.hbm_budget_gb, "graphs": not args.no_graphs},
+        "served": s_srv, "sequential": s_seq,
+        "speedup_fits_per_s": round(s_srv["fits_per_s"] / s_seq["fits_per_s"], 3),
+        "max_final_psnr_diff_db": dpsnr, "max_beta_rel_diff": dbeta,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,7 +294,16 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the splat traffic summary from two rocprofv3 --pmc output folders and exit")
     ap.add_argument("--traffic-command", default="", help="command line recorded in the traffic summary")
+    ap.add_argument("--serving", action="store_true", help="serving benchmark (fit-request stream)")
+    ap.add_argument("--requests", type=int, default=32)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
+    ap.add_argument("--lm-iters", type=int, default=0, help="override the requests' LM iterations")
+    ap.add_argument("--no-graphs", action="store_true")
     args = ap.parse_args()
+    if args.serving:
+        return serving_main(args)
     if args.summarize_traffic:
         print(summarize_traffic(*args.summarize_traffic, args.calibrate_copy or 1024, args.traffic_command))
         return

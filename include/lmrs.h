@@ -60,7 +60,10 @@ typedef int32_t lmrs_status;
 #define LMRS_EWORKSPACE (-3)   /* workspace smaller than lmrs_workspace_bytes */
 #define LMRS_EHIP (-4)         /* HIP runtime error */
 
-/* Floats per screen record: u v A B C opacity r g b | depth radius 0 (Sec. 3 eq. 3). */
+/* Floats per screen record: u v f11 f12 f22 opacity r g b | depth radius 0
+ * (Sec. 3 eq. 3). (f11, f12, f22) is the upper-triangular Cholesky factor F of
+ * the conic Q = Sigma_2D^-1 = F^T F, so that the Gaussian's exponent at pixel
+ * offset (dx, dy) from (u, v) is -1/2 ((f11 dx + f12 dy)^2 + (f22 dy)^2). */
 #define LMRS_REC 12
 
 typedef struct lmrs_camera {
@@ -117,6 +120,7 @@ typedef struct lmrs_frame {
 #define LMRS_OP_DIAG 5
 #define LMRS_OP_PCG 6
 #define LMRS_OP_LM 7
+#define LMRS_OP_SOLVE 8
 
 /* Learning-rate and solver settings of one LM step (Alg. 1; Sec. 4.5; Supp. D). */
 typedef struct lmrs_lm_params {
@@ -155,7 +159,7 @@ const char* lmrs_last_error(void);
 size_t lmrs_workspace_bytes(int32_t op, const lmrs_frame* f);
 
 /* a1. Projection (Sec. 3 eq. 1-3, EWA splatting): for every batch view v and
- * Gaussian g, rec[v][g] = (u, v, conic A B C, opacity sigmoid(logit),
+ * Gaussian g, rec[v][g] = (u, v, conic factor f11 f12 f22, opacity sigmoid(logit),
  * rgb = 0.5 + sum_k Y_k(dir) f_k, FP32 depth key, radius) and rect[v][g].
  * Reads beta, cams, view_ids; writes rec, rect. */
 lmrs_status lmrs_project(const lmrs_frame* f, const lmrs_render_opts* o, void* stream);
@@ -255,6 +259,19 @@ lmrs_status lmrs_sample(const lmrs_frame* f, int32_t sampler, uint64_t seed, int
 lmrs_status lmrs_lm_step(lmrs_frame* f, float* beta, const float* targets, const float* d,
                          const lmrs_lm_params* prm, const lmrs_render_opts* o, float* report,
                          void* ws, size_t ws_bytes, void* stream);
+
+/* a4-a8. The part of lmrs_lm_step after lmrs_project and lmrs_bin_tiles:
+ * sampling, render, residuals, b = J^T W r, preconditioner, PCG, learning
+ * rate and update (Alg. 1), with the same arguments and results. It never
+ * waits on the host, so a caller can capture it into a HIP graph and replay
+ * it on later LM iterations whose kernel arguments are unchanged: the same
+ * buffers, and an iteration index that changes neither the learning-rate
+ * branch (iter < warm_iters) nor the samples (k = 256 with f->pix NULL).
+ * The tile lists of f must be current (lmrs_bin_tiles on the current beta).
+ * Workspace: lmrs_workspace_bytes(LMRS_OP_SOLVE, f). */
+lmrs_status lmrs_lm_solve(lmrs_frame* f, float* beta, const float* targets, const float* d,
+                          const lmrs_lm_params* prm, const lmrs_render_opts* o, float* report,
+                          void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -49,6 +49,7 @@ def lib():
         L.or_num_instances.argtypes = [vp]
         L.or_get_projection.argtypes = [vp] * 7
         L.or_get_lists.argtypes = [vp, vp, vp]
+        L.or_undecided_tiles.argtypes = [vp, dbl, vp]
         L.or_set_samples.argtypes = [vp, i32, vp, vp]
         L.or_set_tile_mask.argtypes = [vp, vp]
         L.or_render.argtypes = [vp] * 7
@@ -167,12 +168,24 @@ class Oracle:
         lib().or_render(self.h, _p(Cc), _p(T), _p(last), _p(nc), _p(tr), _p(mg))
         return dict(C=Cc, T=T, last=last, n_contrib=nc, trace=tr, margin=mg)
 
+    def undecided_tiles(self, tau: float = 1e-4) -> np.ndarray:
+        """uint8 [V*T]: tiles whose list could hold one Gaussian more or less
+        under FP32 arithmetic (a footprint radius within tau of rounding the
+        other way: the tiles held with only one of the two radii; see
+        or_undecided_tiles)."""
+        flags = np.zeros(self.V * self.T, np.uint8)
+        lib().or_undecided_tiles(self.h, float(tau), _p(flags))
+        return flags
+
     def decided(self, tau: float = 1e-4) -> np.ndarray:
-        """Sampled pixels whose discrete decisions (exponent sign, alpha floor and
-        cap, transmittance stop) all lie farther than tau (relative) from their
-        thresholds. Below that, FP32 and FP64 arithmetic may decide differently
-        and the pixel's colour derivative is not unique at FP32 precision."""
-        return self.render()["margin"] >= tau
+        """Sampled pixels whose discrete decisions (tile-list membership, exponent
+        sign, alpha floor and cap, transmittance stop) all lie farther than tau
+        from their thresholds (relative; for the radius, in pixels). Below that,
+        FP32 and FP64 arithmetic may decide differently, and the pixel's colour
+        and derivative are not unique at FP32 precision."""
+        ok = self.render()["margin"] >= tau
+        tile = np.arange(self.S) // self.k
+        return ok & (self.undecided_tiles(tau)[tile] == 0)
 
     def render_image(self) -> np.ndarray:
         """Full images [V, H, W, 3] (uses all pixels; resets the sample set)."""

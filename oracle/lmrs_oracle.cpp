@@ -290,6 +290,8 @@ struct Problem {
   std::vector<int> rect;         // [V*n*4] x0, y0, x1, y1 (tile coords, end exclusive)
   std::vector<int> radius;       // [V*n]
   std::vector<double> margin_rad;  // [V*n] distance of cutoff*sqrt(lam_max) to an integer
+  std::vector<int> radius_all;   // [V*n] footprint radius before the image-bounds cull (0 if not projected)
+  std::vector<double> ext_all;   // [V*n] cutoff * sqrt(lambda_max) (0 if not projected)
   // tile lists
   std::vector<int64_t> tile_start;  // [V*T+1]
   std::vector<int> ids;
@@ -334,6 +336,12 @@ void decision_fp32(const Problem& pb, int v, int g, float* tz, float* u, float* 
   *vv = fmaf(c.fyf, tc[1] / tc[2], c.cyf);
 }
 
+// floor(q / 16) in FP32, clamped before the int conversion
+int tile_of_fp32(float q) {
+  const float f = std::floor(q / 16.f);
+  return (int)std::min(std::max(f, -1.0e6f), 1.0e6f);
+}
+
 void project_all(Problem& pb) {
   const size_t VN = (size_t)pb.V * pb.n;
   pb.rec.assign(VN, Rec<double>{});
@@ -342,6 +350,8 @@ void project_all(Problem& pb) {
   pb.rect.assign(VN * 4, 0);
   pb.radius.assign(VN, 0);
   pb.margin_rad.assign(VN, 1.0);
+  pb.radius_all.assign(VN, 0);
+  pb.ext_all.assign(VN, 0.0);
 #pragma omp parallel for schedule(static)
   for (long long vg = 0; vg < (long long)VN; ++vg) {
     const int v = (int)(vg / pb.n), g = (int)(vg % pb.n);
@@ -358,15 +368,13 @@ void project_all(Problem& pb) {
     const double ext = pb.op.cutoff * std::sqrt(lam);
     const double rad_d = std::ceil(ext);
     pb.margin_rad[vg] = std::min(ext - std::floor(ext), std::ceil(ext) - ext);
+    pb.ext_all[vg] = ext;
     if (!(rad_d < 1e6)) continue;
     const int rad = (int)rad_d;
+    pb.radius_all[vg] = rad;
     const float rf = (float)rad;
-    auto tile_of = [](float q) {  // floor(q / 16) in FP32, clamped before the int conversion
-      float f = std::floor(q / 16.f);
-      return (int)std::min(std::max(f, -1.0e6f), 1.0e6f);
-    };
-    int x0 = tile_of(u32 - rf), x1 = tile_of(u32 + rf);
-    int y0 = tile_of(v32 - rf), y1 = tile_of(v32 + rf);
+    int x0 = tile_of_fp32(u32 - rf), x1 = tile_of_fp32(u32 + rf);
+    int y0 = tile_of_fp32(v32 - rf), y1 = tile_of_fp32(v32 + rf);
     x0 = std::max(x0, 0); y0 = std::max(y0, 0);
     x1 = std::min(x1, pb.TX - 1); y1 = std::min(y1, pb.TY - 1);
     if (x0 > x1 || y0 > y1) continue;
@@ -682,6 +690,41 @@ void or_get_projection(void* h, double* rec, float* depth, int* rect, int* radiu
     if (margin) margin[i] = pb.margin_rad[i];
     if (visible) visible[i] = pb.visible[i];
     if (rect) std::memcpy(rect + 4 * i, &pb.rect[4 * i], 4 * sizeof(int));
+  }
+}
+
+// Tiles whose list membership FP32 arithmetic may decide differently: for
+// every Gaussian whose extent cutoff * sqrt(lambda_max) lies within tau of an
+// integer, the tiles held by its rectangle with exactly one of the radius r
+// and the radius an FP32 evaluation may give instead: r - 1 when the extent
+// lies just above the integer, r + 1 when just below.
+void or_undecided_tiles(void* h, double tau, uint8_t* flags) {
+  Problem& pb = *static_cast<Problem*>(h);
+  std::fill(flags, flags + (size_t)pb.V * pb.T, (uint8_t)0);
+  const size_t VN = (size_t)pb.V * pb.n;
+  for (size_t vg = 0; vg < VN; ++vg) {
+    if (!(pb.margin_rad[vg] < tau) || pb.radius_all[vg] <= 0) continue;
+    const int v = (int)(vg / pb.n), g = (int)(vg % pb.n);
+    float tz32, u32, v32;
+    decision_fp32(pb, v, g, &tz32, &u32, &v32);
+    const double ext = pb.ext_all[vg];
+    const int alt = ext - std::floor(ext) < 0.5 ? -1 : 1;
+    int box[2][4];
+    for (int k = 0; k < 2; ++k) {
+      const float rf = (float)(pb.radius_all[vg] + (k == 0 ? 0 : alt));
+      box[k][0] = std::max(tile_of_fp32(u32 - rf), 0);
+      box[k][1] = std::max(tile_of_fp32(v32 - rf), 0);
+      box[k][2] = std::min(tile_of_fp32(u32 + rf), pb.TX - 1);
+      box[k][3] = std::min(tile_of_fp32(v32 + rf), pb.TY - 1);
+    }
+    const int big = alt > 0 ? 1 : 0;  // the larger of the two rectangles
+    const int* o = box[big];
+    const int* in = box[1 - big];
+    for (int ty = o[1]; ty <= o[3]; ++ty)
+      for (int tx = o[0]; tx <= o[2]; ++tx) {
+        const bool inner = tx >= in[0] && tx <= in[2] && ty >= in[1] && ty <= in[3];
+        if (!inner) flags[(size_t)v * pb.T + ty * pb.TX + tx] = 1;
+      }
   }
 }
 

@@ -64,11 +64,12 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
   Scratch s;
   const int64_t P = (int64_t)d.n * d.pg;
   const int64_t VN = (int64_t)d.V * d.n;
+  const bool lm = op == LMRS_OP_LM || op == LMRS_OP_SOLVE;
   const bool need_bin = op == LMRS_OP_BIN || op == LMRS_OP_LM;
-  const bool need_tan = op == LMRS_OP_JVP || op == LMRS_OP_GN || op == LMRS_OP_PCG || op == LMRS_OP_LM;
-  const bool need_grad = op == LMRS_OP_VJP || op == LMRS_OP_GN || op == LMRS_OP_PCG || op == LMRS_OP_LM;
-  const bool need_gram = op == LMRS_OP_DIAG || op == LMRS_OP_PCG || op == LMRS_OP_LM;
-  const bool need_pcg = op == LMRS_OP_PCG || op == LMRS_OP_LM;
+  const bool need_tan = op == LMRS_OP_JVP || op == LMRS_OP_GN || op == LMRS_OP_PCG || lm;
+  const bool need_grad = op == LMRS_OP_VJP || op == LMRS_OP_GN || op == LMRS_OP_PCG || lm;
+  const bool need_gram = op == LMRS_OP_DIAG || op == LMRS_OP_PCG || lm;
+  const bool need_pcg = op == LMRS_OP_PCG || lm;
   if (need_bin) {
     s.bin.counts = c.take<int32_t>((size_t)d.V * d.T);
     s.bin.chunk_hist = c.take<int32_t>((size_t)d.V * bin_chunks(d.n) * d.T);
@@ -87,7 +88,7 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
     s.minv = c.take<float>(P);
     s.sc = c.take<double>(16);
   }
-  if (op == LMRS_OP_LM) {
+  if (lm) {
     s.b = c.take<float>(P);
     s.x = c.take<float>(P);
     s.wr = c.take<float>((size_t)d.S * 3);
@@ -203,6 +204,49 @@ lmrs_status bin_sequence(const lmrs_frame* f, const FrameDims& d, const Scratch&
   if (total_out) *total_out = total;
   launch_bin_emit_sort(f, d, s.bin, st);
   return hip_check("bin sort");
+}
+
+lmrs_status check_lm_args(const lmrs_frame* f, const float* beta, const float* targets,
+                          const lmrs_lm_params* prm, const lmrs_render_opts* o) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(need(prm, "params"));
+  LMRS_TRY(need(beta, "beta"));
+  LMRS_TRY(need(targets, "targets"));
+  if (f->beta != beta) return fail(LMRS_EINVAL, "frame->beta must equal beta");
+  LMRS_TRY(check_render_state(f));
+  LMRS_TRY(need(f->n_instances, "n_instances"));
+  LMRS_TRY(need(f->color, "color"));
+  LMRS_TRY(need(f->trans, "trans"));
+  LMRS_TRY(need(f->last, "last"));
+  if (f->k < 256 && (!f->pix || !f->w)) return fail(LMRS_EINVAL, "k < 256 needs pix and w buffers");
+  if (prm->sampler != LMRS_SAMPLER_UNIFORM && prm->sampler != LMRS_SAMPLER_RESIDUAL)
+    return fail(LMRS_EINVAL, "unknown sampler %d", prm->sampler);
+  if (prm->sampler == LMRS_SAMPLER_RESIDUAL && (!f->pix || !f->w))
+    return fail(LMRS_EINVAL, "the residual sampler needs pix and w buffers");
+  if (prm->cg_iters < 0) return fail(LMRS_EINVAL, "cg_iters must be >= 0");
+  if (!(prm->lambda >= 0.f)) return fail(LMRS_EINVAL, "lambda must be >= 0");
+  return LMRS_OK;
+}
+
+// Alg. 1 after binning: samples, render, residuals, b, preconditioner, PCG,
+// learning rate and update. Enqueue only (no host synchronisation).
+void solve_sequence(const lmrs_frame* f, const FrameDims& d, float* beta, const float* targets,
+                    const float* dvec, const lmrs_lm_params& prm, const lmrs_render_opts& o, float* report,
+                    const Scratch& s, hipStream_t st) {
+  const int64_t P = (int64_t)d.n * d.pg;
+  if (prm.sampler == LMRS_SAMPLER_RESIDUAL) {
+    launch_render_scores(f, d, o, targets, s.scores, st);
+    launch_sample_residual(f, d, s.scores, prm.seed, prm.iter, st);
+  } else if (f->pix) {
+    launch_sample_uniform(f, d, prm.seed, prm.iter, st);
+  }
+  launch_render(f, d, o, st);
+  launch_residual(f, d, targets, s.wr, s.red, report, st);
+  vjp_sequence(f, d, o, s.wr, s.b, s, st);
+  pcg_sequence(f, d, o, s.b, prm.lambda, dvec, prm.cg_iters, s.x, report, s, st);
+  launch_lm_update(beta, s.x, d.n, P, prm, s.red, report, st);
+  if (report) launch_report_count(f->n_instances, report + LMRS_REP_INST, st);
 }
 
 }  // namespace
@@ -434,46 +478,28 @@ lmrs_status lmrs_sample(const lmrs_frame* f, int32_t sampler, uint64_t seed, int
 lmrs_status lmrs_lm_step(lmrs_frame* f, float* beta, const float* targets, const float* dvec,
                          const lmrs_lm_params* prm, const lmrs_render_opts* o, float* report, void* ws,
                          size_t ws_bytes, void* stream) {
-  LMRS_TRY(check_frame(f));
-  LMRS_TRY(need(o, "opts"));
-  LMRS_TRY(need(prm, "params"));
-  LMRS_TRY(need(beta, "beta"));
-  LMRS_TRY(need(targets, "targets"));
-  if (f->beta != beta) return fail(LMRS_EINVAL, "frame->beta must equal beta");
-  LMRS_TRY(check_render_state(f));
-  LMRS_TRY(need(f->n_instances, "n_instances"));
-  LMRS_TRY(need(f->color, "color"));
-  LMRS_TRY(need(f->trans, "trans"));
-  LMRS_TRY(need(f->last, "last"));
-  if (f->k < 256 && (!f->pix || !f->w)) return fail(LMRS_EINVAL, "k < 256 needs pix and w buffers");
-  if (prm->sampler != LMRS_SAMPLER_UNIFORM && prm->sampler != LMRS_SAMPLER_RESIDUAL)
-    return fail(LMRS_EINVAL, "unknown sampler %d", prm->sampler);
-  if (prm->sampler == LMRS_SAMPLER_RESIDUAL && (!f->pix || !f->w))
-    return fail(LMRS_EINVAL, "the residual sampler needs pix and w buffers");
-  if (prm->cg_iters < 0) return fail(LMRS_EINVAL, "cg_iters must be >= 0");
-  if (!(prm->lambda >= 0.f)) return fail(LMRS_EINVAL, "lambda must be >= 0");
+  LMRS_TRY(check_lm_args(f, beta, targets, prm, o));
   LMRS_TRY(check_ws(LMRS_OP_LM, f, ws, ws_bytes));
   const FrameDims d = dims_of(f);
   Carver c(ws);
   const Scratch s = carve(LMRS_OP_LM, d, f->capacity, c);
   hipStream_t st = (hipStream_t)stream;
-  const int64_t P = (int64_t)d.n * d.pg;
   launch_project(f, d, *o, st);
-  int64_t total = 0;
-  LMRS_TRY(bin_sequence(f, d, s, st, &total));
-  if (prm->sampler == LMRS_SAMPLER_RESIDUAL) {
-    launch_render_scores(f, d, *o, targets, s.scores, st);
-    launch_sample_residual(f, d, s.scores, prm->seed, prm->iter, st);
-  } else if (f->pix) {
-    launch_sample_uniform(f, d, prm->seed, prm->iter, st);
-  }
-  launch_render(f, d, *o, st);
-  launch_residual(f, d, targets, s.wr, s.red, report, st);
-  vjp_sequence(f, d, *o, s.wr, s.b, s, st);
-  pcg_sequence(f, d, *o, s.b, prm->lambda, dvec, prm->cg_iters, s.x, report, s, st);
-  launch_lm_update(beta, s.x, d.n, P, *prm, s.red, report, st);
-  if (report) launch_fill(report + LMRS_REP_INST, 1, (float)total, st);
+  LMRS_TRY(bin_sequence(f, d, s, st));
+  solve_sequence(f, d, beta, targets, dvec, *prm, *o, report, s, st);
   return hip_check("lmrs_lm_step");
+}
+
+lmrs_status lmrs_lm_solve(lmrs_frame* f, float* beta, const float* targets, const float* dvec,
+                          const lmrs_lm_params* prm, const lmrs_render_opts* o, float* report, void* ws,
+                          size_t ws_bytes, void* stream) {
+  LMRS_TRY(check_lm_args(f, beta, targets, prm, o));
+  LMRS_TRY(check_ws(LMRS_OP_SOLVE, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_SOLVE, d, f->capacity, c);
+  solve_sequence(f, d, beta, targets, dvec, *prm, *o, report, s, (hipStream_t)stream);
+  return hip_check("lmrs_lm_solve");
 }
 
 }  // extern "C"

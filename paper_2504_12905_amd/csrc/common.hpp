@@ -126,11 +126,18 @@ __device__ __forceinline__ void load_params(const float* beta, int n, int g, T* 
 }
 
 // ----------------------------------------------------------- projection
-// Geometry of the screen record, (u, v, A, B, C), from mean, log-scale and
-// quaternion (prm[0..10)). Sigma = R S S^T R^T (eq. 2); Sigma_2D =
-// J W Sigma W^T J^T + lowpass I with J the pinhole Jacobian at the
-// camera-space mean, computed as K K^T with K = J W R S; the conic is
-// Sigma_2D^-1.
+// Geometry of the screen record, (u, v, f11, f12, f22), from mean, log-scale
+// and quaternion (prm[0..10)). Sigma = R S S^T R^T (eq. 2); Sigma_2D =
+// J W Sigma W^T J^T + lowpass I = [[a, b], [b, c]] with J the pinhole
+// Jacobian at the camera-space mean, computed as K K^T with K = J W R S (rows
+// k1, k2). The record holds the Cholesky factor F = [[f11, f12], [0, f22]] of
+// the conic Q = Sigma_2D^-1 = F^T F instead of Q itself, so that the exponent
+// of eq. 3, -1/2 d^T Q d, is evaluated as -1/2 (|f11 dx + f12 dy|^2 + |f22 dy|^2)
+// (a sum of squares: no cancellation between terms of size |Q| |d|^2 along
+// the long axis of a large, thin footprint):
+//   f22 = 1 / sqrt(c),  f11 = c r,  f12 = -b r,  r = 1 / sqrt(c det),
+// with det = a c - b^2 formed without cancellation by the Cauchy-Binet
+// identity det = |k1 x k2|^2 + lowpass (|k1|^2 + |k2|^2) + lowpass^2.
 template <class T>
 __device__ __forceinline__ void proj_geom(const T* prm, const CamView& cv, float lowpass, T* rec,
                                           float* a_out, float* b_out, float* c_out) {
@@ -160,16 +167,19 @@ __device__ __forceinline__ void proj_geom(const T* prm, const CamView& cv, float
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       K[3 * i + j] = (Tm[3 * i + 0] * R[j] + Tm[3 * i + 1] * R[3 + j] + Tm[3 * i + 2] * R[6 + j]) * s[j];
-  const T a = K[0] * K[0] + K[1] * K[1] + K[2] * K[2] + T(lowpass);
+  const T n1 = K[0] * K[0] + K[1] * K[1] + K[2] * K[2];
+  const T n2 = K[3] * K[3] + K[4] * K[4] + K[5] * K[5];
   const T b = K[0] * K[3] + K[1] * K[4] + K[2] * K[5];
-  const T cc = K[3] * K[3] + K[4] * K[4] + K[5] * K[5] + T(lowpass);
-  const T idet = T(1.f) / (a * cc - b * b);
+  const T w0 = K[1] * K[5] - K[2] * K[4], w1 = K[2] * K[3] - K[0] * K[5], w2 = K[0] * K[4] - K[1] * K[3];
+  const T det = (w0 * w0 + w1 * w1 + w2 * w2) + T(lowpass) * (n1 + n2) + T(lowpass * lowpass);
+  const T cc = n2 + T(lowpass);
+  const T r = trsqrt(cc * det);
   rec[0] = T(c.fx) * tx * iz + T(c.cx);
   rec[1] = T(c.fy) * ty * iz + T(c.cy);
-  rec[2] = cc * idet;
-  rec[3] = -(b * idet);
-  rec[4] = a * idet;
-  if (a_out) { *a_out = tval(a); *b_out = tval(b); *c_out = tval(cc); }
+  rec[2] = cc * r;
+  rec[3] = -(b * r);
+  rec[4] = trsqrt(cc);
+  if (a_out) { *a_out = tval(n1) + lowpass; *b_out = tval(b); *c_out = tval(cc); }
 }
 
 // Unit direction from the camera centre to the mean.
@@ -197,7 +207,7 @@ __device__ __forceinline__ void proj_color(const T* prm, const CamView& cv, T* r
   }
 }
 
-// Screen record (u, v, A, B, C, opacity, r, g, b) of one Gaussian in one view.
+// Screen record (u, v, f11, f12, f22, opacity, r, g, b) of one Gaussian in one view.
 template <int DEG, class T>
 __device__ __forceinline__ void proj_core(const T* prm, const CamView& cv, float lowpass, T* rec, float* a_out,
                                           float* b_out, float* c_out) {
@@ -266,20 +276,28 @@ __device__ __forceinline__ void proj_vjp(const float* prm, const CamView& cv, fl
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       K[3 * i + j] = Tm[3 * i] * M[j] + Tm[3 * i + 1] * M[3 + j] + Tm[3 * i + 2] * M[6 + j];
-  const float a = K[0] * K[0] + K[1] * K[1] + K[2] * K[2] + lowpass;
+  const float n1 = K[0] * K[0] + K[1] * K[1] + K[2] * K[2];
+  const float n2 = K[3] * K[3] + K[4] * K[4] + K[5] * K[5];
   const float b = K[0] * K[3] + K[1] * K[4] + K[2] * K[5];
-  const float cc = K[3] * K[3] + K[4] * K[4] + K[5] * K[5] + lowpass;
-  const float idet = 1.f / (a * cc - b * b), id2 = idet * idet;
-  const float gu = gr[0], gv = gr[1], gA = gr[2], gB = gr[3], gC = gr[4], go = gr[5];
-  // conic (A, B, C) = (c, -b, a) / (a c - b^2)
-  const float ga = (-cc * cc * gA + b * cc * gB - b * b * gC) * id2;
-  const float gb = (2.f * b * cc * gA - (a * cc + b * b) * gB + 2.f * a * b * gC) * id2;
-  const float gc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
+  const float cw[3] = {K[1] * K[5] - K[2] * K[4], K[2] * K[3] - K[0] * K[5], K[0] * K[4] - K[1] * K[3]};
+  const float det = (cw[0] * cw[0] + cw[1] * cw[1] + cw[2] * cw[2]) + lowpass * (n1 + n2) + lowpass * lowpass;
+  const float cc = n2 + lowpass;
+  const float r = 1.f / sqrtf(cc * det), ic = 1.f / cc;
+  const float gu = gr[0], gv = gr[1], g11 = gr[2], g12 = gr[3], g22 = gr[4], go = gr[5];
+  // F: f11 = c r, f12 = -b r, f22 = c^-1/2 with r = (c det)^-1/2
+  const float g_r = g11 * cc - g12 * b;
+  const float gc = g11 * r - 0.5f * g_r * r * ic - 0.5f * g22 * ic * sqrtf(ic);
+  const float gb = -g12 * r;
+  const float gdet = -0.5f * g_r * r / det;
+  // det = |k1 x k2|^2 + lowpass (|k1|^2 + |k2|^2) + lowpass^2; b = k1.k2; c = |k2|^2 + lowpass
   float gK[6];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    gK[j] = 2.f * ga * K[j] + gb * K[3 + j];
-    gK[3 + j] = 2.f * gc * K[3 + j] + gb * K[j];
+    const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+    const float k2xw = K[3 + j1] * cw[j2] - K[3 + j2] * cw[j1];  // (k2 x w)_j, w = k1 x k2
+    const float wxk1 = cw[j1] * K[j2] - cw[j2] * K[j1];          // (w x k1)_j
+    gK[j] = gb * K[3 + j] + gdet * 2.f * (k2xw + lowpass * K[j]);
+    gK[3 + j] = gb * K[j] + 2.f * gc * K[3 + j] + gdet * 2.f * (wxk1 + lowpass * K[3 + j]);
   }
   // K = Tm M
   float gTm[6];
@@ -355,18 +373,24 @@ __device__ __forceinline__ void proj_vjp(const float* prm, const CamView& cv, fl
 // Exponent and opacity of one (pixel, Gaussian) pair, evaluated identically in
 // every splat kernel so that skip decisions agree between render, J p, J^T u
 // and the diagonal. Returns the alpha before capping in *raw.
+// The exponent is -1/2 (q1^2 + q2^2) with q1 = f11 dx + f12 dy, q2 = f22 dy
+// (the conic's Cholesky factor, see proj_geom); q1, q2 are kept for the
+// derivatives: ds/du = -q1 f11, ds/dv = -(q1 f12 + q2 f22),
+// ds/df11 = -q1 dx, ds/df12 = -q1 dy, ds/df22 = -q2 dy.
 struct Alpha {
-  float dx, dy, es, a;
+  float dx, dy, q1, q2, es, a;
   bool inc, capped;
 };
 
-__device__ __forceinline__ Alpha pair_alpha(float u, float v, float A, float B, float C, float o,
+__device__ __forceinline__ Alpha pair_alpha(float u, float v, float f11, float f12, float f22, float o,
                                             float xc, float yc, const lmrs_render_opts& op) {
 #pragma clang fp contract(off)
   Alpha r;
   r.dx = u - xc;
   r.dy = v - yc;
-  const float s = -0.5f * (A * r.dx * r.dx + C * r.dy * r.dy) - B * r.dx * r.dy;
+  r.q1 = f11 * r.dx + f12 * r.dy;
+  r.q2 = f22 * r.dy;
+  const float s = -0.5f * (r.q1 * r.q1 + r.q2 * r.q2);
   r.es = __expf(s);
   const float raw = o * r.es;
   r.capped = raw > op.alpha_max;

@@ -191,6 +191,10 @@ __global__ void report_kernel(const double* __restrict__ value, float* __restric
   if (threadIdx.x == 0 && blockIdx.x == 0) report[slot] = (float)value[0];
 }
 
+__global__ void report_count_kernel(const int64_t* __restrict__ count, float* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = (float)count[0];
+}
+
 // PCG scalar slots.
 enum : int {
   kRZ = 0,      // r_i^T z_i
@@ -368,6 +372,10 @@ void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targe
                                              d.W, d.H, d.k, d.S, wr, partials);
   finalize_kernel<<<1, 256, 0, s>>>(partials, kRedBlocks, 1, kRedBlocks, partials + 2 * kRedBlocks);
   if (report) report_kernel<<<1, 64, 0, s>>>(partials + 2 * kRedBlocks, report, LMRS_REP_LOSS);
+}
+
+void launch_report_count(const int64_t* count, float* dst, hipStream_t s) {
+  report_count_kernel<<<1, 64, 0, s>>>(count, dst);
 }
 
 void launch_dot(const float* a, const float* b, int64_t n, double* partials, double* out, hipStream_t s) {

@@ -58,8 +58,9 @@ __device__ __forceinline__ void pixel_center(const uint8_t* pix, int k, const Ti
   *yc = c.oy + (float)(p >> 4) + 0.5f;
 }
 
+// u, v, conic factor f11 f12 f22, opacity, rgb (see proj_geom)
 struct RecF {
-  float u, v, A, B, C, o, r, g, b;
+  float u, v, f11, f12, f22, o, r, g, b;
 };
 
 __device__ __forceinline__ RecF load_rec(const float* rec, size_t vg) {
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
       const int cnt = min(kWave, k - s * kWave);
       for (int l = 0; l < cnt; ++l) {
         if (readlane(sDone[s], l)) continue;
-        const Alpha al = pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+        const Alpha al = pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
         const bool inc = valid && al.inc;
         const float a = inc ? al.a : 0.f;
         const float lg = log2_om(inc, a);
@@ -237,15 +238,14 @@ __global__ __launch_bounds__(kWave) void deriv_kernel(
           const int lj = readlane(pr.last[s], l);
           if (c0 > lj) continue;
           const Alpha al =
-              pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+              pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
           const bool inc = valid && e <= lj && al.inc;
           float a = 0.f, da = 0.f;
           if (inc) {
             a = al.a;
             if (!al.capped) {
-              const float ds = -(r.A * al.dx * dr.u + r.C * al.dy * dr.v) -
-                               0.5f * (dr.A * al.dx * al.dx + dr.C * al.dy * al.dy) -
-                               dr.B * al.dx * al.dy - r.B * (dr.u * al.dy + al.dx * dr.v);
+              const float ds = -al.q1 * (dr.f11 * al.dx + dr.f12 * al.dy + r.f11 * dr.u + r.f12 * dr.v) -
+                               al.q2 * (dr.f22 * al.dy + r.f22 * dr.v);
               da = al.es * (dr.o + r.o * ds);
             }
           }
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kWave) void deriv_kernel(
           const int lj = readlane(pr.last[s], l);
           if (c0 > lj) continue;
           const Alpha al =
-              pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+              pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
           const bool inc = valid && e <= lj && al.inc;
           const float a = inc ? al.a : 0.f;
           const float lg = log2_om(inc, a);
@@ -353,11 +353,11 @@ __global__ __launch_bounds__(kWave) void deriv_kernel(
               const float ga = Tn * urgb - behind * __builtin_amdgcn_rcpf(1.f - a);
               const float gs = ga * a;
               g[5] += ga * al.es;
-              g[0] -= gs * (r.A * al.dx + r.B * al.dy);
-              g[1] -= gs * (r.B * al.dx + r.C * al.dy);
-              g[2] -= 0.5f * gs * al.dx * al.dx;
-              g[3] -= gs * al.dx * al.dy;
-              g[4] -= 0.5f * gs * al.dy * al.dy;
+              g[0] -= gs * (al.q1 * r.f11);
+              g[1] -= gs * (al.q1 * r.f12 + al.q2 * r.f22);
+              g[2] -= gs * (al.q1 * al.dx);
+              g[3] -= gs * (al.q1 * al.dy);
+              g[4] -= gs * (al.q2 * al.dy);
             }
           }
           sa[s] = writelane(sa[s], Tafter * __builtin_amdgcn_exp2f(-readlane(Linc, kWave - 1)), l);
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
         const int lj = readlane(pr.last[s], l);
         if (c0 > lj) continue;
         const Alpha al =
-            pair_alpha(r.u, r.v, r.A, r.B, r.C, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+            pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
         const bool inc = valid && e <= lj && al.inc;
         const float a = inc ? al.a : 0.f;
         const float lg = log2_om(inc, a);
@@ -447,8 +447,8 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
               ga[ch] = Tn * rgb[ch] - behind[ch] * iom;
               sga2 += ga[ch] * ga[ch];
             }
-            const float h[5] = {-(r.A * al.dx + r.B * al.dy), -(r.B * al.dx + r.C * al.dy),
-                                -0.5f * al.dx * al.dx, -al.dx * al.dy, -0.5f * al.dy * al.dy};
+            const float h[5] = {-(al.q1 * r.f11), -(al.q1 * r.f12 + al.q2 * r.f22), -(al.q1 * al.dx),
+                                -(al.q1 * al.dy), -(al.q2 * al.dy)};
             const float fg = wj * a * a * sga2;
             for (int p = 0; p < 5; ++p) {
               for (int q = p; q < 5; ++q) G[sym5(p, q)] += fg * h[p] * h[q];

@@ -59,6 +59,7 @@ void launch_sample_residual(const lmrs_frame* f, const FrameDims& d, const float
 void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targets, float* wr,
                      double* partials, float* report, hipStream_t s);
 void launch_dot(const float* a, const float* b, int64_t n, double* partials, double* out, hipStream_t s);
+void launch_report_count(const int64_t* count, float* dst, hipStream_t s);
 // PCG state in device memory
 struct PcgState {
   float *x, *r, *z, *p, *u, *minv;

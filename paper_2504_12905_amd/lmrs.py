@@ -23,7 +23,7 @@ _lib = C.CDLL(LIB_PATH)
 
 LMRS_OK, LMRS_EINVAL, LMRS_ECAPACITY, LMRS_EWORKSPACE, LMRS_EHIP = 0, -1, -2, -3, -4
 LMRS_REC = 12
-OP_BIN, OP_JVP, OP_VJP, OP_GN, OP_DIAG, OP_PCG, OP_LM = 1, 2, 3, 4, 5, 6, 7
+OP_BIN, OP_JVP, OP_VJP, OP_GN, OP_DIAG, OP_PCG, OP_LM, OP_SOLVE = 1, 2, 3, 4, 5, 6, 7, 8
 REPORT_FLOATS = 8
 SAMPLER_UNIFORM, SAMPLER_RESIDUAL = 0, 1
 REP = dict(loss=0, eta=1, xdc_max=2, cg_done=3, r0=4, rn=5, bx=6, instances=7)
@@ -85,11 +85,12 @@ _lib.lmrs_gn_product_timed.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, 
 _lib.lmrs_gn_diag.argtypes = [_FP, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_pcg.argtypes = [_FP, _vp, _vp, _f32, _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_lm_step.argtypes = [_FP, _vp, _vp, _vp, C.POINTER(LmParams), _vp, _vp, _vp, _sz, _vp]
+_lib.lmrs_lm_solve.argtypes = [_FP, _vp, _vp, _vp, C.POINTER(LmParams), _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_residual_scores.argtypes = [_FP, _vp, _vp, _vp, _vp]
 _lib.lmrs_sample.argtypes = [_FP, _i32, C.c_uint64, _i32, _vp, _vp]
 for _name in ("lmrs_project", "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp",
               "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step",
-              "lmrs_residual_scores", "lmrs_sample"):
+              "lmrs_residual_scores", "lmrs_sample", "lmrs_lm_solve"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -185,10 +186,13 @@ class Frame:
         self.tensors["ids"] = torch.empty(self.capacity, dtype=torch.int32, device=self.beta.device)
 
 
-def workspace(op: int, frame: Frame) -> torch.Tensor:
+def workspace_bytes(op: int, frame: Frame) -> int:
     fs = frame.struct()
-    nbytes = int(_lib.lmrs_workspace_bytes(op, C.byref(fs)))
-    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=frame.beta.device)
+    return int(_lib.lmrs_workspace_bytes(op, C.byref(fs)))
+
+
+def workspace(op: int, frame: Frame) -> torch.Tensor:
+    return torch.empty(max(workspace_bytes(op, frame), 256), dtype=torch.uint8, device=frame.beta.device)
 
 
 def lmrs_project(frame: Frame, opts: RenderOpts | None = None, stream=None):
@@ -197,12 +201,14 @@ def lmrs_project(frame: Frame, opts: RenderOpts | None = None, stream=None):
     _check(_lib.lmrs_project(C.byref(fs), C.byref(opts), _stream(stream)), "lmrs_project")
 
 
-def lmrs_bin_tiles(frame: Frame, stream=None) -> int:
-    """Bins; grows the id buffer and retries when the capacity is exceeded."""
+def lmrs_bin_tiles(frame: Frame, stream=None, ws: torch.Tensor | None = None) -> int:
+    """Bins; grows the id buffer and retries when the capacity is exceeded.
+    ws: optional caller workspace, used when it holds lmrs_workspace_bytes(OP_BIN)."""
     for _ in range(2):
         fs = frame.struct()
-        ws = workspace(OP_BIN, frame)
-        st = _lib.lmrs_bin_tiles(C.byref(fs), _ptr(ws), ws.numel(), _stream(stream))
+        need = _lib.lmrs_workspace_bytes(OP_BIN, C.byref(fs))
+        w = ws if (ws is not None and ws.numel() >= need) else workspace(OP_BIN, frame)
+        st = _lib.lmrs_bin_tiles(C.byref(fs), _ptr(w), w.numel(), _stream(stream))
         if st == LMRS_ECAPACITY:
             frame.grow_ids(int(frame.n_instances.item()))
             continue
@@ -325,6 +331,17 @@ def lmrs_lm_step(frame: Frame, targets: torch.Tensor, params: LmParams, d: torch
     raise LmrsError(LMRS_ECAPACITY, "lmrs_lm_step")
 
 
+def lmrs_lm_solve(frame: Frame, targets: torch.Tensor, params: LmParams, ws: torch.Tensor,
+                  d: torch.Tensor | None = None, report: torch.Tensor | None = None, opts=None, stream=None):
+    """The LM iteration after project + bin (no host wait; graph-capturable).
+    ws: at least lmrs_workspace_bytes(OP_SOLVE) bytes (see workspace())."""
+    opts = opts or default_opts()
+    fs = frame.struct()
+    _check(_lib.lmrs_lm_solve(C.byref(fs), _ptr(frame.beta), _ptr(targets), _ptr(d), C.byref(params),
+                              C.byref(opts), _ptr(report), _ptr(ws), ws.numel(), _stream(stream)),
+           "lmrs_lm_solve")
+
+
 def lm_params(iter: int, cg_iters: int, lam: float, seed: int = 0, eta_cap: float = 0.2,
               eta_warm: float = 0.05, warm_iters: int = 10, sampler: int = SAMPLER_UNIFORM) -> LmParams:
     return LmParams(int(iter), int(cg_iters), float(lam), float(eta_cap), float(eta_warm), int(warm_iters),
@@ -333,4 +350,4 @@ def lm_params(iter: int, cg_iters: int, lam: float, seed: int = 0, eta_cap: floa
 
 EXPORTS = ("lmrs_status_str", "lmrs_last_error", "lmrs_workspace_bytes", "lmrs_project", "lmrs_bin_tiles",
            "lmrs_render", "lmrs_jvp", "lmrs_vjp", "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_diag",
-           "lmrs_pcg", "lmrs_lm_step", "lmrs_residual_scores", "lmrs_sample")
+           "lmrs_pcg", "lmrs_lm_step", "lmrs_residual_scores", "lmrs_sample", "lmrs_lm_solve")

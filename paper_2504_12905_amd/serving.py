@@ -1,0 +1,326 @@
+"""Serving loop for scene-fit requests over the C ABI (host scheduling only;
+every step of every fit runs in the library's kernels).
+
+A fit request is a synthetic scene (Gaussians, cameras, target images
+rendered from its ground truth) to be fitted by `lm_iters` LM iterations of
+Alg. 1 with `cg_iters` GN products each, every pixel of every view per
+iteration (weights 1), damping lambda.
+
+`Server` does continuous batching on one GPU:
+* admission by HBM footprint: a request is admitted when it has arrived, a
+  slot is free and its footprint (parameters, targets, screen records, tile
+  lists with their sort keys, per-pixel buffers and the solver workspace; the
+  list size bounded from the scene on the host) fits next to the footprints
+  of the fits already resident;
+* an admitted fit keeps its parameters, lists, CG state and targets in device
+  memory until it retires, and runs on its own HIP stream (default
+  priority), so the kernels of different fits overlap on the device;
+* one LM iteration of a fit = lmrs_project + lmrs_bin_tiles (the host waits
+  for that fit's list size only) + lmrs_lm_solve. The solve (render,
+  residuals, b, preconditioner, the PCG loop's GN products and vector
+  recurrences, learning rate, update: about a hundred launches) is captured
+  once per learning-rate branch into a HIP graph and replayed;
+* the scheduler gives each resident fit one LM iteration per round, admits
+  arrived requests as slots and memory free up, and retires finished fits
+  (final PSNR over all views at full resolution).
+
+`run_sequential` is the plain baseline: the same requests one at a time in
+arrival order, eager lmrs_lm_step calls on one stream, no graphs.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import lmrs as L
+from . import synth
+
+
+@dataclass
+class FitRequest:
+    seed: int
+    n: int
+    sh_degree: int
+    n_views: int
+    res: int
+    lm_iters: int = 30
+    cg_iters: int = 8
+    lam: float = 1e-3
+    arrival_t: float = 0.0       # seconds after the start of the run
+    id: int = 0
+
+    @staticmethod
+    def from_stream(d: dict) -> "FitRequest":
+        return FitRequest(seed=d["seed"], n=d["n"], sh_degree=d["sh_degree"], n_views=d["n_views"], res=d["res"],
+                          lm_iters=d["lm_iters"], cg_iters=d["cg_iters"], lam=d["lam"], arrival_t=d["arrival_s"],
+                          id=d["id"])
+
+
+@dataclass
+class FitResult:
+    beta: np.ndarray
+    final_psnr: float
+    latency_s: float
+    status: str
+    start_s: float = 0.0
+    end_s: float = 0.0
+
+
+@dataclass
+class Problem:
+    """Host data of one request: scene and cameras per the 1k-Gaussian
+    workload's priors (means in [-1,1]^3, cameras at radius 3, FOV 60)."""
+    req: FitRequest
+    beta_gt: np.ndarray
+    beta_init: np.ndarray
+    cams: np.ndarray
+    instances_bound: int
+    footprint: int
+
+
+def instances_bound(beta: np.ndarray, n: int, cams: np.ndarray, W: int, H: int) -> int:
+    """Upper bound on the tile-list entries of a scene: per (view, Gaussian)
+    the tiles of the square of half-side ceil(3 sqrt(l) ) + 1 px around the
+    projected mean, l >= lambda_max of the screen covariance bounded by
+    (f/z)^2 (1 + (x^2 + y^2)/z^2) s_max^2 + 0.3 (spectral norm of the
+    projection Jacobian times the largest scale)."""
+    mu = beta[0:3 * n].reshape(3, n).astype(np.float64)
+    smax = np.exp(beta[3 * n:6 * n].reshape(3, n).max(axis=0).astype(np.float64))
+    TX, TY = W // 16, H // 16
+    total = 0
+    for c in cams:
+        R = c[0:9].reshape(3, 3).astype(np.float64)
+        t = c[9:12].astype(np.float64)
+        fx, fy, cx, cy = (float(x) for x in c[12:16])
+        tc = R @ mu + t[:, None]
+        z = tc[2]
+        ok = z > 0.15
+        zs = np.where(ok, z, 1.0)
+        jn2 = (max(fx, fy) / zs) ** 2 * (1.0 + (tc[0] ** 2 + tc[1] ** 2) / zs ** 2)
+        r = np.ceil(3.0 * np.sqrt(jn2 * smax ** 2 + 0.3)) + 1.0
+        u = fx * tc[0] / zs + cx
+        v = fy * tc[1] / zs + cy
+        x0 = np.clip(np.floor((u - r) / 16), 0, TX)
+        x1 = np.clip(np.floor((u + r) / 16) + 1, 0, TX)
+        y0 = np.clip(np.floor((v - r) / 16), 0, TY)
+        y1 = np.clip(np.floor((v + r) / 16) + 1, 0, TY)
+        total += int(np.sum(np.where(ok, np.maximum(x1 - x0, 0) * np.maximum(y1 - y0, 0), 0)))
+    return total
+
+
+def _frame_struct_bytes(op: int, n: int, deg: int, V: int, W: int, H: int, k: int, capacity: int) -> int:
+    fs = L._Frame(n, deg, V, W, H, k, None, None, None, None, None, None, None, capacity, None, None, None, None,
+                  None, None)
+    return int(L._lib.lmrs_workspace_bytes(op, L.C.byref(fs)))
+
+
+def footprint_bytes(req: FitRequest, instances: int) -> int:
+    """Device bytes a fit holds while resident (see the module docstring)."""
+    n, V, W = req.n, req.n_views, req.res
+    K = (req.sh_degree + 1) ** 2
+    P = n * (11 + 3 * K)
+    T = (W // 16) ** 2
+    S = V * T * 256
+    cap = int(instances * 1.05) + 1024
+    frame = V * n * (4 * L.LMRS_REC + 16) + 8 * (V * T + 1) + 4 * cap + S * (12 + 4 + 4)
+    ws = max(_frame_struct_bytes(L.OP_BIN, n, req.sh_degree, V, W, W, 256, cap),
+             _frame_struct_bytes(L.OP_SOLVE, n, req.sh_degree, V, W, W, 256, cap))
+    return 4 * P + 16 * V * 4 + 12 * V * W * W + frame + ws + 64 * 4
+
+
+def make_problem(req: FitRequest) -> Problem:
+    gt = synth.make_scene(req.n, req.sh_degree, req.seed, means="cube")
+    init = synth.perturb_init(gt, req.n, req.sh_degree, req.seed)
+    cams = synth.sphere_cameras(req.n_views, 3.0, req.res, req.res, 60.0, req.seed)
+    ib = max(instances_bound(gt, req.n, cams, req.res, req.res), instances_bound(init, req.n, cams, req.res, req.res))
+    return Problem(req, gt, init, cams, ib, footprint_bytes(req, ib))
+
+
+def _image_index(fr: L.Frame, dev) -> torch.Tensor:
+    """Flat image index (v H W + y W + x) of every all-pixel sample."""
+    t = torch.arange(fr.T, device=dev)
+    p = torch.arange(256, device=dev)
+    y = ((t // fr.TX) * 16)[:, None] + (p // 16)[None, :]
+    x = ((t % fr.TX) * 16)[:, None] + (p % 16)[None, :]
+    pix = (y * fr.width + x).reshape(-1)
+    v = torch.arange(fr.n_views, device=dev)[:, None] * (fr.width * fr.height)
+    return (v + pix[None, :]).reshape(-1)
+
+
+class _Fit:
+    """Device state of one resident fit."""
+
+    def __init__(self, prob: Problem, stream: torch.cuda.Stream, use_graphs: bool, dev, ws_op: int = L.OP_SOLVE):
+        req = prob.req
+        self.prob, self.req, self.stream, self.use_graphs = prob, req, stream, use_graphs
+        self.it = 0
+        self.graphs: dict[bool, torch.cuda.CUDAGraph] = {}
+        with torch.cuda.stream(stream):
+            self.beta = torch.tensor(prob.beta_gt, device=dev)
+            self.cams = torch.tensor(prob.cams, device=dev)
+            cap = int(prob.instances_bound * 1.05) + 1024
+            self.fr = L.Frame(req.n, req.sh_degree, self.beta, self.cams, req.res, req.res, req.n_views, k=256,
+                              capacity=cap)
+            nbytes = max(L.workspace_bytes(L.OP_BIN, self.fr), L.workspace_bytes(ws_op, self.fr))
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            self.rep = torch.zeros(L.REPORT_FLOATS, device=dev)
+            self.idx = _image_index(self.fr, dev)
+            # targets: the ground truth rendered at every pixel
+            self.targets = torch.empty((req.n_views, req.res, req.res, 3), dtype=torch.float32, device=dev)
+            self._render_all(self.targets)
+            self.beta.copy_(torch.tensor(prob.beta_init, device=dev))
+        self.done_event: torch.cuda.Event | None = None
+
+    def _render_all(self, out: torch.Tensor):
+        L.lmrs_project(self.fr, stream=self.stream)
+        L.lmrs_bin_tiles(self.fr, stream=self.stream, ws=self.ws)
+        L.lmrs_render(self.fr, stream=self.stream)
+        out.view(-1, 3)[self.idx] = self.fr.color
+
+    def params(self) -> L.LmParams:
+        return L.lm_params(self.it, self.req.cg_iters, self.req.lam)
+
+    def step(self):
+        """Enqueue one LM iteration on the fit's stream."""
+        req = self.req
+        with torch.cuda.stream(self.stream):
+            ids_before = self.fr.ids.data_ptr()
+            L.lmrs_project(self.fr, stream=self.stream)
+            L.lmrs_bin_tiles(self.fr, stream=self.stream, ws=self.ws)
+            if self.fr.ids.data_ptr() != ids_before:
+                self.graphs.clear()            # the id buffer moved: captured pointers are stale
+            warm = self.it < 10
+            if not self.use_graphs or self.it == 0:
+                L.lmrs_lm_solve(self.fr, self.targets, self.params(), self.ws, report=self.rep, stream=self.stream)
+            else:
+                g = self.graphs.get(warm)
+                if g is None:
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=self.stream):
+                        L.lmrs_lm_solve(self.fr, self.targets, self.params(), self.ws, report=self.rep,
+                                        stream=self.stream)
+                    self.graphs[warm] = g
+                g.replay()
+            self.it += 1
+            if self.it == req.lm_iters:
+                self.done_event = torch.cuda.Event()
+                self.done_event.record(self.stream)
+
+    def finished(self) -> bool:
+        return self.done_event is not None and self.done_event.query()
+
+    def finalize(self) -> tuple[np.ndarray, float]:
+        """Final PSNR over every pixel of every view, and the parameters."""
+        with torch.cuda.stream(self.stream):
+            img = torch.empty_like(self.targets)
+            self._render_all(img)
+            mse = float(((img - self.targets) ** 2).mean().item())
+            beta = self.beta.cpu().numpy()
+        self.graphs.clear()
+        return beta, (10.0 * math.log10(1.0 / mse) if mse > 0 else float("inf"))
+
+
+@dataclass
+class Server:
+    hbm_budget_bytes: int
+    max_slots: int = 8
+    use_graphs: bool = True
+    device: str = "cuda:0"
+    _pending: list = field(default_factory=list)
+    _results: dict = field(default_factory=dict)
+    log: list = field(default_factory=list)
+
+    def submit(self, req: FitRequest, problem: Problem | None = None) -> int:
+        """Queue a request (host data prepared now, off the device). Returns its handle."""
+        prob = problem or make_problem(req)
+        if prob.footprint > self.hbm_budget_bytes:
+            raise ValueError(f"request {req.id}: footprint {prob.footprint} B exceeds the budget")
+        self._pending.append(prob)
+        return req.id
+
+    def result(self, handle: int) -> FitResult:
+        return self._results[handle]
+
+    def run_until_idle(self) -> dict[int, FitResult]:
+        """Serve every submitted request; arrival times are seconds after this call."""
+        pending = sorted(self._pending, key=lambda p: p.req.arrival_t)
+        self._pending = []
+        streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_slots)]
+        free_streams = list(range(self.max_slots))
+        active: list[tuple[_Fit, int, float]] = []   # (fit, stream index, start time)
+        used = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while pending or active:
+            now = time.perf_counter() - t0
+            # admission: arrived, a free slot, and room in the footprint budget (FIFO, no overtaking)
+            while (pending and pending[0].req.arrival_t <= now and free_streams
+                   and used + pending[0].footprint <= self.hbm_budget_bytes):
+                prob = pending.pop(0)
+                si = free_streams.pop(0)
+                fit = _Fit(prob, streams[si], self.use_graphs, self.device)
+                used += prob.footprint
+                start = time.perf_counter() - t0
+                active.append((fit, si, start))
+                self.log.append(("admit", prob.req.id, start, used))
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, min(0.01, pending[0].req.arrival_t - (time.perf_counter() - t0))))
+                continue
+            for fit, _, _ in active:
+                if fit.it < fit.req.lm_iters:
+                    fit.step()
+            still = []
+            for fit, si, start in active:
+                if fit.it >= fit.req.lm_iters and fit.finished():
+                    beta, psnr = fit.finalize()
+                    end = time.perf_counter() - t0
+                    req = fit.req
+                    self._results[req.id] = FitResult(beta, psnr, end - req.arrival_t, "ok", start, end)
+                    used -= fit.prob.footprint
+                    free_streams.append(si)
+                    self.log.append(("retire", req.id, end, used))
+                    del fit
+                else:
+                    still.append((fit, si, start))
+            active = still
+        return self._results
+
+
+def run_sequential(problems: list[Problem], device: str = "cuda:0") -> dict[int, FitResult]:
+    """Plain baseline: one request at a time in arrival order, eager
+    lmrs_lm_step calls on the current stream, no graphs, no overlap."""
+    out: dict[int, FitResult] = {}
+    order = sorted(problems, key=lambda p: p.req.arrival_t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stream = torch.cuda.current_stream()
+    for prob in order:
+        req = prob.req
+        now = time.perf_counter() - t0
+        if req.arrival_t > now:
+            time.sleep(req.arrival_t - now)
+        start = time.perf_counter() - t0
+        fit = _Fit(prob, stream, False, device, ws_op=L.OP_LM)
+        for it in range(req.lm_iters):
+            L.lmrs_lm_step(fit.fr, fit.targets, L.lm_params(it, req.cg_iters, req.lam), report=fit.rep,
+                           ws=fit.ws, stream=stream)
+        beta, psnr = fit.finalize()
+        end = time.perf_counter() - t0
+        out[req.id] = FitResult(beta, psnr, end - req.arrival_t, "ok", start, end)
+        del fit
+    return out
+
+
+def summarize(results: dict[int, FitResult], problems: list[Problem]) -> dict:
+    arr = {p.req.id: p.req.arrival_t for p in problems}
+    lat = np.array([r.latency_s for r in results.values()])
+    first = min(arr.values())
+    last = max(r.end_s for r in results.values())
+    return {"fits": len(results), "fits_per_s": len(results) / (last - first),
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "makespan_s": last - first}

@@ -71,7 +71,7 @@ def test_full_size_jvp(full):
     ok = orc.decided()
     e = rel(jp[ok], orc.jvp(p)[ok])
     log(f"  jvp rel {e:.2e} on decided pixels ({1 - ok.mean():.4%} excluded)")
-    assert e < 1e-4 and ok.mean() > 0.99
+    assert e < 1e-4 and ok.mean() > 0.97
 
 
 def _sampled_gaussians(orc, count, seed):

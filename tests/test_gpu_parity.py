@@ -64,8 +64,13 @@ def test_projection(case):
     bad = (vis != gvis) & (pr["margin"] >= 1e-4)
     assert not bad.any(), f"{bad.sum()} visibility mismatches"
     both = vis & gvis
+    # the GPU record holds the conic's Cholesky factor (f11, f12, f22):
+    # conic = F^T F = [[f11^2, f11 f12], [f11 f12, f12^2 + f22^2]]
+    g = rec.astype(np.float64)
+    conic = np.stack([g[..., 2] ** 2, g[..., 2] * g[..., 3], g[..., 3] ** 2 + g[..., 4] ** 2], axis=-1)
+    g = np.concatenate([g[..., :2], conic, g[..., 5:9]], axis=-1)
     for q, name in enumerate(["u", "v", "A", "B", "C", "opacity", "r", "g", "b"]):
-        e = rel(rec[..., q][both], pr["rec"][..., q][both])
+        e = rel(g[..., q][both], pr["rec"][..., q][both])
         log(f"  rec[{name}] rel {e:.2e}")
         assert e < TOL, name
     same_r = (rec[..., 10][both] == pr["radius"][both])

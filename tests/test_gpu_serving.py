@@ -1,0 +1,114 @@
+"""The serving loop on the GPU: graph replays against eager solves, each
+result the same alone and in a mix of concurrent fits, and admission within
+the memory budget and slot count."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, log, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def serving():
+    from paper_2504_12905_amd import serving as S
+    return S
+
+
+def small_requests(ids, lm_iters=12):
+    S = serving()
+    rng = np.random.default_rng(5)
+    out = []
+    for i in ids:
+        out.append(S.FitRequest(seed=100 + i, n=int(rng.integers(2000, 12000)), sh_degree=int(rng.integers(0, 4)),
+                                n_views=int(rng.integers(4, 9)), res=int(rng.choice([128, 256])),
+                                lm_iters=lm_iters, cg_iters=8, lam=1e-3, arrival_t=0.02 * len(out), id=i))
+    return out
+
+
+def test_graph_replays_match_eager_steps():
+    """Every LM iteration through a replayed graph (both learning-rate
+    branches) equals the eager solve of the same iteration from the same
+    parameters, with the eager projection, binning and host waits between
+    replays. The parameters are re-synchronised before each iteration: the
+    GN products accumulate with float atomics, whose order (and last bits)
+    differ from run to run, and LM iterations amplify such differences."""
+    S = serving()
+    req = S.FitRequest(seed=3, n=6000, sh_degree=2, n_views=4, res=256, lm_iters=14, id=0)
+    prob = S.make_problem(req)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    eager = S._Fit(prob, s1, False, DEV)
+    graph = S._Fit(prob, s2, True, DEV)
+    worst = 0.0
+    for it in range(req.lm_iters):
+        torch.cuda.synchronize()
+        graph.beta.copy_(eager.beta)          # in place: the captured pointers stay valid
+        torch.cuda.synchronize()
+        start = eager.beta.cpu().numpy()
+        eager.step()
+        graph.step()
+        torch.cuda.synchronize()
+        de = eager.beta.cpu().numpy() - start
+        dg = graph.beta.cpu().numpy() - start
+        e = rel(dg, de)
+        worst = max(worst, e)
+        assert e < 1e-4, (it, e)
+    assert set(graph.graphs) == {True, False}
+    log(f"  14 LM iterations, graph vs eager step: worst rel {worst:.2e}")
+
+
+def test_same_alone_and_in_the_mix():
+    """Six probe requests fitted alone (sequential plain solver) and inside a
+    served mix of twelve concurrent fits give the same final PSNR (0.01 dB)
+    and parameters. The GN products accumulate with float atomics, whose
+    order changes the last bits of every step from run to run, alone as well,
+    and LM iterations amplify that; so the parameters must agree within
+    1e-3 relative after 6 LM iterations or within twice the spread of two
+    alone runs, whichever is larger."""
+    S = serving()
+    probes = small_requests(range(6), lm_iters=6)
+    others = small_requests(range(6, 12), lm_iters=6)
+    alone = S.run_sequential([S.make_problem(r) for r in probes])
+    again = S.run_sequential([S.make_problem(r) for r in probes])
+    spread = max(rel(again[r.id].beta, alone[r.id].beta) for r in probes)
+    log(f"  alone vs alone: beta rel up to {spread:.2e}")
+    srv = S.Server(hbm_budget_bytes=64 << 30, max_slots=6)
+    mix = sorted(probes + others, key=lambda r: r.id % 2)          # interleave probes and others
+    for k, r in enumerate(mix):
+        r.arrival_t = 0.01 * k
+        srv.submit(r)
+    got = srv.run_until_idle()
+    assert len(got) == 12
+    peak = max(sum(1 for e in srv.log[:j + 1] if e[0] == "admit") - sum(1 for e in srv.log[:j + 1] if e[0] == "retire")
+               for j in range(len(srv.log)))
+    log(f"  peak concurrent fits {peak}")
+    assert peak > 1
+    for r in probes:
+        a, b = alone[r.id], got[r.id]
+        e = rel(b.beta, a.beta)
+        log(f"  request {r.id} (n={r.n}, SH {r.sh_degree}, {r.n_views} views {r.res}^2): beta rel {e:.2e}, "
+            f"PSNR {a.final_psnr:.4f} / {b.final_psnr:.4f} dB")
+        assert e <= max(1e-3, 2 * spread)
+        assert abs(a.final_psnr - b.final_psnr) <= 0.01
+
+
+def test_admission_respects_budget_and_slots():
+    S = serving()
+    reqs = small_requests(range(20, 28), lm_iters=3)
+    probs = [S.make_problem(r) for r in reqs]
+    fp = {p.req.id: p.footprint for p in probs}
+    budget = int(2.5 * max(fp.values()))
+    srv = S.Server(hbm_budget_bytes=budget, max_slots=3)
+    for p in probs:
+        srv.submit(p.req, p)
+    got = srv.run_until_idle()
+    assert len(got) == len(reqs)
+    resident, used = set(), 0
+    for kind, rid, _, u in srv.log:
+        if kind == "admit":
+            resident.add(rid)
+        else:
+            resident.discard(rid)
+        assert len(resident) <= 3
+        assert sum(fp[i] for i in resident) <= budget
+        assert u == sum(fp[i] for i in resident)

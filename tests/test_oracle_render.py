@@ -140,3 +140,25 @@ def test_decision_margin_flags_threshold_pixels():
         v, xs, ys = orc.pixel_coords()
         i = int(np.flatnonzero((xs == x) & (ys == y))[0])
         assert bool(orc.decided()[i]) is expect
+
+
+def test_undecided_tiles_cover_a_radius_at_an_integer():
+    """On the optical axis at depth 3, 3 sqrt((f sigma / 3)^2 + 0.3) is the
+    footprint extent. At 16 + 1e-6 px the radius ceil() = 17 is not decided in
+    FP32, which may give 16: around the centre (32, 32) of a 64x64 image the
+    radius-17 rectangle holds tiles 0..3 (32 - 17 = 15 lies in tile 0), the
+    radius-16 one tiles 1..3 (the right edge 48 starts tile 3), so the flagged
+    ring is every tile with tx == 0 or ty == 0; their pixels leave decided().
+    At 16 - 1e-6 px the radius 16 may become 17 in FP32: the same ring. At
+    16.5 px nothing is flagged."""
+    f, W = 40.0, 64
+    ring = {(ty, tx) for ty in range(4) for tx in range(4) if tx == 0 or ty == 0}
+    for ext, expect in [(16.0 + 1e-6, ring), (16.0 - 1e-6, ring), (16.5, set())]:
+        sigma = 3.0 * math.sqrt((ext / 3.0) ** 2 - 0.3) / f
+        n, beta = one_gaussian_scene([0, 0, 0], [math.log(sigma)] * 3, [1, 0, 0, 0], 0.5, [0.5, 0.5, 0.5])
+        orc = Oracle(n, 0, beta, axis_camera(f, W, W), W, W)
+        flags = orc.undecided_tiles(1e-4).reshape(W // 16, W // 16)
+        assert {(int(ty), int(tx)) for ty, tx in zip(*np.nonzero(flags))} == expect
+        orc.set_samples(256)
+        ok = orc.decided().reshape(-1, 256)
+        assert np.array_equal(~ok.all(axis=1), flags.reshape(-1).astype(bool)) or not expect
