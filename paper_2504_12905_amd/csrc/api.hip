@@ -28,7 +28,7 @@ lmrs_status hip_check(const char* what) {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-constexpr int kRedDoubles = 2 * kRedBlocks + 64;
+constexpr int kRedDoubles = 4 * kRedBlocks + 64;
 
 // Bump allocator over the caller's workspace; the same sequence of take()
 // calls sizes the workspace (base == nullptr) and carves it.
@@ -86,7 +86,7 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
     s.p = c.take<float>(P);
     s.u = c.take<float>(P);
     s.minv = c.take<float>(P);
-    s.sc = c.take<double>(16);
+    s.sc = c.take<double>(32);
   }
   if (lm) {
     s.b = c.take<float>(P);
@@ -170,23 +170,33 @@ void vjp_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opt
 void diag_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* out,
                    const Scratch& s, hipStream_t st) {
   launch_fill(s.gram, (int64_t)d.V * d.n * kGram, 0.f, st);
-  launch_gram(f, d, o, s.gram, st);
+  launch_gram(f, d, o, s.gram, nullptr, nullptr, st);
   launch_chain_diag(f, d, o, s.gram, out, st);
 }
 
+// b = J^T u and diag(J^T W J) from one reverse walk (the Gram pass with J^T u).
+void vjp_diag_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* u,
+                       float* b, float* diag, const Scratch& s, hipStream_t st) {
+  launch_fill(s.gram, (int64_t)d.V * d.n * kGram, 0.f, st);
+  launch_fill(s.grad2d, (int64_t)d.V * d.n * 9, 0.f, st);
+  launch_gram(f, d, o, s.gram, u, s.grad2d, st);
+  launch_chain_vjp(f, d, o, s.grad2d, nullptr, 0.f, nullptr, b, st);
+  launch_chain_diag(f, d, o, s.gram, diag, st);
+}
+
+// PCG of Alg. 1; diag(J^T W J) is formed here unless have_diag (then s.diag holds it).
 void pcg_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* b,
                   float lambda, const float* dvec, int iters, float* x, float* report, const Scratch& s,
-                  hipStream_t st) {
+                  hipStream_t st, bool have_diag = false) {
   const int64_t P = (int64_t)d.n * d.pg;
-  diag_sequence(f, d, o, s.diag, s, st);
+  if (!have_diag) diag_sequence(f, d, o, s.diag, s, st);
   PcgState ps{x, s.r, s.z, s.p, s.u, s.minv, s.sc, s.red};
   launch_pcg_init(b, s.diag, lambda, dvec, P, ps, st);
   for (int it = 0; it < iters; ++it) {
     gn_sequence(f, d, o, s.p, lambda, dvec, s.u, s, st);
-    launch_pcg_update(P, ps, st);
-    launch_pcg_direction(P, ps, st);
+    launch_pcg_iteration(it, P, ps, st);
   }
-  if (report) launch_pcg_report(b, P, ps, report, st);
+  if (report) launch_pcg_report(b, iters, P, ps, report, st);
 }
 
 // count, wait for the total, then emit and sort.
@@ -243,8 +253,8 @@ void solve_sequence(const lmrs_frame* f, const FrameDims& d, float* beta, const 
   }
   launch_render(f, d, o, st);
   launch_residual(f, d, targets, s.wr, s.red, report, st);
-  vjp_sequence(f, d, o, s.wr, s.b, s, st);
-  pcg_sequence(f, d, o, s.b, prm.lambda, dvec, prm.cg_iters, s.x, report, s, st);
+  vjp_diag_sequence(f, d, o, s.wr, s.b, s.diag, s, st);
+  pcg_sequence(f, d, o, s.b, prm.lambda, dvec, prm.cg_iters, s.x, report, s, st, true);
   launch_lm_update(beta, s.x, d.n, P, prm, s.red, report, st);
   if (report) launch_report_count(f->n_instances, report + LMRS_REP_INST, st);
 }

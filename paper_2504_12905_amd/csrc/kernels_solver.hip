@@ -238,27 +238,43 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(const float* __restrict__
   }
 }
 
-__global__ void pcg_init_scalars_kernel(double* __restrict__ sc) {
+// Sum of partials[0, count) in a fixed order (the same in every block).
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ partials, int count,
+                                                  double* s_red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) acc += partials[i];
+  return block_sum(acc, s_red);
+}
+
+// Scalars after pcg_init_kernel: r0^T z0 and r0^T r0 from its partials.
+__global__ __launch_bounds__(256) void pcg_init_scalars_kernel(const double* __restrict__ partials,
+                                                               double* __restrict__ sc) {
+  __shared__ double s_red[256];
+  const double rz = reduce_partials(partials, kRedBlocks, s_red);
+  const double rr = reduce_partials(partials + kRedBlocks, kRedBlocks, s_red);
   if (threadIdx.x == 0) {
-    sc[kRZ0] = sc[kRZ];
-    sc[kRR0] = sc[kRR];
-    sc[kStop] = 0.0;
-    sc[kDone] = 0.0;
-    sc[kAlpha] = 0.0;
-    sc[kBeta] = 0.0;
+    for (int i = 0; i < kScalars; ++i) sc[i] = 0.0;
+    sc[kRZ] = sc[kRZ0] = rz;
+    sc[kRR] = sc[kRR0] = rr;
   }
 }
 
+// Iteration i reads the scalar bank cur and pcg_dir_kernel writes the bank
+// of iteration i + 1, so no kernel reads a slot that it writes.
 // alpha = r^T z / p^T u (0 once stopped); x += alpha p; r -= alpha u; z = M^-1 r.
-__global__ __launch_bounds__(256) void pcg_update_kernel(int64_t P, const double* __restrict__ sc,
+// p^T u comes from dot_partial_kernel's partials (reduced in every block).
+__global__ __launch_bounds__(256) void pcg_update_kernel(int64_t P, double* __restrict__ cur,
+                                                         const double* __restrict__ pu_partials,
                                                          float* __restrict__ x, float* __restrict__ r,
                                                          float* __restrict__ z, const float* __restrict__ p,
                                                          const float* __restrict__ u,
                                                          const float* __restrict__ minv,
                                                          double* __restrict__ partials) {
   __shared__ double s_red[256];
-  const double rz = sc[kRZ], pu = sc[kPU];
-  const bool go = sc[kStop] == 0.0 && pu > 0.0 && rz > 1e-30 * sc[kRZ0];
+  const double pu = reduce_partials(pu_partials, kRedBlocks, s_red);
+  const double rz = cur[kRZ];
+  const bool go = cur[kStop] == 0.0 && pu > 0.0 && rz > 1e-30 * cur[kRZ0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) cur[kPU] = pu;
   const float alpha = go ? (float)(rz / pu) : 0.f;
   double rz1 = 0.0, rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
@@ -281,27 +297,34 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t P, const double
   }
 }
 
-// After pcg_update's reductions (kRZNew, kRR): beta and the stop flag.
-__global__ void pcg_scalar_kernel(double* __restrict__ sc) {
-  if (threadIdx.x != 0) return;
-  const double rz = sc[kRZ], pu = sc[kPU];
-  const bool go = sc[kStop] == 0.0 && pu > 0.0 && rz > 1e-30 * sc[kRZ0];
-  if (go) {
-    sc[kBeta] = sc[kRZNew] / rz;
-    sc[kRZ] = sc[kRZNew];
-    sc[kDone] += 1.0;
-  } else {
-    sc[kStop] = 1.0;
-    sc[kBeta] = 0.0;
-  }
-}
-
-__global__ __launch_bounds__(256) void pcg_dir_kernel(int64_t P, const double* __restrict__ sc,
+// r_{i+1}^T z_{i+1} and r^T r from pcg_update_kernel's partials; beta, the
+// stop flag and the next scalar bank; p = z + beta p.
+__global__ __launch_bounds__(256) void pcg_dir_kernel(int64_t P, const double* __restrict__ cur,
+                                                      double* __restrict__ next,
+                                                      const double* __restrict__ partials,
                                                       const float* __restrict__ z, float* __restrict__ p) {
-  if (sc[kStop] != 0.0) return;
-  const float beta = (float)sc[kBeta];
+  __shared__ double s_red[256];
+  const double rz_new = reduce_partials(partials, kRedBlocks, s_red);
+  const double rr = reduce_partials(partials + kRedBlocks, kRedBlocks, s_red);
+  const double rz = cur[kRZ], pu = cur[kPU];
+  const bool go = cur[kStop] == 0.0 && pu > 0.0 && rz > 1e-30 * cur[kRZ0];
+  const double beta = go ? rz_new / rz : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int i = 0; i < kScalars; ++i) next[i] = cur[i];
+    next[kRZNew] = rz_new;
+    next[kRR] = rr;
+    next[kBeta] = beta;
+    if (go) {
+      next[kRZ] = rz_new;
+      next[kDone] = cur[kDone] + 1.0;
+    } else {
+      next[kStop] = 1.0;
+    }
+  }
+  if (!go) return;
+  const float b = (float)beta;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256)
-    p[i] = z[i] + beta * p[i];
+    p[i] = z[i] + b * p[i];
 }
 
 __global__ void pcg_report_kernel(const double* __restrict__ sc, const double* __restrict__ bx,
@@ -329,11 +352,20 @@ __global__ __launch_bounds__(256) void absmax_partial_kernel(const float* __rest
   if (threadIdx.x == 0) partials[blockIdx.x] = s_red[0];
 }
 
-__global__ void lr_kernel(const double* __restrict__ partials, int count, lmrs_lm_params prm,
-                          double* __restrict__ eta_out, float* __restrict__ report) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(256) void lr_kernel(const double* __restrict__ partials, int count,
+                                                  lmrs_lm_params prm, double* __restrict__ eta_out,
+                                                  float* __restrict__ report) {
+  __shared__ double s_red[256];
   double m = 0.0;
-  for (int i = 0; i < count; ++i) m = fmax(m, partials[i]);
+  for (int i = threadIdx.x; i < count; i += 256) m = fmax(m, partials[i]);
+  s_red[threadIdx.x] = m;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) s_red[threadIdx.x] = fmax(s_red[threadIdx.x], s_red[threadIdx.x + d]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  m = s_red[0];
   double eta;
   if (prm.iter < prm.warm_iters) eta = prm.eta_warm;
   else eta = m > 0.0 ? fmin((double)prm.eta_cap, 1.0 / m) : (double)prm.eta_cap;
@@ -387,36 +419,27 @@ void launch_pcg_init(const float* b, const float* diag, float lambda, const floa
                      PcgState st, hipStream_t s) {
   pcg_init_kernel<<<kRedBlocks, 256, 0, s>>>(b, diag, lambda, dvec, P, st.x, st.r, st.z, st.p, st.minv,
                                              st.partials);
-  // rz -> sc[kRZ], rr -> sc[kRR]
-  finalize_kernel<<<1, 256, 0, s>>>(st.partials, kRedBlocks, 1, kRedBlocks, st.sc + kRZ);
-  finalize_kernel<<<1, 256, 0, s>>>(st.partials + kRedBlocks, kRedBlocks, 1, kRedBlocks, st.sc + kRR);
-  pcg_init_scalars_kernel<<<1, 64, 0, s>>>(st.sc);
+  pcg_init_scalars_kernel<<<1, 256, 0, s>>>(st.partials, st.bank(0));
 }
 
-void launch_pcg_update(int64_t P, PcgState st, hipStream_t s) {
-  // p^T u first
+void launch_pcg_iteration(int it, int64_t P, PcgState st, hipStream_t s) {
+  double* cur = st.bank(it);
   dot_partial_kernel<<<kRedBlocks, 256, 0, s>>>(st.p, st.u, P, st.partials);
-  finalize_kernel<<<1, 256, 0, s>>>(st.partials, kRedBlocks, 1, kRedBlocks, st.sc + kPU);
-  pcg_update_kernel<<<kRedBlocks, 256, 0, s>>>(P, st.sc, st.x, st.r, st.z, st.p, st.u, st.minv,
-                                               st.partials);
-  finalize_kernel<<<1, 256, 0, s>>>(st.partials, kRedBlocks, 1, kRedBlocks, st.sc + kRZNew);
-  finalize_kernel<<<1, 256, 0, s>>>(st.partials + kRedBlocks, kRedBlocks, 1, kRedBlocks, st.sc + kRR);
-  pcg_scalar_kernel<<<1, 64, 0, s>>>(st.sc);
+  pcg_update_kernel<<<kRedBlocks, 256, 0, s>>>(P, cur, st.partials, st.x, st.r, st.z, st.p, st.u, st.minv,
+                                               st.partials + 2 * kRedBlocks);
+  pcg_dir_kernel<<<kRedBlocks, 256, 0, s>>>(P, cur, st.bank(it + 1), st.partials + 2 * kRedBlocks, st.z, st.p);
 }
 
-void launch_pcg_direction(int64_t P, PcgState st, hipStream_t s) {
-  pcg_dir_kernel<<<kRedBlocks, 256, 0, s>>>(P, st.sc, st.z, st.p);
-}
-
-void launch_pcg_report(const float* b, int64_t P, PcgState st, float* report, hipStream_t s) {
-  launch_dot(b, st.x, P, st.partials, st.sc + 10, s);
-  pcg_report_kernel<<<1, 64, 0, s>>>(st.sc, st.sc + 10, report);
+void launch_pcg_report(const float* b, int iters, int64_t P, PcgState st, float* report, hipStream_t s) {
+  double* fin = st.bank(iters);
+  launch_dot(b, st.x, P, st.partials, fin + 10, s);
+  pcg_report_kernel<<<1, 64, 0, s>>>(fin, fin + 10, report);
 }
 
 void launch_lm_update(float* beta, const float* x, int n, int64_t P, const lmrs_lm_params& prm,
                       double* partials, float* report, hipStream_t s) {
   absmax_partial_kernel<<<kRedBlocks, 256, 0, s>>>(x + (int64_t)11 * n, (int64_t)3 * n, partials);
-  lr_kernel<<<1, 64, 0, s>>>(partials, kRedBlocks, prm, partials + kRedBlocks, report);
+  lr_kernel<<<1, 256, 0, s>>>(partials, kRedBlocks, prm, partials + kRedBlocks, report);
   lm_apply_kernel<<<kRedBlocks, 256, 0, s>>>(beta, x, P, partials + kRedBlocks);
 }
 

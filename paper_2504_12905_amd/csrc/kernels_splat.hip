@@ -378,7 +378,11 @@ __global__ __launch_bounds__(kWave) void deriv_kernel(
 // Per (view, Gaussian) weighted Gram of d C_c / d rec over the tile's pixels
 // and channels: geometry block, geometry x colour, colour, opacity. Walks
 // like the reverse pass of deriv_kernel, with one "colour behind" per channel.
-template <int NS>
+// With VJP it also forms J^T u (u = u_in, e.g. the weighted residuals) on the
+// same walk: the colour behind an entry seen through u is sum_c u_c times the
+// per-channel colour behind, so the right-hand side b = J^T W r of an LM step
+// costs no walk of its own.
+template <int NS, bool VJP>
 __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ rec,
                                                      const int64_t* __restrict__ tile_start,
                                                      const int32_t* __restrict__ ids,
@@ -387,12 +391,13 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
                                                      const float* __restrict__ trans,
                                                      const int32_t* __restrict__ lastv, int n, int T,
                                                      int TX, int k, lmrs_render_opts o,
-                                                     float* __restrict__ gram) {
+                                                     float* __restrict__ gram, const float* __restrict__ u_in,
+                                                     float* __restrict__ grad2d) {
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX);
   PixelRegs<NS> pr;
   const int lmax = load_pixel_regs<NS>(pix, wts, lastv, k, c, pr);
-  float sT[NS], sS0[NS], sS1[NS], sS2[NS];
+  float sT[NS], sS0[NS], sS1[NS], sS2[NS], sU0[NS], sU1[NS], sU2[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int j = s * kWave + lane;
@@ -400,6 +405,13 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
     sS0[s] = sT[s] * o.bg[0];
     sS1[s] = sT[s] * o.bg[1];
     sS2[s] = sT[s] * o.bg[2];
+    sU0[s] = sU1[s] = sU2[s] = 0.f;
+    if (VJP && j < k) {
+      const int64_t i = c.tile_lin * k + j;
+      sU0[s] = u_in[3 * i];
+      sU1[s] = u_in[3 * i + 1];
+      sU2[s] = u_in[3 * i + 2];
+    }
   }
   if (lmax < 0) return;
   for (int c0 = (lmax / kWave) * kWave; c0 >= 0; c0 -= kWave) {
@@ -411,8 +423,9 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
       id = ids[c.start + e];
       r = load_rec(rec, (size_t)c.v * n + id);
     }
-    float G[kGram];
+    float G[kGram], g[9];
     for (int q = 0; q < kGram; ++q) G[q] = 0.f;
+    for (int q = 0; q < 9; ++q) g[q] = 0.f;
     const float rgb[3] = {r.r, r.g, r.b};
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -440,6 +453,15 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
           const float wj = readlane(pr.w[s], l);
           const float aT = a * Tn;
           G[30] += wj * aT * aT;
+          float u[3] = {0.f, 0.f, 0.f};
+          if (VJP) {
+            u[0] = readlane(sU0[s], l);
+            u[1] = readlane(sU1[s], l);
+            u[2] = readlane(sU2[s], l);
+            g[6] += u[0] * aT;
+            g[7] += u[1] * aT;
+            g[8] += u[2] * aT;
+          }
           if (!al.capped) {
             float ga[3], sga2 = 0.f;
             const float iom = __builtin_amdgcn_rcpf(1.f - a);
@@ -455,6 +477,11 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
               for (int ch = 0; ch < 3; ++ch) G[15 + 3 * p + ch] += wj * ga[ch] * a * h[p] * aT;
             }
             G[31] += wj * sga2 * al.es * al.es;
+            if (VJP) {
+              const float gu = u[0] * ga[0] + u[1] * ga[1] + u[2] * ga[2];
+              g[5] += gu * al.es;
+              for (int p = 0; p < 5; ++p) g[p] += gu * a * h[p];
+            }
           }
         }
         sT[s] = writelane(sT[s], Tafter * __builtin_amdgcn_exp2f(-readlane(Linc, kWave - 1)), l);
@@ -468,6 +495,12 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
       for (int q = 0; q < kGram; ++q) any |= G[q] != 0.f;
       if (any)
         for (int q = 0; q < kGram; ++q) atomicAdd(&gram[((size_t)c.v * kGram + q) * n + id], G[q]);
+      if (VJP) {
+        bool anyg = false;
+        for (int q = 0; q < 9; ++q) anyg |= g[q] != 0.f;
+        if (anyg)
+          for (int q = 0; q < 9; ++q) atomicAdd(&grad2d[((size_t)c.v * 9 + q) * n + id], g[q]);
+      }
     }
   }
 }
@@ -514,14 +547,18 @@ void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_
 }
 
 void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* gram,
-                 hipStream_t s) {
+                 const float* u, float* grad2d, hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
-  if (d.k <= kWave)
-    gram_kernel<1><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last,
-                                               d.n, d.T, d.TX, d.k, o, gram);
-  else
-    gram_kernel<4><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last,
-                                               d.n, d.T, d.TX, d.k, o, gram);
+#define LMRS_GRAM_ARGS \
+  f->rec, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T, d.TX, d.k, o, gram, u, grad2d
+  if (u) {
+    if (d.k <= kWave) gram_kernel<1, true><<<tiles, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+    else gram_kernel<4, true><<<tiles, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+  } else {
+    if (d.k <= kWave) gram_kernel<1, false><<<tiles, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+    else gram_kernel<4, false><<<tiles, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+  }
+#undef LMRS_GRAM_ARGS
 }
 
 }  // namespace lmrs

@@ -47,8 +47,9 @@ void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_re
 // mode: 1 = J p only (writes jp), 2 = J^T u only (reads u), 3 = fused GN (J^T W J p)
 void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                   const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s);
+// gram[V][32][n]; with u non-NULL also grad2d += J^T u (u: [S][3])
 void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* gram,
-                 hipStream_t s);
+                 const float* u, float* grad2d, hipStream_t s);
 
 // solver side (kernels_solver.hip)
 constexpr int kRedBlocks = 512;  // partial sums per reduction
@@ -63,14 +64,15 @@ void launch_report_count(const int64_t* count, float* dst, hipStream_t s);
 // PCG state in device memory
 struct PcgState {
   float *x, *r, *z, *p, *u, *minv;
-  double* sc;        // scalars: see kernels_solver.hip
-  double* partials;  // [2 * kRedBlocks]
+  double* sc;        // two banks of 16 scalars: iteration i reads bank i % 2 (see kernels_solver.hip)
+  double* partials;  // [4 * kRedBlocks]
+  __host__ __device__ double* bank(int it) const { return sc + 16 * (it & 1); }
 };
 void launch_pcg_init(const float* b, const float* diag, float lambda, const float* dvec, int64_t P,
                      PcgState st, hipStream_t s);
-void launch_pcg_update(int64_t P, PcgState st, hipStream_t s);
-void launch_pcg_direction(int64_t P, PcgState st, hipStream_t s);
-void launch_pcg_report(const float* b, int64_t P, PcgState st, float* report, hipStream_t s);
+// one PCG iteration after the product u = A p: p^T u, alpha, x, r, z, beta, p
+void launch_pcg_iteration(int it, int64_t P, PcgState st, hipStream_t s);
+void launch_pcg_report(const float* b, int iters, int64_t P, PcgState st, float* report, hipStream_t s);
 void launch_lm_update(float* beta, const float* x, int n, int64_t P, const lmrs_lm_params& prm,
                       double* partials, float* report, hipStream_t s);
 
