@@ -273,6 +273,12 @@ def serving_main(args):
         "served": s_srv, "sequential": s_seq,
         "speedup_fits_per_s": round(s_srv["fits_per_s"] / s_seq["fits_per_s"], 3),
         "max_final_psnr_diff_db": dpsnr, "max_beta_rel_diff": dbeta,
+        "requests": [{"id": r.id, "n": r.n, "sh": r.sh_degree, "views": r.n_views, "res": r.res,
+                      "arrival_s": round(r.arrival_t, 3),
+                      "seq_start_s": round(seq[r.id].start_s, 3), "seq_end_s": round(seq[r.id].end_s, 3),
+                      "srv_start_s": round(got[r.id].start_s, 3), "srv_end_s": round(got[r.id].end_s, 3),
+                      "psnr_seq": round(seq[r.id].final_psnr, 3), "psnr_srv": round(got[r.id].final_psnr, 3)}
+                     for r in reqs],
     }
     print(json.dumps(res), flush=True)
 

@@ -49,7 +49,7 @@ class FitRequest:
     res: int
     lm_iters: int = 30
     cg_iters: int = 8
-    lam: float = 1e-3
+    lam: float = 0.1
     arrival_t: float = 0.0       # seconds after the start of the run
     id: int = 0
 

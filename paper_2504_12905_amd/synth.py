@@ -241,5 +241,5 @@ def request_stream(n_requests: int = 256, rate_hz: float = 20.0, seed: int = 0) 
         n = int(round(math.exp(g.uniform(math.log(2000), math.log(200_000)))))
         out.append(dict(id=i, seed=i, arrival_s=t, n=n, sh_degree=int(g.integers(0, 4)),
                         n_views=int(g.integers(4, 33)), res=int(g.choice([256, 512, 800])),
-                        lm_iters=30, cg_iters=8, lam=1e-3))
+                        lm_iters=30, cg_iters=8, lam=0.1))
     return out
