@@ -16,10 +16,15 @@
 //    breaks ties.
 // 5. sort: one workgroup per tile sorts its segment. Segments of up to 4096
 //    keys are sorted in LDS by a bitonic network; longer ones sort 4096-key
-//    runs in LDS and then merge runs pairwise in HBM by merge path: each
-//    thread takes an equal share of the output, finds where that share
-//    starts in the two runs by one binary search along the merge path, and
-//    merges its share sequentially (keys are unique within a tile).
+//    runs in LDS and then merge runs pairwise by merge path (keys are unique
+//    within a tile). The merged output is cut into windows of 2048 keys; the
+//    split of every window boundary between the two runs is found first, one
+//    binary search per thread in parallel; then each window's two input
+//    slices are loaded into LDS with coalesced reads, each thread locates its
+//    8 outputs on the merge path inside LDS and merges them, and the window
+//    is written back coalesced. Tiles near the image centre of large scenes
+//    hold hundreds of thousands of keys, so this merge (not the LDS sort)
+//    sets the time of the whole launch.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -154,23 +159,59 @@ __device__ void sort_chunk(const uint64_t* src, uint64_t* dst, int len, uint64_t
   __syncthreads();
 }
 
-// Merge sorted runs A[0, na) and B[0, nb) into out[0, na + nb).
-__device__ void merge_path(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb, uint64_t* out) {
-  const int64_t total = na + nb;
-  const int64_t per = (total + kSortThreads - 1) / kSortThreads;
-  const int64_t d0 = min(total, (int64_t)threadIdx.x * per);
-  const int64_t d1 = min(total, d0 + per);
-  if (d0 >= d1) return;
-  // number of A elements among the first d0 outputs
-  int64_t lo = max<int64_t>(0, d0 - nb), hi = min(d0, na);
+constexpr int kMergeWindow = 2048;                 // merged keys per LDS window
+constexpr int kMergePer = kMergeWindow / kSortThreads;  // outputs per thread per window
+
+// Number of A keys among the first d keys of the merge of sorted A[0, na) and B[0, nb).
+__device__ __forceinline__ int64_t merge_split(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb,
+                                               int64_t d) {
+  int64_t lo = max<int64_t>(0, d - nb), hi = min(d, na);
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if (A[mid] < B[d0 - 1 - mid]) lo = mid + 1; else hi = mid;
+    if (A[mid] < B[d - 1 - mid]) lo = mid + 1; else hi = mid;
   }
-  int64_t i = lo, j = d0 - lo;
-  for (int64_t d = d0; d < d1; ++d) {
-    const bool take_a = j >= nb || (i < na && A[i] < B[j]);
-    out[d] = take_a ? A[i++] : B[j++];
+  return lo;
+}
+
+// Merge sorted runs A[0, na) and B[0, nb) into out[0, na + nb) through LDS
+// windows. s: 2 * kMergeWindow keys of LDS (window data, then the splits).
+__device__ void merge_runs(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb, uint64_t* out,
+                           uint64_t* s) {
+  const int64_t total = na + nb;
+  const int64_t nw = (total + kMergeWindow - 1) / kMergeWindow;
+  int64_t* split = reinterpret_cast<int64_t*>(s + kMergeWindow);
+  constexpr int64_t kBatch = kMergeWindow - 1;  // windows whose boundaries fit the split array
+  for (int64_t w0 = 0; w0 < nw; w0 += kBatch) {
+    const int64_t wn = min(kBatch, nw - w0);
+    for (int64_t q = threadIdx.x; q <= wn; q += kSortThreads)
+      split[q] = merge_split(A, na, B, nb, min((w0 + q) * kMergeWindow, total));
+    __syncthreads();
+    for (int64_t q = 0; q < wn; ++q) {
+      const int64_t d0 = (w0 + q) * kMergeWindow, d1 = min(d0 + kMergeWindow, total);
+      const int64_t a0 = split[q], a1 = split[q + 1];
+      const int la = (int)(a1 - a0), lb = (int)((d1 - d0) - la);
+      const int64_t b0 = d0 - a0;
+      for (int i = threadIdx.x; i < la; i += kSortThreads) s[i] = A[a0 + i];
+      for (int i = threadIdx.x; i < lb; i += kSortThreads) s[la + i] = B[b0 + i];
+      __syncthreads();
+      const int o0 = threadIdx.x * kMergePer, n_out = (int)(d1 - d0);
+      if (o0 < n_out) {
+        const uint64_t* sa = s;
+        const uint64_t* sb = s + la;
+        int lo = max(0, o0 - lb), hi = min(o0, la);
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (sa[mid] < sb[o0 - 1 - mid]) lo = mid + 1; else hi = mid;
+        }
+        int i = lo, j = o0 - lo;
+        const int o1 = min(o0 + kMergePer, n_out);
+        for (int o = o0; o < o1; ++o) {
+          const bool take_a = j >= lb || (i < la && sa[i] < sb[j]);
+          out[d0 + o] = take_a ? sa[i++] : sb[j++];
+        }
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -193,9 +234,8 @@ __global__ __launch_bounds__(kSortThreads) void sort_kernel(const int64_t* __res
       for (int64_t base = 0; base < len; base += 2 * run) {
         const int64_t na = min(run, len - base);
         const int64_t nb = max<int64_t>(0, min(run, len - base - run));
-        merge_path(src + base, na, src + base + na, nb, dst + base);
+        merge_runs(src + base, na, src + base + na, nb, dst + base, s);
       }
-      __syncthreads();
       uint64_t* t = src;
       src = dst;
       dst = t;
