@@ -412,14 +412,17 @@ def main():
     e1.synchronize()
     unfused_ms = e0.elapsed_time(e1) / args.gn_reps
     out_gpu = out.double().cpu().numpy()
+    # the state of the timed product, for the oracle (the stage breakdown below re-samples)
+    beta_h, pix_h, w_h, vids_h = (fr.beta.cpu().numpy(), fr.pix.cpu().numpy(), fr.w.cpu().numpy(),
+                                  view_ids.cpu().numpy())
+    last = fr.last.view(V * fr.T, k).to(torch.int64)
+    entries = int((last.max(dim=1).values + 1).clamp(min=0).sum().item())
+    pairs = int((last + 1).clamp(min=0).sum().item())
 
     breakdown = lm_breakdown(L, torch, fr, targets, w, sampler, it, gn_ms)
     log("[bench] LM-step stages (ms, each run alone): " + ", ".join(f"{k} {v:.2f}" for k, v in breakdown.items()))
 
-    # --- algorithmic work of the fused splat kernel in this launch
-    last = fr.last.view(V * fr.T, k).to(torch.int64)
-    entries = int((last.max(dim=1).values + 1).clamp(min=0).sum().item())
-    pairs = int((last + 1).clamp(min=0).sum().item())
+    # --- algorithmic work of the fused splat kernel in the timed launches
     S = fr.S
     b_alg = entries * BYTES_PER_ENTRY + S * BYTES_PER_PIXEL
     f_alg = pairs * FLOPS_PER_PAIR
@@ -448,8 +451,7 @@ def main():
     cpu, parity = None, None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline (the same GN product in FP64)")
-        cpu, ref = cpu_baseline(w, fr.beta.cpu().numpy(), w.cams, view_ids.cpu().numpy(), fr.pix.cpu().numpy(),
-                                fr.w.cpu().numpy(), w.lam, p.cpu().numpy(), args.cpu_budget,
+        cpu, ref = cpu_baseline(w, beta_h, w.cams, vids_h, pix_h, w_h, w.lam, p.cpu().numpy(), args.cpu_budget,
                                 n_views=None if args.workload == "cfg1" else 2)
         if ref is not None:
             parity = float(np.linalg.norm(out_gpu - ref) / np.linalg.norm(ref))

@@ -55,7 +55,7 @@ def test_workspace_sizes(M):
 
 
 @pytest.mark.parametrize("bad", [dict(n=0), dict(sh_degree=4), dict(width=100), dict(n_views=0),
-                                 dict(k=0), dict(k=300)])
+                                 dict(k=0), dict(k=300), dict(width=2064, height=2048)])
 def test_invalid_frames_rejected_on_host(M, bad):
     f = frame(M, **bad)
     f.beta = 1  # never dereferenced: validation fails first

@@ -66,3 +66,45 @@ def test_long_tile_list_merge_path():
     fr, orc = check_all("long-list", n, 0, beta, axis_camera(f, 64, 64), 64, 64)
     ts = np_(fr.tile_start)
     assert np.diff(ts).max() > 4096
+
+
+def _one_tile_cloud(n, seed, f=120.0, W=64):
+    """n small Gaussians whose footprints all fall inside tile (2, 2) of a WxW view."""
+    rng = np.random.default_rng(seed)
+    zc = rng.uniform(2.0, 4.0, n)
+    u, v = rng.uniform(35.0, 45.0, n), rng.uniform(35.0, 45.0, n)
+    mu = np.stack([(u - 32.0) * zc / f, (v - 32.0) * zc / f, zc - 3.0], 1)
+    n, beta = one_gaussian_scene(mu, [math.log(0.004)] * 3, [1, 0, 0, 0], -1.0, [0.3, 0.6, 0.9])
+    return n, beta, axis_camera(f, W, W)
+
+
+def test_list_of_three_sort_chunks():
+    """12,000 entries in one tile: three 4096-key runs, so the first merge pass
+    has a run without a partner and the second merges 8192 + 3808 keys."""
+    n, beta, cams = _one_tile_cloud(12000, 8)
+    fr, orc = check_all("three-chunk list", n, 0, beta, cams, 64, 64)
+    assert np.diff(np_(fr.tile_start)).max() == 12000
+
+
+def test_four_million_entry_tile_lists():
+    """4.2 M entries in one tile: each merge pass covers more than 2,047 windows
+    of 2,048 keys, so the window splits are found in several batches. Lists
+    only (bit-exact against the oracle)."""
+    n, beta, cams = _one_tile_cloud(4_200_000, 9)
+    log("[edge] 4.2M-entry tile")
+    fr = gpu_frame(n, 0, beta, cams, 64, 64, render=False)
+    gts, gids = lists_of(fr)
+    orc = oracle_for(n, 0, beta, cams, 64, 64)
+    ots, oids = orc.lists()
+    assert np.diff(ots).max() == n
+    assert compare_lists(gts, gids, ots, oids, orc.projection()["margin"], orc.T) == 0
+
+
+def test_maximum_tiles_per_view():
+    """A 2048x2048 view has 16,384 tiles, the most one view may have (the
+    binning histogram of a view lives in LDS); one sample per tile."""
+    w = synth.config0()
+    W = 2048
+    cams = synth.sphere_cameras(1, 3.0, W, W, 60.0, 5)
+    pix, wts = sample_uniform(6, 0, np.arange(1), (W // 16) ** 2, 1)
+    check_all("2048x2048", w.n, 0, w.beta_init, cams, W, W, 1, pix, wts)
