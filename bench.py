@@ -283,6 +283,34 @@ def serving_main(args):
     print(json.dumps(res), flush=True)
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "gn_splat_counters_cfg1.txt")
+
+
+def summarize_counters(dirs: list[str], command: str) -> str:
+    """Median per dispatch of every counter found in rocprofv3 --pmc output
+    folders, for the fused splat kernel; writes COUNTERS_FILE."""
+    import csv
+    import glob
+    vals: dict[str, list[float]] = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                if "deriv_kernel<3" in row["Kernel_Name"]:
+                    vals.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+    if not vals:
+        raise SystemExit("no deriv_kernel<3> dispatches in " + " ".join(dirs))
+    lines = ["# rocprofv3 counters of the fused splat kernel deriv_kernel<3> (one GN product),",
+             "# 100k-Gaussian object-scale workload (8 views 800x800, 26 samples/tile); median per dispatch.",
+             "# Commands (one --pmc pass per counter group, from the repository root):",
+             f"#   {command}"]
+    for k in sorted(vals):
+        lines.append(f"{k}: {float(np.median(vals[k])):.6g}  (dispatches: {len(vals[k])})")
+    text = "\n".join(lines) + "\n"
+    with open(COUNTERS_FILE, "w") as f:
+        f.write(text)
+    return text
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +328,8 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the splat traffic summary from two rocprofv3 --pmc output folders and exit")
     ap.add_argument("--traffic-command", default="", help="command line recorded in the traffic summary")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
+                    help="write the splat counter summary from rocprofv3 --pmc output folders and exit")
     ap.add_argument("--serving", action="store_true", help="serving benchmark (fit-request stream)")
     ap.add_argument("--requests", type=int, default=32)
     ap.add_argument("--rate", type=float, default=20.0)
@@ -310,6 +340,9 @@ def main():
     args = ap.parse_args()
     if args.serving:
         return serving_main(args)
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.traffic_command))
+        return
     if args.summarize_traffic:
         print(summarize_traffic(*args.summarize_traffic, args.calibrate_copy or 1024, args.traffic_command))
         return
