@@ -18,7 +18,9 @@
  *   state between calls. Host structs are read during the call only.
  * Streams. `stream` is a hipStream_t passed as void* (NULL = default stream).
  *   Work is enqueued and the call returns, except lmrs_bin_tiles and
- *   lmrs_lm_step, which wait for the tile-instance count (see there).
+ *   lmrs_lm_step, which wait for the tile-instance count (see there). Calls
+ *   on one frame must be ordered on one stream: they share the frame's
+ *   buffers, including the work counters in lmrs_frame.sched.
  * Errors.  Arguments are checked on the host before anything is enqueued; a
  *   failed check returns a negative status and enqueues nothing.
  *   lmrs_last_error() gives a message for the calling thread. A fault inside
@@ -110,7 +112,20 @@ typedef struct lmrs_frame {
   float* trans;           /* [S] final transmittance            (render: out)   */
   int32_t* last;          /* [S] list position of the last blended Gaussian,
                              -1 if none                          (render: out)   */
+  int32_t* sched;         /* [LMRS_SCHED_INTS(V*T)] tile schedule of the splat
+                             walks (render: out; jvp, vjp, gn, lm: read, counters
+                             updated). Layout: [0, V*T) tile ids by decreasing
+                             walk length; [V*T, 2 V*T) walk length of each tile
+                             (sum over its samples of the 64-entry list chunks
+                             up to their last blended Gaussian); then 4 counters
+                             (next ticket, finished waves, tiles with a
+                             non-empty walk, 0). The splat kernels hand tiles to
+                             their waves in this order and leave the counters as
+                             they found them.                                  */
 } lmrs_frame;
+
+/* Length in int32 of lmrs_frame.sched for a batch of `tiles` = V*T tiles. */
+#define LMRS_SCHED_INTS(tiles) (2 * (int64_t)(tiles) + 4)
 
 /* Operation codes for lmrs_workspace_bytes. */
 #define LMRS_OP_BIN 1
@@ -174,7 +189,8 @@ lmrs_status lmrs_bin_tiles(const lmrs_frame* f, void* ws, size_t ws_bytes, void*
 
 /* a3. Forward render of the sampled pixels (Sec. 3 eq. 3; Supp. A Alg. 2):
  * front-to-back blending of each pixel's tile list. Writes color (with
- * background), trans (final T) and last. */
+ * background), trans (final T), last, and sched (the tile order the
+ * derivative kernels follow, from the walk lengths that last fixes). */
 lmrs_status lmrs_render(const lmrs_frame* f, const lmrs_render_opts* o, void* stream);
 
 /* J p at every sampled pixel (Sec. 4.2; Supp. A "Jv kernel", Alg. 3):

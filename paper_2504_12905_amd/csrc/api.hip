@@ -141,7 +141,7 @@ lmrs_status check_render_state(const lmrs_frame* f) {
 lmrs_status check_deriv_state(const lmrs_frame* f) {
   lmrs_status st = check_render_state(f);
   if (st) return st;
-  if ((st = need(f->trans, "trans")) || (st = need(f->last, "last"))) return st;
+  if ((st = need(f->trans, "trans")) || (st = need(f->last, "last")) || (st = need(f->sched, "sched"))) return st;
   return LMRS_OK;
 }
 
@@ -229,6 +229,7 @@ lmrs_status check_lm_args(const lmrs_frame* f, const float* beta, const float* t
   LMRS_TRY(need(f->color, "color"));
   LMRS_TRY(need(f->trans, "trans"));
   LMRS_TRY(need(f->last, "last"));
+  LMRS_TRY(need(f->sched, "sched"));
   if (f->k < 256 && (!f->pix || !f->w)) return fail(LMRS_EINVAL, "k < 256 needs pix and w buffers");
   if (prm->sampler != LMRS_SAMPLER_UNIFORM && prm->sampler != LMRS_SAMPLER_RESIDUAL)
     return fail(LMRS_EINVAL, "unknown sampler %d", prm->sampler);
@@ -337,6 +338,7 @@ lmrs_status lmrs_render(const lmrs_frame* f, const lmrs_render_opts* o, void* st
   LMRS_TRY(need(f->color, "color"));
   LMRS_TRY(need(f->trans, "trans"));
   LMRS_TRY(need(f->last, "last"));
+  LMRS_TRY(need(f->sched, "sched"));
   launch_render(f, dims_of(f), *o, (hipStream_t)stream);
   return hip_check("lmrs_render");
 }

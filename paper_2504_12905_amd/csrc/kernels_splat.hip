@@ -3,7 +3,9 @@
 // kernel"), their fused composition J^T W J p (the operator product of the
 // PCG loop in Alg. 1), and the weighted Gram blocks behind diag(J^T W J).
 //
-// Work layout (one 64-lane wave per (view, tile)). The paper launches one
+// Work layout (one 64-lane wave per (view, tile) at a time; the derivative
+// kernels hand tiles to a persistent grid of waves, longest walk first, see
+// "tile schedule" below). The paper launches one
 // thread per sampled pixel; with ~10 % of a 16x16 tile sampled that leaves
 // most of a wave64 idle and forces cross-lane reductions of every Gaussian's
 // gradient. Here the lanes own list entries instead: a chunk of 64 entries
@@ -24,6 +26,9 @@
 //
 // Discrete decisions (list, opacity skip, cap, stop position) come from the
 // render and are recomputed bit-identically by pair_alpha().
+#include <algorithm>
+#include <atomic>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -39,9 +44,9 @@ struct TileCtx {
   float ox, oy;
 };
 
-__device__ __forceinline__ TileCtx tile_ctx(const int64_t* tile_start, int T, int TX) {
+__device__ __forceinline__ TileCtx tile_ctx(const int64_t* tile_start, int T, int TX, int64_t tile_lin) {
   TileCtx c;
-  c.tile_lin = blockIdx.x;
+  c.tile_lin = tile_lin;
   c.v = (int)(c.tile_lin / T);
   c.t = (int)(c.tile_lin % T);
   c.start = tile_start[c.tile_lin];
@@ -100,6 +105,122 @@ __device__ __forceinline__ int load_pixel_regs(const uint8_t* pix, const float* 
 
 __device__ __forceinline__ float log2_om(bool inc, float a) { return inc ? __log2f(1.f - a) : 0.f; }
 
+// ------------------------------------------------------------ tile schedule
+// A tile's cost in the derivative walks is its walk length: the number of
+// (sampled pixel, 64-entry chunk) steps, i.e. the sum over its pixels of the
+// chunks up to the pixel's last blended entry. Within one view batch it
+// ranges from 0 (empty tiles, often most of an object-centred image) to
+// hundreds, and one wave per tile in grid order leaves some SIMDs with twice
+// the mean work while others idle. The derivative kernels therefore run a
+// persistent grid whose waves take tiles from a shared ticket counter in
+// order of decreasing walk length (list scheduling: longest first, then
+// whoever is free takes the next), which keeps every SIMD busy to the end.
+// Cutting long tiles into parts over their pixels was tried and is slower:
+// every part walks the list chunks again and flushes its own atomics.
+//
+// sched = [order (tiles) | walk length (tiles) | ticket, finished, busy, 0].
+constexpr int kSchedBins = 1024;
+constexpr int kSchedThreads = 1024;
+constexpr int kSchedUnroll = 8;
+
+struct SchedRef {
+  const int32_t* order;
+  int32_t* ctr;
+  int tiles;
+};
+
+__device__ __forceinline__ SchedRef sched_ref(int32_t* sched, int tiles) {
+  return SchedRef{sched, sched + 2 * (int64_t)tiles, tiles};
+}
+
+// Tiles handed out by one persistent launch: every tile, or (for the walks
+// that do nothing on a tile without blended entries) only the busy ones,
+// which the schedule puts first.
+__device__ __forceinline__ int sched_count(const SchedRef& sr, bool busy_only) {
+  return busy_only ? min(max(sr.ctr[2], 0), sr.tiles) : sr.tiles;
+}
+
+// Next tile of this wave, -1 when the launch has run out of tickets, -2 for
+// an entry that is not a tile of this frame (skipped).
+__device__ __forceinline__ int sched_next(const SchedRef& sr, int count) {
+  int t = 0;
+  if (lane_id() == 0) t = atomicAdd(sr.ctr, 1);
+  t = readlane(t, 0);
+  if (t < 0 || t >= count) return -1;
+  const int tile = sr.order[t];
+  return (unsigned)tile < (unsigned)sr.tiles ? tile : -2;
+}
+
+// Called once by every wave of the launch: the last wave to finish returns
+// the counters to zero for the next launch on the frame.
+__device__ __forceinline__ void sched_finish(const SchedRef& sr) {
+  if (lane_id() == 0) {
+    if (atomicAdd(sr.ctr + 1, 1) == (int)gridDim.x - 1) {
+      atomicExch(sr.ctr, 0);
+      atomicExch(sr.ctr + 1, 0);
+    }
+  }
+}
+
+// Bin of a walk length, 0 = longest: exact below 512, then 16 per bin.
+__device__ __forceinline__ int sched_bin(int len) {
+  const int key = len < 512 ? len : min(kSchedBins - 1, 512 + ((len - 512) >> 4));
+  return kSchedBins - 1 - key;
+}
+
+// One workgroup: counting sort of the tiles by walk-length bin (descending),
+// then the counters for the launches that follow.
+__global__ __launch_bounds__(kSchedThreads) void sched_kernel(int32_t* __restrict__ sched, int tiles) {
+  __shared__ int hist[kSchedBins];
+  __shared__ int wsum[kSchedThreads / kWave];
+  const int tid = threadIdx.x;
+  const int32_t* len = sched + tiles;
+  hist[tid] = 0;
+  __syncthreads();
+  for (int base = 0; base < tiles; base += kSchedThreads * kSchedUnroll) {
+    int b[kSchedUnroll];
+#pragma unroll
+    for (int u = 0; u < kSchedUnroll; ++u) {
+      const int i = base + u * kSchedThreads + tid;
+      b[u] = i < tiles ? sched_bin(max(len[i], 0)) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kSchedUnroll; ++u)
+      if (b[u] >= 0) atomicAdd(&hist[b[u]], 1);
+  }
+  __syncthreads();
+  const int own = hist[tid];
+  int x = own;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int y = __shfl_up(x, d, kWave);
+    if ((tid & (kWave - 1)) >= d) x += y;
+  }
+  if ((tid & (kWave - 1)) == kWave - 1) wsum[tid / kWave] = x;
+  __syncthreads();
+  for (int w = 0; w < tid / kWave; ++w) x += wsum[w];
+  hist[tid] = x - own;  // first position of this bin
+  __syncthreads();
+  for (int base = 0; base < tiles; base += kSchedThreads * kSchedUnroll) {
+    int b[kSchedUnroll];
+#pragma unroll
+    for (int u = 0; u < kSchedUnroll; ++u) {
+      const int i = base + u * kSchedThreads + tid;
+      b[u] = i < tiles ? sched_bin(max(len[i], 0)) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kSchedUnroll; ++u)
+      if (b[u] >= 0) sched[atomicAdd(&hist[b[u]], 1)] = base + u * kSchedThreads + tid;
+  }
+  if (tid == kSchedBins - 1) {  // the last bin holds the tiles with walk length 0
+    int32_t* ctr = sched + 2 * (int64_t)tiles;
+    atomicExch(ctr, 0);
+    atomicExch(ctr + 1, 0);
+    atomicExch(ctr + 2, tiles - own);
+    atomicExch(ctr + 3, 0);
+  }
+}
+
 // ------------------------------------------------------------------ render
 // SCORE = false: colour (with background), final transmittance and last
 // blended position of every sampled pixel. SCORE = true (every pixel, k = 256):
@@ -119,9 +240,10 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
                                                        const uint8_t* __restrict__ pix, int n, int T,
                                                        int TX, int k, lmrs_render_opts o,
                                                        float* __restrict__ color, float* __restrict__ trans,
-                                                       int32_t* __restrict__ last, ScoreOut so) {
+                                                       int32_t* __restrict__ last,
+                                                       int32_t* __restrict__ walk_len, ScoreOut so) {
   const int lane = lane_id();
-  const TileCtx c = tile_ctx(tile_start, T, TX);
+  const TileCtx c = tile_ctx(tile_start, T, TX, blockIdx.x);
   PixelRegs<NS> pr;
   load_pixel_regs<NS>(pix, nullptr, nullptr, k, c, pr);
   float sT[NS], sC0[NS], sC1[NS], sC2[NS];
@@ -195,21 +317,28 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
       }
     }
   }
+  if (!SCORE) {
+    int steps = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) steps += sLast[s] >= 0 ? sLast[s] / kWave + 1 : 0;
+    const float total = wave_total((float)steps);  // a sort key: exact up to 2^24 steps
+    if (lane == 0) walk_len[c.tile_lin] = (int32_t)total;
+  }
 }
 
 // ----------------------------------------------------- J p, J^T u, fused GN
 // MODE 1: jp = J p.  MODE 2: grad2d += J^T u.  MODE 3: grad2d += J^T W J p.
 template <int MODE, int NS>
-__global__ __launch_bounds__(kWave) void deriv_kernel(
+__device__ __forceinline__ void deriv_tile(
     const float* __restrict__ rec, const float* __restrict__ tan, const int64_t* __restrict__ tile_start,
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
     const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
-    lmrs_render_opts o, const float* __restrict__ u_in, float* __restrict__ jp_out,
-    float* __restrict__ grad2d) {
+    const lmrs_render_opts& o, const float* __restrict__ u_in, float* __restrict__ jp_out,
+    float* __restrict__ grad2d, int64_t tile_lin) {
   constexpr bool FWD = MODE != 2;
   constexpr bool REV = MODE != 1;
   const int lane = lane_id();
-  const TileCtx c = tile_ctx(tile_start, T, TX);
+  const TileCtx c = tile_ctx(tile_start, T, TX, tile_lin);
   PixelRegs<NS> pr;
   const int lmax = load_pixel_regs<NS>(pix, wts, lastv, k, c, pr);
   // forward: a = T in front of the chunk, b = its tangent, u0..u2 = d colour
@@ -374,6 +503,27 @@ __global__ __launch_bounds__(kWave) void deriv_kernel(
   }
 }
 
+// Persistent grid over the tile schedule; J p visits every tile (it writes
+// every sample), the reverse walks only tiles with blended entries.
+template <int MODE, int NS>
+__global__ __launch_bounds__(kWave) void deriv_kernel(
+    const float* __restrict__ rec, const float* __restrict__ tan, const int64_t* __restrict__ tile_start,
+    const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
+    const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
+    lmrs_render_opts o, const float* __restrict__ u_in, float* __restrict__ jp_out,
+    float* __restrict__ grad2d, int32_t* __restrict__ sched, int tiles) {
+  const SchedRef sr = sched_ref(sched, tiles);
+  const int count = sched_count(sr, MODE != 1);
+  for (;;) {
+    const int tile = sched_next(sr, count);
+    if (tile == -1) break;
+    if (tile >= 0)
+      deriv_tile<MODE, NS>(rec, tan, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, u_in, jp_out,
+                           grad2d, tile);
+  }
+  sched_finish(sr);
+}
+
 // --------------------------------------------------------------- Gram
 // Per (view, Gaussian) weighted Gram of d C_c / d rec over the tile's pixels
 // and channels: geometry block, geometry x colour, colour, opacity. Walks
@@ -383,18 +533,15 @@ __global__ __launch_bounds__(kWave) void deriv_kernel(
 // per-channel colour behind, so the right-hand side b = J^T W r of an LM step
 // costs no walk of its own.
 template <int NS, bool VJP>
-__global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ rec,
-                                                     const int64_t* __restrict__ tile_start,
-                                                     const int32_t* __restrict__ ids,
-                                                     const uint8_t* __restrict__ pix,
-                                                     const float* __restrict__ wts,
-                                                     const float* __restrict__ trans,
-                                                     const int32_t* __restrict__ lastv, int n, int T,
-                                                     int TX, int k, lmrs_render_opts o,
-                                                     float* __restrict__ gram, const float* __restrict__ u_in,
-                                                     float* __restrict__ grad2d) {
+__device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const int64_t* __restrict__ tile_start,
+                                          const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix,
+                                          const float* __restrict__ wts, const float* __restrict__ trans,
+                                          const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
+                                          const lmrs_render_opts& o, float* __restrict__ gram,
+                                          const float* __restrict__ u_in, float* __restrict__ grad2d,
+                                          int64_t tile_lin) {
   const int lane = lane_id();
-  const TileCtx c = tile_ctx(tile_start, T, TX);
+  const TileCtx c = tile_ctx(tile_start, T, TX, tile_lin);
   PixelRegs<NS> pr;
   const int lmax = load_pixel_regs<NS>(pix, wts, lastv, k, c, pr);
   float sT[NS], sS0[NS], sS1[NS], sS2[NS], sU0[NS], sU1[NS], sU2[NS];
@@ -505,17 +652,69 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
   }
 }
 
+template <int NS, bool VJP>
+__global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ rec,
+                                                     const int64_t* __restrict__ tile_start,
+                                                     const int32_t* __restrict__ ids,
+                                                     const uint8_t* __restrict__ pix,
+                                                     const float* __restrict__ wts,
+                                                     const float* __restrict__ trans,
+                                                     const int32_t* __restrict__ lastv, int n, int T,
+                                                     int TX, int k, lmrs_render_opts o,
+                                                     float* __restrict__ gram, const float* __restrict__ u_in,
+                                                     float* __restrict__ grad2d, int32_t* __restrict__ sched,
+                                                     int tiles) {
+  const SchedRef sr = sched_ref(sched, tiles);
+  const int count = sched_count(sr, true);
+  for (;;) {
+    const int tile = sched_next(sr, count);
+    if (tile == -1) break;
+    if (tile >= 0)
+      gram_tile<NS, VJP>(rec, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, gram, u_in, grad2d, tile);
+  }
+  sched_finish(sr);
+}
+
+// Waves of a persistent splat launch: one per kTilesPerWave tiles of the
+// batch, between kMinWavesPerCU and kMaxWavesPerCU per CU. With few busy
+// tiles of uneven walks (an object in the middle of the views), few waves per
+// SIMD let the ticket order balance the work; with many tiles, more waves
+// hide more latency. Measured on the 100k- and 1.5M-Gaussian workloads:
+// 8 per CU is best for 20,000 tiles of which a third are busy, 32 per CU for
+// 65,728 busy tiles. The busy count is only known on the device, so the tile
+// count of the batch stands in for it.
+constexpr int kMinWavesPerCU = 8;
+constexpr int kMaxWavesPerCU = 32;
+constexpr int kTilesPerWave = 10;
+
+unsigned persistent_grid(int64_t tiles) {
+  static std::atomic<int> cus[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int c = cus[dev].load(std::memory_order_relaxed);
+  if (c <= 0) {
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cus[dev].store(c, std::memory_order_relaxed);
+  }
+  const int64_t want = std::min<int64_t>((int64_t)c * kMaxWavesPerCU,
+                                         std::max<int64_t>((int64_t)c * kMinWavesPerCU,
+                                                           (tiles + kTilesPerWave - 1) / kTilesPerWave));
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, want));
+}
+
 }  // namespace
 
 void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   const ScoreOut none{nullptr, nullptr, 0, 0, nullptr};
+  int32_t* walk_len = f->sched + tiles;
   if (d.k <= kWave)
     render_kernel<1, false><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k,
-                                                    o, f->color, f->trans, f->last, none);
+                                                    o, f->color, f->trans, f->last, walk_len, none);
   else
     render_kernel<4, false><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k,
-                                                    o, f->color, f->trans, f->last, none);
+                                                    o, f->color, f->trans, f->last, walk_len, none);
+  sched_kernel<<<1, kSchedThreads, 0, s>>>(f->sched, (int)tiles);
 }
 
 void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
@@ -523,40 +722,43 @@ void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_re
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   const ScoreOut so{targets, f->view_ids, d.W, d.H, scores};
   render_kernel<4, true><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, nullptr, d.n, d.T, d.TX, 256, o,
-                                                 nullptr, nullptr, nullptr, so);
+                                                 nullptr, nullptr, nullptr, nullptr, so);
 }
 
 void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                   const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s) {
-  const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
+  const int tiles = d.V * d.T;
+  const unsigned grid = persistent_grid(tiles);
 #define LMRS_DERIV_ARGS                                                                              \
   f->rec, tan, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T, d.TX, d.k, o, u, jp, \
-      grad2d
+      grad2d, f->sched, tiles
   const bool small = d.k <= kWave;
   if (mode == 1) {
-    if (small) deriv_kernel<1, 1><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
-    else deriv_kernel<1, 4><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    if (small) deriv_kernel<1, 1><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    else deriv_kernel<1, 4><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
   } else if (mode == 2) {
-    if (small) deriv_kernel<2, 1><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
-    else deriv_kernel<2, 4><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    if (small) deriv_kernel<2, 1><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    else deriv_kernel<2, 4><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
   } else {
-    if (small) deriv_kernel<3, 1><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
-    else deriv_kernel<3, 4><<<tiles, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    if (small) deriv_kernel<3, 1><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    else deriv_kernel<3, 4><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
   }
 #undef LMRS_DERIV_ARGS
 }
 
 void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* gram,
                  const float* u, float* grad2d, hipStream_t s) {
-  const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
-#define LMRS_GRAM_ARGS \
-  f->rec, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T, d.TX, d.k, o, gram, u, grad2d
+  const int tiles = d.V * d.T;
+  const unsigned grid = persistent_grid(tiles);
+#define LMRS_GRAM_ARGS                                                                                      \
+  f->rec, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T, d.TX, d.k, o, gram, u, grad2d, \
+      f->sched, tiles
   if (u) {
-    if (d.k <= kWave) gram_kernel<1, true><<<tiles, kWave, 0, s>>>(LMRS_GRAM_ARGS);
-    else gram_kernel<4, true><<<tiles, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+    if (d.k <= kWave) gram_kernel<1, true><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+    else gram_kernel<4, true><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
   } else {
-    if (d.k <= kWave) gram_kernel<1, false><<<tiles, kWave, 0, s>>>(LMRS_GRAM_ARGS);
-    else gram_kernel<4, false><<<tiles, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+    if (d.k <= kWave) gram_kernel<1, false><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+    else gram_kernel<4, false><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
   }
 #undef LMRS_GRAM_ARGS
 }

@@ -59,7 +59,12 @@ class _Frame(C.Structure):
                 ("rec", C.c_void_p), ("rect", C.c_void_p), ("tile_start", C.c_void_p),
                 ("ids", C.c_void_p), ("capacity", C.c_int64), ("n_instances", C.c_void_p),
                 ("pix", C.c_void_p), ("w", C.c_void_p), ("color", C.c_void_p),
-                ("trans", C.c_void_p), ("last", C.c_void_p)]
+                ("trans", C.c_void_p), ("last", C.c_void_p), ("sched", C.c_void_p)]
+
+
+def sched_ints(tiles: int) -> int:
+    """int32 length of lmrs_frame.sched for `tiles` = V*T (LMRS_SCHED_INTS)."""
+    return 2 * int(tiles) + 4
 
 
 class LmParams(C.Structure):
@@ -143,6 +148,7 @@ class Frame:
         t["rect"] = torch.empty((V, n, 4), dtype=torch.int32, device=dev)
         t["tile_start"] = torch.zeros(V * self.T + 1, dtype=torch.int64, device=dev)
         t["n_instances"] = torch.zeros(1, dtype=torch.int64, device=dev)
+        t["sched"] = torch.zeros(sched_ints(V * self.T), dtype=torch.int32, device=dev)
         t["ids"] = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
         self.set_k(self.k, self.sampled or self.k < 256)
 
@@ -179,7 +185,8 @@ class Frame:
                       t["ids"].data_ptr(), self.capacity, t["n_instances"].data_ptr(),
                       None if t["pix"] is None else t["pix"].data_ptr(),
                       None if t["w"] is None else t["w"].data_ptr(),
-                      t["color"].data_ptr(), t["trans"].data_ptr(), t["last"].data_ptr())
+                      t["color"].data_ptr(), t["trans"].data_ptr(), t["last"].data_ptr(),
+                      t["sched"].data_ptr())
 
     def grow_ids(self, needed: int):
         self.capacity = int(needed * 1.25) + 1024

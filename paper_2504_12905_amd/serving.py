@@ -126,7 +126,8 @@ def footprint_bytes(req: FitRequest, instances: int) -> int:
     T = (W // 16) ** 2
     S = V * T * 256
     cap = int(instances * 1.05) + 1024
-    frame = V * n * (4 * L.LMRS_REC + 16) + 8 * (V * T + 1) + 4 * cap + S * (12 + 4 + 4)
+    frame = (V * n * (4 * L.LMRS_REC + 16) + 8 * (V * T + 1) + 4 * cap + S * (12 + 4 + 4)
+             + 4 * L.sched_ints(V * T))
     ws = max(_frame_struct_bytes(L.OP_BIN, n, req.sh_degree, V, W, W, 256, cap),
              _frame_struct_bytes(L.OP_SOLVE, n, req.sh_degree, V, W, W, 256, cap))
     return 4 * P + 16 * V * 4 + 12 * V * W * W + frame + ws + 64 * 4

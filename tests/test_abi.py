@@ -76,5 +76,8 @@ def test_missing_buffers_and_small_workspace_rejected(M):
     for name in ("rec", "rect", "tile_start", "ids", "cams", "trans", "last"):
         setattr(f, name, 256)
     st = M._lib.lmrs_gn_product(C.byref(f), C.byref(opts), 256, C.c_float(0.1), None, 512, 256, 16, None)
+    assert st == M.LMRS_EINVAL and b"sched" in M._lib.lmrs_last_error()  # no tile schedule buffer
+    f.sched = 256
+    st = M._lib.lmrs_gn_product(C.byref(f), C.byref(opts), 256, C.c_float(0.1), None, 512, 256, 16, None)
     assert st == M.LMRS_EWORKSPACE
     assert M._lib.lmrs_status_str(st) == b"workspace too small"
