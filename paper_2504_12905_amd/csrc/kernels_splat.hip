@@ -162,6 +162,21 @@ __device__ __forceinline__ void sched_finish(const SchedRef& sr) {
   }
 }
 
+// The same for a workgroup whose waves share one tile: one thread takes the
+// ticket (the caller broadcasts it) and signs the workgroup off.
+__device__ __forceinline__ int sched_take(const SchedRef& sr, int count) {
+  const int t = atomicAdd(sr.ctr, 1);
+  if (t < 0 || t >= count) return -1;
+  const int tile = sr.order[t];
+  return (unsigned)tile < (unsigned)sr.tiles ? tile : -2;
+}
+__device__ __forceinline__ void sched_sign_off(const SchedRef& sr) {
+  if (atomicAdd(sr.ctr + 1, 1) == (int)gridDim.x - 1) {
+    atomicExch(sr.ctr, 0);
+    atomicExch(sr.ctr + 1, 0);
+  }
+}
+
 // Bin of a walk length, 0 = longest: exact below 512, then 16 per bin.
 __device__ __forceinline__ int sched_bin(int len) {
   const int key = len < 512 ? len : min(kSchedBins - 1, 512 + ((len - 512) >> 4));
@@ -328,19 +343,25 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
 
 // ----------------------------------------------------- J p, J^T u, fused GN
 // MODE 1: jp = J p.  MODE 2: grad2d += J^T u.  MODE 3: grad2d += J^T W J p.
-template <int MODE, int NS>
+template <int MODE, int NS, int W>
 __device__ __forceinline__ void deriv_tile(
     const float* __restrict__ rec, const float* __restrict__ tan, const int64_t* __restrict__ tile_start,
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
     const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
     const lmrs_render_opts& o, const float* __restrict__ u_in, float* __restrict__ jp_out,
-    float* __restrict__ grad2d, int64_t tile_lin) {
+    float* __restrict__ grad2d, int64_t tile_lin, int wv, float* red) {
   constexpr bool FWD = MODE != 2;
   constexpr bool REV = MODE != 1;
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX, tile_lin);
   PixelRegs<NS> pr;
   const int lmax = load_pixel_regs<NS>(pix, wts, lastv, k, c, pr);
+  // this wave's pixels: sample slots j with j % W == wv (W waves share the tile)
+  int lm_own = -1;
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    if ((lane & (W - 1)) == wv) lm_own = max(lm_own, pr.last[s]);
+  const int lmax_own = uniform(wave_max_i(lm_own));
   // forward: a = T in front of the chunk, b = its tangent, u0..u2 = d colour
   // reverse: a = T behind the chunk range already walked, b = u . (colour behind + T_final bg), u = weights
   float sa[NS], sb[NS], su0[NS], su1[NS], su2[NS];
@@ -351,7 +372,7 @@ __device__ __forceinline__ void deriv_tile(
       sa[s] = 1.f;
       sb[s] = su0[s] = su1[s] = su2[s] = 0.f;
     }
-    for (int c0 = 0; c0 <= lmax; c0 += kWave) {
+    for (int c0 = 0; c0 <= lmax_own; c0 += kWave) {
       const int e = c0 + lane;
       const bool valid = e < c.len;
       RecF r{}, dr{};
@@ -363,7 +384,7 @@ __device__ __forceinline__ void deriv_tile(
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int cnt = min(kWave, k - s * kWave);
-        for (int l = 0; l < cnt; ++l) {
+        for (int l = wv; l < cnt; l += W) {
           const int lj = readlane(pr.last[s], l);
           if (c0 > lj) continue;
           const Alpha al =
@@ -410,7 +431,7 @@ __device__ __forceinline__ void deriv_tile(
       const int j = s * kWave + lane;
       const float d0 = su0[s] + o.bg[0] * sb[s], d1 = su1[s] + o.bg[1] * sb[s], d2 = su2[s] + o.bg[2] * sb[s];
       if (MODE == 1) {
-        if (j < k) {
+        if (j < k && (lane & (W - 1)) == wv) {
           const int64_t i = c.tile_lin * k + j;
           jp_out[3 * i] = d0;
           jp_out[3 * i + 1] = d1;
@@ -442,7 +463,8 @@ __device__ __forceinline__ void deriv_tile(
       }
       sb[s] = sa[s] * (su0[s] * o.bg[0] + su1[s] * o.bg[1] + su2[s] * o.bg[2]);
     }
-    if (lmax < 0) return;
+    if (lmax < 0) return;  // the same for every wave of the workgroup
+    int chunk = 0;
     for (int c0 = (lmax / kWave) * kWave; c0 >= 0; c0 -= kWave) {
       const int e = c0 + (kWave - 1 - lane);  // reversed: lane 0 holds the chunk's deepest entry
       const bool valid = e < c.len;
@@ -456,7 +478,7 @@ __device__ __forceinline__ void deriv_tile(
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int cnt = min(kWave, k - s * kWave);
-        for (int l = 0; l < cnt; ++l) {
+        for (int l = wv; l < cnt; l += W) {
           const int lj = readlane(pr.last[s], l);
           if (c0 > lj) continue;
           const Alpha al =
@@ -493,35 +515,54 @@ __device__ __forceinline__ void deriv_tile(
           sb[s] = writelane(sb[s], S + readlane(Sinc, kWave - 1), l);
         }
       }
-      if (valid) {
-        bool any = false;
-        for (int q = 0; q < 9; ++q) any |= g[q] != 0.f;
-        if (any)
-          for (int q = 0; q < 9; ++q) atomicAdd(&grad2d[((size_t)c.v * 9 + q) * n + id], g[q]);
+      // the waves' partial gradients of each entry meet in LDS (double
+      // buffered by chunk, so one barrier per chunk); wave wv adds up and
+      // flushes components wv, wv + W, ...
+      float* buf = red + (chunk & 1) * (W * 9 * kWave);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) buf[(wv * 9 + q) * kWave + lane] = g[q];
+      __syncthreads();
+      for (int q = wv; q < 9; q += W) {
+        float sum = 0.f;
+#pragma unroll
+        for (int w = 0; w < W; ++w) sum += buf[(w * 9 + q) * kWave + lane];
+        if (valid && sum != 0.f) atomicAdd(&grad2d[((size_t)c.v * 9 + q) * n + id], sum);
       }
+      ++chunk;
     }
   }
 }
 
 // Persistent grid over the tile schedule; J p visits every tile (it writes
-// every sample), the reverse walks only tiles with blended entries.
-template <int MODE, int NS>
-__global__ __launch_bounds__(kWave) void deriv_kernel(
+// every sample), the reverse walks only tiles with blended entries. A
+// workgroup of W waves takes one tile at a time and deals its sampled pixels
+// to the waves (slot j to wave j % W): more waves per SIMD without cutting
+// the work into more, smaller items. W is chosen from the samples per tile
+// (launch_deriv).
+template <int MODE, int NS, int W>
+__global__ __launch_bounds__(kWave* W) void deriv_kernel(
     const float* __restrict__ rec, const float* __restrict__ tan, const int64_t* __restrict__ tile_start,
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
     const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
     lmrs_render_opts o, const float* __restrict__ u_in, float* __restrict__ jp_out,
     float* __restrict__ grad2d, int32_t* __restrict__ sched, int tiles) {
+  __shared__ int next_tile[2];
+  __shared__ float red[MODE == 1 ? 1 : 2 * W * 9 * kWave];
+  const int wv = uniform((int)(threadIdx.x / kWave));
   const SchedRef sr = sched_ref(sched, tiles);
   const int count = sched_count(sr, MODE != 1);
-  for (;;) {
-    const int tile = sched_next(sr, count);
+  for (int it = 0;; ++it) {
+    // double buffered: a slot is rewritten two tickets later, after every
+    // wave has passed the barrier of the ticket in between
+    if (threadIdx.x == 0) next_tile[it & 1] = sched_take(sr, count);
+    __syncthreads();
+    const int tile = next_tile[it & 1];
     if (tile == -1) break;
     if (tile >= 0)
-      deriv_tile<MODE, NS>(rec, tan, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, u_in, jp_out,
-                           grad2d, tile);
+      deriv_tile<MODE, NS, W>(rec, tan, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, u_in, jp_out,
+                           grad2d, tile, wv, red);
   }
-  sched_finish(sr);
+  if (threadIdx.x == 0) sched_sign_off(sr);
 }
 
 // --------------------------------------------------------------- Gram
@@ -702,6 +743,15 @@ unsigned persistent_grid(int64_t tiles) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, want));
 }
 
+// Workgroups of W waves for a persistent derivative launch: one wave per
+// kTilesPerWave / W tiles, between kMinWavesPerCU and kMaxWavesPerCU waves
+// per CU (see persistent_grid; the LDS of the reduction buffers allows 32
+// waves per CU).
+unsigned persistent_groups(int64_t tiles, int w) {
+  const int64_t waves = (int64_t)persistent_grid(tiles * w);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, waves / w));
+}
+
 }  // namespace
 
 void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
@@ -725,25 +775,38 @@ void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_re
                                                  nullptr, nullptr, nullptr, nullptr, so);
 }
 
-void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
-                  const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s) {
+template <int W>
+void launch_deriv_w(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
+                    const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s) {
+  static_assert(kWave % W == 0, "pixel slots are dealt to the waves by lane");
   const int tiles = d.V * d.T;
-  const unsigned grid = persistent_grid(tiles);
+  const unsigned grid = persistent_groups(tiles, W);
+  const unsigned block = kWave * W;
 #define LMRS_DERIV_ARGS                                                                              \
   f->rec, tan, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T, d.TX, d.k, o, u, jp, \
       grad2d, f->sched, tiles
   const bool small = d.k <= kWave;
   if (mode == 1) {
-    if (small) deriv_kernel<1, 1><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
-    else deriv_kernel<1, 4><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    if (small) deriv_kernel<1, 1, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
+    else deriv_kernel<1, 4, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
   } else if (mode == 2) {
-    if (small) deriv_kernel<2, 1><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
-    else deriv_kernel<2, 4><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    if (small) deriv_kernel<2, 1, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
+    else deriv_kernel<2, 4, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
   } else {
-    if (small) deriv_kernel<3, 1><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
-    else deriv_kernel<3, 4><<<grid, kWave, 0, s>>>(LMRS_DERIV_ARGS);
+    if (small) deriv_kernel<3, 1, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
+    else deriv_kernel<3, 4, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
   }
 #undef LMRS_DERIV_ARGS
+}
+
+void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
+                  const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s) {
+  // Measured: 4 waves per tile at 26 samples per tile (100k workload) take the
+  // fused splat from 0.59 to 0.535 ms; at 13 samples (1.5M workload) 2 or 4
+  // waves are slower than one (9.24 and 9.47 against 9.13 ms), their chunk
+  // loads and per-chunk reductions being shared by too few pixel steps.
+  if (d.k >= 24) launch_deriv_w<4>(mode, f, d, o, tan, u, jp, grad2d, s);
+  else launch_deriv_w<1>(mode, f, d, o, tan, u, jp, grad2d, s);
 }
 
 void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* gram,
