@@ -73,8 +73,15 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
   if (need_bin) {
     s.bin.counts = c.take<int32_t>((size_t)d.V * d.T);
     s.bin.chunk_hist = c.take<int32_t>((size_t)d.V * bin_chunks(d.n) * d.T);
-    s.bin.keys = c.take<uint64_t>((size_t)capacity);
-    s.bin.tmp = c.take<uint64_t>((size_t)capacity);
+    s.bin.keys = c.take<uint32_t>((size_t)capacity);
+    s.bin.tmp = c.take<uint32_t>((size_t)capacity);
+    for (int q = 0; q < 2; ++q) {
+      s.bin.vkey[q] = c.take<uint32_t>((size_t)VN);
+      s.bin.vval[q] = c.take<uint32_t>((size_t)VN);
+    }
+    s.bin.rank = c.take<int32_t>((size_t)VN);
+    s.bin.order = c.take<int32_t>((size_t)VN);
+    s.bin.vcount = c.take<int32_t>((size_t)view_sort_count_ints(d.n, d.V));
   }
   if (need_tan) s.tan = c.take<float>((size_t)VN * LMRS_REC);
   if (need_grad) s.grad2d = c.take<float>((size_t)VN * 9);

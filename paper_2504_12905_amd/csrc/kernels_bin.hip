@@ -10,21 +10,24 @@
 //    and the tile total is formed.
 // 3. scan: exclusive prefix sum over the V*T totals -> tile_start (int64),
 //    total -> n_instances.
-// 4. emit: each (view, Gaussian) writes the 64-bit key (depth bits << 32 | id)
-//    into its tiles' segments at (tile start + chunk offset + LDS cursor).
-//    Depths are > znear > 0, so their IEEE bits order like the values; the id
-//    breaks ties.
-// 5. sort: one workgroup per tile sorts its segment. Segments of up to 4096
-//    keys are sorted in LDS by a bitonic network; longer ones sort 4096-key
-//    runs in LDS and then merge runs pairwise by merge path (keys are unique
-//    within a tile). The merged output is cut into windows of 2048 keys; the
-//    split of every window boundary between the two runs is found first, one
-//    binary search per thread in parallel; then each window's two input
-//    slices are loaded into LDS with coalesced reads, each thread locates its
-//    8 outputs on the merge path inside LDS and merges them, and the window
-//    is written back coalesced. Tiles near the image centre of large scenes
-//    hold hundreds of thousands of keys, so this merge (not the LDS sort)
-//    sets the time of the whole launch.
+// 4. depth ranks: one workgroup per view sorts (depth bits, Gaussian id)
+//    pairs by a stable LSD radix sort (ties keep ascending id), giving each
+//    Gaussian its depth rank in the view and the rank -> id table.
+//    Depths are > znear > 0 for every Gaussian that is emitted, so their IEEE
+//    bits order like the values (culled ones sort anywhere; they are never
+//    emitted).
+// 5. emit: each (view, Gaussian) writes its depth rank (32 bits) into its
+//    tiles' segments at (tile start + chunk offset + LDS cursor).
+// 6. sort: one workgroup per tile sorts its segment of ranks by a stable LSD
+//    radix sort (8-bit digits, as many passes as the ranks have bits) and
+//    writes ids = rank -> id of the view. Each pass counts digits per wave
+//    over the wave's quarter of the segment, turns the counts into
+//    (digit, wave) offsets, and then every wave scatters its quarter in
+//    order, 64 keys at a time, ranking equal digits within the wave from 8
+//    ballots. Ranks are unique within a view, so the order is the depth order
+//    with ties by id, and no pass is longer than the segment: the tiles of
+//    hundreds of thousands of entries near the centre of large scenes cost
+//    a few linear passes instead of a merge tree.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -32,8 +35,6 @@ namespace lmrs {
 
 namespace {
 
-constexpr int kSortThreads = 256;
-constexpr int kSortChunk = 4096;
 constexpr int kChunk = 8192;  // Gaussians per binning workgroup
 
 constexpr int kBinThreads = 1024;
@@ -103,10 +104,10 @@ __global__ __launch_bounds__(1024) void scan_kernel(int32_t* __restrict__ counts
 }
 
 __global__ __launch_bounds__(kBinThreads) void emit_kernel(const int4* __restrict__ rect,
-                                                            const float* __restrict__ rec, int n, int TX, int T,
+                                                            const int32_t* __restrict__ rank, int n, int TX, int T,
                                                             int n_chunks, const int32_t* __restrict__ chunk_hist,
                                                             const int64_t* __restrict__ tile_start,
-                                                            uint64_t* __restrict__ keys) {
+                                                            uint32_t* __restrict__ keys) {
   extern __shared__ int32_t s_cur[];
   const int chunk = blockIdx.x, v = blockIdx.y;
   const int32_t* off = chunk_hist + ((size_t)v * n_chunks + chunk) * T;
@@ -119,8 +120,7 @@ __global__ __launch_bounds__(kBinThreads) void emit_kernel(const int4* __restric
     const size_t vg = (size_t)v * n + g;
     const int4 rc = rect[vg];
     if (rc.x >= rc.z) continue;
-    const uint32_t dbits = __float_as_uint(rec[vg * LMRS_REC + 9]);
-    const uint64_t key = ((uint64_t)dbits << 32) | (uint32_t)g;
+    const uint32_t key = (uint32_t)rank[vg];
     for (int ty = rc.y; ty < rc.w; ++ty)
       for (int tx = rc.x; tx < rc.z; ++tx) {
         const int t = ty * TX + tx;
@@ -130,118 +130,236 @@ __global__ __launch_bounds__(kBinThreads) void emit_kernel(const int4* __restric
   }
 }
 
-// Bitonic sort of s[0..m) in LDS, m a power of two.
-__device__ void lds_bitonic(uint64_t* s, int m) {
-  for (int size = 2; size <= m; size <<= 1)
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < (m >> 1); i += kSortThreads) {
-        const int lo = 2 * stride * (i / stride) + (i % stride);
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint64_t x = s[lo], y = s[hi];
-        if ((x > y) == up) {
-          s[lo] = y;
-          s[hi] = x;
-        }
-      }
-      __syncthreads();
+// ------------------------------------------------------------ radix sort
+// Stable LSD radix sorts of 32-bit keys with 8-bit digits. A "part" is a
+// contiguous range of the input owned by one wave: the wave counts the
+// digits of its part, the counts of all parts become (digit, part) offsets,
+// and the wave scatters its part in order, 64 keys at a time, ranking equal
+// digits within the 64 by 8 ballots. Keys are loaded kRadixUnroll steps
+// ahead so that the loads of a wave overlap.
+constexpr int kRadixBins = 256;
+constexpr int kRadixUnroll = 8;
+
+__device__ __forceinline__ int digit_of(uint32_t key, int shift, int bins) {
+  return (int)((key >> shift) & (uint32_t)(bins - 1));
+}
+
+// Adds the digit counts of src[b0, b1) to cnt[] (LDS). One wave.
+__device__ __forceinline__ void part_count(const uint32_t* src, int64_t b0, int64_t b1, int shift, int bins,
+                                           int* cnt) {
+  const int lane = lane_id();
+  for (int64_t i0 = b0; i0 < b1; i0 += kWave * kRadixUnroll) {
+    uint32_t key[kRadixUnroll];
+#pragma unroll
+    for (int u = 0; u < kRadixUnroll; ++u) {
+      const int64_t i = i0 + u * kWave + lane;
+      key[u] = i < b1 ? src[i] : 0u;
     }
-}
-
-// Sort keys[a, a+len) of one chunk through LDS; result to dst (may equal src).
-__device__ void sort_chunk(const uint64_t* src, uint64_t* dst, int len, uint64_t* s) {
-  int m = 1;
-  while (m < len) m <<= 1;
-  for (int i = threadIdx.x; i < m; i += kSortThreads) s[i] = i < len ? src[i] : ~0ull;
-  __syncthreads();
-  lds_bitonic(s, m);
-  for (int i = threadIdx.x; i < len; i += kSortThreads) dst[i] = s[i];
-  __syncthreads();
-}
-
-constexpr int kMergeWindow = 2048;                 // merged keys per LDS window
-constexpr int kMergePer = kMergeWindow / kSortThreads;  // outputs per thread per window
-
-// Number of A keys among the first d keys of the merge of sorted A[0, na) and B[0, nb).
-__device__ __forceinline__ int64_t merge_split(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb,
-                                               int64_t d) {
-  int64_t lo = max<int64_t>(0, d - nb), hi = min(d, na);
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (A[mid] < B[d - 1 - mid]) lo = mid + 1; else hi = mid;
+#pragma unroll
+    for (int u = 0; u < kRadixUnroll; ++u)
+      if (i0 + u * kWave + lane < b1) atomicAdd(&cnt[digit_of(key[u], shift, bins)], 1);
   }
-  return lo;
 }
 
-// Merge sorted runs A[0, na) and B[0, nb) into out[0, na + nb) through LDS
-// windows. s: 2 * kMergeWindow keys of LDS (window data, then the splits).
-__device__ void merge_runs(const uint64_t* A, int64_t na, const uint64_t* B, int64_t nb, uint64_t* out,
-                           uint64_t* s) {
-  const int64_t total = na + nb;
-  const int64_t nw = (total + kMergeWindow - 1) / kMergeWindow;
-  int64_t* split = reinterpret_cast<int64_t*>(s + kMergeWindow);
-  constexpr int64_t kBatch = kMergeWindow - 1;  // windows whose boundaries fit the split array
-  for (int64_t w0 = 0; w0 < nw; w0 += kBatch) {
-    const int64_t wn = min(kBatch, nw - w0);
-    for (int64_t q = threadIdx.x; q <= wn; q += kSortThreads)
-      split[q] = merge_split(A, na, B, nb, min((w0 + q) * kMergeWindow, total));
+// Scatters src[b0, b1) (and vsrc, if given) to dst at the running cursors
+// cur[digit] (LDS, advanced here). One wave; the order within a digit is
+// the input order.
+__device__ __forceinline__ void part_scatter(const uint32_t* src, uint32_t* dst, const uint32_t* vsrc,
+                                             uint32_t* vdst, int64_t b0, int64_t b1, int shift, int bins,
+                                             int* cur) {
+  const int lane = lane_id();
+  const uint64_t below_mask = (1ull << lane) - 1ull;
+  for (int64_t i0 = b0; i0 < b1; i0 += kWave * kRadixUnroll) {
+    uint32_t key[kRadixUnroll], val[kRadixUnroll];
+#pragma unroll
+    for (int u = 0; u < kRadixUnroll; ++u) {
+      const int64_t i = i0 + u * kWave + lane;
+      key[u] = i < b1 ? src[i] : 0u;
+      val[u] = vsrc && i < b1 ? vsrc[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kRadixUnroll; ++u) {
+      if (i0 + u * kWave >= b1) break;  // wave-uniform
+      const bool valid = i0 + u * kWave + lane < b1;
+      const int dg = digit_of(key[u], shift, bins);
+      uint64_t peers = __ballot(valid);  // lanes of this step with the same digit
+      for (int bit = 1, q = 0; bit < bins; bit <<= 1, ++q) {
+        const uint64_t set = __ballot((dg >> q) & 1);
+        peers &= ((dg >> q) & 1) ? set : ~set;
+      }
+      const int before = __popcll(peers & below_mask);
+      const int base = cur[dg];
+      if (valid) {
+        dst[base + before] = key[u];
+        if (vdst) vdst[base + before] = val[u];
+        if (before == 0) cur[dg] = base + __popcll(peers);  // one lane per digit moves the cursor
+      }
+    }
+  }
+}
+
+// Exclusive scan of x over the first kRadixBins threads of the workgroup
+// (one digit each); the other threads pass 0 and get 0. wsum: LDS, 4 ints.
+__device__ __forceinline__ int bins_exclusive_scan(int x, int* wsum) {
+  const int tid = threadIdx.x, lane = lane_id();
+  int y = x;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int z = __shfl_up(y, d, kWave);
+    if (lane >= d) y += z;
+  }
+  if (tid < kRadixBins && lane == kWave - 1) wsum[tid / kWave] = y;
+  __syncthreads();
+  int run = y - x;
+  if (tid < kRadixBins)
+    for (int v = 0; v < tid / kWave; ++v) run += wsum[v];
+  __syncthreads();
+  return tid < kRadixBins ? run : 0;
+}
+
+// ---- per-view depth sort: every wave of the grid owns kViewPart keys of a view
+constexpr int kViewPart = 4096;
+constexpr int kViewThreads = 256;
+constexpr int kViewWaves = kViewThreads / kWave;
+
+__device__ __forceinline__ int view_parts(int n) { return (n + kViewPart - 1) / kViewPart; }
+
+__global__ __launch_bounds__(kViewThreads) void view_init_kernel(const float* __restrict__ rec, int n, int V,
+                                                                  uint32_t* __restrict__ key,
+                                                                  uint32_t* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * kViewThreads + threadIdx.x;
+  if (i >= (int64_t)V * n) return;
+  key[i] = __float_as_uint(rec[i * LMRS_REC + 9]);
+  val[i] = (uint32_t)(i % n);
+}
+
+// counts[v][digit][part]
+__global__ __launch_bounds__(kViewThreads) void view_count_kernel(const uint32_t* __restrict__ key, int n, int V,
+                                                                   int shift, int32_t* __restrict__ counts) {
+  __shared__ int cnt[kViewWaves][kRadixBins];
+  const int w = threadIdx.x / kWave;
+  for (int i = threadIdx.x; i < kViewWaves * kRadixBins; i += kViewThreads) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  const int np = view_parts(n);
+  const int64_t part = (int64_t)blockIdx.x * kViewWaves + w;  // over V * np
+  if (part < (int64_t)V * np) {
+    const int v = (int)(part / np), p = (int)(part % np);
+    const int64_t b0 = (int64_t)v * n + (int64_t)p * kViewPart, b1 = (int64_t)v * n + min(n, (p + 1) * kViewPart);
+    part_count(key, b0, b1, shift, kRadixBins, cnt[w]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kViewWaves * kRadixBins; i += kViewThreads) {
+    const int ww = i / kRadixBins, d = i % kRadixBins;
+    const int64_t pt = (int64_t)blockIdx.x * kViewWaves + ww;
+    if (pt < (int64_t)V * np) {
+      const int v = (int)(pt / np), p = (int)(pt % np);
+      counts[((int64_t)v * kRadixBins + d) * np + p] = cnt[ww][d];
+    }
+  }
+}
+
+// One workgroup per view: counts -> exclusive offsets in (digit, part) order,
+// relative to the view's first key.
+__global__ __launch_bounds__(1024) void view_offsets_kernel(int32_t* __restrict__ counts, int n) {
+  __shared__ int64_t part_sum[1024];
+  const int np = view_parts(n);
+  const int64_t m = (int64_t)kRadixBins * np;
+  int32_t* c = counts + (int64_t)blockIdx.x * m;
+  const int tid = threadIdx.x;
+  const int64_t per = (m + 1023) / 1024, a = tid * per, b = min(m, a + per);
+  int64_t acc = 0;
+  for (int64_t i = a; i < b; ++i) acc += c[i];
+  part_sum[tid] = acc;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int64_t y = tid >= d ? part_sum[tid - d] : 0;
     __syncthreads();
-    for (int64_t q = 0; q < wn; ++q) {
-      const int64_t d0 = (w0 + q) * kMergeWindow, d1 = min(d0 + kMergeWindow, total);
-      const int64_t a0 = split[q], a1 = split[q + 1];
-      const int la = (int)(a1 - a0), lb = (int)((d1 - d0) - la);
-      const int64_t b0 = d0 - a0;
-      for (int i = threadIdx.x; i < la; i += kSortThreads) s[i] = A[a0 + i];
-      for (int i = threadIdx.x; i < lb; i += kSortThreads) s[la + i] = B[b0 + i];
-      __syncthreads();
-      const int o0 = threadIdx.x * kMergePer, n_out = (int)(d1 - d0);
-      if (o0 < n_out) {
-        const uint64_t* sa = s;
-        const uint64_t* sb = s + la;
-        int lo = max(0, o0 - lb), hi = min(o0, la);
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (sa[mid] < sb[o0 - 1 - mid]) lo = mid + 1; else hi = mid;
-        }
-        int i = lo, j = o0 - lo;
-        const int o1 = min(o0 + kMergePer, n_out);
-        for (int o = o0; o < o1; ++o) {
-          const bool take_a = j >= lb || (i < la && sa[i] < sb[j]);
-          out[d0 + o] = take_a ? sa[i++] : sb[j++];
-        }
-      }
-      __syncthreads();
-    }
+    part_sum[tid] += y;
+    __syncthreads();
+  }
+  int64_t run = part_sum[tid] - acc;
+  for (int64_t i = a; i < b; ++i) {
+    const int32_t x = c[i];
+    c[i] = (int32_t)run;
+    run += x;
   }
 }
 
-__global__ __launch_bounds__(kSortThreads) void sort_kernel(const int64_t* __restrict__ tile_start,
-                                                            uint64_t* __restrict__ keys,
-                                                            uint64_t* __restrict__ tmp,
-                                                            int32_t* __restrict__ ids) {
-  __shared__ uint64_t s[kSortChunk];
+__global__ __launch_bounds__(kViewThreads) void view_scatter_kernel(const uint32_t* __restrict__ ksrc,
+                                                                     uint32_t* __restrict__ kdst,
+                                                                     const uint32_t* __restrict__ vsrc,
+                                                                     uint32_t* __restrict__ vdst, int n, int V,
+                                                                     int shift,
+                                                                     const int32_t* __restrict__ counts) {
+  __shared__ int cur[kViewWaves][kRadixBins];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int np = view_parts(n);
+  const int64_t part = (int64_t)blockIdx.x * kViewWaves + w;
+  if (part >= (int64_t)V * np) return;  // whole wave
+  const int v = (int)(part / np), p = (int)(part % np);
+  const int64_t vb = (int64_t)v * n;
+  for (int d = lane; d < kRadixBins; d += kWave) cur[w][d] = counts[((int64_t)v * kRadixBins + d) * np + p];
+  const int64_t b0 = vb + (int64_t)p * kViewPart, b1 = vb + min(n, (p + 1) * kViewPart);
+  part_scatter(ksrc, kdst + vb, vsrc, vdst + vb, b0, b1, shift, kRadixBins, cur[w]);
+}
+
+__global__ __launch_bounds__(kViewThreads) void view_rank_kernel(const uint32_t* __restrict__ sorted_val, int n,
+                                                                  int V, int32_t* __restrict__ rank,
+                                                                  int32_t* __restrict__ order) {
+  const int64_t i = (int64_t)blockIdx.x * kViewThreads + threadIdx.x;
+  if (i >= (int64_t)V * n) return;
+  const int64_t vb = i / n * n;
+  const uint32_t g = sorted_val[i];
+  order[i] = (int32_t)g;
+  rank[vb + g] = (int32_t)(i - vb);
+}
+
+// ---- per-tile sort of depth ranks: one workgroup per tile, wave w owns the
+// part [len w / 4, len (w + 1) / 4) of the segment
+constexpr int kTileSortThreads = 256;
+constexpr int kTileSortWaves = kTileSortThreads / kWave;
+
+__global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64_t* __restrict__ tile_start,
+                                                                     uint32_t* __restrict__ keys,
+                                                                     uint32_t* __restrict__ tmp,
+                                                                     const int32_t* __restrict__ order, int n, int T,
+                                                                     int rank_bits, int32_t* __restrict__ ids) {
+  __shared__ int cnt[kTileSortWaves][kRadixBins];
+  __shared__ int wsum[kRadixBins / kWave];
   const int64_t a = tile_start[blockIdx.x];
   const int64_t len = tile_start[blockIdx.x + 1] - a;
   if (len == 0) return;
-  uint64_t* src = keys + a;
-  uint64_t* dst = tmp + a;
-  if (len <= kSortChunk) {
-    sort_chunk(src, src, (int)len, s);
-  } else {
-    for (int64_t c = 0; c < len; c += kSortChunk)
-      sort_chunk(src + c, src + c, (int)min<int64_t>(kSortChunk, len - c), s);
-    for (int64_t run = kSortChunk; run < len; run <<= 1) {
-      for (int64_t base = 0; base < len; base += 2 * run) {
-        const int64_t na = min(run, len - base);
-        const int64_t nb = max<int64_t>(0, min(run, len - base - run));
-        merge_runs(src + base, na, src + base + na, nb, dst + base, s);
-      }
-      uint64_t* t = src;
-      src = dst;
-      dst = t;
+  const int tid = threadIdx.x, w = tid / kWave;
+  uint32_t* src = keys + a;
+  uint32_t* dst = tmp + a;
+  const int64_t b0 = len * w / kTileSortWaves, b1 = len * (w + 1) / kTileSortWaves;
+  for (int shift = 0; shift < rank_bits; shift += 8) {
+    const int bins = 1 << min(8, rank_bits - shift);
+    for (int i = tid; i < kTileSortWaves * kRadixBins; i += kTileSortThreads) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    part_count(src, b0, b1, shift, bins, cnt[w]);
+    __syncthreads();
+    int c[kTileSortWaves], tot = 0;
+#pragma unroll
+    for (int v = 0; v < kTileSortWaves; ++v) {
+      c[v] = cnt[v][tid];
+      tot += c[v];
     }
+    int run = bins_exclusive_scan(tot, wsum);
+#pragma unroll
+    for (int v = 0; v < kTileSortWaves; ++v) {
+      cnt[v][tid] = run;
+      run += c[v];
+    }
+    __syncthreads();
+    part_scatter(src, dst, nullptr, nullptr, b0, b1, shift, bins, cnt[w]);
+    __syncthreads();
+    uint32_t* t = src;
+    src = dst;
+    dst = t;
   }
-  for (int64_t i = threadIdx.x; i < len; i += kSortThreads) ids[a + i] = (int32_t)(src[i] & 0xffffffffu);
+  const int32_t* ord = order + (size_t)(blockIdx.x / T) * n;
+  for (int64_t i = tid; i < len; i += kTileSortThreads) ids[a + i] = ord[src[i]];
 }
 
 }  // namespace
@@ -259,12 +377,30 @@ void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hip
 }
 
 void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
+  // depth ranks per view: four 8-bit passes over the FP32 depth bits
+  const int64_t vn = (int64_t)d.V * d.n;
+  const int np = (d.n + kViewPart - 1) / kViewPart;
+  const unsigned vblocks = (unsigned)((vn + kViewThreads - 1) / kViewThreads);
+  const unsigned pblocks = (unsigned)(((int64_t)d.V * np + kViewWaves - 1) / kViewWaves);
+  view_init_kernel<<<vblocks, kViewThreads, 0, s>>>(f->rec, d.n, d.V, b.vkey[0], b.vval[0]);
+  for (int pass = 0; pass < 4; ++pass) {
+    const int q = pass & 1;
+    view_count_kernel<<<pblocks, kViewThreads, 0, s>>>(b.vkey[q], d.n, d.V, 8 * pass, b.vcount);
+    view_offsets_kernel<<<d.V, 1024, 0, s>>>(b.vcount, d.n);
+    view_scatter_kernel<<<pblocks, kViewThreads, 0, s>>>(b.vkey[q], b.vkey[q ^ 1], b.vval[q], b.vval[q ^ 1], d.n,
+                                                          d.V, 8 * pass, b.vcount);
+  }
+  view_rank_kernel<<<vblocks, kViewThreads, 0, s>>>(b.vval[0], d.n, d.V, b.rank, b.order);
+
   const int nc = bin_chunks(d.n);
   const size_t lds = (size_t)d.T * sizeof(int32_t);
-  emit_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), f->rec, d.n, d.TX,
+  emit_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), b.rank, d.n, d.TX,
                                                       d.T, nc, b.chunk_hist, f->tile_start, b.keys);
-  sort_kernel<<<(unsigned)((int64_t)d.V * d.T), kSortThreads, 0, s>>>(f->tile_start, b.keys, b.tmp,
-                                                                     f->ids);
+  const int rank_bits = d.n > 1 ? 32 - __builtin_clz((unsigned)(d.n - 1)) : 0;
+  tile_sort_kernel<<<(unsigned)((int64_t)d.V * d.T), kTileSortThreads, 0, s>>>(f->tile_start, b.keys, b.tmp,
+                                                                              b.order, d.n, d.T, rank_bits, f->ids);
 }
+
+int view_sort_count_ints(int n, int V) { return V * ((n + kViewPart - 1) / kViewPart) * kRadixBins; }
 
 }  // namespace lmrs

@@ -54,8 +54,9 @@ def test_one_sample_per_tile():
     check_all("cfg0-k1", w.n, 0, w.beta_init, w.cams, w.width, w.height, 1, pix, wts)
 
 
-def test_long_tile_list_merge_path():
-    # 6000 small Gaussians in front of one tile: the tile list exceeds the 4096-key LDS sort chunk
+def test_long_tile_list():
+    # 6000 small Gaussians in front of one tile: a long list, sorted by several radix passes whose
+    # four wave parts each hold 1,500 entries
     rng = np.random.default_rng(7)
     n, f = 6000, 120.0
     zc = rng.uniform(2.0, 4.0, n)                 # camera depth
@@ -78,18 +79,18 @@ def _one_tile_cloud(n, seed, f=120.0, W=64):
     return n, beta, axis_camera(f, W, W)
 
 
-def test_list_of_three_sort_chunks():
-    """12,000 entries in one tile: three 4096-key runs, so the first merge pass
-    has a run without a partner and the second merges 8192 + 3808 keys."""
+def test_list_of_twelve_thousand():
+    """12,000 entries in one tile (14-bit depth ranks: two radix passes, the
+    second on 6-bit digits)."""
     n, beta, cams = _one_tile_cloud(12000, 8)
     fr, orc = check_all("three-chunk list", n, 0, beta, cams, 64, 64)
     assert np.diff(np_(fr.tile_start)).max() == 12000
 
 
 def test_four_million_entry_tile_lists():
-    """4.2 M entries in one tile: each merge pass covers more than 2,047 windows
-    of 2,048 keys, so the window splits are found in several batches. Lists
-    only (bit-exact against the oracle)."""
+    """4.2 M entries in one tile: a 4.2M-Gaussian view sort and 23-bit depth
+    ranks (three radix passes of a 4.2M-entry segment). Lists only (bit-exact
+    against the oracle)."""
     n, beta, cams = _one_tile_cloud(4_200_000, 9)
     log("[edge] 4.2M-entry tile")
     fr = gpu_frame(n, 0, beta, cams, 64, 64, render=False)
@@ -98,6 +99,21 @@ def test_four_million_entry_tile_lists():
     ots, oids = orc.lists()
     assert np.diff(ots).max() == n
     assert compare_lists(gts, gids, ots, oids, orc.projection()["margin"], orc.T) == 0
+
+
+def test_equal_depths_keep_id_order():
+    """Gaussians at exactly the same depth (identical FP32 depth keys): the
+    lists order them by ascending id (the stable view sort keeps id order)."""
+    rng = np.random.default_rng(11)
+    n, f = 300, 120.0
+    u, v = rng.uniform(35.0, 45.0, n), rng.uniform(35.0, 45.0, n)
+    zc = np.where(np.arange(n) % 3 == 0, 2.5, 3.25)  # two depth classes, each shared by many Gaussians
+    mu = np.stack([(u - 32.0) * zc / f, (v - 32.0) * zc / f, zc - 3.0], 1)
+    n, beta = one_gaussian_scene(mu, [math.log(0.004)] * 3, [1, 0, 0, 0], -1.0, [0.3, 0.6, 0.9])
+    fr, orc = check_all("equal depths", n, 0, beta, axis_camera(f, 64, 64), 64, 64)
+    rec = np_(fr.rec)[0]
+    vis = np_(fr.rect)[0][:, 0] < np_(fr.rect)[0][:, 2]
+    assert len(np.unique(rec[vis, 9].view(np.uint32))) == 2
 
 
 def test_maximum_tiles_per_view():
