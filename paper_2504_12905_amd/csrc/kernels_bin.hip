@@ -315,9 +315,12 @@ __global__ __launch_bounds__(kViewThreads) void view_rank_kernel(const uint32_t*
 }
 
 // ---- per-tile sort of depth ranks: one workgroup per tile, wave w owns the
-// part [len w / 4, len (w + 1) / 4) of the segment
+// part [len w / 4, len (w + 1) / 4) of the segment. Segments of up to
+// kTileSortLds keys are sorted in LDS (one coalesced load and store), longer
+// ones pass through the keys / tmp buffers in global memory.
 constexpr int kTileSortThreads = 256;
 constexpr int kTileSortWaves = kTileSortThreads / kWave;
+constexpr int kTileSortLds = 4096;
 
 __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64_t* __restrict__ tile_start,
                                                                      uint32_t* __restrict__ keys,
@@ -326,12 +329,20 @@ __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64
                                                                      int rank_bits, int32_t* __restrict__ ids) {
   __shared__ int cnt[kTileSortWaves][kRadixBins];
   __shared__ int wsum[kRadixBins / kWave];
+  __shared__ uint32_t buf[2][kTileSortLds];
   const int64_t a = tile_start[blockIdx.x];
   const int64_t len = tile_start[blockIdx.x + 1] - a;
   if (len == 0) return;
   const int tid = threadIdx.x, w = tid / kWave;
+  const bool in_lds = len <= kTileSortLds;
   uint32_t* src = keys + a;
   uint32_t* dst = tmp + a;
+  if (in_lds) {
+    for (int i = tid; i < len; i += kTileSortThreads) buf[0][i] = src[i];
+    src = buf[0];
+    dst = buf[1];
+    __syncthreads();
+  }
   const int64_t b0 = len * w / kTileSortWaves, b1 = len * (w + 1) / kTileSortWaves;
   for (int shift = 0; shift < rank_bits; shift += 8) {
     const int bins = 1 << min(8, rank_bits - shift);
