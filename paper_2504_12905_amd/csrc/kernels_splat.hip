@@ -342,6 +342,49 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
 }
 
 // ----------------------------------------------------- J p, J^T u, fused GN
+// One forward step: pixel (xc, yc) (transmittance Tc and its tangent dTc in
+// front of the chunk, last blended entry lj) against the chunk's entries, one
+// per lane. cr/cg/cb: this lane's entry's term of the colour tangent; tp / tq:
+// the chunk's transmittance product and the sum of its tangent ratios.
+struct FwdStep {
+  float cr, cg, cb, Tc, dTc, tp, tq;
+};
+
+__device__ __forceinline__ FwdStep fwd_step(const RecF& r, const RecF& dr, int e, bool valid, int lj, float xc,
+                                            float yc, float Tc, float dTc, const lmrs_render_opts& o) {
+  const Alpha al = pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, xc, yc, o);
+  const bool inc = valid && e <= lj && al.inc;
+  float a = 0.f, da = 0.f;
+  if (inc) {
+    a = al.a;
+    if (!al.capped) {
+      const float ds = -al.q1 * (dr.f11 * al.dx + dr.f12 * al.dy + r.f11 * dr.u + r.f12 * dr.v) -
+                       al.q2 * (dr.f22 * al.dy + r.f22 * dr.v);
+      da = al.es * (dr.o + r.o * ds);
+    }
+  }
+  const float lg = log2_om(inc, a);
+  const float q = inc ? -da * __builtin_amdgcn_rcpf(1.f - a) : 0.f;
+  const float Linc = scan_add(lg);
+  const float Qinc = scan_add(q);
+  const float pin = __builtin_amdgcn_exp2f(Linc - lg);  // product of (1 - alpha) in front, within the chunk
+  const float Tn = Tc * pin;
+  const float dTn = pin * (dTc + Tc * (Qinc - q));
+  FwdStep st;
+  st.cr = st.cg = st.cb = 0.f;
+  if (inc) {
+    const float aT = a * Tn, gT = da * Tn + a * dTn;
+    st.cr = dr.r * aT + r.r * gT;
+    st.cg = dr.g * aT + r.g * gT;
+    st.cb = dr.b * aT + r.b * gT;
+  }
+  st.Tc = Tc;
+  st.dTc = dTc;
+  st.tp = __builtin_amdgcn_exp2f(readlane(Linc, kWave - 1));
+  st.tq = readlane(Qinc, kWave - 1);
+  return st;
+}
+
 // MODE 1: jp = J p.  MODE 2: grad2d += J^T u.  MODE 3: grad2d += J^T W J p.
 template <int MODE, int NS, int W>
 __device__ __forceinline__ void deriv_tile(
@@ -372,6 +415,15 @@ __device__ __forceinline__ void deriv_tile(
       sa[s] = 1.f;
       sb[s] = su0[s] = su1[s] = su2[s] = 0.f;
     }
+    // With up to 32 samples per tile and several waves per tile, each lane
+    // keeps its entry's colour-tangent contribution to each of the wave's
+    // pixels in registers (acc[m] for the wave's pixel m) and the wave sums
+    // them once after the walk, instead of three wave sums per step.
+    constexpr int MP = W > 1 && NS == 1 ? 32 / W : 1;
+    const bool acc_path = MP > 1 && k <= 32;
+    float A0[MP], A1[MP], A2[MP];
+#pragma unroll
+    for (int m = 0; m < MP; ++m) A0[m] = A1[m] = A2[m] = 0.f;
     for (int c0 = 0; c0 <= lmax_own; c0 += kWave) {
       const int e = c0 + lane;
       const bool valid = e < c.len;
@@ -381,49 +433,47 @@ __device__ __forceinline__ void deriv_tile(
         r = load_rec(rec, vg);
         dr = load_rec(tan, vg);
       }
+      if (acc_path) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int cnt = min(kWave, k - s * kWave);
-        for (int l = wv; l < cnt; l += W) {
-          const int lj = readlane(pr.last[s], l);
+        for (int m = 0; m < MP; ++m) {
+          const int l = wv + m * W;
+          if (l >= k) break;
+          const int lj = readlane(pr.last[0], l);
           if (c0 > lj) continue;
-          const Alpha al =
-              pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
-          const bool inc = valid && e <= lj && al.inc;
-          float a = 0.f, da = 0.f;
-          if (inc) {
-            a = al.a;
-            if (!al.capped) {
-              const float ds = -al.q1 * (dr.f11 * al.dx + dr.f12 * al.dy + r.f11 * dr.u + r.f12 * dr.v) -
-                               al.q2 * (dr.f22 * al.dy + r.f22 * dr.v);
-              da = al.es * (dr.o + r.o * ds);
-            }
-          }
-          const float lg = log2_om(inc, a);
-          const float q = inc ? -da * __builtin_amdgcn_rcpf(1.f - a) : 0.f;
-          const float Linc = scan_add(lg);
-          const float Qinc = scan_add(q);
-          const float Tc = readlane(sa[s], l), dTc = readlane(sb[s], l);
-          const float pin = __builtin_amdgcn_exp2f(Linc - lg);  // product of (1 - alpha) in front, within the chunk
-          const float Tn = Tc * pin;
-          const float dTn = pin * (dTc + Tc * (Qinc - q));
-          float cr = 0.f, cg = 0.f, cb = 0.f;
-          if (inc) {
-            const float aT = a * Tn, gT = da * Tn + a * dTn;
-            cr = dr.r * aT + r.r * gT;
-            cg = dr.g * aT + r.g * gT;
-            cb = dr.b * aT + r.b * gT;
-          }
-          cr = wave_total(cr);
-          cg = wave_total(cg);
-          cb = wave_total(cb);
-          const float tp = __builtin_amdgcn_exp2f(readlane(Linc, kWave - 1)), tq = readlane(Qinc, kWave - 1);
-          su0[s] = writelane(su0[s], readlane(su0[s], l) + cr, l);
-          su1[s] = writelane(su1[s], readlane(su1[s], l) + cg, l);
-          su2[s] = writelane(su2[s], readlane(su2[s], l) + cb, l);
-          sa[s] = writelane(sa[s], Tc * tp, l);
-          sb[s] = writelane(sb[s], tp * (dTc + Tc * tq), l);
+          const FwdStep st = fwd_step(r, dr, e, valid, lj, readlane(pr.xc[0], l), readlane(pr.yc[0], l),
+                                      readlane(sa[0], l), readlane(sb[0], l), o);
+          A0[m] += st.cr;
+          A1[m] += st.cg;
+          A2[m] += st.cb;
+          sa[0] = writelane(sa[0], st.Tc * st.tp, l);
+          sb[0] = writelane(sb[0], st.tp * (st.dTc + st.Tc * st.tq), l);
         }
+      } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int cnt = min(kWave, k - s * kWave);
+          for (int l = wv; l < cnt; l += W) {
+            const int lj = readlane(pr.last[s], l);
+            if (c0 > lj) continue;
+            const FwdStep st = fwd_step(r, dr, e, valid, lj, readlane(pr.xc[s], l), readlane(pr.yc[s], l),
+                                        readlane(sa[s], l), readlane(sb[s], l), o);
+            su0[s] = writelane(su0[s], readlane(su0[s], l) + wave_total(st.cr), l);
+            su1[s] = writelane(su1[s], readlane(su1[s], l) + wave_total(st.cg), l);
+            su2[s] = writelane(su2[s], readlane(su2[s], l) + wave_total(st.cb), l);
+            sa[s] = writelane(sa[s], st.Tc * st.tp, l);
+            sb[s] = writelane(sb[s], st.tp * (st.dTc + st.Tc * st.tq), l);
+          }
+        }
+      }
+    }
+    if (acc_path) {
+#pragma unroll
+      for (int m = 0; m < MP; ++m) {
+        const int l = wv + m * W;
+        if (l >= k) break;
+        su0[0] = writelane(su0[0], wave_total(A0[m]), l);
+        su1[0] = writelane(su1[0], wave_total(A1[m]), l);
+        su2[0] = writelane(su2[0], wave_total(A2[m]), l);
       }
     }
 #pragma unroll
