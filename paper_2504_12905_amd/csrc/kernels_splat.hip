@@ -352,32 +352,26 @@ struct FwdStep {
 
 __device__ __forceinline__ FwdStep fwd_step(const RecF& r, const RecF& dr, int e, bool valid, int lj, float xc,
                                             float yc, float Tc, float dTc, const lmrs_render_opts& o) {
+  // written with selects only (no per-lane branches), so that the steps of
+  // several pixels can share one basic block
   const Alpha al = pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, xc, yc, o);
   const bool inc = valid && e <= lj && al.inc;
-  float a = 0.f, da = 0.f;
-  if (inc) {
-    a = al.a;
-    if (!al.capped) {
-      const float ds = -al.q1 * (dr.f11 * al.dx + dr.f12 * al.dy + r.f11 * dr.u + r.f12 * dr.v) -
-                       al.q2 * (dr.f22 * al.dy + r.f22 * dr.v);
-      da = al.es * (dr.o + r.o * ds);
-    }
-  }
-  const float lg = log2_om(inc, a);
+  const float a = inc ? al.a : 0.f;
+  const float ds = -al.q1 * (dr.f11 * al.dx + dr.f12 * al.dy + r.f11 * dr.u + r.f12 * dr.v) -
+                   al.q2 * (dr.f22 * al.dy + r.f22 * dr.v);
+  const float da = inc && !al.capped ? al.es * (dr.o + r.o * ds) : 0.f;
+  const float lg = inc ? __log2f(1.f - a) : 0.f;
   const float q = inc ? -da * __builtin_amdgcn_rcpf(1.f - a) : 0.f;
   const float Linc = scan_add(lg);
   const float Qinc = scan_add(q);
   const float pin = __builtin_amdgcn_exp2f(Linc - lg);  // product of (1 - alpha) in front, within the chunk
   const float Tn = Tc * pin;
   const float dTn = pin * (dTc + Tc * (Qinc - q));
+  const float aT = a * Tn, gT = da * Tn + a * dTn;
   FwdStep st;
-  st.cr = st.cg = st.cb = 0.f;
-  if (inc) {
-    const float aT = a * Tn, gT = da * Tn + a * dTn;
-    st.cr = dr.r * aT + r.r * gT;
-    st.cg = dr.g * aT + r.g * gT;
-    st.cb = dr.b * aT + r.b * gT;
-  }
+  st.cr = inc ? dr.r * aT + r.r * gT : 0.f;
+  st.cg = inc ? dr.g * aT + r.g * gT : 0.f;
+  st.cb = inc ? dr.b * aT + r.b * gT : 0.f;
   st.Tc = Tc;
   st.dTc = dTc;
   st.tp = __builtin_amdgcn_exp2f(readlane(Linc, kWave - 1));
@@ -436,10 +430,12 @@ __device__ __forceinline__ void deriv_tile(
       if (acc_path) {
 #pragma unroll
         for (int m = 0; m < MP; ++m) {
+          // no branches: for a pixel past its last entry (or a slot past k,
+          // whose last is -1) the step adds nothing and leaves T and its
+          // tangent as they are, and the steps of the wave's pixels form
+          // one block that the compiler can interleave
           const int l = wv + m * W;
-          if (l >= k) break;
           const int lj = readlane(pr.last[0], l);
-          if (c0 > lj) continue;
           const FwdStep st = fwd_step(r, dr, e, valid, lj, readlane(pr.xc[0], l), readlane(pr.yc[0], l),
                                       readlane(sa[0], l), readlane(sb[0], l), o);
           A0[m] += st.cr;
