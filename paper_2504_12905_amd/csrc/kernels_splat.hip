@@ -74,6 +74,30 @@ __device__ __forceinline__ RecF load_rec(const float* rec, size_t vg) {
   return RecF{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
 }
 
+// List id at entry c0 + lane of the tile, -1 past the end of the list.
+__device__ __forceinline__ int fwd_chunk_id(const int32_t* ids, const TileCtx& c, int c0) {
+  const int e = c0 + lane_id();
+  return e < c.len ? ids[c.start + e] : -1;
+}
+
+// List id at entry c0 + 63 - lane of the tile (the reverse walk's lane
+// order), -1 past the end of the list.
+__device__ __forceinline__ int rev_chunk_id(const int32_t* ids, const TileCtx& c, int c0) {
+  const int e = c0 + kWave - 1 - lane_id();
+  return e < c.len ? ids[c.start + e] : -1;
+}
+
+// Makes the wave wait here until the loads into these registers (prefetched
+// for the next chunk) have landed. The reverse walk places it before the
+// chunk's gradient atomics: one counter orders all vector memory operations
+// of a wave, so a wait for those loads at the top of the next chunk would
+// also wait for the atomics issued in between.
+__device__ __forceinline__ void landed(const RecF& r) {
+  asm volatile("" ::"v"(r.u), "v"(r.v), "v"(r.f11), "v"(r.f12), "v"(r.f22), "v"(r.o), "v"(r.r), "v"(r.g),
+               "v"(r.b));
+}
+__device__ __forceinline__ void landed(int x) { asm volatile("" ::"v"(x)); }
+
 // Pixel 64 s + l of a tile lives in slot s of lane l.
 template <int NS>
 struct PixelRegs {
@@ -418,15 +442,28 @@ __device__ __forceinline__ void deriv_tile(
     float A0[MP], A1[MP], A2[MP];
 #pragma unroll
     for (int m = 0; m < MP; ++m) A0[m] = A1[m] = A2[m] = 0.f;
+    // the next chunk's records and tangents and the list ids of the one
+    // after load while a chunk is walked
+    RecF rn{}, drn{};
+    {
+      const int id0 = fwd_chunk_id(ids, c, 0);
+      if (lmax_own >= 0 && id0 >= 0) {
+        rn = load_rec(rec, (size_t)c.v * n + id0);
+        drn = load_rec(tan, (size_t)c.v * n + id0);
+      }
+    }
+    int idn = lmax_own >= kWave ? fwd_chunk_id(ids, c, kWave) : -1;
     for (int c0 = 0; c0 <= lmax_own; c0 += kWave) {
       const int e = c0 + lane;
       const bool valid = e < c.len;
-      RecF r{}, dr{};
-      if (valid) {
-        const size_t vg = (size_t)c.v * n + ids[c.start + e];
-        r = load_rec(rec, vg);
-        dr = load_rec(tan, vg);
+      const RecF r = rn, dr = drn;
+      rn = RecF{};
+      drn = RecF{};
+      if (idn >= 0) {
+        rn = load_rec(rec, (size_t)c.v * n + idn);
+        drn = load_rec(tan, (size_t)c.v * n + idn);
       }
+      idn = c0 + 2 * kWave <= lmax_own ? fwd_chunk_id(ids, c, c0 + 2 * kWave) : -1;
       if (acc_path) {
 #pragma unroll
         for (int m = 0; m < MP; ++m) {
@@ -511,15 +548,24 @@ __device__ __forceinline__ void deriv_tile(
     }
     if (lmax < 0) return;  // the same for every wave of the workgroup
     int chunk = 0;
-    for (int c0 = (lmax / kWave) * kWave; c0 >= 0; c0 -= kWave) {
-      const int e = c0 + (kWave - 1 - lane);  // reversed: lane 0 holds the chunk's deepest entry
+    // reversed: lane 0 holds the chunk's deepest entry. The next chunk's
+    // records and the list ids of the one after load while a chunk is walked.
+    const int ctop = (lmax / kWave) * kWave;
+    int idc = rev_chunk_id(ids, c, ctop);
+    RecF rn{};
+    if (idc >= 0) rn = load_rec(rec, (size_t)c.v * n + idc);
+    int idn = ctop >= kWave ? rev_chunk_id(ids, c, ctop - kWave) : -1;
+    landed(rn);  // so that no path reaches the loop head with a load pending
+    landed(idn);
+    for (int c0 = ctop; c0 >= 0; c0 -= kWave) {
+      const int e = c0 + (kWave - 1 - lane);
       const bool valid = e < c.len;
-      RecF r{};
-      int id = 0;
-      if (valid) {
-        id = ids[c.start + e];
-        r = load_rec(rec, (size_t)c.v * n + id);
-      }
+      const RecF r = rn;
+      const int id = max(idc, 0);
+      rn = RecF{};
+      if (idn >= 0) rn = load_rec(rec, (size_t)c.v * n + idn);
+      idc = idn;
+      idn = c0 >= 2 * kWave ? rev_chunk_id(ids, c, c0 - 2 * kWave) : -1;
       float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
@@ -567,6 +613,8 @@ __device__ __forceinline__ void deriv_tile(
       float* buf = red + (chunk & 1) * (W * 9 * kWave);
 #pragma unroll
       for (int q = 0; q < 9; ++q) buf[(wv * 9 + q) * kWave + lane] = g[q];
+      landed(rn);
+      landed(idn);
       __syncthreads();
       for (int q = wv; q < 9; q += W) {
         float sum = 0.f;
