@@ -159,12 +159,14 @@ lmrs_status check_deriv_state(const lmrs_frame* f) {
   } while (0)
 
 // J^T W J p + lambda d p into out (tangent, fused splat, chain).
+// pu_part (optional): partials of p . out for the PCG update.
 void gn_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* p,
-                 float lambda, const float* dvec, float* out, const Scratch& s, hipStream_t st) {
+                 float lambda, const float* dvec, float* out, const Scratch& s, hipStream_t st,
+                 double* pu_part = nullptr) {
   launch_tangent(f, d, o, p, s.tan, st);
   launch_fill(s.grad2d, (int64_t)d.V * d.n * 9, 0.f, st);
   launch_deriv(3, f, d, o, s.tan, nullptr, nullptr, s.grad2d, st);
-  launch_chain_vjp(f, d, o, s.grad2d, p, lambda, dvec, out, st);
+  launch_chain_vjp(f, d, o, s.grad2d, p, lambda, dvec, out, st, pu_part);
 }
 
 void vjp_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* u,
@@ -200,8 +202,8 @@ void pcg_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opt
   PcgState ps{x, s.r, s.z, s.p, s.u, s.minv, s.sc, s.red};
   launch_pcg_init(b, s.diag, lambda, dvec, P, ps, st);
   for (int it = 0; it < iters; ++it) {
-    gn_sequence(f, d, o, s.p, lambda, dvec, s.u, s, st);
-    launch_pcg_iteration(it, P, ps, st);
+    gn_sequence(f, d, o, s.p, lambda, dvec, s.u, s, st, ps.partials);
+    launch_pcg_iteration(it, P, chain_vjp_blocks(d.n, true), ps, st);
   }
   if (report) launch_pcg_report(b, iters, P, ps, report, st);
 }

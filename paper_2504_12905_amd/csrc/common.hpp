@@ -457,6 +457,20 @@ __device__ __forceinline__ float wave_max_f(float x) {
   return x;
 }
 
+// Sum of x over a workgroup of 256 threads in a fixed order (deterministic);
+// s_red: 256 doubles of LDS. Every thread of the workgroup must call it.
+__device__ __forceinline__ double block_sum(double x, double* s_red) {
+  s_red[threadIdx.x] = x;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) s_red[threadIdx.x] += s_red[threadIdx.x + d];
+    __syncthreads();
+  }
+  const double r = s_red[0];
+  __syncthreads();
+  return r;
+}
+
 // Upper-triangle index of (i, j), i <= j < 5, in a 5x5 symmetric block.
 __host__ __device__ constexpr int sym5(int i, int j) { return i * 5 - i * (i - 1) / 2 + (j - i); }
 

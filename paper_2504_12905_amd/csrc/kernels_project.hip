@@ -6,6 +6,8 @@
 // component-major so consecutive lanes read consecutive words. Records are
 // [V][n][12] floats (three float4) so the splat kernels gather one record
 // with three 16-byte loads.
+#include <algorithm>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -91,37 +93,51 @@ __global__ __launch_bounds__(kBlock) void tangent_kernel(const float* __restrict
   out[2] = make_float4(r[8].d, 0.f, 0.f, 0.f);
 }
 
-// out[beta_g] = sum_v (d rec_vg / d beta_g)^T grad2d[v][:][g]  (+ lambda d p)
+// out[beta_g] = sum_v (d rec_vg / d beta_g)^T grad2d[v][:][g]  (+ lambda d p).
+// With pu_part, each workgroup also leaves its partial sum of p . out in
+// pu_part[blockIdx.x] (FP64; the PCG update reduces them), which saves the
+// operator product's separate pass over p and u.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
     const float* __restrict__ beta, int n, int V, const lmrs_camera* __restrict__ cams,
     const int32_t* __restrict__ view_ids, float lowpass, const float* __restrict__ grad2d,
-    const float* __restrict__ p, float lambda, const float* __restrict__ dvec, float* __restrict__ out) {
+    const float* __restrict__ p, float lambda, const float* __restrict__ dvec, float* __restrict__ out,
+    double* __restrict__ pu_part) {
   constexpr int PG = ShDims<DEG>::PG;
-  const int g = blockIdx.x * kBlock + threadIdx.x;
-  if (g >= n) return;
-  float prm[PG], gp[PG];
-  load_params<PG>(beta, n, g, prm);
+  double pu = 0.0;
+  for (int g = blockIdx.x * kBlock + threadIdx.x; g < n; g += gridDim.x * kBlock) {
+    float prm[PG], gp[PG];
+    load_params<PG>(beta, n, g, prm);
 #pragma unroll
-  for (int j = 0; j < PG; ++j) gp[j] = 0.f;
-  for (int v = 0; v < V; ++v) {
-    float gr[9];
-    bool any = false;
+    for (int j = 0; j < PG; ++j) gp[j] = 0.f;
+    for (int v = 0; v < V; ++v) {
+      float gr[9];
+      bool any = false;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      gr[q] = grad2d[((size_t)v * 9 + q) * n + g];
-      any |= gr[q] != 0.f;
+      for (int q = 0; q < 9; ++q) {
+        gr[q] = grad2d[((size_t)v * 9 + q) * n + g];
+        any |= gr[q] != 0.f;
+      }
+      if (!any) continue;
+      const CamView cv = load_cam(cams, view_ids, v);
+      proj_vjp<DEG>(prm, cv, lowpass, gr, gp);
     }
-    if (!any) continue;
-    const CamView cv = load_cam(cams, view_ids, v);
-    proj_vjp<DEG>(prm, cv, lowpass, gr, gp);
-  }
 #pragma unroll
-  for (int j = 0; j < PG; ++j) {
-    const size_t idx = (size_t)j * n + g;
-    float val = gp[j];
-    if (p) val += lambda * (dvec ? dvec[idx] : 1.f) * p[idx];
-    out[idx] = val;
+    for (int j = 0; j < PG; ++j) {
+      const size_t idx = (size_t)j * n + g;
+      float val = gp[j];
+      if (p) {
+        const float pj = p[idx];
+        val += lambda * (dvec ? dvec[idx] : 1.f) * pj;
+        pu += (double)pj * (double)val;
+      }
+      out[idx] = val;
+    }
+  }
+  if (pu_part) {
+    __shared__ double s_red[kBlock];
+    const double r = block_sum(pu, s_red);
+    if (threadIdx.x == 0) pu_part[blockIdx.x] = r;
   }
 }
 
@@ -232,15 +248,20 @@ void launch_tangent(const lmrs_frame* f, const FrameDims& d, const lmrs_render_o
   }
 }
 
+int chain_vjp_blocks(int n, bool partials) {
+  const int blocks = (n + kBlock - 1) / kBlock;
+  return partials ? std::min(blocks, kRedBlocks) : blocks;
+}
+
 void launch_chain_vjp(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                       const float* grad2d, const float* p, float lambda, const float* dvec, float* out,
-                      hipStream_t s) {
-  const unsigned grid = (d.n + kBlock - 1) / kBlock;
+                      hipStream_t s, double* pu_part) {
+  const unsigned grid = (unsigned)chain_vjp_blocks(d.n, pu_part != nullptr);
   switch (d.deg) {
-    case 0: chain_vjp_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out); break;
-    case 1: chain_vjp_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out); break;
-    case 2: chain_vjp_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out); break;
-    default: chain_vjp_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out); break;
+    case 0: chain_vjp_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part); break;
+    case 1: chain_vjp_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part); break;
+    case 2: chain_vjp_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part); break;
+    default: chain_vjp_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part); break;
   }
 }
 

@@ -151,17 +151,6 @@ __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__
   if (threadIdx.x == 0) partials[blockIdx.x] = s_red[0];
 }
 
-__device__ __forceinline__ double block_sum(double x, double* s_red) {
-  s_red[threadIdx.x] = x;
-  __syncthreads();
-  for (int d = 128; d > 0; d >>= 1) {
-    if ((int)threadIdx.x < d) s_red[threadIdx.x] += s_red[threadIdx.x + d];
-    __syncthreads();
-  }
-  const double r = s_red[0];
-  __syncthreads();
-  return r;
-}
 
 __global__ __launch_bounds__(256) void dot_partial_kernel(const float* __restrict__ a,
                                                           const float* __restrict__ b, int64_t n,
@@ -262,16 +251,17 @@ __global__ __launch_bounds__(256) void pcg_init_scalars_kernel(const double* __r
 // Iteration i reads the scalar bank cur and pcg_dir_kernel writes the bank
 // of iteration i + 1, so no kernel reads a slot that it writes.
 // alpha = r^T z / p^T u (0 once stopped); x += alpha p; r -= alpha u; z = M^-1 r.
-// p^T u comes from dot_partial_kernel's partials (reduced in every block).
+// p^T u comes from the partials that the GN product's chain kernel leaves
+// (pu_count of them, reduced in every block).
 __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t P, double* __restrict__ cur,
-                                                         const double* __restrict__ pu_partials,
+                                                         const double* __restrict__ pu_partials, int pu_count,
                                                          float* __restrict__ x, float* __restrict__ r,
                                                          float* __restrict__ z, const float* __restrict__ p,
                                                          const float* __restrict__ u,
                                                          const float* __restrict__ minv,
                                                          double* __restrict__ partials) {
   __shared__ double s_red[256];
-  const double pu = reduce_partials(pu_partials, kRedBlocks, s_red);
+  const double pu = reduce_partials(pu_partials, pu_count, s_red);
   const double rz = cur[kRZ];
   const bool go = cur[kStop] == 0.0 && pu > 0.0 && rz > 1e-30 * cur[kRZ0];
   if (blockIdx.x == 0 && threadIdx.x == 0) cur[kPU] = pu;
@@ -422,11 +412,10 @@ void launch_pcg_init(const float* b, const float* diag, float lambda, const floa
   pcg_init_scalars_kernel<<<1, 256, 0, s>>>(st.partials, st.bank(0));
 }
 
-void launch_pcg_iteration(int it, int64_t P, PcgState st, hipStream_t s) {
+void launch_pcg_iteration(int it, int64_t P, int pu_count, PcgState st, hipStream_t s) {
   double* cur = st.bank(it);
-  dot_partial_kernel<<<kRedBlocks, 256, 0, s>>>(st.p, st.u, P, st.partials);
-  pcg_update_kernel<<<kRedBlocks, 256, 0, s>>>(P, cur, st.partials, st.x, st.r, st.z, st.p, st.u, st.minv,
-                                               st.partials + 2 * kRedBlocks);
+  pcg_update_kernel<<<kRedBlocks, 256, 0, s>>>(P, cur, st.partials, pu_count, st.x, st.r, st.z, st.p, st.u,
+                                               st.minv, st.partials + 2 * kRedBlocks);
   pcg_dir_kernel<<<kRedBlocks, 256, 0, s>>>(P, cur, st.bank(it + 1), st.partials + 2 * kRedBlocks, st.z, st.p);
 }
 

@@ -20,9 +20,11 @@ FrameDims dims_of(const lmrs_frame* f);
 void launch_project(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s);
 void launch_tangent(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* p,
                     float* tan, hipStream_t s);
+// pu_part (optional): one FP64 partial of p . out per workgroup, chain_vjp_blocks(n, true) of them
 void launch_chain_vjp(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                       const float* grad2d, const float* p, float lambda, const float* dvec, float* out,
-                      hipStream_t s);
+                      hipStream_t s, double* pu_part = nullptr);
+int chain_vjp_blocks(int n, bool partials);
 void launch_chain_diag(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                        const float* gram, float* out, hipStream_t s);
 void launch_fill(float* x, int64_t count, float value, hipStream_t s);
@@ -76,8 +78,9 @@ struct PcgState {
 };
 void launch_pcg_init(const float* b, const float* diag, float lambda, const float* dvec, int64_t P,
                      PcgState st, hipStream_t s);
-// one PCG iteration after the product u = A p: p^T u, alpha, x, r, z, beta, p
-void launch_pcg_iteration(int it, int64_t P, PcgState st, hipStream_t s);
+// one PCG iteration after the product u = A p, whose chain kernel left pu_count
+// partials of p^T u in st.partials: alpha, x, r, z, beta, p
+void launch_pcg_iteration(int it, int64_t P, int pu_count, PcgState st, hipStream_t s);
 void launch_pcg_report(const float* b, int iters, int64_t P, PcgState st, float* report, hipStream_t s);
 void launch_lm_update(float* beta, const float* x, int n, int64_t P, const lmrs_lm_params& prm,
                       double* partials, float* report, hipStream_t s);
