@@ -227,6 +227,26 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(const float* __restrict__
   }
 }
 
+// VEC floats as one unit: float4 (16-byte accesses) or a single float.
+template <int VEC>
+struct Vec;
+template <>
+struct Vec<1> {
+  using T = float;
+  __device__ static float load(const float* a, int64_t i) { return a[i]; }
+  __device__ static void store(float* a, int64_t i, float v) { a[i] = v; }
+  __device__ static float& at(float& v, int) { return v; }
+  __device__ static float at(const float& v, int) { return v; }
+};
+template <>
+struct Vec<4> {
+  using T = float4;
+  __device__ static float4 load(const float* a, int64_t i) { return reinterpret_cast<const float4*>(a)[i]; }
+  __device__ static void store(float* a, int64_t i, float4 v) { reinterpret_cast<float4*>(a)[i] = v; }
+  __device__ static float& at(float4& v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; }
+  __device__ static float at(const float4& v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; }
+};
+
 // Sum of partials[0, count) in a fixed order (the same in every block).
 __device__ __forceinline__ double reduce_partials(const double* __restrict__ partials, int count,
                                                   double* s_red) {
@@ -253,6 +273,7 @@ __global__ __launch_bounds__(256) void pcg_init_scalars_kernel(const double* __r
 // alpha = r^T z / p^T u (0 once stopped); x += alpha p; r -= alpha u; z = M^-1 r.
 // p^T u comes from the partials that the GN product's chain kernel leaves
 // (pu_count of them, reduced in every block).
+template <int VEC>
 __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t P, double* __restrict__ cur,
                                                          const double* __restrict__ pu_partials, int pu_count,
                                                          float* __restrict__ x, float* __restrict__ r,
@@ -267,17 +288,46 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t P, double* __re
   if (blockIdx.x == 0 && threadIdx.x == 0) cur[kPU] = pu;
   const float alpha = go ? (float)(rz / pu) : 0.f;
   double rz1 = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
-    float ri = r[i];
+  // VEC consecutive elements per thread and step (16-byte loads when 4)
+  using V = Vec<VEC>;
+  const int64_t units = P / VEC;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < units; i += (int64_t)gridDim.x * 256) {
+    typename V::T rv = V::load(r, i);
+    const typename V::T mv = V::load(minv, i);
     if (go) {
-      x[i] += alpha * p[i];
-      ri -= alpha * u[i];
-      r[i] = ri;
+      typename V::T xv = V::load(x, i);
+      const typename V::T pv = V::load(p, i), uv = V::load(u, i);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        V::at(xv, c) += alpha * V::at(pv, c);
+        V::at(rv, c) -= alpha * V::at(uv, c);
+      }
+      V::store(x, i, xv);
+      V::store(r, i, rv);
     }
-    const float zi = minv[i] * ri;
-    z[i] = zi;
-    rz1 += (double)ri * zi;
-    rr += (double)ri * ri;
+    typename V::T zv;
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) {
+      const float ri = V::at(rv, c), zi = V::at(mv, c) * ri;
+      V::at(zv, c) = zi;
+      rz1 += (double)ri * zi;
+      rr += (double)ri * ri;
+    }
+    V::store(z, i, zv);
+  }
+  if (blockIdx.x == 0) {  // the last P % VEC elements
+    for (int64_t i = units * VEC + threadIdx.x; i < P; i += 256) {
+      float ri = r[i];
+      if (go) {
+        x[i] += alpha * p[i];
+        ri -= alpha * u[i];
+        r[i] = ri;
+      }
+      const float zi = minv[i] * ri;
+      z[i] = zi;
+      rz1 += (double)ri * zi;
+      rr += (double)ri * ri;
+    }
   }
   const double a = block_sum(rz1, s_red);
   const double c = block_sum(rr, s_red);
@@ -289,6 +339,7 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(int64_t P, double* __re
 
 // r_{i+1}^T z_{i+1} and r^T r from pcg_update_kernel's partials; beta, the
 // stop flag and the next scalar bank; p = z + beta p.
+template <int VEC>
 __global__ __launch_bounds__(256) void pcg_dir_kernel(int64_t P, const double* __restrict__ cur,
                                                       double* __restrict__ next,
                                                       const double* __restrict__ partials,
@@ -313,8 +364,17 @@ __global__ __launch_bounds__(256) void pcg_dir_kernel(int64_t P, const double* _
   }
   if (!go) return;
   const float b = (float)beta;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256)
-    p[i] = z[i] + b * p[i];
+  using V = Vec<VEC>;
+  const int64_t units = P / VEC;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < units; i += (int64_t)gridDim.x * 256) {
+    const typename V::T zv = V::load(z, i);
+    typename V::T pv = V::load(p, i);
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) V::at(pv, c) = V::at(zv, c) + b * V::at(pv, c);
+    V::store(p, i, pv);
+  }
+  if (blockIdx.x == 0)
+    for (int64_t i = units * VEC + threadIdx.x; i < P; i += 256) p[i] = z[i] + b * p[i];
 }
 
 __global__ void pcg_report_kernel(const double* __restrict__ sc, const double* __restrict__ bx,
@@ -412,11 +472,23 @@ void launch_pcg_init(const float* b, const float* diag, float lambda, const floa
   pcg_init_scalars_kernel<<<1, 256, 0, s>>>(st.partials, st.bank(0));
 }
 
+static bool aligned16(const void* a) { return (reinterpret_cast<uintptr_t>(a) & 15) == 0; }
+
 void launch_pcg_iteration(int it, int64_t P, int pu_count, PcgState st, hipStream_t s) {
   double* cur = st.bank(it);
-  pcg_update_kernel<<<kRedBlocks, 256, 0, s>>>(P, cur, st.partials, pu_count, st.x, st.r, st.z, st.p, st.u,
-                                               st.minv, st.partials + 2 * kRedBlocks);
-  pcg_dir_kernel<<<kRedBlocks, 256, 0, s>>>(P, cur, st.bank(it + 1), st.partials + 2 * kRedBlocks, st.z, st.p);
+  const bool vec = aligned16(st.x) && aligned16(st.r) && aligned16(st.z) && aligned16(st.p) && aligned16(st.u) &&
+                   aligned16(st.minv);
+  if (vec) {
+    pcg_update_kernel<4><<<kRedBlocks, 256, 0, s>>>(P, cur, st.partials, pu_count, st.x, st.r, st.z, st.p, st.u,
+                                                    st.minv, st.partials + 2 * kRedBlocks);
+    pcg_dir_kernel<4><<<kRedBlocks, 256, 0, s>>>(P, cur, st.bank(it + 1), st.partials + 2 * kRedBlocks, st.z,
+                                                 st.p);
+  } else {
+    pcg_update_kernel<1><<<kRedBlocks, 256, 0, s>>>(P, cur, st.partials, pu_count, st.x, st.r, st.z, st.p, st.u,
+                                                    st.minv, st.partials + 2 * kRedBlocks);
+    pcg_dir_kernel<1><<<kRedBlocks, 256, 0, s>>>(P, cur, st.bank(it + 1), st.partials + 2 * kRedBlocks, st.z,
+                                                 st.p);
+  }
 }
 
 void launch_pcg_report(const float* b, int iters, int64_t P, PcgState st, float* report, hipStream_t s) {
