@@ -63,34 +63,37 @@ __global__ __launch_bounds__(kBlock) void project_kernel(const float* __restrict
   rect[vg] = rc;
 }
 
-// Tangent of the screen record along direction p (forward mode).
+// Tangent of the screen record along direction p (forward mode). One thread
+// per Gaussian loads its parameters and direction once and forms the tangent
+// in every view of the batch.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void tangent_kernel(const float* __restrict__ beta,
-                                                         const float* __restrict__ p, int n,
+                                                         const float* __restrict__ p, int n, int V,
                                                          const lmrs_camera* __restrict__ cams,
                                                          const int32_t* __restrict__ view_ids,
                                                          const int4* __restrict__ rect, float lowpass,
                                                          float* __restrict__ tan) {
   constexpr int PG = ShDims<DEG>::PG;
   const int g = blockIdx.x * kBlock + threadIdx.x;
-  const int v = blockIdx.y;
   if (g >= n) return;
-  const size_t vg = (size_t)v * n + g;
-  float4* out = reinterpret_cast<float4*>(tan + vg * LMRS_REC);
-  const int4 rc = rect[vg];
-  if (rc.x >= rc.z) {
-    out[0] = out[1] = out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-    return;
-  }
-  const CamView cv = load_cam(cams, view_ids, v);
   dualf prm[PG];
 #pragma unroll
   for (int j = 0; j < PG; ++j) prm[j] = dualf(beta[(size_t)j * n + g], p[(size_t)j * n + g]);
-  dualf r[9];
-  proj_core<DEG>(prm, cv, lowpass, r, nullptr, nullptr, nullptr);
-  out[0] = make_float4(r[0].d, r[1].d, r[2].d, r[3].d);
-  out[1] = make_float4(r[4].d, r[5].d, r[6].d, r[7].d);
-  out[2] = make_float4(r[8].d, 0.f, 0.f, 0.f);
+  for (int v = 0; v < V; ++v) {
+    const size_t vg = (size_t)v * n + g;
+    float4* out = reinterpret_cast<float4*>(tan + vg * LMRS_REC);
+    const int4 rc = rect[vg];
+    if (rc.x >= rc.z) {
+      out[0] = out[1] = out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+      continue;
+    }
+    const CamView cv = load_cam(cams, view_ids, v);
+    dualf r[9];
+    proj_core<DEG>(prm, cv, lowpass, r, nullptr, nullptr, nullptr);
+    out[0] = make_float4(r[0].d, r[1].d, r[2].d, r[3].d);
+    out[1] = make_float4(r[4].d, r[5].d, r[6].d, r[7].d);
+    out[2] = make_float4(r[8].d, 0.f, 0.f, 0.f);
+  }
 }
 
 // out[beta_g] = sum_v (d rec_vg / d beta_g)^T grad2d[v][:][g]  (+ lambda d p).
@@ -238,13 +241,13 @@ void launch_project(const lmrs_frame* f, const FrameDims& d, const lmrs_render_o
 
 void launch_tangent(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* p,
                     float* tan, hipStream_t s) {
-  dim3 grid((d.n + kBlock - 1) / kBlock, d.V);
+  const unsigned grid = (d.n + kBlock - 1) / kBlock;
   auto* rect = reinterpret_cast<const int4*>(f->rect);
   switch (d.deg) {
-    case 0: tangent_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, f->cams, f->view_ids, rect, o.lowpass, tan); break;
-    case 1: tangent_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, f->cams, f->view_ids, rect, o.lowpass, tan); break;
-    case 2: tangent_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, f->cams, f->view_ids, rect, o.lowpass, tan); break;
-    default: tangent_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, f->cams, f->view_ids, rect, o.lowpass, tan); break;
+    case 0: tangent_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, d.V, f->cams, f->view_ids, rect, o.lowpass, tan); break;
+    case 1: tangent_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, d.V, f->cams, f->view_ids, rect, o.lowpass, tan); break;
+    case 2: tangent_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, d.V, f->cams, f->view_ids, rect, o.lowpass, tan); break;
+    default: tangent_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, p, d.n, d.V, f->cams, f->view_ids, rect, o.lowpass, tan); break;
   }
 }
 
