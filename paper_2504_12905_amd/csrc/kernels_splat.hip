@@ -272,8 +272,9 @@ struct ScoreOut {
   float* score;             // [V][T][256]
 };
 
-template <int NS, bool SCORE>
-__global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__ rec,
+// W waves share a tile; wave wv renders the sample slots j with j % W == wv.
+template <int NS, bool SCORE, int W>
+__global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restrict__ rec,
                                                        const int64_t* __restrict__ tile_start,
                                                        const int32_t* __restrict__ ids,
                                                        const uint8_t* __restrict__ pix, int n, int T,
@@ -282,6 +283,8 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
                                                        int32_t* __restrict__ last,
                                                        int32_t* __restrict__ walk_len, ScoreOut so) {
   const int lane = lane_id();
+  const int wv = uniform((int)(threadIdx.x / kWave));
+  const bool mine = (lane & (W - 1)) == wv;
   const TileCtx c = tile_ctx(tile_start, T, TX, blockIdx.x);
   PixelRegs<NS> pr;
   load_pixel_regs<NS>(pix, nullptr, nullptr, k, c, pr);
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
     sDone[s] = 0;
   }
   const float log_tmin = __log2f(o.t_min);
-  int remaining = k;
+  int remaining = k / W + (wv < k % W ? 1 : 0);  // this wave's pixels
   for (int c0 = 0; c0 < c.len && remaining > 0; c0 += kWave) {
     const bool valid = c0 + lane < c.len;
     RecF r{};
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int cnt = min(kWave, k - s * kWave);
-      for (int l = 0; l < cnt; ++l) {
+      for (int l = wv; l < cnt; l += W) {
         if (readlane(sDone[s], l)) continue;
         const Alpha al = pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
         const bool inc = valid && al.inc;
@@ -337,7 +340,7 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int j = s * kWave + lane;
-    if (j < k) {
+    if (j < k && mine) {
       const int64_t i = c.tile_lin * k + j;
       const float c0 = sC0[s] + sT[s] * o.bg[0];
       const float c1 = sC1[s] + sT[s] * o.bg[1];
@@ -359,9 +362,16 @@ __global__ __launch_bounds__(kWave) void render_kernel(const float* __restrict__
   if (!SCORE) {
     int steps = 0;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) steps += sLast[s] >= 0 ? sLast[s] / kWave + 1 : 0;
+    for (int s = 0; s < NS; ++s) steps += mine && sLast[s] >= 0 ? sLast[s] / kWave + 1 : 0;
+    __shared__ float part[W];
     const float total = wave_total((float)steps);  // a sort key: exact up to 2^24 steps
-    if (lane == 0) walk_len[c.tile_lin] = (int32_t)total;
+    if (lane == 0) part[wv] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float sum = 0.f;
+      for (int w = 0; w < W; ++w) sum += part[w];
+      walk_len[c.tile_lin] = (int32_t)sum;
+    }
   }
 }
 
@@ -848,16 +858,24 @@ unsigned persistent_groups(int64_t tiles, int w) {
 
 }  // namespace
 
-void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
+template <int W>
+void launch_render_w(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   const ScoreOut none{nullptr, nullptr, 0, 0, nullptr};
   int32_t* walk_len = f->sched + tiles;
   if (d.k <= kWave)
-    render_kernel<1, false><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k,
-                                                    o, f->color, f->trans, f->last, walk_len, none);
+    render_kernel<1, false, W><<<tiles, kWave * W, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX,
+                                                           d.k, o, f->color, f->trans, f->last, walk_len, none);
   else
-    render_kernel<4, false><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k,
-                                                    o, f->color, f->trans, f->last, walk_len, none);
+    render_kernel<4, false, W><<<tiles, kWave * W, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX,
+                                                           d.k, o, f->color, f->trans, f->last, walk_len, none);
+}
+
+void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
+  // 4 waves per tile share its pixels from 24 samples per tile up (as in the derivative walks)
+  if (d.k >= 24) launch_render_w<4>(f, d, o, s);
+  else launch_render_w<1>(f, d, o, s);
+  const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   sched_kernel<<<1, kSchedThreads, 0, s>>>(f->sched, (int)tiles);
 }
 
@@ -865,8 +883,8 @@ void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_re
                           const float* targets, float* scores, hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   const ScoreOut so{targets, f->view_ids, d.W, d.H, scores};
-  render_kernel<4, true><<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, nullptr, d.n, d.T, d.TX, 256, o,
-                                                 nullptr, nullptr, nullptr, nullptr, so);
+  render_kernel<4, true, 4><<<tiles, kWave * 4, 0, s>>>(f->rec, f->tile_start, f->ids, nullptr, d.n, d.T, d.TX,
+                                                        256, o, nullptr, nullptr, nullptr, nullptr, so);
 }
 
 template <int W>
