@@ -169,11 +169,17 @@ __global__ __launch_bounds__(kBlock) void chain_diag_kernel(
   for (int v = 0; v < V; ++v) {
     float G[kGram];
     bool any = false;
+    const float4* row = reinterpret_cast<const float4*>(gram + ((size_t)v * n + g) * kGram);
 #pragma unroll
-    for (int e = 0; e < kGram; ++e) {
-      G[e] = gram[((size_t)v * kGram + e) * n + g];
-      any |= G[e] != 0.f;
+    for (int e4 = 0; e4 < kGram / 4; ++e4) {
+      const float4 x = row[e4];
+      G[4 * e4] = x.x;
+      G[4 * e4 + 1] = x.y;
+      G[4 * e4 + 2] = x.z;
+      G[4 * e4 + 3] = x.w;
     }
+#pragma unroll
+    for (int e = 0; e < kGram; ++e) any |= G[e] != 0.f;
     if (!any) continue;
     const CamView cv = load_cam(cams, view_ids, v);
     float Jc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};

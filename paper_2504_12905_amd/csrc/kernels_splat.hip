@@ -684,7 +684,7 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
                                           const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
                                           const lmrs_render_opts& o, float* __restrict__ gram,
                                           const float* __restrict__ u_in, float* __restrict__ grad2d,
-                                          int64_t tile_lin) {
+                                          int64_t tile_lin, float* tr, int* tr_id) {
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX, tile_lin);
   PixelRegs<NS> pr;
@@ -782,11 +782,23 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
         sS2[s] = writelane(sS2[s], S[2] + tot[2], l);
       }
     }
+    // Gram flush, transposed through LDS: the atomic instruction t covers
+    // entries 2t and 2t + 1 with lanes holding their 32 components, so that
+    // each instruction updates two Gaussians' 128-byte Gram rows instead of
+    // one word in each of 64 rows.
+#pragma unroll
+    for (int q = 0; q < kGram; ++q) tr[q * (kWave + 1) + lane] = G[q];
+    tr_id[lane] = valid ? id : -1;
+    {
+      const int q = lane & (kGram - 1), half = lane >> 5;
+      for (int t = 0; t < kWave / 2; ++t) {
+        const int e = 2 * t + half;
+        const int ide = tr_id[e];
+        const float val = tr[q * (kWave + 1) + e];
+        if (ide >= 0 && val != 0.f) atomicAdd(&gram[((size_t)c.v * n + ide) * kGram + q], val);
+      }
+    }
     if (valid) {
-      bool any = false;
-      for (int q = 0; q < kGram; ++q) any |= G[q] != 0.f;
-      if (any)
-        for (int q = 0; q < kGram; ++q) atomicAdd(&gram[((size_t)c.v * kGram + q) * n + id], G[q]);
       if (VJP) {
         bool anyg = false;
         for (int q = 0; q < 9; ++q) anyg |= g[q] != 0.f;
@@ -809,13 +821,16 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
                                                      float* __restrict__ gram, const float* __restrict__ u_in,
                                                      float* __restrict__ grad2d, int32_t* __restrict__ sched,
                                                      int tiles) {
+  __shared__ float tr[kGram * (kWave + 1)];  // Gram flush transpose (padded rows: no bank conflicts)
+  __shared__ int tr_id[kWave];
   const SchedRef sr = sched_ref(sched, tiles);
   const int count = sched_count(sr, true);
   for (;;) {
     const int tile = sched_next(sr, count);
     if (tile == -1) break;
     if (tile >= 0)
-      gram_tile<NS, VJP>(rec, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, gram, u_in, grad2d, tile);
+      gram_tile<NS, VJP>(rec, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, gram, u_in, grad2d, tile,
+                         tr, tr_id);
   }
   sched_finish(sr);
 }

@@ -55,7 +55,7 @@ void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_re
 // mode: 1 = J p only (writes jp), 2 = J^T u only (reads u), 3 = fused GN (J^T W J p)
 void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                   const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s);
-// gram[V][32][n]; with u non-NULL also grad2d += J^T u (u: [S][3])
+// gram[V][n][32] (one 128-byte row per (view, Gaussian)); with u non-NULL also grad2d += J^T u (u: [S][3])
 void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* gram,
                  const float* u, float* grad2d, hipStream_t s);
 
