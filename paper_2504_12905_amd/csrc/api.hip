@@ -84,7 +84,7 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
     s.bin.vcount = c.take<int32_t>((size_t)view_sort_count_ints(d.n, d.V));
   }
   if (need_tan) s.tan = c.take<float>((size_t)VN * LMRS_REC);
-  if (need_grad) s.grad2d = c.take<float>((size_t)VN * 9);
+  if (need_grad) s.grad2d = c.take<float>((size_t)VN * kGradRow);
   if (need_gram) s.gram = c.take<float>((size_t)VN * kGram);
   if (need_pcg) {
     s.diag = c.take<float>(P);
@@ -164,14 +164,14 @@ void gn_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts
                  float lambda, const float* dvec, float* out, const Scratch& s, hipStream_t st,
                  double* pu_part = nullptr) {
   launch_tangent(f, d, o, p, s.tan, st);
-  launch_fill(s.grad2d, (int64_t)d.V * d.n * 9, 0.f, st);
+  launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
   launch_deriv(3, f, d, o, s.tan, nullptr, nullptr, s.grad2d, st);
   launch_chain_vjp(f, d, o, s.grad2d, p, lambda, dvec, out, st, pu_part);
 }
 
 void vjp_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* u,
                   float* out, const Scratch& s, hipStream_t st) {
-  launch_fill(s.grad2d, (int64_t)d.V * d.n * 9, 0.f, st);
+  launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
   launch_deriv(2, f, d, o, nullptr, u, nullptr, s.grad2d, st);
   launch_chain_vjp(f, d, o, s.grad2d, nullptr, 0.f, nullptr, out, st);
 }
@@ -187,7 +187,7 @@ void diag_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_op
 void vjp_diag_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* u,
                        float* b, float* diag, const Scratch& s, hipStream_t st) {
   launch_fill(s.gram, (int64_t)d.V * d.n * kGram, 0.f, st);
-  launch_fill(s.grad2d, (int64_t)d.V * d.n * 9, 0.f, st);
+  launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
   launch_gram(f, d, o, s.gram, u, s.grad2d, st);
   launch_chain_vjp(f, d, o, s.grad2d, nullptr, 0.f, nullptr, b, st);
   launch_chain_diag(f, d, o, s.gram, diag, st);
@@ -421,7 +421,7 @@ lmrs_status lmrs_gn_product_timed(const lmrs_frame* f, const lmrs_render_opts* o
   (void)hipEventRecord(ev[0], st);
   launch_tangent(f, d, *o, p, s.tan, st);
   (void)hipEventRecord(ev[1], st);
-  launch_fill(s.grad2d, (int64_t)d.V * d.n * 9, 0.f, st);
+  launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
   (void)hipEventRecord(ev[2], st);
   launch_deriv(3, f, d, *o, s.tan, nullptr, nullptr, s.grad2d, st);
   (void)hipEventRecord(ev[3], st);

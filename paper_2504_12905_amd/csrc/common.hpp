@@ -20,6 +20,7 @@ namespace lmrs {
 constexpr int kTile = 16;
 constexpr int kWave = 64;
 constexpr int kGram = 32;            // Gram entries kept per (view, Gaussian)
+constexpr int kGradRow = 16;         // floats per (view, Gaussian) row of screen gradients (9 used)
 
 // ------------------------------------------------------------------ duals
 struct dualf {

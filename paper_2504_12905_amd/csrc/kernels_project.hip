@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void tangent_kernel(const float* __restrict
   }
 }
 
-// out[beta_g] = sum_v (d rec_vg / d beta_g)^T grad2d[v][:][g]  (+ lambda d p).
+// out[beta_g] = sum_v (d rec_vg / d beta_g)^T grad2d[v][g][0..9)  (+ lambda d p).
 // With pu_part, each workgroup also leaves its partial sum of p . out in
 // pu_part[blockIdx.x] (FP64; the PCG update reduces them), which saves the
 // operator product's separate pass over p and u.
@@ -116,11 +116,13 @@ __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
     for (int v = 0; v < V; ++v) {
       float gr[9];
       bool any = false;
+      const float* row = grad2d + ((size_t)v * n + g) * kGradRow;
+      const float4 a = reinterpret_cast<const float4*>(row)[0], b = reinterpret_cast<const float4*>(row)[1];
+      gr[0] = a.x; gr[1] = a.y; gr[2] = a.z; gr[3] = a.w;
+      gr[4] = b.x; gr[5] = b.y; gr[6] = b.z; gr[7] = b.w;
+      gr[8] = row[8];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        gr[q] = grad2d[((size_t)v * 9 + q) * n + g];
-        any |= gr[q] != 0.f;
-      }
+      for (int q = 0; q < 9; ++q) any |= gr[q] != 0.f;
       if (!any) continue;
       const CamView cv = load_cam(cams, view_ids, v);
       proj_vjp<DEG>(prm, cv, lowpass, gr, gp);

@@ -376,6 +376,11 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
 }
 
 // ----------------------------------------------------- J p, J^T u, fused GN
+// LDS of one reverse-walk chunk of a W-wave workgroup: the waves' partial
+// gradients (rows of 65 floats per (wave, component)) and the chunk's ids.
+template <int W>
+constexpr int kRedBuf = W * 9 * (kWave + 1) + kWave;
+
 // One forward step: pixel (xc, yc) (transmittance Tc and its tangent dTc in
 // front of the chunk, last blended entry lj) against the chunk's entries, one
 // per lane. cr/cg/cb: this lane's entry's term of the colour tangent; tp / tq:
@@ -620,17 +625,26 @@ __device__ __forceinline__ void deriv_tile(
       // the waves' partial gradients of each entry meet in LDS (double
       // buffered by chunk, so one barrier per chunk); wave wv adds up and
       // flushes components wv, wv + W, ...
-      float* buf = red + (chunk & 1) * (W * 9 * kWave);
+      float* buf = red + (chunk & 1) * kRedBuf<W>;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) buf[(wv * 9 + q) * kWave + lane] = g[q];
+      for (int q = 0; q < 9; ++q) buf[(wv * 9 + q) * (kWave + 1) + lane] = g[q];
+      if (wv == 0) reinterpret_cast<int*>(buf + W * 9 * (kWave + 1))[lane] = valid ? id : -1;
       landed(rn);
       landed(idn);
       __syncthreads();
-      for (int q = wv; q < 9; q += W) {
+      // flush transposed: an atomic instruction covers 4 entries with 16 lanes
+      // each (their 9 components), i.e. 4 gradient rows of 64 bytes
+      const int* ent_id = reinterpret_cast<const int*>(buf + W * 9 * (kWave + 1));
+      const int q = lane & (kGradRow - 1);
+      for (int t = wv; t < kWave / 4; t += W) {
+        const int ent = 4 * t + (lane >> 4);
+        const int ide = ent_id[ent];
         float sum = 0.f;
+        if (q < 9) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) sum += buf[(w * 9 + q) * kWave + lane];
-        if (valid && sum != 0.f) atomicAdd(&grad2d[((size_t)c.v * 9 + q) * n + id], sum);
+          for (int w = 0; w < W; ++w) sum += buf[(w * 9 + q) * (kWave + 1) + ent];
+        }
+        if (ide >= 0 && q < 9 && sum != 0.f) atomicAdd(&grad2d[((size_t)c.v * n + ide) * kGradRow + q], sum);
       }
       ++chunk;
     }
@@ -651,7 +665,7 @@ __global__ __launch_bounds__(kWave* W) void deriv_kernel(
     lmrs_render_opts o, const float* __restrict__ u_in, float* __restrict__ jp_out,
     float* __restrict__ grad2d, int32_t* __restrict__ sched, int tiles) {
   __shared__ int next_tile[2];
-  __shared__ float red[MODE == 1 ? 1 : 2 * W * 9 * kWave];
+  __shared__ float red[MODE == 1 ? 1 : 2 * kRedBuf<W>];
   const int wv = uniform((int)(threadIdx.x / kWave));
   const SchedRef sr = sched_ref(sched, tiles);
   const int count = sched_count(sr, MODE != 1);
@@ -798,12 +812,15 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
         if (ide >= 0 && val != 0.f) atomicAdd(&gram[((size_t)c.v * n + ide) * kGram + q], val);
       }
     }
-    if (valid) {
-      if (VJP) {
-        bool anyg = false;
-        for (int q = 0; q < 9; ++q) anyg |= g[q] != 0.f;
-        if (anyg)
-          for (int q = 0; q < 9; ++q) atomicAdd(&grad2d[((size_t)c.v * 9 + q) * n + id], g[q]);
+    if (VJP) {  // J^T u, transposed the same way: 4 gradient rows per instruction
+#pragma unroll
+      for (int q = 0; q < 9; ++q) tr[q * (kWave + 1) + lane] = g[q];
+      const int q = lane & (kGradRow - 1);
+      for (int t = 0; t < kWave / 4; ++t) {
+        const int e = 4 * t + (lane >> 4);
+        const int ide = tr_id[e];
+        const float val = q < 9 ? tr[q * (kWave + 1) + e] : 0.f;
+        if (ide >= 0 && val != 0.f) atomicAdd(&grad2d[((size_t)c.v * n + ide) * kGradRow + q], val);
       }
     }
   }
