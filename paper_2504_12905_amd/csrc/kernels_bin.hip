@@ -322,6 +322,37 @@ constexpr int kTileSortThreads = 256;
 constexpr int kTileSortWaves = kTileSortThreads / kWave;
 constexpr int kTileSortLds = 4096;
 
+// One stable counting pass of a block that is in LDS: src -> dst (both LDS,
+// blen <= kTileSortLds) by digit; leaves the block's digit totals in tot[]
+// and their exclusive prefix in start[] (thread d owns digit d). Every
+// thread of the workgroup calls it.
+__device__ void lds_block_pass(const uint32_t* src, uint32_t* dst, int blen, int shift, int bins,
+                               int (*cnt)[kRadixBins], int* wsum, int* tot, int* start) {
+  const int tid = threadIdx.x, w = tid / kWave;
+  const int64_t b0 = (int64_t)blen * w / kTileSortWaves, b1 = (int64_t)blen * (w + 1) / kTileSortWaves;
+  for (int i = tid; i < kTileSortWaves * kRadixBins; i += kTileSortThreads) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  part_count(src, b0, b1, shift, bins, cnt[w]);
+  __syncthreads();
+  int c[kTileSortWaves], t = 0;
+#pragma unroll
+  for (int v = 0; v < kTileSortWaves; ++v) {
+    c[v] = cnt[v][tid];
+    t += c[v];
+  }
+  int run = bins_exclusive_scan(t, wsum);
+  tot[tid] = t;
+  start[tid] = run;
+#pragma unroll
+  for (int v = 0; v < kTileSortWaves; ++v) {
+    cnt[v][tid] = run;
+    run += c[v];
+  }
+  __syncthreads();
+  part_scatter(src, dst, nullptr, nullptr, b0, b1, shift, bins, cnt[w]);
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64_t* __restrict__ tile_start,
                                                                      uint32_t* __restrict__ keys,
                                                                      uint32_t* __restrict__ tmp,
@@ -329,20 +360,28 @@ __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64
                                                                      int rank_bits, int32_t* __restrict__ ids) {
   __shared__ int cnt[kTileSortWaves][kRadixBins];
   __shared__ int wsum[kRadixBins / kWave];
+  __shared__ int tot[kRadixBins], start[kRadixBins], goff[kRadixBins];
   __shared__ uint32_t buf[2][kTileSortLds];
   const int64_t a = tile_start[blockIdx.x];
   const int64_t len = tile_start[blockIdx.x + 1] - a;
   if (len == 0) return;
   const int tid = threadIdx.x, w = tid / kWave;
-  const bool in_lds = len <= kTileSortLds;
+  const int32_t* ord = order + (size_t)(blockIdx.x / T) * n;
+  if (len <= kTileSortLds) {  // the whole segment in LDS
+    for (int i = tid; i < len; i += kTileSortThreads) buf[0][i] = keys[a + i];
+    __syncthreads();
+    int q = 0;
+    for (int shift = 0; shift < rank_bits; shift += 8, q ^= 1)
+      lds_block_pass(buf[q], buf[q ^ 1], (int)len, shift, 1 << min(8, rank_bits - shift), cnt, wsum, tot, start);
+    for (int i = tid; i < len; i += kTileSortThreads) ids[a + i] = ord[buf[q][i]];
+    return;
+  }
+  // Longer segments: per pass, the digit totals of the whole segment give
+  // each digit its output range; then blocks of kTileSortLds keys are
+  // sorted by the digit in LDS, in order, and written out as runs of equal
+  // digits (consecutive addresses) at the digits' running offsets.
   uint32_t* src = keys + a;
   uint32_t* dst = tmp + a;
-  if (in_lds) {
-    for (int i = tid; i < len; i += kTileSortThreads) buf[0][i] = src[i];
-    src = buf[0];
-    dst = buf[1];
-    __syncthreads();
-  }
   const int64_t b0 = len * w / kTileSortWaves, b1 = len * (w + 1) / kTileSortWaves;
   for (int shift = 0; shift < rank_bits; shift += 8) {
     const int bins = 1 << min(8, rank_bits - shift);
@@ -350,26 +389,29 @@ __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64
     __syncthreads();
     part_count(src, b0, b1, shift, bins, cnt[w]);
     __syncthreads();
-    int c[kTileSortWaves], tot = 0;
+    int t = 0;
 #pragma unroll
-    for (int v = 0; v < kTileSortWaves; ++v) {
-      c[v] = cnt[v][tid];
-      tot += c[v];
-    }
-    int run = bins_exclusive_scan(tot, wsum);
-#pragma unroll
-    for (int v = 0; v < kTileSortWaves; ++v) {
-      cnt[v][tid] = run;
-      run += c[v];
-    }
+    for (int v = 0; v < kTileSortWaves; ++v) t += cnt[v][tid];
+    goff[tid] = bins_exclusive_scan(t, wsum);
     __syncthreads();
-    part_scatter(src, dst, nullptr, nullptr, b0, b1, shift, bins, cnt[w]);
-    __syncthreads();
-    uint32_t* t = src;
+    for (int64_t base = 0; base < len; base += kTileSortLds) {
+      const int blen = (int)min<int64_t>(kTileSortLds, len - base);
+      for (int i = tid; i < blen; i += kTileSortThreads) buf[0][i] = src[base + i];
+      __syncthreads();
+      lds_block_pass(buf[0], buf[1], blen, shift, bins, cnt, wsum, tot, start);
+      for (int i = tid; i < blen; i += kTileSortThreads) {
+        const uint32_t key = buf[1][i];
+        const int d = digit_of(key, shift, bins);
+        dst[goff[d] + (i - start[d])] = key;
+      }
+      __syncthreads();
+      goff[tid] += tot[tid];
+      __syncthreads();
+    }
+    uint32_t* tt = src;
     src = dst;
-    dst = t;
+    dst = tt;
   }
-  const int32_t* ord = order + (size_t)(blockIdx.x / T) * n;
   for (int64_t i = tid; i < len; i += kTileSortThreads) ids[a + i] = ord[src[i]];
 }
 
