@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kViewThreads) void view_rank_kernel(const uint32_t*
 // ones pass through the keys / tmp buffers in global memory.
 constexpr int kTileSortThreads = 256;
 constexpr int kTileSortWaves = kTileSortThreads / kWave;
-constexpr int kTileSortLds = 4096;
+constexpr int kTileSortLds = 2048;
 
 // One stable counting pass of a block that is in LDS: src -> dst (both LDS,
 // blen <= kTileSortLds) by digit; leaves the block's digit totals in tot[]
