@@ -116,6 +116,33 @@ def test_equal_depths_keep_id_order():
     assert len(np.unique(rec[vis, 9].view(np.uint32))) == 2
 
 
+@pytest.mark.parametrize("k", [24, 40, 64])
+def test_four_wave_paths(k):
+    """Samples per tile at which the derivative walks run 4 waves per tile:
+    24 (per-lane colour-tangent accumulators, fewest pixels per wave), 40 and
+    64 (pixels beyond 32 per tile: one wave sum per step), against the oracle."""
+    n, deg = 3000, 2
+    gt = synth.make_scene(n, deg, 12, means="ball")
+    beta = synth.perturb_init(gt, n, deg, 12)
+    cams = synth.sphere_cameras(2, 4.0, 128, 96, 60.0, 12)
+    pix, wts = sample_uniform(13, 0, np.arange(2), (128 // 16) * (96 // 16), k)
+    fr, orc = check_all(f"k={k}", n, deg, beta, cams, 128, 96, k, pix, wts)
+    p = np.random.default_rng(1).normal(size=orc.P).astype(np.float32)
+    jp = np_(lib().lmrs_jvp(fr, torch.tensor(p, device=DEV)))
+    ok = orc.decided()
+    e = rel(jp[ok], orc.jvp(p)[ok])
+    log(f"  k={k} jvp rel {e:.2e} on decided pixels")
+    assert e < 1e-4
+    u = np.random.default_rng(2).normal(size=(orc.S, 3)).astype(np.float32)
+    e = rel(np_(lib().lmrs_vjp(fr, torch.tensor(u, device=DEV))), orc.vjp(u))
+    log(f"  k={k} vjp rel {e:.2e}")
+    assert e < 1e-4
+    d = np_(lib().lmrs_gn_diag(fr))
+    e = rel(d, orc.diag())
+    log(f"  k={k} diag rel {e:.2e}")
+    assert e < 1e-4
+
+
 def test_maximum_tiles_per_view():
     """A 2048x2048 view has 16,384 tiles, the most one view may have (the
     binning histogram of a view lives in LDS); one sample per tile."""

@@ -168,6 +168,22 @@ def test_pcg(case):
     assert float(b @ x) > 0
 
 
+def test_pcg_unaligned_output(case):
+    """x at an address that is not 16-byte aligned takes the scalar PCG vector
+    kernels; the result matches the vectorised run (both FP32 recurrences with
+    FP64 dot products, in different summation orders)."""
+    rng = np.random.default_rng(6)
+    b = torch.tensor(case.orc.vjp(rng.normal(size=(case.orc.S, 3))).astype(np.float32), device=DEV)
+    x_al = np_(lib().lmrs_pcg(case.fr, b, 0.1, 8))
+    buf = torch.zeros(case.P + 1, device=DEV)
+    x_un = buf[1:]
+    assert x_un.data_ptr() % 16 != 0
+    lib().lmrs_pcg(case.fr, b, 0.1, 8, x=x_un)
+    e = rel(np_(x_un), x_al)
+    log(f"  unaligned vs aligned PCG rel {e:.2e}")
+    assert e < 1e-4
+
+
 def test_sampler_bit_exact():
     L = lib()
     cams = synth.sphere_cameras(6, 4.0, 128, 96, 60.0, 0)
