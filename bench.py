@@ -375,9 +375,12 @@ def main():
     rep = torch.zeros(L.REPORT_FLOATS, device=dev)
     rng = np.random.default_rng(w.seed)
     ws = None
+    # the views of every LM step, drawn up front and kept on the device
+    all_vids = torch.tensor(np.stack([rng.choice(w.cams.shape[0], V, replace=False)
+                                      for _ in range(args.warmup + args.steps)]).astype(np.int32), device=dev)
 
     def step(it):
-        view_ids.copy_(torch.tensor(rng.choice(w.cams.shape[0], V, replace=False).astype(np.int32)))
+        view_ids.copy_(all_vids[it])
         # the binding allocates a larger workspace itself if the tile lists outgrow ws
         L.lmrs_lm_step(fr, targets, L.lm_params(it, w.cg_iters, w.lam, seed=w.seed, sampler=sampler), report=rep,
                        ws=ws)

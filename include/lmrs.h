@@ -15,7 +15,10 @@
  * --------------------------------
  * Memory.  Every pointer marked "device" is HBM owned by the caller; the
  *   library never allocates, frees or retains device memory, and keeps no
- *   state between calls. Host structs are read during the call only.
+ *   device state between calls. Host structs are read during the call only.
+ *   For its wait on the tile-instance count, lmrs_bin_tiles / lmrs_lm_step
+ *   create once per host thread one HIP event and one pinned host word, kept
+ *   for the life of the thread.
  * Streams. `stream` is a hipStream_t passed as void* (NULL = default stream).
  *   Work is enqueued and the call returns, except lmrs_bin_tiles and
  *   lmrs_lm_step, which wait for the tile-instance count (see there). Calls

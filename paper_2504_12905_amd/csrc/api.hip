@@ -208,15 +208,30 @@ void pcg_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opt
   if (report) launch_pcg_report(b, iters, P, ps, report, st);
 }
 
-// count, wait for the total, then emit and sort.
+// Count, then the per-view depth sort (it does not need the count, so it
+// runs on the device while the host waits for the total), then emit and sort.
 lmrs_status bin_sequence(const lmrs_frame* f, const FrameDims& d, const Scratch& s, hipStream_t st,
                          int64_t* total_out = nullptr) {
+  // per host thread: an event after the count's copy and a pinned host word
+  // for the count (kept for the life of the thread)
+  static thread_local hipEvent_t counted = nullptr;
+  static thread_local int64_t* count_host = nullptr;
+  if (!counted && hipEventCreateWithFlags(&counted, hipEventDisableTiming) != hipSuccess) {
+    counted = nullptr;
+    return hip_check("bin count event");
+  }
+  if (!count_host && hipHostMalloc(reinterpret_cast<void**>(&count_host), sizeof(int64_t)) != hipSuccess) {
+    count_host = nullptr;
+    return hip_check("bin count buffer");
+  }
   launch_bin_count(f, d, s.bin, st);
-  int64_t total = 0;
-  if (hipMemcpyAsync(&total, f->n_instances, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
+  if (hipMemcpyAsync(count_host, f->n_instances, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipEventRecord(counted, st) != hipSuccess)
     return hip_check("bin count");
+  launch_view_sort(f, d, s.bin, st);
+  if (hipEventSynchronize(counted) != hipSuccess) return hip_check("bin count");
   LMRS_TRY(hip_check("bin count"));
+  const int64_t total = *count_host;
   if (total > f->capacity)
     return fail(LMRS_ECAPACITY, "%lld tile-list entries needed, capacity %lld", (long long)total,
                 (long long)f->capacity);

@@ -429,7 +429,7 @@ void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hip
   scan_kernel<<<1, 1024, 0, s>>>(b.counts, m, f->tile_start, f->n_instances);
 }
 
-void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
+void launch_view_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
   // depth ranks per view: four 8-bit passes over the FP32 depth bits
   const int64_t vn = (int64_t)d.V * d.n;
   const int np = (d.n + kViewPart - 1) / kViewPart;
@@ -444,7 +444,9 @@ void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b,
                                                           d.V, 8 * pass, b.vcount);
   }
   view_rank_kernel<<<vblocks, kViewThreads, 0, s>>>(b.vval[0], d.n, d.V, b.rank, b.order);
+}
 
+void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
   const int nc = bin_chunks(d.n);
   const size_t lds = (size_t)d.T * sizeof(int32_t);
   emit_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), b.rank, d.n, d.TX,

@@ -45,6 +45,9 @@ int view_sort_count_ints(int n, int V);
 constexpr int kMaxTilesPerView = 16384;  // LDS histogram of one view's tiles (64 KB)
 int bin_chunks(int n);
 void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s);
+// per-view depth ranks (independent of the tile counts)
+void launch_view_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s);
+// emission of the ranks and per-tile sort (after launch_view_sort)
 void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s);
 
 // splatting (kernels_splat.hip)
