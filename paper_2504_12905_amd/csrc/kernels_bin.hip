@@ -19,15 +19,16 @@
 // 5. emit: each (view, Gaussian) writes its depth rank (32 bits) into its
 //    tiles' segments at (tile start + chunk offset + LDS cursor).
 // 6. sort: one workgroup per tile sorts its segment of ranks by a stable LSD
-//    radix sort (8-bit digits, as many passes as the ranks have bits) and
-//    writes ids = rank -> id of the view. Each pass counts digits per wave
-//    over the wave's quarter of the segment, turns the counts into
-//    (digit, wave) offsets, and then every wave scatters its quarter in
-//    order, 64 keys at a time, ranking equal digits within the wave from 8
-//    ballots. Ranks are unique within a view, so the order is the depth order
-//    with ties by id, and no pass is longer than the segment: the tiles of
-//    hundreds of thousands of entries near the centre of large scenes cost
-//    a few linear passes instead of a merge tree.
+//    radix sort (8- or 9-bit digits, as few passes as the ranks allow) and
+//    writes ids = rank -> id of the view. A block of up to 2048 keys sits in
+//    LDS: each wave counts the digits of its quarter, the counts become
+//    (digit, wave) offsets, and every wave scatters its quarter in order, 64
+//    keys at a time, ranking equal digits within the 64 by ballots (one per
+//    digit bit). Longer segments take the digit totals of the whole segment
+//    per pass, then sort 2048-key blocks this way and write each block out
+//    as runs of consecutive addresses. Ranks are unique within a view, so the
+//    order is the depth order with ties by id, and every pass is linear in
+//    the segment.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(kBinThreads) void emit_kernel(const int4* __restric
 }
 
 // ------------------------------------------------------------ radix sort
-// Stable LSD radix sorts of 32-bit keys with 8-bit digits. A "part" is a
+// Stable LSD radix sorts of 32-bit keys, digits of up to 9 bits. A "part" is a
 // contiguous range of the input owned by one wave: the wave counts the
 // digits of its part, the counts of all parts become (digit, part) offsets,
 // and the wave scatters its part in order, 64 keys at a time, ranking equal
@@ -322,31 +323,62 @@ constexpr int kTileSortThreads = 256;
 constexpr int kTileSortWaves = kTileSortThreads / kWave;
 constexpr int kTileSortLds = 2048;
 
+// The tile sort uses digits of 9 bits when that saves a pass (ranks of 17
+// or 18 bits: two passes instead of three), else of 8 bits (fewer, longer
+// runs of equal digits in the block write-out). Counters for up to 512
+// digits, two per thread of the workgroup.
+constexpr int kTileBins = 512;
+static_assert(kTileBins == 2 * kTileSortThreads, "two digits per thread");
+
+// Exclusive scan over the kTileBins digit totals, thread t owning digits 2t
+// and 2t + 1 (totals x0, x1); returns the start of digit 2t. wsum: LDS, 4 ints.
+__device__ __forceinline__ int pair_exclusive_scan(int x0, int x1, int* wsum) {
+  const int tid = threadIdx.x, lane = lane_id();
+  const int x = x0 + x1;
+  int y = x;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int z = __shfl_up(y, d, kWave);
+    if (lane >= d) y += z;
+  }
+  if (lane == kWave - 1) wsum[tid / kWave] = y;
+  __syncthreads();
+  int run = y - x;
+  for (int v = 0; v < tid / kWave; ++v) run += wsum[v];
+  __syncthreads();
+  return run;
+}
+
 // One stable counting pass of a block that is in LDS: src -> dst (both LDS,
 // blen <= kTileSortLds) by digit; leaves the block's digit totals in tot[]
-// and their exclusive prefix in start[] (thread d owns digit d). Every
-// thread of the workgroup calls it.
+// and their exclusive prefix in start[]. Every thread of the workgroup calls it.
 __device__ void lds_block_pass(const uint32_t* src, uint32_t* dst, int blen, int shift, int bins,
-                               int (*cnt)[kRadixBins], int* wsum, int* tot, int* start) {
+                               int (*cnt)[kTileBins], int* wsum, int* tot, int* start) {
   const int tid = threadIdx.x, w = tid / kWave;
   const int64_t b0 = (int64_t)blen * w / kTileSortWaves, b1 = (int64_t)blen * (w + 1) / kTileSortWaves;
-  for (int i = tid; i < kTileSortWaves * kRadixBins; i += kTileSortThreads) (&cnt[0][0])[i] = 0;
+  for (int i = tid; i < kTileSortWaves * kTileBins; i += kTileSortThreads) (&cnt[0][0])[i] = 0;
   __syncthreads();
   part_count(src, b0, b1, shift, bins, cnt[w]);
   __syncthreads();
-  int c[kTileSortWaves], t = 0;
+  int c0[kTileSortWaves], c1[kTileSortWaves], t0 = 0, t1 = 0;
 #pragma unroll
   for (int v = 0; v < kTileSortWaves; ++v) {
-    c[v] = cnt[v][tid];
-    t += c[v];
+    c0[v] = cnt[v][2 * tid];
+    c1[v] = cnt[v][2 * tid + 1];
+    t0 += c0[v];
+    t1 += c1[v];
   }
-  int run = bins_exclusive_scan(t, wsum);
-  tot[tid] = t;
-  start[tid] = run;
+  int run0 = pair_exclusive_scan(t0, t1, wsum), run1 = run0 + t0;
+  tot[2 * tid] = t0;
+  tot[2 * tid + 1] = t1;
+  start[2 * tid] = run0;
+  start[2 * tid + 1] = run1;
 #pragma unroll
   for (int v = 0; v < kTileSortWaves; ++v) {
-    cnt[v][tid] = run;
-    run += c[v];
+    cnt[v][2 * tid] = run0;
+    cnt[v][2 * tid + 1] = run1;
+    run0 += c0[v];
+    run1 += c1[v];
   }
   __syncthreads();
   part_scatter(src, dst, nullptr, nullptr, b0, b1, shift, bins, cnt[w]);
@@ -357,10 +389,11 @@ __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64
                                                                      uint32_t* __restrict__ keys,
                                                                      uint32_t* __restrict__ tmp,
                                                                      const int32_t* __restrict__ order, int n, int T,
-                                                                     int rank_bits, int32_t* __restrict__ ids) {
-  __shared__ int cnt[kTileSortWaves][kRadixBins];
-  __shared__ int wsum[kRadixBins / kWave];
-  __shared__ int tot[kRadixBins], start[kRadixBins], goff[kRadixBins];
+                                                                     int rank_bits, int digit_bits,
+                                                                     int32_t* __restrict__ ids) {
+  __shared__ int cnt[kTileSortWaves][kTileBins];
+  __shared__ int wsum[kTileSortThreads / kWave];
+  __shared__ int tot[kTileBins], start[kTileBins], goff[kTileBins];
   __shared__ uint32_t buf[2][kTileSortLds];
   const int64_t a = tile_start[blockIdx.x];
   const int64_t len = tile_start[blockIdx.x + 1] - a;
@@ -371,8 +404,9 @@ __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64
     for (int i = tid; i < len; i += kTileSortThreads) buf[0][i] = keys[a + i];
     __syncthreads();
     int q = 0;
-    for (int shift = 0; shift < rank_bits; shift += 8, q ^= 1)
-      lds_block_pass(buf[q], buf[q ^ 1], (int)len, shift, 1 << min(8, rank_bits - shift), cnt, wsum, tot, start);
+    for (int shift = 0; shift < rank_bits; shift += digit_bits, q ^= 1)
+      lds_block_pass(buf[q], buf[q ^ 1], (int)len, shift, 1 << min(digit_bits, rank_bits - shift), cnt, wsum, tot,
+                     start);
     for (int i = tid; i < len; i += kTileSortThreads) ids[a + i] = ord[buf[q][i]];
     return;
   }
@@ -383,16 +417,21 @@ __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64
   uint32_t* src = keys + a;
   uint32_t* dst = tmp + a;
   const int64_t b0 = len * w / kTileSortWaves, b1 = len * (w + 1) / kTileSortWaves;
-  for (int shift = 0; shift < rank_bits; shift += 8) {
-    const int bins = 1 << min(8, rank_bits - shift);
-    for (int i = tid; i < kTileSortWaves * kRadixBins; i += kTileSortThreads) (&cnt[0][0])[i] = 0;
+  for (int shift = 0; shift < rank_bits; shift += digit_bits) {
+    const int bins = 1 << min(digit_bits, rank_bits - shift);
+    for (int i = tid; i < kTileSortWaves * kTileBins; i += kTileSortThreads) (&cnt[0][0])[i] = 0;
     __syncthreads();
     part_count(src, b0, b1, shift, bins, cnt[w]);
     __syncthreads();
-    int t = 0;
+    int t0 = 0, t1 = 0;
 #pragma unroll
-    for (int v = 0; v < kTileSortWaves; ++v) t += cnt[v][tid];
-    goff[tid] = bins_exclusive_scan(t, wsum);
+    for (int v = 0; v < kTileSortWaves; ++v) {
+      t0 += cnt[v][2 * tid];
+      t1 += cnt[v][2 * tid + 1];
+    }
+    const int run0 = pair_exclusive_scan(t0, t1, wsum);
+    goff[2 * tid] = run0;
+    goff[2 * tid + 1] = run0 + t0;
     __syncthreads();
     for (int64_t base = 0; base < len; base += kTileSortLds) {
       const int blen = (int)min<int64_t>(kTileSortLds, len - base);
@@ -405,7 +444,8 @@ __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64
         dst[goff[d] + (i - start[d])] = key;
       }
       __syncthreads();
-      goff[tid] += tot[tid];
+      goff[2 * tid] += tot[2 * tid];
+      goff[2 * tid + 1] += tot[2 * tid + 1];
       __syncthreads();
     }
     uint32_t* tt = src;
@@ -452,8 +492,9 @@ void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b,
   emit_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), b.rank, d.n, d.TX,
                                                       d.T, nc, b.chunk_hist, f->tile_start, b.keys);
   const int rank_bits = d.n > 1 ? 32 - __builtin_clz((unsigned)(d.n - 1)) : 0;
-  tile_sort_kernel<<<(unsigned)((int64_t)d.V * d.T), kTileSortThreads, 0, s>>>(f->tile_start, b.keys, b.tmp,
-                                                                              b.order, d.n, d.T, rank_bits, f->ids);
+  const int digit_bits = (rank_bits + 8) / 9 < (rank_bits + 7) / 8 ? 9 : 8;
+  tile_sort_kernel<<<(unsigned)((int64_t)d.V * d.T), kTileSortThreads, 0, s>>>(
+      f->tile_start, b.keys, b.tmp, b.order, d.n, d.T, rank_bits, digit_bits, f->ids);
 }
 
 int view_sort_count_ints(int n, int V) { return V * ((n + kViewPart - 1) / kViewPart) * kRadixBins; }
