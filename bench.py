@@ -78,10 +78,11 @@ def render_targets(L, torch, w, beta_gt, cams, dev):
     return targets
 
 
-def traffic_from_profile(kernel_hash: str):
+def traffic_from_profile(kernel_hash: str, default_workload: bool):
     """HBM bytes per launch of the fused splat kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    rocprofv3 counter summary, if it was taken on the current kernel source and
+    on the workload being timed (the summary covers the default 100k one)."""
+    if not default_workload or not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
     for line in open(TRAFFIC_FILE):
@@ -467,7 +468,7 @@ def main():
     tflops = f_alg / t_splat / 1e12
     hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tflops / FP32_VECTOR_PEAK_TFLOPS
     kernel_hash = hashlib.sha256(open(SPLAT_SOURCE, "rb").read()).hexdigest()
-    traffic = traffic_from_profile(kernel_hash)
+    traffic = traffic_from_profile(kernel_hash, args.workload == "cfg1" and args.n is None)
     bound_alu = alu_frac > hbm_frac
     roofline = {
         "kernel": "deriv_kernel<3> (fused J p / weight / J^T u splat of lmrs_gn_product)",

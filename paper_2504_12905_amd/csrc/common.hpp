@@ -444,6 +444,30 @@ __device__ __forceinline__ float scan_add(float x) {
   return x;
 }
 
+// Inclusive product scan over the same DPP steps. Each step is one
+// v_mul_f32_dpp with bound_ctrl off, so a lane without a source (and a row
+// outside the mask) keeps its value, i.e. multiplies by 1; the compiler folds
+// no multiply into DPP, hence the assembly. Every DPP read of a VGPR written
+// by the VALU instruction before it needs two wait states (s_nop 1), also the
+// first one and whatever reads the result after the block.
+__device__ __forceinline__ float scan_mul(float x) {
+  asm("s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+      "s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+      "s_nop 1"
+      : "+v"(x));
+  return x;
+}
+
 // Sum over all 64 lanes (wave-uniform).
 __device__ __forceinline__ float wave_total(float x) { return readlane(scan_add(x), kWave - 1); }
 

@@ -11,12 +11,13 @@
 // gradient. Here the lanes own list entries instead: a chunk of 64 entries
 // of the tile's depth-sorted list is loaded, one record per lane, and the
 // wave walks the tile's sampled pixels one after another. For each pixel
-// the transmittance in front of every entry is 2^(prefix sum of
-// log2(1 - alpha)) across the lanes (a DPP scan), carried from chunk to
-// chunk; J p needs one more prefix sum for its derivative. J^T u walks the
-// chunks back to front with the lane order reversed inside a chunk, so the
-// colour blended behind an entry and the transmittance product behind it are
-// prefix sums as well. Each lane then holds its Gaussian's screen-space
+// the transmittance in front of every entry is a prefix product of
+// (1 - alpha) across the lanes (a DPP scan), carried from chunk to chunk (the
+// render, which decides where a pixel stops, sums log2(1 - alpha) instead
+// and compares with log2 of the threshold); J p needs one prefix sum more for
+// its derivative. J^T u walks the chunks back to front with the lane order
+// reversed inside a chunk, so the colour blended behind an entry and the
+// transmittance product behind it are prefix scans as well. Each lane then holds its Gaussian's screen-space
 // gradient summed over all pixels of the tile and issues one atomic add per
 // component: no per-Gaussian cross-lane reduction. A pixel's loop stops at
 // its last blended entry (`last` from the render), so work follows the
@@ -399,11 +400,12 @@ __device__ __forceinline__ FwdStep fwd_step(const RecF& r, const RecF& dr, int e
   const float ds = -al.q1 * (dr.f11 * al.dx + dr.f12 * al.dy + r.f11 * dr.u + r.f12 * dr.v) -
                    al.q2 * (dr.f22 * al.dy + r.f22 * dr.v);
   const float da = inc && !al.capped ? al.es * (dr.o + r.o * ds) : 0.f;
-  const float lg = inc ? __log2f(1.f - a) : 0.f;
-  const float q = inc ? -da * __builtin_amdgcn_rcpf(1.f - a) : 0.f;
-  const float Linc = scan_add(lg);
+  const float om = inc ? 1.f - a : 1.f;
+  const float rom = __builtin_amdgcn_rcpf(om);
+  const float q = inc ? -da * rom : 0.f;
+  const float Pinc = scan_mul(om);  // product of (1 - alpha) up to and including this entry
   const float Qinc = scan_add(q);
-  const float pin = __builtin_amdgcn_exp2f(Linc - lg);  // product of (1 - alpha) in front, within the chunk
+  const float pin = Pinc * rom;  // product of (1 - alpha) in front, within the chunk
   const float Tn = Tc * pin;
   const float dTn = pin * (dTc + Tc * (Qinc - q));
   const float aT = a * Tn, gT = da * Tn + a * dTn;
@@ -413,7 +415,7 @@ __device__ __forceinline__ FwdStep fwd_step(const RecF& r, const RecF& dr, int e
   st.cb = inc ? dr.b * aT + r.b * gT : 0.f;
   st.Tc = Tc;
   st.dTc = dTc;
-  st.tp = __builtin_amdgcn_exp2f(readlane(Linc, kWave - 1));
+  st.tp = readlane(Pinc, kWave - 1);
   st.tq = readlane(Qinc, kWave - 1);
   return st;
 }
@@ -592,10 +594,10 @@ __device__ __forceinline__ void deriv_tile(
               pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
           const bool inc = valid && e <= lj && al.inc;
           const float a = inc ? al.a : 0.f;
-          const float lg = log2_om(inc, a);
-          const float Linc = scan_add(lg);  // over this entry and the ones behind it in the chunk
+          // product of (1 - alpha) over this entry and the ones behind it in the chunk
+          const float rP = __builtin_amdgcn_rcpf(scan_mul(inc ? 1.f - a : 1.f));
           const float Tafter = readlane(sa[s], l);
-          const float Tn = Tafter * __builtin_amdgcn_exp2f(-Linc);
+          const float Tn = Tafter * rP;
           const float u0 = readlane(su0[s], l), u1 = readlane(su1[s], l), u2 = readlane(su2[s], l);
           const float urgb = u0 * r.r + u1 * r.g + u2 * r.b;
           const float term = inc ? urgb * a * Tn : 0.f;
@@ -618,7 +620,7 @@ __device__ __forceinline__ void deriv_tile(
               g[4] -= gs * (al.q2 * al.dy);
             }
           }
-          sa[s] = writelane(sa[s], Tafter * __builtin_amdgcn_exp2f(-readlane(Linc, kWave - 1)), l);
+          sa[s] = writelane(sa[s], Tafter * readlane(rP, kWave - 1), l);
           sb[s] = writelane(sb[s], S + readlane(Sinc, kWave - 1), l);
         }
       }
@@ -743,10 +745,9 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
             pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
         const bool inc = valid && e <= lj && al.inc;
         const float a = inc ? al.a : 0.f;
-        const float lg = log2_om(inc, a);
-        const float Linc = scan_add(lg);
+        const float rP = __builtin_amdgcn_rcpf(scan_mul(inc ? 1.f - a : 1.f));
         const float Tafter = readlane(sT[s], l);
-        const float Tn = Tafter * __builtin_amdgcn_exp2f(-Linc);
+        const float Tn = Tafter * rP;
         const float S[3] = {readlane(sS0[s], l), readlane(sS1[s], l), readlane(sS2[s], l)};
         float behind[3], tot[3];
         for (int ch = 0; ch < 3; ++ch) {
@@ -790,7 +791,7 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
             }
           }
         }
-        sT[s] = writelane(sT[s], Tafter * __builtin_amdgcn_exp2f(-readlane(Linc, kWave - 1)), l);
+        sT[s] = writelane(sT[s], Tafter * readlane(rP, kWave - 1), l);
         sS0[s] = writelane(sS0[s], S[0] + tot[0], l);
         sS1[s] = writelane(sS1[s], S[1] + tot[1], l);
         sS2[s] = writelane(sS2[s], S[2] + tot[2], l);
