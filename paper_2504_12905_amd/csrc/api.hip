@@ -74,14 +74,13 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
     s.bin.counts = c.take<int32_t>((size_t)d.V * d.T);
     s.bin.chunk_hist = c.take<int32_t>((size_t)d.V * bin_chunks(d.n) * d.T);
     s.bin.keys = c.take<uint32_t>((size_t)capacity);
-    s.bin.tmp = c.take<uint32_t>((size_t)capacity);
     for (int q = 0; q < 2; ++q) {
       s.bin.vkey[q] = c.take<uint32_t>((size_t)VN);
       s.bin.vval[q] = c.take<uint32_t>((size_t)VN);
     }
-    s.bin.rank = c.take<int32_t>((size_t)VN);
-    s.bin.order = c.take<int32_t>((size_t)VN);
+    s.bin.order = reinterpret_cast<int32_t*>(s.bin.vval[0]);
     s.bin.vcount = c.take<int32_t>((size_t)view_sort_count_ints(d.n, d.V));
+    s.bin.area_part = c.take<int64_t>(kBinAreaParts);
   }
   if (need_tan) s.tan = c.take<float>((size_t)VN * LMRS_REC);
   if (need_grad) s.grad2d = c.take<float>((size_t)VN * kGradRow);
@@ -224,11 +223,13 @@ lmrs_status bin_sequence(const lmrs_frame* f, const FrameDims& d, const Scratch&
     count_host = nullptr;
     return hip_check("bin count buffer");
   }
-  launch_bin_count(f, d, s.bin, st);
+  launch_bin_total(f, d, s.bin, st);
   if (hipMemcpyAsync(count_host, f->n_instances, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipEventRecord(counted, st) != hipSuccess)
     return hip_check("bin count");
+  // while the host waits for the count: depth ranks, per-chunk tile counts, tile_start
   launch_view_sort(f, d, s.bin, st);
+  launch_bin_count(f, d, s.bin, st);
   if (hipEventSynchronize(counted) != hipSuccess) return hip_check("bin count");
   LMRS_TRY(hip_check("bin count"));
   const int64_t total = *count_host;

@@ -1,34 +1,29 @@
 // Tile binning and depth sort (Sec. 3: Gaussians are sorted by depth before
 // blending; Supp. A: 16x16 tiles).
 //
-// Gaussians of one view are processed in chunks of kChunk by one workgroup,
-// which keeps a histogram / cursor over all tiles of the view in LDS, so the
-// only atomics are LDS atomics inside a workgroup (a single hot tile can hold
-// thousands of entries; global atomics on it serialise across the chip).
-// 1. hist: per (view, chunk) count of the chunk's Gaussians per tile.
-// 2. column scan: per (view, tile), the chunks' counts become running offsets
-//    and the tile total is formed.
-// 3. scan: exclusive prefix sum over the V*T totals -> tile_start (int64),
-//    total -> n_instances.
-// 4. depth ranks: one workgroup per view sorts (depth bits, Gaussian id)
-//    pairs by a stable LSD radix sort (ties keep ascending id), giving each
-//    Gaussian its depth rank in the view and the rank -> id table.
-//    Depths are > znear > 0 for every Gaussian that is emitted, so their IEEE
-//    bits order like the values (culled ones sort anywhere; they are never
-//    emitted).
-// 5. emit: each (view, Gaussian) writes its depth rank (32 bits) into its
-//    tiles' segments at (tile start + chunk offset + LDS cursor).
-// 6. sort: one workgroup per tile sorts its segment of ranks by a stable LSD
-//    radix sort (8- or 9-bit digits, as few passes as the ranks allow) and
-//    writes ids = rank -> id of the view. A block of up to 2048 keys sits in
-//    LDS: each wave counts the digits of its quarter, the counts become
-//    (digit, wave) offsets, and every wave scatters its quarter in order, 64
-//    keys at a time, ranking equal digits within the 64 by ballots (one per
-//    digit bit). Longer segments take the digit totals of the whole segment
-//    per pass, then sort 2048-key blocks this way and write each block out
-//    as runs of consecutive addresses. Ranks are unique within a view, so the
-//    order is the depth order with ties by id, and every pass is linear in
-//    the segment.
+// 1. total: the number of tile-list entries (sum of the rect areas), copied
+//    to the host first so that its wait overlaps the steps below.
+// 2. depth ranks: per view, a stable LSD radix sort of (depth bits, Gaussian
+//    id) over all waves of the grid (ties keep ascending id) gives each
+//    Gaussian its depth rank and the rank -> id table. Depths are > znear > 0
+//    for every Gaussian that is emitted, so their IEEE bits order like the
+//    values (culled ones sort anywhere; they are never emitted).
+// 3. hist: the Gaussians of a view in rank order, cut into chunks of kChunk
+//    ranks; one workgroup per (view, chunk) counts its Gaussians per tile in
+//    LDS (the only atomics are LDS atomics: a hot tile can hold thousands of
+//    entries, and global atomics on it would serialise across the chip).
+// 4. column scan per (view, tile) over the chunks -> running offsets; scan
+//    over the V*T totals -> tile_start (int64).
+// 5. emit: each chunk writes its Gaussians' ranks into their tiles'
+//    segments at (tile start + chunk offset + LDS cursor). A tile's list is
+//    thereby ordered by chunk, i.e. by rank up to the order inside each
+//    chunk's run, and a run holds at most kChunk entries.
+// 6. sort: one workgroup per tile takes windows of up to kTileSortLds
+//    entries that end at a run boundary (the runs are read off the ranks),
+//    sorts each in LDS by a stable LSD radix sort of the ranks relative to
+//    the window's first chunk (8- or 9-bit digits), and writes ids = rank ->
+//    id. Every entry is read and written once; ranks are unique within a
+//    view, so the order is the depth order with ties by id.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -36,20 +31,49 @@ namespace lmrs {
 
 namespace {
 
-constexpr int kChunk = 8192;  // Gaussians per binning workgroup
+constexpr int kChunkBits = 11;
+constexpr int kChunk = 1 << kChunkBits;  // ranks per binning workgroup (and entries per run, at most)
+static_assert(kChunk <= 2048, "a run must fit one sort window");
 
 constexpr int kBinThreads = 1024;
 
-__global__ __launch_bounds__(kBinThreads) void hist_kernel(const int4* __restrict__ rect, int n, int TX, int T,
-                                                            int n_chunks, int32_t* __restrict__ chunk_hist) {
+__device__ __forceinline__ int rect_area(const int4& rc) {
+  return rc.x < rc.z && rc.y < rc.w ? (rc.z - rc.x) * (rc.w - rc.y) : 0;
+}
+
+// Sum of the rect areas of all (view, Gaussian) pairs: partial sums per block.
+constexpr int kAreaBlocks = kBinAreaParts;
+__global__ __launch_bounds__(256) void area_kernel(const int4* __restrict__ rect, int64_t m,
+                                                   int64_t* __restrict__ part) {
+  __shared__ double s_red[256];
+  int64_t acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+    acc += rect_area(rect[i]);
+  // exact: the sums stay far below 2^53
+  const double tot = block_sum((double)acc, s_red);
+  if (threadIdx.x == 0) part[blockIdx.x] = (int64_t)tot;
+}
+
+__global__ __launch_bounds__(256) void area_total_kernel(const int64_t* __restrict__ part, int np,
+                                                         int64_t* __restrict__ total) {
+  __shared__ double s_red[256];
+  int64_t acc = 0;
+  for (int i = threadIdx.x; i < np; i += 256) acc += part[i];
+  const double tot = block_sum((double)acc, s_red);
+  if (threadIdx.x == 0) *total = (int64_t)tot;
+}
+
+__global__ __launch_bounds__(kBinThreads) void hist_kernel(const int4* __restrict__ rect,
+                                                            const int32_t* __restrict__ order, int n, int TX,
+                                                            int T, int n_chunks, int32_t* __restrict__ chunk_hist) {
   extern __shared__ int32_t s_hist[];
   const int chunk = blockIdx.x, v = blockIdx.y;
   for (int t = threadIdx.x; t < T; t += kBinThreads) s_hist[t] = 0;
   __syncthreads();
-  const int g0 = chunk * kChunk;
-  const int g1 = min(n, g0 + kChunk);
-  for (int g = g0 + (int)threadIdx.x; g < g1; g += kBinThreads) {
-    const int4 rc = rect[(size_t)v * n + g];
+  const int r0 = chunk * kChunk;
+  const int r1 = min(n, r0 + kChunk);
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBinThreads) {
+    const int4 rc = rect[(size_t)v * n + order[(size_t)v * n + r]];
     for (int ty = rc.y; ty < rc.w; ++ty)
       for (int tx = rc.x; tx < rc.z; ++tx) atomicAdd(&s_hist[ty * TX + tx], 1);
   }
@@ -59,17 +83,25 @@ __global__ __launch_bounds__(kBinThreads) void hist_kernel(const int4* __restric
 }
 
 // Per (view, tile): chunk counts -> running offsets; tile total -> counts.
+// The counts are read kColUnroll chunks ahead of the running sum.
+constexpr int kColUnroll = 8;
 __global__ __launch_bounds__(256) void colscan_kernel(int32_t* __restrict__ chunk_hist, int V, int T,
                                                       int n_chunks, int32_t* __restrict__ counts) {
   const int64_t vt = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (vt >= (int64_t)V * T) return;
   const int v = (int)(vt / T), t = (int)(vt % T);
+  int32_t* h = chunk_hist + (size_t)v * n_chunks * T + t;
   int32_t run = 0;
-  for (int c = 0; c < n_chunks; ++c) {
-    int32_t* h = chunk_hist + ((size_t)v * n_chunks + c) * T + t;
-    const int32_t x = *h;
-    *h = run;
-    run += x;
+  for (int c0 = 0; c0 < n_chunks; c0 += kColUnroll) {
+    int32_t x[kColUnroll];
+#pragma unroll
+    for (int u = 0; u < kColUnroll; ++u) x[u] = c0 + u < n_chunks ? h[(size_t)(c0 + u) * T] : 0;
+#pragma unroll
+    for (int u = 0; u < kColUnroll; ++u)
+      if (c0 + u < n_chunks) {
+        h[(size_t)(c0 + u) * T] = run;
+        run += x[u];
+      }
   }
   counts[vt] = run;
 }
@@ -105,7 +137,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(int32_t* __restrict__ counts
 }
 
 __global__ __launch_bounds__(kBinThreads) void emit_kernel(const int4* __restrict__ rect,
-                                                            const int32_t* __restrict__ rank, int n, int TX, int T,
+                                                            const int32_t* __restrict__ order, int n, int TX, int T,
                                                             int n_chunks, const int32_t* __restrict__ chunk_hist,
                                                             const int64_t* __restrict__ tile_start,
                                                             uint32_t* __restrict__ keys) {
@@ -115,18 +147,16 @@ __global__ __launch_bounds__(kBinThreads) void emit_kernel(const int4* __restric
   for (int t = threadIdx.x; t < T; t += kBinThreads) s_cur[t] = off[t];
   __syncthreads();
   const int64_t* ts = tile_start + (size_t)v * T;
-  const int g0 = chunk * kChunk;
-  const int g1 = min(n, g0 + kChunk);
-  for (int g = g0 + (int)threadIdx.x; g < g1; g += kBinThreads) {
-    const size_t vg = (size_t)v * n + g;
-    const int4 rc = rect[vg];
+  const int r0 = chunk * kChunk;
+  const int r1 = min(n, r0 + kChunk);
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBinThreads) {
+    const int4 rc = rect[(size_t)v * n + order[(size_t)v * n + r]];
     if (rc.x >= rc.z) continue;
-    const uint32_t key = (uint32_t)rank[vg];
     for (int ty = rc.y; ty < rc.w; ++ty)
       for (int tx = rc.x; tx < rc.z; ++tx) {
         const int t = ty * TX + tx;
         const int slot = atomicAdd(&s_cur[t], 1);
-        keys[ts[t] + slot] = key;
+        keys[ts[t] + slot] = (uint32_t)r;
       }
   }
 }
@@ -304,29 +334,15 @@ __global__ __launch_bounds__(kViewThreads) void view_scatter_kernel(const uint32
   part_scatter(ksrc, kdst + vb, vsrc, vdst + vb, b0, b1, shift, kRadixBins, cur[w]);
 }
 
-__global__ __launch_bounds__(kViewThreads) void view_rank_kernel(const uint32_t* __restrict__ sorted_val, int n,
-                                                                  int V, int32_t* __restrict__ rank,
-                                                                  int32_t* __restrict__ order) {
-  const int64_t i = (int64_t)blockIdx.x * kViewThreads + threadIdx.x;
-  if (i >= (int64_t)V * n) return;
-  const int64_t vb = i / n * n;
-  const uint32_t g = sorted_val[i];
-  order[i] = (int32_t)g;
-  rank[vb + g] = (int32_t)(i - vb);
-}
-
-// ---- per-tile sort of depth ranks: one workgroup per tile, wave w owns the
-// part [len w / 4, len (w + 1) / 4) of the segment. Segments of up to
-// kTileSortLds keys are sorted in LDS (one coalesced load and store), longer
-// ones pass through the keys / tmp buffers in global memory.
+// ---- per-tile sort of depth ranks: one workgroup per tile, windows of up to
+// kTileSortLds entries in LDS, wave w owning the part [len w / 4,
+// len (w + 1) / 4) of a window.
 constexpr int kTileSortThreads = 256;
 constexpr int kTileSortWaves = kTileSortThreads / kWave;
 constexpr int kTileSortLds = 2048;
+static_assert(kChunk <= kTileSortLds, "a run must fit one sort window");
 
-// The tile sort uses digits of 9 bits when that saves a pass (ranks of 17
-// or 18 bits: two passes instead of three), else of 8 bits (fewer, longer
-// runs of equal digits in the block write-out). Counters for up to 512
-// digits, two per thread of the workgroup.
+// Digits of up to 9 bits; counters for up to 512 digits, two per thread.
 constexpr int kTileBins = 512;
 static_assert(kTileBins == 2 * kTileSortThreads, "two digits per thread");
 
@@ -350,10 +366,9 @@ __device__ __forceinline__ int pair_exclusive_scan(int x0, int x1, int* wsum) {
 }
 
 // One stable counting pass of a block that is in LDS: src -> dst (both LDS,
-// blen <= kTileSortLds) by digit; leaves the block's digit totals in tot[]
-// and their exclusive prefix in start[]. Every thread of the workgroup calls it.
+// blen <= kTileSortLds) by digit. Every thread of the workgroup calls it.
 __device__ void lds_block_pass(const uint32_t* src, uint32_t* dst, int blen, int shift, int bins,
-                               int (*cnt)[kTileBins], int* wsum, int* tot, int* start) {
+                               int (*cnt)[kTileBins], int* wsum) {
   const int tid = threadIdx.x, w = tid / kWave;
   const int64_t b0 = (int64_t)blen * w / kTileSortWaves, b1 = (int64_t)blen * (w + 1) / kTileSortWaves;
   for (int i = tid; i < kTileSortWaves * kTileBins; i += kTileSortThreads) (&cnt[0][0])[i] = 0;
@@ -369,10 +384,6 @@ __device__ void lds_block_pass(const uint32_t* src, uint32_t* dst, int blen, int
     t1 += c1[v];
   }
   int run0 = pair_exclusive_scan(t0, t1, wsum), run1 = run0 + t0;
-  tot[2 * tid] = t0;
-  tot[2 * tid + 1] = t1;
-  start[2 * tid] = run0;
-  start[2 * tid + 1] = run1;
 #pragma unroll
   for (int v = 0; v < kTileSortWaves; ++v) {
     cnt[v][2 * tid] = run0;
@@ -385,85 +396,69 @@ __device__ void lds_block_pass(const uint32_t* src, uint32_t* dst, int blen, int
   __syncthreads();
 }
 
+// A tile's list arrives as runs of ranks, one per chunk in chunk order (rank
+// >> kChunkBits non-decreasing along the list), each run unordered and at
+// most kChunk long. A window starts at a run and ends before the run that
+// the entry after it belongs to, so it holds whole runs only, at least one.
 __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64_t* __restrict__ tile_start,
-                                                                     uint32_t* __restrict__ keys,
-                                                                     uint32_t* __restrict__ tmp,
+                                                                     const uint32_t* __restrict__ keys,
                                                                      const int32_t* __restrict__ order, int n, int T,
-                                                                     int rank_bits, int digit_bits,
                                                                      int32_t* __restrict__ ids) {
   __shared__ int cnt[kTileSortWaves][kTileBins];
   __shared__ int wsum[kTileSortThreads / kWave];
-  __shared__ int tot[kTileBins], start[kTileBins], goff[kTileBins];
   __shared__ uint32_t buf[2][kTileSortLds];
   const int64_t a = tile_start[blockIdx.x];
   const int64_t len = tile_start[blockIdx.x + 1] - a;
-  if (len == 0) return;
-  const int tid = threadIdx.x, w = tid / kWave;
+  const int tid = threadIdx.x;
   const int32_t* ord = order + (size_t)(blockIdx.x / T) * n;
-  if (len <= kTileSortLds) {  // the whole segment in LDS
-    for (int i = tid; i < len; i += kTileSortThreads) buf[0][i] = keys[a + i];
+  for (int64_t pos = 0; pos < len;) {
+    const int wlen = (int)min<int64_t>(kTileSortLds, len - pos);
+    for (int i = tid; i < wlen; i += kTileSortThreads) buf[0][i] = keys[a + pos + i];
+    // the run of the entry after the window (none: past every run)
+    const uint32_t next_run = pos + wlen < len ? keys[a + pos + wlen] >> kChunkBits : 0xffffffffu;
+    __syncthreads();
+    // m: the entries of runs before next_run's, a prefix of the window
+    // (never empty for lists written by emit_kernel)
+    int m = 0;
+    for (int i0 = 0; i0 < wlen; i0 += kTileSortThreads) {
+      const int i = i0 + tid;
+      m += __syncthreads_count(i < wlen && (buf[0][i] >> kChunkBits) < next_run);
+    }
+    m = m > 0 ? m : wlen;
+    // ranks relative to the first run's chunk; the largest lies in the last run
+    const uint32_t base = (buf[0][0] >> kChunkBits) << kChunkBits;
+    const uint32_t top = ((buf[0][m - 1] >> kChunkBits) << kChunkBits) + (kChunk - 1) - base;
+    const int bits = top > 0 ? 32 - __clz(top) : 1;
+    const int passes = (bits + 8) / 9;
+    const int digit_bits = (bits + passes - 1) / passes;
+    __syncthreads();
+    for (int i = tid; i < m; i += kTileSortThreads) buf[0][i] -= base;
     __syncthreads();
     int q = 0;
-    for (int shift = 0; shift < rank_bits; shift += digit_bits, q ^= 1)
-      lds_block_pass(buf[q], buf[q ^ 1], (int)len, shift, 1 << min(digit_bits, rank_bits - shift), cnt, wsum, tot,
-                     start);
-    for (int i = tid; i < len; i += kTileSortThreads) ids[a + i] = ord[buf[q][i]];
-    return;
+    for (int shift = 0; shift < bits; shift += digit_bits, q ^= 1)
+      lds_block_pass(buf[q], buf[q ^ 1], m, shift, 1 << min(digit_bits, bits - shift), cnt, wsum);
+    for (int i = tid; i < m; i += kTileSortThreads) ids[a + pos + i] = ord[buf[q][i] + base];
+    pos += m;
+    __syncthreads();
   }
-  // Longer segments: per pass, the digit totals of the whole segment give
-  // each digit its output range; then blocks of kTileSortLds keys are
-  // sorted by the digit in LDS, in order, and written out as runs of equal
-  // digits (consecutive addresses) at the digits' running offsets.
-  uint32_t* src = keys + a;
-  uint32_t* dst = tmp + a;
-  const int64_t b0 = len * w / kTileSortWaves, b1 = len * (w + 1) / kTileSortWaves;
-  for (int shift = 0; shift < rank_bits; shift += digit_bits) {
-    const int bins = 1 << min(digit_bits, rank_bits - shift);
-    for (int i = tid; i < kTileSortWaves * kTileBins; i += kTileSortThreads) (&cnt[0][0])[i] = 0;
-    __syncthreads();
-    part_count(src, b0, b1, shift, bins, cnt[w]);
-    __syncthreads();
-    int t0 = 0, t1 = 0;
-#pragma unroll
-    for (int v = 0; v < kTileSortWaves; ++v) {
-      t0 += cnt[v][2 * tid];
-      t1 += cnt[v][2 * tid + 1];
-    }
-    const int run0 = pair_exclusive_scan(t0, t1, wsum);
-    goff[2 * tid] = run0;
-    goff[2 * tid + 1] = run0 + t0;
-    __syncthreads();
-    for (int64_t base = 0; base < len; base += kTileSortLds) {
-      const int blen = (int)min<int64_t>(kTileSortLds, len - base);
-      for (int i = tid; i < blen; i += kTileSortThreads) buf[0][i] = src[base + i];
-      __syncthreads();
-      lds_block_pass(buf[0], buf[1], blen, shift, bins, cnt, wsum, tot, start);
-      for (int i = tid; i < blen; i += kTileSortThreads) {
-        const uint32_t key = buf[1][i];
-        const int d = digit_of(key, shift, bins);
-        dst[goff[d] + (i - start[d])] = key;
-      }
-      __syncthreads();
-      goff[2 * tid] += tot[2 * tid];
-      goff[2 * tid + 1] += tot[2 * tid + 1];
-      __syncthreads();
-    }
-    uint32_t* tt = src;
-    src = dst;
-    dst = tt;
-  }
-  for (int64_t i = tid; i < len; i += kTileSortThreads) ids[a + i] = ord[src[i]];
 }
 
 }  // namespace
 
 int bin_chunks(int n) { return (n + kChunk - 1) / kChunk; }
 
+void launch_bin_total(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
+  const int64_t m = (int64_t)d.V * d.n;
+  const int blocks = (int)std::min<int64_t>(kAreaBlocks, std::max<int64_t>(1, (m + 255) / 256));
+  area_kernel<<<blocks, 256, 0, s>>>(reinterpret_cast<const int4*>(f->rect), m, b.area_part);
+  area_total_kernel<<<1, 256, 0, s>>>(b.area_part, blocks, f->n_instances);
+}
+
 void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
   const int nc = bin_chunks(d.n);
   const size_t lds = (size_t)d.T * sizeof(int32_t);
-  hist_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), d.n, d.TX, d.T,
-                                                      nc, b.chunk_hist);
+  hist_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), b.order, d.n, d.TX,
+                                                      d.T, nc, b.chunk_hist);
   const int64_t m = (int64_t)d.V * d.T;
   colscan_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(b.chunk_hist, d.V, d.T, nc, b.counts);
   scan_kernel<<<1, 1024, 0, s>>>(b.counts, m, f->tile_start, f->n_instances);
@@ -483,18 +478,16 @@ void launch_view_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hip
     view_scatter_kernel<<<pblocks, kViewThreads, 0, s>>>(b.vkey[q], b.vkey[q ^ 1], b.vval[q], b.vval[q ^ 1], d.n,
                                                           d.V, 8 * pass, b.vcount);
   }
-  view_rank_kernel<<<vblocks, kViewThreads, 0, s>>>(b.vval[0], d.n, d.V, b.rank, b.order);
+  // after four passes the sorted ids are in vval[0]: that is the rank -> id table
 }
 
 void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
   const int nc = bin_chunks(d.n);
   const size_t lds = (size_t)d.T * sizeof(int32_t);
-  emit_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), b.rank, d.n, d.TX,
+  emit_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), b.order, d.n, d.TX,
                                                       d.T, nc, b.chunk_hist, f->tile_start, b.keys);
-  const int rank_bits = d.n > 1 ? 32 - __builtin_clz((unsigned)(d.n - 1)) : 0;
-  const int digit_bits = (rank_bits + 8) / 9 < (rank_bits + 7) / 8 ? 9 : 8;
-  tile_sort_kernel<<<(unsigned)((int64_t)d.V * d.T), kTileSortThreads, 0, s>>>(
-      f->tile_start, b.keys, b.tmp, b.order, d.n, d.T, rank_bits, digit_bits, f->ids);
+  tile_sort_kernel<<<(unsigned)((int64_t)d.V * d.T), kTileSortThreads, 0, s>>>(f->tile_start, b.keys, b.order,
+                                                                              d.n, d.T, f->ids);
 }
 
 int view_sort_count_ints(int n, int V) { return V * ((n + kViewPart - 1) / kViewPart) * kRadixBins; }

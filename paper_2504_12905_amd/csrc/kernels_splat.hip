@@ -12,10 +12,8 @@
 // of the tile's depth-sorted list is loaded, one record per lane, and the
 // wave walks the tile's sampled pixels one after another. For each pixel
 // the transmittance in front of every entry is a prefix product of
-// (1 - alpha) across the lanes (a DPP scan), carried from chunk to chunk (the
-// render, which decides where a pixel stops, sums log2(1 - alpha) instead
-// and compares with log2 of the threshold); J p needs one prefix sum more for
-// its derivative. J^T u walks the chunks back to front with the lane order
+// (1 - alpha) across the lanes (a DPP scan), carried from chunk to chunk; J p
+// needs one prefix sum more for its derivative. J^T u walks the chunks back to front with the lane order
 // reversed inside a chunk, so the colour blended behind an entry and the
 // transmittance product behind it are prefix scans as well. Each lane then holds its Gaussian's screen-space
 // gradient summed over all pixels of the tile and issues one atomic add per
@@ -127,8 +125,6 @@ __device__ __forceinline__ int load_pixel_regs(const uint8_t* pix, const float* 
   }
   return uniform(wave_max_i(lmax));
 }
-
-__device__ __forceinline__ float log2_om(bool inc, float a) { return inc ? __log2f(1.f - a) : 0.f; }
 
 // ------------------------------------------------------------ tile schedule
 // A tile's cost in the derivative walks is its walk length: the number of
@@ -298,7 +294,6 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
     sLast[s] = -1;
     sDone[s] = 0;
   }
-  const float log_tmin = __log2f(o.t_min);
   int remaining = k / W + (wv < k % W ? 1 : 0);  // this wave's pixels
   for (int c0 = 0; c0 < c.len && remaining > 0; c0 += kWave) {
     const bool valid = c0 + lane < c.len;
@@ -312,19 +307,18 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
         const Alpha al = pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
         const bool inc = valid && al.inc;
         const float a = inc ? al.a : 0.f;
-        const float lg = log2_om(inc, a);
-        const float Linc = scan_add(lg);
+        const float om = inc ? 1.f - a : 1.f;
         const float Tc = readlane(sT[s], l);
-        const float lTc = __log2f(Tc);
+        const float Taft = Tc * scan_mul(om);  // T behind this entry
         // first entry whose blending would take T below t_min
-        const uint64_t stop = __ballot(inc && lTc + Linc < log_tmin);
+        const uint64_t stop = __ballot(inc && Taft < o.t_min);
         const int f = stop ? __ffsll((unsigned long long)stop) - 1 : kWave;
         const bool ok = inc && lane < f;
-        const float Tex = Tc * __builtin_amdgcn_exp2f(Linc - lg);
+        const float Tex = Taft * __builtin_amdgcn_rcpf(om);  // T in front of it
         const float wgt = ok ? a * Tex : 0.f;
         const float cr = wave_total(wgt * r.r), cg = wave_total(wgt * r.g), cb = wave_total(wgt * r.b);
         const uint64_t okm = __ballot(ok);
-        const float Tnext = f < kWave ? readlane(Tex, f) : Tc * __builtin_amdgcn_exp2f(readlane(Linc, kWave - 1));
+        const float Tnext = f < kWave ? readlane(Tex, f) : readlane(Taft, kWave - 1);
         sT[s] = writelane(sT[s], Tnext, l);
         sC0[s] = writelane(sC0[s], readlane(sC0[s], l) + cr, l);
         sC1[s] = writelane(sC1[s], readlane(sC1[s], l) + cg, l);

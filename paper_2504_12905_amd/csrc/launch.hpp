@@ -34,16 +34,17 @@ struct BinScratch {
   int32_t* counts;      // [V*T]
   int32_t* chunk_hist;  // [V][bin_chunks(n)][T]
   uint32_t* keys;       // [capacity] depth ranks per tile segment
-  uint32_t* tmp;        // [capacity]
   uint32_t* vkey[2];    // [V][n] depth bits, sort ping-pong
   uint32_t* vval[2];    // [V][n] Gaussian ids, sort ping-pong
-  int32_t* rank;        // [V][n] depth rank of each Gaussian in its view
-  int32_t* order;       // [V][n] Gaussian id of each depth rank
+  int32_t* order;       // [V][n] Gaussian id of each depth rank (= vval[0] after the sort)
   int32_t* vcount;      // [view_sort_count_ints(n, V)] digit counts / offsets of the view sort
+  int64_t* area_part;   // [kBinAreaParts] partial sums of the entry count
 };
+constexpr int kBinAreaParts = 1024;
 int view_sort_count_ints(int n, int V);
 constexpr int kMaxTilesPerView = 16384;  // LDS histogram of one view's tiles (64 KB)
 int bin_chunks(int n);
+void launch_bin_total(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s);
 void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s);
 // per-view depth ranks (independent of the tile counts)
 void launch_view_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s);
