@@ -258,10 +258,11 @@ __global__ __launch_bounds__(kSchedThreads) void sched_kernel(int32_t* __restric
 }
 
 // ------------------------------------------------------------------ render
-// SCORE = false: colour (with background), final transmittance and last
-// blended position of every sampled pixel. SCORE = true (every pixel, k = 256):
-// only the pixel's residual magnitude |C_R - I_R| + |C_G - I_G| + |C_B - I_B|
-// against the target image of its camera, for the residual-weighted sampler.
+// Colour (with background), final transmittance and last blended position of
+// every sampled pixel, and the tile's walk length for the schedule.
+// score_kernel below: for every pixel only its residual magnitude
+// |C_R - I_R| + |C_G - I_G| + |C_B - I_B| against the target image of its
+// camera, for the residual-weighted sampler.
 struct ScoreOut {
   const float* targets;     // [cameras][H][W][3]
   const int32_t* view_ids;  // [V] or NULL
@@ -270,7 +271,7 @@ struct ScoreOut {
 };
 
 // W waves share a tile; wave wv renders the sample slots j with j % W == wv.
-template <int NS, bool SCORE, int W>
+template <int NS, int W>
 __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restrict__ rec,
                                                        const int64_t* __restrict__ tile_start,
                                                        const int32_t* __restrict__ ids,
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
                                                        int TX, int k, lmrs_render_opts o,
                                                        float* __restrict__ color, float* __restrict__ trans,
                                                        int32_t* __restrict__ last,
-                                                       int32_t* __restrict__ walk_len, ScoreOut so) {
+                                                       int32_t* __restrict__ walk_len) {
   const int lane = lane_id();
   const int wv = uniform((int)(threadIdx.x / kWave));
   const bool mine = (lane & (W - 1)) == wv;
@@ -331,43 +332,102 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
       }
     }
   }
-  const int cam = SCORE ? (so.view_ids ? so.view_ids[c.v] : c.v) : 0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int j = s * kWave + lane;
     if (j < k && mine) {
       const int64_t i = c.tile_lin * k + j;
-      const float c0 = sC0[s] + sT[s] * o.bg[0];
-      const float c1 = sC1[s] + sT[s] * o.bg[1];
-      const float c2 = sC2[s] + sT[s] * o.bg[2];
-      if (SCORE) {
-        const int p = pix ? (int)pix[i] : j;
-        const int x = (c.t % TX) * kTile + (p & 15), y = (c.t / TX) * kTile + (p >> 4);
-        const float* tg = so.targets + (((int64_t)cam * so.H + y) * so.W + x) * 3;
-        so.score[i] = (fabsf(c0 - tg[0]) + fabsf(c1 - tg[1])) + fabsf(c2 - tg[2]);
-      } else {
-        color[3 * i] = c0;
-        color[3 * i + 1] = c1;
-        color[3 * i + 2] = c2;
-        trans[i] = sT[s];
-        last[i] = sLast[s];
+      color[3 * i] = sC0[s] + sT[s] * o.bg[0];
+      color[3 * i + 1] = sC1[s] + sT[s] * o.bg[1];
+      color[3 * i + 2] = sC2[s] + sT[s] * o.bg[2];
+      trans[i] = sT[s];
+      last[i] = sLast[s];
+    }
+  }
+  int steps = 0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) steps += mine && sLast[s] >= 0 ? sLast[s] / kWave + 1 : 0;
+  __shared__ float part[W];
+  const float total = wave_total((float)steps);  // a sort key: exact up to 2^24 steps
+  if (lane == 0) part[wv] = total;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float sum = 0.f;
+    for (int w = 0; w < W; ++w) sum += part[w];
+    walk_len[c.tile_lin] = (int32_t)sum;
+  }
+}
+
+// Residual scores of every pixel (lmrs_residual_scores). With all 256 pixels
+// of a tile to render, a lane per pixel needs about half the instructions
+// per (pixel, entry) pair of the entry-per-lane walk, which pays prefix
+// scans and three wave sums per pixel step: thread j blends pixel j, the
+// list's records pass through LDS 256 at a time (one loaded per thread, the
+// next chunk's while this one is blended) and every lane reads the same
+// record at once (an LDS broadcast). A pixel stops where the walk above
+// stops it (the first entry that would take T below t_min), here with the
+// transmittance multiplied entry by entry; a wave leaves a chunk when all
+// its pixels have stopped, the workgroup its list when all 256 have.
+constexpr int kScoreThreads = 256;
+
+__global__ __launch_bounds__(kScoreThreads) void score_kernel(const float* __restrict__ rec,
+                                                              const int64_t* __restrict__ tile_start,
+                                                              const int32_t* __restrict__ ids, int n, int T,
+                                                              int TX, lmrs_render_opts o, ScoreOut so) {
+  __shared__ float4 s_rec[kScoreThreads * 3];
+  const int tid = threadIdx.x;
+  const TileCtx c = tile_ctx(tile_start, T, TX, blockIdx.x);
+  const float xc = c.ox + (float)(tid & 15) + 0.5f, yc = c.oy + (float)(tid >> 4) + 0.5f;
+  const float4* rec4 = reinterpret_cast<const float4*>(rec);
+  const size_t vb = (size_t)c.v * n;
+  float Tr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  bool done = false;
+  float4 q0{}, q1{}, q2{};
+  if (tid < c.len) {
+    const size_t g = (vb + (size_t)ids[c.start + tid]) * 3;
+    q0 = rec4[g];
+    q1 = rec4[g + 1];
+    q2 = rec4[g + 2];
+  }
+  for (int64_t c0 = 0; c0 < c.len; c0 += kScoreThreads) {
+    __syncthreads();  // the previous chunk has been read
+    s_rec[3 * tid] = q0;
+    s_rec[3 * tid + 1] = q1;
+    s_rec[3 * tid + 2] = q2;
+    __syncthreads();
+    if (c0 + kScoreThreads + tid < c.len) {
+      const size_t g = (vb + (size_t)ids[c.start + c0 + kScoreThreads + tid]) * 3;
+      q0 = rec4[g];
+      q1 = rec4[g + 1];
+      q2 = rec4[g + 2];
+    }
+    const int cnt = (int)min<int64_t>(kScoreThreads, c.len - c0);
+    if (!done) {
+      for (int e = 0; e < cnt; ++e) {
+        const float4 a = s_rec[3 * e], b = s_rec[3 * e + 1];
+        const float cb = s_rec[3 * e + 2].x;
+        const Alpha al = pair_alpha(a.x, a.y, a.z, a.w, b.x, b.y, xc, yc, o);
+        if (al.inc) {
+          const float Tn = Tr * (1.f - al.a);
+          if (Tn < o.t_min) {
+            done = true;
+            break;
+          }
+          const float wgt = al.a * Tr;
+          C0 += wgt * b.z;
+          C1 += wgt * b.w;
+          C2 += wgt * cb;
+          Tr = Tn;
+        }
       }
     }
+    if (__syncthreads_and(done)) break;
   }
-  if (!SCORE) {
-    int steps = 0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) steps += mine && sLast[s] >= 0 ? sLast[s] / kWave + 1 : 0;
-    __shared__ float part[W];
-    const float total = wave_total((float)steps);  // a sort key: exact up to 2^24 steps
-    if (lane == 0) part[wv] = total;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float sum = 0.f;
-      for (int w = 0; w < W; ++w) sum += part[w];
-      walk_len[c.tile_lin] = (int32_t)sum;
-    }
-  }
+  const int cam = so.view_ids ? so.view_ids[c.v] : c.v;
+  const int x = (c.t % TX) * kTile + (tid & 15), y = (c.t / TX) * kTile + (tid >> 4);
+  const float* tg = so.targets + (((int64_t)cam * so.H + y) * so.W + x) * 3;
+  const float r0 = C0 + Tr * o.bg[0], r1 = C1 + Tr * o.bg[1], r2 = C2 + Tr * o.bg[2];
+  so.score[c.tile_lin * 256 + tid] = (fabsf(r0 - tg[0]) + fabsf(r1 - tg[1])) + fabsf(r2 - tg[2]);
 }
 
 // ----------------------------------------------------- J p, J^T u, fused GN
@@ -888,14 +948,13 @@ unsigned persistent_groups(int64_t tiles, int w) {
 template <int W>
 void launch_render_w(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
-  const ScoreOut none{nullptr, nullptr, 0, 0, nullptr};
   int32_t* walk_len = f->sched + tiles;
   if (d.k <= kWave)
-    render_kernel<1, false, W><<<tiles, kWave * W, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX,
-                                                           d.k, o, f->color, f->trans, f->last, walk_len, none);
+    render_kernel<1, W><<<tiles, kWave * W, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k, o,
+                                                    f->color, f->trans, f->last, walk_len);
   else
-    render_kernel<4, false, W><<<tiles, kWave * W, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX,
-                                                           d.k, o, f->color, f->trans, f->last, walk_len, none);
+    render_kernel<4, W><<<tiles, kWave * W, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k, o,
+                                                    f->color, f->trans, f->last, walk_len);
 }
 
 void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
@@ -910,8 +969,7 @@ void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_re
                           const float* targets, float* scores, hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   const ScoreOut so{targets, f->view_ids, d.W, d.H, scores};
-  render_kernel<4, true, 4><<<tiles, kWave * 4, 0, s>>>(f->rec, f->tile_start, f->ids, nullptr, d.n, d.T, d.TX,
-                                                        256, o, nullptr, nullptr, nullptr, nullptr, so);
+  score_kernel<<<tiles, kScoreThreads, 0, s>>>(f->rec, f->tile_start, f->ids, d.n, d.T, d.TX, o, so);
 }
 
 template <int W>
