@@ -20,10 +20,11 @@
 //    chunk's run, and a run holds at most kChunk entries.
 // 6. sort: one workgroup per tile takes windows of up to kTileSortLds
 //    entries that end at a run boundary (the runs are read off the ranks),
-//    sorts each in LDS by a stable LSD radix sort of the ranks relative to
-//    the window's first chunk (8- or 9-bit digits), and writes ids = rank ->
-//    id. Every entry is read and written once; ranks are unique within a
-//    view, so the order is the depth order with ties by id.
+//    sorts each in LDS by the ranks relative to the window's first chunk (a
+//    bitmap of the ranks when they span up to 64 chunks, else a stable LSD
+//    radix sort with digits of up to 9 bits), and writes ids = rank -> id.
+//    Every entry is read and written once; ranks are unique within a view,
+//    so the order is the depth order with ties by id.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -400,20 +401,31 @@ __device__ void lds_block_pass(const uint32_t* src, uint32_t* dst, int blen, int
 // >> kChunkBits non-decreasing along the list), each run unordered and at
 // most kChunk long. A window starts at a run and ends before the run that
 // the entry after it belongs to, so it holds whole runs only, at least one.
+// Its ranks relative to the first run's chunk are unique and below
+// (runs spanned) * kChunk: up to kBitmapWords * 32 they are sorted by
+// setting one bit each in an LDS bitmap and reading the set bits back in
+// order (each thread a range of words, at the running count of the ranges
+// before it) into LDS, from where the ids are written out coalesced; wider
+// windows (short lists spanning many chunks) take the
+// radix passes.
+constexpr int kBitmapWords = kTileSortLds + kTileSortWaves * kTileBins;
+
 __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64_t* __restrict__ tile_start,
                                                                      const uint32_t* __restrict__ keys,
                                                                      const int32_t* __restrict__ order, int n, int T,
                                                                      int32_t* __restrict__ ids) {
-  __shared__ int cnt[kTileSortWaves][kTileBins];
+  // s_work: the radix passes' second buffer and digit counters, or the bitmap
+  __shared__ uint32_t s_keys[kTileSortLds];
+  __shared__ uint32_t s_work[kBitmapWords];
   __shared__ int wsum[kTileSortThreads / kWave];
-  __shared__ uint32_t buf[2][kTileSortLds];
+  int(*cnt)[kTileBins] = reinterpret_cast<int(*)[kTileBins]>(s_work + kTileSortLds);
   const int64_t a = tile_start[blockIdx.x];
   const int64_t len = tile_start[blockIdx.x + 1] - a;
   const int tid = threadIdx.x;
   const int32_t* ord = order + (size_t)(blockIdx.x / T) * n;
   for (int64_t pos = 0; pos < len;) {
     const int wlen = (int)min<int64_t>(kTileSortLds, len - pos);
-    for (int i = tid; i < wlen; i += kTileSortThreads) buf[0][i] = keys[a + pos + i];
+    for (int i = tid; i < wlen; i += kTileSortThreads) s_keys[i] = keys[a + pos + i];
     // the run of the entry after the window (none: past every run)
     const uint32_t next_run = pos + wlen < len ? keys[a + pos + wlen] >> kChunkBits : 0xffffffffu;
     __syncthreads();
@@ -422,22 +434,48 @@ __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const int64
     int m = 0;
     for (int i0 = 0; i0 < wlen; i0 += kTileSortThreads) {
       const int i = i0 + tid;
-      m += __syncthreads_count(i < wlen && (buf[0][i] >> kChunkBits) < next_run);
+      m += __syncthreads_count(i < wlen && (s_keys[i] >> kChunkBits) < next_run);
     }
     m = m > 0 ? m : wlen;
     // ranks relative to the first run's chunk; the largest lies in the last run
-    const uint32_t base = (buf[0][0] >> kChunkBits) << kChunkBits;
-    const uint32_t top = ((buf[0][m - 1] >> kChunkBits) << kChunkBits) + (kChunk - 1) - base;
-    const int bits = top > 0 ? 32 - __clz(top) : 1;
-    const int passes = (bits + 8) / 9;
-    const int digit_bits = (bits + passes - 1) / passes;
-    __syncthreads();
-    for (int i = tid; i < m; i += kTileSortThreads) buf[0][i] -= base;
-    __syncthreads();
-    int q = 0;
-    for (int shift = 0; shift < bits; shift += digit_bits, q ^= 1)
-      lds_block_pass(buf[q], buf[q ^ 1], m, shift, 1 << min(digit_bits, bits - shift), cnt, wsum);
-    for (int i = tid; i < m; i += kTileSortThreads) ids[a + pos + i] = ord[buf[q][i] + base];
+    const uint32_t base = (s_keys[0] >> kChunkBits) << kChunkBits;
+    const uint32_t top = ((s_keys[m - 1] >> kChunkBits) << kChunkBits) + (kChunk - 1) - base;
+    int32_t* out = ids + a + pos;
+    if (top < (uint32_t)kBitmapWords * 32u) {
+      const int nwords = (int)(top >> 5) + 1;
+      for (int i = tid; i < nwords; i += kTileSortThreads) s_work[i] = 0u;
+      __syncthreads();
+      for (int i = tid; i < m; i += kTileSortThreads) {
+        const uint32_t r = s_keys[i] - base;
+        atomicOr(&s_work[r >> 5], 1u << (r & 31));
+      }
+      __syncthreads();
+      const int wpt = (nwords + kTileSortThreads - 1) / kTileSortThreads;
+      const int w0 = min(nwords, tid * wpt), w1 = min(nwords, w0 + wpt);
+      int own = 0;
+      for (int w = w0; w < w1; ++w) own += __popc(s_work[w]);
+      int p = pair_exclusive_scan(own, 0, wsum);  // (its barriers also retire the reads of s_keys)
+      for (int w = w0; w < w1; ++w)
+        for (uint32_t bits = s_work[w]; bits; bits &= bits - 1u)
+          s_keys[p++] = base + ((uint32_t)w << 5) + (uint32_t)(__ffs(bits) - 1);
+      __syncthreads();
+      for (int i = tid; i < m; i += kTileSortThreads) out[i] = ord[s_keys[i]];
+    } else {
+      const int nbits = 32 - __clz(top);
+      const int passes = (nbits + 8) / 9;
+      const int digit_bits = (nbits + passes - 1) / passes;
+      __syncthreads();
+      for (int i = tid; i < m; i += kTileSortThreads) s_keys[i] -= base;
+      __syncthreads();
+      uint32_t *src = s_keys, *dst = s_work;
+      for (int shift = 0; shift < nbits; shift += digit_bits) {
+        lds_block_pass(src, dst, m, shift, 1 << min(digit_bits, nbits - shift), cnt, wsum);
+        uint32_t* t = src;
+        src = dst;
+        dst = t;
+      }
+      for (int i = tid; i < m; i += kTileSortThreads) out[i] = ord[src[i] + base];
+    }
     pos += m;
     __syncthreads();
   }
