@@ -31,7 +31,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GN products (J^T J p)/sec at 100k Gaussians vs plain; served fits/sec + p99"
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+# FP32 vector peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA)
+# x 2.4 GHz. The library is built with packed FP32 arithmetic switched off
+# (-packed-fp32-ops), which the published 157.3 TFLOP/s assumes.
+FP32_VECTOR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP32_PACKED_PEAK_TFLOPS = 157.3
 SPLAT_SOURCE = os.path.join(ROOT, "paper_2504_12905_amd", "csrc", "kernels_splat.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gn_splat_traffic_cfg1.txt")
 
@@ -43,10 +47,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gn_splat_traffic_cfg1.txt")
 BYTES_PER_ENTRY = 4 + 36 + 36 + 36
 BYTES_PER_PIXEL = 1 + 4 + 4 + 4
 # Algorithmic FP32 operations per (sampled pixel, list entry) pair walked:
-# opacity test 14 (offsets 2, quadratic form 7, exp 1, scale 1, compares 3),
-# exponent tangent 17, alpha tangent 3, transmittance and its tangent 5,
-# colour tangent 12, reverse transmittance 2, blended-behind term 6,
-# alpha adjoint 4, screen-gradient accumulation 24.
+# forward: opacity test 14 (offsets 2, quadratic form 7, exp 1, scale 1,
+# compares 3), exponent tangent 17, alpha tangent 3, transmittance and its
+# tangent 5, colour tangent 12; reverse: opacity test 14, transmittance 2,
+# blended-behind term 6, alpha adjoint 4, screen-gradient accumulation 24.
 FLOPS_PER_PAIR = 14 + 17 + 3 + 5 + 12 + 14 + 2 + 6 + 4 + 24
 
 
@@ -480,6 +484,7 @@ def main():
         "traffic": traffic,
         "hbm_gbs": round(gbs, 3), "hbm_frac": round(hbm_frac, 6),
         "alu_tflops": round(tflops, 4), "alu_frac": round(alu_frac, 6),
+        "alu_frac_of_packed_peak": round(tflops / FP32_PACKED_PEAK_TFLOPS, 6),
         "algorithmic_bytes": b_alg, "algorithmic_flops": f_alg,
         "traversed_entries": entries, "pixel_entry_pairs": pairs, "sampled_pixels": S,
         "ms_per_launch": round(float(phase_ms[2]), 4),
