@@ -475,7 +475,16 @@ __device__ __forceinline__ FwdStep fwd_step(const RecF& r, const RecF& dr, int e
 }
 
 // MODE 1: jp = J p.  MODE 2: grad2d += J^T u.  MODE 3: grad2d += J^T W J p.
-template <int MODE, int NS, int W>
+//
+// W waves share a tile. With one slot of pixels (NS == 1) and at most MP
+// pixels per wave (MP > 1), the tile's pixels are dealt by depth: ranked by
+// last blended entry (deepest first, ties by slot), the first ranks go to
+// wave 0, the next to wave 1, and so on, so that the pixels of a wave walk
+// about as far as each other and a wave stops at its own deepest pixel.
+// Wave wv's pixel m is slot px[m] with last entry pl[m] (-1 for m past its
+// pixels). Otherwise slot j goes to wave j % W. Each wave keeps the state of
+// its pixels in its own registers from the forward walk to the reverse walk.
+template <int MODE, int NS, int W, int MP>
 __device__ __forceinline__ void deriv_tile(
     const float* __restrict__ rec, const float* __restrict__ tan, const int64_t* __restrict__ tile_start,
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
@@ -484,16 +493,42 @@ __device__ __forceinline__ void deriv_tile(
     float* __restrict__ grad2d, int64_t tile_lin, int wv, float* red) {
   constexpr bool FWD = MODE != 2;
   constexpr bool REV = MODE != 1;
+  constexpr bool DEALT = W > 1 && NS == 1 && MP > 1;
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX, tile_lin);
   PixelRegs<NS> pr;
   const int lmax = load_pixel_regs<NS>(pix, wts, lastv, k, c, pr);
-  // this wave's pixels: sample slots j with j % W == wv (W waves share the tile)
-  int lm_own = -1;
+  int px[DEALT ? MP : 1], pl[DEALT ? MP : 1];
+  bool own[NS];
+  int lmax_own;
+  if (DEALT) {
+    // rank of this lane's pixel; wave w takes ranks [first_w, first_w + count_w)
+    const int my_last = pr.last[0];
+    int rank = 0;
+    for (int q = 0; q < k; ++q) {
+      const int lq = readlane(pr.last[0], q);
+      rank += lq > my_last || (lq == my_last && q < lane) ? 1 : 0;
+    }
+    const int base = k / W, extra = k % W;
+    const int first = wv * base + min(wv, extra), cnt = base + (wv < extra ? 1 : 0);
+    own[0] = lane < k && rank >= first && rank < first + cnt;
 #pragma unroll
-  for (int s = 0; s < NS; ++s)
-    if ((lane & (W - 1)) == wv) lm_own = max(lm_own, pr.last[s]);
-  const int lmax_own = uniform(wave_max_i(lm_own));
+    for (int m = 0; m < MP; ++m) {
+      const uint64_t b = __ballot(lane < k && rank == first + m && m < cnt);
+      px[m] = b ? __ffsll((unsigned long long)b) - 1 : 0;
+      pl[m] = b ? readlane(pr.last[0], px[m]) : -1;
+    }
+    lmax_own = pl[0];
+  } else {
+    int lm_own = -1;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      own[s] = s * kWave + lane < k && (lane & (W - 1)) == wv;
+      if (own[s]) lm_own = max(lm_own, pr.last[s]);
+    }
+    lmax_own = uniform(wave_max_i(lm_own));
+    px[0] = pl[0] = 0;
+  }
   // forward: a = T in front of the chunk, b = its tangent, u0..u2 = d colour
   // reverse: a = T behind the chunk range already walked, b = u . (colour behind + T_final bg), u = weights
   float sa[NS], sb[NS], su0[NS], su1[NS], su2[NS];
@@ -504,15 +539,13 @@ __device__ __forceinline__ void deriv_tile(
       sa[s] = 1.f;
       sb[s] = su0[s] = su1[s] = su2[s] = 0.f;
     }
-    // With up to 32 samples per tile and several waves per tile, each lane
-    // keeps its entry's colour-tangent contribution to each of the wave's
-    // pixels in registers (acc[m] for the wave's pixel m) and the wave sums
-    // them once after the walk, instead of three wave sums per step.
-    constexpr int MP = W > 1 && NS == 1 ? 32 / W : 1;
-    const bool acc_path = MP > 1 && k <= 32;
-    float A0[MP], A1[MP], A2[MP];
+    // With dealt pixels each lane keeps its entry's colour-tangent
+    // contribution to each of the wave's pixels in registers (A[m] for the
+    // wave's pixel m) and the wave sums them once after the walk, instead
+    // of three wave sums per step.
+    float A0[DEALT ? MP : 1], A1[DEALT ? MP : 1], A2[DEALT ? MP : 1];
 #pragma unroll
-    for (int m = 0; m < MP; ++m) A0[m] = A1[m] = A2[m] = 0.f;
+    for (int m = 0; m < (DEALT ? MP : 1); ++m) A0[m] = A1[m] = A2[m] = 0.f;
     // the next chunk's records and tangents and the list ids of the one
     // after load while a chunk is walked
     RecF rn{}, drn{};
@@ -535,16 +568,15 @@ __device__ __forceinline__ void deriv_tile(
         drn = load_rec(tan, (size_t)c.v * n + idn);
       }
       idn = c0 + 2 * kWave <= lmax_own ? fwd_chunk_id(ids, c, c0 + 2 * kWave) : -1;
-      if (acc_path) {
+      if (DEALT) {
 #pragma unroll
         for (int m = 0; m < MP; ++m) {
-          // no branches: for a pixel past its last entry (or a slot past k,
-          // whose last is -1) the step adds nothing and leaves T and its
+          // no branches: for a pixel past its last entry (or a slot without
+          // a pixel, last -1) the step adds nothing and leaves T and its
           // tangent as they are, and the steps of the wave's pixels form
           // one block that the compiler can interleave
-          const int l = wv + m * W;
-          const int lj = readlane(pr.last[0], l);
-          const FwdStep st = fwd_step(r, dr, e, valid, lj, readlane(pr.xc[0], l), readlane(pr.yc[0], l),
+          const int l = px[m];
+          const FwdStep st = fwd_step(r, dr, e, valid, pl[m], readlane(pr.xc[0], l), readlane(pr.yc[0], l),
                                       readlane(sa[0], l), readlane(sb[0], l), o);
           A0[m] += st.cr;
           A1[m] += st.cg;
@@ -570,14 +602,13 @@ __device__ __forceinline__ void deriv_tile(
         }
       }
     }
-    if (acc_path) {
+    if (DEALT) {
 #pragma unroll
       for (int m = 0; m < MP; ++m) {
-        const int l = wv + m * W;
-        if (l >= k) break;
-        su0[0] = writelane(su0[0], wave_total(A0[m]), l);
-        su1[0] = writelane(su1[0], wave_total(A1[m]), l);
-        su2[0] = writelane(su2[0], wave_total(A2[m]), l);
+        if (pl[m] < 0) break;  // no blended entry (or no pixel): the tangent stays 0
+        su0[0] = writelane(su0[0], wave_total(A0[m]), px[m]);
+        su1[0] = writelane(su1[0], wave_total(A1[m]), px[m]);
+        su2[0] = writelane(su2[0], wave_total(A2[m]), px[m]);
       }
     }
 #pragma unroll
@@ -585,7 +616,7 @@ __device__ __forceinline__ void deriv_tile(
       const int j = s * kWave + lane;
       const float d0 = su0[s] + o.bg[0] * sb[s], d1 = su1[s] + o.bg[1] * sb[s], d2 = su2[s] + o.bg[2] * sb[s];
       if (MODE == 1) {
-        if (j < k && (lane & (W - 1)) == wv) {
+        if (own[s]) {
           const int64_t i = c.tile_lin * k + j;
           jp_out[3 * i] = d0;
           jp_out[3 * i + 1] = d1;
@@ -638,44 +669,53 @@ __device__ __forceinline__ void deriv_tile(
       idc = idn;
       idn = c0 >= 2 * kWave ? rev_chunk_id(ids, c, c0 - 2 * kWave) : -1;
       float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int cnt = min(kWave, k - s * kWave);
-        for (int l = wv; l < cnt; l += W) {
-          const int lj = readlane(pr.last[s], l);
-          if (c0 > lj) continue;
-          const Alpha al =
-              pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
-          const bool inc = valid && e <= lj && al.inc;
-          const float a = inc ? al.a : 0.f;
-          // product of (1 - alpha) over this entry and the ones behind it in the chunk
-          const float rP = __builtin_amdgcn_rcpf(scan_mul(inc ? 1.f - a : 1.f));
-          const float Tafter = readlane(sa[s], l);
-          const float Tn = Tafter * rP;
-          const float u0 = readlane(su0[s], l), u1 = readlane(su1[s], l), u2 = readlane(su2[s], l);
-          const float urgb = u0 * r.r + u1 * r.g + u2 * r.b;
-          const float term = inc ? urgb * a * Tn : 0.f;
-          const float Sinc = scan_add(term);
-          const float S = readlane(sb[s], l);
-          if (inc) {
-            const float aT = a * Tn;
-            g[6] += u0 * aT;
-            g[7] += u1 * aT;
-            g[8] += u2 * aT;
-            if (!al.capped) {
-              const float behind = S + (Sinc - term);
-              const float ga = Tn * urgb - behind * __builtin_amdgcn_rcpf(1.f - a);
-              const float gs = ga * a;
-              g[5] += ga * al.es;
-              g[0] -= gs * (al.q1 * r.f11);
-              g[1] -= gs * (al.q1 * r.f12 + al.q2 * r.f22);
-              g[2] -= gs * (al.q1 * al.dx);
-              g[3] -= gs * (al.q1 * al.dy);
-              g[4] -= gs * (al.q2 * al.dy);
-            }
+      // one pixel (slot s, lane l, last entry lj) against the chunk
+      auto rev_step = [&](int s, int l, int lj) {
+        const Alpha al =
+            pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+        const bool inc = valid && e <= lj && al.inc;
+        const float a = inc ? al.a : 0.f;
+        // product of (1 - alpha) over this entry and the ones behind it in the chunk
+        const float rP = __builtin_amdgcn_rcpf(scan_mul(inc ? 1.f - a : 1.f));
+        const float Tafter = readlane(sa[s], l);
+        const float Tn = Tafter * rP;
+        const float u0 = readlane(su0[s], l), u1 = readlane(su1[s], l), u2 = readlane(su2[s], l);
+        const float urgb = u0 * r.r + u1 * r.g + u2 * r.b;
+        const float term = inc ? urgb * a * Tn : 0.f;
+        const float Sinc = scan_add(term);
+        const float S = readlane(sb[s], l);
+        if (inc) {
+          const float aT = a * Tn;
+          g[6] += u0 * aT;
+          g[7] += u1 * aT;
+          g[8] += u2 * aT;
+          if (!al.capped) {
+            const float behind = S + (Sinc - term);
+            const float ga = Tn * urgb - behind * __builtin_amdgcn_rcpf(1.f - a);
+            const float gs = ga * a;
+            g[5] += ga * al.es;
+            g[0] -= gs * (al.q1 * r.f11);
+            g[1] -= gs * (al.q1 * r.f12 + al.q2 * r.f22);
+            g[2] -= gs * (al.q1 * al.dx);
+            g[3] -= gs * (al.q1 * al.dy);
+            g[4] -= gs * (al.q2 * al.dy);
           }
-          sa[s] = writelane(sa[s], Tafter * readlane(rP, kWave - 1), l);
-          sb[s] = writelane(sb[s], S + readlane(Sinc, kWave - 1), l);
+        }
+        sa[s] = writelane(sa[s], Tafter * readlane(rP, kWave - 1), l);
+        sb[s] = writelane(sb[s], S + readlane(Sinc, kWave - 1), l);
+      };
+      if (DEALT) {
+#pragma unroll
+        for (int m = 0; m < MP; ++m)
+          if (c0 <= pl[m]) rev_step(0, px[m], pl[m]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int cnt = min(kWave, k - s * kWave);
+          for (int l = wv; l < cnt; l += W) {
+            const int lj = readlane(pr.last[s], l);
+            if (c0 <= lj) rev_step(s, l, lj);
+          }
         }
       }
       // the waves' partial gradients of each entry meet in LDS (double
@@ -710,10 +750,10 @@ __device__ __forceinline__ void deriv_tile(
 // Persistent grid over the tile schedule; J p visits every tile (it writes
 // every sample), the reverse walks only tiles with blended entries. A
 // workgroup of W waves takes one tile at a time and deals its sampled pixels
-// to the waves (slot j to wave j % W): more waves per SIMD without cutting
-// the work into more, smaller items. W is chosen from the samples per tile
+// to the waves (deriv_tile): more waves per SIMD without cutting the work
+// into more, smaller items. W and MP are chosen from the samples per tile
 // (launch_deriv).
-template <int MODE, int NS, int W>
+template <int MODE, int NS, int W, int MP>
 __global__ __launch_bounds__(kWave* W) void deriv_kernel(
     const float* __restrict__ rec, const float* __restrict__ tan, const int64_t* __restrict__ tile_start,
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
@@ -733,7 +773,7 @@ __global__ __launch_bounds__(kWave* W) void deriv_kernel(
     const int tile = next_tile[it & 1];
     if (tile == -1) break;
     if (tile >= 0)
-      deriv_tile<MODE, NS, W>(rec, tan, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, u_in, jp_out,
+      deriv_tile<MODE, NS, W, MP>(rec, tan, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, u_in, jp_out,
                            grad2d, tile, wv, red);
   }
   if (threadIdx.x == 0) sched_sign_off(sr);
@@ -972,28 +1012,38 @@ void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_re
   score_kernel<<<tiles, kScoreThreads, 0, s>>>(f->rec, f->tile_start, f->ids, d.n, d.T, d.TX, o, so);
 }
 
-template <int W>
-void launch_deriv_w(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
-                    const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s) {
+template <int MODE, int W>
+void launch_deriv_mode(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* tan,
+                       const float* u, float* jp, float* grad2d, hipStream_t s) {
   static_assert(kWave % W == 0, "pixel slots are dealt to the waves by lane");
   const int tiles = d.V * d.T;
   const unsigned grid = persistent_groups(tiles, W);
   const unsigned block = kWave * W;
-#define LMRS_DERIV_ARGS                                                                              \
-  f->rec, tan, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T, d.TX, d.k, o, u, jp, \
-      grad2d, f->sched, tiles
   const bool small = d.k <= kWave;
-  if (mode == 1) {
-    if (small) deriv_kernel<1, 1, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
-    else deriv_kernel<1, 4, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
-  } else if (mode == 2) {
-    if (small) deriv_kernel<2, 1, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
-    else deriv_kernel<2, 4, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
-  } else {
-    if (small) deriv_kernel<3, 1, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
-    else deriv_kernel<3, 4, W><<<grid, block, 0, s>>>(LMRS_DERIV_ARGS);
+  // pixels per wave when they are dealt by depth (several waves, one slot,
+  // at most 8 per wave), else 1 (dealt by slot)
+  const int mp = W > 1 && small && d.k <= 8 * W ? (d.k + W - 1) / W : 1;
+  auto go = [&](auto kern) {
+    kern<<<grid, block, 0, s>>>(f->rec, tan, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T,
+                                d.TX, d.k, o, u, jp, grad2d, f->sched, tiles);
+  };
+  if (!small) {
+    go(deriv_kernel<MODE, 4, W, 1>);
+  } else if (mp <= 1) {
+    go(deriv_kernel<MODE, 1, W, 1>);
+  } else if constexpr (W > 1) {
+    if (mp <= 6) go(deriv_kernel<MODE, 1, W, 6>);
+    else if (mp == 7) go(deriv_kernel<MODE, 1, W, 7>);
+    else go(deriv_kernel<MODE, 1, W, 8>);
   }
-#undef LMRS_DERIV_ARGS
+}
+
+template <int W>
+void launch_deriv_w(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
+                    const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s) {
+  if (mode == 1) launch_deriv_mode<1, W>(f, d, o, tan, u, jp, grad2d, s);
+  else if (mode == 2) launch_deriv_mode<2, W>(f, d, o, tan, u, jp, grad2d, s);
+  else launch_deriv_mode<3, W>(f, d, o, tan, u, jp, grad2d, s);
 }
 
 void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,

@@ -116,11 +116,13 @@ def test_equal_depths_keep_id_order():
     assert len(np.unique(rec[vis, 9].view(np.uint32))) == 2
 
 
-@pytest.mark.parametrize("k", [24, 40, 64])
+@pytest.mark.parametrize("k", [24, 27, 32, 40, 64])
 def test_four_wave_paths(k):
     """Samples per tile at which the derivative walks run 4 waves per tile:
-    24 (per-lane colour-tangent accumulators, fewest pixels per wave), 40 and
-    64 (pixels beyond 32 per tile: one wave sum per step), against the oracle."""
+    24, 27 and 32 (pixels dealt to the waves by depth, 6, 7 and 8 per wave,
+    with per-lane colour-tangent accumulators), 40 and 64 (pixels beyond 32
+    per tile: dealt by slot, one wave sum per step), against the oracle
+    (GN product in check_all, J p, J^T u and the diagonal here)."""
     n, deg = 3000, 2
     gt = synth.make_scene(n, deg, 12, means="ball")
     beta = synth.perturb_init(gt, n, deg, 12)
