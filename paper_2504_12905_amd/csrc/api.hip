@@ -159,13 +159,15 @@ lmrs_status check_deriv_state(const lmrs_frame* f) {
 
 // J^T W J p + lambda d p into out (tangent, fused splat, chain).
 // pu_part (optional): partials of p . out for the PCG update.
+// grad_zero: s.grad2d is known to be all zero (a previous chain cleared it),
+// so it needs no fill; the chain leaves it all zero again.
 void gn_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* p,
                  float lambda, const float* dvec, float* out, const Scratch& s, hipStream_t st,
-                 double* pu_part = nullptr) {
+                 double* pu_part = nullptr, bool grad_zero = false) {
   launch_tangent(f, d, o, p, s.tan, st);
-  launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
+  if (!grad_zero) launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
   launch_deriv(3, f, d, o, s.tan, nullptr, nullptr, s.grad2d, st);
-  launch_chain_vjp(f, d, o, s.grad2d, p, lambda, dvec, out, st, pu_part);
+  launch_chain_vjp(f, d, o, s.grad2d, p, lambda, dvec, out, st, pu_part, true);
 }
 
 void vjp_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* u,
@@ -188,20 +190,21 @@ void vjp_diag_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_rende
   launch_fill(s.gram, (int64_t)d.V * d.n * kGram, 0.f, st);
   launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
   launch_gram(f, d, o, s.gram, u, s.grad2d, st);
-  launch_chain_vjp(f, d, o, s.grad2d, nullptr, 0.f, nullptr, b, st);
+  launch_chain_vjp(f, d, o, s.grad2d, nullptr, 0.f, nullptr, b, st, nullptr, true);  // leaves grad2d zero
   launch_chain_diag(f, d, o, s.gram, diag, st);
 }
 
-// PCG of Alg. 1; diag(J^T W J) is formed here unless have_diag (then s.diag holds it).
+// PCG of Alg. 1; diag(J^T W J) is formed here unless have_diag (then s.diag
+// holds it). grad_zero: s.grad2d is all zero on entry (vjp_diag_sequence ran).
 void pcg_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* b,
                   float lambda, const float* dvec, int iters, float* x, float* report, const Scratch& s,
-                  hipStream_t st, bool have_diag = false) {
+                  hipStream_t st, bool have_diag = false, bool grad_zero = false) {
   const int64_t P = (int64_t)d.n * d.pg;
   if (!have_diag) diag_sequence(f, d, o, s.diag, s, st);
   PcgState ps{x, s.r, s.z, s.p, s.u, s.minv, s.sc, s.red};
   launch_pcg_init(b, s.diag, lambda, dvec, P, ps, st);
   for (int it = 0; it < iters; ++it) {
-    gn_sequence(f, d, o, s.p, lambda, dvec, s.u, s, st, ps.partials);
+    gn_sequence(f, d, o, s.p, lambda, dvec, s.u, s, st, ps.partials, grad_zero || it > 0);
     launch_pcg_iteration(it, P, chain_vjp_blocks(d.n, true), ps, st);
   }
   if (report) launch_pcg_report(b, iters, P, ps, report, st);
@@ -280,7 +283,7 @@ void solve_sequence(const lmrs_frame* f, const FrameDims& d, float* beta, const 
   launch_render(f, d, o, st);
   launch_residual(f, d, targets, s.wr, s.red, report, st);
   vjp_diag_sequence(f, d, o, s.wr, s.b, s.diag, s, st);
-  pcg_sequence(f, d, o, s.b, prm.lambda, dvec, prm.cg_iters, s.x, report, s, st, true);
+  pcg_sequence(f, d, o, s.b, prm.lambda, dvec, prm.cg_iters, s.x, report, s, st, true, true);
   launch_lm_update(beta, s.x, d.n, P, prm, s.red, report, st);
   if (report) launch_report_count(f->n_instances, report + LMRS_REP_INST, st);
 }

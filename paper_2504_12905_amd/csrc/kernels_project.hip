@@ -99,13 +99,15 @@ __global__ __launch_bounds__(kBlock) void tangent_kernel(const float* __restrict
 // out[beta_g] = sum_v (d rec_vg / d beta_g)^T grad2d[v][g][0..9)  (+ lambda d p).
 // With pu_part, each workgroup also leaves its partial sum of p . out in
 // pu_part[blockIdx.x] (FP64; the PCG update reduces them), which saves the
-// operator product's separate pass over p and u.
+// operator product's separate pass over p and u. With zero_rows it clears
+// the non-zero rows it has read, so that grad2d is all zero again for the
+// next accumulation (instead of a fill of the whole buffer).
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
     const float* __restrict__ beta, int n, int V, const lmrs_camera* __restrict__ cams,
-    const int32_t* __restrict__ view_ids, float lowpass, const float* __restrict__ grad2d,
+    const int32_t* __restrict__ view_ids, float lowpass, float* __restrict__ grad2d,
     const float* __restrict__ p, float lambda, const float* __restrict__ dvec, float* __restrict__ out,
-    double* __restrict__ pu_part) {
+    double* __restrict__ pu_part, bool zero_rows) {
   constexpr int PG = ShDims<DEG>::PG;
   double pu = 0.0;
   for (int g = blockIdx.x * kBlock + threadIdx.x; g < n; g += gridDim.x * kBlock) {
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
     for (int v = 0; v < V; ++v) {
       float gr[9];
       bool any = false;
-      const float* row = grad2d + ((size_t)v * n + g) * kGradRow;
+      float* row = grad2d + ((size_t)v * n + g) * kGradRow;
       const float4 a = reinterpret_cast<const float4*>(row)[0], b = reinterpret_cast<const float4*>(row)[1];
       gr[0] = a.x; gr[1] = a.y; gr[2] = a.z; gr[3] = a.w;
       gr[4] = b.x; gr[5] = b.y; gr[6] = b.z; gr[7] = b.w;
@@ -124,6 +126,10 @@ __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
 #pragma unroll
       for (int q = 0; q < 9; ++q) any |= gr[q] != 0.f;
       if (!any) continue;
+      if (zero_rows) {
+        reinterpret_cast<float4*>(row)[0] = reinterpret_cast<float4*>(row)[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        row[8] = 0.f;
+      }
       const CamView cv = load_cam(cams, view_ids, v);
       proj_vjp<DEG>(prm, cv, lowpass, gr, gp);
     }
@@ -265,14 +271,14 @@ int chain_vjp_blocks(int n, bool partials) {
 }
 
 void launch_chain_vjp(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
-                      const float* grad2d, const float* p, float lambda, const float* dvec, float* out,
-                      hipStream_t s, double* pu_part) {
+                      float* grad2d, const float* p, float lambda, const float* dvec, float* out,
+                      hipStream_t s, double* pu_part, bool zero_rows) {
   const unsigned grid = (unsigned)chain_vjp_blocks(d.n, pu_part != nullptr);
   switch (d.deg) {
-    case 0: chain_vjp_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part); break;
-    case 1: chain_vjp_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part); break;
-    case 2: chain_vjp_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part); break;
-    default: chain_vjp_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part); break;
+    case 0: chain_vjp_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part, zero_rows); break;
+    case 1: chain_vjp_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part, zero_rows); break;
+    case 2: chain_vjp_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part, zero_rows); break;
+    default: chain_vjp_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part, zero_rows); break;
   }
 }
 

@@ -21,9 +21,11 @@ void launch_project(const lmrs_frame* f, const FrameDims& d, const lmrs_render_o
 void launch_tangent(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* p,
                     float* tan, hipStream_t s);
 // pu_part (optional): one FP64 partial of p . out per workgroup, chain_vjp_blocks(n, true) of them
+// zero_rows: clear the non-zero grad2d rows after reading them (grad2d is
+// then all zero for the next accumulation).
 void launch_chain_vjp(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
-                      const float* grad2d, const float* p, float lambda, const float* dvec, float* out,
-                      hipStream_t s, double* pu_part = nullptr);
+                      float* grad2d, const float* p, float lambda, const float* dvec, float* out,
+                      hipStream_t s, double* pu_part = nullptr, bool zero_rows = false);
 int chain_vjp_blocks(int n, bool partials);
 void launch_chain_diag(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                        const float* gram, float* out, hipStream_t s);
