@@ -1048,11 +1048,13 @@ void launch_deriv_w(int mode, const lmrs_frame* f, const FrameDims& d, const lmr
 
 void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                   const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s) {
-  // Measured: 4 waves per tile at 26 samples per tile (100k workload) take the
-  // fused splat from 0.59 to 0.535 ms; at 13 samples (1.5M workload) 2 or 4
-  // waves are slower than one (9.24 and 9.47 against 9.13 ms), their chunk
-  // loads and per-chunk reductions being shared by too few pixel steps.
+  // Measured: 4 waves per tile at 26 samples per tile (100k workload) took the
+  // fused splat from 0.59 to 0.535 ms with pixels dealt by slot. At 13 samples
+  // (1.5M workload) 2 or 4 slot-dealt waves were slower than one (9.24 and
+  // 9.47 against 9.13 ms); 2 waves with pixels dealt by depth are faster
+  // (4.07 -> 3.90 ms).
   if (d.k >= 24) launch_deriv_w<4>(mode, f, d, o, tan, u, jp, grad2d, s);
+  else if (d.k >= 12) launch_deriv_w<2>(mode, f, d, o, tan, u, jp, grad2d, s);
   else launch_deriv_w<1>(mode, f, d, o, tan, u, jp, grad2d, s);
 }
 

@@ -116,12 +116,13 @@ def test_equal_depths_keep_id_order():
     assert len(np.unique(rec[vis, 9].view(np.uint32))) == 2
 
 
-@pytest.mark.parametrize("k", [24, 27, 32, 40, 64])
-def test_four_wave_paths(k):
-    """Samples per tile at which the derivative walks run 4 waves per tile:
-    24, 27 and 32 (pixels dealt to the waves by depth, 6, 7 and 8 per wave,
-    with per-lane colour-tangent accumulators), 40 and 64 (pixels beyond 32
-    per tile: dealt by slot, one wave sum per step), against the oracle
+@pytest.mark.parametrize("k", [13, 16, 24, 27, 32, 40, 64])
+def test_multi_wave_paths(k):
+    """Samples per tile at which the derivative walks run several waves per
+    tile: 13 and 16 (2 waves, 7 and 8 pixels each) and 24, 27 and 32 (4
+    waves, 6 to 8 pixels each), pixels dealt to the waves by depth with
+    per-lane colour-tangent accumulators; 40 and 64 (4 waves, pixels beyond
+    32 per tile: dealt by slot, one wave sum per step). Against the oracle
     (GN product in check_all, J p, J^T u and the diagonal here)."""
     n, deg = 3000, 2
     gt = synth.make_scene(n, deg, 12, means="ball")
