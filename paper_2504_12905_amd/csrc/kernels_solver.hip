@@ -59,9 +59,17 @@ __global__ __launch_bounds__(256) void sample_kernel(const int32_t* __restrict__
   __syncthreads();
   if (p < k) s_sel[(int)(s[p] & 0xff)] = 1;
   __syncthreads();
-  if (s_sel[p]) {
-    int pos = 0;
-    for (int q = 0; q < p; ++q) pos += s_sel[q];
+  // position of pixel p among the selected ones: selected lanes below it in
+  // its wave (ballot) plus the selected pixels of the waves before
+  const bool sel = s_sel[p] != 0;
+  const uint64_t selm = __ballot(sel);
+  const uint64_t below = selm & ((1ull << (p & (kWave - 1))) - 1ull);
+  __shared__ int s_wave[256 / kWave];
+  if ((p & (kWave - 1)) == 0) s_wave[p / kWave] = __popcll(selm);
+  __syncthreads();
+  if (sel) {
+    int pos = __popcll(below);
+    for (int q = 0; q < p / kWave; ++q) pos += s_wave[q];
     pix[tile_lin * k + pos] = (uint8_t)p;
     w[tile_lin * k + pos] = 256.f / (float)k;
   }
