@@ -271,7 +271,11 @@ struct ScoreOut {
 };
 
 // W waves share a tile; wave wv renders the sample slots j with j % W == wv.
-template <int NS, int W>
+// With one slot of pixels and MP > 1 (at most MP pixels per wave), each lane
+// keeps its entry's colour contribution to each of the wave's pixels in
+// registers and the wave sums them once at the end, instead of three wave
+// sums per step.
+template <int NS, int W, int MP>
 __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restrict__ rec,
                                                        const int64_t* __restrict__ tile_start,
                                                        const int32_t* __restrict__ ids,
@@ -295,41 +299,71 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
     sLast[s] = -1;
     sDone[s] = 0;
   }
+  constexpr bool ACC = NS == 1 && MP > 1;
+  float A0[ACC ? MP : 1], A1[ACC ? MP : 1], A2[ACC ? MP : 1];
+#pragma unroll
+  for (int m = 0; m < (ACC ? MP : 1); ++m) A0[m] = A1[m] = A2[m] = 0.f;
   int remaining = k / W + (wv < k % W ? 1 : 0);  // this wave's pixels
   for (int c0 = 0; c0 < c.len && remaining > 0; c0 += kWave) {
     const bool valid = c0 + lane < c.len;
     RecF r{};
     if (valid) r = load_rec(rec, (size_t)c.v * n + ids[c.start + c0 + lane]);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int cnt = min(kWave, k - s * kWave);
-      for (int l = wv; l < cnt; l += W) {
-        if (readlane(sDone[s], l)) continue;
-        const Alpha al = pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
-        const bool inc = valid && al.inc;
-        const float a = inc ? al.a : 0.f;
-        const float om = inc ? 1.f - a : 1.f;
-        const float Tc = readlane(sT[s], l);
-        const float Taft = Tc * scan_mul(om);  // T behind this entry
-        // first entry whose blending would take T below t_min
-        const uint64_t stop = __ballot(inc && Taft < o.t_min);
-        const int f = stop ? __ffsll((unsigned long long)stop) - 1 : kWave;
-        const bool ok = inc && lane < f;
-        const float Tex = Taft * __builtin_amdgcn_rcpf(om);  // T in front of it
-        const float wgt = ok ? a * Tex : 0.f;
+    // pixel l of slot s (accumulator m in the accumulator path) against the chunk
+    auto step = [&](int s, int l, int m) {
+      const Alpha al = pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+      const bool inc = valid && al.inc;
+      const float a = inc ? al.a : 0.f;
+      const float om = inc ? 1.f - a : 1.f;
+      const float Tc = readlane(sT[s], l);
+      const float Taft = Tc * scan_mul(om);  // T behind this entry
+      // first entry whose blending would take T below t_min
+      const uint64_t stop = __ballot(inc && Taft < o.t_min);
+      const int f = stop ? __ffsll((unsigned long long)stop) - 1 : kWave;
+      const bool ok = inc && lane < f;
+      const float Tex = Taft * __builtin_amdgcn_rcpf(om);  // T in front of it
+      const float wgt = ok ? a * Tex : 0.f;
+      if (ACC) {
+        A0[m] += wgt * r.r;
+        A1[m] += wgt * r.g;
+        A2[m] += wgt * r.b;
+      } else {
         const float cr = wave_total(wgt * r.r), cg = wave_total(wgt * r.g), cb = wave_total(wgt * r.b);
-        const uint64_t okm = __ballot(ok);
-        const float Tnext = f < kWave ? readlane(Tex, f) : readlane(Taft, kWave - 1);
-        sT[s] = writelane(sT[s], Tnext, l);
         sC0[s] = writelane(sC0[s], readlane(sC0[s], l) + cr, l);
         sC1[s] = writelane(sC1[s], readlane(sC1[s], l) + cg, l);
         sC2[s] = writelane(sC2[s], readlane(sC2[s], l) + cb, l);
-        if (okm) sLast[s] = writelane(sLast[s], c0 + 63 - __clzll((long long)okm), l);
-        if (f < kWave) {
-          sDone[s] = writelane(sDone[s], 1, l);
-          --remaining;
-        }
       }
+      const uint64_t okm = __ballot(ok);
+      const float Tnext = f < kWave ? readlane(Tex, f) : readlane(Taft, kWave - 1);
+      sT[s] = writelane(sT[s], Tnext, l);
+      if (okm) sLast[s] = writelane(sLast[s], c0 + 63 - __clzll((long long)okm), l);
+      if (f < kWave) {
+        sDone[s] = writelane(sDone[s], 1, l);
+        --remaining;
+      }
+    };
+    if (ACC) {
+#pragma unroll
+      for (int m = 0; m < (ACC ? MP : 1); ++m) {
+        const int l = wv + m * W;
+        if (l < k && !readlane(sDone[0], l)) step(0, l, m);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int cnt = min(kWave, k - s * kWave);
+        for (int l = wv; l < cnt; l += W)
+          if (!readlane(sDone[s], l)) step(s, l, 0);
+      }
+    }
+  }
+  if (ACC) {
+#pragma unroll
+    for (int m = 0; m < (ACC ? MP : 1); ++m) {
+      const int l = wv + m * W;
+      if (l >= k) break;
+      sC0[0] = writelane(sC0[0], wave_total(A0[m]), l);
+      sC1[0] = writelane(sC1[0], wave_total(A1[m]), l);
+      sC2[0] = writelane(sC2[0], wave_total(A2[m]), l);
     }
   }
 #pragma unroll
@@ -989,12 +1023,16 @@ template <int W>
 void launch_render_w(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   int32_t* walk_len = f->sched + tiles;
-  if (d.k <= kWave)
-    render_kernel<1, W><<<tiles, kWave * W, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k, o,
-                                                    f->color, f->trans, f->last, walk_len);
-  else
-    render_kernel<4, W><<<tiles, kWave * W, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k, o,
-                                                    f->color, f->trans, f->last, walk_len);
+  // pixels per wave with per-lane colour accumulators: up to 8 or 16
+  const int per_wave = (d.k + W - 1) / W;
+  auto go = [&](auto kern) {
+    kern<<<tiles, kWave * W, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k, o, f->color,
+                                     f->trans, f->last, walk_len);
+  };
+  if (d.k > kWave) go(render_kernel<4, W, 1>);
+  else if (per_wave <= 8) go(render_kernel<1, W, 8>);
+  else if (per_wave <= 16) go(render_kernel<1, W, 16>);
+  else go(render_kernel<1, W, 1>);
 }
 
 void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
