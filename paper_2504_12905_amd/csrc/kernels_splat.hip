@@ -220,9 +220,14 @@ __global__ __launch_bounds__(kSchedThreads) void sched_kernel(int32_t* __restric
       const int i = base + u * kSchedThreads + tid;
       b[u] = i < tiles ? sched_bin(max(len[i], 0)) : -1;
     }
+    // empty tiles (often most of them) all fall in the last bin: counted
+    // per wave by ballot rather than by one LDS atomic each on one address
 #pragma unroll
-    for (int u = 0; u < kSchedUnroll; ++u)
-      if (b[u] >= 0) atomicAdd(&hist[b[u]], 1);
+    for (int u = 0; u < kSchedUnroll; ++u) {
+      const uint64_t empty = __ballot(b[u] == kSchedBins - 1);
+      if (b[u] >= 0 && b[u] != kSchedBins - 1) atomicAdd(&hist[b[u]], 1);
+      if (lane_id() == 0 && empty) atomicAdd(&hist[kSchedBins - 1], __popcll(empty));
+    }
   }
   __syncthreads();
   const int own = hist[tid];
@@ -245,8 +250,15 @@ __global__ __launch_bounds__(kSchedThreads) void sched_kernel(int32_t* __restric
       b[u] = i < tiles ? sched_bin(max(len[i], 0)) : -1;
     }
 #pragma unroll
-    for (int u = 0; u < kSchedUnroll; ++u)
-      if (b[u] >= 0) sched[atomicAdd(&hist[b[u]], 1)] = base + u * kSchedThreads + tid;
+    for (int u = 0; u < kSchedUnroll; ++u) {
+      const int i = base + u * kSchedThreads + tid;
+      const uint64_t empty = __ballot(b[u] == kSchedBins - 1);
+      if (b[u] >= 0 && b[u] != kSchedBins - 1) sched[atomicAdd(&hist[b[u]], 1)] = i;
+      int first = 0;
+      if (lane_id() == 0 && empty) first = atomicAdd(&hist[kSchedBins - 1], __popcll(empty));
+      first = readlane(first, 0);
+      if (b[u] == kSchedBins - 1) sched[first + __popcll(empty & ((1ull << lane_id()) - 1ull))] = i;
+    }
   }
   if (tid == kSchedBins - 1) {  // the last bin holds the tiles with walk length 0
     int32_t* ctr = sched + 2 * (int64_t)tiles;
