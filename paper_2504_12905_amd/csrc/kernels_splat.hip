@@ -3,25 +3,27 @@
 // kernel"), their fused composition J^T W J p (the operator product of the
 // PCG loop in Alg. 1), and the weighted Gram blocks behind diag(J^T W J).
 //
-// Work layout (one 64-lane wave per (view, tile) at a time; the derivative
-// kernels hand tiles to a persistent grid of waves, longest walk first, see
-// "tile schedule" below). The paper launches one
-// thread per sampled pixel; with ~10 % of a 16x16 tile sampled that leaves
-// most of a wave64 idle and forces cross-lane reductions of every Gaussian's
-// gradient. Here the lanes own list entries instead: a chunk of 64 entries
-// of the tile's depth-sorted list is loaded, one record per lane, and the
-// wave walks the tile's sampled pixels one after another. For each pixel
-// the transmittance in front of every entry is a prefix product of
-// (1 - alpha) across the lanes (a DPP scan), carried from chunk to chunk; J p
-// needs one prefix sum more for its derivative. J^T u walks the chunks back to front with the lane order
-// reversed inside a chunk, so the colour blended behind an entry and the
-// transmittance product behind it are prefix scans as well. Each lane then holds its Gaussian's screen-space
-// gradient summed over all pixels of the tile and issues one atomic add per
-// component: no per-Gaussian cross-lane reduction. A pixel's loop stops at
-// its last blended entry (`last` from the render), so work follows the
-// actual blend depth per pixel. Per-pixel state lives in lane registers
-// (pixel 64 s + l in slot s of lane l) and is read and written with
-// readlane / writelane.
+// Work layout. The paper launches one thread per sampled pixel; with ~10 %
+// of a 16x16 tile sampled that leaves most of a wave64 idle and forces
+// cross-lane reductions of every Gaussian's gradient. Here the lanes own list
+// entries instead: a chunk of 64 entries of the tile's depth-sorted list is
+// loaded, one record per lane, and a wave walks its share of the tile's
+// sampled pixels one after another (a tile's pixels are dealt to 1, 2 or 4
+// waves of a workgroup, see deriv_tile; the derivative kernels hand tiles to
+// a persistent grid, longest walk first, see "tile schedule" below). For
+// each pixel the transmittance in front of every entry is a prefix product
+// of (1 - alpha) across the lanes (a DPP scan), carried from chunk to chunk;
+// J p needs one prefix sum more for its derivative. J^T u walks the chunks
+// back to front with the lane order reversed inside a chunk, so the colour
+// blended behind an entry and the transmittance product behind it are prefix
+// scans as well. Each lane accumulates its entry's screen-space gradient
+// over the wave's pixels; per chunk the waves' partials meet in LDS and are
+// flushed transposed, an atomic instruction covering whole 64-byte gradient
+// rows of 4 entries. A pixel's loop stops at its last blended entry (`last`
+// from the render), so work follows the actual blend depth per pixel.
+// Per-pixel state lives in lane registers (pixel 64 s + l in slot s of lane
+// l) and is read and written with readlane / writelane. The residual scores
+// (every pixel of a tile) take a lane per pixel instead (score_kernel).
 //
 // Discrete decisions (list, opacity skip, cap, stop position) come from the
 // render and are recomputed bit-identically by pair_alpha().
