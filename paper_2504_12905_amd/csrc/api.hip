@@ -81,6 +81,7 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
     s.bin.order = reinterpret_cast<int32_t*>(s.bin.vval[0]);
     s.bin.vcount = c.take<int32_t>((size_t)view_sort_count_ints(d.n, d.V));
     s.bin.area_part = c.take<int64_t>(kBinAreaParts);
+    s.bin.col_part = c.take<int64_t>(((size_t)d.V * d.T + 255) / 256);
   }
   if (need_tan) s.tan = c.take<float>((size_t)VN * LMRS_REC);
   if (need_grad) s.grad2d = c.take<float>((size_t)VN * kGradRow);

@@ -13,7 +13,7 @@
 //    LDS (the only atomics are LDS atomics: a hot tile can hold thousands of
 //    entries, and global atomics on it would serialise across the chip).
 // 4. column scan per (view, tile) over the chunks -> running offsets; scan
-//    over the V*T totals -> tile_start (int64).
+//    over the V*T totals -> tile_start (int64), in 256-tile workgroups.
 // 5. emit: each chunk writes its Gaussians' ranks into their tiles'
 //    segments at (tile start + chunk offset + LDS cursor). A tile's list is
 //    thereby ordered by chunk, i.e. by rank up to the order inside each
@@ -118,57 +118,68 @@ __global__ __launch_bounds__(kBinThreads) void hist_kernel(const int4* __restric
   for (int t = threadIdx.x; t < T; t += kBinThreads) dst[t] = s_hist[t];
 }
 
-// Per (view, tile): chunk counts -> running offsets; tile total -> counts.
-// The counts are read kColUnroll chunks ahead of the running sum.
+// Per (view, tile): chunk counts -> running offsets; tile total -> counts;
+// each workgroup's sum of its 256 tile totals -> col_part. The counts are
+// read kColUnroll chunks ahead of the running sum.
 constexpr int kColUnroll = 8;
 __global__ __launch_bounds__(256) void colscan_kernel(int32_t* __restrict__ chunk_hist, int V, int T,
-                                                      int n_chunks, int32_t* __restrict__ counts) {
+                                                      int n_chunks, int32_t* __restrict__ counts,
+                                                      int64_t* __restrict__ col_part) {
+  __shared__ double s_red[256];
   const int64_t vt = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (vt >= (int64_t)V * T) return;
-  const int v = (int)(vt / T), t = (int)(vt % T);
-  int32_t* h = chunk_hist + (size_t)v * n_chunks * T + t;
   int32_t run = 0;
-  for (int c0 = 0; c0 < n_chunks; c0 += kColUnroll) {
-    int32_t x[kColUnroll];
+  if (vt < (int64_t)V * T) {
+    const int v = (int)(vt / T), t = (int)(vt % T);
+    int32_t* h = chunk_hist + (size_t)v * n_chunks * T + t;
+    for (int c0 = 0; c0 < n_chunks; c0 += kColUnroll) {
+      int32_t x[kColUnroll];
 #pragma unroll
-    for (int u = 0; u < kColUnroll; ++u) x[u] = c0 + u < n_chunks ? h[(size_t)(c0 + u) * T] : 0;
+      for (int u = 0; u < kColUnroll; ++u) x[u] = c0 + u < n_chunks ? h[(size_t)(c0 + u) * T] : 0;
 #pragma unroll
-    for (int u = 0; u < kColUnroll; ++u)
-      if (c0 + u < n_chunks) {
-        h[(size_t)(c0 + u) * T] = run;
-        run += x[u];
-      }
+      for (int u = 0; u < kColUnroll; ++u)
+        if (c0 + u < n_chunks) {
+          h[(size_t)(c0 + u) * T] = run;
+          run += x[u];
+        }
+    }
+    counts[vt] = run;
   }
-  counts[vt] = run;
+  const double sum = block_sum((double)run, s_red);  // exact: far below 2^53
+  if (threadIdx.x == 0) col_part[blockIdx.x] = (int64_t)sum;
 }
 
-// Single workgroup of 1024 threads scans `m` counts.
-__global__ __launch_bounds__(1024) void scan_kernel(int32_t* __restrict__ counts, int64_t m,
-                                                    int64_t* __restrict__ tile_start,
-                                                    int64_t* __restrict__ total) {
-  __shared__ int64_t s_part[1024];
-  const int tid = threadIdx.x;
-  const int64_t per = (m + 1023) / 1024;
-  const int64_t a = tid * per, b = min(m, a + per);
-  int64_t acc = 0;
-  for (int64_t i = a; i < b; ++i) acc += counts[i];
-  s_part[tid] = acc;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan of the partials
-    int64_t y = tid >= d ? s_part[tid - d] : 0;
-    __syncthreads();
-    s_part[tid] += y;
-    __syncthreads();
+// tile_start = exclusive prefix sum of the m tile totals, in the workgroups
+// of colscan_kernel: each adds the col_part of the workgroups before it to a
+// scan of its own 256 totals; the counts are reset to zero for the cursors of
+// the next binning. The last entry also gives tile_start[m] and the total.
+__global__ __launch_bounds__(256) void tile_start_kernel(int32_t* __restrict__ counts, int64_t m,
+                                                         const int64_t* __restrict__ col_part,
+                                                         int64_t* __restrict__ tile_start,
+                                                         int64_t* __restrict__ total) {
+  __shared__ double s_red[256];
+  __shared__ int64_t s_wave[256 / kWave];
+  const int tid = threadIdx.x, lane = lane_id();
+  int64_t before = 0;
+  for (int b = tid; b < (int)blockIdx.x; b += 256) before += col_part[b];
+  const int64_t off = (int64_t)block_sum((double)before, s_red);
+  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  const int64_t x = i < m ? counts[i] : 0;
+  int64_t y = x;  // inclusive scan over the workgroup
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t z = __shfl_up(y, d, kWave);
+    if (lane >= d) y += z;
   }
-  int64_t run = s_part[tid] - acc;
-  for (int64_t i = a; i < b; ++i) {
-    tile_start[i] = run;
-    run += counts[i];
+  if (lane == kWave - 1) s_wave[tid / kWave] = y;
+  __syncthreads();
+  for (int w = 0; w < tid / kWave; ++w) y += s_wave[w];
+  if (i < m) {
+    tile_start[i] = off + y - x;
     counts[i] = 0;
   }
-  if (tid == 1023) {
-    tile_start[m] = s_part[1023];
-    *total = s_part[1023];
+  if (i == m - 1) {
+    tile_start[m] = off + y;
+    *total = off + y;
   }
 }
 
@@ -527,8 +538,9 @@ void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hip
   hist_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), b.order, d.n, d.TX,
                                                       d.T, nc, b.chunk_hist);
   const int64_t m = (int64_t)d.V * d.T;
-  colscan_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(b.chunk_hist, d.V, d.T, nc, b.counts);
-  scan_kernel<<<1, 1024, 0, s>>>(b.counts, m, f->tile_start, f->n_instances);
+  const unsigned cblocks = (unsigned)((m + 255) / 256);
+  colscan_kernel<<<cblocks, 256, 0, s>>>(b.chunk_hist, d.V, d.T, nc, b.counts, b.col_part);
+  tile_start_kernel<<<cblocks, 256, 0, s>>>(b.counts, m, b.col_part, f->tile_start, f->n_instances);
 }
 
 void launch_view_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {

@@ -41,6 +41,7 @@ struct BinScratch {
   int32_t* order;       // [V][n] Gaussian id of each depth rank (= vval[0] after the sort)
   int32_t* vcount;      // [view_sort_count_ints(n, V)] digit counts / offsets of the view sort
   int64_t* area_part;   // [kBinAreaParts] partial sums of the entry count
+  int64_t* col_part;    // [ceil(V*T / 256)] per-workgroup sums of the tile totals
 };
 constexpr int kBinAreaParts = 1024;
 int view_sort_count_ints(int n, int V);
