@@ -207,34 +207,6 @@ enum : int {
   kScalars = 16
 };
 
-__global__ __launch_bounds__(256) void pcg_init_kernel(const float* __restrict__ b,
-                                                       const float* __restrict__ diag, float lambda,
-                                                       const float* __restrict__ dvec, int64_t P,
-                                                       float* __restrict__ x, float* __restrict__ r,
-                                                       float* __restrict__ z, float* __restrict__ p,
-                                                       float* __restrict__ minv, double* __restrict__ partials) {
-  __shared__ double s_red[256];
-  double rz = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
-    const float m = 1.f / (diag[i] + lambda * (dvec ? dvec[i] : 1.f));
-    const float bi = b[i];
-    minv[i] = m;
-    x[i] = 0.f;
-    r[i] = bi;
-    const float zi = m * bi;
-    z[i] = zi;
-    p[i] = zi;
-    rz += (double)bi * zi;
-    rr += (double)bi * bi;
-  }
-  const double a = block_sum(rz, s_red);
-  const double c = block_sum(rr, s_red);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = a;
-    partials[kRedBlocks + blockIdx.x] = c;
-  }
-}
-
 // VEC floats as one unit: float4 (16-byte accesses) or a single float.
 template <int VEC>
 struct Vec;
@@ -261,6 +233,61 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
   double acc = 0.0;
   for (int i = threadIdx.x; i < count; i += 256) acc += partials[i];
   return block_sum(acc, s_red);
+}
+
+// x = 0, r = b, M^-1 = 1 / (diag + lambda d), z = p = M^-1 r, and the
+// partials of r^T z and r^T r; VEC consecutive elements per thread and step.
+template <int VEC>
+__global__ __launch_bounds__(256) void pcg_init_kernel(const float* __restrict__ b,
+                                                       const float* __restrict__ diag, float lambda,
+                                                       const float* __restrict__ dvec, int64_t P,
+                                                       float* __restrict__ x, float* __restrict__ r,
+                                                       float* __restrict__ z, float* __restrict__ p,
+                                                       float* __restrict__ minv, double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  double rz = 0.0, rr = 0.0;
+  using V = Vec<VEC>;
+  const int64_t units = P / VEC;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < units; i += (int64_t)gridDim.x * 256) {
+    const typename V::T dv = V::load(diag, i), bv = V::load(b, i);
+    typename V::T ev;
+    if (dvec) ev = V::load(dvec, i);
+    typename V::T mv, zv, xv;
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) {
+      const float m = 1.f / (V::at(dv, c) + lambda * (dvec ? V::at(ev, c) : 1.f));
+      const float bi = V::at(bv, c), zi = m * bi;
+      V::at(mv, c) = m;
+      V::at(zv, c) = zi;
+      V::at(xv, c) = 0.f;
+      rz += (double)bi * zi;
+      rr += (double)bi * bi;
+    }
+    V::store(minv, i, mv);
+    V::store(x, i, xv);
+    V::store(r, i, bv);
+    V::store(z, i, zv);
+    V::store(p, i, zv);
+  }
+  if (blockIdx.x == 0) {  // the last P % VEC elements
+    for (int64_t i = units * VEC + threadIdx.x; i < P; i += 256) {
+      const float m = 1.f / (diag[i] + lambda * (dvec ? dvec[i] : 1.f));
+      const float bi = b[i], zi = m * bi;
+      minv[i] = m;
+      x[i] = 0.f;
+      r[i] = bi;
+      z[i] = zi;
+      p[i] = zi;
+      rz += (double)bi * zi;
+      rr += (double)bi * bi;
+    }
+  }
+  const double a = block_sum(rz, s_red);
+  const double c = block_sum(rr, s_red);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = a;
+    partials[kRedBlocks + blockIdx.x] = c;
+  }
 }
 
 // Scalars after pcg_init_kernel: r0^T z0 and r0^T r0 from its partials.
@@ -473,14 +500,19 @@ void launch_dot(const float* a, const float* b, int64_t n, double* partials, dou
   finalize_kernel<<<1, 256, 0, s>>>(partials, kRedBlocks, 1, kRedBlocks, out);
 }
 
+static bool aligned16(const void* a) { return (reinterpret_cast<uintptr_t>(a) & 15) == 0; }
+
 void launch_pcg_init(const float* b, const float* diag, float lambda, const float* dvec, int64_t P,
                      PcgState st, hipStream_t s) {
-  pcg_init_kernel<<<kRedBlocks, 256, 0, s>>>(b, diag, lambda, dvec, P, st.x, st.r, st.z, st.p, st.minv,
-                                             st.partials);
+  if (aligned16(b) && aligned16(diag) && (!dvec || aligned16(dvec)) && aligned16(st.x) && aligned16(st.r) &&
+      aligned16(st.z) && aligned16(st.p) && aligned16(st.minv))
+    pcg_init_kernel<4><<<kRedBlocks, 256, 0, s>>>(b, diag, lambda, dvec, P, st.x, st.r, st.z, st.p, st.minv,
+                                                  st.partials);
+  else
+    pcg_init_kernel<1><<<kRedBlocks, 256, 0, s>>>(b, diag, lambda, dvec, P, st.x, st.r, st.z, st.p, st.minv,
+                                                  st.partials);
   pcg_init_scalars_kernel<<<1, 256, 0, s>>>(st.partials, st.bank(0));
 }
-
-static bool aligned16(const void* a) { return (reinterpret_cast<uintptr_t>(a) & 15) == 0; }
 
 void launch_pcg_iteration(int it, int64_t P, int pu_count, PcgState st, hipStream_t s) {
   double* cur = st.bank(it);
