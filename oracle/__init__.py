@@ -22,17 +22,29 @@ from .build import LIB, build
 _lib = None
 
 # Rasteriser options: alpha floor and cap, transmittance stop, EWA low-pass
-# (px^2), near plane, footprint extent in sigmas, background RGB.
-DEFAULT_OPTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, lowpass=0.3, znear=0.2,
-                    cutoff=3.0, bg=(0.0, 0.0, 0.0))
+# (px^2), near plane, footprint extent in sigmas, background RGB. The options
+# block of the problem statement holds FP32 numbers, so each value is the
+# FP32 number nearest the decimal one (0.3 is 0.30000001192092896), on the
+# FP64 side as well: both sides then decide with the same thresholds.
+def _f32(x: float) -> float:
+    return float(np.float32(x))
+
+
+DEFAULT_OPTS = dict(alpha_min=_f32(1.0 / 255.0), alpha_max=_f32(0.99), t_min=_f32(1e-4), lowpass=_f32(0.3),
+                    znear=_f32(0.2), cutoff=3.0, bg=(0.0, 0.0, 0.0))
+
+# Bound on how far two FP64 evaluations of a list decision (footprint radius
+# extent, rectangle edge, near-plane depth) may disagree, in pixels / depth
+# units: the extents are below 1e4 px and FP64 carries 16 digits.
+TAU_LIST = 1e-9
 
 
 def opts_array(opts: dict | None = None) -> np.ndarray:
     o = dict(DEFAULT_OPTS)
     if opts:
         o.update(opts)
-    return np.array([o["alpha_min"], o["alpha_max"], o["t_min"], o["lowpass"], o["znear"],
-                     o["cutoff"], *o["bg"]], dtype=np.float64)
+    vals = [o["alpha_min"], o["alpha_max"], o["t_min"], o["lowpass"], o["znear"], o["cutoff"], *o["bg"]]
+    return np.array([_f32(x) for x in vals], dtype=np.float64)
 
 
 def lib():
@@ -47,7 +59,7 @@ def lib():
         L.or_destroy.argtypes = [vp]
         L.or_num_instances.restype = i64
         L.or_num_instances.argtypes = [vp]
-        L.or_get_projection.argtypes = [vp] * 7
+        L.or_get_projection.argtypes = [vp] * 8
         L.or_get_lists.argtypes = [vp, vp, vp]
         L.or_undecided_tiles.argtypes = [vp, dbl, vp]
         L.or_set_samples.argtypes = [vp, i32, vp, vp]
@@ -61,6 +73,7 @@ def lib():
         L.or_proj_jacobian.argtypes = [vp, i32, i32, vp]
         L.or_sh_basis.argtypes = [i32, dbl, dbl, dbl, vp]
         L.or_num_threads.restype = i32
+        L.or_set_num_threads.argtypes = [i32]
         _lib = L
     return _lib
 
@@ -108,14 +121,20 @@ class Oracle:
     def projection(self):
         VN = self.V * self.n
         rec = np.zeros((self.V, self.n, 9))
-        depth = np.zeros((self.V, self.n), np.float32)
+        depth = np.zeros((self.V, self.n))
         rect = np.zeros((self.V, self.n, 4), np.int32)
         radius = np.zeros((self.V, self.n), np.int32)
         margin = np.zeros((self.V, self.n))
+        margin_rad = np.zeros((self.V, self.n))
         vis = np.zeros((self.V, self.n), np.uint8)
-        lib().or_get_projection(self.h, _p(rec), _p(depth), _p(rect), _p(radius), _p(margin), _p(vis))
+        lib().or_get_projection(self.h, _p(rec), _p(depth), _p(rect), _p(radius), _p(margin), _p(vis),
+                                _p(margin_rad))
         assert rec.size == VN * 9
-        return dict(rec=rec, depth=depth, rect=rect, radius=radius, margin=margin, visible=vis)
+        # depth: FP64 camera z (the sort key); margin: distance of the closest list
+        # decision to its threshold (radius extent to an integer, rectangle edge
+        # to a tile edge, depth to the near plane), margin_rad: the radius part
+        return dict(rec=rec, depth=depth, rect=rect, radius=radius, margin=margin, margin_rad=margin_rad,
+                    visible=vis)
 
     def lists(self):
         ni = lib().or_num_instances(self.h)
@@ -168,24 +187,27 @@ class Oracle:
         lib().or_render(self.h, _p(Cc), _p(T), _p(last), _p(nc), _p(tr), _p(mg))
         return dict(C=Cc, T=T, last=last, n_contrib=nc, trace=tr, margin=mg)
 
-    def undecided_tiles(self, tau: float = 1e-4) -> np.ndarray:
+    def undecided_tiles(self, tau: float = TAU_LIST) -> np.ndarray:
         """uint8 [V*T]: tiles whose list could hold one Gaussian more or less
-        under FP32 arithmetic (a footprint radius within tau of rounding the
-        other way: the tiles held with only one of the two radii; see
-        or_undecided_tiles)."""
+        under a less exact evaluation of a footprint radius (its extent within
+        tau px of an integer: the tiles held with only one of the two radii;
+        see or_undecided_tiles)."""
         flags = np.zeros(self.V * self.T, np.uint8)
         lib().or_undecided_tiles(self.h, float(tau), _p(flags))
         return flags
 
-    def decided(self, tau: float = 1e-4) -> np.ndarray:
-        """Sampled pixels whose discrete decisions (tile-list membership, exponent
-        sign, alpha floor and cap, transmittance stop) all lie farther than tau
-        from their thresholds (relative; for the radius, in pixels). Below that,
-        FP32 and FP64 arithmetic may decide differently, and the pixel's colour
-        and derivative are not unique at FP32 precision."""
+    def decided(self, tau: float = 1e-4, tau_list: float = TAU_LIST) -> np.ndarray:
+        """Sampled pixels whose blend decisions (exponent sign, alpha floor and
+        cap, transmittance stop) all lie farther than tau (relative) from their
+        thresholds, in tiles whose lists no radius within tau_list px of an
+        integer could change. The blend decisions are taken in FP32 on the GPU
+        and in FP64 here, so below tau they may differ, and the pixel's colour
+        and derivative are then not unique at FP32 precision. List decisions
+        are FP64 on both sides (tau_list bounds the disagreement of two FP64
+        evaluations)."""
         ok = self.render()["margin"] >= tau
         tile = np.arange(self.S) // self.k
-        return ok & (self.undecided_tiles(tau)[tile] == 0)
+        return ok & (self.undecided_tiles(tau_list)[tile] == 0)
 
     def render_image(self) -> np.ndarray:
         """Full images [V, H, W, 3] (uses all pixels; resets the sample set)."""
@@ -254,3 +276,8 @@ def sh_basis(deg: int, d: np.ndarray) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads of the oracle's OpenMP regions from now on (this thread)."""
+    lib().or_set_num_threads(int(t))

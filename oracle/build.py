@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "liblmrs_oracle.so")
 def build(force: bool = True) -> str:
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
-    # -ffp-contract=off keeps the FP32 decision expressions exactly as written.
+    # -ffp-contract=off: every expression is evaluated as written (no fused multiply-adds).
     cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
            "-o", LIB + ".tmp", SRC]
     subprocess.check_call(cmd)

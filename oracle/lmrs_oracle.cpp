@@ -16,12 +16,13 @@
 // Rasteriser constants (alpha floor/cap, transmittance stop, low-pass, near
 // plane, 3-sigma extent) are the options block; the paper defers them to 3DGS.
 //
-// Every floating-point computation is FP64 except the discrete decisions that
-// build the tile lists (depth key, projected centre for the tile rectangle):
-// those are taken in FP32 with a fixed operation order, the precision the
-// paper's kernels use, so that the lists are comparable bit for bit. The
-// footprint radius comes from the FP64 eigenvalue; its distance to the next
-// integer is reported as a margin.
+// Every floating-point computation is FP64, the discrete decisions that build
+// the tile lists included: a Gaussian is listed when its camera depth exceeds
+// the near plane and its footprint square of half-width ceil(3 sqrt(lambda_max))
+// around the projected centre overlaps the tile; lists are ordered by camera
+// depth, ties by Gaussian index. The distance of each such decision to its
+// threshold (extent to the next integer, square edge to a tile edge, depth to
+// the near plane) is reported as a margin.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -72,7 +73,6 @@ struct Opts {
 
 struct Cam {
   double R[9], t[3], fx, fy, cx, cy, campos[3];
-  float Rf[9], tf[3], fxf, fyf, cxf, cyf;
 };
 
 constexpr int kTile = 16;
@@ -286,10 +286,11 @@ struct Problem {
   // projection, per (view, Gaussian)
   std::vector<Rec<double>> rec;  // [V*n]
   std::vector<uint8_t> visible;  // [V*n]
-  std::vector<float> depth32;    // [V*n] FP32 depth key
+  std::vector<double> depth;     // [V*n] camera-space z of the mean (the sort key)
   std::vector<int> rect;         // [V*n*4] x0, y0, x1, y1 (tile coords, end exclusive)
   std::vector<int> radius;       // [V*n]
   std::vector<double> margin_rad;  // [V*n] distance of cutoff*sqrt(lam_max) to an integer
+  std::vector<double> margin_list; // [V*n] smallest distance of a list decision to its threshold
   std::vector<int> radius_all;   // [V*n] footprint radius before the image-bounds cull (0 if not projected)
   std::vector<double> ext_all;   // [V*n] cutoff * sqrt(lambda_max) (0 if not projected)
   // tile lists
@@ -318,38 +319,30 @@ struct Problem {
   double weight_of(int64_t i) const { return w.empty() ? 1.0 : w[(size_t)i]; }
 };
 
-// FP32 quantities that decide list membership and order (fixed operation order).
-void decision_fp32(const Problem& pb, int v, int g, float* tz, float* u, float* vv) {
-  const Cam& c = pb.cams[v];
-  const float m[3] = {(float)pb.beta[g], (float)pb.beta[(size_t)pb.n + g],
-                      (float)pb.beta[(size_t)2 * pb.n + g]};
-  float tc[3];
-  for (int i = 0; i < 3; ++i) {
-    float acc = c.tf[i];
-    acc = fmaf(c.Rf[3 * i + 0], m[0], acc);
-    acc = fmaf(c.Rf[3 * i + 1], m[1], acc);
-    acc = fmaf(c.Rf[3 * i + 2], m[2], acc);
-    tc[i] = acc;
-  }
-  *tz = tc[2];
-  *u = fmaf(c.fxf, tc[0] / tc[2], c.cxf);
-  *vv = fmaf(c.fyf, tc[1] / tc[2], c.cyf);
+// Tile index floor(q / 16), clamped before the int conversion (a centre far
+// outside the image gives an index far outside too).
+int tile_index(double q) { return (int)std::min(std::max(std::floor(q / kTile), -1.0e6), 1.0e6); }
+
+// Distance of q to the nearest multiple of 16 (a tile edge, in pixels).
+double edge_margin(double q) {
+  const double f = q / kTile;
+  return std::fabs(f - std::round(f)) * kTile;
 }
 
-// floor(q / 16) in FP32, clamped before the int conversion
-int tile_of_fp32(float q) {
-  const float f = std::floor(q / 16.f);
-  return (int)std::min(std::max(f, -1.0e6f), 1.0e6f);
-}
-
+// Per (view, Gaussian): camera depth t_z = (R mu + t)_z, the screen record and,
+// when t_z is beyond the near plane and the projected centre is finite, the
+// footprint radius r = ceil(cutoff sqrt(lambda_max)) and the tile rectangle
+// {tile x : 16 x <= u + r and 16 x + 16 > u - r} (same for y), clipped to the
+// image; an empty rectangle means the Gaussian is listed nowhere.
 void project_all(Problem& pb) {
   const size_t VN = (size_t)pb.V * pb.n;
   pb.rec.assign(VN, Rec<double>{});
   pb.visible.assign(VN, 0);
-  pb.depth32.assign(VN, 0.f);
+  pb.depth.assign(VN, 0.0);
   pb.rect.assign(VN * 4, 0);
   pb.radius.assign(VN, 0);
   pb.margin_rad.assign(VN, 1.0);
+  pb.margin_list.assign(VN, 1e30);
   pb.radius_all.assign(VN, 0);
   pb.ext_all.assign(VN, 0.0);
 #pragma omp parallel for schedule(static)
@@ -357,13 +350,16 @@ void project_all(Problem& pb) {
     const int v = (int)(vg / pb.n), g = (int)(vg % pb.n);
     double prm[11 + 48];
     pb.params_of(g, prm);
-    float tz32, u32, v32;
-    decision_fp32(pb, v, g, &tz32, &u32, &v32);
-    pb.depth32[vg] = tz32;
-    if (!(tz32 > (float)pb.op.znear) || !std::isfinite(u32) || !std::isfinite(v32)) continue;
+    const Cam& c = pb.cams[v];
+    double tc[3];
+    for (int i = 0; i < 3; ++i)
+      tc[i] = c.R[3 * i + 0] * prm[0] + c.R[3 * i + 1] * prm[1] + c.R[3 * i + 2] * prm[2] + c.t[i];
+    pb.depth[vg] = tc[2];
+    pb.margin_list[vg] = std::fabs(tc[2] - pb.op.znear);
     Rec<double> r;
     double lam = 0.0;
-    if (!project_cont(prm, pb.deg, pb.cams[v], pb.op, r, &lam)) continue;
+    if (!project_cont(prm, pb.deg, c, pb.op, r, &lam)) continue;  // t_z <= znear
+    if (!std::isfinite(r.u) || !std::isfinite(r.v)) continue;
     pb.rec[vg] = r;
     const double ext = pb.op.cutoff * std::sqrt(lam);
     const double rad_d = std::ceil(ext);
@@ -372,9 +368,11 @@ void project_all(Problem& pb) {
     if (!(rad_d < 1e6)) continue;
     const int rad = (int)rad_d;
     pb.radius_all[vg] = rad;
-    const float rf = (float)rad;
-    int x0 = tile_of_fp32(u32 - rf), x1 = tile_of_fp32(u32 + rf);
-    int y0 = tile_of_fp32(v32 - rf), y1 = tile_of_fp32(v32 + rf);
+    const double lo_x = r.u - rad, hi_x = r.u + rad, lo_y = r.v - rad, hi_y = r.v + rad;
+    pb.margin_list[vg] = std::min({pb.margin_list[vg], pb.margin_rad[vg], edge_margin(lo_x), edge_margin(hi_x),
+                                   edge_margin(lo_y), edge_margin(hi_y)});
+    int x0 = tile_index(lo_x), x1 = tile_index(hi_x);
+    int y0 = tile_index(lo_y), y1 = tile_index(hi_y);
     x0 = std::max(x0, 0); y0 = std::max(y0, 0);
     x1 = std::min(x1, pb.TX - 1); y1 = std::min(y1, pb.TY - 1);
     if (x0 > x1 || y0 > y1) continue;
@@ -386,9 +384,9 @@ void project_all(Problem& pb) {
 }
 
 // Tile lists: every visible Gaussian whose tile rectangle holds the tile,
-// ascending FP32 depth key, ties by ascending Gaussian index.
+// ascending camera depth, ties by ascending Gaussian index.
 void bin_all(Problem& pb) {
-  std::vector<std::vector<std::pair<float, int>>> lists((size_t)pb.V * pb.T);
+  std::vector<std::vector<std::pair<double, int>>> lists((size_t)pb.V * pb.T);
   for (int v = 0; v < pb.V; ++v)
     for (int g = 0; g < pb.n; ++g) {
       const size_t vg = (size_t)v * pb.n + g;
@@ -396,7 +394,7 @@ void bin_all(Problem& pb) {
       const int* rc = &pb.rect[vg * 4];
       for (int ty = rc[1]; ty < rc[3]; ++ty)
         for (int tx = rc[0]; tx < rc[2]; ++tx)
-          lists[(size_t)v * pb.T + ty * pb.TX + tx].push_back({pb.depth32[vg], g});
+          lists[(size_t)v * pb.T + ty * pb.TX + tx].push_back({pb.depth[vg], g});
     }
   pb.tile_start.assign((size_t)pb.V * pb.T + 1, 0);
   for (size_t i = 0; i < lists.size(); ++i) pb.tile_start[i + 1] = pb.tile_start[i] + lists[i].size();
@@ -419,10 +417,9 @@ void setup(Problem& pb, int n, int deg, const double* beta, int V, const float* 
   for (int v = 0; v < V; ++v) {
     const float* c = cams + 16 * v;
     Cam& k = pb.cams[v];
-    for (int i = 0; i < 9; ++i) { k.R[i] = c[i]; k.Rf[i] = c[i]; }
-    for (int i = 0; i < 3; ++i) { k.t[i] = c[9 + i]; k.tf[i] = c[9 + i]; }
+    for (int i = 0; i < 9; ++i) k.R[i] = c[i];
+    for (int i = 0; i < 3; ++i) k.t[i] = c[9 + i];
     k.fx = c[12]; k.fy = c[13]; k.cx = c[14]; k.cy = c[15];
-    k.fxf = c[12]; k.fyf = c[13]; k.cxf = c[14]; k.cyf = c[15];
     for (int i = 0; i < 3; ++i)  // camera centre -R^T t
       k.campos[i] = -(k.R[0 + i] * k.t[0] + k.R[3 + i] * k.t[1] + k.R[6 + i] * k.t[2]);
   }
@@ -679,43 +676,48 @@ void or_destroy(void* h) { delete static_cast<Problem*>(h); }
 
 int64_t or_num_instances(void* h) { return (int64_t) static_cast<Problem*>(h)->ids.size(); }
 
-void or_get_projection(void* h, double* rec, float* depth, int* rect, int* radius, double* margin,
-                       uint8_t* visible) {
+// margin: per (view, Gaussian) the smallest distance of a list decision to
+// its threshold (radius extent to an integer, rectangle edge to a tile edge,
+// depth to the near plane); margin_rad: the radius part alone.
+void or_get_projection(void* h, double* rec, double* depth, int* rect, int* radius, double* margin,
+                       uint8_t* visible, double* margin_rad) {
   Problem& pb = *static_cast<Problem*>(h);
   const size_t VN = (size_t)pb.V * pb.n;
   for (size_t i = 0; i < VN; ++i) {
     if (rec) rec_to_array(pb.rec[i], rec + i * kRec);
-    if (depth) depth[i] = pb.depth32[i];
+    if (depth) depth[i] = pb.depth[i];
     if (radius) radius[i] = pb.radius[i];
-    if (margin) margin[i] = pb.margin_rad[i];
+    if (margin) margin[i] = pb.margin_list[i];
+    if (margin_rad) margin_rad[i] = pb.margin_rad[i];
     if (visible) visible[i] = pb.visible[i];
     if (rect) std::memcpy(rect + 4 * i, &pb.rect[4 * i], 4 * sizeof(int));
   }
 }
 
-// Tiles whose list membership FP32 arithmetic may decide differently: for
-// every Gaussian whose extent cutoff * sqrt(lambda_max) lies within tau of an
-// integer, the tiles held by its rectangle with exactly one of the radius r
-// and the radius an FP32 evaluation may give instead: r - 1 when the extent
-// lies just above the integer, r + 1 when just below.
+// Tiles whose list membership a less exact evaluation of the radius may
+// decide differently: for every Gaussian whose extent cutoff * sqrt(lambda_max)
+// lies within tau of an integer, the tiles held by its rectangle with exactly
+// one of the radius r and the neighbouring radius such an evaluation may give
+// instead: r - 1 when the extent lies just above the integer, r + 1 when just
+// below.
 void or_undecided_tiles(void* h, double tau, uint8_t* flags) {
   Problem& pb = *static_cast<Problem*>(h);
   std::fill(flags, flags + (size_t)pb.V * pb.T, (uint8_t)0);
   const size_t VN = (size_t)pb.V * pb.n;
   for (size_t vg = 0; vg < VN; ++vg) {
     if (!(pb.margin_rad[vg] < tau) || pb.radius_all[vg] <= 0) continue;
-    const int v = (int)(vg / pb.n), g = (int)(vg % pb.n);
-    float tz32, u32, v32;
-    decision_fp32(pb, v, g, &tz32, &u32, &v32);
+    const int v = (int)(vg / pb.n);
+    const double u = pb.rec[vg].u, vv = pb.rec[vg].v;
     const double ext = pb.ext_all[vg];
     const int alt = ext - std::floor(ext) < 0.5 ? -1 : 1;
+    auto tile_of = tile_index;
     int box[2][4];
     for (int k = 0; k < 2; ++k) {
-      const float rf = (float)(pb.radius_all[vg] + (k == 0 ? 0 : alt));
-      box[k][0] = std::max(tile_of_fp32(u32 - rf), 0);
-      box[k][1] = std::max(tile_of_fp32(v32 - rf), 0);
-      box[k][2] = std::min(tile_of_fp32(u32 + rf), pb.TX - 1);
-      box[k][3] = std::min(tile_of_fp32(v32 + rf), pb.TY - 1);
+      const double rf = pb.radius_all[vg] + (k == 0 ? 0 : alt);
+      box[k][0] = std::max(tile_of(u - rf), 0);
+      box[k][1] = std::max(tile_of(vv - rf), 0);
+      box[k][2] = std::min(tile_of(u + rf), pb.TX - 1);
+      box[k][3] = std::min(tile_of(vv + rf), pb.TY - 1);
     }
     const int big = alt > 0 ? 1 : 0;  // the larger of the two rectangles
     const int* o = box[big];
@@ -866,6 +868,15 @@ int or_num_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+
+// Threads of the following parallel regions (the calling thread's setting).
+void or_set_num_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+#else
+  (void)t;
 #endif
 }
 

@@ -14,7 +14,9 @@ with the smallest (word, p) are taken and listed in ascending pixel order.
 
 The residual-weighted sampler (Supp. E, q_residual) draws k pixels per tile
 with replacement from the softmax of the pixels' residual magnitudes inside
-the tile; see ``sample_residual``.
+the tile; see ``sample_residual``. The contribution-weighted sampler (Supp. E,
+q_Gaussian) draws them in proportion to the number of Gaussians blended into
+each pixel; see ``sample_gaussian``.
 """
 from __future__ import annotations
 
@@ -65,11 +67,10 @@ def sample_uniform(seed: int, it: int, cam_ids, n_tiles: int, k: int):
     return chosen.astype(np.uint8), w
 
 
-def draw_uniforms(seed: int, it: int, cam_ids, n_tiles: int, k: int) -> np.ndarray:
-    """float64 [V, T, k] in [0, 1): draw j of tile t in camera c at LM iteration
+def draw_words(seed: int, it: int, cam_ids, n_tiles: int, k: int) -> np.ndarray:
+    """int64 [V, T, k] in [0, 2^24): draw j of tile t in camera c at LM iteration
     it is the first Philox4x32-10 word of counter (256 + j, t, c, it) (counters
-    0..255 belong to the uniform sampler's pixel keys), cut to its top 24 bits
-    and scaled by 2^-24, so the value is exact in FP32 as well."""
+    0..255 belong to the uniform sampler's pixel keys), cut to its top 24 bits."""
     cam_ids = np.asarray(cam_ids, dtype=np.uint32)
     V = cam_ids.size
     ctr = np.zeros((V, n_tiles, k, 4), dtype=np.uint32)
@@ -78,7 +79,13 @@ def draw_uniforms(seed: int, it: int, cam_ids, n_tiles: int, k: int) -> np.ndarr
     ctr[..., 2] = cam_ids[:, None, None]
     ctr[..., 3] = np.uint32(it)
     word = philox4x32_10(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))[..., 0]
-    return (word >> np.uint32(8)).astype(np.float64) * 2.0 ** -24
+    return (word >> np.uint32(8)).astype(np.int64)
+
+
+def draw_uniforms(seed: int, it: int, cam_ids, n_tiles: int, k: int) -> np.ndarray:
+    """float64 [V, T, k] in [0, 1): the draw words scaled by 2^-24 (exact in
+    FP32 as well)."""
+    return draw_words(seed, it, cam_ids, n_tiles, k).astype(np.float64) * 2.0 ** -24
 
 
 def sample_residual(seed: int, it: int, cam_ids, n_tiles: int, k: int, scores: np.ndarray):
@@ -110,3 +117,33 @@ def sample_residual(seed: int, it: int, cam_ids, n_tiles: int, k: int, scores: n
     lo = hi - qp
     margin = np.minimum(u - lo, hi - u)
     return pix.astype(np.uint8), 1.0 / (k * qp), margin
+
+
+def sample_gaussian(seed: int, it: int, cam_ids, n_tiles: int, k: int, counts: np.ndarray):
+    """Contribution-weighted stratified sampling (Supp. E, q_Gaussian, eq. 17),
+    restricted to each 16x16 tile (Sec. 4.4): inside a tile pixel p has
+    probability q(p) = G_p / sum_q G_q, with G_p the number of Gaussians
+    blended into pixel p (counts, [V, T, 256]). A tile where no pixel has a
+    contribution is sampled uniformly (G_p taken as 1). k independent draws per
+    tile, with replacement, each weighted 1 / (k q(p)) = Z / (k G_p), Z = sum G.
+
+    Draw j takes the smallest p with Q_p > u_j Z, Q_p = G_0 + ... + G_p and
+    u_j = d_j 2^-24 with d_j the draw's 24-bit word: in integers,
+    Q_p 2^24 > d_j Z, so the draws are exact. A pixel with G_p = 0 (in a tile
+    with contributions) is never drawn; its Jacobian row is zero, so it adds
+    nothing to J^T W r or J^T W J either.
+    Returns (pix uint8 [V, T, k] in draw order, w float64 [V, T, k])."""
+    G = np.rint(np.asarray(counts, dtype=np.float64)).astype(np.int64)
+    assert np.all(G >= 0)
+    empty = G.sum(axis=-1, keepdims=True) == 0
+    G = np.where(empty, 1, G)
+    Q = np.cumsum(G, axis=-1)
+    Z = Q[..., -1:]
+    d = draw_words(seed, it, cam_ids, n_tiles, k)
+    pix = np.empty(d.shape, dtype=np.int64)
+    for v in range(d.shape[0]):
+        # smallest p with Q_p 2^24 > d Z = the number of p with Q_p 2^24 <= d Z
+        pix[v] = ((Q[v][:, None, :] << 24) <= (d[v] * Z[v])[:, :, None]).sum(axis=-1)
+    assert np.all(pix < 256)
+    gp = np.take_along_axis(G, pix, axis=-1)
+    return pix.astype(np.uint8), Z.astype(np.float64) / (k * gp)

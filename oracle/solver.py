@@ -13,14 +13,16 @@ products. Readings of the paper that this code fixes:
   coefficients of the solution (so the largest colour change is at most 1);
 * residual-weighted sampling (Supp. E, q_residual): the distribution comes
   from a render of every pixel of the batch views at the current parameters,
-  with |r_p| = |r_p,R| + |r_p,G| + |r_p,B|; see ``residual_scores``.
+  with |r_p| = |r_p,R| + |r_p,G| + |r_p,B|; see ``residual_scores``;
+* contribution-weighted sampling (Supp. E, q_Gaussian): the counts G_p come
+  from the same full render; see ``contributor_counts``.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import Oracle
-from .sampling import sample_residual, sample_uniform
+from .sampling import sample_gaussian, sample_residual, sample_uniform
 
 
 def pcg(apply_A, b: np.ndarray, m_inv: np.ndarray, iters: int):
@@ -77,12 +79,22 @@ def residual_scores(orc: Oracle, targets: np.ndarray) -> np.ndarray:
     return np.abs(res).sum(axis=1).reshape(orc.V, orc.T, 256)
 
 
+def contributor_counts(orc: Oracle) -> np.ndarray:
+    """G_p = the number of Gaussians blended into pixel p (Supp. E, q_Gaussian:
+    skipped transparent ones and those behind the transmittance stop are not
+    counted) at every pixel of the oracle's views, as [V, T, 256] in tile-major
+    pixel order. Leaves the oracle sampling every pixel."""
+    orc.set_samples(256)
+    return orc.render()["n_contrib"].reshape(orc.V, orc.T, 256).astype(np.float64)
+
+
 def lm_step(n, sh_degree, beta, cams_all, targets_all, view_ids, width, height, k, seed, it, lam,
             cg_iters, d=None, opts=None, sampler="uniform"):
     """Alg. 1 for one LM iteration. Returns (beta_next float32, info dict).
 
-    sampler: "uniform" (Sec. 4.4; k = 256 takes every pixel) or "residual"
-    (Supp. E q_residual, k draws per tile with replacement)."""
+    sampler: "uniform" (Sec. 4.4; k = 256 takes every pixel), "residual"
+    (Supp. E q_residual) or "gaussian" (Supp. E q_Gaussian), the last two with
+    k draws per tile with replacement."""
     view_ids = np.asarray(view_ids, dtype=np.int64)
     cams = cams_all[view_ids]                                   # getBatch (view sampling)
     orc = Oracle(n, sh_degree, beta, cams, width, height, opts)  # splatting: project + bin
@@ -90,6 +102,9 @@ def lm_step(n, sh_degree, beta, cams_all, targets_all, view_ids, width, height, 
     if sampler == "residual":
         scores = residual_scores(orc, targets_all[view_ids])
         pix, w, margin = sample_residual(seed, it, view_ids, orc.T, k, scores)
+        orc.set_samples(k, pix, w)
+    elif sampler == "gaussian":
+        pix, w = sample_gaussian(seed, it, view_ids, orc.T, k, contributor_counts(orc))
         orc.set_samples(k, pix, w)
     elif k >= 256:
         orc.set_samples(256)

@@ -10,8 +10,11 @@ from scipy.spatial.transform import Rotation
 from scipy.special import sph_harm_y
 
 import oracle
-from oracle import Oracle
+from oracle import DEFAULT_OPTS, Oracle
 from paper_2504_12905_amd import synth
+
+LOWPASS = DEFAULT_OPTS["lowpass"]      # the FP32 low-pass 0.3 px^2 of the options block
+ALPHA_MIN = DEFAULT_OPTS["alpha_min"]  # the FP32 alpha floor 1/255
 
 
 def one_gaussian_scene(means, log_scales, quats, ologit, rgb, sh_degree=0, sh_rest=None):
@@ -83,7 +86,7 @@ def test_on_axis_isotropic_closed_form():
     o = Oracle(n, 0, beta, axis_camera(f, W, W), W, W)
     pr = o.projection()
     rec = pr["rec"][0, 0]
-    s2 = (f * sigma / 3.0) ** 2 + 0.3
+    s2 = (f * sigma / 3.0) ** 2 + LOWPASS
     np.testing.assert_allclose(rec[:2], [W / 2, W / 2], atol=1e-12)
     np.testing.assert_allclose(rec[2:5], [1 / s2, 0.0, 1 / s2], rtol=1e-12, atol=1e-15)
     assert rec[5] == pytest.approx(0.5)                      # sigmoid(0)
@@ -119,7 +122,7 @@ def test_projection_matches_independent_ewa():
 
             h = 1e-6
             Jp = np.stack([(pi(t + h * e) - pi(t - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
-            S2 = Jp @ Rw @ Sig @ Rw.T @ Jp.T + 0.3 * np.eye(2)
+            S2 = Jp @ Rw @ Sig @ Rw.T @ Jp.T + LOWPASS * np.eye(2)
             Q = np.linalg.inv(S2)
             rec = pr["rec"][v, g]
             np.testing.assert_allclose(rec[:2], pi(t), rtol=1e-12)

@@ -4,9 +4,13 @@ import math
 import numpy as np
 import pytest
 
-from oracle import Oracle
+from oracle import DEFAULT_OPTS, Oracle
 from paper_2504_12905_amd import synth
+
 from test_oracle_geometry import axis_camera, one_gaussian_scene
+
+LOWPASS = DEFAULT_OPTS["lowpass"]      # the FP32 low-pass 0.3 px^2 of the options block
+ALPHA_MIN = DEFAULT_OPTS["alpha_min"]  # the FP32 alpha floor 1/255
 
 
 def test_single_gaussian_closed_form():
@@ -16,13 +20,13 @@ def test_single_gaussian_closed_form():
     n, beta = one_gaussian_scene([0, 0, 0], [math.log(sigma)] * 3, [1, 0, 0, 0], o_logit, rgb)
     orc = Oracle(n, 0, beta, axis_camera(f, W, W), W, W)
     img = orc.render_image()[0]
-    s2 = (f * sigma / 3.0) ** 2 + 0.3
+    s2 = (f * sigma / 3.0) ** 2 + LOWPASS
     r = math.ceil(3 * math.sqrt(s2))
     op = 1 / (1 + math.exp(-o_logit))
     ys, xs = np.mgrid[0:W, 0:W]
     d2 = (xs + 0.5 - W / 2) ** 2 + (ys + 0.5 - W / 2) ** 2
     a = np.minimum(op * np.exp(-0.5 * d2 / s2), 0.99)
-    a[a < 1 / 255] = 0.0
+    a[a < ALPHA_MIN] = 0.0
     # tiles outside the 3-sigma rectangle are not rendered
     tx0, tx1 = math.floor((W / 2 - r) / 16), math.floor((W / 2 + r) / 16)
     in_rect = ((xs // 16 >= tx0) & (xs // 16 <= tx1) & (ys // 16 >= tx0) & (ys // 16 <= tx1))
@@ -48,7 +52,7 @@ def test_two_gaussians_over_operator():
         dx, dy = rec[0] - x, rec[1] - y
         s = -0.5 * (rec[2] * dx * dx + rec[4] * dy * dy) - rec[3] * dx * dy
         a = min(0.99, rec[5] * math.exp(s))
-        return 0.0 if a < 1 / 255 else a
+        return 0.0 if a < ALPHA_MIN else a
 
     for (x, y) in [(15, 15), (16, 17), (13, 18), (18, 12)]:
         a1, a2 = alpha(pr[0], x + 0.5, y + 0.5), alpha(pr[1], x + 0.5, y + 0.5)
@@ -83,7 +87,7 @@ def brute_force_pixel(rec, order, x, y):
         if s > 0:
             continue
         a = min(0.99, r[5] * math.exp(s))
-        if a < 1 / 255:
+        if a < ALPHA_MIN:
             continue
         if T * (1 - a) < 1e-4:
             break
@@ -127,7 +131,7 @@ def test_decision_margin_flags_threshold_pixels():
     decided at tau = 1e-4; with alpha 0.006 it is."""
     f, W = 40.0, 32
     sigma = 0.1
-    s2 = (f * sigma / 3.0) ** 2 + 0.3
+    s2 = (f * sigma / 3.0) ** 2 + LOWPASS
     x, y = 20, 16                        # pixel centre (20.5, 16.5), Gaussian at (16, 16)
     d2 = (x + 0.5 - W / 2) ** 2 + (y + 0.5 - W / 2) ** 2
     g = math.exp(-0.5 * d2 / s2)
@@ -144,21 +148,24 @@ def test_decision_margin_flags_threshold_pixels():
 
 def test_undecided_tiles_cover_a_radius_at_an_integer():
     """On the optical axis at depth 3, 3 sqrt((f sigma / 3)^2 + 0.3) is the
-    footprint extent. At 16 + 1e-6 px the radius ceil() = 17 is not decided in
-    FP32, which may give 16: around the centre (32, 32) of a 64x64 image the
+    footprint extent. At 16 + 1e-6 px the radius ceil() = 17 is not decided to
+    within tau = 1e-4 px, an evaluation that loose may give 16: around the
+    centre (32, 32) of a 64x64 image the
     radius-17 rectangle holds tiles 0..3 (32 - 17 = 15 lies in tile 0), the
     radius-16 one tiles 1..3 (the right edge 48 starts tile 3), so the flagged
-    ring is every tile with tx == 0 or ty == 0; their pixels leave decided().
-    At 16 - 1e-6 px the radius 16 may become 17 in FP32: the same ring. At
-    16.5 px nothing is flagged."""
+    ring is every tile with tx == 0 or ty == 0; their pixels leave
+    decided(tau_list=1e-4). At 16 - 1e-6 px the radius 16 may become 17: the
+    same ring. At 16.5 px nothing is flagged, and at the default tau_list
+    (two FP64 evaluations) the 1e-6 px cases are decided."""
     f, W = 40.0, 64
     ring = {(ty, tx) for ty in range(4) for tx in range(4) if tx == 0 or ty == 0}
     for ext, expect in [(16.0 + 1e-6, ring), (16.0 - 1e-6, ring), (16.5, set())]:
-        sigma = 3.0 * math.sqrt((ext / 3.0) ** 2 - 0.3) / f
+        sigma = 3.0 * math.sqrt((ext / 3.0) ** 2 - LOWPASS) / f
         n, beta = one_gaussian_scene([0, 0, 0], [math.log(sigma)] * 3, [1, 0, 0, 0], 0.5, [0.5, 0.5, 0.5])
         orc = Oracle(n, 0, beta, axis_camera(f, W, W), W, W)
         flags = orc.undecided_tiles(1e-4).reshape(W // 16, W // 16)
         assert {(int(ty), int(tx)) for ty, tx in zip(*np.nonzero(flags))} == expect
         orc.set_samples(256)
-        ok = orc.decided().reshape(-1, 256)
+        ok = orc.decided(tau_list=1e-4).reshape(-1, 256)
         assert np.array_equal(~ok.all(axis=1), flags.reshape(-1).astype(bool)) or not expect
+        assert not orc.undecided_tiles().any()
