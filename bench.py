@@ -30,28 +30,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GN products (J^T J p)/sec at 100k Gaussians vs plain; served fits/sec + p99"
+# Published MI355X peaks: HBM3E 8 TB/s; FP32 vector 157.3 TFLOP/s.
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA)
-# x 2.4 GHz. The library is built with packed FP32 arithmetic switched off
-# (-packed-fp32-ops), which the published 157.3 TFLOP/s assumes.
-FP32_VECTOR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-FP32_PACKED_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3
+# For reference only: the FP32 vector rate without packed FP32 instructions
+# (256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz); the library is built
+# with packed FP32 arithmetic switched off.
+FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 SPLAT_SOURCE = os.path.join(ROOT, "paper_2504_12905_amd", "csrc", "kernels_splat.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gn_splat_traffic_cfg1.txt")
 
-# Algorithmic bytes of the fused splat kernel (one GN product):
-#   per traversed (tile, list entry): list id 4 B + screen record 36 B + its
-#   tangent 36 B read, screen gradient 36 B written;
-#   per sampled pixel: pixel index 1 B, weight 4 B, final transmittance 4 B,
-#   last blended position 4 B.
-BYTES_PER_ENTRY = 4 + 36 + 36 + 36
-BYTES_PER_PIXEL = 1 + 4 + 4 + 4
-# Algorithmic FP32 operations per (sampled pixel, list entry) pair walked:
-# forward: opacity test 14 (offsets 2, quadratic form 7, exp 1, scale 1,
-# compares 3), exponent tangent 17, alpha tangent 3, transmittance and its
-# tangent 5, colour tangent 12; reverse: opacity test 14, transmittance 2,
-# blended-behind term 6, alpha adjoint 4, screen-gradient accumulation 24.
-FLOPS_PER_PAIR = 14 + 17 + 3 + 5 + 12 + 14 + 2 + 6 + 4 + 24
+# Algorithmic work of one GN product, per unit the method must touch:
+#   per traversed list entry (the prefix L*_t of each tile's list up to the
+#   deepest last blended entry of its sampled pixels): id 4 B + screen record
+#   36 B + its tangent 36 B read = 76 B;
+#   per contributing entry (blended by at least one sampled pixel of the
+#   tile): 36 B of screen-gradient partials written;
+#   per sampled pixel: pixel index, weight, final transmittance, last = 16 B;
+#   per blending (pixel, entry) pair: 100 FP32 operations (primal recompute,
+#   tangent, reverse), per walked pair that does not blend: 10 (the opacity
+#   test);
+#   around the splat: p, the parameters and the output once each (4 P x 3 B),
+#   and per visible (view, Gaussian) the tangent record and the screen
+#   gradient written and read (4 x 36 B) and ~600 FP32 operations of the
+#   tangent and reverse projection.
+B_ENTRY, B_CONTRIB, B_PIXEL = 76, 36, 16
+F_ACT, F_SKIP = 100, 10
+B_VIS, F_VIS = 4 * 36, 600
 
 
 def log(*a):
@@ -101,18 +106,50 @@ def traffic_from_profile(kernel_hash: str, default_workload: bool):
         return None
 
 
-def cpu_baseline(w, beta, cams_np, view_ids, pix, wts, lam, p, budget_s=20.0, n_views=None):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _one_core_seconds(w, beta, cams_np, views, pix, wts, lam, pd, threads_after):
+    """Median of 3 oracle GN products on one thread over `views` (after a first call)."""
+    from oracle import Oracle, set_num_threads
+    set_num_threads(1)
+    try:
+        nv = len(views)
+        o1 = Oracle(w.n, w.sh_degree, beta, cams_np[views], w.width, w.height)
+        o1.set_samples(pix.shape[-1], pix[:nv], wts[:nv])
+        o1.gn(pd, lam)
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            o1.gn(pd, lam)
+            times.append(time.perf_counter() - t0)
+        return times
+    finally:
+        set_num_threads(threads_after)
+
+
+def cpu_baseline(w, beta, cams_np, view_ids, pix, wts, lam, p, budget_s=20.0, n_views=None, one_core_views=1):
     """FP64 oracle GN products/s on the same product the GPU timed: the batch
     views (or the first n_views of them, the time then scaled to the whole
     batch), the same samples, parameters and direction p. The first call also
     builds the record Jacobians the later calls reuse (reported apart); then
-    products are repeated until about `budget_s` seconds of CPU work."""
+    products are repeated until about `budget_s` seconds of CPU work. Then the
+    same on one thread, restricted to the first `one_core_views` views (time
+    scaled to the batch), median of 3 after the first call."""
     from oracle import Oracle, num_threads
     V = len(view_ids)
     nv = V if n_views is None else n_views
     orc = Oracle(w.n, w.sh_degree, beta, cams_np[view_ids[:nv]], w.width, w.height)
     orc.set_samples(pix.shape[-1], pix[:nv], wts[:nv])
     pd = p.astype(np.float64)
+    threads = num_threads()
     t0 = time.perf_counter()
     ref = orc.gn(pd, lam)
     first = time.perf_counter() - t0
@@ -122,13 +159,24 @@ def cpu_baseline(w, beta, cams_np, view_ids, pix, wts, lam, p, budget_s=20.0, n_
         orc.gn(pd, lam)
         times.append(time.perf_counter() - t0)
     t1 = float(np.median(times)) * V / nv
+    del orc
+    t_one = _one_core_seconds(w, beta, cams_np, view_ids[:one_core_views], pix, wts, lam, pd, threads) \
+        if one_core_views else None
     part = (f"the full GN product of one LM step ({V} views" if nv == V else
             f"the GN product restricted to {nv} of the {V} batch views, time scaled by {V}/{nv} ({nv} views")
-    return {"value": round(1.0 / t1, 4), "unit": "GN products/s", "cores": num_threads(), "kind": "oracle",
+    return {"value": round(1.0 / t1, 4), "unit": "GN products/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{part}, {pix.shape[-1]} samples/tile, same parameters and p as the GPU's timed "
                       f"product); median of {len(times)} products after a first call of {first:.1f} s that "
                       f"also builds the record Jacobians",
-            "seconds_per_product": round(t1, 4)}, (ref if nv == V else None)
+            "seconds_per_product": round(t1, 4),
+            "one_core": None if t_one is None else {
+                "value": round(1.0 / (float(np.median(t_one)) * V / one_core_views), 5), "unit": "GN products/s",
+                "cores": 1,
+                "sample": f"the product restricted to {one_core_views} of the {V} batch views on one thread, "
+                          f"median of 3 after a first call, time scaled by {V}/{one_core_views}",
+                "seconds_per_product": round(float(np.median(t_one)) * V / one_core_views, 3)}}, \
+        (ref if nv == V else None)
 
 
 def copy_calibration(torch, dev, mib=1024, reps=3):
@@ -235,14 +283,16 @@ def lm_breakdown(L, torch, fr, targets, w, sampler, it, gn_ms):
     return out
 
 
-def serving_main(args):
-    """Served fits/s and p50/p99 latency on a Poisson stream of fit requests,
-    against the plain sequential solver on the same GPU."""
+def serving_leg(args, n_requests: int | None = None) -> dict:
+    """Served fits/s and p50/p99 latency on the first requests of the seeded
+    Poisson stream of fit requests (256 requests at 20 req/s), against the
+    plain sequential solver on the same requests and GPU."""
     import torch
 
     from paper_2504_12905_amd import serving, synth
 
-    stream = synth.request_stream(args.requests, args.rate, seed=0)
+    count = n_requests or args.requests
+    stream = synth.request_stream(256, args.rate, seed=0)[:count]
     reqs = [serving.FitRequest.from_stream(d) for d in stream]
     if args.lm_iters:
         for r in reqs:
@@ -267,24 +317,35 @@ def serving_main(args):
     dpsnr = max(abs(got[i].final_psnr - seq[i].final_psnr) for i in got)
     dbeta = max(float(np.linalg.norm(got[i].beta - seq[i].beta) / np.linalg.norm(seq[i].beta)) for i in got)
     torch.cuda.synchronize()
-    res = {
-        "metric": "served fits/s (continuous batching) vs sequential plain solves", "value": round(s_srv["fits_per_s"], 4),
-        "unit": "fits/s", "n_gpus": 1, "steps": len(reqs), "warmup": 0,
-        "ms_per_step": round(1e3 / s_srv["fits_per_s"], 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"fit-request stream: {len(reqs)} requests, Poisson {args.rate} req/s",
-                   "lm_iters": reqs[0].lm_iters, "cg_iters": reqs[0].cg_iters, "slots": args.slots,
-                   "hbm_budget_gib": args.hbm_budget_gb, "graphs": not args.no_graphs},
-        "served": s_srv, "sequential": s_seq,
+    return {
+        "workload": f"fit-request stream: the first {len(reqs)} of 256 requests (Poisson {args.rate} req/s; "
+                    f"Gaussians log-uniform 2k-200k, SH 0-3, 4-32 views of 256/512/800 px, every pixel)",
+        "requests": len(reqs), "lm_iters": reqs[0].lm_iters, "cg_iters": reqs[0].cg_iters, "lambda": reqs[0].lam,
+        "slots": args.slots, "hbm_budget_gib": args.hbm_budget_gb, "graphs": not args.no_graphs,
+        "fits_per_s": round(s_srv["fits_per_s"], 4), "p50_latency_s": round(s_srv["p50_latency_s"], 3),
+        "p99_latency_s": round(s_srv["p99_latency_s"], 3),
+        "sequential": {k: round(v, 4) if isinstance(v, float) else v for k, v in s_seq.items()},
+        "served": {k: round(v, 4) if isinstance(v, float) else v for k, v in s_srv.items()},
         "speedup_fits_per_s": round(s_srv["fits_per_s"] / s_seq["fits_per_s"], 3),
-        "max_final_psnr_diff_db": dpsnr, "max_beta_rel_diff": dbeta,
-        "requests": [{"id": r.id, "n": r.n, "sh": r.sh_degree, "views": r.n_views, "res": r.res,
-                      "arrival_s": round(r.arrival_t, 3),
-                      "seq_start_s": round(seq[r.id].start_s, 3), "seq_end_s": round(seq[r.id].end_s, 3),
-                      "srv_start_s": round(got[r.id].start_s, 3), "srv_end_s": round(got[r.id].end_s, 3),
-                      "psnr_seq": round(seq[r.id].final_psnr, 3), "psnr_srv": round(got[r.id].final_psnr, 3)}
-                     for r in reqs],
+        "max_final_psnr_diff_db": round(dpsnr, 5), "max_beta_rel_diff": dbeta,
+        "statuses": sorted({r.status for r in got.values()}),
+        "per_request": [{"id": r.id, "n": r.n, "sh": r.sh_degree, "views": r.n_views, "res": r.res,
+                         "arrival_s": round(r.arrival_t, 3),
+                         "seq_s": round(seq[r.id].end_s - seq[r.id].start_s, 3),
+                         "srv_start_s": round(got[r.id].start_s, 3), "srv_end_s": round(got[r.id].end_s, 3),
+                         "psnr_seq": round(seq[r.id].final_psnr, 3), "psnr_srv": round(got[r.id].final_psnr, 3)}
+                        for r in reqs],
     }
+
+
+def serving_main(args):
+    """--serving: the serving leg alone, as its own JSON line."""
+    leg = serving_leg(args)
+    res = {"metric": "served fits/s (continuous batching) vs sequential plain solves", "value": leg["fits_per_s"],
+           "unit": "fits/s", "n_gpus": 1, "steps": leg["requests"], "warmup": 0,
+           "ms_per_step": round(1e3 / leg["fits_per_s"], 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": leg["workload"]}, "serving": leg}
     print(json.dumps(res), flush=True)
 
 
@@ -316,57 +377,21 @@ def summarize_counters(dirs: list[str], command: str) -> str:
     return text
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--gn-reps", type=int, default=50)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--n", type=int, default=None, help="Gaussians (default: the workload's)")
-    ap.add_argument("--workload", choices=["cfg1", "cfg2"], default="cfg1",
-                    help="cfg1: 100k-Gaussian object-scale fit (default); cfg2: 1.5M-Gaussian "
-                         "unbounded-scene fit with residual-weighted sampling")
-    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="run MIB-MiB device copies before the GN timing (HBM-counter calibration)")
-    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write the splat traffic summary from two rocprofv3 --pmc output folders and exit")
-    ap.add_argument("--traffic-command", default="", help="command line recorded in the traffic summary")
-    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
-                    help="write the splat counter summary from rocprofv3 --pmc output folders and exit")
-    ap.add_argument("--serving", action="store_true", help="serving benchmark (fit-request stream)")
-    ap.add_argument("--requests", type=int, default=32)
-    ap.add_argument("--rate", type=float, default=20.0)
-    ap.add_argument("--slots", type=int, default=8)
-    ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
-    ap.add_argument("--lm-iters", type=int, default=0, help="override the requests' LM iterations")
-    ap.add_argument("--no-graphs", action="store_true")
-    args = ap.parse_args()
-    if args.serving:
-        return serving_main(args)
-    if args.summarize_counters:
-        print(summarize_counters(args.summarize_counters, args.traffic_command))
-        return
-    if args.summarize_traffic:
-        print(summarize_traffic(*args.summarize_traffic, args.calibrate_copy or 1024, args.traffic_command))
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
-              "(view sharding, one all-reduce per GN product) is described in DESIGN.md", file=sys.stderr)
-        sys.exit(2)
-
+def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n: int | None = None) -> dict:
+    """LM steps of one workload through the C ABI, timed; then the GN product
+    alone, its roofline position, the LM-step stage breakdown and (with_cpu)
+    the oracle baseline. Returns the JSON record."""
     import torch
 
     from paper_2504_12905_amd import lmrs as L
     from paper_2504_12905_amd import synth
 
     dev = "cuda:0"
-    if args.workload == "cfg1":
-        w = synth.config1(**({} if args.n is None else {"n": args.n}))
+    if workload == "cfg1":
+        w = synth.config1(**({} if n is None else {"n": n}))
         sampler = L.SAMPLER_UNIFORM
     else:
-        w = synth.config2(**({} if args.n is None else {"n": args.n}))
+        w = synth.config2(**({} if n is None else {"n": n}))
         sampler = L.SAMPLER_RESIDUAL
     cams = torch.tensor(w.cams, device=dev)
     beta_gt = torch.tensor(w.beta_gt, device=dev)
@@ -382,7 +407,7 @@ def main():
     ws = None
     # the views of every LM step, drawn up front and kept on the device
     all_vids = torch.tensor(np.stack([rng.choice(w.cams.shape[0], V, replace=False)
-                                      for _ in range(args.warmup + args.steps)]).astype(np.int32), device=dev)
+                                      for _ in range(warmup + steps)]).astype(np.int32), device=dev)
 
     def step(it):
         view_ids.copy_(all_vids[it])
@@ -390,27 +415,27 @@ def main():
         L.lmrs_lm_step(fr, targets, L.lm_params(it, w.cg_iters, w.lam, seed=w.seed, sampler=sampler), report=rep,
                        ws=ws)
 
-    log(f"[bench] warmup {args.warmup} LM steps")
+    log(f"[bench] warmup {warmup} LM steps")
     it = 0
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(it)
         it += 1
     torch.cuda.synchronize()
     # grow the workspace once for the largest instance count seen, outside the timed region
     ws = torch.empty(int(L._lib.lmrs_workspace_bytes(L.OP_LM, L.C.byref(fr.struct())) * 1.1) + 4096,
                      dtype=torch.uint8, device=dev)
-    log(f"[bench] timing {args.steps} LM steps")
+    log(f"[bench] timing {steps} LM steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(it)
         it += 1
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    products = w.cg_iters * args.steps
+    products = w.cg_iters * steps
     value = products / el
     r = rep.cpu().numpy()
-    log(f"[bench] {el / args.steps * 1e3:.2f} ms/LM step, {value:.1f} GN products/s; last step: loss "
+    log(f"[bench] {el / steps * 1e3:.2f} ms/LM step, {value:.1f} GN products/s; last step: loss "
         f"{r[0]:.4e} eta {r[1]:.3f} instances {r[7]:.0f}")
 
     # --- the GN product on its own, at the current parameters and the last step's samples
@@ -456,45 +481,55 @@ def main():
     # the state of the timed product, for the oracle (the stage breakdown below re-samples)
     beta_h, pix_h, w_h, vids_h = (fr.beta.cpu().numpy(), fr.pix.cpu().numpy(), fr.w.cpu().numpy(),
                                   view_ids.cpu().numpy())
-    last = fr.last.view(V * fr.T, k).to(torch.int64)
-    entries = int((last.max(dim=1).values + 1).clamp(min=0).sum().item())
-    pairs = int((last + 1).clamp(min=0).sum().item())
+    cnt = L.lmrs_walk_counts(fr).cpu().numpy().astype(np.int64)
+    entries, contrib, n_act, n_walk = (int(x) for x in cnt)
+    n_vis = int((fr.rect[..., 0] < fr.rect[..., 2]).sum().item())
 
     breakdown = lm_breakdown(L, torch, fr, targets, w, sampler, it, gn_ms)
     log("[bench] LM-step stages (ms, each run alone): " + ", ".join(f"{k} {v:.2f}" for k, v in breakdown.items()))
 
     # --- algorithmic work of the fused splat kernel in the timed launches
     S = fr.S
-    b_alg = entries * BYTES_PER_ENTRY + S * BYTES_PER_PIXEL
-    f_alg = pairs * FLOPS_PER_PAIR
+    b_alg = entries * B_ENTRY + contrib * B_CONTRIB + S * B_PIXEL
+    f_alg = n_act * F_ACT + (n_walk - n_act) * F_SKIP
     t_splat = phase_ms[2] * 1e-3
     gbs = b_alg / t_splat / 1e9
     tflops = f_alg / t_splat / 1e12
-    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tflops / FP32_VECTOR_PEAK_TFLOPS
+    t_hbm, t_alu = b_alg / (HBM_PEAK_GBS * 1e9), f_alg / (FP32_PEAK_TFLOPS * 1e12)
+    bound_alu = t_alu > t_hbm
     kernel_hash = hashlib.sha256(open(SPLAT_SOURCE, "rb").read()).hexdigest()
-    traffic = traffic_from_profile(kernel_hash, args.workload == "cfg1" and args.n is None)
-    bound_alu = alu_frac > hbm_frac
+    traffic = traffic_from_profile(kernel_hash, workload == "cfg1" and n is None)
+    # the whole GN product (tangent projection, splat, reverse chain)
+    b_gn = 4 * fr.P * 3 + n_vis * B_VIS + b_alg
+    f_gn = f_alg + n_vis * F_VIS
+    t_gn = gn_ms * 1e-3
     roofline = {
         "kernel": "deriv_kernel<3> (fused J p / weight / J^T u splat of lmrs_gn_product)",
         "bound": "alu" if bound_alu else "hbm",
         "achieved": round(tflops if bound_alu else gbs, 4),
-        "peak": FP32_VECTOR_PEAK_TFLOPS if bound_alu else HBM_PEAK_GBS,
+        "peak": FP32_PEAK_TFLOPS if bound_alu else HBM_PEAK_GBS,
         "unit": "TFLOP/s" if bound_alu else "GB/s",
-        "frac": round(alu_frac if bound_alu else hbm_frac, 6),
+        "frac": round((t_alu if bound_alu else t_hbm) / t_splat, 6),
         "traffic": traffic,
-        "hbm_gbs": round(gbs, 3), "hbm_frac": round(hbm_frac, 6),
-        "alu_tflops": round(tflops, 4), "alu_frac": round(alu_frac, 6),
-        "alu_frac_of_packed_peak": round(tflops / FP32_PACKED_PEAK_TFLOPS, 6),
+        "hbm_gbs": round(gbs, 3), "hbm_frac": round(gbs / HBM_PEAK_GBS, 6),
+        "alu_tflops": round(tflops, 4), "alu_frac": round(tflops / FP32_PEAK_TFLOPS, 6),
+        "alu_frac_of_unpacked_fp32_rate_note": round(tflops / FP32_UNPACKED_TFLOPS, 6),
+        "t_hbm_bound_ms": round(t_hbm * 1e3, 5), "t_alu_bound_ms": round(t_alu * 1e3, 5),
         "algorithmic_bytes": b_alg, "algorithmic_flops": f_alg,
-        "traversed_entries": entries, "pixel_entry_pairs": pairs, "sampled_pixels": S,
+        "traversed_entries": entries, "contributing_entries": contrib, "blending_pairs": n_act,
+        "walked_pairs": n_walk, "sampled_pixels": S, "visible_view_gaussians": n_vis,
         "ms_per_launch": round(float(phase_ms[2]), 4),
+        "gn_product": {"algorithmic_bytes": b_gn, "algorithmic_flops": f_gn, "ms": round(gn_ms, 4),
+                       "hbm_gbs": round(b_gn / t_gn / 1e9, 3), "hbm_frac": round(b_gn / t_gn / 1e9 / HBM_PEAK_GBS, 6),
+                       "alu_frac": round(f_gn / t_gn / 1e12 / FP32_PEAK_TFLOPS, 6)},
     }
 
     cpu, parity = None, None
-    if not args.no_cpu:
+    if with_cpu:
         log("[bench] CPU oracle baseline (the same GN product in FP64)")
         cpu, ref = cpu_baseline(w, beta_h, w.cams, vids_h, pix_h, w_h, w.lam, p.cpu().numpy(), args.cpu_budget,
-                                n_views=None if args.workload == "cfg1" else 2)
+                                n_views=None if workload == "cfg1" else 2,
+                                one_core_views=1 if workload == "cfg1" else None)
         if ref is not None:
             parity = float(np.linalg.norm(out_gpu - ref) / np.linalg.norm(ref))
         log(f"[bench] oracle {cpu['value']:.4f} GN products/s on {cpu['cores']} threads; "
@@ -502,7 +537,7 @@ def main():
 
     res = {
         "metric": METRIC, "value": round(value, 3), "unit": "GN products/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 3),
+        "steps": steps, "warmup": warmup, "ms_per_step": round(el / steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "gaussians": w.n, "sh_degree": w.sh_degree,
@@ -518,7 +553,63 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(res), flush=True)
+    del fr, targets, ws
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--gn-reps", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--n", type=int, default=None, help="Gaussians (default: the workload's)")
+    ap.add_argument("--workload", choices=["cfg1", "cfg2"], default="cfg1",
+                    help="cfg1: 100k-Gaussian object-scale fit (default); cfg2: 1.5M-Gaussian "
+                         "unbounded-scene fit with residual-weighted sampling")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run MIB-MiB device copies before the GN timing (HBM-counter calibration)")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the splat traffic summary from two rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--traffic-command", default="", help="command line recorded in the traffic summary")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
+                    help="write the splat counter summary from rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--serving", action="store_true", help="serving benchmark (fit-request stream)")
+    ap.add_argument("--requests", type=int, default=32, help="requests of the serving leg (first of the 256)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the 100k workload (no 1.5M-Gaussian and serving sub-records)")
+    ap.add_argument("--cfg2-steps", type=int, default=5, help="timed LM steps of the 1.5M-Gaussian sub-record")
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
+    ap.add_argument("--lm-iters", type=int, default=0, help="override the requests' LM iterations")
+    ap.add_argument("--no-graphs", action="store_true")
+    args = ap.parse_args()
+    if args.serving:
+        return serving_main(args)
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.traffic_command))
+        return
+    if args.summarize_traffic:
+        print(summarize_traffic(*args.summarize_traffic, args.calibrate_copy or 1024, args.traffic_command))
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
+              "(view sharding, one all-reduce per GN product) is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    primary = run_workload(args, args.workload, args.steps, args.warmup, not args.no_cpu, args.n)
+    if args.workload == "cfg1" and args.n is None and not args.no_extra:
+        # the 1.5M-Gaussian unbounded-scene workload: LM-step time and GN-product bandwidth
+        sub = run_workload(args, "cfg2", args.cfg2_steps, 2, False)
+        primary["cfg2"] = {k: sub[k] for k in ("value", "unit", "ms_per_step", "steps", "warmup", "config",
+                                                "roofline")}
+        # served fits/s and latency against the sequential plain solver
+        primary["serving"] = serving_leg(args)
+    print(json.dumps(primary), flush=True)
 
 
 if __name__ == "__main__":

@@ -64,11 +64,21 @@ typedef int32_t lmrs_status;
 #define LMRS_ECAPACITY (-2)    /* tile-instance buffer too small; count written */
 #define LMRS_EWORKSPACE (-3)   /* workspace smaller than lmrs_workspace_bytes */
 #define LMRS_EHIP (-4)         /* HIP runtime error */
+#define LMRS_ENUMERIC (-5)     /* numeric failure recorded on the device (see
+                                  LMRS_REP_STATUS and lmrs_report_status)    */
+#define LMRS_EUNSUPPORTED (-6) /* well-formed request this library does not
+                                  handle (SH degree above 3, more than 16384
+                                  tiles per view)                            */
 
-/* Floats per screen record: u v f11 f12 f22 opacity r g b | depth radius 0
+/* Floats per screen record: u v f11 f12 f22 opacity r g b | key radius sub
  * (Sec. 3 eq. 3). (f11, f12, f22) is the upper-triangular Cholesky factor F of
  * the conic Q = Sigma_2D^-1 = F^T F, so that the Gaussian's exponent at pixel
- * offset (dx, dy) from (u, v) is -1/2 ((f11 dx + f12 dy)^2 + (f22 dy)^2). */
+ * offset (dx, dy) from (u, v) is -1/2 ((f11 dx + f12 dy)^2 + (f22 dy)^2).
+ * The list decisions are taken in FP64: the camera depth z of the mean, the
+ * projected centre and the footprint radius ceil(cutoff sqrt(lambda_max)) of
+ * the 2-D covariance. key is the FP32 number nearest z; sub (the bits of a
+ * uint32) is the number of FP64 values between key and z plus 2^30, so that
+ * (key, sub) orders like z. */
 #define LMRS_REC 12
 
 typedef struct lmrs_camera {
@@ -149,16 +159,23 @@ typedef struct lmrs_lm_params {
   float eta_warm;       /* fixed learning rate of the first iterations (0.05)  */
   int32_t warm_iters;   /* number of such iterations (10)                       */
   uint64_t seed;        /* residual-sampler seed                                */
-  int32_t sampler;      /* LMRS_SAMPLER_UNIFORM or LMRS_SAMPLER_RESIDUAL        */
+  int32_t sampler;      /* LMRS_SAMPLER_UNIFORM, _RESIDUAL or _GAUSSIAN         */
+  int32_t cg_iters_late;/* GN products from iteration late_iter on (Sec. 5: CG
+                           steps rise to 8 after the 50th iteration); 0 keeps
+                           cg_iters throughout                                  */
+  int32_t late_iter;    /* first iteration of cg_iters_late (50)                */
 } lmrs_lm_params;
 
 /* Pixel samplers (lmrs_sample, lmrs_lm_params.sampler). */
 #define LMRS_SAMPLER_UNIFORM 0   /* Sec. 4.4: k distinct pixels per tile        */
 #define LMRS_SAMPLER_RESIDUAL 1  /* Supp. E q_residual: k draws per tile with
                                     replacement from the softmax of |r|         */
+#define LMRS_SAMPLER_GAUSSIAN 2  /* Supp. E q_Gaussian: k draws per tile with
+                                    replacement in proportion to the number of
+                                    Gaussians blended into each pixel           */
 
 /* Slots of the device report written by lmrs_pcg / lmrs_lm_step. */
-#define LMRS_REPORT_FLOATS 8
+#define LMRS_REPORT_FLOATS 12
 #define LMRS_REP_LOSS 0        /* sampled weighted loss sum_i w_i |r_i|^2        */
 #define LMRS_REP_ETA 1         /* learning rate applied                           */
 #define LMRS_REP_XDC_MAX 2     /* max |x| over the DC colour coefficients         */
@@ -167,9 +184,29 @@ typedef struct lmrs_lm_params {
 #define LMRS_REP_RN 5          /* ||r|| after the last iteration                  */
 #define LMRS_REP_BX 6          /* b^T x (> 0 for a descent step)                  */
 #define LMRS_REP_INST 7        /* tile-list entries of this step                  */
+#define LMRS_REP_STATUS 8      /* LMRS_FAIL_* bits of this step, 0 when none      */
+
+/* Numeric failures, detected on the device (calls enqueue and return, so they
+ * cannot be returned as a status). PCG stops at the first one; lmrs_lm_step /
+ * lmrs_lm_solve then leave beta unchanged. */
+#define LMRS_FAIL_NONFINITE 1  /* NaN or Inf in b, the preconditioner, the PCG
+                                  residual or the solution x                   */
+#define LMRS_FAIL_BREAKDOWN 2  /* p^T A p <= 0 (or NaN) before convergence: not
+                                  possible for the SPD operator of Alg. 1, so
+                                  NaN/Inf in p or A p, or a corrupt input      */
+#define LMRS_FAIL_CAPACITY 4   /* (lmrs_lm_iterate) the tile lists needed more
+                                  entries than capacity: they were left empty
+                                  and the step changed nothing; report[INST]
+                                  holds the count needed                       */
 
 const char* lmrs_status_str(lmrs_status s);
 const char* lmrs_last_error(void);
+
+/* The status a host copy of a report (LMRS_REPORT_FLOATS floats) carries in
+ * LMRS_REP_STATUS: LMRS_ECAPACITY for LMRS_FAIL_CAPACITY, LMRS_ENUMERIC for
+ * the numeric bits, LMRS_OK for none (message in lmrs_last_error). report:
+ * host memory; NULL gives LMRS_EINVAL. */
+lmrs_status lmrs_report_status(const float* report);
 
 /* Scratch bytes that call `op` needs for frame `f` (uses n, sh_degree,
  * n_views, width, height, k and capacity). Pass a buffer of at least this
@@ -226,6 +263,18 @@ lmrs_status lmrs_gn_product_timed(const lmrs_frame* f, const lmrs_render_opts* o
                                   float lambda, const float* d, float* out, void* ws, size_t ws_bytes,
                                   void* stream, float* ms);
 
+/* Measurement helper: what the sampled render's walk touches, for the
+ * algorithmic bytes and flops of the splat kernels. Needs the state of
+ * lmrs_jvp (lists, samples, render outputs). counts: device int64[4],
+ * overwritten:
+ *   [0] sum over tiles of L*_t = max over the tile's sampled pixels of last + 1
+ *       (the list prefix a walk traverses);
+ *   [1] sum over tiles of C_t = list entries blended by at least one of the
+ *       tile's sampled pixels (the entries that receive gradient);
+ *   [2] blending (pixel, entry) pairs (Sec. 3 eq. 3 terms with alpha >= alpha_min);
+ *   [3] (pixel, entry) pairs up to and including each pixel's last blended entry. */
+lmrs_status lmrs_walk_counts(const lmrs_frame* f, const lmrs_render_opts* o, int64_t* counts, void* stream);
+
 /* a5. diag(J^T W J) (Alg. 1 preconditioner; Supp. A "Diag(J^T J) kernel"),
  * exact: per (view, Gaussian) the weighted Gram matrix of the screen-record
  * derivatives, then contracted with the record Jacobian. out: device [P]. */
@@ -235,7 +284,8 @@ lmrs_status lmrs_gn_diag(const lmrs_frame* f, const lmrs_render_opts* o, float* 
 /* a5 + a7. Matrix-free PCG of Alg. 1 from x0 = 0: Jacobi preconditioner
  * 1 / (diag(J^T W J) + lambda d), exactly `iters` GN products; x stops
  * changing if p^T A p <= 0 or r^T z collapses. b, x: device [P].
- * report: device [LMRS_REPORT_FLOATS] or NULL (slots CG_DONE, R0, RN, BX). */
+ * report: device [LMRS_REPORT_FLOATS] or NULL (slots CG_DONE, R0, RN, BX,
+ * STATUS). A numeric failure stops the iteration and sets LMRS_REP_STATUS. */
 lmrs_status lmrs_pcg(const lmrs_frame* f, const lmrs_render_opts* o, const float* b, float lambda,
                      const float* d, int32_t iters, float* x, float* report, void* ws,
                      size_t ws_bytes, void* stream);
@@ -249,6 +299,14 @@ lmrs_status lmrs_pcg(const lmrs_frame* f, const lmrs_render_opts* o, const float
 lmrs_status lmrs_residual_scores(const lmrs_frame* f, const lmrs_render_opts* o, const float* targets,
                                  float* scores, void* stream);
 
+/* Contributor counts for the contribution-weighted sampler (Supp. E, eq. 17):
+ * renders every pixel of the batch views (as lmrs_render with k = 256) and
+ * writes counts[(v * T + t) * 256 + p] = G_p, the number of Gaussians blended
+ * into the pixel (skipped transparent ones and those behind the transmittance
+ * stop not counted), as floats. Needs rec, rect and the tile lists.
+ * counts: device [V][T][256]. */
+lmrs_status lmrs_contributor_counts(const lmrs_frame* f, const lmrs_render_opts* o, float* counts, void* stream);
+
 /* a4. Stratified pixel sampling (Sec. 4.4), writes f->pix and f->w
  * ([V][T][k], device; both must be non-NULL).
  * LMRS_SAMPLER_UNIFORM: k distinct pixels per tile, the k smallest
@@ -259,14 +317,42 @@ lmrs_status lmrs_residual_scores(const lmrs_frame* f, const lmrs_render_opts* o,
  *   takes u_j = (top 24 bits of the first Philox word of counter
  *   (256 + j, tile, camera id, iter)) * 2^-24 and the smallest p whose
  *   running sum of q in pixel order exceeds u_j; k draws with replacement
- *   in draw order, weight 1 / (k q(p)). scores is ignored by the uniform
- *   sampler and may be NULL there. Unknown sampler: LMRS_EINVAL. */
+ *   in draw order, weight 1 / (k q(p)).
+ * LMRS_SAMPLER_GAUSSIAN (Supp. E q_Gaussian, eq. 17): scores holds the
+ *   counts G_p of lmrs_contributor_counts; inside each tile q(p) = G_p / Z,
+ *   Z = sum G (a tile with Z = 0 is sampled uniformly, G_p taken as 1); draw j
+ *   takes the 24-bit word d_j of the same counter as the residual sampler and
+ *   the smallest p with (G_0 + ... + G_p) 2^24 > d_j Z, in integers; weight
+ *   Z / (k G_p).
+ * scores is ignored by the uniform sampler and may be NULL there. Unknown
+ * sampler: LMRS_EINVAL. */
 lmrs_status lmrs_sample(const lmrs_frame* f, int32_t sampler, uint64_t seed, int32_t iter, const float* scores,
                         void* stream);
 
+/* View batches by camera clustering (Sec. 4.3), host code (no device work).
+ * lmrs_view_clusters splits n_cams cameras (host lmrs_camera array) into
+ * `batch` clusters by K-means on the 6-D features (camera centre moved to the
+ * centres' mean and scaled by their largest distance from it; viewing
+ * direction = third row of R): D^2 seeding from Philox4x32-10 words of
+ * counters (s, 0, batch, 0x4b4d0001) with key = seed, then Lloyd rounds until
+ * no assignment changes (at most 100; an empty cluster takes the camera
+ * farthest from its own centre). labels: host int32[n_cams], cluster of each
+ * camera. Needs 0 < batch <= n_cams, else LMRS_EINVAL. */
+lmrs_status lmrs_view_clusters(const lmrs_camera* cams, int32_t n_cams, int32_t batch, uint64_t seed,
+                               int32_t* labels);
+
+/* One camera from each cluster for LM iteration `iter`: cluster j (members in
+ * ascending camera index, m of them) gives member floor(d m / 2^24), d the top
+ * 24 bits of the first Philox4x32-10 word of counter (j, iter, batch,
+ * 0x4b4d0002), key = seed. labels: host int32[n_cams] from
+ * lmrs_view_clusters; view_ids: host int32[batch] (out). */
+lmrs_status lmrs_view_batch(const int32_t* labels, int32_t n_cams, int32_t batch, uint64_t seed, int32_t iter,
+                            int32_t* view_ids);
+
 /* a1-a8. One LM iteration of Alg. 1 on the batch views f->view_ids:
  * project, bin, sample k pixels per tile (prm->sampler, as lmrs_sample;
- * the residual sampler first renders every pixel for its scores; with the
+ * the weighted samplers first render every pixel for their scores or
+ * counts; with the
  * uniform sampler and f->pix NULL, k = 256 takes every pixel with weight 1),
  * render, residuals r = C - I against targets
  * (device [*][height][width][3], indexed by camera id), b = J^T W r,
@@ -278,6 +364,21 @@ lmrs_status lmrs_sample(const lmrs_frame* f, int32_t sampler, uint64_t seed, int
 lmrs_status lmrs_lm_step(lmrs_frame* f, float* beta, const float* targets, const float* d,
                          const lmrs_lm_params* prm, const lmrs_render_opts* o, float* report,
                          void* ws, size_t ws_bytes, void* stream);
+
+/* lmrs_bin_tiles without the host's wait: enqueues every launch and returns.
+ * If the count exceeds f->capacity, every list comes out empty (tile_start
+ * all 0, ids untouched) and *n_instances (device) holds the count needed; the
+ * caller finds out by reading it. f->ids must be non-NULL. Graph-capturable. */
+lmrs_status lmrs_bin_tiles_async(const lmrs_frame* f, void* ws, size_t ws_bytes, void* stream);
+
+/* One LM iteration as lmrs_lm_step (same arguments and workspace,
+ * LMRS_OP_LM), with the binning of lmrs_bin_tiles_async: it never waits on
+ * the host, so a whole iteration can be captured into a HIP graph. A count
+ * above f->capacity leaves beta unchanged and sets LMRS_FAIL_CAPACITY in
+ * report[LMRS_REP_STATUS], with the count in report[LMRS_REP_INST]. */
+lmrs_status lmrs_lm_iterate(lmrs_frame* f, float* beta, const float* targets, const float* d,
+                            const lmrs_lm_params* prm, const lmrs_render_opts* o, float* report,
+                            void* ws, size_t ws_bytes, void* stream);
 
 /* a4-a8. The part of lmrs_lm_step after lmrs_project and lmrs_bin_tiles:
  * sampling, render, residuals, b = J^T W r, preconditioner, PCG, learning

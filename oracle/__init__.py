@@ -55,7 +55,7 @@ def lib():
         L = C.CDLL(LIB)
         vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
         L.or_create.restype = vp
-        L.or_create.argtypes = [i32, i32, vp, i32, vp, i32, i32, vp]
+        L.or_create.argtypes = [i32, i32, vp, i32, vp, i32, i32, vp, vp]
         L.or_destroy.argtypes = [vp]
         L.or_num_instances.restype = i64
         L.or_num_instances.argtypes = [vp]
@@ -91,7 +91,7 @@ class Oracle:
     """
 
     def __init__(self, n: int, sh_degree: int, beta: np.ndarray, cams: np.ndarray, width: int,
-                 height: int, opts: dict | None = None):
+                 height: int, opts: dict | None = None, only_tiles: np.ndarray | None = None):
         self.n, self.deg = int(n), int(sh_degree)
         self.K = (self.deg + 1) ** 2
         self.Pg = 11 + 3 * self.K
@@ -104,8 +104,13 @@ class Oracle:
         assert self._beta.size == self.P
         self._cams = np.ascontiguousarray(cams, dtype=np.float32)
         self._opts = opts_array(opts)
+        # only_tiles (uint8 [V*T]): build the lists of these tiles only (the
+        # others stay empty); renders and derivatives are then valid there only
+        self._only = None if only_tiles is None else np.ascontiguousarray(only_tiles, dtype=np.uint8).reshape(-1)
+        if self._only is not None:
+            assert self._only.size == self.V * (self.W // 16) * (self.H // 16)
         self.h = lib().or_create(self.n, self.deg, _p(self._beta), self.V, _p(self._cams), self.W,
-                                 self.H, _p(self._opts))
+                                 self.H, _p(self._opts), _p(self._only))
         if not self.h:
             raise ValueError("oracle: bad problem description")
         self.k = 256

@@ -384,8 +384,10 @@ void project_all(Problem& pb) {
 }
 
 // Tile lists: every visible Gaussian whose tile rectangle holds the tile,
-// ascending camera depth, ties by ascending Gaussian index.
-void bin_all(Problem& pb) {
+// ascending camera depth, ties by ascending Gaussian index. With `only`
+// (uint8 [V*T]), the lists of the other tiles are left empty (a cheaper setup
+// for checks restricted to a few tiles; the listed tiles are unchanged).
+void bin_all(Problem& pb, const uint8_t* only = nullptr) {
   std::vector<std::vector<std::pair<double, int>>> lists((size_t)pb.V * pb.T);
   for (int v = 0; v < pb.V; ++v)
     for (int g = 0; g < pb.n; ++g) {
@@ -393,8 +395,10 @@ void bin_all(Problem& pb) {
       if (!pb.visible[vg]) continue;
       const int* rc = &pb.rect[vg * 4];
       for (int ty = rc[1]; ty < rc[3]; ++ty)
-        for (int tx = rc[0]; tx < rc[2]; ++tx)
-          lists[(size_t)v * pb.T + ty * pb.TX + tx].push_back({pb.depth[vg], g});
+        for (int tx = rc[0]; tx < rc[2]; ++tx) {
+          const size_t t = (size_t)v * pb.T + ty * pb.TX + tx;
+          if (!only || only[t]) lists[t].push_back({pb.depth[vg], g});
+        }
     }
   pb.tile_start.assign((size_t)pb.V * pb.T + 1, 0);
   for (size_t i = 0; i < lists.size(); ++i) pb.tile_start[i + 1] = pb.tile_start[i] + lists[i].size();
@@ -408,7 +412,7 @@ void bin_all(Problem& pb) {
 }
 
 void setup(Problem& pb, int n, int deg, const double* beta, int V, const float* cams, int W, int H,
-           const double* opts) {
+           const double* opts, const uint8_t* only = nullptr) {
   pb.n = n; pb.deg = deg; pb.K = (deg + 1) * (deg + 1); pb.Pg = 11 + 3 * pb.K;
   pb.V = V; pb.W = W; pb.H = H; pb.TX = W / kTile; pb.TY = H / kTile; pb.T = pb.TX * pb.TY;
   pb.beta.assign(beta, beta + (size_t)n * pb.Pg);
@@ -424,7 +428,7 @@ void setup(Problem& pb, int n, int deg, const double* beta, int V, const float* 
       k.campos[i] = -(k.R[0 + i] * k.t[0] + k.R[3 + i] * k.t[1] + k.R[6 + i] * k.t[2]);
   }
   project_all(pb);
-  bin_all(pb);
+  bin_all(pb, only);
   pb.pj_slot.assign((size_t)V * n, -1);
   pb.pj.clear();
 }
@@ -664,11 +668,12 @@ void chain_to_params(Problem& pb, const std::vector<double>& grad_rec, double* o
 // =========================================================== C interface
 extern "C" {
 
+// only: NULL, or uint8 [V*T] tiles whose lists are built (the others empty)
 void* or_create(int n, int deg, const double* beta, int V, const float* cams, int W, int H,
-                const double* opts) {
+                const double* opts, const uint8_t* only) {
   if (n < 0 || deg < 0 || deg > 3 || V <= 0 || W % kTile || H % kTile) return nullptr;
   Problem* pb = new Problem();
-  setup(*pb, n, deg, beta, V, cams, W, H, opts);
+  setup(*pb, n, deg, beta, V, cams, W, H, opts, only);
   return pb;
 }
 

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblmrs.so")
-SOURCES = ["api.hip", "kernels_project.hip", "kernels_bin.hip", "kernels_splat.hip", "kernels_solver.hip"]
+SOURCES = ["api.hip", "kernels_project.hip", "kernels_bin.hip", "kernels_splat.hip", "kernels_solver.hip",
+           "views.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"),
          "-I", CSRC,

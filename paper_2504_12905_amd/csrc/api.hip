@@ -108,19 +108,20 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
 lmrs_status check_frame(const lmrs_frame* f, bool need_samples_k = true) {
   if (!f) return fail(LMRS_EINVAL, "frame is NULL");
   if (f->n <= 0) return fail(LMRS_EINVAL, "n = %d must be positive", f->n);
-  if (f->sh_degree < 0 || f->sh_degree > 3) return fail(LMRS_EINVAL, "sh_degree = %d not in 0..3", f->sh_degree);
+  if (f->sh_degree < 0) return fail(LMRS_EINVAL, "sh_degree = %d is negative", f->sh_degree);
+  if (f->sh_degree > 3) return fail(LMRS_EUNSUPPORTED, "sh_degree = %d: degrees 0..3 are built", f->sh_degree);
   if (f->n_views <= 0) return fail(LMRS_EINVAL, "n_views = %d must be positive", f->n_views);
   if (f->width <= 0 || f->height <= 0 || f->width % kTile || f->height % kTile)
     return fail(LMRS_EINVAL, "image %dx%d must be positive multiples of 16", f->width, f->height);
+  if ((int64_t)(f->width / kTile) * (f->height / kTile) > kMaxTilesPerView)
+    return fail(LMRS_EUNSUPPORTED, "%d x %d image has more than %d tiles", f->width, f->height, kMaxTilesPerView);
+  const int64_t tiles = (int64_t)f->n_views * (f->width / kTile) * (f->height / kTile);
+  if (tiles > 0x7fffffffLL) return fail(LMRS_EINVAL, "too many tiles");
   if (need_samples_k) {
     if (f->k < 1 || f->k > 256) return fail(LMRS_EINVAL, "k = %d not in 1..256", f->k);
     if (!f->pix && f->k != 256) return fail(LMRS_EINVAL, "pix is NULL but k = %d != 256", f->k);
   }
   if (!f->beta) return fail(LMRS_EINVAL, "beta is NULL");
-  const int64_t tiles = (int64_t)f->n_views * (f->width / kTile) * (f->height / kTile);
-  if (tiles > 0x7fffffffLL) return fail(LMRS_EINVAL, "too many tiles");
-  if ((int64_t)(f->width / kTile) * (f->height / kTile) > kMaxTilesPerView)
-    return fail(LMRS_EINVAL, "%d x %d image has more than %d tiles", f->width, f->height, kMaxTilesPerView);
   return LMRS_OK;
 }
 
@@ -245,6 +246,16 @@ lmrs_status bin_sequence(const lmrs_frame* f, const FrameDims& d, const Scratch&
   return hip_check("bin sort");
 }
 
+// The same launches without the host's wait for the count: when the count
+// exceeds f->capacity the lists come out empty (on the device) and
+// *n_instances holds the count needed.
+void bin_sequence_async(const lmrs_frame* f, const FrameDims& d, const Scratch& s, hipStream_t st) {
+  launch_bin_total(f, d, s.bin, st);
+  launch_view_sort(f, d, s.bin, st);
+  launch_bin_count(f, d, s.bin, st);
+  launch_bin_emit_sort(f, d, s.bin, st);
+}
+
 lmrs_status check_lm_args(const lmrs_frame* f, const float* beta, const float* targets,
                           const lmrs_lm_params* prm, const lmrs_render_opts* o) {
   LMRS_TRY(check_frame(f));
@@ -260,11 +271,12 @@ lmrs_status check_lm_args(const lmrs_frame* f, const float* beta, const float* t
   LMRS_TRY(need(f->last, "last"));
   LMRS_TRY(need(f->sched, "sched"));
   if (f->k < 256 && (!f->pix || !f->w)) return fail(LMRS_EINVAL, "k < 256 needs pix and w buffers");
-  if (prm->sampler != LMRS_SAMPLER_UNIFORM && prm->sampler != LMRS_SAMPLER_RESIDUAL)
+  if (prm->sampler != LMRS_SAMPLER_UNIFORM && prm->sampler != LMRS_SAMPLER_RESIDUAL &&
+      prm->sampler != LMRS_SAMPLER_GAUSSIAN)
     return fail(LMRS_EINVAL, "unknown sampler %d", prm->sampler);
-  if (prm->sampler == LMRS_SAMPLER_RESIDUAL && (!f->pix || !f->w))
-    return fail(LMRS_EINVAL, "the residual sampler needs pix and w buffers");
-  if (prm->cg_iters < 0) return fail(LMRS_EINVAL, "cg_iters must be >= 0");
+  if (prm->sampler != LMRS_SAMPLER_UNIFORM && (!f->pix || !f->w))
+    return fail(LMRS_EINVAL, "the weighted samplers need pix and w buffers");
+  if (prm->cg_iters < 0 || prm->cg_iters_late < 0) return fail(LMRS_EINVAL, "cg_iters must be >= 0");
   if (!(prm->lambda >= 0.f)) return fail(LMRS_EINVAL, "lambda must be >= 0");
   return LMRS_OK;
 }
@@ -278,18 +290,27 @@ void solve_sequence(const lmrs_frame* f, const FrameDims& d, float* beta, const 
   if (prm.sampler == LMRS_SAMPLER_RESIDUAL) {
     launch_render_scores(f, d, o, targets, s.scores, st);
     launch_sample_residual(f, d, s.scores, prm.seed, prm.iter, st);
+  } else if (prm.sampler == LMRS_SAMPLER_GAUSSIAN) {
+    launch_render_counts(f, d, o, s.scores, st);
+    launch_sample_gaussian(f, d, s.scores, prm.seed, prm.iter, st);
   } else if (f->pix) {
     launch_sample_uniform(f, d, prm.seed, prm.iter, st);
   }
   launch_render(f, d, o, st);
   launch_residual(f, d, targets, s.wr, s.red, report, st);
   vjp_diag_sequence(f, d, o, s.wr, s.b, s.diag, s, st);
-  pcg_sequence(f, d, o, s.b, prm.lambda, dvec, prm.cg_iters, s.x, report, s, st, true, true);
-  launch_lm_update(beta, s.x, d.n, P, prm, s.red, report, st);
-  if (report) launch_report_count(f->n_instances, report + LMRS_REP_INST, st);
+  // CG schedule (Sec. 5): cg_iters_late GN products from iteration late_iter on
+  const bool late = prm.cg_iters_late > 0 && prm.late_iter > 0 && prm.iter >= prm.late_iter;
+  const int cg = late ? prm.cg_iters_late : prm.cg_iters;
+  pcg_sequence(f, d, o, s.b, prm.lambda, dvec, cg, s.x, report, s, st, true, true);
+  const PcgState ps{s.x, s.r, s.z, s.p, s.u, s.minv, s.sc, s.red};
+  launch_lm_update(beta, s.x, d.n, P, prm, pcg_fail_slot(cg, ps), s.red, report, st);
+  if (report) launch_report_count(f->n_instances, f->capacity, report, st);
 }
 
 }  // namespace
+
+lmrs_status report_error(lmrs_status s, const char* msg) { return fail(s, "%s", msg); }
 
 FrameDims dims_of(const lmrs_frame* f) {
   FrameDims d;
@@ -320,11 +341,25 @@ const char* lmrs_status_str(lmrs_status s) {
     case LMRS_ECAPACITY: return "tile-list capacity exceeded";
     case LMRS_EWORKSPACE: return "workspace too small";
     case LMRS_EHIP: return "HIP runtime error";
+    case LMRS_ENUMERIC: return "numeric failure on the device";
+    case LMRS_EUNSUPPORTED: return "not supported by this library";
     default: return "unknown status";
   }
 }
 
 const char* lmrs_last_error(void) { return g_err; }
+
+lmrs_status lmrs_report_status(const float* report) {
+  if (!report) return fail(LMRS_EINVAL, "report is NULL");
+  const float st = report[LMRS_REP_STATUS];
+  if (st == 0.f) return LMRS_OK;
+  const int bits = (int)st;
+  if (bits & LMRS_FAIL_CAPACITY)
+    return fail(LMRS_ECAPACITY, "tile lists needed %.0f entries, more than the capacity", (double)report[LMRS_REP_INST]);
+  return fail(LMRS_ENUMERIC, "numeric failure on the device:%s%s (status %g)",
+              (bits & LMRS_FAIL_NONFINITE) ? " non-finite values" : "",
+              (bits & LMRS_FAIL_BREAKDOWN) ? " PCG breakdown (p^T A p <= 0)" : "", (double)st);
+}
 
 size_t lmrs_workspace_bytes(int32_t op, const lmrs_frame* f) {
   if (!f || f->n <= 0 || f->n_views <= 0 || f->width <= 0 || f->height <= 0) return 0;
@@ -456,6 +491,15 @@ lmrs_status lmrs_gn_product_timed(const lmrs_frame* f, const lmrs_render_opts* o
   return hip_check("lmrs_gn_product_timed");
 }
 
+lmrs_status lmrs_walk_counts(const lmrs_frame* f, const lmrs_render_opts* o, int64_t* counts, void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_deriv_state(f));
+  LMRS_TRY(need(counts, "counts"));
+  launch_walk_counts(f, dims_of(f), *o, counts, (hipStream_t)stream);
+  return hip_check("lmrs_walk_counts");
+}
+
 lmrs_status lmrs_gn_diag(const lmrs_frame* f, const lmrs_render_opts* o, float* out, void* ws,
                          size_t ws_bytes, void* stream) {
   LMRS_TRY(check_frame(f));
@@ -499,6 +543,15 @@ lmrs_status lmrs_residual_scores(const lmrs_frame* f, const lmrs_render_opts* o,
   return hip_check("lmrs_residual_scores");
 }
 
+lmrs_status lmrs_contributor_counts(const lmrs_frame* f, const lmrs_render_opts* o, float* counts, void* stream) {
+  LMRS_TRY(check_frame(f, false));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_render_state(f));
+  LMRS_TRY(need(counts, "counts"));
+  launch_render_counts(f, dims_of(f), *o, counts, (hipStream_t)stream);
+  return hip_check("lmrs_contributor_counts");
+}
+
 lmrs_status lmrs_sample(const lmrs_frame* f, int32_t sampler, uint64_t seed, int32_t iter, const float* scores,
                         void* stream) {
   LMRS_TRY(check_frame(f));
@@ -510,6 +563,9 @@ lmrs_status lmrs_sample(const lmrs_frame* f, int32_t sampler, uint64_t seed, int
   } else if (sampler == LMRS_SAMPLER_RESIDUAL) {
     LMRS_TRY(need(scores, "scores"));
     launch_sample_residual(f, d, scores, seed, iter, (hipStream_t)stream);
+  } else if (sampler == LMRS_SAMPLER_GAUSSIAN) {
+    LMRS_TRY(need(scores, "scores (contributor counts)"));
+    launch_sample_gaussian(f, d, scores, seed, iter, (hipStream_t)stream);
   } else {
     return fail(LMRS_EINVAL, "unknown sampler %d", sampler);
   }
@@ -529,6 +585,36 @@ lmrs_status lmrs_lm_step(lmrs_frame* f, float* beta, const float* targets, const
   LMRS_TRY(bin_sequence(f, d, s, st));
   solve_sequence(f, d, beta, targets, dvec, *prm, *o, report, s, st);
   return hip_check("lmrs_lm_step");
+}
+
+lmrs_status lmrs_bin_tiles_async(const lmrs_frame* f, void* ws, size_t ws_bytes, void* stream) {
+  LMRS_TRY(check_frame(f, false));
+  LMRS_TRY(need(f->rec, "rec"));
+  LMRS_TRY(need(f->rect, "rect"));
+  LMRS_TRY(need(f->tile_start, "tile_start"));
+  LMRS_TRY(need(f->n_instances, "n_instances"));
+  LMRS_TRY(need(f->ids, "ids"));
+  LMRS_TRY(check_ws(LMRS_OP_BIN, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_BIN, d, f->capacity, c);
+  bin_sequence_async(f, d, s, (hipStream_t)stream);
+  return hip_check("lmrs_bin_tiles_async");
+}
+
+lmrs_status lmrs_lm_iterate(lmrs_frame* f, float* beta, const float* targets, const float* dvec,
+                            const lmrs_lm_params* prm, const lmrs_render_opts* o, float* report, void* ws,
+                            size_t ws_bytes, void* stream) {
+  LMRS_TRY(check_lm_args(f, beta, targets, prm, o));
+  LMRS_TRY(check_ws(LMRS_OP_LM, f, ws, ws_bytes));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_LM, d, f->capacity, c);
+  hipStream_t st = (hipStream_t)stream;
+  launch_project(f, d, *o, st);
+  bin_sequence_async(f, d, s, st);
+  solve_sequence(f, d, beta, targets, dvec, *prm, *o, report, s, st);
+  return hip_check("lmrs_lm_iterate");
 }
 
 lmrs_status lmrs_lm_solve(lmrs_frame* f, float* beta, const float* targets, const float* dvec,

@@ -22,6 +22,23 @@ constexpr int kWave = 64;
 constexpr int kGram = 32;            // Gram entries kept per (view, Gaussian)
 constexpr int kGradRow = 16;         // floats per (view, Gaussian) row of screen gradients (9 used)
 
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC 2011): 10 rounds of two 32x32->64
+// multiplies with key bumps by the Weyl constants. Host and device.
+__host__ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
 // ------------------------------------------------------------------ duals
 struct dualf {
   float v, d;
@@ -41,8 +58,11 @@ __device__ __forceinline__ dualf operator/(dualf a, dualf b) {
   return dualf(q, (a.d - q * b.d) * r);
 }
 __device__ __forceinline__ float tval(float x) { return x; }
+__device__ __forceinline__ double tval(double x) { return x; }
 __device__ __forceinline__ float tval(dualf x) { return x.v; }
 __device__ __forceinline__ float texp(float x) { return expf(x); }
+__device__ __forceinline__ double texp(double x) { return exp(x); }
+__device__ __forceinline__ double trsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ dualf texp(dualf x) {
   const float e = expf(x.v);
   return dualf(e, e * x.d);
@@ -104,19 +124,34 @@ __device__ __forceinline__ CamView load_cam(const lmrs_camera* cams, const int32
   return cv;
 }
 
-// Camera-space mean and projected centre in FP32 with a fixed operation
-// order (these values decide list membership and depth order).
-__device__ __forceinline__ void decision_point(const lmrs_camera& c, float mx, float my, float mz,
-                                               float* tc, float* u, float* v) {
+// Camera-space mean and projected centre in FP64: these decide the near-plane
+// cull, the tile rectangle and the depth order, so they are taken to FP64
+// accuracy (two FP64 evaluations of them agree unless a value lies within
+// ~1e-12 of its threshold).
+__device__ __forceinline__ void decision_point(const lmrs_camera& c, double mx, double my, double mz,
+                                               double* tc, double* u, double* v) {
   for (int i = 0; i < 3; ++i) {
-    float acc = c.t[i];
-    acc = __fmaf_rn(c.R[3 * i + 0], mx, acc);
-    acc = __fmaf_rn(c.R[3 * i + 1], my, acc);
-    acc = __fmaf_rn(c.R[3 * i + 2], mz, acc);
+    double acc = (double)c.t[i];
+    acc = fma((double)c.R[3 * i + 0], mx, acc);
+    acc = fma((double)c.R[3 * i + 1], my, acc);
+    acc = fma((double)c.R[3 * i + 2], mz, acc);
     tc[i] = acc;
   }
-  *u = __fmaf_rn(c.fx, __fdiv_rn(tc[0], tc[2]), c.cx);
-  *v = __fmaf_rn(c.fy, __fdiv_rn(tc[1], tc[2]), c.cy);
+  *u = fma((double)c.fx, tc[0] / tc[2], (double)c.cx);
+  *v = fma((double)c.fy, tc[1] / tc[2], (double)c.cy);
+}
+
+// Depth sort keys of a camera depth z: the FP32 number nearest z, and the
+// count of FP64 numbers between that and z, offset by 2^30. Rounding to nearest
+// is monotone, so (key, sub) in lexicographic order is the order of z itself;
+// |z - key| <= half an FP32 spacing, i.e. at most 2^28 FP64 spacings, so sub
+// fits 31 bits. Both are meaningful for z > 0 only (culled Gaussians are never
+// listed).
+__device__ __forceinline__ void depth_keys(double z, float* key, uint32_t* sub) {
+  const float k = (float)z;
+  *key = k;
+  const int64_t d = (int64_t)__double_as_longlong(z) - (int64_t)__double_as_longlong((double)k);
+  *sub = (uint32_t)(d + (int64_t(1) << 30));
 }
 
 // Load the PG parameters of Gaussian g (component-major beta).
@@ -141,7 +176,7 @@ __device__ __forceinline__ void load_params(const float* beta, int n, int g, T* 
 // identity det = |k1 x k2|^2 + lowpass (|k1|^2 + |k2|^2) + lowpass^2.
 template <class T>
 __device__ __forceinline__ void proj_geom(const T* prm, const CamView& cv, float lowpass, T* rec,
-                                          float* a_out, float* b_out, float* c_out) {
+                                          double* a_out, double* b_out, double* c_out) {
   const lmrs_camera& c = cv.c;
   const T mx = prm[0], my = prm[1], mz = prm[2];
   const T tx = T(c.R[0]) * mx + T(c.R[1]) * my + T(c.R[2]) * mz + T(c.t[0]);
@@ -172,7 +207,7 @@ __device__ __forceinline__ void proj_geom(const T* prm, const CamView& cv, float
   const T n2 = K[3] * K[3] + K[4] * K[4] + K[5] * K[5];
   const T b = K[0] * K[3] + K[1] * K[4] + K[2] * K[5];
   const T w0 = K[1] * K[5] - K[2] * K[4], w1 = K[2] * K[3] - K[0] * K[5], w2 = K[0] * K[4] - K[1] * K[3];
-  const T det = (w0 * w0 + w1 * w1 + w2 * w2) + T(lowpass) * (n1 + n2) + T(lowpass * lowpass);
+  const T det = (w0 * w0 + w1 * w1 + w2 * w2) + T(lowpass) * (n1 + n2) + T(lowpass) * T(lowpass);
   const T cc = n2 + T(lowpass);
   const T r = trsqrt(cc * det);
   rec[0] = T(c.fx) * tx * iz + T(c.cx);
@@ -180,7 +215,7 @@ __device__ __forceinline__ void proj_geom(const T* prm, const CamView& cv, float
   rec[2] = cc * r;
   rec[3] = -(b * r);
   rec[4] = trsqrt(cc);
-  if (a_out) { *a_out = tval(n1) + lowpass; *b_out = tval(b); *c_out = tval(cc); }
+  if (a_out) { *a_out = tval(n1 + T(lowpass)); *b_out = tval(b); *c_out = tval(cc); }
 }
 
 // Unit direction from the camera centre to the mean.
@@ -210,8 +245,8 @@ __device__ __forceinline__ void proj_color(const T* prm, const CamView& cv, T* r
 
 // Screen record (u, v, f11, f12, f22, opacity, r, g, b) of one Gaussian in one view.
 template <int DEG, class T>
-__device__ __forceinline__ void proj_core(const T* prm, const CamView& cv, float lowpass, T* rec, float* a_out,
-                                          float* b_out, float* c_out) {
+__device__ __forceinline__ void proj_core(const T* prm, const CamView& cv, float lowpass, T* rec, double* a_out,
+                                          double* b_out, double* c_out) {
   proj_geom(prm, cv, lowpass, rec, a_out, b_out, c_out);
   rec[5] = T(1.f) / (T(1.f) + texp(-prm[10]));
   proj_color<DEG>(prm, cv, rec + 6);

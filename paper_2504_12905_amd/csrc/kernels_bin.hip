@@ -3,11 +3,13 @@
 //
 // 1. total: the number of tile-list entries (sum of the rect areas), copied
 //    to the host first so that its wait overlaps the steps below.
-// 2. depth ranks: per view, a stable LSD radix sort of (depth bits, Gaussian
-//    id) over all waves of the grid (ties keep ascending id) gives each
-//    Gaussian its depth rank and the rank -> id table. Depths are > znear > 0
-//    for every Gaussian that is emitted, so their IEEE bits order like the
-//    values (culled ones sort anywhere; they are never emitted).
+// 2. depth ranks: per view, a stable LSD radix sort of (FP32 depth key bits,
+//    Gaussian id) over all waves of the grid (ties keep ascending id), then
+//    runs of equal FP32 keys re-ordered by the FP64 depth (sub-key, id), give
+//    each Gaussian its rank in FP64 depth order and the rank -> id table.
+//    Depths are > znear > 0 for every Gaussian that is emitted, so their IEEE
+//    bits order like the values (culled ones sort anywhere; they are never
+//    emitted).
 // 3. hist: the Gaussians of a view in rank order, cut into chunks of kChunk
 //    ranks; one workgroup per (view, chunk) counts its Gaussians per tile in
 //    LDS (the only atomics are LDS atomics: a hot tile can hold thousands of
@@ -151,14 +153,18 @@ __global__ __launch_bounds__(256) void colscan_kernel(int32_t* __restrict__ chun
 // tile_start = exclusive prefix sum of the m tile totals, in the workgroups
 // of colscan_kernel: each adds the col_part of the workgroups before it to a
 // scan of its own 256 totals; the counts are reset to zero for the cursors of
-// the next binning. The last entry also gives tile_start[m] and the total.
+// the next binning. The last entry also gives tile_start[m].
+// When the total (the rect-area sum written before) exceeds `capacity`,
+// every list is left empty instead (tile_start all 0): the entries would not
+// fit the caller's buffers, and the kernels after this one then see no list.
 __global__ __launch_bounds__(256) void tile_start_kernel(int32_t* __restrict__ counts, int64_t m,
                                                          const int64_t* __restrict__ col_part,
                                                          int64_t* __restrict__ tile_start,
-                                                         int64_t* __restrict__ total) {
+                                                         int64_t* __restrict__ total, int64_t capacity) {
   __shared__ double s_red[256];
   __shared__ int64_t s_wave[256 / kWave];
   const int tid = threadIdx.x, lane = lane_id();
+  const bool over = *total > capacity;  // the same value in every workgroup (written by area_total_kernel)
   int64_t before = 0;
   for (int b = tid; b < (int)blockIdx.x; b += 256) before += col_part[b];
   const int64_t off = (int64_t)block_sum((double)before, s_red);
@@ -174,21 +180,20 @@ __global__ __launch_bounds__(256) void tile_start_kernel(int32_t* __restrict__ c
   __syncthreads();
   for (int w = 0; w < tid / kWave; ++w) y += s_wave[w];
   if (i < m) {
-    tile_start[i] = off + y - x;
+    tile_start[i] = over ? 0 : off + y - x;
     counts[i] = 0;
   }
-  if (i == m - 1) {
-    tile_start[m] = off + y;
-    *total = off + y;
-  }
+  if (i == m - 1) tile_start[m] = over ? 0 : off + y;
 }
 
 __global__ __launch_bounds__(kBinThreads) void emit_kernel(const int4* __restrict__ rect,
                                                             const int32_t* __restrict__ order, int n, int TX, int T,
                                                             int n_chunks, const int32_t* __restrict__ chunk_hist,
                                                             const int64_t* __restrict__ tile_start,
+                                                            const int64_t* __restrict__ total, int64_t capacity,
                                                             uint32_t* __restrict__ keys) {
   extern __shared__ int32_t s_cur[];
+  if (*total > capacity) return;  // lists left empty (tile_start_kernel)
   const int chunk = blockIdx.x, v = blockIdx.y;
   const int32_t* off = chunk_hist + ((size_t)v * n_chunks + chunk) * T;
   for (int t = threadIdx.x; t < T; t += kBinThreads) s_cur[t] = off[t];
@@ -375,6 +380,101 @@ __global__ __launch_bounds__(kViewThreads) void view_scatter_kernel(const uint32
   part_scatter(ksrc, kdst + vb, vsrc, vdst + vb, b0, b1, shift, kRadixBins, cur[w]);
 }
 
+// ---- ties of the FP32 depth key. The radix passes order a view's Gaussians
+// by (FP32 key, id); a run of equal keys is then re-ordered by (sub-key, id),
+// the sub-key carrying the FP64 depth's bits below the FP32 key (record slot
+// 11), which gives the order of the FP64 depths with ties by id. One wave per
+// 64 ranks; the wave holding the first rank of a run of two or more sorts the
+// run: each member's place is the count of members before it, written to tmp
+// and copied back. Runs already in order are left alone after one pass over
+// them (equal FP64 depths keep the id order of the radix passes), and only
+// keys of positive finite depths are looked at (culled Gaussians are never
+// listed).
+__device__ __forceinline__ uint32_t depth_sub(const float* __restrict__ rec, int64_t vn, uint32_t g) {
+  return __float_as_uint(rec[(vn + g) * LMRS_REC + 11]);
+}
+
+__global__ __launch_bounds__(256) void view_ties_kernel(const uint32_t* __restrict__ key, uint32_t* __restrict__ val,
+                                                        uint32_t* __restrict__ tmp, const float* __restrict__ rec,
+                                                        int n, int V) {
+  const int lane = lane_id();
+  const int per_view = (n + kWave - 1) / kWave;
+  const int64_t wave = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  if (wave >= (int64_t)V * per_view) return;  // whole wave
+  const int v = (int)(wave / per_view);
+  const int i0 = (int)(wave % per_view) * kWave;
+  const int64_t vn = (int64_t)v * n;
+  const uint32_t* kv = key + vn;
+  uint32_t* ids = val + vn;
+  uint32_t* tv = tmp + vn;
+  const int i = i0 + lane;
+  const uint32_t k = i < n ? kv[i] : 0u;
+  const bool prev_differs = i == 0 || (i < n && kv[i - 1] != k);
+  const bool next_same = i + 1 < n && kv[i + 1] == k;
+  const bool positive = k > 0u && k < 0x7f800000u;
+  for (uint64_t heads = __ballot(i < n && prev_differs && next_same && positive); heads; heads &= heads - 1) {
+    const int src = __ffsll((unsigned long long)heads) - 1;
+    const int a = i0 + src;
+    const uint32_t K = (uint32_t)readlane((int)k, src);
+    // end of the run, and whether it is already in (sub, id) order
+    int e = n;
+    bool sorted = true;
+    for (int base = a; base < n; base += kWave) {
+      const int j = base + lane;
+      const bool in = j < n && kv[j] == K;
+      uint32_t g = 0u, sb = 0u;
+      if (in) {
+        g = ids[j];
+        sb = depth_sub(rec, vn, g);
+      }
+      // order against the next member, held by lane + 1 (or the next step's lane 0)
+      const uint32_t g1 = (uint32_t)__shfl_down((int)g, 1), s1 = (uint32_t)__shfl_down((int)sb, 1);
+      bool ok = true;
+      if (in && lane < kWave - 1 && j + 1 < n && kv[j + 1] == K) ok = sb < s1 || (sb == s1 && g < g1);
+      if (in && lane == kWave - 1 && j + 1 < n && kv[j + 1] == K) {
+        const uint32_t gn = ids[j + 1], sn = depth_sub(rec, vn, gn);
+        ok = sb < sn || (sb == sn && g < gn);
+      }
+      sorted = sorted && (__ballot(!ok) == 0);
+      const uint64_t out = __ballot(!in);
+      if (out) {
+        e = base + __ffsll((unsigned long long)out) - 1;
+        break;
+      }
+    }
+    if (sorted) continue;
+    for (int jb = a; jb < e; jb += kWave) {
+      const int j = jb + lane;
+      uint32_t gj = 0xffffffffu, sj = 0xffffffffu;
+      if (j < e) {
+        gj = ids[j];
+        sj = depth_sub(rec, vn, gj);
+      }
+      int place = 0;
+      for (int mb = a; mb < e; mb += kWave) {
+        const int m = mb + lane;
+        uint32_t gm = 0xffffffffu, sm = 0xffffffffu;
+        if (m < e) {
+          gm = ids[m];
+          sm = depth_sub(rec, vn, gm);
+        }
+        const int cnt = min(kWave, e - mb);
+        for (int q = 0; q < cnt; ++q) {
+          const uint32_t s2 = (uint32_t)readlane((int)sm, q), g2 = (uint32_t)readlane((int)gm, q);
+          place += (s2 < sj || (s2 == sj && g2 < gj)) ? 1 : 0;
+        }
+      }
+      if (j < e) tv[a + place] = gj;
+    }
+    __threadfence();  // the run's places are written; read them back
+    for (int jb = a; jb < e; jb += kWave) {
+      const int j = jb + lane;
+      if (j < e) ids[j] = tv[j];
+    }
+    __threadfence();
+  }
+}
+
 // ---- per-tile sort of depth ranks: one workgroup per tile, windows of up to
 // kTileSortLds entries in LDS, wave w owning the part [len w / 4,
 // len (w + 1) / 4) of a window.
@@ -540,7 +640,7 @@ void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hip
   const int64_t m = (int64_t)d.V * d.T;
   const unsigned cblocks = (unsigned)((m + 255) / 256);
   colscan_kernel<<<cblocks, 256, 0, s>>>(b.chunk_hist, d.V, d.T, nc, b.counts, b.col_part);
-  tile_start_kernel<<<cblocks, 256, 0, s>>>(b.counts, m, b.col_part, f->tile_start, f->n_instances);
+  tile_start_kernel<<<cblocks, 256, 0, s>>>(b.counts, m, b.col_part, f->tile_start, f->n_instances, f->capacity);
 }
 
 void launch_view_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
@@ -557,14 +657,18 @@ void launch_view_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hip
     view_scatter_kernel<<<pblocks, kViewThreads, 0, s>>>(b.vkey[q], b.vkey[q ^ 1], b.vval[q], b.vval[q ^ 1], d.n,
                                                           d.V, 8 * pass, b.vcount);
   }
-  // after four passes the sorted ids are in vval[0]: that is the rank -> id table
+  // after four passes the sorted ids are in vval[0]; with the ties of the FP32
+  // key ordered by the FP64 depth that is the rank -> id table
+  const unsigned tblocks = (unsigned)(((int64_t)d.V * ((d.n + kWave - 1) / kWave) + 3) / 4);
+  view_ties_kernel<<<tblocks, 256, 0, s>>>(b.vkey[0], b.vval[0], b.vkey[1], f->rec, d.n, d.V);
 }
 
 void launch_bin_emit_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
   const int nc = bin_chunks(d.n);
   const size_t lds = (size_t)d.T * sizeof(int32_t);
   emit_kernel<<<dim3(nc, d.V), kBinThreads, lds, s>>>(reinterpret_cast<const int4*>(f->rect), b.order, d.n, d.TX,
-                                                      d.T, nc, b.chunk_hist, f->tile_start, b.keys);
+                                                      d.T, nc, b.chunk_hist, f->tile_start, f->n_instances,
+                                                      f->capacity, b.keys);
   tile_sort_kernel<<<(unsigned)((int64_t)d.V * d.T), kTileSortThreads, 0, s>>>(f->tile_start, b.keys, b.order,
                                                                               d.n, d.T, f->ids);
 }

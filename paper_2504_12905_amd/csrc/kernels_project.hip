@@ -30,36 +30,47 @@ __global__ __launch_bounds__(kBlock) void project_kernel(const float* __restrict
   const CamView cv = load_cam(cams, view_ids, v);
   const size_t vg = (size_t)v * n + g;
   float4* out = reinterpret_cast<float4*>(rec + vg * LMRS_REC);
-  float tc[3], u, vv;
-  decision_point(cv.c, beta[g], beta[(size_t)n + g], beta[(size_t)2 * n + g], tc, &u, &vv);
+  // the list decisions (near-plane cull, footprint radius, tile rectangle,
+  // depth order) from FP64 values
+  double tc[3], u, vv;
+  decision_point(cv.c, (double)beta[g], (double)beta[(size_t)n + g], (double)beta[(size_t)2 * n + g], tc, &u,
+                 &vv);
+  float key;
+  uint32_t sub;
+  depth_keys(tc[2], &key, &sub);
   int4 rc = make_int4(0, 0, 0, 0);
   float r[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float radius = 0.f;
-  if (tc[2] > o.znear && isfinite(u) && isfinite(vv)) {
+  if (tc[2] > (double)o.znear && isfinite(u) && isfinite(vv)) {
     float prm[PG];
     load_params<PG>(beta, n, g, prm);
-    float a, b, c;
-    proj_core<DEG>(prm, cv, o.lowpass, r, &a, &b, &c);
-    r[0] = u;
-    r[1] = vv;
-    const float lam = 0.5f * (a + c) + sqrtf(0.25f * (a - c) * (a - c) + b * b);
-    const float rad = ceilf(o.cutoff * sqrtf(lam));
-    if (rad < 1.0e6f) {
-      auto tile_of = [](float q) {
-        const float f = floorf(q / 16.f);
-        return (int)fminf(fmaxf(f, -1.0e6f), 1.0e6f);
-      };
+    proj_core<DEG>(prm, cv, o.lowpass, r, nullptr, nullptr, nullptr);
+    // the record's geometry (centre, conic factor) rounded from FP64, and the
+    // 2-D covariance whose largest eigenvalue sets the radius
+    double pd[10], gd[5], a, b, c;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) pd[j] = (double)prm[j];
+    proj_geom(pd, cv, o.lowpass, gd, &a, &b, &c);
+    r[0] = (float)u;
+    r[1] = (float)vv;
+    r[2] = (float)gd[2];
+    r[3] = (float)gd[3];
+    r[4] = (float)gd[4];
+    const double lam = 0.5 * (a + c) + sqrt(0.25 * (a - c) * (a - c) + b * b);
+    const double rad = ceil((double)o.cutoff * sqrt(lam));
+    if (rad < 1.0e6) {
+      auto tile_of = [](double q) { return (int)fmin(fmax(floor(q / 16.0), -1.0e6), 1.0e6); };
       int x0 = max(tile_of(u - rad), 0), x1 = min(tile_of(u + rad), TX - 1);
       int y0 = max(tile_of(vv - rad), 0), y1 = min(tile_of(vv + rad), TY - 1);
       if (x0 <= x1 && y0 <= y1) {
         rc = make_int4(x0, y0, x1 + 1, y1 + 1);
-        radius = rad;
+        radius = (float)rad;
       }
     }
   }
   out[0] = make_float4(r[0], r[1], r[2], r[3]);
   out[1] = make_float4(r[4], r[5], r[6], r[7]);
-  out[2] = make_float4(r[8], tc[2], radius, 0.f);
+  out[2] = make_float4(r[8], key, radius, __uint_as_float(sub));
   rect[vg] = rc;
 }
 

@@ -12,21 +12,6 @@ namespace lmrs {
 
 namespace {
 
-// Philox4x32-10 (Salmon et al., SC 2011): 10 rounds of two 32x32->64
-// multiplies with key bumps by the Weyl constants.
-__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
-  for (int r = 0; r < 10; ++r) {
-    if (r > 0) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
-  }
-  return c;
-}
-
 // One workgroup of 256 lanes per (view, tile): lane p draws the key of pixel p
 // from counter (p, tile, camera id, iteration); the k pixels with the smallest
 // (key, p) are taken, listed in ascending pixel order, each with weight 256/k.
@@ -125,6 +110,51 @@ __global__ __launch_bounds__(256) void sample_residual_kernel(const float* __res
   w[tile_lin * k + p] = Z / ((float)k * s_e[lo]);
 }
 
+// Contribution-weighted sampling (Supp. E, q_Gaussian) inside each tile:
+// pixel p has probability q(p) = G_p / Z, Z = sum G, G_p the number of
+// Gaussians blended into the pixel; a tile with Z = 0 is sampled uniformly
+// (G_p taken as 1). Draw j takes the 24-bit word d_j of counter
+// (256 + j, tile, camera id, iteration) (as the residual sampler) and the
+// smallest p with Q_p 2^24 > d_j Z, Q_p = G_0 + ... + G_p, all in 64-bit
+// integers, so the draw is exact; weight Z / (k G_p).
+__global__ __launch_bounds__(256) void sample_gaussian_kernel(const float* __restrict__ counts,
+                                                              const int32_t* __restrict__ view_ids, int T,
+                                                              int k, uint32_t seed_lo, uint32_t seed_hi,
+                                                              uint32_t iter, uint8_t* __restrict__ pix,
+                                                              float* __restrict__ w) {
+  __shared__ int64_t s_q[256];
+  __shared__ int s_g[256];
+  const int p = threadIdx.x;
+  const int64_t tile_lin = blockIdx.x;
+  const int v = (int)(tile_lin / T), t = (int)(tile_lin % T);
+  s_g[p] = (int)counts[tile_lin * 256 + p];
+  __syncthreads();
+  if (p == 0) {
+    int64_t acc = 0;
+    for (int q = 0; q < 256; ++q) acc += s_g[q];
+    const bool empty = acc == 0;
+    acc = 0;
+    for (int q = 0; q < 256; ++q) {
+      if (empty) s_g[q] = 1;
+      acc += s_g[q];
+      s_q[q] = acc;
+    }
+  }
+  __syncthreads();
+  if (p >= k) return;
+  const uint32_t cam = (uint32_t)(view_ids ? view_ids[v] : v);
+  const uint4 r = philox4x32_10(make_uint4(256u + (uint32_t)p, (uint32_t)t, cam, iter), seed_lo, seed_hi);
+  const int64_t Z = s_q[255];
+  const int64_t target = (int64_t)(r.x >> 8) * Z;
+  int lo = 0, hi = 255;  // smallest index with s_q * 2^24 > target (index 255 always qualifies)
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((s_q[mid] << 24) > target) hi = mid; else lo = mid + 1;
+  }
+  pix[tile_lin * k + p] = (uint8_t)lo;
+  w[tile_lin * k + p] = (float)Z / ((float)k * (float)s_g[lo]);
+}
+
 // wr = w * (C - I) at every sampled pixel; partial sums of w |C - I|^2.
 __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__ color,
                                                        const float* __restrict__ targets,
@@ -188,8 +218,14 @@ __global__ void report_kernel(const double* __restrict__ value, float* __restric
   if (threadIdx.x == 0 && blockIdx.x == 0) report[slot] = (float)value[0];
 }
 
-__global__ void report_count_kernel(const int64_t* __restrict__ count, float* __restrict__ dst) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = (float)count[0];
+// report[INST] = the step's tile-list entries; when they exceeded the
+// caller's capacity (the lists were left empty) the capacity bit joins the
+// failure bits.
+__global__ void report_count_kernel(const int64_t* __restrict__ count, int64_t capacity,
+                                    float* __restrict__ report) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  report[LMRS_REP_INST] = (float)count[0];
+  if (count[0] > capacity) report[LMRS_REP_STATUS] = (float)((int)report[LMRS_REP_STATUS] | LMRS_FAIL_CAPACITY);
 }
 
 // PCG scalar slots.
@@ -204,6 +240,7 @@ enum : int {
   kStop = 7,
   kDone = 8,
   kRR0 = 9,
+  kFail = 11,   // LMRS_FAIL_* bits (slot 10 holds b^T x for the report)
   kScalars = 16
 };
 
@@ -300,6 +337,10 @@ __global__ __launch_bounds__(256) void pcg_init_scalars_kernel(const double* __r
     for (int i = 0; i < kScalars; ++i) sc[i] = 0.0;
     sc[kRZ] = sc[kRZ0] = rz;
     sc[kRR] = sc[kRR0] = rr;
+    if (!isfinite(rz) || !isfinite(rr)) {  // NaN / Inf in b or the preconditioner
+      sc[kFail] = LMRS_FAIL_NONFINITE;
+      sc[kStop] = 1.0;
+    }
   }
 }
 
@@ -383,13 +424,23 @@ __global__ __launch_bounds__(256) void pcg_dir_kernel(int64_t P, const double* _
   const double rz_new = reduce_partials(partials, kRedBlocks, s_red);
   const double rr = reduce_partials(partials + kRedBlocks, kRedBlocks, s_red);
   const double rz = cur[kRZ], pu = cur[kPU];
-  const bool go = cur[kStop] == 0.0 && pu > 0.0 && rz > 1e-30 * cur[kRZ0];
+  const bool live = cur[kStop] == 0.0 && rz > 1e-30 * cur[kRZ0];  // not stopped, not converged
+  bool go = live && pu > 0.0;
+  // failures: p^T A p <= 0 (or not a number) before convergence, which an SPD
+  // operator cannot give (breakdown); a residual that is not finite
+  double fail = cur[kFail];
+  if (live && !(pu > 0.0 && isfinite(pu))) fail = (double)((int)fail | LMRS_FAIL_BREAKDOWN);
+  if (go && !(isfinite(rz_new) && isfinite(rr))) {
+    fail = (double)((int)fail | LMRS_FAIL_NONFINITE);
+    go = false;
+  }
   const double beta = go ? rz_new / rz : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     for (int i = 0; i < kScalars; ++i) next[i] = cur[i];
     next[kRZNew] = rz_new;
     next[kRR] = rr;
     next[kBeta] = beta;
+    next[kFail] = fail;
     if (go) {
       next[kRZ] = rz_new;
       next[kDone] = cur[kDone] + 1.0;
@@ -419,15 +470,20 @@ __global__ void pcg_report_kernel(const double* __restrict__ sc, const double* _
   report[LMRS_REP_R0] = (float)sqrt(sc[kRR0]);
   report[LMRS_REP_RN] = (float)sqrt(sc[kRR]);
   report[LMRS_REP_BX] = (float)bx[0];
+  report[LMRS_REP_STATUS] = (float)sc[kFail];
 }
 
-// max |x| over the DC colour coefficients, partial per block.
-__global__ __launch_bounds__(256) void absmax_partial_kernel(const float* __restrict__ x, int64_t n,
-                                                             double* __restrict__ partials) {
+// Partials per block of max |x| over the DC colour coefficients [dc0, dc0 + ndc)
+// and of the count of entries of x (all P) that are not finite.
+__global__ __launch_bounds__(256) void absmax_partial_kernel(const float* __restrict__ x, int64_t P, int64_t dc0,
+                                                             int64_t ndc, double* __restrict__ partials) {
   __shared__ double s_red[256];
-  double m = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    m = fmax(m, (double)fabsf(x[i]));
+  double m = 0.0, bad = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
+    const float v = x[i];
+    if (!isfinite(v)) bad += 1.0;
+    else if (i >= dc0 && i < dc0 + ndc) m = fmax(m, (double)fabsf(v));
+  }
   s_red[threadIdx.x] = m;
   __syncthreads();
   for (int d = 128; d > 0; d >>= 1) {
@@ -435,11 +491,16 @@ __global__ __launch_bounds__(256) void absmax_partial_kernel(const float* __rest
     __syncthreads();
   }
   if (threadIdx.x == 0) partials[blockIdx.x] = s_red[0];
+  const double nb = block_sum(bad, s_red);
+  if (threadIdx.x == 0) partials[kRedBlocks + blockIdx.x] = nb;
 }
 
+// eta from the partials, and the step's failure bits: the PCG's, plus
+// LMRS_FAIL_NONFINITE when x has an entry that is not finite. out[0] = eta,
+// out[1] = failure bits (the update is skipped when they are non-zero).
 __global__ __launch_bounds__(256) void lr_kernel(const double* __restrict__ partials, int count,
-                                                  lmrs_lm_params prm, double* __restrict__ eta_out,
-                                                  float* __restrict__ report) {
+                                                  lmrs_lm_params prm, const double* __restrict__ pcg_fail,
+                                                  double* __restrict__ out, float* __restrict__ report) {
   __shared__ double s_red[256];
   double m = 0.0;
   for (int i = threadIdx.x; i < count; i += 256) m = fmax(m, partials[i]);
@@ -449,20 +510,29 @@ __global__ __launch_bounds__(256) void lr_kernel(const double* __restrict__ part
     if ((int)threadIdx.x < d) s_red[threadIdx.x] = fmax(s_red[threadIdx.x], s_red[threadIdx.x + d]);
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
   m = s_red[0];
+  __syncthreads();
+  double bad = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) bad += partials[kRedBlocks + i];
+  bad = block_sum(bad, s_red);
+  if (threadIdx.x != 0) return;
+  int fail = pcg_fail ? (int)pcg_fail[0] : 0;
+  if (bad > 0.0) fail |= LMRS_FAIL_NONFINITE;
   double eta;
   if (prm.iter < prm.warm_iters) eta = prm.eta_warm;
   else eta = m > 0.0 ? fmin((double)prm.eta_cap, 1.0 / m) : (double)prm.eta_cap;
-  *eta_out = eta;
+  out[0] = eta;
+  out[1] = (double)fail;
   if (report) {
     report[LMRS_REP_ETA] = (float)eta;
     report[LMRS_REP_XDC_MAX] = (float)m;
+    report[LMRS_REP_STATUS] = (float)fail;
   }
 }
 
 __global__ __launch_bounds__(256) void lm_apply_kernel(float* __restrict__ beta, const float* __restrict__ x,
                                                        int64_t P, const double* __restrict__ eta) {
+  if (eta[1] != 0.0) return;  // a numeric failure: the parameters stay as they are
   const float e = (float)eta[0];
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256)
     beta[i] -= e * x[i];
@@ -483,6 +553,13 @@ void launch_sample_residual(const lmrs_frame* f, const FrameDims& d, const float
       f->pix, f->w);
 }
 
+void launch_sample_gaussian(const lmrs_frame* f, const FrameDims& d, const float* counts, uint64_t seed,
+                            int iter, hipStream_t s) {
+  sample_gaussian_kernel<<<(unsigned)((int64_t)d.V * d.T), 256, 0, s>>>(
+      counts, f->view_ids, d.T, d.k, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)iter,
+      f->pix, f->w);
+}
+
 void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targets, float* wr,
                      double* partials, float* report, hipStream_t s) {
   residual_kernel<<<kRedBlocks, 256, 0, s>>>(f->color, targets, f->pix, f->w, f->view_ids, d.T, d.TX,
@@ -491,8 +568,8 @@ void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targe
   if (report) report_kernel<<<1, 64, 0, s>>>(partials + 2 * kRedBlocks, report, LMRS_REP_LOSS);
 }
 
-void launch_report_count(const int64_t* count, float* dst, hipStream_t s) {
-  report_count_kernel<<<1, 64, 0, s>>>(count, dst);
+void launch_report_count(const int64_t* count, int64_t capacity, float* report, hipStream_t s) {
+  report_count_kernel<<<1, 64, 0, s>>>(count, capacity, report);
 }
 
 void launch_dot(const float* a, const float* b, int64_t n, double* partials, double* out, hipStream_t s) {
@@ -537,11 +614,13 @@ void launch_pcg_report(const float* b, int iters, int64_t P, PcgState st, float*
   pcg_report_kernel<<<1, 64, 0, s>>>(fin, fin + 10, report);
 }
 
+const double* pcg_fail_slot(int iters, PcgState st) { return st.bank(iters) + kFail; }
+
 void launch_lm_update(float* beta, const float* x, int n, int64_t P, const lmrs_lm_params& prm,
-                      double* partials, float* report, hipStream_t s) {
-  absmax_partial_kernel<<<kRedBlocks, 256, 0, s>>>(x + (int64_t)11 * n, (int64_t)3 * n, partials);
-  lr_kernel<<<1, 256, 0, s>>>(partials, kRedBlocks, prm, partials + kRedBlocks, report);
-  lm_apply_kernel<<<kRedBlocks, 256, 0, s>>>(beta, x, P, partials + kRedBlocks);
+                      const double* pcg_fail, double* partials, float* report, hipStream_t s) {
+  absmax_partial_kernel<<<kRedBlocks, 256, 0, s>>>(x, P, (int64_t)11 * n, (int64_t)3 * n, partials);
+  lr_kernel<<<1, 256, 0, s>>>(partials, kRedBlocks, prm, pcg_fail, partials + 2 * kRedBlocks, report);
+  lm_apply_kernel<<<kRedBlocks, 256, 0, s>>>(beta, x, P, partials + 2 * kRedBlocks);
 }
 
 }  // namespace lmrs

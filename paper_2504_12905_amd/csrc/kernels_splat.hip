@@ -416,8 +416,11 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
 // stops it (the first entry that would take T below t_min), here with the
 // transmittance multiplied entry by entry; a wave leaves a chunk when all
 // its pixels have stopped, the workgroup its list when all 256 have.
+// With COUNT, the kernel writes instead the number of Gaussians blended into
+// each pixel (the G_p of the contribution-weighted sampler, Supp. E eq. 17).
 constexpr int kScoreThreads = 256;
 
+template <bool COUNT>
 __global__ __launch_bounds__(kScoreThreads) void score_kernel(const float* __restrict__ rec,
                                                               const int64_t* __restrict__ tile_start,
                                                               const int32_t* __restrict__ ids, int n, int T,
@@ -429,6 +432,7 @@ __global__ __launch_bounds__(kScoreThreads) void score_kernel(const float* __res
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
   const size_t vb = (size_t)c.v * n;
   float Tr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  int blended = 0;
   bool done = false;
   float4 q0{}, q1{}, q2{};
   if (tid < c.len) {
@@ -466,10 +470,15 @@ __global__ __launch_bounds__(kScoreThreads) void score_kernel(const float* __res
           C1 += wgt * b.w;
           C2 += wgt * cb;
           Tr = Tn;
+          ++blended;
         }
       }
     }
     if (__syncthreads_and(done)) break;
+  }
+  if (COUNT) {
+    so.score[c.tile_lin * 256 + tid] = (float)blended;
+    return;
   }
   const int cam = so.view_ids ? so.view_ids[c.v] : c.v;
   const int x = (c.t % TX) * kTile + (tid & 15), y = (c.t / TX) * kTile + (tid >> 4);
@@ -1031,7 +1040,81 @@ unsigned persistent_groups(int64_t tiles, int w) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, waves / w));
 }
 
+// Walk counts of the sampled render (measurement): one wave per tile, lanes
+// own 64-entry chunks of its list up to the deepest last blended entry. An
+// entry at or before a pixel's last blended one is blended by that pixel iff
+// it passes the opacity test (the transmittance stop only ends a walk after
+// its last blended entry), so the counts need no transmittance.
+// counts: [0] sum of L*_t (max over the tile's pixels of last + 1), [1] sum
+// of C_t (entries blended by at least one of the tile's pixels), [2] blending
+// (pixel, entry) pairs, [3] (pixel, entry) pairs up to each pixel's last.
+__global__ __launch_bounds__(kWave) void walk_count_kernel(const float* __restrict__ rec,
+                                                            const int64_t* __restrict__ tile_start,
+                                                            const int32_t* __restrict__ ids,
+                                                            const uint8_t* __restrict__ pix,
+                                                            const int32_t* __restrict__ lastv, int n, int T, int TX,
+                                                            int k, lmrs_render_opts o,
+                                                            unsigned long long* __restrict__ counts) {
+  const int lane = lane_id();
+  const TileCtx c = tile_ctx(tile_start, T, TX, blockIdx.x);
+  int lmax = -1;
+  for (int j = lane; j < k; j += kWave) lmax = max(lmax, lastv[c.tile_lin * k + j]);
+  lmax = uniform(wave_max_i(lmax));
+  unsigned long long contrib = 0, act = 0, walked = 0;
+  for (int c0 = 0; c0 <= lmax; c0 += kWave) {
+    const int e = c0 + lane;
+    const bool valid = e <= lmax && e < c.len;
+    RecF r{};
+    if (valid) r = load_rec(rec, (size_t)c.v * n + ids[c.start + e]);
+    bool any = false;
+    for (int j = 0; j < k; ++j) {
+      const int lj = lastv[c.tile_lin * k + j];
+      if (lj < c0) continue;
+      float xc, yc;
+      pixel_center(pix, k, c, j, &xc, &yc);
+      const Alpha al = pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, xc, yc, o);
+      if (valid && e <= lj) {
+        ++walked;
+        if (al.inc) {
+          ++act;
+          any = true;
+        }
+      }
+    }
+    contrib += __popcll(__ballot(any));
+  }
+  // per-lane counts to lane 0 through LDS (exact in 64-bit)
+  __shared__ unsigned long long s_act[kWave], s_walk[kWave];
+  s_act[lane] = act;
+  s_walk[lane] = walked;
+  __syncthreads();
+  if (lane == 0) {
+    unsigned long long ta = 0, tw = 0;
+    for (int l = 0; l < kWave; ++l) {
+      ta += s_act[l];
+      tw += s_walk[l];
+    }
+    atomicAdd(&counts[0], (unsigned long long)(lmax + 1));
+    atomicAdd(&counts[1], contrib);
+    atomicAdd(&counts[2], ta);
+    atomicAdd(&counts[3], tw);
+  }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* __restrict__ x, int m) {
+  if ((int)threadIdx.x < m) x[threadIdx.x] = 0ull;
+}
+
 }  // namespace
+
+void launch_walk_counts(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, int64_t* counts,
+                        hipStream_t s) {
+  auto* cnt = reinterpret_cast<unsigned long long*>(counts);
+  zero_u64_kernel<<<1, kWave, 0, s>>>(cnt, 4);
+  const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
+  walk_count_kernel<<<tiles, kWave, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, f->last, d.n, d.T, d.TX, d.k, o,
+                                            cnt);
+}
 
 template <int W>
 void launch_render_w(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s) {
@@ -1061,7 +1144,14 @@ void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_re
                           const float* targets, float* scores, hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   const ScoreOut so{targets, f->view_ids, d.W, d.H, scores};
-  score_kernel<<<tiles, kScoreThreads, 0, s>>>(f->rec, f->tile_start, f->ids, d.n, d.T, d.TX, o, so);
+  score_kernel<false><<<tiles, kScoreThreads, 0, s>>>(f->rec, f->tile_start, f->ids, d.n, d.T, d.TX, o, so);
+}
+
+void launch_render_counts(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* counts,
+                          hipStream_t s) {
+  const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
+  const ScoreOut so{nullptr, f->view_ids, d.W, d.H, counts};
+  score_kernel<true><<<tiles, kScoreThreads, 0, s>>>(f->rec, f->tile_start, f->ids, d.n, d.T, d.TX, o, so);
 }
 
 template <int MODE, int W>

@@ -16,6 +16,9 @@ struct FrameDims {
 
 FrameDims dims_of(const lmrs_frame* f);
 
+// sets the calling thread's lmrs_last_error() message and returns s
+lmrs_status report_error(lmrs_status s, const char* msg);
+
 // projection side (kernels_project.hip)
 void launch_project(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, hipStream_t s);
 void launch_tangent(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* p,
@@ -59,6 +62,13 @@ void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_op
 // every pixel of the batch views: scores[V][T][256] = sum_c |C_c - I_c| against targets
 void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                           const float* targets, float* scores, hipStream_t s);
+// every pixel of the batch views: counts[V][T][256] = Gaussians blended into the pixel
+void launch_render_counts(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* counts,
+                          hipStream_t s);
+// counts[4] (int64, device): traversed entries, contributing entries, blending
+// pairs, pairs up to each pixel's last blended entry (see walk_count_kernel)
+void launch_walk_counts(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, int64_t* counts,
+                        hipStream_t s);
 // mode: 1 = J p only (writes jp), 2 = J^T u only (reads u), 3 = fused GN (J^T W J p)
 void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                   const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s);
@@ -72,10 +82,14 @@ void launch_sample_uniform(const lmrs_frame* f, const FrameDims& d, uint64_t see
                            hipStream_t s);
 void launch_sample_residual(const lmrs_frame* f, const FrameDims& d, const float* scores, uint64_t seed,
                             int iter, hipStream_t s);
+// counts: [V][T][256] Gaussians blended into each pixel (integers held in floats)
+void launch_sample_gaussian(const lmrs_frame* f, const FrameDims& d, const float* counts, uint64_t seed,
+                            int iter, hipStream_t s);
 void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targets, float* wr,
                      double* partials, float* report, hipStream_t s);
 void launch_dot(const float* a, const float* b, int64_t n, double* partials, double* out, hipStream_t s);
-void launch_report_count(const int64_t* count, float* dst, hipStream_t s);
+// report[INST] = *count; ORs LMRS_FAIL_CAPACITY into report[STATUS] when *count > capacity
+void launch_report_count(const int64_t* count, int64_t capacity, float* report, hipStream_t s);
 // PCG state in device memory
 struct PcgState {
   float *x, *r, *z, *p, *u, *minv;
@@ -89,7 +103,12 @@ void launch_pcg_init(const float* b, const float* diag, float lambda, const floa
 // partials of p^T u in st.partials: alpha, x, r, z, beta, p
 void launch_pcg_iteration(int it, int64_t P, int pu_count, PcgState st, hipStream_t s);
 void launch_pcg_report(const float* b, int iters, int64_t P, PcgState st, float* report, hipStream_t s);
+// the failure bits the PCG left after `iters` iterations (device)
+const double* pcg_fail_slot(int iters, PcgState st);
+// learning rate and update; partials: at least 2 * kRedBlocks + 2 doubles.
+// Skips the update when pcg_fail (device, may be NULL) or a non-finite entry
+// of x flags a numeric failure.
 void launch_lm_update(float* beta, const float* x, int n, int64_t P, const lmrs_lm_params& prm,
-                      double* partials, float* report, hipStream_t s);
+                      const double* pcg_fail, double* partials, float* report, hipStream_t s);
 
 }  // namespace lmrs

@@ -22,11 +22,13 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 LMRS_OK, LMRS_EINVAL, LMRS_ECAPACITY, LMRS_EWORKSPACE, LMRS_EHIP = 0, -1, -2, -3, -4
+LMRS_ENUMERIC, LMRS_EUNSUPPORTED = -5, -6
 LMRS_REC = 12
 OP_BIN, OP_JVP, OP_VJP, OP_GN, OP_DIAG, OP_PCG, OP_LM, OP_SOLVE = 1, 2, 3, 4, 5, 6, 7, 8
-REPORT_FLOATS = 8
-SAMPLER_UNIFORM, SAMPLER_RESIDUAL = 0, 1
-REP = dict(loss=0, eta=1, xdc_max=2, cg_done=3, r0=4, rn=5, bx=6, instances=7)
+REPORT_FLOATS = 12
+SAMPLER_UNIFORM, SAMPLER_RESIDUAL, SAMPLER_GAUSSIAN = 0, 1, 2
+REP = dict(loss=0, eta=1, xdc_max=2, cg_done=3, r0=4, rn=5, bx=6, instances=7, status=8)
+FAIL_NONFINITE, FAIL_BREAKDOWN, FAIL_CAPACITY = 1, 2, 4
 
 
 class LmrsError(RuntimeError):
@@ -70,7 +72,8 @@ def sched_ints(tiles: int) -> int:
 class LmParams(C.Structure):
     _fields_ = [("iter", C.c_int32), ("cg_iters", C.c_int32), ("lam", C.c_float),
                 ("eta_cap", C.c_float), ("eta_warm", C.c_float), ("warm_iters", C.c_int32),
-                ("seed", C.c_uint64), ("sampler", C.c_int32)]
+                ("seed", C.c_uint64), ("sampler", C.c_int32), ("cg_iters_late", C.c_int32),
+                ("late_iter", C.c_int32)]
 
 
 _vp, _i32, _f32, _sz = C.c_void_p, C.c_int32, C.c_float, C.c_size_t
@@ -78,6 +81,8 @@ _FP = C.POINTER(_Frame)
 _lib.lmrs_status_str.restype = C.c_char_p
 _lib.lmrs_status_str.argtypes = [_i32]
 _lib.lmrs_last_error.restype = C.c_char_p
+_lib.lmrs_report_status.restype = _i32
+_lib.lmrs_report_status.argtypes = [_vp]
 _lib.lmrs_workspace_bytes.restype = _sz
 _lib.lmrs_workspace_bytes.argtypes = [_i32, _FP]
 _lib.lmrs_project.argtypes = [_FP, _vp, _vp]
@@ -87,15 +92,23 @@ _lib.lmrs_jvp.argtypes = [_FP, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_vjp.argtypes = [_FP, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_gn_product.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_gn_product_timed.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp, _vp]
+_lib.lmrs_walk_counts.argtypes = [_FP, _vp, _vp, _vp]
 _lib.lmrs_gn_diag.argtypes = [_FP, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_pcg.argtypes = [_FP, _vp, _vp, _f32, _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_lm_step.argtypes = [_FP, _vp, _vp, _vp, C.POINTER(LmParams), _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_lm_solve.argtypes = [_FP, _vp, _vp, _vp, C.POINTER(LmParams), _vp, _vp, _vp, _sz, _vp]
+_lib.lmrs_lm_iterate.argtypes = [_FP, _vp, _vp, _vp, C.POINTER(LmParams), _vp, _vp, _vp, _sz, _vp]
+_lib.lmrs_bin_tiles_async.argtypes = [_FP, _vp, _sz, _vp]
 _lib.lmrs_residual_scores.argtypes = [_FP, _vp, _vp, _vp, _vp]
 _lib.lmrs_sample.argtypes = [_FP, _i32, C.c_uint64, _i32, _vp, _vp]
+_lib.lmrs_contributor_counts.argtypes = [_FP, _vp, _vp, _vp]
+_lib.lmrs_view_clusters.argtypes = [_vp, _i32, _i32, C.c_uint64, _vp]
+_lib.lmrs_view_batch.argtypes = [_vp, _i32, _i32, C.c_uint64, _i32, _vp]
 for _name in ("lmrs_project", "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp",
-              "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step",
-              "lmrs_residual_scores", "lmrs_sample", "lmrs_lm_solve"):
+              "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_walk_counts",
+              "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step", "lmrs_residual_scores", "lmrs_sample", "lmrs_lm_solve",
+              "lmrs_contributor_counts", "lmrs_view_clusters", "lmrs_view_batch", "lmrs_lm_iterate",
+              "lmrs_bin_tiles_async"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -275,6 +288,16 @@ def lmrs_gn_product_timed(frame: Frame, p: torch.Tensor, lam: float, d: torch.Te
     return out, [float(x) for x in ms]
 
 
+def lmrs_walk_counts(frame: Frame, opts=None, stream=None) -> torch.Tensor:
+    """int64 [4] on the device: traversed entries (sum L*_t), contributing
+    entries (sum C_t), blending pairs, pairs up to each pixel's last blend."""
+    opts = opts or default_opts()
+    out = torch.empty(4, dtype=torch.int64, device=frame.beta.device)
+    fs = frame.struct()
+    _check(_lib.lmrs_walk_counts(C.byref(fs), C.byref(opts), _ptr(out), _stream(stream)), "lmrs_walk_counts")
+    return out
+
+
 def lmrs_gn_diag(frame: Frame, out: torch.Tensor | None = None, opts=None, stream=None):
     opts = opts or default_opts()
     out = out if out is not None else torch.empty(frame.P, dtype=torch.float32, device=frame.beta.device)
@@ -309,6 +332,17 @@ def lmrs_residual_scores(frame: Frame, targets: torch.Tensor, out: torch.Tensor 
     return out
 
 
+def lmrs_contributor_counts(frame: Frame, out: torch.Tensor | None = None, opts=None, stream=None) -> torch.Tensor:
+    """[V, T, 256] number of Gaussians blended into every pixel (needs project + bin)."""
+    opts = opts or default_opts()
+    out = out if out is not None else torch.empty((frame.n_views, frame.T, 256), dtype=torch.float32,
+                                                  device=frame.beta.device)
+    fs = frame.struct()
+    _check(_lib.lmrs_contributor_counts(C.byref(fs), C.byref(opts), _ptr(out), _stream(stream)),
+           "lmrs_contributor_counts")
+    return out
+
+
 def lmrs_sample(frame: Frame, sampler: int, seed: int, iter: int, scores: torch.Tensor | None = None,
                 stream=None):
     """Fills frame.pix / frame.w (frame must be sampled)."""
@@ -338,6 +372,24 @@ def lmrs_lm_step(frame: Frame, targets: torch.Tensor, params: LmParams, d: torch
     raise LmrsError(LMRS_ECAPACITY, "lmrs_lm_step")
 
 
+def lmrs_bin_tiles_async(frame: Frame, ws: torch.Tensor, stream=None):
+    """Binning without the host wait (lists empty if frame.capacity is too small)."""
+    fs = frame.struct()
+    _check(_lib.lmrs_bin_tiles_async(C.byref(fs), _ptr(ws), ws.numel(), _stream(stream)), "lmrs_bin_tiles_async")
+
+
+def lmrs_lm_iterate(frame: Frame, targets: torch.Tensor, params: LmParams, ws: torch.Tensor,
+                    d: torch.Tensor | None = None, report: torch.Tensor | None = None, opts=None, stream=None):
+    """One LM iteration that never waits on the host (graph-capturable).
+    ws: at least lmrs_workspace_bytes(OP_LM) bytes. A tile-list count above
+    frame.capacity shows as FAIL_CAPACITY in the report."""
+    opts = opts or default_opts()
+    fs = frame.struct()
+    _check(_lib.lmrs_lm_iterate(C.byref(fs), _ptr(frame.beta), _ptr(targets), _ptr(d), C.byref(params),
+                                C.byref(opts), _ptr(report), _ptr(ws), ws.numel(), _stream(stream)),
+           "lmrs_lm_iterate")
+
+
 def lmrs_lm_solve(frame: Frame, targets: torch.Tensor, params: LmParams, ws: torch.Tensor,
                   d: torch.Tensor | None = None, report: torch.Tensor | None = None, opts=None, stream=None):
     """The LM iteration after project + bin (no host wait; graph-capturable).
@@ -349,12 +401,42 @@ def lmrs_lm_solve(frame: Frame, targets: torch.Tensor, params: LmParams, ws: tor
            "lmrs_lm_solve")
 
 
+def check_report(report: torch.Tensor, where: str = "report"):
+    """Raises LmrsError(LMRS_ENUMERIC) when a report (device or host tensor of
+    REPORT_FLOATS floats) carries numeric-failure bits (waits for the device)."""
+    host = report.detach().to("cpu", torch.float32).contiguous()
+    _check(_lib.lmrs_report_status(C.c_void_p(host.data_ptr())), where)
+
+
+def view_clusters(cams: "np.ndarray", batch: int, seed: int) -> "np.ndarray":
+    """Cluster label of every camera (host float32 [N, 16] rows), Sec. 4.3."""
+    import numpy as np
+    cams = np.ascontiguousarray(cams, dtype=np.float32)
+    labels = np.zeros(cams.shape[0], np.int32)
+    _check(_lib.lmrs_view_clusters(C.c_void_p(cams.ctypes.data), cams.shape[0], int(batch), int(seed),
+                                   C.c_void_p(labels.ctypes.data)), "lmrs_view_clusters")
+    return labels
+
+
+def view_batch(labels: "np.ndarray", batch: int, seed: int, iter: int) -> "np.ndarray":
+    """One camera per cluster for LM iteration `iter` (int32 [batch])."""
+    import numpy as np
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    ids = np.zeros(int(batch), np.int32)
+    _check(_lib.lmrs_view_batch(C.c_void_p(labels.ctypes.data), labels.size, int(batch), int(seed), int(iter),
+                                C.c_void_p(ids.ctypes.data)), "lmrs_view_batch")
+    return ids
+
+
 def lm_params(iter: int, cg_iters: int, lam: float, seed: int = 0, eta_cap: float = 0.2,
-              eta_warm: float = 0.05, warm_iters: int = 10, sampler: int = SAMPLER_UNIFORM) -> LmParams:
+              eta_warm: float = 0.05, warm_iters: int = 10, sampler: int = SAMPLER_UNIFORM,
+              cg_iters_late: int = 0, late_iter: int = 0) -> LmParams:
     return LmParams(int(iter), int(cg_iters), float(lam), float(eta_cap), float(eta_warm), int(warm_iters),
-                    int(seed), int(sampler))
+                    int(seed), int(sampler), int(cg_iters_late), int(late_iter))
 
 
-EXPORTS = ("lmrs_status_str", "lmrs_last_error", "lmrs_workspace_bytes", "lmrs_project", "lmrs_bin_tiles",
-           "lmrs_render", "lmrs_jvp", "lmrs_vjp", "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_diag",
-           "lmrs_pcg", "lmrs_lm_step", "lmrs_residual_scores", "lmrs_sample", "lmrs_lm_solve")
+EXPORTS = ("lmrs_status_str", "lmrs_last_error", "lmrs_report_status", "lmrs_workspace_bytes", "lmrs_project",
+           "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp", "lmrs_gn_product",
+           "lmrs_gn_product_timed", "lmrs_walk_counts", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step",
+           "lmrs_residual_scores", "lmrs_contributor_counts", "lmrs_sample", "lmrs_lm_solve",
+           "lmrs_view_clusters", "lmrs_view_batch", "lmrs_lm_iterate", "lmrs_bin_tiles_async")

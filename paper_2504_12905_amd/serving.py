@@ -15,17 +15,23 @@ iteration (weights 1), damping lambda.
 * an admitted fit keeps its parameters, lists, CG state and targets in device
   memory until it retires, and runs on its own HIP stream (default
   priority), so the kernels of different fits overlap on the device;
-* one LM iteration of a fit = lmrs_project + lmrs_bin_tiles (the host waits
-  for that fit's list size only) + lmrs_lm_solve. The solve (render,
-  residuals, b, preconditioner, the PCG loop's GN products and vector
-  recurrences, learning rate, update: about a hundred launches) is captured
-  once per learning-rate branch into a HIP graph and replayed;
-* the scheduler gives each resident fit one LM iteration per round, admits
-  arrived requests as slots and memory free up, and retires finished fits
-  (final PSNR over all views at full resolution).
+* one LM iteration of a fit is one lmrs_lm_iterate call (projection, binning
+  into an id buffer sized from the host bound, sampling, render, residuals,
+  b, preconditioner, the PCG loop's GN products and vector recurrences,
+  learning rate, update: about a hundred launches), which never waits on the
+  host. It is captured once per learning-rate branch into a HIP graph and
+  replayed; the whole iteration budget of a fit is enqueued at admission, so
+  the host only admits and retires;
+* a fit retires when its last iteration's event has completed: final PSNR
+  over all views at full resolution, and its status: "ok", or "numeric" /
+  "capacity" when any iteration flagged a numeric failure or an overflow of
+  its list buffer (the failure bits of every iteration are OR-ed on the
+  device). A failed fit does not disturb the others: every buffer it touches
+  is its own.
 
 `run_sequential` is the plain baseline: the same requests one at a time in
-arrival order, eager lmrs_lm_step calls on one stream, no graphs.
+arrival order, eager lmrs_lm_step calls on one stream (which wait for each
+iteration's tile-list count), no graphs.
 """
 from __future__ import annotations
 
@@ -129,7 +135,7 @@ def footprint_bytes(req: FitRequest, instances: int) -> int:
     frame = (V * n * (4 * L.LMRS_REC + 16) + 8 * (V * T + 1) + 4 * cap + S * (12 + 4 + 4)
              + 4 * L.sched_ints(V * T))
     ws = max(_frame_struct_bytes(L.OP_BIN, n, req.sh_degree, V, W, W, 256, cap),
-             _frame_struct_bytes(L.OP_SOLVE, n, req.sh_degree, V, W, W, 256, cap))
+             _frame_struct_bytes(L.OP_LM, n, req.sh_degree, V, W, W, 256, cap))
     return 4 * P + 16 * V * 4 + 12 * V * W * W + frame + ws + 64 * 4
 
 
@@ -155,7 +161,7 @@ def _image_index(fr: L.Frame, dev) -> torch.Tensor:
 class _Fit:
     """Device state of one resident fit."""
 
-    def __init__(self, prob: Problem, stream: torch.cuda.Stream, use_graphs: bool, dev, ws_op: int = L.OP_SOLVE):
+    def __init__(self, prob: Problem, stream: torch.cuda.Stream, use_graphs: bool, dev, ws_op: int = L.OP_LM):
         req = prob.req
         self.prob, self.req, self.stream, self.use_graphs = prob, req, stream, use_graphs
         self.it = 0
@@ -169,6 +175,7 @@ class _Fit:
             nbytes = max(L.workspace_bytes(L.OP_BIN, self.fr), L.workspace_bytes(ws_op, self.fr))
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
             self.rep = torch.zeros(L.REPORT_FLOATS, device=dev)
+            self.fail = torch.zeros(1, dtype=torch.int32, device=dev)   # failure bits of every iteration, OR-ed
             self.idx = _image_index(self.fr, dev)
             # targets: the ground truth rendered at every pixel
             self.targets = torch.empty((req.n_views, req.res, req.res, 3), dtype=torch.float32, device=dev)
@@ -185,25 +192,23 @@ class _Fit:
     def params(self) -> L.LmParams:
         return L.lm_params(self.it, self.req.cg_iters, self.req.lam)
 
+    def _iterate(self):
+        L.lmrs_lm_iterate(self.fr, self.targets, self.params(), self.ws, report=self.rep, stream=self.stream)
+        self.fail.bitwise_or_(self.rep[L.REP["status"]:L.REP["status"] + 1].to(torch.int32))
+
     def step(self):
-        """Enqueue one LM iteration on the fit's stream."""
+        """Enqueue one LM iteration on the fit's stream (never waits on the host)."""
         req = self.req
         with torch.cuda.stream(self.stream):
-            ids_before = self.fr.ids.data_ptr()
-            L.lmrs_project(self.fr, stream=self.stream)
-            L.lmrs_bin_tiles(self.fr, stream=self.stream, ws=self.ws)
-            if self.fr.ids.data_ptr() != ids_before:
-                self.graphs.clear()            # the id buffer moved: captured pointers are stale
             warm = self.it < 10
-            if not self.use_graphs or self.it == 0:
-                L.lmrs_lm_solve(self.fr, self.targets, self.params(), self.ws, report=self.rep, stream=self.stream)
+            if not self.use_graphs:
+                self._iterate()
             else:
                 g = self.graphs.get(warm)
                 if g is None:
                     g = torch.cuda.CUDAGraph()
                     with torch.cuda.graph(g, stream=self.stream):
-                        L.lmrs_lm_solve(self.fr, self.targets, self.params(), self.ws, report=self.rep,
-                                        stream=self.stream)
+                        self._iterate()
                     self.graphs[warm] = g
                 g.replay()
             self.it += 1
@@ -214,6 +219,12 @@ class _Fit:
     def finished(self) -> bool:
         return self.done_event is not None and self.done_event.query()
 
+    def status(self) -> str:
+        bits = int(self.fail.item())
+        if bits & L.FAIL_CAPACITY:
+            return "capacity"
+        return "numeric" if bits else "ok"
+
     def finalize(self) -> tuple[np.ndarray, float]:
         """Final PSNR over every pixel of every view, and the parameters."""
         with torch.cuda.stream(self.stream):
@@ -222,6 +233,8 @@ class _Fit:
             mse = float(((img - self.targets) ** 2).mean().item())
             beta = self.beta.cpu().numpy()
         self.graphs.clear()
+        if not math.isfinite(mse):
+            return beta, float("nan")
         return beta, (10.0 * math.log10(1.0 / mse) if mse > 0 else float("inf"))
 
 
@@ -272,8 +285,9 @@ class Server:
                 if pending:
                     time.sleep(max(0.0, min(0.01, pending[0].req.arrival_t - (time.perf_counter() - t0))))
                 continue
+            # the whole iteration budget of each newly admitted fit is enqueued at once
             for fit, _, _ in active:
-                if fit.it < fit.req.lm_iters:
+                while fit.it < fit.req.lm_iters:
                     fit.step()
             still = []
             for fit, si, start in active:
@@ -281,13 +295,15 @@ class Server:
                     beta, psnr = fit.finalize()
                     end = time.perf_counter() - t0
                     req = fit.req
-                    self._results[req.id] = FitResult(beta, psnr, end - req.arrival_t, "ok", start, end)
+                    self._results[req.id] = FitResult(beta, psnr, end - req.arrival_t, fit.status(), start, end)
                     used -= fit.prob.footprint
                     free_streams.append(si)
                     self.log.append(("retire", req.id, end, used))
                     del fit
                 else:
                     still.append((fit, si, start))
+            if len(still) == len(active) and not (pending and pending[0].req.arrival_t <= now and free_streams):
+                time.sleep(2e-4)   # nothing to admit or retire yet
             active = still
         return self._results
 
@@ -310,9 +326,10 @@ def run_sequential(problems: list[Problem], device: str = "cuda:0") -> dict[int,
         for it in range(req.lm_iters):
             L.lmrs_lm_step(fit.fr, fit.targets, L.lm_params(it, req.cg_iters, req.lam), report=fit.rep,
                            ws=fit.ws, stream=stream)
+            fit.fail.bitwise_or_(fit.rep[L.REP["status"]:L.REP["status"] + 1].to(torch.int32))
         beta, psnr = fit.finalize()
         end = time.perf_counter() - t0
-        out[req.id] = FitResult(beta, psnr, end - req.arrival_t, "ok", start, end)
+        out[req.id] = FitResult(beta, psnr, end - req.arrival_t, fit.status(), start, end)
         del fit
     return out
 

@@ -54,8 +54,8 @@ def test_workspace_sizes(M):
     assert M._lib.lmrs_workspace_bytes(M.OP_GN, None) == 0
 
 
-@pytest.mark.parametrize("bad", [dict(n=0), dict(sh_degree=4), dict(width=100), dict(n_views=0),
-                                 dict(k=0), dict(k=300), dict(width=2064, height=2048)])
+@pytest.mark.parametrize("bad", [dict(n=0), dict(sh_degree=-1), dict(width=100), dict(n_views=0),
+                                 dict(k=0), dict(k=300)])
 def test_invalid_frames_rejected_on_host(M, bad):
     f = frame(M, **bad)
     f.beta = 1  # never dereferenced: validation fails first
@@ -63,6 +63,30 @@ def test_invalid_frames_rejected_on_host(M, bad):
     st = M._lib.lmrs_render(C.byref(f), C.byref(opts), None)
     assert st == M.LMRS_EINVAL
     assert M._lib.lmrs_last_error()
+
+
+@pytest.mark.parametrize("big", [dict(sh_degree=4), dict(width=2064, height=2048)])
+def test_unsupported_frames_rejected_on_host(M, big):
+    """Well-formed but beyond what the library builds: SH degree 4, a view of
+    more than 16384 tiles."""
+    f = frame(M, **big)
+    f.beta = 1
+    st = M._lib.lmrs_render(C.byref(f), C.byref(M.default_opts()), None)
+    assert st == M.LMRS_EUNSUPPORTED
+    assert M._lib.lmrs_status_str(st) == b"not supported by this library"
+
+
+def test_report_status(M):
+    """lmrs_report_status reads the failure bits of a host copy of a report."""
+    rep = (C.c_float * M.REPORT_FLOATS)()
+    assert M._lib.lmrs_report_status(rep) == M.LMRS_OK
+    rep[M.REP["status"]] = float(M.FAIL_BREAKDOWN)
+    assert M._lib.lmrs_report_status(rep) == M.LMRS_ENUMERIC
+    assert b"breakdown" in M._lib.lmrs_last_error()
+    rep[M.REP["status"]] = float(M.FAIL_NONFINITE)
+    assert M._lib.lmrs_report_status(rep) == M.LMRS_ENUMERIC
+    assert b"non-finite" in M._lib.lmrs_last_error()
+    assert M._lib.lmrs_report_status(None) == M.LMRS_EINVAL
 
 
 def test_missing_buffers_and_small_workspace_rejected(M):

@@ -173,3 +173,88 @@ def test_config3_full_size():
     e_j = rel(to_samples(np_(jp), orc)[on], orc.jvp(np_(p).astype(np.float64))[on])
     log(f"  config3 forward rel {e_f:.2e}, forward-mode rel {e_j:.2e} on {mask.sum()} tiles")
     assert e_f < 1e-4 and e_j < 1e-4
+
+
+def _tile_subset(w, beta, views, tiles_per_view, seed):
+    """A tile mask of `tiles_per_view` busy tiles in each of the views."""
+    full = Oracle(w.n, w.sh_degree, beta, w.cams[views], w.width, w.height)
+    ts, _ = full.lists()
+    rng = np.random.default_rng(seed)
+    mask = np.zeros(full.V * full.T, np.uint8)
+    for v in range(full.V):
+        busy = v * full.T + np.flatnonzero(np.diff(ts[v * full.T:(v + 1) * full.T + 1]) > 0)
+        mask[rng.choice(busy, tiles_per_view, replace=False)] = 1
+    return mask
+
+
+def _tile_oracle(w, beta, views, mask):
+    """The oracle on the masked tiles only (lists built there, renders there)."""
+    o = Oracle(w.n, w.sh_degree, beta, w.cams[views], w.width, w.height, only_tiles=mask)
+    o.set_samples(256)
+    o.set_tile_mask(mask)
+    return o
+
+
+def test_config3_256_fd_directions():
+    """Config 3 as specified: 200k Gaussians, SH 3, 16 views at 512x512,
+    lmrs_render behind torch.autograd. For 256 directions p_k = g/||g||
+    (g ~ N(0, I), seed 3) the GPU's forward-mode J p_k and the gradient
+    <grad L, p_k> of L = 1/2 |r|^2 (r against seeded noise targets) are compared
+    with central differences of the FP64 oracle (h = 1e-3) on 4,096 pixels per
+    view of 4 views (16 busy tiles each, seed 4), the oracle building only
+    those tiles' lists; pixels whose decisions differ at
+    beta +- h p or lie within 1e-4 of a threshold are left out (reported)."""
+    from paper_2504_12905_amd.autograd import LmrsRender
+    w = synth.config3()
+    W = w.width
+    views = [0, 5, 10, 15]
+    mask = _tile_subset(w, w.beta_init, views, 16, 4)
+    orc = _tile_oracle(w, w.beta_init, views, mask)
+    log(f"  oracle on {int(mask.sum())} tiles of {len(views)} views")
+    vo, xo, yo = orc.pixel_coords()
+    on = np.repeat(mask.astype(bool), 256)
+    # flat indices of the oracle's sampled pixels in the GPU image [16, H, W, 3]
+    gidx = torch.tensor(((np.asarray(views)[vo] * W + yo) * W + xo)[on], device=DEV)
+    target = np.random.default_rng(16).uniform(0, 1, size=(16, W, W, 3)).astype(np.float32)
+    tgt_on = target.reshape(-1, 3)[gidx.cpu().numpy()]
+    gviews = views_of(w.cams, W, W)
+    b = torch.tensor(w.beta_init, device=DEV)
+    base = orc.render()
+    ok = orc.decided()[on]
+    r_on = base["C"][on] - tgt_on
+    # GPU gradient of L = 1/2 sum over the subset pixels of |r|^2 (u = r there, 0 elsewhere)
+    bg = b.clone().requires_grad_(True)
+    img = LmrsRender.apply(bg, w.n, w.sh_degree, gviews)
+    u = torch.zeros_like(img).view(-1, 3)
+    u[gidx] = img.detach().view(-1, 3)[gidx] - torch.tensor(tgt_on, device=DEV)
+    (grad,) = torch.autograd.grad(img, bg, u.view(img.shape))
+    grad = grad.double()
+    h = 1e-3
+    rng = np.random.default_rng(3)
+    worst_j, worst_g, excl = 0.0, 0.0, []
+    for k in range(256):
+        g = rng.normal(size=b.numel())
+        p = g / np.linalg.norm(g)
+        pt = torch.tensor(p.astype(np.float32), device=DEV)
+        jp = gpu_jvp(b, pt, w.n, w.sh_degree, gviews).view(-1, 3)[gidx].cpu().numpy().astype(np.float64)
+        outs = []
+        for s in (1.0, -1.0):
+            outs.append(_tile_oracle(w, w.beta_init.astype(np.float64) + s * h * p, views, mask).render())
+        same = ((outs[0]["trace"] == base["trace"]) & (outs[1]["trace"] == base["trace"]))[on] & ok
+        excl.append(1.0 - same.mean())
+        fd = ((outs[0]["C"] - outs[1]["C"]) / (2 * h))[on]
+        worst_j = max(worst_j, rel(jp[same], fd[same]))
+        # <grad L, p> against the central difference of L over the pixels kept
+        Lp = 0.5 * (((outs[0]["C"][on] - tgt_on)[same]) ** 2).sum()
+        Lm = 0.5 * (((outs[1]["C"][on] - tgt_on)[same]) ** 2).sum()
+        gl_fd = (Lp - Lm) / (2 * h)
+        gl = float((jp[same] * r_on[same]).sum())     # <J p, r> over the same pixels
+        worst_g = max(worst_g, abs(gl - gl_fd) / max(abs(gl_fd), 1e-12))
+    # the adjoint side: <grad L, p> from the backward pass equals <J p, r> over all subset pixels
+    g_last = float((grad * torch.tensor(p, device=DEV)).sum())
+    jp_all = float((jp * r_on).sum())
+    log(f"  256 FD directions: worst J p rel {worst_j:.2e}, worst <grad L, p> rel {worst_g:.2e}, "
+        f"excluded {np.mean(excl):.4%}; backward <grad L,p> {g_last:.6e} vs <J p, r> {jp_all:.6e}")
+    assert np.mean(excl) < 0.05
+    assert worst_j < 1e-4 and worst_g < 1e-4
+    assert abs(g_last - jp_all) <= 1e-4 * abs(jp_all)

@@ -5,7 +5,7 @@ SH degree 3, 1264x832 images (4,108 tiles), residual-weighted sampling with
 oracle's lists (~1.6e8 entries) and renders within tens of seconds.
 
 Targets are seeded uniform-noise images (not renders by the HIP path). Checked:
-every tile list (bit-exact up to radius-margin exceptions), the residual
+every tile list (bit-exact: FP64 list decisions on both sides), the residual
 magnitudes of every pixel, the draws (identical except within 1e-5 of an
 interval end), then with the oracle's draws loaded into the GPU frame: the
 sampled render, J p on decided pixels and the GN product on a sample of
@@ -46,8 +46,8 @@ def test_cfg2_lists(big):
     gts, gids = lists_of(fr)
     ots, oids = orc.lists()
     ex = compare_lists(gts, gids, ots, oids, orc.projection()["margin"], orc.T)
-    log(f"  {oids.size} list entries, {ex} radius-margin exceptions")
-    assert ex <= 1e-5 * oids.size
+    log(f"  {oids.size} list entries, {ex} exceptions")
+    assert ex == 0
 
 
 def test_cfg2_residual_sampling_and_operators(big):
@@ -91,7 +91,7 @@ def test_cfg2_residual_sampling_and_operators(big):
     # everywhere and one stop decision taken the other way at a threshold
     # pixel outweighs all the rounding: T is compared on decided pixels
     assert eC < 1e-4 and eCd < 1e-4 and eTd < 1e-4
-    assert ej < 1e-4 and ok.mean() > 0.8
+    assert ej < 1e-4 and ok.mean() > 0.95
     gn = np_(L.lmrs_gn_product(fr, pt, w.lam))
     vis = orc.projection()["visible"].any(axis=0)
     sel = np.sort(np.random.default_rng(2).choice(np.flatnonzero(vis), 48, replace=False))

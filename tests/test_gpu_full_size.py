@@ -4,13 +4,14 @@ Gaussians, SH degree 3, 8 of 64 views at 800x800, 26 samples per 16x16 tile
 
 Compared with the FP64 oracle: every tile list (bit-exact), every sampled
 pixel's colour and transmittance, J p at every sampled pixel, and the GN
-product / J^T u on a sample of Gaussians (the oracle restricted to the tiles
-that list them, which leaves those Gaussians' outputs exact)."""
+product, J^T u and diag(J^T W J) on all 5.9 M parameters, each norm-wise
+(bar 1e-4) and element-wise (max |a - b| / (|b| + 1e-3 max|b|), logged and
+bounded)."""
 import numpy as np
 import pytest
 import torch
 
-from gpu_util import DEV, compare_lists, lib, lists_of, log, np_, rel
+from gpu_util import DEV, compare_lists, elem, lib, lists_of, log, np_, rel
 from oracle import Oracle
 from oracle.sampling import sample_uniform
 from paper_2504_12905_amd import synth
@@ -40,18 +41,15 @@ def full():
 
 
 def test_full_size_lists(full):
-    """Bit-exact lists except where the footprint radius ceil(3 sqrt(lambda_max))
-    is not decided by FP32 arithmetic: compare_lists asserts that every
-    mismatched Gaussian has its FP64 3 sqrt(lambda_max) within 1e-4 of an
-    integer (the FP32 evaluation error is ~3e-5 px at these radii), and the
-    common members keep their order. At 800k (view, Gaussian) pairs a handful
-    of such radii occur; their count is reported and bounded."""
+    """Bit-exact lists: membership and depth order are FP64 decisions on both
+    sides, and no decision of this workload lies within 1e-9 of its threshold
+    (the closest is ~5e-7 px), so there is no exception."""
     w, fr, orc = full
     gts, gids = lists_of(fr)
     ots, oids = orc.lists()
     ex = compare_lists(gts, gids, ots, oids, orc.projection()["margin"], orc.T)
-    log(f"  {oids.size} list entries, {ex} radius-margin exceptions")
-    assert ex <= 1e-5 * oids.size
+    log(f"  {oids.size} list entries, {ex} exceptions")
+    assert ex == 0
 
 
 def test_full_size_render(full):
@@ -69,51 +67,45 @@ def test_full_size_jvp(full):
     p = np.random.default_rng(1).normal(size=orc.P).astype(np.float32)
     jp = np_(lib().lmrs_jvp(fr, torch.tensor(p, device=DEV)))
     ok = orc.decided()
-    e = rel(jp[ok], orc.jvp(p)[ok])
-    log(f"  jvp rel {e:.2e} on decided pixels ({1 - ok.mean():.4%} excluded)")
-    assert e < 1e-4 and ok.mean() > 0.97
+    ref = orc.jvp(p)
+    e, m = rel(jp[ok], ref[ok]), elem(jp[ok], ref[ok])
+    log(f"  jvp rel {e:.2e}, elementwise {m:.2e} on decided pixels ({1 - ok.mean():.4%} excluded)")
+    assert e < 1e-4 and ok.mean() > 0.99
 
 
-def _sampled_gaussians(orc, count, seed):
-    vis = orc.projection()["visible"].any(axis=0)
-    return np.sort(np.random.default_rng(seed).choice(np.flatnonzero(vis), count, replace=False))
+# Element-wise bar of the full-vector comparisons. The FP32 sums over pixels
+# carry errors of ~1e-6 of the summed magnitudes; an entry much smaller than
+# its summands (cancellation) is measured against 1e-3 of the largest entry.
+ELEM = 1e-3
 
 
-def _mask_for(orc, sel):
-    ts, ids = orc.lists()
-    hit = np.isin(ids, sel)
-    tile_of = np.repeat(np.arange(orc.V * orc.T), np.diff(ts))
-    mask = np.zeros(orc.V * orc.T, np.uint8)
-    mask[np.unique(tile_of[hit])] = 1
-    return mask
-
-
-def test_full_size_gn_product_sampled_gaussians(full):
+def test_full_size_gn_product_full_vector(full):
     w, fr, orc = full
-    sel = _sampled_gaussians(orc, 48, 2)
-    p = np.random.default_rng(3).normal(size=orc.P).astype(np.float32)
+    p = np.random.default_rng(7).normal(size=orc.P).astype(np.float32)
     out = np_(lib().lmrs_gn_product(fr, torch.tensor(p, device=DEV), w.lam))
-    orc.set_tile_mask(_mask_for(orc, sel))
     ref = orc.gn(p, w.lam)
-    orc.set_tile_mask(None)
-    idx = (np.arange(orc.Pg)[:, None] * orc.n + sel[None, :]).reshape(-1)
-    e = rel(out[idx], ref[idx])
-    log(f"  gn rel on {sel.size} Gaussians x {orc.Pg} params: {e:.2e}")
-    assert e < 1e-4
+    e, m = rel(out, ref), elem(out, ref)
+    log(f"  gn full vector ({orc.P} entries): rel {e:.2e}, elementwise {m:.2e}")
+    assert e < 1e-4 and m < ELEM
 
 
-def test_full_size_vjp_sampled_gaussians(full):
+def test_full_size_vjp_full_vector(full):
     w, fr, orc = full
-    sel = _sampled_gaussians(orc, 48, 4)
-    u = np.random.default_rng(5).normal(size=(orc.S, 3)).astype(np.float32)
+    u = np.random.default_rng(8).normal(size=(orc.S, 3)).astype(np.float32)
     out = np_(lib().lmrs_vjp(fr, torch.tensor(u, device=DEV)))
-    orc.set_tile_mask(_mask_for(orc, sel))
     ref = orc.vjp(u)
-    orc.set_tile_mask(None)
-    idx = (np.arange(orc.Pg)[:, None] * orc.n + sel[None, :]).reshape(-1)
-    e = rel(out[idx], ref[idx])
-    log(f"  vjp rel on {sel.size} Gaussians: {e:.2e}")
-    assert e < 1e-4
+    e, m = rel(out, ref), elem(out, ref)
+    log(f"  J^T u full vector: rel {e:.2e}, elementwise {m:.2e}")
+    assert e < 1e-4 and m < ELEM
+
+
+def test_full_size_diag_full_vector(full):
+    w, fr, orc = full
+    out = np_(lib().lmrs_gn_diag(fr))
+    ref = orc.diag()
+    e, m = rel(out, ref), elem(out, ref)
+    log(f"  diag(J^T W J) full vector: rel {e:.2e}, elementwise {m:.2e}")
+    assert e < 1e-4 and m < ELEM
 
 
 def test_full_size_adjoint_identity(full):

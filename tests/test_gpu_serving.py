@@ -60,11 +60,10 @@ def test_graph_replays_match_eager_steps():
 def test_same_alone_and_in_the_mix():
     """Six probe requests fitted alone (sequential plain solver) and inside a
     served mix of twelve concurrent fits give the same final PSNR (0.01 dB)
-    and parameters. The GN products accumulate with float atomics, whose
-    order changes the last bits of every step from run to run, alone as well;
-    so the parameters must agree within 1e-3 relative after 6 LM iterations
-    or within twice the spread of two alone runs, whichever is larger
-    (measured: both spreads below 1e-6 at lambda 0.1)."""
+    and parameters within 1e-4 relative. The GN products accumulate with float
+    atomics, whose order changes the last bits of every step from run to run,
+    alone as well (two alone runs differ by < 1e-6 after 6 LM iterations at
+    lambda 0.1), so the bar cannot be bitwise."""
     S = serving()
     probes = small_requests(range(6), lm_iters=6)
     others = small_requests(range(6, 12), lm_iters=6)
@@ -88,8 +87,39 @@ def test_same_alone_and_in_the_mix():
         e = rel(b.beta, a.beta)
         log(f"  request {r.id} (n={r.n}, SH {r.sh_degree}, {r.n_views} views {r.res}^2): beta rel {e:.2e}, "
             f"PSNR {a.final_psnr:.4f} / {b.final_psnr:.4f} dB")
-        assert e <= max(1e-3, 2 * spread)
+        assert e <= max(1e-4, 2 * spread)
         assert abs(a.final_psnr - b.final_psnr) <= 0.01
+        assert a.status == b.status == "ok"
+
+
+def test_failed_fit_is_isolated():
+    """A request whose initial colours hold NaN retires with status "numeric"
+    and its parameters untouched, while the three fits served beside it end
+    as they do alone (parameters within 1e-4, PSNR within 0.01 dB)."""
+    S = serving()
+    reqs = small_requests(range(40, 44), lm_iters=5)
+    probs = [S.make_problem(r) for r in reqs]
+    bad = probs[1]
+    n = bad.req.n
+    bad.beta_init = bad.beta_init.copy()
+    bad.beta_init[11 * n: 11 * n + n // 2] = np.nan      # DC red of half the Gaussians
+    good = [p for p in probs if p is not bad]
+    alone = S.run_sequential([S.make_problem(p.req) for p in good])
+    srv = S.Server(hbm_budget_bytes=64 << 30, max_slots=4)
+    for p in probs:
+        srv.submit(p.req, p)
+    got = srv.run_until_idle()
+    log(f"  statuses: {[got[p.req.id].status for p in probs]}")
+    assert got[bad.req.id].status == "numeric"
+    b = got[bad.req.id].beta
+    assert np.array_equal(np.isnan(b), np.isnan(bad.beta_init))
+    ok = ~np.isnan(bad.beta_init)
+    assert np.array_equal(b[ok], bad.beta_init[ok].astype(np.float32))
+    for p in good:
+        a, g = alone[p.req.id], got[p.req.id]
+        assert g.status == "ok"
+        assert rel(g.beta, a.beta) <= 1e-4
+        assert abs(a.final_psnr - g.final_psnr) <= 0.01
 
 
 def test_admission_respects_budget_and_slots():

@@ -169,3 +169,19 @@ def test_undecided_tiles_cover_a_radius_at_an_integer():
         ok = orc.decided(tau_list=1e-4).reshape(-1, 256)
         assert np.array_equal(~ok.all(axis=1), flags.reshape(-1).astype(bool)) or not expect
         assert not orc.undecided_tiles().any()
+
+
+def test_only_tiles_setup_keeps_those_lists_and_renders():
+    """An oracle that builds the lists of some tiles only has exactly the full
+    oracle's lists and render there (and empty lists elsewhere)."""
+    w = synth.config0()
+    full = Oracle(w.n, 0, w.beta_init, w.cams, w.width, w.height)
+    mask = (np.arange(full.V * full.T) % 3 == 1).astype(np.uint8)
+    part = Oracle(w.n, 0, w.beta_init, w.cams, w.width, w.height, only_tiles=mask)
+    ts_f, ids_f = full.lists()
+    ts_p, ids_p = part.lists()
+    for t in range(full.V * full.T):
+        got = ids_p[ts_p[t]:ts_p[t + 1]]
+        assert list(got) == (list(ids_f[ts_f[t]:ts_f[t + 1]]) if mask[t] else [])
+    on = np.repeat(mask.astype(bool), 256)
+    assert np.array_equal(part.render()["C"][on], full.render()["C"][on])
