@@ -64,6 +64,7 @@ def lib():
         L.or_undecided_tiles.argtypes = [vp, dbl, vp]
         L.or_set_samples.argtypes = [vp, i32, vp, vp]
         L.or_set_tile_mask.argtypes = [vp, vp]
+        L.or_set_channel_weights.argtypes = [vp, vp]
         L.or_render.argtypes = [vp] * 7
         L.or_jvp.argtypes = [vp, vp, vp]
         L.or_vjp.argtypes = [vp, vp, vp]
@@ -158,6 +159,14 @@ class Oracle:
         if self.w is not None:
             assert self.w.size == self.V * self.T * self.k
         lib().or_set_samples(self.h, self.k, _p(self.pix), _p(self.w))
+        self._wc = None
+
+    def set_channel_weights(self, wc: np.ndarray | None):
+        """Per-channel weights [S, 3] of the GN operator (None: the sample weights)."""
+        self._wc = None if wc is None else np.ascontiguousarray(wc, dtype=np.float64).reshape(-1)
+        if self._wc is not None:
+            assert self._wc.size == 3 * self.S
+        lib().or_set_channel_weights(self.h, _p(self._wc))
 
     def set_tile_mask(self, mask: np.ndarray | None):
         self._mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)

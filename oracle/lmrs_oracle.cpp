@@ -317,6 +317,9 @@ struct Problem {
     *py = (t / TX) * kTile + (p / kTile);
   }
   double weight_of(int64_t i) const { return w.empty() ? 1.0 : w[(size_t)i]; }
+  // per-channel weights of the GN operator (empty: weight_of for every channel)
+  std::vector<double> wc;        // [V*T*k*3]
+  double op_weight_of(int64_t i, int c) const { return wc.empty() ? weight_of(i) : wc[(size_t)i * 3 + c]; }
 };
 
 // Tile index floor(q / 16), clamped before the int conversion (a centre far
@@ -749,6 +752,13 @@ void or_set_samples(void* h, int k, const uint8_t* pix, const float* w) {
   const size_t cnt = (size_t)pb.V * pb.T * k;
   if (pix) pb.pix.assign(pix, pix + cnt); else pb.pix.clear();
   if (w) { pb.w.resize(cnt); for (size_t i = 0; i < cnt; ++i) pb.w[i] = w[i]; } else pb.w.clear();
+  pb.wc.clear();
+}
+
+// Per-channel weights [S*3] of the GN operator (NULL: the sample weights).
+void or_set_channel_weights(void* h, const double* wc) {
+  Problem& pb = *static_cast<Problem*>(h);
+  if (wc) pb.wc.assign(wc, wc + (size_t)pb.S() * 3); else pb.wc.clear();
 }
 
 void or_set_tile_mask(void* h, const uint8_t* mask) {
@@ -792,7 +802,7 @@ void or_gn(void* h, const double* p, double lam, const double* d, double* out) {
   std::vector<double> jp((size_t)S * 3, 0.0);
   or_jvp(h, p, jp.data());
   for (int64_t i = 0; i < S; ++i)
-    for (int c = 0; c < 3; ++c) jp[3 * i + c] *= pb.weight_of(i);
+    for (int c = 0; c < 3; ++c) jp[3 * i + c] *= pb.op_weight_of(i, c);
   or_vjp(h, jp.data(), out);
   const size_t P = (size_t)pb.n * pb.Pg;
   for (size_t j = 0; j < P; ++j) out[j] += lam * (d ? d[j] : 1.0) * p[j];
