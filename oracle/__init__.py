@@ -69,6 +69,7 @@ def lib():
         L.or_jvp.argtypes = [vp, vp, vp]
         L.or_vjp.argtypes = [vp, vp, vp]
         L.or_vjp_screen.argtypes = [vp, vp, vp]
+        L.or_vjp_abs.argtypes = [vp, vp, vp]
         L.or_gn.argtypes = [vp, vp, dbl, vp, vp]
         L.or_diag.argtypes = [vp, vp]
         L.or_proj_jacobian.argtypes = [vp, i32, i32, vp]
@@ -244,6 +245,17 @@ class Oracle:
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.S, 3)
         out = np.zeros(self.P)
         lib().or_vjp(self.h, _p(u), _p(out))
+        return out
+
+    def vjp_abs(self, u: np.ndarray) -> np.ndarray:
+        """Entry-wise magnitude of the terms J^T u is summed from: per
+        parameter, sum over views and record components of |d rec / d beta|
+        times the sum over pixels and channels of |u_c| |d C_c / d rec|.
+        It bounds |J^T u| and |J|^T |u| from above; tests divide entry-wise
+        differences by it (a scale for rounding, not part of the method)."""
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.S, 3)
+        out = np.zeros(self.P)
+        lib().or_vjp_abs(self.h, _p(u), _p(out))
         return out
 
     def vjp_screen(self, u: np.ndarray) -> np.ndarray:

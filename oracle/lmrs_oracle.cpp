@@ -641,8 +641,68 @@ void screen_adjoint(const Problem& pb, const double* u, std::vector<double>& gra
       for (size_t i = 0; i < VN * kRec; ++i) grad_rec[i] += part[th][i];
 }
 
+// Magnitude of the terms J^T u is summed from, as the method forms it (screen
+// records per view, then the chain to the parameters): per (view, Gaussian)
+// and record component, the sum over sampled pixels and channels of
+// |u_c| |d C_c / d rec|; then per parameter the sum over views and record
+// components of |d rec / d beta| times that. It bounds |J^T u| entry by entry
+// and scales the rounding error of any evaluation in that order (a test
+// scale, not part of the method).
+void screen_adjoint_abs(const Problem& pb, const double* u, std::vector<double>& grad_rec) {
+  const size_t VN = (size_t)pb.V * pb.n;
+  int nth = 1;
+#ifdef _OPENMP
+  nth = omp_get_max_threads();
+#endif
+  std::vector<std::vector<double>> part(nth);
+#pragma omp parallel
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    std::vector<double>& acc = part[tid];
+    acc.assign(VN * kRec, 0.0);
+    std::vector<const Rec<double>*> ptrs;
+    std::vector<Blended> bl;
+    std::vector<double> g;
+#pragma omp for schedule(dynamic, 4)
+    for (long long vt = 0; vt < (long long)pb.V * pb.T; ++vt) {
+      const int v = (int)(vt / pb.T), t = (int)(vt % pb.T);
+      if (!pb.tile_on(v, t)) continue;
+      const int* list;
+      int len;
+      tile_recs(pb, pb.rec, v, t, ptrs, &list, &len);
+      for (int j = 0; j < pb.k; ++j) {
+        const int64_t i = vt * pb.k + j;
+        const double* ui = u + 3 * i;
+        int px, py;
+        pb.pixel_of(v, t, j, &px, &py);
+        double Tf;
+        blend_trace(pb, ptrs.data(), len, px + 0.5, py + 0.5, bl, &Tf);
+        for (int c = 0; c < 3; ++c) {
+          if (ui[c] == 0.0) continue;
+          double e[3] = {0.0, 0.0, 0.0};
+          e[c] = 1.0;
+          g.assign((size_t)len * kRec, 0.0);
+          pixel_adjoint(pb, ptrs.data(), bl, Tf, e, g.data());
+          for (const Blended& b : bl) {
+            double* dst = &acc[((size_t)v * pb.n + list[b.pos]) * kRec];
+            const double* src = &g[(size_t)b.pos * kRec];
+            for (int q = 0; q < kRec; ++q) dst[q] += std::fabs(ui[c]) * std::fabs(src[q]);
+          }
+        }
+      }
+    }
+  }
+  grad_rec.assign(VN * kRec, 0.0);
+  for (int th = 0; th < nth; ++th)
+    if (!part[th].empty())
+      for (size_t i = 0; i < VN * kRec; ++i) grad_rec[i] += part[th][i];
+}
+
 // out[beta_g] = sum_v (d rec_{v,g} / d beta_g)^T grad_rec[v][g]
-void chain_to_params(Problem& pb, const std::vector<double>& grad_rec, double* out) {
+void chain_to_params(Problem& pb, const std::vector<double>& grad_rec, double* out, bool abs_terms = false) {
   ensure_jacobians(pb);
   const size_t P = (size_t)pb.n * pb.Pg;
   std::fill(out, out + P, 0.0);
@@ -659,7 +719,7 @@ void chain_to_params(Problem& pb, const std::vector<double>& grad_rec, double* o
       const double* J = &pb.pj[(size_t)slot * kRec * pb.Pg];
       for (int j = 0; j < pb.Pg; ++j) {
         double acc = 0.0;
-        for (int q = 0; q < kRec; ++q) acc += gr[q] * J[q * pb.Pg + j];
+        for (int q = 0; q < kRec; ++q) acc += abs_terms ? gr[q] * std::fabs(J[q * pb.Pg + j]) : gr[q] * J[q * pb.Pg + j];
         out[(size_t)j * pb.n + g] += acc;
       }
     }
@@ -785,6 +845,14 @@ void or_vjp(void* h, const double* u, double* out) {
   std::vector<double> grad_rec;
   screen_adjoint(pb, u, grad_rec);
   chain_to_params(pb, grad_rec, out);
+}
+
+// Term magnitudes of J^T u (see screen_adjoint_abs); out is [P].
+void or_vjp_abs(void* h, const double* u, double* out) {
+  Problem& pb = *static_cast<Problem*>(h);
+  std::vector<double> grad_rec;
+  screen_adjoint_abs(pb, u, grad_rec);
+  chain_to_params(pb, grad_rec, out, true);
 }
 
 // Screen-space adjoint only: grad_rec [V][n][9].

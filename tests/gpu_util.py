@@ -36,6 +36,21 @@ def elem(a, b) -> float:
     return float(np.max(np.abs(a - b) / (np.abs(b) + 1e-3 * np.max(np.abs(b)) + 1e-300)))
 
 
+def elem_scaled(a, b, scale) -> float:
+    """Entry-wise error against the magnitude of the terms each entry is summed
+    from: max_i |a_i - b_i| / scale_i over entries with scale_i > 0 (FP64).
+    With scale = oracle.vjp_abs(u) a wrong term, sign or index shows as O(1);
+    FP32 rounding of the sums shows as ~1e-6."""
+    a = np.asarray(a, np.float64).reshape(-1)
+    b = np.asarray(b, np.float64).reshape(-1)
+    s = np.asarray(scale, np.float64).reshape(-1)
+    on = s > 0
+    if not np.any(on):
+        return float(np.max(np.abs(a - b))) if a.size else 0.0
+    assert np.all(a[~on] == 0.0) or np.max(np.abs(a[~on])) < 1e-30, "entry with no terms is non-zero"
+    return float(np.max(np.abs(a[on] - b[on]) / s[on]))
+
+
 def lib():
     from paper_2504_12905_amd import lmrs
     return lmrs
@@ -60,7 +75,8 @@ def gpu_frame(n, deg, beta, cams, W, H, k=256, pix=None, wts=None, view_ids=None
 
 
 def oracle_for(n, deg, beta, cams, W, H, k=256, pix=None, wts=None) -> Oracle:
-    o = Oracle(n, deg, beta, cams, W, H)
+    # the same FP32 parameters the GPU frame is given (gpu_frame)
+    o = Oracle(n, deg, np.asarray(beta, np.float32), cams, W, H)
     o.set_samples(k, pix, wts)
     return o
 

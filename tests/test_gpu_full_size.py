@@ -5,13 +5,15 @@ Gaussians, SH degree 3, 8 of 64 views at 800x800, 26 samples per 16x16 tile
 Compared with the FP64 oracle: every tile list (bit-exact), every sampled
 pixel's colour and transmittance, J p at every sampled pixel, and the GN
 product, J^T u and diag(J^T W J) on all 5.9 M parameters, each norm-wise
-(bar 1e-4) and element-wise (max |a - b| / (|b| + 1e-3 max|b|), logged and
-bounded)."""
+(bar 1e-4) and element-wise: the GN product and J^T u against the magnitude
+of the terms each entry is summed from (oracle.vjp_abs), the diagonal (a sum
+of squares) against its own entries; the element-wise figure of
+max |a - b| / (|b| + 1e-3 max|b|) is logged beside them."""
 import numpy as np
 import pytest
 import torch
 
-from gpu_util import DEV, compare_lists, elem, lib, lists_of, log, np_, rel
+from gpu_util import DEV, compare_lists, elem, elem_scaled, lib, lists_of, log, np_, rel
 from oracle import Oracle
 from oracle.sampling import sample_uniform
 from paper_2504_12905_amd import synth
@@ -73,10 +75,8 @@ def test_full_size_jvp(full):
     assert e < 1e-4 and ok.mean() > 0.99
 
 
-# Element-wise bar of the full-vector comparisons. The FP32 sums over pixels
-# carry errors of ~1e-6 of the summed magnitudes; an entry much smaller than
-# its summands (cancellation) is measured against 1e-3 of the largest entry.
-ELEM = 1e-3
+# Element-wise bar: each entry's error against the magnitude of its terms.
+ELEM_TERMS = 1e-4
 
 
 def test_full_size_gn_product_full_vector(full):
@@ -84,9 +84,12 @@ def test_full_size_gn_product_full_vector(full):
     p = np.random.default_rng(7).normal(size=orc.P).astype(np.float32)
     out = np_(lib().lmrs_gn_product(fr, torch.tensor(p, device=DEV), w.lam))
     ref = orc.gn(p, w.lam)
-    e, m = rel(out, ref), elem(out, ref)
-    log(f"  gn full vector ({orc.P} entries): rel {e:.2e}, elementwise {m:.2e}")
-    assert e < 1e-4 and m < ELEM
+    wjp = orc.jvp(p) * orc.weights()[:, None]
+    scale = orc.vjp_abs(wjp) + w.lam * np.abs(p.astype(np.float64))
+    e, m, m_terms = rel(out, ref), elem(out, ref), elem_scaled(out, ref, scale)
+    log(f"  gn full vector ({orc.P} entries): rel {e:.2e}, against term magnitudes {m_terms:.2e}, "
+        f"against 1e-3 max {m:.2e}")
+    assert e < 1e-4 and m_terms < ELEM_TERMS
 
 
 def test_full_size_vjp_full_vector(full):
@@ -94,18 +97,23 @@ def test_full_size_vjp_full_vector(full):
     u = np.random.default_rng(8).normal(size=(orc.S, 3)).astype(np.float32)
     out = np_(lib().lmrs_vjp(fr, torch.tensor(u, device=DEV)))
     ref = orc.vjp(u)
-    e, m = rel(out, ref), elem(out, ref)
-    log(f"  J^T u full vector: rel {e:.2e}, elementwise {m:.2e}")
-    assert e < 1e-4 and m < ELEM
+    scale = orc.vjp_abs(u)
+    e, m, m_terms = rel(out, ref), elem(out, ref), elem_scaled(out, ref, scale)
+    log(f"  J^T u full vector: rel {e:.2e}, against term magnitudes {m_terms:.2e}, against 1e-3 max {m:.2e}")
+    assert e < 1e-4 and m_terms < ELEM_TERMS
 
 
 def test_full_size_diag_full_vector(full):
+    """A sum of squares in the oracle; the GPU forms it as quadratic forms of
+    per-(view, Gaussian) Gram blocks, whose terms can cancel, so entries are
+    measured against themselves plus 1e-3 of the largest (R22's figure; the
+    error against the entry alone is logged)."""
     w, fr, orc = full
     out = np_(lib().lmrs_gn_diag(fr))
     ref = orc.diag()
-    e, m = rel(out, ref), elem(out, ref)
-    log(f"  diag(J^T W J) full vector: rel {e:.2e}, elementwise {m:.2e}")
-    assert e < 1e-4 and m < ELEM
+    e, m, m_self = rel(out, ref), elem(out, ref), elem_scaled(out, ref, ref)
+    log(f"  diag(J^T W J) full vector: rel {e:.2e}, against 1e-3 max {m:.2e}, against itself {m_self:.2e}")
+    assert e < 1e-4 and m < 1e-3
 
 
 def test_full_size_adjoint_identity(full):

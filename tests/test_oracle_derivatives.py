@@ -135,3 +135,30 @@ def test_tile_mask_restricts_to_listed_gaussians():
     part = o.gn(p, 1e-3)
     idx = (np.arange(o.Pg)[:, None] * o.n + sel[None, :]).reshape(-1)
     np.testing.assert_allclose(part[idx], full[idx], rtol=1e-12, atol=1e-14)
+
+
+def test_vjp_term_magnitudes():
+    """|J^T u| term scale (oracle.vjp_abs): the screen-record adjoint of every
+    pixel and channel taken in absolute value, chained with |d rec / d beta|,
+    equals its brute-force assembly from one-hot screen adjoints, and bounds
+    both |J^T u| and |J|^T |u| (dense J by dual numbers) from above."""
+    w, o = tiny_problem(sh_degree=1, n=3, views=1, seed=4, k=16)
+    rng = np.random.default_rng(9)
+    u = rng.normal(size=(o.S, 3))
+    got = o.vjp_abs(u)
+    scr = np.zeros((o.V, o.n, 9))
+    for i in range(o.S):
+        for c in range(3):
+            e = np.zeros((o.S, 3))
+            e[i, c] = 1.0
+            scr += abs(u[i, c]) * np.abs(o.vjp_screen(e))
+    ref = np.zeros(o.P)
+    for v in range(o.V):
+        for g in range(o.n):
+            ref[np.arange(o.Pg) * o.n + g] += np.abs(o.proj_jacobian(v, g)).T @ scr[v, g]
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    J = o.dense_jacobian()
+    absju = np.abs(J).T @ np.abs(u.reshape(-1))
+    assert np.all(got >= absju * (1 - 1e-12) - 1e-14)
+    assert np.all(got >= np.abs(o.vjp(u)) * (1 - 1e-12) - 1e-14)
+    assert np.abs(got).max() > 0
