@@ -253,6 +253,19 @@ lmrs_status lmrs_gn_product(const lmrs_frame* f, const lmrs_render_opts* o, cons
                             float lambda, const float* d, float* out, void* ws, size_t ws_bytes,
                             void* stream);
 
+/* lmrs_gn_product for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same launches and result, with its scratch (tangent records and screen
+ * gradients, lmrs_workspace_bytes(LMRS_OP_GN, f) bytes) taken from a static
+ * device array of 64 MiB per GPU instead of a workspace argument (frames up to
+ * about 599k views x Gaussians). The array is loaded with the library and held
+ * until the process ends; the call allocates nothing. A frame that needs more
+ * returns LMRS_EWORKSPACE. Every call on one GPU uses that GPU's array, so
+ * calls that overlap on one GPU (other streams or threads) race: serialize
+ * them. The first call on a device looks up the array's address there. */
+lmrs_status lmrs_gn_product_noalloc(const lmrs_frame* f, const lmrs_render_opts* o, const float* p,
+                                    float lambda, const float* d, float* out, void* stream);
+
 /* Measurement variant of lmrs_gn_product: the same four launches (tangent
  * projection, zero fill, fused splat, reverse chain) with HIP events
  * recorded on `stream` between them; waits for the last event and writes

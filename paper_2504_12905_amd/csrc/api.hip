@@ -2,6 +2,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -328,6 +329,43 @@ FrameDims dims_of(const lmrs_frame* f) {
   return d;
 }
 
+// ------------------------------------------------------------ no-alloc GN
+// Scratch memory of lmrs_gn_product_noalloc: one array per GPU, loaded with
+// the code object and held until the process ends, shared by every call on
+// that GPU. Host code never passes the array's name to a kernel (on the host
+// it is only a stand-in for the symbol): it takes the array's device address
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+constexpr int kNoAllocDevices = 64;
+
+}  // namespace lmrs
+
+static __device__ __align__(256) unsigned char scratch[lmrs::kNoAllocBytes];
+
+namespace lmrs {
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocDevices] = {};
+
+// Device address of the current device's scratch array.
+lmrs_status noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return hip_check("hipGetDevice");
+  if (dev < 0 || dev >= kNoAllocDevices) return fail(LMRS_EUNSUPPORTED, "device %d: scratch kept for %d devices", dev,
+                                                      kNoAllocDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail(LMRS_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LMRS_OK;
+}
+
+}  // namespace
 }  // namespace lmrs
 
 using namespace lmrs;
@@ -627,6 +665,32 @@ lmrs_status lmrs_lm_solve(lmrs_frame* f, float* beta, const float* targets, cons
   const Scratch s = carve(LMRS_OP_SOLVE, d, f->capacity, c);
   solve_sequence(f, d, beta, targets, dvec, *prm, *o, report, s, (hipStream_t)stream);
   return hip_check("lmrs_lm_solve");
+}
+
+
+lmrs_status lmrs_gn_product_noalloc(const lmrs_frame* f, const lmrs_render_opts* o, const float* p, float lambda,
+                                    const float* dvec, float* out, void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_deriv_state(f));
+  LMRS_TRY(need(p, "p"));
+  LMRS_TRY(need(out, "out"));
+  if (p == out) return fail(LMRS_EINVAL, "p and out must not alias");
+  const size_t need_bytes = lmrs_workspace_bytes(LMRS_OP_GN, f);
+  if (need_bytes > kNoAllocBytes)
+    return fail(LMRS_EWORKSPACE,
+                "lmrs_gn_product_noalloc: this frame needs %zu bytes of scratch, the static array holds %zu "
+                "(views x Gaussians up to about %zu); use lmrs_gn_product with a workspace",
+                need_bytes, kNoAllocBytes, kNoAllocBytes / ((LMRS_REC + kGradRow) * sizeof(float)));
+  void* ws = nullptr;
+  LMRS_TRY(noalloc_scratch(&ws));
+  const FrameDims d = dims_of(f);
+  Carver c(ws);
+  const Scratch s = carve(LMRS_OP_GN, d, f->capacity, c);
+  // the tangent records are written in full; the screen-gradient rows hold
+  // the previous call's values and are cleared by a fill kernel first
+  gn_sequence(f, d, *o, p, lambda, dvec, out, s, (hipStream_t)stream);
+  return hip_check("lmrs_gn_product_noalloc");
 }
 
 }  // extern "C"

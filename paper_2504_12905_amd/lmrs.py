@@ -92,6 +92,7 @@ _lib.lmrs_jvp.argtypes = [_FP, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_vjp.argtypes = [_FP, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_gn_product.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_gn_product_timed.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp, _vp]
+_lib.lmrs_gn_product_noalloc.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp]
 _lib.lmrs_walk_counts.argtypes = [_FP, _vp, _vp, _vp]
 _lib.lmrs_gn_diag.argtypes = [_FP, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_pcg.argtypes = [_FP, _vp, _vp, _f32, _vp, _i32, _vp, _vp, _vp, _sz, _vp]
@@ -105,7 +106,7 @@ _lib.lmrs_contributor_counts.argtypes = [_FP, _vp, _vp, _vp]
 _lib.lmrs_view_clusters.argtypes = [_vp, _i32, _i32, C.c_uint64, _vp]
 _lib.lmrs_view_batch.argtypes = [_vp, _i32, _i32, C.c_uint64, _i32, _vp]
 for _name in ("lmrs_project", "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp",
-              "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_walk_counts",
+              "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_product_noalloc", "lmrs_walk_counts",
               "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step", "lmrs_residual_scores", "lmrs_sample", "lmrs_lm_solve",
               "lmrs_contributor_counts", "lmrs_view_clusters", "lmrs_view_batch", "lmrs_lm_iterate",
               "lmrs_bin_tiles_async"):
@@ -274,6 +275,17 @@ def lmrs_gn_product(frame: Frame, p: torch.Tensor, lam: float, d: torch.Tensor |
     return out
 
 
+def lmrs_gn_product_noalloc(frame: Frame, p: torch.Tensor, lam: float, out: torch.Tensor,
+                            d: torch.Tensor | None = None, opts=None, stream=None):
+    """lmrs_gn_product with the library's static scratch array (no workspace;
+    the C call allocates nothing). out: caller-allocated [P]."""
+    opts = opts or default_opts()
+    fs = frame.struct()
+    _check(_lib.lmrs_gn_product_noalloc(C.byref(fs), C.byref(opts), _ptr(p), float(lam), _ptr(d), _ptr(out),
+                                        _stream(stream)), "lmrs_gn_product_noalloc")
+    return out
+
+
 def lmrs_gn_product_timed(frame: Frame, p: torch.Tensor, lam: float, d: torch.Tensor | None = None,
                           out: torch.Tensor | None = None, opts=None, stream=None,
                           ws: torch.Tensor | None = None):
@@ -437,6 +449,6 @@ def lm_params(iter: int, cg_iters: int, lam: float, seed: int = 0, eta_cap: floa
 
 EXPORTS = ("lmrs_status_str", "lmrs_last_error", "lmrs_report_status", "lmrs_workspace_bytes", "lmrs_project",
            "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp", "lmrs_gn_product",
-           "lmrs_gn_product_timed", "lmrs_walk_counts", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step",
+           "lmrs_gn_product_timed", "lmrs_gn_product_noalloc", "lmrs_walk_counts", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step",
            "lmrs_residual_scores", "lmrs_contributor_counts", "lmrs_sample", "lmrs_lm_solve",
            "lmrs_view_clusters", "lmrs_view_batch", "lmrs_lm_iterate", "lmrs_bin_tiles_async")
