@@ -274,12 +274,12 @@ def lm_breakdown(L, torch, fr, targets, w, sampler, it, gn_ms):
     out["b = J^T W r"] = wall(lambda: L.lmrs_vjp(fr, u, out=b))
     dg = torch.empty_like(b)
     L.lmrs_gn_diag(fr, out=dg)
-    out["diag"] = wall(lambda: L.lmrs_gn_diag(fr, out=dg))
+    out["diag (+ blend table)"] = wall(lambda: L.lmrs_gn_diag(fr, out=dg))
     out[f"{w.cg_iters} GN products"] = w.cg_iters * gn_ms
     x = torch.empty_like(b)
     L.lmrs_pcg(fr, b, w.lam, w.cg_iters, x=x)
     pcg = wall(lambda: L.lmrs_pcg(fr, b, w.lam, w.cg_iters, x=x))
-    out["PCG vector work"] = max(0.0, pcg - out["diag"] - w.cg_iters * gn_ms)
+    out["PCG vector work"] = max(0.0, pcg - out["diag (+ blend table)"] - w.cg_iters * gn_ms)
     return out
 
 
@@ -409,17 +409,21 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
     all_vids = torch.tensor(np.stack([rng.choice(w.cams.shape[0], V, replace=False)
                                       for _ in range(warmup + steps)]).astype(np.int32), device=dev)
 
-    def step(it):
+    def step(it, grow=False):
         view_ids.copy_(all_vids[it])
         # the binding allocates a larger workspace itself if the tile lists outgrow ws
         L.lmrs_lm_step(fr, targets, L.lm_params(it, w.cg_iters, w.lam, seed=w.seed, sampler=sampler), report=rep,
-                       ws=ws)
+                       ws=ws, grow_blend=grow)
 
     log(f"[bench] warmup {warmup} LM steps")
     it = 0
+    max_pairs = 0
     for _ in range(warmup):
-        step(it)
+        step(it, grow=True)
+        max_pairs = max(max_pairs, fr.blend_pairs())
         it += 1
+    # blend table for the largest pair count seen, with room for other view batches
+    fr.ensure_blend(int(max_pairs * 1.3))
     torch.cuda.synchronize()
     # grow the workspace once for the largest instance count seen, outside the timed region
     ws = torch.empty(int(L._lib.lmrs_workspace_bytes(L.OP_LM, L.C.byref(fr.struct())) * 1.1) + 4096,
@@ -436,7 +440,7 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
     value = products / el
     r = rep.cpu().numpy()
     log(f"[bench] {el / steps * 1e3:.2f} ms/LM step, {value:.1f} GN products/s; last step: loss "
-        f"{r[0]:.4e} eta {r[1]:.3f} instances {r[7]:.0f}")
+        f"{r[0]:.4e} eta {r[1]:.3f} instances {r[7]:.0f} blend pairs {r[9]:.0f} (table for {fr.blend_capacity})")
 
     # --- the GN product on its own, at the current parameters and the last step's samples
     L.lmrs_project(fr)
@@ -448,22 +452,43 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
     gws = L.workspace(L.OP_GN, fr)
     if args.calibrate_copy:
         copy_calibration(torch, dev, args.calibrate_copy)
-    for _ in range(5):
-        L.lmrs_gn_product(fr, p, w.lam, out=out, ws=gws)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.gn_reps)]
-    for e0, e1 in ev:
-        e0.record(stream)
-        L.lmrs_gn_product(fr, p, w.lam, out=out, ws=gws)
-        e1.record(stream)
+
+    def median_gn_ms():
+        for _ in range(5):
+            L.lmrs_gn_product(fr, p, w.lam, out=out, ws=gws)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.gn_reps)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            L.lmrs_gn_product(fr, p, w.lam, out=out, ws=gws)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median(np.array([e0.elapsed_time(e1) for e0, e1 in ev])))
+
+    # the plain matrix-free product: every product walks the tile lists (the
+    # render left the blend table stale)
+    assert not fr.blend_built()
+    walk_ms = median_gn_ms()
+    walk_phases = np.median(np.array([L.lmrs_gn_product_timed(fr, p, w.lam, out=out, ws=gws)[1]
+                                      for _ in range(args.gn_reps)]), axis=0)
+    # the blend table (built once per LM step by the right-hand-side pass; here on its own)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    L.lmrs_linearize(fr)
+    e1.record(stream)
     torch.cuda.synchronize()
-    per_call = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
-    gn_ms = float(np.median(per_call))
+    linearize_ms = e0.elapsed_time(e1)
+    table = fr.blend_built()
+    gn_ms = median_gn_ms()
     phases = np.array([L.lmrs_gn_product_timed(fr, p, w.lam, out=out, ws=gws)[1] for _ in range(args.gn_reps)])
     phase_ms = np.median(phases, axis=0)
+    splat_phase = 2 if table else 3
     log(f"[bench] GN product median {gn_ms:.3f} ms over {args.gn_reps} calls (tangent {phase_ms[0]:.3f}, "
-        f"fill {phase_ms[1]:.3f}, fused splat {phase_ms[2]:.3f}, chain {phase_ms[3]:.3f})")
+        f"fill {phase_ms[1]:.3f}, table splat {phase_ms[2]:.3f}, fused walk {phase_ms[3]:.3f}, "
+        f"chain {phase_ms[4]:.3f}); blend table built: {table} ({linearize_ms:.3f} ms on its own); "
+        f"walking the lists instead: {walk_ms:.3f} ms (fused walk {walk_phases[3]:.3f})")
     # the unfused comparator: J p to HBM, weights, then J^T u (same state)
     wts = fr.w.view(-1, 1)
     jp = torch.empty((fr.S, 3), dtype=torch.float32, device=dev)
@@ -492,7 +517,7 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
     S = fr.S
     b_alg = entries * B_ENTRY + contrib * B_CONTRIB + S * B_PIXEL
     f_alg = n_act * F_ACT + (n_walk - n_act) * F_SKIP
-    t_splat = phase_ms[2] * 1e-3
+    t_splat = phase_ms[splat_phase] * 1e-3
     gbs = b_alg / t_splat / 1e9
     tflops = f_alg / t_splat / 1e12
     t_hbm, t_alu = b_alg / (HBM_PEAK_GBS * 1e9), f_alg / (FP32_PEAK_TFLOPS * 1e12)
@@ -504,7 +529,8 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
     f_gn = f_alg + n_vis * F_VIS
     t_gn = gn_ms * 1e-3
     roofline = {
-        "kernel": "deriv_kernel<3> (fused J p / weight / J^T u splat of lmrs_gn_product)",
+        "kernel": ("blend_gn_kernel (J p / weight / J^T u over the blend table, in lmrs_gn_product)" if table
+                   else "deriv_kernel<3> (fused J p / weight / J^T u walk of lmrs_gn_product)"),
         "bound": "alu" if bound_alu else "hbm",
         "achieved": round(tflops if bound_alu else gbs, 4),
         "peak": FP32_PEAK_TFLOPS if bound_alu else HBM_PEAK_GBS,
@@ -518,7 +544,7 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
         "algorithmic_bytes": b_alg, "algorithmic_flops": f_alg,
         "traversed_entries": entries, "contributing_entries": contrib, "blending_pairs": n_act,
         "walked_pairs": n_walk, "sampled_pixels": S, "visible_view_gaussians": n_vis,
-        "ms_per_launch": round(float(phase_ms[2]), 4),
+        "ms_per_launch": round(float(phase_ms[splat_phase]), 4),
         "gn_product": {"algorithmic_bytes": b_gn, "algorithmic_flops": f_gn, "ms": round(gn_ms, 4),
                        "hbm_gbs": round(b_gn / t_gn / 1e9, 3), "hbm_frac": round(b_gn / t_gn / 1e9 / HBM_PEAK_GBS, 6),
                        "alu_frac": round(f_gn / t_gn / 1e12 / FP32_PEAK_TFLOPS, 6)},
@@ -546,6 +572,11 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
                    "gn_product_ms_median": round(gn_ms, 4),
                    "gn_products_per_s_isolated": round(1e3 / gn_ms, 2),
                    "gn_phase_ms_median": [round(float(x), 4) for x in phase_ms],
+                   "gn_phases": ["tangent", "fill", "blend-table splat", "fused walk", "chain"],
+                   "gn_walk_ms_median": round(walk_ms, 4),
+                   "gn_walk_phase_ms_median": [round(float(x), 4) for x in walk_phases],
+                   "linearize_ms": round(linearize_ms, 4),
+                   "blend_table": {"built": table, "pairs": fr.blend_pairs(), "bytes_per_pair": 44},
                    "gn_unfused_jvp_vjp_ms": round(unfused_ms, 4),
                    "gn_parity_rel_vs_oracle": parity,
                    "sampler": "residual" if sampler == L.SAMPLER_RESIDUAL else "uniform",

@@ -135,6 +135,34 @@ typedef struct lmrs_frame {
                              non-empty walk, 0). The splat kernels hand tiles to
                              their waves in this order and leave the counters as
                              they found them.                                  */
+  /* Blend table: the linearization of the sampled render at the current
+   * parameters, one record per blending (sampled pixel, list entry) pair
+   * (optional: blend_k NULL = not kept, and every GN product walks the tile
+   * lists). For pair (pixel i, Gaussian g) with opacity a and transmittance
+   * T in front of g, K = d C_i / d a = T rgb_g - (colour behind g, background
+   * included) / (1 - a) per channel (0 when a is capped), so that
+   * d C_i = a T d rgb_g + K d a. The record derivatives of a are recomputed
+   * from g's screen record and the pixel. The Gauss-Newton products of eq. 14
+   * are then sums over these pairs instead of walks over the lists.
+   * lmrs_render counts the pairs of each tile into blend_start and marks the
+   * table stale; the right-hand-side / diagonal pass (lmrs_gn_diag,
+   * lmrs_linearize, lmrs_pcg, lmrs_lm_*) writes it when the count fits
+   * blend_capacity and marks it built; lmrs_gn_product and the PCG's products
+   * use it when built and walk the lists otherwise. Gaussian ids < 2^24. */
+  float* blend_k;         /* [2][blend_capacity][4]: K_R, K_G, K_B, a T; copy 0
+                             grouped by Gaussian, copy 1 by pixel (within each
+                             tile and 64-entry list chunk)                    */
+  uint32_t* blend_m;      /* [2][blend_capacity]: Gaussian id << 8 | sample
+                             slot, for the pairs of blend_k                   */
+  int32_t* blend_run;     /* [blend_capacity]: starts (relative to the tile's
+                             first pair) of runs of at most 32 pairs of one
+                             Gaussian; the runs of a tile are in order and
+                             cover its pairs                                  */
+  int32_t* blend_runs;    /* [V*T] runs per tile                               */
+  int64_t* blend_start;   /* [V*T + 2] pair offset of each tile; [V*T] = total
+                             pairs of the batch; [V*T + 1] = 1 when the table
+                             is built for the current render, else 0          */
+  int64_t blend_capacity; /* pairs available in blend_k, blend_m, blend_run   */
 } lmrs_frame;
 
 /* Length in int32 of lmrs_frame.sched for a batch of `tiles` = V*T tiles. */
@@ -185,6 +213,8 @@ typedef struct lmrs_lm_params {
 #define LMRS_REP_BX 6          /* b^T x (> 0 for a descent step)                  */
 #define LMRS_REP_INST 7        /* tile-list entries of this step                  */
 #define LMRS_REP_STATUS 8      /* LMRS_FAIL_* bits of this step, 0 when none      */
+#define LMRS_REP_PAIRS 9       /* blending (pixel, Gaussian) pairs of this step
+                                  (the blend table needs that many entries)      */
 
 /* Numeric failures, detected on the device (calls enqueue and return, so they
  * cannot be returned as a status). PCG stops at the first one; lmrs_lm_step /
@@ -215,13 +245,15 @@ size_t lmrs_workspace_bytes(int32_t op, const lmrs_frame* f);
 
 /* a1. Projection (Sec. 3 eq. 1-3, EWA splatting): for every batch view v and
  * Gaussian g, rec[v][g] = (u, v, conic factor f11 f12 f22, opacity sigmoid(logit),
- * rgb = 0.5 + sum_k Y_k(dir) f_k, FP32 depth key, radius) and rect[v][g].
- * Reads beta, cams, view_ids; writes rec, rect. */
+ * rgb = 0.5 + sum_k Y_k(dir) f_k, low word of the FP64 camera depth's bits,
+ * radius, high word) and rect[v][g]. The near-plane cull, the footprint
+ * radius ceil(cutoff sqrt(lambda_max)) and the tile rectangle are decided in
+ * FP64. Reads beta, cams, view_ids; writes rec, rect. */
 lmrs_status lmrs_project(const lmrs_frame* f, const lmrs_render_opts* o, void* stream);
 
 /* a2. Tile binning and depth sort (Sec. 3: projected Gaussians are sorted by
  * depth; Supp. A: 16x16 tiles). For each view and tile, ids of the Gaussians
- * whose rect holds the tile, ascending depth key, ties by ascending id.
+ * whose rect holds the tile, ascending FP64 camera depth, ties by ascending id.
  * Reads rect and rec; writes n_instances, tile_start and ids. Waits for the
  * instance count; if it exceeds capacity returns LMRS_ECAPACITY with
  * *n_instances (device) holding the count needed and ids untouched. */
@@ -266,12 +298,13 @@ lmrs_status lmrs_gn_product(const lmrs_frame* f, const lmrs_render_opts* o, cons
 lmrs_status lmrs_gn_product_noalloc(const lmrs_frame* f, const lmrs_render_opts* o, const float* p,
                                     float lambda, const float* d, float* out, void* stream);
 
-/* Measurement variant of lmrs_gn_product: the same four launches (tangent
- * projection, zero fill, fused splat, reverse chain) with HIP events
- * recorded on `stream` between them; waits for the last event and writes
- * the elapsed milliseconds of each launch to ms[4] (host):
- * ms[0] tangent, ms[1] fill, ms[2] fused splat, ms[3] chain. For profiling
- * and benchmarks; the result in out is identical to lmrs_gn_product's. */
+/* Measurement variant of lmrs_gn_product: the same launches (tangent
+ * projection, zero fill, the splat from the blend table, the fused list walk
+ * (one of the two exits at once), reverse chain) with HIP events recorded on
+ * `stream` between them; waits for the last event and writes the elapsed
+ * milliseconds of each launch to ms[5] (host): ms[0] tangent, ms[1] fill,
+ * ms[2] blend-table splat, ms[3] fused walk, ms[4] chain. For profiling and
+ * benchmarks; the result in out is identical to lmrs_gn_product's. */
 lmrs_status lmrs_gn_product_timed(const lmrs_frame* f, const lmrs_render_opts* o, const float* p,
                                   float lambda, const float* d, float* out, void* ws, size_t ws_bytes,
                                   void* stream, float* ms);
@@ -287,6 +320,13 @@ lmrs_status lmrs_gn_product_timed(const lmrs_frame* f, const lmrs_render_opts* o
  *   [2] blending (pixel, entry) pairs (Sec. 3 eq. 3 terms with alpha >= alpha_min);
  *   [3] (pixel, entry) pairs up to and including each pixel's last blended entry. */
 lmrs_status lmrs_walk_counts(const lmrs_frame* f, const lmrs_render_opts* o, int64_t* counts, void* stream);
+
+/* Builds the blend table of f (see lmrs_frame) for the current render: one
+ * reverse walk over the lists (the walk of the diagonal pass without its
+ * sums). Needs the state of lmrs_jvp and the blend buffers; when the pair
+ * count (blend_start[V*T], written by lmrs_render) exceeds blend_capacity the
+ * table stays unbuilt and the GN products walk the lists. No workspace. */
+lmrs_status lmrs_linearize(const lmrs_frame* f, const lmrs_render_opts* o, void* stream);
 
 /* a5. diag(J^T W J) (Alg. 1 preconditioner; Supp. A "Diag(J^T J) kernel"),
  * exact: per (view, Gaussian) the weighted Gram matrix of the screen-record

@@ -55,7 +55,7 @@ class LmrsRender(torch.autograd.Function):
     def forward(ctx, beta: torch.Tensor, n: int, sh_degree: int, views: Views):
         b = beta.detach().contiguous()
         fr = L.Frame(n, sh_degree, b, views.cams, views.width, views.height, views.n_views,
-                     view_ids=views.view_ids, k=256)
+                     view_ids=views.view_ids, k=256, blend=False)
         opts = views.opts or L.default_opts()
         L.lmrs_project(fr, opts)
         L.lmrs_bin_tiles(fr)

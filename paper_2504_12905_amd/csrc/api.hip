@@ -123,6 +123,12 @@ lmrs_status check_frame(const lmrs_frame* f, bool need_samples_k = true) {
     if (!f->pix && f->k != 256) return fail(LMRS_EINVAL, "pix is NULL but k = %d != 256", f->k);
   }
   if (!f->beta) return fail(LMRS_EINVAL, "beta is NULL");
+  if (f->blend_k) {
+    if (!f->blend_m || !f->blend_run || !f->blend_runs || !f->blend_start)
+      return fail(LMRS_EINVAL, "blend_k is set: blend_m, blend_run, blend_runs and blend_start are needed");
+    if (f->blend_capacity < 0) return fail(LMRS_EINVAL, "blend_capacity is negative");
+    if (f->n >= (1 << 24)) return fail(LMRS_EUNSUPPORTED, "the blend table holds Gaussian ids below 2^24 (n = %d)", f->n);
+  }
   return LMRS_OK;
 }
 
@@ -169,6 +175,8 @@ void gn_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts
                  double* pu_part = nullptr, bool grad_zero = false) {
   launch_tangent(f, d, o, p, s.tan, st);
   if (!grad_zero) launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
+  // from the blend table when it is built for this render, else the fused walk
+  launch_blend_gn(f, d, o, s.tan, s.grad2d, st);
   launch_deriv(3, f, d, o, s.tan, nullptr, nullptr, s.grad2d, st);
   launch_chain_vjp(f, d, o, s.grad2d, p, lambda, dvec, out, st, pu_part, true);
 }
@@ -306,7 +314,9 @@ void solve_sequence(const lmrs_frame* f, const FrameDims& d, float* beta, const 
   pcg_sequence(f, d, o, s.b, prm.lambda, dvec, cg, s.x, report, s, st, true, true);
   const PcgState ps{s.x, s.r, s.z, s.p, s.u, s.minv, s.sc, s.red};
   launch_lm_update(beta, s.x, d.n, P, prm, pcg_fail_slot(cg, ps), s.red, report, st);
-  if (report) launch_report_count(f->n_instances, f->capacity, report, st);
+  if (report)
+    launch_report_count(f->n_instances, f->capacity, report, st,
+                        f->blend_k ? f->blend_start + (int64_t)d.V * d.T : nullptr);
 }
 
 }  // namespace
@@ -508,23 +518,25 @@ lmrs_status lmrs_gn_product_timed(const lmrs_frame* f, const lmrs_render_opts* o
   Carver c(ws);
   const Scratch s = carve(LMRS_OP_GN, d, f->capacity, c);
   hipStream_t st = (hipStream_t)stream;
-  hipEvent_t ev[5];
-  for (int i = 0; i < 5; ++i)
+  hipEvent_t ev[6];
+  for (int i = 0; i < 6; ++i)
     if (hipEventCreate(&ev[i]) != hipSuccess) return hip_check("hipEventCreate");
   (void)hipEventRecord(ev[0], st);
   launch_tangent(f, d, *o, p, s.tan, st);
   (void)hipEventRecord(ev[1], st);
   launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
   (void)hipEventRecord(ev[2], st);
-  launch_deriv(3, f, d, *o, s.tan, nullptr, nullptr, s.grad2d, st);
+  launch_blend_gn(f, d, *o, s.tan, s.grad2d, st);
   (void)hipEventRecord(ev[3], st);
-  launch_chain_vjp(f, d, *o, s.grad2d, p, lambda, dvec, out, st);
+  launch_deriv(3, f, d, *o, s.tan, nullptr, nullptr, s.grad2d, st);
   (void)hipEventRecord(ev[4], st);
+  launch_chain_vjp(f, d, *o, s.grad2d, p, lambda, dvec, out, st);
+  (void)hipEventRecord(ev[5], st);
   lmrs_status status = LMRS_OK;
-  if (hipEventSynchronize(ev[4]) != hipSuccess) status = hip_check("hipEventSynchronize");
-  for (int i = 0; i < 4 && status == LMRS_OK; ++i)
+  if (hipEventSynchronize(ev[5]) != hipSuccess) status = hip_check("hipEventSynchronize");
+  for (int i = 0; i < 5 && status == LMRS_OK; ++i)
     if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess) status = hip_check("hipEventElapsedTime");
-  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
   if (status != LMRS_OK) return status;
   return hip_check("lmrs_gn_product_timed");
 }
@@ -536,6 +548,15 @@ lmrs_status lmrs_walk_counts(const lmrs_frame* f, const lmrs_render_opts* o, int
   LMRS_TRY(need(counts, "counts"));
   launch_walk_counts(f, dims_of(f), *o, counts, (hipStream_t)stream);
   return hip_check("lmrs_walk_counts");
+}
+
+lmrs_status lmrs_linearize(const lmrs_frame* f, const lmrs_render_opts* o, void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_deriv_state(f));
+  if (!f->blend_k) return fail(LMRS_EINVAL, "lmrs_linearize: the frame has no blend table (blend_k is NULL)");
+  launch_gram(f, dims_of(f), *o, nullptr, nullptr, nullptr, (hipStream_t)stream, false);
+  return hip_check("lmrs_linearize");
 }
 
 lmrs_status lmrs_gn_diag(const lmrs_frame* f, const lmrs_render_opts* o, float* out, void* ws,

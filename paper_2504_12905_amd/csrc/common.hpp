@@ -141,17 +141,30 @@ __device__ __forceinline__ void decision_point(const lmrs_camera& c, double mx, 
   *v = fma((double)c.fy, tc[1] / tc[2], (double)c.cy);
 }
 
-// Depth sort keys of a camera depth z: the FP32 number nearest z, and the
-// count of FP64 numbers between that and z, offset by 2^30. Rounding to nearest
-// is monotone, so (key, sub) in lexicographic order is the order of z itself;
-// |z - key| <= half an FP32 spacing, i.e. at most 2^28 FP64 spacings, so sub
-// fits 31 bits. Both are meaningful for z > 0 only (culled Gaussians are never
-// listed).
-__device__ __forceinline__ void depth_keys(double z, float* key, uint32_t* sub) {
-  const float k = (float)z;
-  *key = k;
-  const int64_t d = (int64_t)__double_as_longlong(z) - (int64_t)__double_as_longlong((double)k);
-  *sub = (uint32_t)(d + (int64_t(1) << 30));
+// The camera depth z of a (view, Gaussian) travels in the screen record as
+// the two 32-bit halves of its FP64 bits (record slots 9 = low, 11 = high);
+// for z > 0 those bits order like z itself.
+__device__ __forceinline__ void depth_words(double z, float* lo, float* hi) {
+  const uint64_t b = (uint64_t)__double_as_longlong(z);
+  *lo = __uint_as_float((uint32_t)b);
+  *hi = __uint_as_float((uint32_t)(b >> 32));
+}
+__device__ __forceinline__ uint64_t depth_bits(float lo, float hi) {
+  return ((uint64_t)__float_as_uint(hi) << 32) | __float_as_uint(lo);
+}
+
+// 32-bit sort key of a depth, monotone in z: 0 for z <= 0 (never listed); for
+// z > 0, 5 bits of binary exponent e - kDepthEmin and the top 27 bits of the
+// mantissa, saturating at 1 below 2^kDepthEmin and at 2^32 - 1 from
+// 2^(kDepthEmin + 32) on. Depths with equal keys (within 2^-27 relative of
+// each other) are put in FP64 order by a tie pass over the sorted keys.
+constexpr int kDepthEmin = -16;
+__device__ __forceinline__ uint32_t depth_sort_key(uint64_t b) {
+  if ((int64_t)b <= 0) return 0u;
+  const int e = (int)((b >> 52) & 0x7ff) - 1023 - kDepthEmin;
+  if (e < 0) return 1u;
+  if (e >= 32) return 0xffffffffu;
+  return max(((uint32_t)e << 27) | (uint32_t)((b >> 25) & 0x7ffffffu), 1u);
 }
 
 // Load the PG parameters of Gaussian g (component-major beta).
@@ -447,6 +460,7 @@ namespace dpp {
 constexpr int kRowShr = 0x110;     // row_shr:n = kRowShr + n
 constexpr int kRowBcast15 = 0x142; // lane 15 of each row to the next row
 constexpr int kRowBcast31 = 0x143; // lane 31 to rows 2 and 3
+constexpr int kWaveShr1 = 0x138;   // lane l - 1 to lane l across the whole wave
 }  // namespace dpp
 
 template <int CTRL, int ROW_MASK = 0xf>

@@ -3,13 +3,13 @@
 //
 // 1. total: the number of tile-list entries (sum of the rect areas), copied
 //    to the host first so that its wait overlaps the steps below.
-// 2. depth ranks: per view, a stable LSD radix sort of (FP32 depth key bits,
-//    Gaussian id) over all waves of the grid (ties keep ascending id), then
-//    runs of equal FP32 keys re-ordered by the FP64 depth (sub-key, id), give
-//    each Gaussian its rank in FP64 depth order and the rank -> id table.
-//    Depths are > znear > 0 for every Gaussian that is emitted, so their IEEE
-//    bits order like the values (culled ones sort anywhere; they are never
-//    emitted).
+// 2. depth ranks: per view, a stable LSD radix sort of (32-bit depth key,
+//    Gaussian id) over all waves of the grid (ties keep ascending id; the key
+//    is monotone in the FP64 depth, see depth_sort_key), then runs of equal
+//    keys re-ordered by the FP64 depth (its bits, then id), give each
+//    Gaussian its rank in FP64 depth order and the rank -> id table. Depths
+//    are > znear > 0 for every Gaussian that is emitted (culled ones sort
+//    anywhere; they are never emitted).
 // 3. hist: the Gaussians of a view in rank order, cut into chunks of kChunk
 //    ranks; one workgroup per (view, chunk) counts its Gaussians per tile in
 //    LDS (the only atomics are LDS atomics: a hot tile can hold thousands of
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kViewThreads) void view_init_kernel(const float* __
                                                                   uint32_t* __restrict__ val) {
   const int64_t i = (int64_t)blockIdx.x * kViewThreads + threadIdx.x;
   if (i >= (int64_t)V * n) return;
-  key[i] = __float_as_uint(rec[i * LMRS_REC + 9]);
+  key[i] = depth_sort_key(depth_bits(rec[i * LMRS_REC + 9], rec[i * LMRS_REC + 11]));
   val[i] = (uint32_t)(i % n);
 }
 
@@ -380,18 +380,18 @@ __global__ __launch_bounds__(kViewThreads) void view_scatter_kernel(const uint32
   part_scatter(ksrc, kdst + vb, vsrc, vdst + vb, b0, b1, shift, kRadixBins, cur[w]);
 }
 
-// ---- ties of the FP32 depth key. The radix passes order a view's Gaussians
-// by (FP32 key, id); a run of equal keys is then re-ordered by (sub-key, id),
-// the sub-key carrying the FP64 depth's bits below the FP32 key (record slot
-// 11), which gives the order of the FP64 depths with ties by id. One wave per
-// 64 ranks; the wave holding the first rank of a run of two or more sorts the
-// run: each member's place is the count of members before it, written to tmp
-// and copied back. Runs already in order are left alone after one pass over
-// them (equal FP64 depths keep the id order of the radix passes), and only
-// keys of positive finite depths are looked at (culled Gaussians are never
-// listed).
-__device__ __forceinline__ uint32_t depth_sub(const float* __restrict__ rec, int64_t vn, uint32_t g) {
-  return __float_as_uint(rec[(vn + g) * LMRS_REC + 11]);
+// ---- ties of the depth key. The radix passes order a view's Gaussians by
+// (32-bit depth key, id); a run of equal keys (depths within 2^-27 relative)
+// is then re-ordered by (FP64 depth bits, id), which gives the order of the
+// FP64 depths with ties by id. One wave per 64 ranks; the wave holding the
+// first rank of a run of two or more sorts the run: each member's place is
+// the count of members before it, written to tmp and copied back. Runs
+// already in order are left alone after one pass over them (equal FP64
+// depths keep the id order of the radix passes), and key 0 (depth <= 0,
+// culled, never listed) is not looked at.
+__device__ __forceinline__ uint64_t depth_of(const float* __restrict__ rec, int64_t vn, uint32_t g) {
+  const float* r = rec + (vn + g) * LMRS_REC;
+  return depth_bits(r[9], r[11]);
 }
 
 __global__ __launch_bounds__(256) void view_ties_kernel(const uint32_t* __restrict__ key, uint32_t* __restrict__ val,
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) void view_ties_kernel(const uint32_t* __restri
   const uint32_t k = i < n ? kv[i] : 0u;
   const bool prev_differs = i == 0 || (i < n && kv[i - 1] != k);
   const bool next_same = i + 1 < n && kv[i + 1] == k;
-  const bool positive = k > 0u && k < 0x7f800000u;
+  const bool positive = k != 0u;  // z > 0
   for (uint64_t heads = __ballot(i < n && prev_differs && next_same && positive); heads; heads &= heads - 1) {
     const int src = __ffsll((unsigned long long)heads) - 1;
     const int a = i0 + src;
@@ -422,17 +422,21 @@ __global__ __launch_bounds__(256) void view_ties_kernel(const uint32_t* __restri
     for (int base = a; base < n; base += kWave) {
       const int j = base + lane;
       const bool in = j < n && kv[j] == K;
-      uint32_t g = 0u, sb = 0u;
+      uint32_t g = 0u;
+      uint64_t sb = 0u;
       if (in) {
         g = ids[j];
-        sb = depth_sub(rec, vn, g);
+        sb = depth_of(rec, vn, g);
       }
       // order against the next member, held by lane + 1 (or the next step's lane 0)
-      const uint32_t g1 = (uint32_t)__shfl_down((int)g, 1), s1 = (uint32_t)__shfl_down((int)sb, 1);
+      const uint32_t g1 = (uint32_t)__shfl_down((int)g, 1);
+      const uint64_t s1 = ((uint64_t)(uint32_t)__shfl_down((int)(uint32_t)(sb >> 32), 1) << 32) |
+                          (uint32_t)__shfl_down((int)(uint32_t)sb, 1);
       bool ok = true;
       if (in && lane < kWave - 1 && j + 1 < n && kv[j + 1] == K) ok = sb < s1 || (sb == s1 && g < g1);
       if (in && lane == kWave - 1 && j + 1 < n && kv[j + 1] == K) {
-        const uint32_t gn = ids[j + 1], sn = depth_sub(rec, vn, gn);
+        const uint32_t gn = ids[j + 1];
+        const uint64_t sn = depth_of(rec, vn, gn);
         ok = sb < sn || (sb == sn && g < gn);
       }
       sorted = sorted && (__ballot(!ok) == 0);
@@ -445,22 +449,26 @@ __global__ __launch_bounds__(256) void view_ties_kernel(const uint32_t* __restri
     if (sorted) continue;
     for (int jb = a; jb < e; jb += kWave) {
       const int j = jb + lane;
-      uint32_t gj = 0xffffffffu, sj = 0xffffffffu;
+      uint32_t gj = 0xffffffffu;
+      uint64_t sj = ~0ull;
       if (j < e) {
         gj = ids[j];
-        sj = depth_sub(rec, vn, gj);
+        sj = depth_of(rec, vn, gj);
       }
       int place = 0;
       for (int mb = a; mb < e; mb += kWave) {
         const int m = mb + lane;
-        uint32_t gm = 0xffffffffu, sm = 0xffffffffu;
+        uint32_t gm = 0xffffffffu;
+        uint64_t sm = ~0ull;
         if (m < e) {
           gm = ids[m];
-          sm = depth_sub(rec, vn, gm);
+          sm = depth_of(rec, vn, gm);
         }
         const int cnt = min(kWave, e - mb);
         for (int q = 0; q < cnt; ++q) {
-          const uint32_t s2 = (uint32_t)readlane((int)sm, q), g2 = (uint32_t)readlane((int)gm, q);
+          const uint64_t s2 = ((uint64_t)(uint32_t)readlane((int)(uint32_t)(sm >> 32), q) << 32) |
+                              (uint32_t)readlane((int)(uint32_t)sm, q);
+          const uint32_t g2 = (uint32_t)readlane((int)gm, q);
           place += (s2 < sj || (s2 == sj && g2 < gj)) ? 1 : 0;
         }
       }
@@ -644,7 +652,7 @@ void launch_bin_count(const lmrs_frame* f, const FrameDims& d, BinScratch b, hip
 }
 
 void launch_view_sort(const lmrs_frame* f, const FrameDims& d, BinScratch b, hipStream_t s) {
-  // depth ranks per view: four 8-bit passes over the FP32 depth bits
+  // depth ranks per view: four 8-bit passes over the 32-bit depth keys
   const int64_t vn = (int64_t)d.V * d.n;
   const int np = (d.n + kViewPart - 1) / kViewPart;
   const unsigned vblocks = (unsigned)((vn + kViewThreads - 1) / kViewThreads);

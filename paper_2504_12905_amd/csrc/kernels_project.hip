@@ -35,9 +35,8 @@ __global__ __launch_bounds__(kBlock) void project_kernel(const float* __restrict
   double tc[3], u, vv;
   decision_point(cv.c, (double)beta[g], (double)beta[(size_t)n + g], (double)beta[(size_t)2 * n + g], tc, &u,
                  &vv);
-  float key;
-  uint32_t sub;
-  depth_keys(tc[2], &key, &sub);
+  float zlo, zhi;
+  depth_words(tc[2], &zlo, &zhi);
   int4 rc = make_int4(0, 0, 0, 0);
   float r[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float radius = 0.f;
@@ -70,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(const float* __restrict
   }
   out[0] = make_float4(r[0], r[1], r[2], r[3]);
   out[1] = make_float4(r[4], r[5], r[6], r[7]);
-  out[2] = make_float4(r[8], key, radius, __uint_as_float(sub));
+  out[2] = make_float4(r[8], zlo, radius, zhi);
   rect[vg] = rc;
 }
 

@@ -222,9 +222,10 @@ __global__ void report_kernel(const double* __restrict__ value, float* __restric
 // caller's capacity (the lists were left empty) the capacity bit joins the
 // failure bits.
 __global__ void report_count_kernel(const int64_t* __restrict__ count, int64_t capacity,
-                                    float* __restrict__ report) {
+                                    float* __restrict__ report, const int64_t* __restrict__ pairs) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   report[LMRS_REP_INST] = (float)count[0];
+  if (pairs) report[LMRS_REP_PAIRS] = (float)pairs[0];
   if (count[0] > capacity) report[LMRS_REP_STATUS] = (float)((int)report[LMRS_REP_STATUS] | LMRS_FAIL_CAPACITY);
 }
 
@@ -568,8 +569,9 @@ void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targe
   if (report) report_kernel<<<1, 64, 0, s>>>(partials + 2 * kRedBlocks, report, LMRS_REP_LOSS);
 }
 
-void launch_report_count(const int64_t* count, int64_t capacity, float* report, hipStream_t s) {
-  report_count_kernel<<<1, 64, 0, s>>>(count, capacity, report);
+void launch_report_count(const int64_t* count, int64_t capacity, float* report, hipStream_t s,
+                         const int64_t* pairs) {
+  report_count_kernel<<<1, 64, 0, s>>>(count, capacity, report, pairs);
 }
 
 void launch_dot(const float* a, const float* b, int64_t n, double* partials, double* out, hipStream_t s) {

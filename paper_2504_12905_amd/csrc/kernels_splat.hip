@@ -75,6 +75,14 @@ __device__ __forceinline__ RecF load_rec(const float* rec, size_t vg) {
   return RecF{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
 }
 
+// The footprint part of a record (u, v, f11, f12, f22, opacity): two loads.
+__device__ __forceinline__ RecF load_geo(const float* rec, size_t vg) {
+  const float* p = rec + vg * LMRS_REC;
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  const float2 b = *reinterpret_cast<const float2*>(p + 4);
+  return RecF{a.x, a.y, a.z, a.w, b.x, b.y, 0.f, 0.f, 0.f};
+}
+
 // List id at entry c0 + lane of the tile, -1 past the end of the list.
 __device__ __forceinline__ int fwd_chunk_id(const int32_t* ids, const TileCtx& c, int c0) {
   const int e = c0 + lane_id();
@@ -297,7 +305,8 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
                                                        int TX, int k, lmrs_render_opts o,
                                                        float* __restrict__ color, float* __restrict__ trans,
                                                        int32_t* __restrict__ last,
-                                                       int32_t* __restrict__ walk_len) {
+                                                       int32_t* __restrict__ walk_len,
+                                                       int64_t* __restrict__ pair_count) {
   const int lane = lane_id();
   const int wv = uniform((int)(threadIdx.x / kWave));
   const bool mine = (lane & (W - 1)) == wv;
@@ -318,6 +327,7 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
 #pragma unroll
   for (int m = 0; m < (ACC ? MP : 1); ++m) A0[m] = A1[m] = A2[m] = 0.f;
   int remaining = k / W + (wv < k % W ? 1 : 0);  // this wave's pixels
+  int npairs = 0;  // blending (pixel, entry) pairs of this wave's pixels
   for (int c0 = 0; c0 < c.len && remaining > 0; c0 += kWave) {
     const bool valid = c0 + lane < c.len;
     RecF r{};
@@ -347,6 +357,7 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
         sC2[s] = writelane(sC2[s], readlane(sC2[s], l) + cb, l);
       }
       const uint64_t okm = __ballot(ok);
+      npairs += __popcll(okm);
       const float Tnext = f < kWave ? readlane(Tex, f) : readlane(Taft, kWave - 1);
       sT[s] = writelane(sT[s], Tnext, l);
       if (okm) sLast[s] = writelane(sLast[s], c0 + 63 - __clzll((long long)okm), l);
@@ -396,13 +407,54 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
 #pragma unroll
   for (int s = 0; s < NS; ++s) steps += mine && sLast[s] >= 0 ? sLast[s] / kWave + 1 : 0;
   __shared__ float part[W];
+  __shared__ int part_pairs[W];
   const float total = wave_total((float)steps);  // a sort key: exact up to 2^24 steps
-  if (lane == 0) part[wv] = total;
+  if (lane == 0) {
+    part[wv] = total;
+    part_pairs[wv] = npairs;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     float sum = 0.f;
-    for (int w = 0; w < W; ++w) sum += part[w];
+    int64_t pairs = 0;
+    for (int w = 0; w < W; ++w) {
+      sum += part[w];
+      pairs += part_pairs[w];
+    }
     walk_len[c.tile_lin] = (int32_t)sum;
+    if (pair_count) pair_count[c.tile_lin] = pairs;
+  }
+}
+
+// Blend-table offsets: the per-tile pair counts the render wrote into
+// start[0, m) become exclusive offsets; start[m] = total, start[m + 1] = 0
+// (the table is stale until the reverse walk rebuilds it). One workgroup;
+// each thread scans a contiguous block of tiles.
+constexpr int kBlendScanThreads = 1024;
+__global__ __launch_bounds__(kBlendScanThreads) void blend_scan_kernel(int64_t* __restrict__ start, int64_t m) {
+  __shared__ int64_t s_part[kBlendScanThreads];
+  const int tid = threadIdx.x;
+  const int64_t per = (m + kBlendScanThreads - 1) / kBlendScanThreads;
+  const int64_t a = min(m, tid * per), b = min(m, a + per);
+  int64_t acc = 0;
+  for (int64_t i = a; i < b; ++i) acc += start[i];
+  s_part[tid] = acc;
+  __syncthreads();
+  for (int d = 1; d < kBlendScanThreads; d <<= 1) {
+    const int64_t y = tid >= d ? s_part[tid - d] : 0;
+    __syncthreads();
+    s_part[tid] += y;
+    __syncthreads();
+  }
+  int64_t run = s_part[tid] - acc;
+  for (int64_t i = a; i < b; ++i) {
+    const int64_t x = start[i];
+    start[i] = run;
+    run += x;
+  }
+  if (tid == kBlendScanThreads - 1) {
+    start[m] = s_part[tid];
+    start[m + 1] = 0;
   }
 }
 
@@ -816,9 +868,10 @@ __global__ __launch_bounds__(kWave* W) void deriv_kernel(
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
     const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
     lmrs_render_opts o, const float* __restrict__ u_in, float* __restrict__ jp_out,
-    float* __restrict__ grad2d, int32_t* __restrict__ sched, int tiles) {
+    float* __restrict__ grad2d, int32_t* __restrict__ sched, int tiles, const int64_t* __restrict__ built) {
   __shared__ int next_tile[2];
   __shared__ float red[MODE == 1 ? 1 : 2 * kRedBuf<W>];
+  if (built && *built == 1) return;  // the blend table holds this render: blend_gn_kernel ran instead
   const int wv = uniform((int)(threadIdx.x / kWave));
   const SchedRef sr = sched_ref(sched, tiles);
   const int count = sched_count(sr, MODE != 1);
@@ -844,14 +897,48 @@ __global__ __launch_bounds__(kWave* W) void deriv_kernel(
 // same walk: the colour behind an entry seen through u is sum_c u_c times the
 // per-channel colour behind, so the right-hand side b = J^T W r of an LM step
 // costs no walk of its own.
-template <int NS, bool VJP>
+//
+// With a blend table to fill (BlendOut::on) the walk also writes one record
+// per blending (pixel, entry) pair: K = d C / d alpha per channel (the
+// quantity ga below; 0 when alpha is capped) and alpha T, with the Gaussian
+// id and the sample slot, twice. A tile's pairs start at blend_start[tile],
+// the chunks back to front; inside a chunk's block the first copy is grouped
+// by entry (an entry's pixels in slot order; each entry's pairs form runs of
+// at most kBlendRun, whose starts go to blend_run), the second, at offset
+// blend_capacity, by pixel (a pixel's entries in lane order). A first pass
+// over the chunk's pixels counts each entry's pairs so that every lane knows
+// where its entry-grouped pairs go; the pixel-grouped ones follow from a
+// ballot per pixel.
+constexpr int kBlendRun = 32;
+
+struct BlendOut {
+  float4* k;
+  uint32_t* m;
+  int32_t* run;
+  int32_t* runs;
+  const int64_t* start;
+  bool on;
+  int64_t pix_major;  // offset of the pixel-major copy in k and m (the capacity)
+};
+
+__device__ __forceinline__ int wave_excl_scan_i(int x) {
+  int y = x;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int z = __shfl_up(y, d, kWave);
+    if (lane_id() >= d) y += z;
+  }
+  return y - x;
+}
+
+template <int NS, bool VJP, bool GRAM>
 __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const int64_t* __restrict__ tile_start,
                                           const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix,
                                           const float* __restrict__ wts, const float* __restrict__ trans,
                                           const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
                                           const lmrs_render_opts& o, float* __restrict__ gram,
                                           const float* __restrict__ u_in, float* __restrict__ grad2d,
-                                          int64_t tile_lin, float* tr, int* tr_id) {
+                                          const BlendOut& bo, int64_t tile_lin, float* tr, int* tr_id) {
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX, tile_lin);
   PixelRegs<NS> pr;
@@ -873,6 +960,12 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
     }
   }
   if (lmax < 0) return;
+  const int64_t blend_base = bo.on ? bo.start[c.tile_lin] : 0;
+  // the render counted the tile's pairs with the same opacity tests; writes
+  // stay inside the tile's range regardless
+  const int64_t blend_end = bo.on ? bo.start[c.tile_lin + 1] : 0;
+  int64_t blend_cursor = 0;  // pairs of the tile written so far
+  int run_cursor = 0;        // runs of the tile written so far
   for (int c0 = (lmax / kWave) * kWave; c0 >= 0; c0 -= kWave) {
     const int e = c0 + (kWave - 1 - lane);
     const bool valid = e < c.len;
@@ -882,8 +975,36 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
       id = ids[c.start + e];
       r = load_rec(rec, (size_t)c.v * n + id);
     }
-    float G[kGram], g[9];
-    for (int q = 0; q < kGram; ++q) G[q] = 0.f;
+    int64_t my_pair = 0, chunk_block = 0;
+    if (bo.on) {
+      // the pixels that blend this lane's entry, counted first
+      int cnt = 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int ccount = min(kWave, k - s * kWave);
+        for (int l = 0; l < ccount; ++l) {
+          const int lj = readlane(pr.last[s], l);
+          if (c0 > lj) continue;
+          const Alpha al =
+              pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
+          cnt += (valid && e <= lj && al.inc) ? 1 : 0;
+        }
+      }
+      const int pieces = (cnt + kBlendRun - 1) / kBlendRun;
+      const int off = wave_excl_scan_i(cnt), roff = wave_excl_scan_i(pieces);
+      const int tot = readlane(off + cnt, kWave - 1), rtot = readlane(roff + pieces, kWave - 1);
+      for (int j = 0; j < pieces; ++j) {
+        const int64_t at = blend_base + run_cursor + roff + j;
+        if (at < blend_end) bo.run[at] = (int32_t)(blend_cursor + off + j * kBlendRun);
+      }
+      my_pair = blend_base + blend_cursor + off;
+      chunk_block = blend_base + blend_cursor;
+      blend_cursor += tot;
+      run_cursor += rtot;
+    }
+    int64_t pix_cursor = 0;  // pixel-major copy: pairs of the chunk written so far
+    float G[GRAM ? kGram : 1], g[9];
+    for (int q = 0; q < (GRAM ? kGram : 1); ++q) G[q] = 0.f;
     for (int q = 0; q < 9; ++q) g[q] = 0.f;
     const float rgb[3] = {r.r, r.g, r.b};
 #pragma unroll
@@ -895,6 +1016,12 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
         const Alpha al =
             pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, readlane(pr.xc[s], l), readlane(pr.yc[s], l), o);
         const bool inc = valid && e <= lj && al.inc;
+        int64_t my_pix_pair = 0;
+        if (bo.on) {  // pixel-major copy: this pixel's pairs in lane order
+          const uint64_t incm = __ballot(inc);
+          my_pix_pair = chunk_block + pix_cursor + __popcll(incm & ((1ull << lane) - 1ull));
+          pix_cursor += __popcll(incm);
+        }
         const float a = inc ? al.a : 0.f;
         const float rP = __builtin_amdgcn_rcpf(scan_mul(inc ? 1.f - a : 1.f));
         const float Tafter = readlane(sT[s], l);
@@ -910,7 +1037,7 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
         if (inc) {
           const float wj = readlane(pr.w[s], l);
           const float aT = a * Tn;
-          G[30] += wj * aT * aT;
+          if (GRAM) G[GRAM ? 30 : 0] += wj * aT * aT;
           float u[3] = {0.f, 0.f, 0.f};
           if (VJP) {
             u[0] = readlane(sU0[s], l);
@@ -920,8 +1047,9 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
             g[7] += u[1] * aT;
             g[8] += u[2] * aT;
           }
+          float ga[3] = {0.f, 0.f, 0.f};
           if (!al.capped) {
-            float ga[3], sga2 = 0.f;
+            float sga2 = 0.f;
             const float iom = __builtin_amdgcn_rcpf(1.f - a);
             for (int ch = 0; ch < 3; ++ch) {
               ga[ch] = Tn * rgb[ch] - behind[ch] * iom;
@@ -929,18 +1057,31 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
             }
             const float h[5] = {-(al.q1 * r.f11), -(al.q1 * r.f12 + al.q2 * r.f22), -(al.q1 * al.dx),
                                 -(al.q1 * al.dy), -(al.q2 * al.dy)};
-            const float fg = wj * a * a * sga2;
-            for (int p = 0; p < 5; ++p) {
-              for (int q = p; q < 5; ++q) G[sym5(p, q)] += fg * h[p] * h[q];
-              for (int ch = 0; ch < 3; ++ch) G[15 + 3 * p + ch] += wj * ga[ch] * a * h[p] * aT;
+            if (GRAM) {
+              const float fg = wj * a * a * sga2;
+              for (int p = 0; p < 5; ++p) {
+                for (int q = p; q < 5; ++q) G[GRAM ? sym5(p, q) : 0] += fg * h[p] * h[q];
+                for (int ch = 0; ch < 3; ++ch) G[GRAM ? 15 + 3 * p + ch : 0] += wj * ga[ch] * a * h[p] * aT;
+              }
+              G[GRAM ? 31 : 0] += wj * sga2 * al.es * al.es;
             }
-            G[31] += wj * sga2 * al.es * al.es;
             if (VJP) {
               const float gu = u[0] * ga[0] + u[1] * ga[1] + u[2] * ga[2];
               g[5] += gu * al.es;
               for (int p = 0; p < 5; ++p) g[p] += gu * a * h[p];
             }
           }
+          if (bo.on && my_pair < blend_end) {
+            const float4 kv = make_float4(ga[0], ga[1], ga[2], aT);
+            const uint32_t mv = ((uint32_t)id << 8) | (uint32_t)(s * kWave + l);
+            bo.k[my_pair] = kv;
+            bo.m[my_pair] = mv;
+            if (my_pix_pair < blend_end) {
+              bo.k[bo.pix_major + my_pix_pair] = kv;
+              bo.m[bo.pix_major + my_pix_pair] = mv;
+            }
+          }
+          ++my_pair;
         }
         sT[s] = writelane(sT[s], Tafter * readlane(rP, kWave - 1), l);
         sS0[s] = writelane(sS0[s], S[0] + tot[0], l);
@@ -948,19 +1089,19 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
         sS2[s] = writelane(sS2[s], S[2] + tot[2], l);
       }
     }
-    // Gram flush, transposed through LDS: the atomic instruction t covers
-    // entries 2t and 2t + 1 with lanes holding their 32 components, so that
-    // each instruction updates two Gaussians' 128-byte Gram rows instead of
-    // one word in each of 64 rows.
-#pragma unroll
-    for (int q = 0; q < kGram; ++q) tr[q * (kWave + 1) + lane] = G[q];
     tr_id[lane] = valid ? id : -1;
-    {
+    if (GRAM) {
+      // Gram flush, transposed through LDS: the atomic instruction t covers
+      // entries 2t and 2t + 1 with lanes holding their 32 components, so that
+      // each instruction updates two Gaussians' 128-byte Gram rows instead of
+      // one word in each of 64 rows.
+#pragma unroll
+      for (int q = 0; q < (GRAM ? kGram : 1); ++q) tr[q * (kWave + 1) + lane] = G[q];
       const int q = lane & (kGram - 1), half = lane >> 5;
       for (int t = 0; t < kWave / 2; ++t) {
-        const int e = 2 * t + half;
-        const int ide = tr_id[e];
-        const float val = tr[q * (kWave + 1) + e];
+        const int e2 = 2 * t + half;
+        const int ide = tr_id[e2];
+        const float val = tr[q * (kWave + 1) + e2];
         if (ide >= 0 && val != 0.f) atomicAdd(&gram[((size_t)c.v * n + ide) * kGram + q], val);
       }
     }
@@ -969,16 +1110,17 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
       for (int q = 0; q < 9; ++q) tr[q * (kWave + 1) + lane] = g[q];
       const int q = lane & (kGradRow - 1);
       for (int t = 0; t < kWave / 4; ++t) {
-        const int e = 4 * t + (lane >> 4);
-        const int ide = tr_id[e];
-        const float val = q < 9 ? tr[q * (kWave + 1) + e] : 0.f;
+        const int e2 = 4 * t + (lane >> 4);
+        const int ide = tr_id[e2];
+        const float val = q < 9 ? tr[q * (kWave + 1) + e2] : 0.f;
         if (ide >= 0 && val != 0.f) atomicAdd(&grad2d[((size_t)c.v * n + ide) * kGradRow + q], val);
       }
     }
   }
+  if (bo.on && lane == 0) bo.runs[c.tile_lin] = run_cursor;
 }
 
-template <int NS, bool VJP>
+template <int NS, bool VJP, bool GRAM>
 __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ rec,
                                                      const int64_t* __restrict__ tile_start,
                                                      const int32_t* __restrict__ ids,
@@ -989,19 +1131,335 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
                                                      int TX, int k, lmrs_render_opts o,
                                                      float* __restrict__ gram, const float* __restrict__ u_in,
                                                      float* __restrict__ grad2d, int32_t* __restrict__ sched,
-                                                     int tiles) {
-  __shared__ float tr[kGram * (kWave + 1)];  // Gram flush transpose (padded rows: no bank conflicts)
+                                                     int tiles, BlendOut bo, int64_t blend_capacity) {
+  __shared__ float tr[kGram * (kWave + 1)];  // flush transposes (padded rows: no bank conflicts)
   __shared__ int tr_id[kWave];
   const SchedRef sr = sched_ref(sched, tiles);
   const int count = sched_count(sr, true);
+  // the table is written only when the render's pair count fits
+  bo.on = bo.on && bo.start[tiles] <= blend_capacity;
   for (;;) {
     const int tile = sched_next(sr, count);
     if (tile == -1) break;
     if (tile >= 0)
-      gram_tile<NS, VJP>(rec, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, gram, u_in, grad2d, tile,
-                         tr, tr_id);
+      gram_tile<NS, VJP, GRAM>(rec, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, gram, u_in, grad2d,
+                               bo, tile, tr, tr_id);
   }
   sched_finish(sr);
+}
+
+// After the walk that fills the blend table: built iff the pairs fitted.
+__global__ void blend_built_kernel(int64_t* __restrict__ start, int64_t m, int64_t capacity) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) start[m + 1] = start[m] <= capacity ? 1 : 0;
+}
+
+// ------------------------------------------------- GN product from the table
+// J^T W J p (eq. 14) over the blend table instead of the tile lists. Per
+// tile (one workgroup of kBlendGnThreads, one workgroup per busy tile in the
+// schedule's order, longest first), lanes take consecutive pairs of the
+// tile's table (the pixel-grouped copy, then the Gaussian-grouped one), so
+// every load of the table is coalesced:
+//  1. J p, over the pixel-grouped copy of the table: each pair's
+//     d C = a T d rgb + K d a (d a from its Gaussian's screen record and
+//     tangent record, gathered; the pixel centre from LDS), summed over the
+//     lanes holding the same pixel by a segmented DPP scan; one LDS atomic
+//     per pixel segment (per-pair LDS float atomics took 0.19 ms for this
+//     phase on the 100k workload against 0.07 with plain stores);
+//  2. u = w J p in place;
+//  3. J^T u: each pair's record gradient, (u . K) d a / d rec and a T u on
+//     the colour, then a segmented sum over the lanes holding the same
+//     Gaussian (the table keeps a Gaussian's pairs together): DPP shifts
+//     inside rows of 16 lanes and row broadcasts across them, each step
+//     masked by the distance to the segment head. The last lane of each
+//     segment hands its sums to a transposed flush through LDS (one atomic
+//     instruction per 4 Gaussians' 64-byte rows).
+// The opacity, exponent and their record derivatives are recomputed from the
+// screen record and the pixel centre (pair_alpha, the render's own
+// arithmetic), so a pair costs 20 bytes of table.
+constexpr int kBlendGnThreads = 256;
+constexpr int kBlendGnWaves = kBlendGnThreads / kWave;
+
+// Inclusive sums over each segment of consecutive lanes (dist = lane minus
+// the segment's first lane): per step, x += x[source] * keep, keep = 1 when
+// the source lane lies in the same segment, as one v_fmac_f32_dpp (DPP on
+// the first operand; a lane without a source in its row, or outside the row
+// mask, keeps its value). Steps: row shifts by 1, 2, 4, 8, then the row-15
+// and row-31 broadcasts. The components of a step are independent, which
+// covers the two wait states a DPP read needs after a VALU write of the same
+// register; the s_nop at either end covers the code around.
+__device__ __forceinline__ void seg_scan3(float (&g)[3], int dist) {
+  const int lane = lane_id();
+  const float k1 = dist >= 1 ? 1.f : 0.f, k2 = dist >= 2 ? 1.f : 0.f, k4 = dist >= 4 ? 1.f : 0.f,
+              k8 = dist >= 8 ? 1.f : 0.f;
+  const float k15 = dist > (lane & 15) ? 1.f : 0.f, k31 = dist > (lane & 31) ? 1.f : 0.f;
+  asm volatile("s_nop 1\n\t"
+               "v_fmac_f32_dpp %0, %0, %3 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %3 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %3 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2])
+               : "v"(k1));
+  asm volatile("v_fmac_f32_dpp %0, %0, %3 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %3 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %3 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2])
+               : "v"(k2));
+  asm volatile("v_fmac_f32_dpp %0, %0, %3 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %3 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %3 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2])
+               : "v"(k4));
+  asm volatile("v_fmac_f32_dpp %0, %0, %3 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %3 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %3 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2])
+               : "v"(k8));
+  asm volatile("v_fmac_f32_dpp %0, %0, %3 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %3 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %3 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2])
+               : "v"(k15));
+  asm volatile("v_fmac_f32_dpp %0, %0, %3 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %3 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %3 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "s_nop 1"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2])
+               : "v"(k31));
+}
+
+__device__ __forceinline__ void seg_scan9(float (&g)[9], int dist) {
+  const int lane = lane_id();
+  const float k1 = dist >= 1 ? 1.f : 0.f, k2 = dist >= 2 ? 1.f : 0.f, k4 = dist >= 4 ? 1.f : 0.f,
+              k8 = dist >= 8 ? 1.f : 0.f;
+  const float k15 = dist > (lane & 15) ? 1.f : 0.f, k31 = dist > (lane & 31) ? 1.f : 0.f;
+  asm volatile("s_nop 1\n\t"
+               "v_fmac_f32_dpp %0, %0, %9 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %9 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %9 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %3, %3, %9 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %4, %4, %9 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %5, %5, %9 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %6, %6, %9 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %7, %7, %9 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %8, %8, %9 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]), "+v"(g[8])
+               : "v"(k1));
+  asm volatile("v_fmac_f32_dpp %0, %0, %9 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %9 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %9 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %3, %3, %9 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %4, %4, %9 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %5, %5, %9 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %6, %6, %9 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %7, %7, %9 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %8, %8, %9 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]), "+v"(g[8])
+               : "v"(k2));
+  asm volatile("v_fmac_f32_dpp %0, %0, %9 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %9 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %9 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %3, %3, %9 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %4, %4, %9 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %5, %5, %9 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %6, %6, %9 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %7, %7, %9 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %8, %8, %9 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]), "+v"(g[8])
+               : "v"(k4));
+  asm volatile("v_fmac_f32_dpp %0, %0, %9 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %9 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %9 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %3, %3, %9 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %4, %4, %9 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %5, %5, %9 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %6, %6, %9 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %7, %7, %9 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %8, %8, %9 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]), "+v"(g[8])
+               : "v"(k8));
+  asm volatile("v_fmac_f32_dpp %0, %0, %9 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %9 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %9 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %3, %3, %9 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %4, %4, %9 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %5, %5, %9 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %6, %6, %9 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %7, %7, %9 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %8, %8, %9 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]), "+v"(g[8])
+               : "v"(k15));
+  asm volatile("v_fmac_f32_dpp %0, %0, %9 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %1, %1, %9 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %2, %2, %9 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %3, %3, %9 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %4, %4, %9 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %5, %5, %9 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %6, %6, %9 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %7, %7, %9 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "v_fmac_f32_dpp %8, %8, %9 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+               "s_nop 1"
+               : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]), "+v"(g[8])
+               : "v"(k31));
+}
+
+__global__ __launch_bounds__(kBlendGnThreads) void blend_gn_kernel(
+    const float* __restrict__ rec, const float* __restrict__ tan, const float4* __restrict__ bk,
+    const uint32_t* __restrict__ bm, const int64_t* __restrict__ bstart, const uint8_t* __restrict__ pix,
+    const float* __restrict__ wts, int n, int T, int TX, int k, lmrs_render_opts o, float* __restrict__ grad2d,
+    int32_t* __restrict__ sched, int tiles, int64_t pix_major) {
+  __shared__ float4 s_u[kMaxK];    // J p, then u, of each sample slot (4th word unused)
+  __shared__ float2 s_xy[kMaxK];  // pixel centre of each sample slot
+  __shared__ float s_tr[kBlendGnWaves][9 * (kWave + 1)];
+  __shared__ int s_id[kBlendGnWaves][kWave];
+  if (bstart[tiles + 1] != 1) return;  // no table for this render: the list walk runs instead
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+  const uint64_t below = (1ull << lane) - 1ull;
+  // one workgroup per busy tile, the longest first (the dispatcher hands out
+  // workgroups in index order as CUs free up: no shared ticket counter)
+  const SchedRef sr = sched_ref(sched, tiles);
+  if ((int)blockIdx.x >= sched_count(sr, true)) return;
+  {
+    const int tile = sr.order[blockIdx.x];
+    if ((unsigned)tile >= (unsigned)tiles) return;
+    const int v = tile / T, t = tile % T;
+    const float ox = (float)((t % TX) * kTile), oy = (float)((t / TX) * kTile);
+    const int64_t ps = bstart[tile], pe = bstart[tile + 1];
+    const size_t vb = (size_t)v * n;
+    for (int j = tid; j < k; j += kBlendGnThreads) {
+      const int p = pix ? (int)pix[(int64_t)tile * k + j] : j;
+      s_xy[j] = make_float2(ox + (float)(p & 15) + 0.5f, oy + (float)(p >> 4) + 0.5f);
+      s_u[j] = float4{};
+    }
+    __syncthreads();
+    // 1. J p at the tile's sampled pixels, over the pixel-grouped copy of
+    // the table (64 consecutive pairs per wave step; the table entry two steps
+    // ahead and the records one step ahead in flight): each pair's
+    // d C = a T d rgb + K d a, summed over the lanes of the same pixel, the
+    // last lane of each pixel adding the sums into its LDS slot
+    {
+      const float4* __restrict__ pk = bk + pix_major;
+      const uint32_t* __restrict__ pm = bm + pix_major;
+      const RecF zero{};
+      auto valid_g = [&](uint32_t m) { return m != 0xffffffffu && (int)(m >> 8) < n; };
+      int64_t i = ps + (int64_t)wv * kWave + lane;
+      uint32_t m1 = 0xffffffffu, m2 = 0xffffffffu;
+      float4 k1{}, k2{};
+      RecF r1 = zero, d1 = zero;
+      if (i < pe) { m1 = pm[i]; k1 = pk[i]; }
+      if (i + kBlendGnThreads < pe) { m2 = pm[i + kBlendGnThreads]; k2 = pk[i + kBlendGnThreads]; }
+      if (valid_g(m1)) { r1 = load_geo(rec, vb + (m1 >> 8)); d1 = load_rec(tan, vb + (m1 >> 8)); }
+      for (int64_t base = ps + (int64_t)wv * kWave; base < pe; base += kBlendGnThreads, i += kBlendGnThreads) {
+        const uint32_t m0 = m1;
+        const float4 kk = k1;
+        const RecF r = r1, dr = d1;
+        m1 = m2; k1 = k2;
+        m2 = 0xffffffffu;
+        if (i + 2 * kBlendGnThreads < pe) { m2 = pm[i + 2 * kBlendGnThreads]; k2 = pk[i + 2 * kBlendGnThreads]; }
+        if (valid_g(m1)) { r1 = load_geo(rec, vb + (m1 >> 8)); d1 = load_rec(tan, vb + (m1 >> 8)); }
+        int j = (int)(m0 & 255u);
+        if (!valid_g(m0) || j >= k) j = -1;  // not a pair of this frame
+        float dc[3] = {0.f, 0.f, 0.f};
+        if (j >= 0) {
+          const float2 xy = s_xy[j];
+          const Alpha al = pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, xy.x, xy.y, o);
+          const float ds = -al.q1 * (dr.f11 * al.dx + dr.f12 * al.dy + r.f11 * dr.u + r.f12 * dr.v) -
+                           al.q2 * (dr.f22 * al.dy + r.f22 * dr.v);
+          const float da = al.es * (dr.o + r.o * ds);  // multiplies K, which is 0 when alpha is capped
+          dc[0] = dr.r * kk.w + kk.x * da;
+          dc[1] = dr.g * kk.w + kk.y * da;
+          dc[2] = dr.b * kk.w + kk.z * da;
+        }
+        const int prev = __builtin_amdgcn_update_dpp(-2, j, dpp::kWaveShr1, 0xf, 0xf, false);
+        const uint64_t heads = __ballot(lane == 0 || j != prev);
+        const int dist = lane - (63 - __clzll((long long)(heads & (below | (1ull << lane)))));
+        seg_scan3(dc, dist);
+        const bool is_end = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ull);
+        if (is_end && j >= 0) {
+          atomicAdd(&s_u[j].x, dc[0]);
+          atomicAdd(&s_u[j].y, dc[1]);
+          atomicAdd(&s_u[j].z, dc[2]);
+        }
+      }
+    }
+    __syncthreads();
+    // 2. u = w J p
+    for (int j = tid; j < k; j += kBlendGnThreads) {
+      const float w = wts ? wts[(int64_t)tile * k + j] : 1.f;
+      const float4 x = s_u[j];
+      s_u[j] = make_float4(x.x * w, x.y * w, x.z * w, 0.f);
+    }
+    __syncthreads();
+    // 3. J^T u over 64 consecutive pairs per wave step, pipelined like 1.
+    const RecF zero_r{};
+    int64_t base = ps + (int64_t)wv * kWave;
+    uint32_t n1 = 0xffffffffu, n2 = 0xffffffffu;
+    float4 c1{}, c2{};
+    RecF q1r = zero_r;
+    auto ok_g = [&](uint32_t m) { return m != 0xffffffffu && (int)(m >> 8) < n; };
+    if (base + lane < pe) { n1 = bm[base + lane]; c1 = bk[base + lane]; }
+    if (base + kBlendGnThreads + lane < pe) { n2 = bm[base + kBlendGnThreads + lane]; c2 = bk[base + kBlendGnThreads + lane]; }
+    if (ok_g(n1)) q1r = load_geo(rec, vb + (n1 >> 8));
+    for (; base < pe; base += kBlendGnThreads) {
+      const uint32_t m = n1;
+      const float4 kk = c1;
+      const RecF r = q1r;
+      n1 = n2; c1 = c2;
+      n2 = 0xffffffffu;
+      if (base + 2 * kBlendGnThreads + lane < pe) {
+        n2 = bm[base + 2 * kBlendGnThreads + lane];
+        c2 = bk[base + 2 * kBlendGnThreads + lane];
+      }
+      if (ok_g(n1)) q1r = load_geo(rec, vb + (n1 >> 8));
+      float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      int gid = -1;
+      {
+        const int j = (int)(m & 255u);
+        if (ok_g(m) && j < k) {
+          gid = (int)(m >> 8);
+          const float2 xy = s_xy[j];
+          const Alpha al = pair_alpha(r.u, r.v, r.f11, r.f12, r.f22, r.o, xy.x, xy.y, o);
+          const float4 uu = s_u[j];
+          const float u0 = uu.x, u1 = uu.y, u2 = uu.z;
+          g[6] = u0 * kk.w;
+          g[7] = u1 * kk.w;
+          g[8] = u2 * kk.w;
+          const float ga = kk.x * u0 + kk.y * u1 + kk.z * u2;
+          const float gs = ga * al.a;
+          g[5] = ga * al.es;
+          g[0] = -(gs * (al.q1 * r.f11));
+          g[1] = -(gs * (al.q1 * r.f12 + al.q2 * r.f22));
+          g[2] = -(gs * (al.q1 * al.dx));
+          g[3] = -(gs * (al.q1 * al.dy));
+          g[4] = -(gs * (al.q2 * al.dy));
+        }
+      }
+      // segments: lanes holding the same Gaussian (consecutive in the table)
+      const int prev = __builtin_amdgcn_update_dpp(-2, gid, dpp::kWaveShr1, 0xf, 0xf, false);
+      const uint64_t heads = __ballot(lane == 0 || gid != prev);
+      const int dist = lane - (63 - __clzll((long long)(heads & (below | (1ull << lane)))));
+      seg_scan9(g, dist);
+      // the last lane of each segment hands its Gaussian's sums to a
+      // transposed flush: an atomic instruction covers 4 Gaussians' rows
+      const uint64_t ends = (heads >> 1) | (1ull << 63);
+      const bool is_end = (ends >> lane) & 1ull;
+      const int slot = __popcll(ends & below);
+      const int nseg = __popcll(ends);
+      float* tr = s_tr[wv];
+      if (is_end) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) tr[q * (kWave + 1) + slot] = g[q];
+        s_id[wv][slot] = gid;
+      }
+      const int q = lane & (kGradRow - 1);
+      for (int e = 0; 4 * e < nseg; ++e) {
+        const int ent = 4 * e + (lane >> 4);
+        if (ent < nseg && q < 9) {
+          const int ide = s_id[wv][ent];
+          const float val = tr[q * (kWave + 1) + ent];
+          if (ide >= 0 && val != 0.f) atomicAdd(&grad2d[(vb + ide) * kGradRow + q], val);
+        }
+      }
+    }
+  }
 }
 
 // Waves of a persistent splat launch: one per kTilesPerWave tiles of the
@@ -1124,7 +1582,7 @@ void launch_render_w(const lmrs_frame* f, const FrameDims& d, const lmrs_render_
   const int per_wave = (d.k + W - 1) / W;
   auto go = [&](auto kern) {
     kern<<<tiles, kWave * W, 0, s>>>(f->rec, f->tile_start, f->ids, f->pix, d.n, d.T, d.TX, d.k, o, f->color,
-                                     f->trans, f->last, walk_len);
+                                     f->trans, f->last, walk_len, f->blend_k ? f->blend_start : nullptr);
   };
   if (d.k > kWave) go(render_kernel<4, W, 1>);
   else if (per_wave <= 8) go(render_kernel<1, W, 8>);
@@ -1138,6 +1596,7 @@ void launch_render(const lmrs_frame* f, const FrameDims& d, const lmrs_render_op
   else launch_render_w<1>(f, d, o, s);
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   sched_kernel<<<1, kSchedThreads, 0, s>>>(f->sched, (int)tiles);
+  if (f->blend_k) blend_scan_kernel<<<1, kBlendScanThreads, 0, s>>>(f->blend_start, (int64_t)tiles);
 }
 
 void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
@@ -1156,7 +1615,7 @@ void launch_render_counts(const lmrs_frame* f, const FrameDims& d, const lmrs_re
 
 template <int MODE, int W>
 void launch_deriv_mode(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* tan,
-                       const float* u, float* jp, float* grad2d, hipStream_t s) {
+                       const float* u, float* jp, float* grad2d, hipStream_t s, const int64_t* built) {
   static_assert(kWave % W == 0, "pixel slots are dealt to the waves by lane");
   const int tiles = d.V * d.T;
   const unsigned grid = persistent_groups(tiles, W);
@@ -1167,7 +1626,7 @@ void launch_deriv_mode(const lmrs_frame* f, const FrameDims& d, const lmrs_rende
   const int mp = W > 1 && small && d.k <= 8 * W ? (d.k + W - 1) / W : 1;
   auto go = [&](auto kern) {
     kern<<<grid, block, 0, s>>>(f->rec, tan, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T,
-                                d.TX, d.k, o, u, jp, grad2d, f->sched, tiles);
+                                d.TX, d.k, o, u, jp, grad2d, f->sched, tiles, built);
   };
   if (!small) {
     go(deriv_kernel<MODE, 4, W, 1>);
@@ -1182,39 +1641,58 @@ void launch_deriv_mode(const lmrs_frame* f, const FrameDims& d, const lmrs_rende
 
 template <int W>
 void launch_deriv_w(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
-                    const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s) {
-  if (mode == 1) launch_deriv_mode<1, W>(f, d, o, tan, u, jp, grad2d, s);
-  else if (mode == 2) launch_deriv_mode<2, W>(f, d, o, tan, u, jp, grad2d, s);
-  else launch_deriv_mode<3, W>(f, d, o, tan, u, jp, grad2d, s);
+                    const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s,
+                    const int64_t* built) {
+  if (mode == 1) launch_deriv_mode<1, W>(f, d, o, tan, u, jp, grad2d, s, nullptr);
+  else if (mode == 2) launch_deriv_mode<2, W>(f, d, o, tan, u, jp, grad2d, s, nullptr);
+  else launch_deriv_mode<3, W>(f, d, o, tan, u, jp, grad2d, s, built);
 }
 
 void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o,
                   const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s) {
+  // the fused walk (mode 3) steps aside when the blend table is built
+  const int64_t* built = mode == 3 && f->blend_k ? f->blend_start + (int64_t)d.V * d.T + 1 : nullptr;
   // Measured: 4 waves per tile at 26 samples per tile (100k workload) took the
   // fused splat from 0.59 to 0.535 ms with pixels dealt by slot. At 13 samples
   // (1.5M workload) 2 or 4 slot-dealt waves were slower than one (9.24 and
   // 9.47 against 9.13 ms); 2 waves with pixels dealt by depth are faster
   // (4.07 -> 3.90 ms).
-  if (d.k >= 24) launch_deriv_w<4>(mode, f, d, o, tan, u, jp, grad2d, s);
-  else if (d.k >= 12) launch_deriv_w<2>(mode, f, d, o, tan, u, jp, grad2d, s);
-  else launch_deriv_w<1>(mode, f, d, o, tan, u, jp, grad2d, s);
+  if (d.k >= 24) launch_deriv_w<4>(mode, f, d, o, tan, u, jp, grad2d, s, built);
+  else if (d.k >= 12) launch_deriv_w<2>(mode, f, d, o, tan, u, jp, grad2d, s, built);
+  else launch_deriv_w<1>(mode, f, d, o, tan, u, jp, grad2d, s, built);
 }
 
 void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* gram,
-                 const float* u, float* grad2d, hipStream_t s) {
+                 const float* u, float* grad2d, hipStream_t s, bool gram_sums) {
   const int tiles = d.V * d.T;
   const unsigned grid = persistent_grid(tiles);
+  BlendOut bo{reinterpret_cast<float4*>(f->blend_k), f->blend_m, f->blend_run, f->blend_runs, f->blend_start,
+              f->blend_k != nullptr, f->blend_capacity};
 #define LMRS_GRAM_ARGS                                                                                      \
   f->rec, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T, d.TX, d.k, o, gram, u, grad2d, \
-      f->sched, tiles
-  if (u) {
-    if (d.k <= kWave) gram_kernel<1, true><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
-    else gram_kernel<4, true><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+      f->sched, tiles, bo, f->blend_capacity
+  const bool wide = d.k > kWave;
+  if (!gram_sums) {
+    if (!wide) gram_kernel<1, false, false><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+    else gram_kernel<4, false, false><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+  } else if (u) {
+    if (!wide) gram_kernel<1, true, true><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+    else gram_kernel<4, true, true><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
   } else {
-    if (d.k <= kWave) gram_kernel<1, false><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
-    else gram_kernel<4, false><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+    if (!wide) gram_kernel<1, false, true><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
+    else gram_kernel<4, false, true><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
   }
 #undef LMRS_GRAM_ARGS
+  if (f->blend_k) blend_built_kernel<<<1, 64, 0, s>>>(f->blend_start, (int64_t)tiles, f->blend_capacity);
+}
+
+void launch_blend_gn(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* tan,
+                     float* grad2d, hipStream_t s) {
+  if (!f->blend_k) return;
+  const int tiles = d.V * d.T;
+  blend_gn_kernel<<<(unsigned)tiles, kBlendGnThreads, 0, s>>>(f->rec, tan, reinterpret_cast<const float4*>(f->blend_k),
+                                                   f->blend_m, f->blend_start, f->pix, f->w, d.n, d.T, d.TX, d.k, o,
+                                                   grad2d, f->sched, tiles, f->blend_capacity);
 }
 
 }  // namespace lmrs

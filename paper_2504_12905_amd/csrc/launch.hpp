@@ -74,7 +74,11 @@ void launch_deriv(int mode, const lmrs_frame* f, const FrameDims& d, const lmrs_
                   const float* tan, const float* u, float* jp, float* grad2d, hipStream_t s);
 // gram[V][n][32] (one 128-byte row per (view, Gaussian)); with u non-NULL also grad2d += J^T u (u: [S][3])
 void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* gram,
-                 const float* u, float* grad2d, hipStream_t s);
+                 const float* u, float* grad2d, hipStream_t s, bool gram_sums = true);
+// J^T W J p from the blend table into grad2d (exits at once unless the table
+// is built; the fused walk of launch_deriv(3) then runs instead)
+void launch_blend_gn(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* tan,
+                     float* grad2d, hipStream_t s);
 
 // solver side (kernels_solver.hip)
 constexpr int kRedBlocks = 512;  // partial sums per reduction
@@ -89,7 +93,9 @@ void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targe
                      double* partials, float* report, hipStream_t s);
 void launch_dot(const float* a, const float* b, int64_t n, double* partials, double* out, hipStream_t s);
 // report[INST] = *count; ORs LMRS_FAIL_CAPACITY into report[STATUS] when *count > capacity
-void launch_report_count(const int64_t* count, int64_t capacity, float* report, hipStream_t s);
+// and report[PAIRS] = *pairs when pairs is not NULL
+void launch_report_count(const int64_t* count, int64_t capacity, float* report, hipStream_t s,
+                         const int64_t* pairs = nullptr);
 // PCG state in device memory
 struct PcgState {
   float *x, *r, *z, *p, *u, *minv;

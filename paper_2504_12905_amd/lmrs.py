@@ -27,7 +27,7 @@ LMRS_REC = 12
 OP_BIN, OP_JVP, OP_VJP, OP_GN, OP_DIAG, OP_PCG, OP_LM, OP_SOLVE = 1, 2, 3, 4, 5, 6, 7, 8
 REPORT_FLOATS = 12
 SAMPLER_UNIFORM, SAMPLER_RESIDUAL, SAMPLER_GAUSSIAN = 0, 1, 2
-REP = dict(loss=0, eta=1, xdc_max=2, cg_done=3, r0=4, rn=5, bx=6, instances=7, status=8)
+REP = dict(loss=0, eta=1, xdc_max=2, cg_done=3, r0=4, rn=5, bx=6, instances=7, status=8, pairs=9)
 FAIL_NONFINITE, FAIL_BREAKDOWN, FAIL_CAPACITY = 1, 2, 4
 
 
@@ -61,7 +61,9 @@ class _Frame(C.Structure):
                 ("rec", C.c_void_p), ("rect", C.c_void_p), ("tile_start", C.c_void_p),
                 ("ids", C.c_void_p), ("capacity", C.c_int64), ("n_instances", C.c_void_p),
                 ("pix", C.c_void_p), ("w", C.c_void_p), ("color", C.c_void_p),
-                ("trans", C.c_void_p), ("last", C.c_void_p), ("sched", C.c_void_p)]
+                ("trans", C.c_void_p), ("last", C.c_void_p), ("sched", C.c_void_p),
+                ("blend_k", C.c_void_p), ("blend_m", C.c_void_p), ("blend_run", C.c_void_p),
+                ("blend_runs", C.c_void_p), ("blend_start", C.c_void_p), ("blend_capacity", C.c_int64)]
 
 
 def sched_ints(tiles: int) -> int:
@@ -94,6 +96,7 @@ _lib.lmrs_gn_product.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_gn_product_timed.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp, _vp]
 _lib.lmrs_gn_product_noalloc.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp]
 _lib.lmrs_walk_counts.argtypes = [_FP, _vp, _vp, _vp]
+_lib.lmrs_linearize.argtypes = [_FP, _vp, _vp]
 _lib.lmrs_gn_diag.argtypes = [_FP, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_pcg.argtypes = [_FP, _vp, _vp, _f32, _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.lmrs_lm_step.argtypes = [_FP, _vp, _vp, _vp, C.POINTER(LmParams), _vp, _vp, _vp, _sz, _vp]
@@ -106,7 +109,7 @@ _lib.lmrs_contributor_counts.argtypes = [_FP, _vp, _vp, _vp]
 _lib.lmrs_view_clusters.argtypes = [_vp, _i32, _i32, C.c_uint64, _vp]
 _lib.lmrs_view_batch.argtypes = [_vp, _i32, _i32, C.c_uint64, _i32, _vp]
 for _name in ("lmrs_project", "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp",
-              "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_product_noalloc", "lmrs_walk_counts",
+              "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_product_noalloc", "lmrs_walk_counts", "lmrs_linearize",
               "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step", "lmrs_residual_scores", "lmrs_sample", "lmrs_lm_solve",
               "lmrs_contributor_counts", "lmrs_view_clusters", "lmrs_view_batch", "lmrs_lm_iterate",
               "lmrs_bin_tiles_async"):
@@ -145,6 +148,8 @@ class Frame:
     k: int = 256
     sampled: bool = False          # allocate pix / w (needed when k < 256)
     capacity: int = 0
+    blend: bool = True             # keep the blend table (the render's linearization; see lmrs_frame)
+    blend_capacity: int = 0        # pairs it can hold (grown by ensure_blend)
     tensors: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -164,7 +169,40 @@ class Frame:
         t["n_instances"] = torch.zeros(1, dtype=torch.int64, device=dev)
         t["sched"] = torch.zeros(sched_ints(V * self.T), dtype=torch.int32, device=dev)
         t["ids"] = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
+        if self.blend:
+            t["blend_start"] = torch.zeros(V * self.T + 2, dtype=torch.int64, device=dev)
+            t["blend_runs"] = torch.zeros(V * self.T, dtype=torch.int32, device=dev)
+            self._alloc_blend(self.blend_capacity)
         self.set_k(self.k, self.sampled or self.k < 256)
+
+    def _alloc_blend(self, cap: int):
+        dev = self.beta.device
+        self.blend_capacity = max(int(cap), 0)
+        m = max(self.blend_capacity, 1)
+        t = self.tensors
+        t["blend_k"] = torch.empty((2, m, 4), dtype=torch.float32, device=dev)   # two orders of the pairs
+        t["blend_m"] = torch.empty((2, m), dtype=torch.int32, device=dev)
+        t["blend_run"] = torch.empty(m, dtype=torch.int32, device=dev)
+        if "blend_start" in t:
+            t["blend_start"][self.n_views * self.T + 1] = 0   # new buffers hold no table
+
+    def blend_pairs(self) -> int:
+        """Blending (pixel, Gaussian) pairs of the last render (waits for the device)."""
+        return int(self.tensors["blend_start"][self.n_views * self.T].item()) if self.blend else 0
+
+    def blend_built(self) -> bool:
+        return bool(self.blend and int(self.tensors["blend_start"][self.n_views * self.T + 1].item()) == 1)
+
+    def ensure_blend(self, needed: int | None = None, margin: float = 1.15) -> bool:
+        """Grows the blend table to hold `needed` pairs (default: the last
+        render's count); returns True when it grew."""
+        if not self.blend:
+            return False
+        needed = self.blend_pairs() if needed is None else int(needed)
+        if needed <= self.blend_capacity:
+            return False
+        self._alloc_blend(int(needed * margin) + 4096)
+        return True
 
     def set_k(self, k: int, sampled: bool):
         dev = self.beta.device
@@ -200,7 +238,14 @@ class Frame:
                       None if t["pix"] is None else t["pix"].data_ptr(),
                       None if t["w"] is None else t["w"].data_ptr(),
                       t["color"].data_ptr(), t["trans"].data_ptr(), t["last"].data_ptr(),
-                      t["sched"].data_ptr())
+                      t["sched"].data_ptr(), *self._blend_fields())
+
+    def _blend_fields(self):
+        if not self.blend:
+            return (None, None, None, None, None, 0)
+        t = self.tensors
+        return (t["blend_k"].data_ptr(), t["blend_m"].data_ptr(), t["blend_run"].data_ptr(),
+                t["blend_runs"].data_ptr(), t["blend_start"].data_ptr(), self.blend_capacity)
 
     def grow_ids(self, needed: int):
         self.capacity = int(needed * 1.25) + 1024
@@ -238,10 +283,21 @@ def lmrs_bin_tiles(frame: Frame, stream=None, ws: torch.Tensor | None = None) ->
     raise LmrsError(LMRS_ECAPACITY, "lmrs_bin_tiles")
 
 
-def lmrs_render(frame: Frame, opts: RenderOpts | None = None, stream=None):
+def lmrs_render(frame: Frame, opts: RenderOpts | None = None, stream=None, grow_blend: bool = True):
+    """grow_blend: afterwards wait for the render's pair count and grow the
+    frame's blend table to hold it (so that lmrs_linearize can build it)."""
     opts = opts or default_opts()
     fs = frame.struct()
     _check(_lib.lmrs_render(C.byref(fs), C.byref(opts), _stream(stream)), "lmrs_render")
+    if grow_blend and frame.blend:
+        frame.ensure_blend()
+
+
+def lmrs_linearize(frame: Frame, opts: RenderOpts | None = None, stream=None):
+    """Builds the frame's blend table for its current render (see lmrs_linearize in lmrs.h)."""
+    opts = opts or default_opts()
+    fs = frame.struct()
+    _check(_lib.lmrs_linearize(C.byref(fs), C.byref(opts), _stream(stream)), "lmrs_linearize")
 
 
 def lmrs_jvp(frame: Frame, p: torch.Tensor, out: torch.Tensor | None = None, opts=None, stream=None):
@@ -289,11 +345,12 @@ def lmrs_gn_product_noalloc(frame: Frame, p: torch.Tensor, lam: float, out: torc
 def lmrs_gn_product_timed(frame: Frame, p: torch.Tensor, lam: float, d: torch.Tensor | None = None,
                           out: torch.Tensor | None = None, opts=None, stream=None,
                           ws: torch.Tensor | None = None):
-    """Returns (out, [ms tangent, ms fill, ms fused splat, ms chain])."""
+    """Returns (out, [ms tangent, ms fill, ms blend-table splat, ms fused walk, ms chain]);
+    of the two splats one exits at once (the table when it is not built)."""
     opts = opts or default_opts()
     out = out if out is not None else torch.empty(frame.P, dtype=torch.float32, device=p.device)
     ws = ws if ws is not None else workspace(OP_GN, frame)
-    ms = (C.c_float * 4)()
+    ms = (C.c_float * 5)()
     fs = frame.struct()
     _check(_lib.lmrs_gn_product_timed(C.byref(fs), C.byref(opts), _ptr(p), float(lam), _ptr(d), _ptr(out),
                                       _ptr(ws), ws.numel(), _stream(stream), ms), "lmrs_gn_product_timed")
@@ -367,8 +424,12 @@ def lmrs_sample(frame: Frame, sampler: int, seed: int, iter: int, scores: torch.
 
 
 def lmrs_lm_step(frame: Frame, targets: torch.Tensor, params: LmParams, d: torch.Tensor | None = None,
-                 report: torch.Tensor | None = None, opts=None, stream=None, ws: torch.Tensor | None = None):
-    """One LM iteration in place on frame.beta; grows the id buffer and retries on overflow."""
+                 report: torch.Tensor | None = None, opts=None, stream=None, ws: torch.Tensor | None = None,
+                 grow_blend: bool = True):
+    """One LM iteration in place on frame.beta; grows the id buffer and retries on overflow.
+    grow_blend: afterwards wait for the step's pair count and grow the frame's
+    blend table for the next step (a step whose pairs do not fit walks the
+    lists instead)."""
     opts = opts or default_opts()
     for _ in range(3):
         fs = frame.struct()
@@ -380,6 +441,8 @@ def lmrs_lm_step(frame: Frame, targets: torch.Tensor, params: LmParams, d: torch
             frame.grow_ids(int(frame.n_instances.item()))
             continue
         _check(st, "lmrs_lm_step")
+        if grow_blend and frame.blend:
+            frame.ensure_blend()
         return
     raise LmrsError(LMRS_ECAPACITY, "lmrs_lm_step")
 
@@ -449,6 +512,7 @@ def lm_params(iter: int, cg_iters: int, lam: float, seed: int = 0, eta_cap: floa
 
 EXPORTS = ("lmrs_status_str", "lmrs_last_error", "lmrs_report_status", "lmrs_workspace_bytes", "lmrs_project",
            "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp", "lmrs_gn_product",
-           "lmrs_gn_product_timed", "lmrs_gn_product_noalloc", "lmrs_walk_counts", "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step",
+           "lmrs_gn_product_timed", "lmrs_gn_product_noalloc", "lmrs_walk_counts", "lmrs_linearize",
+           "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step",
            "lmrs_residual_scores", "lmrs_contributor_counts", "lmrs_sample", "lmrs_lm_solve",
            "lmrs_view_clusters", "lmrs_view_batch", "lmrs_lm_iterate", "lmrs_bin_tiles_async")

@@ -171,7 +171,7 @@ class _Fit:
             self.cams = torch.tensor(prob.cams, device=dev)
             cap = int(prob.instances_bound * 1.05) + 1024
             self.fr = L.Frame(req.n, req.sh_degree, self.beta, self.cams, req.res, req.res, req.n_views, k=256,
-                              capacity=cap)
+                              capacity=cap, blend=False)
             nbytes = max(L.workspace_bytes(L.OP_BIN, self.fr), L.workspace_bytes(ws_op, self.fr))
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
             self.rep = torch.zeros(L.REPORT_FLOATS, device=dev)

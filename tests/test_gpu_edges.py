@@ -102,8 +102,9 @@ def test_four_million_entry_tile_lists():
 
 
 def test_equal_depths_keep_id_order():
-    """Gaussians at exactly the same depth (identical FP32 depth keys): the
-    lists order them by ascending id (the stable view sort keeps id order)."""
+    """Gaussians at exactly the same depth (identical FP64 depths): the lists
+    order them by ascending id (the stable view sort keeps id order and the
+    tie pass leaves such runs alone)."""
     rng = np.random.default_rng(11)
     n, f = 300, 120.0
     u, v = rng.uniform(35.0, 45.0, n), rng.uniform(35.0, 45.0, n)
@@ -113,7 +114,9 @@ def test_equal_depths_keep_id_order():
     fr, orc = check_all("equal depths", n, 0, beta, axis_camera(f, 64, 64), 64, 64)
     rec = np_(fr.rec)[0]
     vis = np_(fr.rect)[0][:, 0] < np_(fr.rect)[0][:, 2]
-    assert len(np.unique(rec[vis, 9].view(np.uint32))) == 2
+    z = ((rec[vis, 11].view(np.uint32).astype(np.uint64) << np.uint64(32)) |
+         rec[vis, 9].view(np.uint32).astype(np.uint64)).view(np.float64)
+    assert len(np.unique(z)) == 2
 
 
 @pytest.mark.parametrize("k", [13, 16, 24, 27, 32, 40, 64])

@@ -60,12 +60,10 @@ def test_projection(case):
     vis = pr["visible"] > 0
     rect = np_(case.fr.rect)
     gvis = rect[..., 0] < rect[..., 2]
-    # depth keys: the FP32 number nearest the FP64 depth, and the FP64 depth
-    # itself recovered from (key, sub-key) within a few FP64 spacings
-    key = rec[..., 9]
-    assert np.array_equal(key[vis], pr["depth"][vis].astype(np.float32))
-    sub = rec[..., 11].view(np.uint32).astype(np.int64) - (1 << 30)
-    z = (key.astype(np.float64).view(np.int64) + sub).view(np.float64)
+    # the FP64 camera depth (record words 9 = low, 11 = high): the oracle's
+    # within a few FP64 spacings (both FP64, different operation order)
+    z = ((rec[..., 11].view(np.uint32).astype(np.uint64) << np.uint64(32)) |
+         rec[..., 9].view(np.uint32).astype(np.uint64)).view(np.float64)
     assert np.all(np.abs(z[vis] - pr["depth"][vis]) <= 4 * np.spacing(pr["depth"][vis]))
     bad = (vis != gvis) & (pr["margin"] >= TAU_LIST)
     assert not bad.any(), f"{bad.sum()} visibility mismatches"
