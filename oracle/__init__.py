@@ -248,11 +248,13 @@ class Oracle:
         return out
 
     def vjp_abs(self, u: np.ndarray) -> np.ndarray:
-        """Entry-wise magnitude of the terms J^T u is summed from: per
-        parameter, sum over views and record components of |d rec / d beta|
-        times the sum over pixels and channels of |u_c| |d C_c / d rec|.
-        It bounds |J^T u| and |J|^T |u| from above; tests divide entry-wise
-        differences by it (a scale for rounding, not part of the method)."""
+        """Entry-wise magnitude of the terms J^T u is summed from: the
+        reverse pass with every quantity replaced by the sum of the magnitudes
+        of its terms (the colour behind, d/d alpha = T u.rgb - behind/(1-alpha)
+        as T|u.rgb| + |behind|/(1-alpha), ...), then the chain with
+        |d rec / d beta|. It bounds |J^T u| and |J|^T |u| from above and equals
+        them where no term can cancel; tests divide entry-wise differences by
+        it (a scale for rounding, not part of the method)."""
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.S, 3)
         out = np.zeros(self.P)
         lib().or_vjp_abs(self.h, _p(u), _p(out))

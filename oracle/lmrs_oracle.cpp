@@ -641,13 +641,41 @@ void screen_adjoint(const Problem& pb, const double* u, std::vector<double>& gra
       for (size_t i = 0; i < VN * kRec; ++i) grad_rec[i] += part[th][i];
 }
 
-// Magnitude of the terms J^T u is summed from, as the method forms it (screen
-// records per view, then the chain to the parameters): per (view, Gaussian)
-// and record component, the sum over sampled pixels and channels of
-// |u_c| |d C_c / d rec|; then per parameter the sum over views and record
-// components of |d rec / d beta| times that. It bounds |J^T u| entry by entry
-// and scales the rounding error of any evaluation in that order (a test
-// scale, not part of the method).
+// Magnitude of the terms J^T u is summed from, as the method forms it: the
+// adjoint of pixel_adjoint with every quantity replaced by the sum of the
+// magnitudes of the terms it is made of (u . rgb by sum_c |u_c||rgb_c|, the
+// colour behind by the sum of its terms, d/d a_n by
+// T_n |u.rgb| + |behind| / (1 - a_n), d/d s by that times a_n and the conic
+// and offset factors by their magnitudes), summed over pixels per (view,
+// Gaussian) and record component; then per parameter the sum over views and
+// record components of |d rec / d beta| times that. It bounds |J^T u| and
+// |J|^T |u| entry by entry and scales the rounding error of an evaluation in
+// this order, cancellation inside d/d a_n included (a test scale, not part of
+// the method).
+void pixel_adjoint_abs(const Problem& pb, const Rec<double>* const* recs, const std::vector<Blended>& bl,
+                       double Tfinal, const double* u, double* grad /*[len][9]*/) {
+  const double au[3] = {std::fabs(u[0]), std::fabs(u[1]), std::fabs(u[2])};
+  double behind = Tfinal * (au[0] * std::fabs(pb.op.bg[0]) + au[1] * std::fabs(pb.op.bg[1]) +
+                            au[2] * std::fabs(pb.op.bg[2]));
+  for (int q = (int)bl.size() - 1; q >= 0; --q) {
+    const Blended& b = bl[q];
+    const Rec<double>& r = *recs[b.pos];
+    const double urgb = au[0] * std::fabs(r.rgb[0]) + au[1] * std::fabs(r.rgb[1]) + au[2] * std::fabs(r.rgb[2]);
+    const double ga = b.T * urgb + behind / (1.0 - b.a);
+    behind += urgb * b.a * b.T;
+    double* g = grad + (size_t)b.pos * kRec;
+    for (int c = 0; c < 3; ++c) g[6 + c] += au[c] * b.a * b.T;
+    if (b.capped) continue;
+    const double gs = ga * b.a;
+    g[5] += ga * b.es;
+    g[0] += gs * (std::fabs(r.A * b.dx) + std::fabs(r.B * b.dy));
+    g[1] += gs * (std::fabs(r.B * b.dx) + std::fabs(r.C * b.dy));
+    g[2] += gs * (0.5 * b.dx * b.dx);
+    g[3] += gs * std::fabs(b.dx * b.dy);
+    g[4] += gs * (0.5 * b.dy * b.dy);
+  }
+}
+
 void screen_adjoint_abs(const Problem& pb, const double* u, std::vector<double>& grad_rec) {
   const size_t VN = (size_t)pb.V * pb.n;
   int nth = 1;
@@ -680,17 +708,13 @@ void screen_adjoint_abs(const Problem& pb, const double* u, std::vector<double>&
         pb.pixel_of(v, t, j, &px, &py);
         double Tf;
         blend_trace(pb, ptrs.data(), len, px + 0.5, py + 0.5, bl, &Tf);
-        for (int c = 0; c < 3; ++c) {
-          if (ui[c] == 0.0) continue;
-          double e[3] = {0.0, 0.0, 0.0};
-          e[c] = 1.0;
-          g.assign((size_t)len * kRec, 0.0);
-          pixel_adjoint(pb, ptrs.data(), bl, Tf, e, g.data());
-          for (const Blended& b : bl) {
-            double* dst = &acc[((size_t)v * pb.n + list[b.pos]) * kRec];
-            const double* src = &g[(size_t)b.pos * kRec];
-            for (int q = 0; q < kRec; ++q) dst[q] += std::fabs(ui[c]) * std::fabs(src[q]);
-          }
+        if (ui[0] == 0.0 && ui[1] == 0.0 && ui[2] == 0.0) continue;
+        g.assign((size_t)len * kRec, 0.0);
+        pixel_adjoint_abs(pb, ptrs.data(), bl, Tf, ui, g.data());
+        for (const Blended& b : bl) {
+          double* dst = &acc[((size_t)v * pb.n + list[b.pos]) * kRec];
+          const double* src = &g[(size_t)b.pos * kRec];
+          for (int q = 0; q < kRec; ++q) dst[q] += src[q];
         }
       }
     }
