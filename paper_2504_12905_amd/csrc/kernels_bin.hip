@@ -383,12 +383,15 @@ __global__ __launch_bounds__(kViewThreads) void view_scatter_kernel(const uint32
 // ---- ties of the depth key. The radix passes order a view's Gaussians by
 // (32-bit depth key, id); a run of equal keys (depths within 2^-27 relative)
 // is then re-ordered by (FP64 depth bits, id), which gives the order of the
-// FP64 depths with ties by id. One wave per 64 ranks; the wave holding the
-// first rank of a run of two or more sorts the run: each member's place is
-// the count of members before it, written to tmp and copied back. Runs
-// already in order are left alone after one pass over them (equal FP64
-// depths keep the id order of the radix passes), and key 0 (depth <= 0,
-// culled, never listed) is not looked at.
+// FP64 depths with ties by id. One wave per 64 ranks. A run of up to
+// kTieShort members (nearly all runs) is sorted by the lane at its head in
+// registers; the wave holding the first rank of a longer run sorts it: each
+// member's place is the count of members before it, written to tmp and
+// copied back, and runs already in order are left alone after one pass over
+// them (equal FP64 depths keep the id order of the radix passes). Key 0
+// (depth <= 0, culled, never listed) is not looked at.
+constexpr int kTieShort = 8;
+
 __device__ __forceinline__ uint64_t depth_of(const float* __restrict__ rec, int64_t vn, uint32_t g) {
   const float* r = rec + (vn + g) * LMRS_REC;
   return depth_bits(r[9], r[11]);
@@ -412,7 +415,55 @@ __global__ __launch_bounds__(256) void view_ties_kernel(const uint32_t* __restri
   const bool prev_differs = i == 0 || (i < n && kv[i - 1] != k);
   const bool next_same = i + 1 < n && kv[i + 1] == k;
   const bool positive = k != 0u;  // z > 0
-  for (uint64_t heads = __ballot(i < n && prev_differs && next_same && positive); heads; heads &= heads - 1) {
+  const bool head = i < n && prev_differs && next_same && positive;
+  // Short runs (up to kTieShort members, nearly all of them) are put in
+  // order by the lane at their head, with an insertion sort in registers;
+  // longer ones by the whole wave below.
+  bool long_run = false;
+  if (head) {
+    uint32_t g[kTieShort];
+    uint64_t z[kTieShort];
+    int len = 0;
+#pragma unroll
+    for (int q = 0; q < kTieShort; ++q) {
+      if (q == len && i + q < n && (q < 2 || kv[i + q] == k)) {
+        g[q] = ids[i + q];
+        z[q] = depth_of(rec, vn, g[q]);
+        ++len;
+      }
+    }
+    long_run = len == kTieShort && i + kTieShort < n && kv[i + kTieShort] == k;
+    if (!long_run) {
+      // odd-even transposition sort of (depth bits, id) with fixed indices;
+      // slots past the run hold the largest key and stay last
+      uint32_t g0[kTieShort];
+#pragma unroll
+      for (int q = 0; q < kTieShort; ++q) {
+        if (q >= len) {
+          g[q] = 0xffffffffu;
+          z[q] = ~0ull;
+        }
+        g0[q] = g[q];
+      }
+#pragma unroll
+      for (int r = 0; r < kTieShort; ++r) {
+#pragma unroll
+        for (int q = r & 1; q + 1 < kTieShort; q += 2) {
+          const bool swap = z[q] > z[q + 1] || (z[q] == z[q + 1] && g[q] > g[q + 1]);
+          const uint64_t za = swap ? z[q + 1] : z[q], zb = swap ? z[q] : z[q + 1];
+          const uint32_t ga = swap ? g[q + 1] : g[q], gb = swap ? g[q] : g[q + 1];
+          z[q] = za;
+          z[q + 1] = zb;
+          g[q] = ga;
+          g[q + 1] = gb;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kTieShort; ++q)
+        if (q < len && g[q] != g0[q]) ids[i + q] = g[q];
+    }
+  }
+  for (uint64_t heads = __ballot(head && long_run); heads; heads &= heads - 1) {
     const int src = __ffsll((unsigned long long)heads) - 1;
     const int a = i0 + src;
     const uint32_t K = (uint32_t)readlane((int)k, src);
