@@ -15,7 +15,11 @@ products. Readings of the paper that this code fixes:
   from a render of every pixel of the batch views at the current parameters,
   with |r_p| = |r_p,R| + |r_p,G| + |r_p,B|; see ``residual_scores``;
 * contribution-weighted sampling (Supp. E, q_Gaussian): the counts G_p come
-  from the same full render; see ``contributor_counts``.
+  from the same full render; see ``contributor_counts``;
+* SSIM residual (Supp. B, Sec. 6; ``ssim_weight`` > 0): the SSIM terms come
+  from full renders of the batch views, and the Gauss-Newton system of the
+  step is that of ``ssim.residual_and_weights``: b = J^T u, the operator
+  weighted per channel by wc, the preconditioner's diagonal by wbar.
 """
 from __future__ import annotations
 
@@ -23,6 +27,7 @@ import numpy as np
 
 from . import Oracle
 from .sampling import sample_gaussian, sample_residual, sample_uniform
+from .ssim import residual_and_weights, ssim_terms
 
 
 def pcg(apply_A, b: np.ndarray, m_inv: np.ndarray, iters: int):
@@ -89,7 +94,7 @@ def contributor_counts(orc: Oracle) -> np.ndarray:
 
 
 def lm_step(n, sh_degree, beta, cams_all, targets_all, view_ids, width, height, k, seed, it, lam,
-            cg_iters, d=None, opts=None, sampler="uniform"):
+            cg_iters, d=None, opts=None, sampler="uniform", ssim_weight=0.0):
     """Alg. 1 for one LM iteration. Returns (beta_next float32, info dict).
 
     sampler: "uniform" (Sec. 4.4; k = 256 takes every pixel), "residual"
@@ -114,14 +119,29 @@ def lm_step(n, sh_degree, beta, cams_all, targets_all, view_ids, width, height, 
     fwd = orc.render()
     res = fwd["C"] - gather_targets(targets_all[view_ids], orc)  # r = I_hat - I  (eq. 7)
     wts = orc.weights()
-    b = orc.vjp(wts[:, None] * res)                             # r0 = J^T W r
-    D = orc.diag()                                              # diag(J^T W J)
+    if ssim_weight > 0:
+        k_s, pix_s, w_s = orc.k, orc.pix, orc.w
+        img = orc.render_image()                                # every pixel of the batch views
+        orc.set_samples(k_s, pix_s, w_s)
+        tg = np.asarray(targets_all[view_ids], np.float64)
+        u, wc, wbar = residual_and_weights(orc, img, tg, wts, s=ssim_weight)
+        b = orc.vjp(u)                                          # r0 = J^T u
+        orc.set_samples(k_s, pix_s, wbar)
+        D = orc.diag()                                          # diag(J^T diag(wbar) J)
+        orc.set_channel_weights(wc)                             # operator J^T diag(wc) J
+        v, px, py = orc.pixel_coords()
+        rho = 1.0 - ssim_terms(img, tg)[0][v, py, px]
+        loss = float(np.sum(wts[:, None] * (res ** 2 + ssim_weight * rho ** 2)))
+    else:
+        b = orc.vjp(wts[:, None] * res)                         # r0 = J^T W r
+        D = orc.diag()                                          # diag(J^T W J)
+        loss = float(np.sum(wts[:, None] * res ** 2))
     dd = np.ones(orc.P) if d is None else np.asarray(d, np.float64)
     m_inv = 1.0 / (D + lam * dd)                                # M^-1 = 1 / diag(J^T W J + lam d)
     x, norms, done = pcg(lambda p: orc.gn(p, lam, dd), b, m_inv, cg_iters)
     eta = learning_rate(x, n, it)
     beta_next = (beta.astype(np.float64) - eta * x).astype(np.float32)
-    info = dict(loss_sampled=float(np.sum(wts[:, None] * res ** 2)), b=b, diag=D, x=x, eta=eta,
+    info = dict(loss_sampled=loss, b=b, diag=D, x=x, eta=eta,
                 cg_norms=norms, cg_done=done, residual=res, weights=wts, samples=orc.pix,
                 sample_margin=margin)
     return beta_next, info

@@ -117,3 +117,38 @@ def test_channel_weighted_operator_against_dense_jacobian():
     np.testing.assert_allclose(orc.gn(p, 0.1), ref, rtol=1e-10, atol=1e-12)
     orc.set_channel_weights(None)
     np.testing.assert_allclose(orc.gn(p, 0.1), J.T @ (J @ p) + 0.1 * p, rtol=1e-10, atol=1e-12)
+
+
+def _ssim_objective(tw, beta, target, s=0.2):
+    img = Oracle(tw.n, tw.sh_degree, beta, tw.cams, tw.width, tw.height).render_image()
+    ssim, _ = ssim_terms(img, target)
+    return float(((img - target) ** 2).sum() + s * ((1 - ssim) ** 2).sum())
+
+
+def test_lm_step_with_ssim_solves_the_weighted_system_and_descends():
+    """The oracle's LM step with the SSIM residual: run to convergence, its x
+    solves the dense system (J^T diag(wc) J + lambda I) x = J^T u built from
+    the dual-number Jacobian columns; its preconditioner diagonal is the
+    column sums of wbar J^2; and a short step along -x lowers the SSIM + colour
+    objective (tiny scene, every pixel)."""
+    from oracle.solver import lm_step
+    tw = synth.tiny(n=3, sh_degree=1, n_views=1, size=32, seed=7)
+    target = Oracle(tw.n, 1, tw.beta_gt, tw.cams, tw.width, tw.height).render_image()
+    beta = np.asarray(tw.beta_init, np.float32)
+    orc = Oracle(tw.n, 1, beta, tw.cams, tw.width, tw.height)
+    lam = 0.1
+    beta_next, info = lm_step(tw.n, 1, beta, tw.cams, target.astype(np.float32), [0], tw.width, tw.height,
+                              256, 0, 0, lam, orc.P, ssim_weight=0.2)
+    orc.set_samples(256)
+    img = orc.render_image()
+    u, wc, wbar = residual_and_weights(orc, img, target, np.ones(orc.S), s=0.2)
+    J = np.stack([orc.jvp(e).reshape(-1) for e in np.eye(orc.P)], axis=1)   # [3S, P]
+    A = J.T @ (wc.reshape(-1)[:, None] * J) + lam * np.eye(orc.P)
+    x = np.linalg.solve(A, J.T @ u.reshape(-1))
+    np.testing.assert_allclose(info["x"], x, rtol=1e-5, atol=1e-7 * np.abs(x).max())
+    np.testing.assert_allclose(info["diag"], (np.repeat(wbar, 3)[:, None] * J ** 2).sum(axis=0),
+                               rtol=1e-6, atol=1e-12)
+    assert info["b"] @ info["x"] > 0
+    e0 = _ssim_objective(tw, beta, target)
+    e1 = _ssim_objective(tw, (beta.astype(np.float64) - 0.05 * info["x"]).astype(np.float32), target)
+    assert e1 < e0
