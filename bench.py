@@ -38,7 +38,16 @@ FP32_PEAK_TFLOPS = 157.3
 # with packed FP32 arithmetic switched off.
 FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 SPLAT_SOURCE = os.path.join(ROOT, "paper_2504_12905_amd", "csrc", "kernels_splat.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gn_splat_traffic_cfg1.txt")
+# the GN product's splat kernels: over the blend table (when built) and the
+# fused list walk; name match in profiler output, summary files
+SPLAT_KERNELS = {
+    "table": ("blend_gn_kernel", "blend_gn_kernel (GN product over the blend table)",
+              os.path.join(ROOT, "profiles", "gn_blend_traffic_cfg1.txt"),
+              os.path.join(ROOT, "profiles", "gn_blend_counters_cfg1.txt")),
+    "walk": ("deriv_kernel<3", "deriv_kernel<3> (fused list walk of the GN product)",
+             os.path.join(ROOT, "profiles", "gn_splat_traffic_cfg1.txt"),
+             os.path.join(ROOT, "profiles", "gn_splat_counters_cfg1.txt")),
+}
 
 # Algorithmic work of one GN product, per unit the method must touch:
 #   per traversed list entry (the prefix L*_t of each tile's list up to the
@@ -87,14 +96,16 @@ def render_targets(L, torch, w, beta_gt, cams, dev):
     return targets
 
 
-def traffic_from_profile(kernel_hash: str, default_workload: bool):
-    """HBM bytes per launch of the fused splat kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source and
-    on the workload being timed (the summary covers the default 100k one)."""
-    if not default_workload or not os.path.exists(TRAFFIC_FILE):
+def traffic_from_profile(kernel_hash: str, default_workload: bool, which: str = "table"):
+    """HBM bytes per launch of a splat kernel ("table" or "walk") from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    source and on the workload being timed (the summary covers the default
+    100k one)."""
+    path = SPLAT_KERNELS[which][2]
+    if not default_workload or not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
@@ -192,10 +203,12 @@ def copy_calibration(torch, dev, mib=1024, reps=3):
 
 
 def summarize_traffic(fetch_dir: str, write_dir: str, copy_mib: int, command: str, copy_reps: int = 3) -> str:
-    """Per-launch HBM bytes of the fused splat kernel from two rocprofv3 --pmc
-    runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by the
-    ratio of the known copy size to what the same counter reads for the plain
-    copy kernel of the same run. Writes TRAFFIC_FILE and returns its text."""
+    """Per-launch HBM bytes of the GN product's splat kernels (over the blend
+    table and the fused list walk, each where the run launched it) from two
+    rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each
+    scaled by the ratio of the known copy size to what the same counter reads
+    for the plain copy kernel of the same run. Writes one summary file per
+    kernel found and returns their text."""
     import csv
     import glob
 
@@ -211,39 +224,47 @@ def summarize_traffic(fetch_dir: str, write_dir: str, copy_mib: int, command: st
                 vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
         return vals
 
-    out = {}
-    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
-        vals = per_kernel(d, counter)
-        splat = [x for k, v in vals.items() if "deriv_kernel<3" in k for x in v]
+    runs = {c: per_kernel(d, c) for c, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir))}
+    copy = {}
+    for counter, vals in runs.items():
         # the calibration copies are the largest dispatches of the runtime's
         # device-to-device copy kernel in the run (reps of the same size)
-        copy = sorted(x for k, v in vals.items() if "copyBuffer" in k for x in v)[-copy_reps:]
-        if not splat or not copy:
-            raise SystemExit(f"{counter}: kernels found: {sorted(vals)[:20]}")
-        splat_kib = float(np.median(splat))
-        copy_kib = float(np.median(copy))
-        scale = copy_mib * 1024.0 / copy_kib
-        out[counter] = (splat_kib, copy_kib, scale)
-    fetch = out["FETCH_SIZE"][0] * out["FETCH_SIZE"][2] * 1024
-    write = out["WRITE_SIZE"][0] * out["WRITE_SIZE"][2] * 1024
+        c = sorted(x for k, v in vals.items() if "copyBuffer" in k for x in v)[-copy_reps:]
+        if not c:
+            raise SystemExit(f"{counter}: no copy kernel; kernels found: {sorted(vals)[:20]}")
+        copy[counter] = float(np.median(c))
     kernel_hash = hashlib.sha256(open(SPLAT_SOURCE, "rb").read()).hexdigest()
-    text = (f"# HBM traffic of the fused splat kernel deriv_kernel<3> (one GN product),\n"
-            f"# 100k-Gaussian object-scale workload (8 views 800x800, 26 samples/tile).\n"
-            f"# Commands (one counter per run, from the repository root):\n"
-            f"#   {command}\n"
-            f"# Counter values are KiB per dispatch (median over the GN products of the run);\n"
-            f"# each is scaled by (known copy size / the same counter for a {copy_mib} MiB device copy).\n"
-            f"fetch_kib_splat: {out['FETCH_SIZE'][0]:.1f}\n"
-            f"fetch_kib_copy_{copy_mib}MiB: {out['FETCH_SIZE'][1]:.1f}\n"
-            f"fetch_scale: {out['FETCH_SIZE'][2]:.4f}\n"
-            f"write_kib_splat: {out['WRITE_SIZE'][0]:.1f}\n"
-            f"write_kib_copy_{copy_mib}MiB: {out['WRITE_SIZE'][1]:.1f}\n"
-            f"write_scale: {out['WRITE_SIZE'][2]:.4f}\n"
-            f"hbm_bytes_per_launch: {fetch + write:.0f}\n"
-            f"kernel_source_sha256: {kernel_hash}\n")
-    with open(TRAFFIC_FILE, "w") as f:
-        f.write(text)
-    return text
+    texts = []
+    for which, (match, title, path, _) in SPLAT_KERNELS.items():
+        out = {}
+        for counter, vals in runs.items():
+            xs = [x for k, v in vals.items() if match in k for x in v]
+            if xs:
+                out[counter] = (float(np.median(xs)), copy[counter], copy_mib * 1024.0 / copy[counter])
+        if len(out) < 2:
+            continue
+        fetch = out["FETCH_SIZE"][0] * out["FETCH_SIZE"][2] * 1024
+        write = out["WRITE_SIZE"][0] * out["WRITE_SIZE"][2] * 1024
+        text = (f"# HBM traffic of {title}, one launch per GN product,\n"
+                f"# 100k-Gaussian object-scale workload (8 views 800x800, 26 samples/tile).\n"
+                f"# Commands (one counter per run, from the repository root):\n"
+                f"#   {command}\n"
+                f"# Counter values are KiB per dispatch (median over the launches of the run);\n"
+                f"# each is scaled by (known copy size / the same counter for a {copy_mib} MiB device copy).\n"
+                f"fetch_kib_splat: {out['FETCH_SIZE'][0]:.1f}\n"
+                f"fetch_kib_copy_{copy_mib}MiB: {out['FETCH_SIZE'][1]:.1f}\n"
+                f"fetch_scale: {out['FETCH_SIZE'][2]:.4f}\n"
+                f"write_kib_splat: {out['WRITE_SIZE'][0]:.1f}\n"
+                f"write_kib_copy_{copy_mib}MiB: {out['WRITE_SIZE'][1]:.1f}\n"
+                f"write_scale: {out['WRITE_SIZE'][2]:.4f}\n"
+                f"hbm_bytes_per_launch: {fetch + write:.0f}\n"
+                f"kernel_source_sha256: {kernel_hash}\n")
+        with open(path, "w") as f:
+            f.write(text)
+        texts.append(text)
+    if not texts:
+        raise SystemExit("no splat kernel dispatches in both counter runs")
+    return "\n".join(texts)
 
 
 def lm_breakdown(L, torch, fr, targets, w, sampler, it, gn_ms):
@@ -349,32 +370,35 @@ def serving_main(args):
     print(json.dumps(res), flush=True)
 
 
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "gn_splat_counters_cfg1.txt")
-
-
 def summarize_counters(dirs: list[str], command: str) -> str:
     """Median per dispatch of every counter found in rocprofv3 --pmc output
-    folders, for the fused splat kernel; writes COUNTERS_FILE."""
+    folders, for each of the GN product's splat kernels the run launched;
+    writes one summary file per kernel."""
     import csv
     import glob
-    vals: dict[str, list[float]] = {}
-    for d in dirs:
-        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            for row in csv.DictReader(open(f)):
-                if "deriv_kernel<3" in row["Kernel_Name"]:
-                    vals.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
-    if not vals:
-        raise SystemExit("no deriv_kernel<3> dispatches in " + " ".join(dirs))
-    lines = ["# rocprofv3 counters of the fused splat kernel deriv_kernel<3> (one GN product),",
-             "# 100k-Gaussian object-scale workload (8 views 800x800, 26 samples/tile); median per dispatch.",
-             "# Commands (one --pmc pass per counter group, from the repository root):",
-             f"#   {command}"]
-    for k in sorted(vals):
-        lines.append(f"{k}: {float(np.median(vals[k])):.6g}  (dispatches: {len(vals[k])})")
-    text = "\n".join(lines) + "\n"
-    with open(COUNTERS_FILE, "w") as f:
-        f.write(text)
-    return text
+    texts = []
+    for which, (match, title, _, path) in SPLAT_KERNELS.items():
+        vals: dict[str, list[float]] = {}
+        for d in dirs:
+            for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+                for row in csv.DictReader(open(f)):
+                    if match in row["Kernel_Name"]:
+                        vals.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+        if not vals:
+            continue
+        lines = [f"# rocprofv3 counters of {title},",
+                 "# 100k-Gaussian object-scale workload (8 views 800x800, 26 samples/tile); median per dispatch.",
+                 "# Commands (one --pmc pass per counter group, from the repository root):",
+                 f"#   {command}"]
+        for k in sorted(vals):
+            lines.append(f"{k}: {float(np.median(vals[k])):.6g}  (dispatches: {len(vals[k])})")
+        text = "\n".join(lines) + "\n"
+        with open(path, "w") as f:
+            f.write(text)
+        texts.append(text)
+    if not texts:
+        raise SystemExit("no splat kernel dispatches in " + " ".join(dirs))
+    return "\n".join(texts)
 
 
 def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n: int | None = None) -> dict:
@@ -523,7 +547,7 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
     t_hbm, t_alu = b_alg / (HBM_PEAK_GBS * 1e9), f_alg / (FP32_PEAK_TFLOPS * 1e12)
     bound_alu = t_alu > t_hbm
     kernel_hash = hashlib.sha256(open(SPLAT_SOURCE, "rb").read()).hexdigest()
-    traffic = traffic_from_profile(kernel_hash, workload == "cfg1" and n is None)
+    traffic = traffic_from_profile(kernel_hash, workload == "cfg1" and n is None, "table" if table else "walk")
     # the whole GN product (tangent projection, splat, reverse chain)
     b_gn = 4 * fr.P * 3 + n_vis * B_VIS + b_alg
     f_gn = f_alg + n_vis * F_VIS

@@ -163,6 +163,15 @@ typedef struct lmrs_frame {
                              pairs of the batch; [V*T + 1] = 1 when the table
                              is built for the current render, else 0          */
   int64_t blend_capacity; /* pairs available in blend_k, blend_m, blend_run   */
+  /* SSIM residual (Supp. B, Sec. 6; see lmrs_ssim_residual). NULL when not
+   * used. With wc set, the operator of lmrs_gn_product, lmrs_pcg and the LM
+   * calls is J^T diag(wc) J + lambda D, and the diagonal of lmrs_gn_diag and
+   * of the Jacobi preconditioner is that of J^T diag(wbar) J, wbar the mean
+   * of a sample's three channel weights. */
+  float* wc;              /* [S][3] per-channel operator weights, or NULL = w
+                             on every channel         (ssim, lm with SSIM: out) */
+  float* image;           /* [V][height][width][3] full render of the batch
+                             views                    (ssim, lm with SSIM: out) */
 } lmrs_frame;
 
 /* Length in int32 of lmrs_frame.sched for a batch of `tiles` = V*T tiles. */
@@ -192,6 +201,10 @@ typedef struct lmrs_lm_params {
                            steps rise to 8 after the 50th iteration); 0 keeps
                            cg_iters throughout                                  */
   int32_t late_iter;    /* first iteration of cg_iters_late (50)                */
+  float ssim_weight;    /* s > 0 adds the SSIM residual with weight s beside the
+                           colour residual (Supp. B: 0.2; see
+                           lmrs_ssim_residual) and needs f->wc and f->image;
+                           0 = colour residual only (f->wc ignored)             */
 } lmrs_lm_params;
 
 /* Pixel samplers (lmrs_sample, lmrs_lm_params.sampler). */
@@ -204,7 +217,8 @@ typedef struct lmrs_lm_params {
 
 /* Slots of the device report written by lmrs_pcg / lmrs_lm_step. */
 #define LMRS_REPORT_FLOATS 12
-#define LMRS_REP_LOSS 0        /* sampled weighted loss sum_i w_i |r_i|^2        */
+#define LMRS_REP_LOSS 0        /* sampled weighted loss sum_i w_i |r_i|^2 (with
+                                  SSIM: sum_i w_i (|r_i|^2 + s |rho_i|^2))     */
 #define LMRS_REP_ETA 1         /* learning rate applied                           */
 #define LMRS_REP_XDC_MAX 2     /* max |x| over the DC colour coefficients         */
 #define LMRS_REP_CG_DONE 3     /* PCG iterations that updated x                  */
@@ -360,6 +374,29 @@ lmrs_status lmrs_residual_scores(const lmrs_frame* f, const lmrs_render_opts* o,
  * counts: device [V][T][256]. */
 lmrs_status lmrs_contributor_counts(const lmrs_frame* f, const lmrs_render_opts* o, float* counts, void* stream);
 
+/* SSIM residual with the diagonal approximation (Supp. B "Results with SSIM
+ * loss"; Sec. 6 Limitations). The paper adds SSIM to the colour loss with
+ * weights 0.2 and 1.0 and keeps only the dependence of each pixel's SSIM on
+ * that pixel's own rendered colour; it gives no formula. Here: per colour
+ * channel c, SSIM_c(p) of Wang et al. over an 11 x 11 Gaussian window
+ * (sigma 1.5, weights summing to 1, zero outside the image), C1 = 0.01^2,
+ * C2 = 0.03^2, enters the least-squares objective as a second residual
+ * rho = 1 - SSIM_c(p) per sampled pixel and channel with weight s:
+ *   E = sum_i w_i sum_c (r_ic^2 + s rho_ic^2),  r = C - I.
+ * With delta = -d SSIM_c(p) / d C_c(p) (the centre pixel only), the
+ * Gauss-Newton system has b = J^T u and operator J^T diag(wc) J + lambda D,
+ *   u_ic = w_i (r_ic + s delta_ic rho_ic),  wc_ic = w_i (1 + s delta_ic^2).
+ * This call renders every pixel of the batch views into f->image (as
+ * lmrs_render with k = 256, background added), then at every sample writes
+ * u (device [S][3]) and f->wc. r, SSIM and delta come from f->image and the
+ * targets (device [*][height][width][3], indexed by camera id); the window
+ * sums are taken in FP64. tile_loss: device double [V*T] (the tile's share
+ * of E) or NULL. Needs rec, rect, the tile lists and f->pix / f->w (or k =
+ * 256 with pix NULL); s >= 0. lmrs_lm_step with prm->ssim_weight = s calls
+ * it in place of the colour residual. */
+lmrs_status lmrs_ssim_residual(const lmrs_frame* f, const lmrs_render_opts* o, const float* targets, float s,
+                               float* u, double* tile_loss, void* stream);
+
 /* a4. Stratified pixel sampling (Sec. 4.4), writes f->pix and f->w
  * ([V][T][k], device; both must be non-NULL).
  * LMRS_SAMPLER_UNIFORM: k distinct pixels per tile, the k smallest
@@ -408,7 +445,9 @@ lmrs_status lmrs_view_batch(const int32_t* labels, int32_t n_cams, int32_t batch
  * counts; with the
  * uniform sampler and f->pix NULL, k = 256 takes every pixel with weight 1),
  * render, residuals r = C - I against targets
- * (device [*][height][width][3], indexed by camera id), b = J^T W r,
+ * (device [*][height][width][3], indexed by camera id), b = J^T W r (with
+ * prm->ssim_weight > 0: the SSIM residual of lmrs_ssim_residual added, b =
+ * J^T u and the operator weighted by f->wc),
  * Jacobi-PCG, learning rate (Sec. 4.5: eta_warm for iter < warm_iters, else
  * min(eta_cap, 1 / max |x_dc|)) and the descent update beta <- beta - eta x.
  * f->beta must equal beta; f->pix and f->w receive the samples. Waits for the

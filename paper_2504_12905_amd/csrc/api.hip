@@ -55,6 +55,7 @@ struct Scratch {
   float* x = nullptr;
   float* wr = nullptr;
   float* scores = nullptr;
+  double* tile_loss = nullptr;
   double* sc = nullptr;
   double* red = nullptr;
   BinScratch bin{};
@@ -101,6 +102,7 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
     s.x = c.take<float>(P);
     s.wr = c.take<float>((size_t)d.S * 3);
     s.scores = c.take<float>((size_t)d.V * d.T * 256);
+    s.tile_loss = c.take<double>((size_t)d.V * d.T);
   }
   s.red = c.take<double>(kRedDoubles);
   return s;
@@ -287,15 +289,24 @@ lmrs_status check_lm_args(const lmrs_frame* f, const float* beta, const float* t
     return fail(LMRS_EINVAL, "the weighted samplers need pix and w buffers");
   if (prm->cg_iters < 0 || prm->cg_iters_late < 0) return fail(LMRS_EINVAL, "cg_iters must be >= 0");
   if (!(prm->lambda >= 0.f)) return fail(LMRS_EINVAL, "lambda must be >= 0");
+  if (!(prm->ssim_weight >= 0.f) || prm->ssim_weight > 1e30f)
+    return fail(LMRS_EINVAL, "ssim_weight must be finite and >= 0");
+  if (prm->ssim_weight > 0.f && (!f->wc || !f->image))
+    return fail(LMRS_EINVAL, "ssim_weight > 0 needs the frame's wc and image buffers");
   return LMRS_OK;
 }
 
 // Alg. 1 after binning: samples, render, residuals, b, preconditioner, PCG,
 // learning rate and update. Enqueue only (no host synchronisation).
-void solve_sequence(const lmrs_frame* f, const FrameDims& d, float* beta, const float* targets,
+void solve_sequence(const lmrs_frame* f_in, const FrameDims& d, float* beta, const float* targets,
                     const float* dvec, const lmrs_lm_params& prm, const lmrs_render_opts& o, float* report,
                     const Scratch& s, hipStream_t st) {
   const int64_t P = (int64_t)d.n * d.pg;
+  // the operator takes per-channel weights only from this step's SSIM residual
+  const bool ssim = prm.ssim_weight > 0.f;
+  lmrs_frame fc = *f_in;
+  if (!ssim) fc.wc = nullptr;
+  const lmrs_frame* f = &fc;
   if (prm.sampler == LMRS_SAMPLER_RESIDUAL) {
     launch_render_scores(f, d, o, targets, s.scores, st);
     launch_sample_residual(f, d, s.scores, prm.seed, prm.iter, st);
@@ -306,7 +317,12 @@ void solve_sequence(const lmrs_frame* f, const FrameDims& d, float* beta, const 
     launch_sample_uniform(f, d, prm.seed, prm.iter, st);
   }
   launch_render(f, d, o, st);
-  launch_residual(f, d, targets, s.wr, s.red, report, st);
+  if (ssim) {
+    launch_render_image(f, d, o, f->image, st);
+    launch_ssim(f, d, targets, prm.ssim_weight, s.wr, s.tile_loss, s.red + 2 * kRedBlocks, report, st);
+  } else {
+    launch_residual(f, d, targets, s.wr, s.red, report, st);
+  }
   vjp_diag_sequence(f, d, o, s.wr, s.b, s.diag, s, st);
   // CG schedule (Sec. 5): cg_iters_late GN products from iteration late_iter on
   const bool late = prm.cg_iters_late > 0 && prm.late_iter > 0 && prm.iter >= prm.late_iter;
@@ -609,6 +625,22 @@ lmrs_status lmrs_contributor_counts(const lmrs_frame* f, const lmrs_render_opts*
   LMRS_TRY(need(counts, "counts"));
   launch_render_counts(f, dims_of(f), *o, counts, (hipStream_t)stream);
   return hip_check("lmrs_contributor_counts");
+}
+
+lmrs_status lmrs_ssim_residual(const lmrs_frame* f, const lmrs_render_opts* o, const float* targets, float s,
+                               float* u, double* tile_loss, void* stream) {
+  LMRS_TRY(check_frame(f));
+  LMRS_TRY(need(o, "opts"));
+  LMRS_TRY(check_render_state(f));
+  LMRS_TRY(need(targets, "targets"));
+  LMRS_TRY(need(u, "u"));
+  LMRS_TRY(need(f->wc, "wc"));
+  LMRS_TRY(need(f->image, "image"));
+  if (!(s >= 0.f) || s > 1e30f) return fail(LMRS_EINVAL, "s must be finite and >= 0");
+  const FrameDims d = dims_of(f);
+  launch_render_image(f, d, *o, f->image, (hipStream_t)stream);
+  launch_ssim(f, d, targets, s, u, tile_loss, nullptr, nullptr, (hipStream_t)stream);
+  return hip_check("lmrs_ssim_residual");
 }
 
 lmrs_status lmrs_sample(const lmrs_frame* f, int32_t sampler, uint64_t seed, int32_t iter, const float* scores,

@@ -539,6 +539,104 @@ __global__ __launch_bounds__(256) void lm_apply_kernel(float* __restrict__ beta,
     beta[i] -= e * x[i];
 }
 
+// SSIM residual with the diagonal approximation (Supp. B; Sec. 6 names the
+// approximation, the paper gives no formula). One workgroup per (view, tile):
+// the tile's pixels and a 5-pixel ring around it, of the rendered image and
+// of the target, are staged in LDS (zero outside the image), and each
+// (sample, channel) item sums its 11 x 11 Gaussian window (sigma 1.5, weights
+// summing to 1) in FP64: the local means, variances and covariance of the
+// SSIM of Wang et al., C1 = 0.01^2, C2 = 0.03^2. With the centre pixel's
+// window weight g0, the derivative of SSIM with respect to the rendered
+// colour of the centre pixel alone (the diagonal approximation) follows from
+// d mu_x = g0, d sigma_x^2 = 2 g0 (x_p - mu_x), d sigma_xy = g0 (y_p - mu_y).
+// Writes, with r = x_p - y_p, rho = 1 - SSIM, delta = -d SSIM / d x_p:
+//   u = w (r + s delta rho), wc = w (1 + s delta^2),
+// and the tile's share of the objective, sum w (r^2 + s rho^2).
+constexpr int kSsimHalf = 5;                      // 11 x 11 window
+constexpr int kSsimSpan = kTile + 2 * kSsimHalf;  // staged rows and columns
+constexpr int kSsimPlane = kSsimSpan * kSsimSpan;
+
+__global__ __launch_bounds__(256) void ssim_kernel(const float* __restrict__ image, const float* __restrict__ targets,
+                                                   const int32_t* __restrict__ view_ids,
+                                                   const uint8_t* __restrict__ pix, const float* __restrict__ wts,
+                                                   int T, int TX, int W, int H, int k, double s_w,
+                                                   float* __restrict__ u, float* __restrict__ wc,
+                                                   double* __restrict__ tile_loss) {
+  __shared__ float sx[3 * kSsimPlane];
+  __shared__ float sy[3 * kSsimPlane];
+  __shared__ double s_red[256];
+  const int tid = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int v = (int)(tile / T), t = (int)(tile % T);
+  const int cam = view_ids ? view_ids[v] : v;
+  const int x0 = (t % TX) * kTile - kSsimHalf, y0 = (t / TX) * kTile - kSsimHalf;
+  for (int e = tid; e < kSsimPlane; e += 256) {
+    const int gx = x0 + e % kSsimSpan, gy = y0 + e / kSsimSpan;
+    const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+    const int64_t pi = in ? (((int64_t)v * H + gy) * W + gx) * 3 : 0;
+    const int64_t ti = in ? (((int64_t)cam * H + gy) * W + gx) * 3 : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sx[c * kSsimPlane + e] = in ? image[pi + c] : 0.f;
+      sy[c * kSsimPlane + e] = in ? targets[ti + c] : 0.f;
+    }
+  }
+  // the window's 1-D weights exp(-d^2 / (2 sigma^2)), normalised
+  double g[2 * kSsimHalf + 1];
+  double gs = 0.0;
+#pragma unroll
+  for (int a = 0; a <= 2 * kSsimHalf; ++a) {
+    const double d = (double)(a - kSsimHalf);
+    g[a] = exp(-d * d / (2.0 * 1.5 * 1.5));
+    gs += g[a];
+  }
+#pragma unroll
+  for (int a = 0; a <= 2 * kSsimHalf; ++a) g[a] /= gs;
+  const double g0 = g[kSsimHalf] * g[kSsimHalf];
+  constexpr double C1 = 0.01 * 0.01, C2 = 0.03 * 0.03;
+  __syncthreads();
+  double loss = 0.0;
+  for (int q = tid; q < 3 * k; q += 256) {
+    const int j = q / 3, c = q % 3;
+    const int64_t i = tile * k + j;
+    const int p = pix ? (int)pix[i] : j;
+    const int off = c * kSsimPlane + (p >> 4) * kSsimSpan + (p & 15);  // the window's first row and column
+    double mx = 0.0, my = 0.0, mxx = 0.0, myy = 0.0, mxy = 0.0;
+#pragma unroll
+    for (int a = 0; a <= 2 * kSsimHalf; ++a) {
+      double rx = 0.0, ry = 0.0, rxx = 0.0, ryy = 0.0, rxy = 0.0;
+#pragma unroll
+      for (int b = 0; b <= 2 * kSsimHalf; ++b) {
+        const double xv = sx[off + a * kSsimSpan + b], yv = sy[off + a * kSsimSpan + b];
+        rx += g[b] * xv;
+        ry += g[b] * yv;
+        rxx += g[b] * (xv * xv);
+        ryy += g[b] * (yv * yv);
+        rxy += g[b] * (xv * yv);
+      }
+      mx += g[a] * rx;
+      my += g[a] * ry;
+      mxx += g[a] * rxx;
+      myy += g[a] * ryy;
+      mxy += g[a] * rxy;
+    }
+    const double vx = mxx - mx * mx, vy = myy - my * my, cxy = mxy - mx * my;
+    const double a1 = 2.0 * mx * my + C1, a2 = 2.0 * cxy + C2;
+    const double b1 = mx * mx + my * my + C1, b2 = vx + vy + C2;
+    const double ssim = (a1 * a2) / (b1 * b2);
+    const int centre = off + kSsimHalf * kSsimSpan + kSsimHalf;
+    const double xp = sx[centre], yp = sy[centre];
+    const double dssim = 2.0 * g0 * ((my * a2 + a1 * (yp - my)) / (b1 * b2) - ssim * (mx / b1 + (xp - mx) / b2));
+    const double delta = -dssim, rho = 1.0 - ssim, r = xp - yp;
+    const double w = wts ? (double)wts[i] : 1.0;
+    u[3 * i + c] = (float)(w * (r + s_w * delta * rho));
+    wc[3 * i + c] = (float)(w * (1.0 + s_w * delta * delta));
+    loss += w * (r * r + s_w * rho * rho);
+  }
+  const double tot = block_sum(loss, s_red);
+  if (tid == 0 && tile_loss) tile_loss[tile] = tot;
+}
+
 }  // namespace
 
 void launch_sample_uniform(const lmrs_frame* f, const FrameDims& d, uint64_t seed, int iter, hipStream_t s) {
@@ -567,6 +665,17 @@ void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targe
                                              d.W, d.H, d.k, d.S, wr, partials);
   finalize_kernel<<<1, 256, 0, s>>>(partials, kRedBlocks, 1, kRedBlocks, partials + 2 * kRedBlocks);
   if (report) report_kernel<<<1, 64, 0, s>>>(partials + 2 * kRedBlocks, report, LMRS_REP_LOSS);
+}
+
+void launch_ssim(const lmrs_frame* f, const FrameDims& d, const float* targets, float s_w, float* u,
+                 double* tile_loss, double* loss_out, float* report, hipStream_t s) {
+  const int64_t tiles = (int64_t)d.V * d.T;
+  ssim_kernel<<<(unsigned)tiles, 256, 0, s>>>(f->image, targets, f->view_ids, f->pix, f->w, d.T, d.TX, d.W, d.H,
+                                              d.k, (double)s_w, u, f->wc, tile_loss);
+  if (loss_out && tile_loss) {
+    finalize_kernel<<<1, 256, 0, s>>>(tile_loss, (int)tiles, 1, (int)tiles, loss_out);
+    if (report) report_kernel<<<1, 64, 0, s>>>(loss_out, report, LMRS_REP_LOSS);
+  }
 }
 
 void launch_report_count(const int64_t* count, int64_t capacity, float* report, hipStream_t s,

@@ -114,9 +114,12 @@ struct PixelRegs {
   int last[NS];
 };
 
+// w[s]: the sample weight, or with per-channel weights wc ([S][3], the SSIM
+// residual's operator weights) their channel mean (the weight of the diagonal
+// pass).
 template <int NS>
-__device__ __forceinline__ int load_pixel_regs(const uint8_t* pix, const float* wts, const int32_t* lastv, int k,
-                                               const TileCtx& c, PixelRegs<NS>& pr) {
+__device__ __forceinline__ int load_pixel_regs(const uint8_t* pix, const float* wts, const float* wc,
+                                               const int32_t* lastv, int k, const TileCtx& c, PixelRegs<NS>& pr) {
   int lmax = -1;
   const int lane = lane_id();
 #pragma unroll
@@ -128,7 +131,7 @@ __device__ __forceinline__ int load_pixel_regs(const uint8_t* pix, const float* 
     if (j < k) {
       const int64_t i = c.tile_lin * k + j;
       pixel_center(pix, k, c, j, &pr.xc[s], &pr.yc[s]);
-      pr.w[s] = wts ? wts[i] : 1.f;
+      pr.w[s] = wc ? ((wc[3 * i] + wc[3 * i + 1]) + wc[3 * i + 2]) * (1.f / 3.f) : wts ? wts[i] : 1.f;
       if (lastv) pr.last[s] = lastv[i];
       lmax = max(lmax, pr.last[s]);
     }
@@ -289,8 +292,11 @@ struct ScoreOut {
   const float* targets;     // [cameras][H][W][3]
   const int32_t* view_ids;  // [V] or NULL
   int W, H;
-  float* score;             // [V][T][256]
+  float* score;             // [V][T][256], or the image [V][H][W][3]
 };
+
+// What score_kernel writes per pixel.
+enum ScoreMode { kScoreResidual = 0, kScoreCount = 1, kScoreImage = 2 };
 
 // W waves share a tile; wave wv renders the sample slots j with j % W == wv.
 // With one slot of pixels and MP > 1 (at most MP pixels per wave), each lane
@@ -312,7 +318,7 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
   const bool mine = (lane & (W - 1)) == wv;
   const TileCtx c = tile_ctx(tile_start, T, TX, blockIdx.x);
   PixelRegs<NS> pr;
-  load_pixel_regs<NS>(pix, nullptr, nullptr, k, c, pr);
+  load_pixel_regs<NS>(pix, nullptr, nullptr, nullptr, k, c, pr);
   float sT[NS], sC0[NS], sC1[NS], sC2[NS];
   int sLast[NS], sDone[NS];
 #pragma unroll
@@ -468,11 +474,12 @@ __global__ __launch_bounds__(kBlendScanThreads) void blend_scan_kernel(int64_t* 
 // stops it (the first entry that would take T below t_min), here with the
 // transmittance multiplied entry by entry; a wave leaves a chunk when all
 // its pixels have stopped, the workgroup its list when all 256 have.
-// With COUNT, the kernel writes instead the number of Gaussians blended into
-// each pixel (the G_p of the contribution-weighted sampler, Supp. E eq. 17).
+// kScoreCount writes instead the number of Gaussians blended into each pixel
+// (the G_p of the contribution-weighted sampler, Supp. E eq. 17), kScoreImage
+// the rendered colour (background added) into a [V][H][W][3] image.
 constexpr int kScoreThreads = 256;
 
-template <bool COUNT>
+template <int MODE>
 __global__ __launch_bounds__(kScoreThreads) void score_kernel(const float* __restrict__ rec,
                                                               const int64_t* __restrict__ tile_start,
                                                               const int32_t* __restrict__ ids, int n, int T,
@@ -528,14 +535,21 @@ __global__ __launch_bounds__(kScoreThreads) void score_kernel(const float* __res
     }
     if (__syncthreads_and(done)) break;
   }
-  if (COUNT) {
+  if (MODE == kScoreCount) {
     so.score[c.tile_lin * 256 + tid] = (float)blended;
     return;
   }
-  const int cam = so.view_ids ? so.view_ids[c.v] : c.v;
   const int x = (c.t % TX) * kTile + (tid & 15), y = (c.t / TX) * kTile + (tid >> 4);
-  const float* tg = so.targets + (((int64_t)cam * so.H + y) * so.W + x) * 3;
   const float r0 = C0 + Tr * o.bg[0], r1 = C1 + Tr * o.bg[1], r2 = C2 + Tr * o.bg[2];
+  if (MODE == kScoreImage) {
+    float* px = so.score + (((int64_t)c.v * so.H + y) * so.W + x) * 3;
+    px[0] = r0;
+    px[1] = r1;
+    px[2] = r2;
+    return;
+  }
+  const int cam = so.view_ids ? so.view_ids[c.v] : c.v;
+  const float* tg = so.targets + (((int64_t)cam * so.H + y) * so.W + x) * 3;
   so.score[c.tile_lin * 256 + tid] = (fabsf(r0 - tg[0]) + fabsf(r1 - tg[1])) + fabsf(r2 - tg[2]);
 }
 
@@ -597,8 +611,8 @@ template <int MODE, int NS, int W, int MP>
 __device__ __forceinline__ void deriv_tile(
     const float* __restrict__ rec, const float* __restrict__ tan, const int64_t* __restrict__ tile_start,
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
-    const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
-    const lmrs_render_opts& o, const float* __restrict__ u_in, float* __restrict__ jp_out,
+    const float* __restrict__ wc, const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n,
+    int T, int TX, int k, const lmrs_render_opts& o, const float* __restrict__ u_in, float* __restrict__ jp_out,
     float* __restrict__ grad2d, int64_t tile_lin, int wv, float* red) {
   constexpr bool FWD = MODE != 2;
   constexpr bool REV = MODE != 1;
@@ -606,7 +620,7 @@ __device__ __forceinline__ void deriv_tile(
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX, tile_lin);
   PixelRegs<NS> pr;
-  const int lmax = load_pixel_regs<NS>(pix, wts, lastv, k, c, pr);
+  const int lmax = load_pixel_regs<NS>(pix, wts, nullptr, lastv, k, c, pr);
   int px[DEALT ? MP : 1], pl[DEALT ? MP : 1];
   bool own[NS];
   int lmax_own;
@@ -731,6 +745,17 @@ __device__ __forceinline__ void deriv_tile(
           jp_out[3 * i + 1] = d1;
           jp_out[3 * i + 2] = d2;
         }
+      } else if (wc) {  // per-channel operator weights
+        float w0 = 0.f, w1 = 0.f, w2 = 0.f;
+        if (j < k) {
+          const int64_t i = c.tile_lin * k + j;
+          w0 = wc[3 * i];
+          w1 = wc[3 * i + 1];
+          w2 = wc[3 * i + 2];
+        }
+        su0[s] = w0 * d0;
+        su1[s] = w1 * d1;
+        su2[s] = w2 * d2;
       } else {
         su0[s] = pr.w[s] * d0;
         su1[s] = pr.w[s] * d1;
@@ -866,8 +891,8 @@ template <int MODE, int NS, int W, int MP>
 __global__ __launch_bounds__(kWave* W) void deriv_kernel(
     const float* __restrict__ rec, const float* __restrict__ tan, const int64_t* __restrict__ tile_start,
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
-    const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
-    lmrs_render_opts o, const float* __restrict__ u_in, float* __restrict__ jp_out,
+    const float* __restrict__ wc, const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n,
+    int T, int TX, int k, lmrs_render_opts o, const float* __restrict__ u_in, float* __restrict__ jp_out,
     float* __restrict__ grad2d, int32_t* __restrict__ sched, int tiles, const int64_t* __restrict__ built) {
   __shared__ int next_tile[2];
   __shared__ float red[MODE == 1 ? 1 : 2 * kRedBuf<W>];
@@ -883,8 +908,8 @@ __global__ __launch_bounds__(kWave* W) void deriv_kernel(
     const int tile = next_tile[it & 1];
     if (tile == -1) break;
     if (tile >= 0)
-      deriv_tile<MODE, NS, W, MP>(rec, tan, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, u_in, jp_out,
-                           grad2d, tile, wv, red);
+      deriv_tile<MODE, NS, W, MP>(rec, tan, tile_start, ids, pix, wts, wc, trans, lastv, n, T, TX, k, o, u_in,
+                                  jp_out, grad2d, tile, wv, red);
   }
   if (threadIdx.x == 0) sched_sign_off(sr);
 }
@@ -934,7 +959,8 @@ __device__ __forceinline__ int wave_excl_scan_i(int x) {
 template <int NS, bool VJP, bool GRAM>
 __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const int64_t* __restrict__ tile_start,
                                           const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix,
-                                          const float* __restrict__ wts, const float* __restrict__ trans,
+                                          const float* __restrict__ wts, const float* __restrict__ wc,
+                                          const float* __restrict__ trans,
                                           const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
                                           const lmrs_render_opts& o, float* __restrict__ gram,
                                           const float* __restrict__ u_in, float* __restrict__ grad2d,
@@ -942,7 +968,7 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX, tile_lin);
   PixelRegs<NS> pr;
-  const int lmax = load_pixel_regs<NS>(pix, wts, lastv, k, c, pr);
+  const int lmax = load_pixel_regs<NS>(pix, wts, wc, lastv, k, c, pr);
   float sT[NS], sS0[NS], sS1[NS], sS2[NS], sU0[NS], sU1[NS], sU2[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
@@ -1126,6 +1152,7 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
                                                      const int32_t* __restrict__ ids,
                                                      const uint8_t* __restrict__ pix,
                                                      const float* __restrict__ wts,
+                                                     const float* __restrict__ wc,
                                                      const float* __restrict__ trans,
                                                      const int32_t* __restrict__ lastv, int n, int T,
                                                      int TX, int k, lmrs_render_opts o,
@@ -1142,8 +1169,8 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
     const int tile = sched_next(sr, count);
     if (tile == -1) break;
     if (tile >= 0)
-      gram_tile<NS, VJP, GRAM>(rec, tile_start, ids, pix, wts, trans, lastv, n, T, TX, k, o, gram, u_in, grad2d,
-                               bo, tile, tr, tr_id);
+      gram_tile<NS, VJP, GRAM>(rec, tile_start, ids, pix, wts, wc, trans, lastv, n, T, TX, k, o, gram, u_in,
+                               grad2d, bo, tile, tr, tr_id);
   }
   sched_finish(sr);
 }
@@ -1304,7 +1331,8 @@ __device__ __forceinline__ void seg_scan9(float (&g)[9], int dist) {
 __global__ __launch_bounds__(kBlendGnThreads) void blend_gn_kernel(
     const float* __restrict__ rec, const float* __restrict__ tan, const float4* __restrict__ bk,
     const uint32_t* __restrict__ bm, const int64_t* __restrict__ bstart, const uint8_t* __restrict__ pix,
-    const float* __restrict__ wts, int n, int T, int TX, int k, lmrs_render_opts o, float* __restrict__ grad2d,
+    const float* __restrict__ wts, const float* __restrict__ wc, int n, int T, int TX, int k, lmrs_render_opts o,
+    float* __restrict__ grad2d,
     int32_t* __restrict__ sched, int tiles, int64_t pix_major) {
   __shared__ float4 s_u[kMaxK];    // J p, then u, of each sample slot (4th word unused)
   __shared__ float2 s_xy[kMaxK];  // pixel centre of each sample slot
@@ -1381,11 +1409,16 @@ __global__ __launch_bounds__(kBlendGnThreads) void blend_gn_kernel(
       }
     }
     __syncthreads();
-    // 2. u = w J p
+    // 2. u = w J p (per channel with operator weights wc)
     for (int j = tid; j < k; j += kBlendGnThreads) {
-      const float w = wts ? wts[(int64_t)tile * k + j] : 1.f;
+      const int64_t i = (int64_t)tile * k + j;
       const float4 x = s_u[j];
-      s_u[j] = make_float4(x.x * w, x.y * w, x.z * w, 0.f);
+      if (wc) {
+        s_u[j] = make_float4(x.x * wc[3 * i], x.y * wc[3 * i + 1], x.z * wc[3 * i + 2], 0.f);
+      } else {
+        const float w = wts ? wts[i] : 1.f;
+        s_u[j] = make_float4(x.x * w, x.y * w, x.z * w, 0.f);
+      }
     }
     __syncthreads();
     // 3. J^T u over 64 consecutive pairs per wave step, pipelined like 1.
@@ -1603,14 +1636,22 @@ void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_re
                           const float* targets, float* scores, hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   const ScoreOut so{targets, f->view_ids, d.W, d.H, scores};
-  score_kernel<false><<<tiles, kScoreThreads, 0, s>>>(f->rec, f->tile_start, f->ids, d.n, d.T, d.TX, o, so);
+  score_kernel<kScoreResidual><<<tiles, kScoreThreads, 0, s>>>(f->rec, f->tile_start, f->ids, d.n, d.T, d.TX, o,
+                                                                so);
+}
+
+void launch_render_image(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* image,
+                         hipStream_t s) {
+  const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
+  const ScoreOut so{nullptr, f->view_ids, d.W, d.H, image};
+  score_kernel<kScoreImage><<<tiles, kScoreThreads, 0, s>>>(f->rec, f->tile_start, f->ids, d.n, d.T, d.TX, o, so);
 }
 
 void launch_render_counts(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* counts,
                           hipStream_t s) {
   const unsigned tiles = (unsigned)((int64_t)d.V * d.T);
   const ScoreOut so{nullptr, f->view_ids, d.W, d.H, counts};
-  score_kernel<true><<<tiles, kScoreThreads, 0, s>>>(f->rec, f->tile_start, f->ids, d.n, d.T, d.TX, o, so);
+  score_kernel<kScoreCount><<<tiles, kScoreThreads, 0, s>>>(f->rec, f->tile_start, f->ids, d.n, d.T, d.TX, o, so);
 }
 
 template <int MODE, int W>
@@ -1625,8 +1666,8 @@ void launch_deriv_mode(const lmrs_frame* f, const FrameDims& d, const lmrs_rende
   // at most 8 per wave), else 1 (dealt by slot)
   const int mp = W > 1 && small && d.k <= 8 * W ? (d.k + W - 1) / W : 1;
   auto go = [&](auto kern) {
-    kern<<<grid, block, 0, s>>>(f->rec, tan, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T,
-                                d.TX, d.k, o, u, jp, grad2d, f->sched, tiles, built);
+    kern<<<grid, block, 0, s>>>(f->rec, tan, f->tile_start, f->ids, f->pix, f->w, MODE == 3 ? f->wc : nullptr,
+                                f->trans, f->last, d.n, d.T, d.TX, d.k, o, u, jp, grad2d, f->sched, tiles, built);
   };
   if (!small) {
     go(deriv_kernel<MODE, 4, W, 1>);
@@ -1669,7 +1710,7 @@ void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts
   BlendOut bo{reinterpret_cast<float4*>(f->blend_k), f->blend_m, f->blend_run, f->blend_runs, f->blend_start,
               f->blend_k != nullptr, f->blend_capacity};
 #define LMRS_GRAM_ARGS                                                                                      \
-  f->rec, f->tile_start, f->ids, f->pix, f->w, f->trans, f->last, d.n, d.T, d.TX, d.k, o, gram, u, grad2d, \
+  f->rec, f->tile_start, f->ids, f->pix, f->w, f->wc, f->trans, f->last, d.n, d.T, d.TX, d.k, o, gram, u, grad2d, \
       f->sched, tiles, bo, f->blend_capacity
   const bool wide = d.k > kWave;
   if (!gram_sums) {
@@ -1691,7 +1732,7 @@ void launch_blend_gn(const lmrs_frame* f, const FrameDims& d, const lmrs_render_
   if (!f->blend_k) return;
   const int tiles = d.V * d.T;
   blend_gn_kernel<<<(unsigned)tiles, kBlendGnThreads, 0, s>>>(f->rec, tan, reinterpret_cast<const float4*>(f->blend_k),
-                                                   f->blend_m, f->blend_start, f->pix, f->w, d.n, d.T, d.TX, d.k, o,
+                                                   f->blend_m, f->blend_start, f->pix, f->w, f->wc, d.n, d.T, d.TX, d.k, o,
                                                    grad2d, f->sched, tiles, f->blend_capacity);
 }
 

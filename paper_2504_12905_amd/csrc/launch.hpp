@@ -65,6 +65,9 @@ void launch_render_scores(const lmrs_frame* f, const FrameDims& d, const lmrs_re
 // every pixel of the batch views: counts[V][T][256] = Gaussians blended into the pixel
 void launch_render_counts(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* counts,
                           hipStream_t s);
+// every pixel of the batch views: image[V][H][W][3] = rendered colour with background
+void launch_render_image(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* image,
+                         hipStream_t s);
 // counts[4] (int64, device): traversed entries, contributing entries, blending
 // pairs, pairs up to each pixel's last blended entry (see walk_count_kernel)
 void launch_walk_counts(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, int64_t* counts,
@@ -91,6 +94,11 @@ void launch_sample_gaussian(const lmrs_frame* f, const FrameDims& d, const float
                             int iter, hipStream_t s);
 void launch_residual(const lmrs_frame* f, const FrameDims& d, const float* targets, float* wr,
                      double* partials, float* report, hipStream_t s);
+// SSIM residual at the samples from f->image and the targets: u[S][3], f->wc;
+// tile_loss[V*T] (may be NULL) the tiles' shares of the objective, summed
+// into *loss_out (and report[LOSS]) when loss_out is not NULL
+void launch_ssim(const lmrs_frame* f, const FrameDims& d, const float* targets, float s_w, float* u,
+                 double* tile_loss, double* loss_out, float* report, hipStream_t s);
 void launch_dot(const float* a, const float* b, int64_t n, double* partials, double* out, hipStream_t s);
 // report[INST] = *count; ORs LMRS_FAIL_CAPACITY into report[STATUS] when *count > capacity
 // and report[PAIRS] = *pairs when pairs is not NULL

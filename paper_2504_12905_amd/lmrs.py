@@ -63,7 +63,8 @@ class _Frame(C.Structure):
                 ("pix", C.c_void_p), ("w", C.c_void_p), ("color", C.c_void_p),
                 ("trans", C.c_void_p), ("last", C.c_void_p), ("sched", C.c_void_p),
                 ("blend_k", C.c_void_p), ("blend_m", C.c_void_p), ("blend_run", C.c_void_p),
-                ("blend_runs", C.c_void_p), ("blend_start", C.c_void_p), ("blend_capacity", C.c_int64)]
+                ("blend_runs", C.c_void_p), ("blend_start", C.c_void_p), ("blend_capacity", C.c_int64),
+                ("wc", C.c_void_p), ("image", C.c_void_p)]
 
 
 def sched_ints(tiles: int) -> int:
@@ -75,7 +76,7 @@ class LmParams(C.Structure):
     _fields_ = [("iter", C.c_int32), ("cg_iters", C.c_int32), ("lam", C.c_float),
                 ("eta_cap", C.c_float), ("eta_warm", C.c_float), ("warm_iters", C.c_int32),
                 ("seed", C.c_uint64), ("sampler", C.c_int32), ("cg_iters_late", C.c_int32),
-                ("late_iter", C.c_int32)]
+                ("late_iter", C.c_int32), ("ssim_weight", C.c_float)]
 
 
 _vp, _i32, _f32, _sz = C.c_void_p, C.c_int32, C.c_float, C.c_size_t
@@ -106,13 +107,14 @@ _lib.lmrs_bin_tiles_async.argtypes = [_FP, _vp, _sz, _vp]
 _lib.lmrs_residual_scores.argtypes = [_FP, _vp, _vp, _vp, _vp]
 _lib.lmrs_sample.argtypes = [_FP, _i32, C.c_uint64, _i32, _vp, _vp]
 _lib.lmrs_contributor_counts.argtypes = [_FP, _vp, _vp, _vp]
+_lib.lmrs_ssim_residual.argtypes = [_FP, _vp, _vp, _f32, _vp, _vp, _vp]
 _lib.lmrs_view_clusters.argtypes = [_vp, _i32, _i32, C.c_uint64, _vp]
 _lib.lmrs_view_batch.argtypes = [_vp, _i32, _i32, C.c_uint64, _i32, _vp]
 for _name in ("lmrs_project", "lmrs_bin_tiles", "lmrs_render", "lmrs_jvp", "lmrs_vjp",
               "lmrs_gn_product", "lmrs_gn_product_timed", "lmrs_gn_product_noalloc", "lmrs_walk_counts", "lmrs_linearize",
               "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step", "lmrs_residual_scores", "lmrs_sample", "lmrs_lm_solve",
               "lmrs_contributor_counts", "lmrs_view_clusters", "lmrs_view_batch", "lmrs_lm_iterate",
-              "lmrs_bin_tiles_async"):
+              "lmrs_bin_tiles_async", "lmrs_ssim_residual"):
     getattr(_lib, _name).restype = _i32
 
 
@@ -150,6 +152,7 @@ class Frame:
     capacity: int = 0
     blend: bool = True             # keep the blend table (the render's linearization; see lmrs_frame)
     blend_capacity: int = 0        # pairs it can hold (grown by ensure_blend)
+    ssim: bool = False             # allocate wc / image (the SSIM residual's buffers)
     tensors: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -215,6 +218,11 @@ class Frame:
         else:
             t["pix"], t["w"] = None, None
         t["color"] = torch.empty((S, 3), dtype=torch.float32, device=dev)
+        if self.ssim:
+            t["wc"] = torch.empty((S, 3), dtype=torch.float32, device=dev)
+            t["image"] = torch.empty((self.n_views, self.height, self.width, 3), dtype=torch.float32, device=dev)
+        else:
+            t["wc"], t["image"] = None, None
         t["trans"] = torch.empty(S, dtype=torch.float32, device=dev)
         t["last"] = torch.empty(S, dtype=torch.int32, device=dev)
 
@@ -238,7 +246,9 @@ class Frame:
                       None if t["pix"] is None else t["pix"].data_ptr(),
                       None if t["w"] is None else t["w"].data_ptr(),
                       t["color"].data_ptr(), t["trans"].data_ptr(), t["last"].data_ptr(),
-                      t["sched"].data_ptr(), *self._blend_fields())
+                      t["sched"].data_ptr(), *self._blend_fields(),
+                      None if t["wc"] is None else t["wc"].data_ptr(),
+                      None if t["image"] is None else t["image"].data_ptr())
 
     def _blend_fields(self):
         if not self.blend:
@@ -412,6 +422,26 @@ def lmrs_contributor_counts(frame: Frame, out: torch.Tensor | None = None, opts=
     return out
 
 
+def lmrs_ssim_residual(frame: Frame, targets: torch.Tensor, s: float = 0.2, u: torch.Tensor | None = None,
+                       tile_loss: torch.Tensor | None = None, opts=None, stream=None) -> torch.Tensor:
+    """SSIM residual with the diagonal approximation at the frame's samples
+    (needs project + bin + samples; frame built with ssim=True): renders every
+    pixel into frame.image, writes frame.wc and returns u [S, 3] =
+    w (r + s delta rho). tile_loss: float64 [V*T] or None."""
+    opts = opts or default_opts()
+    assert frame.ssim, "Frame(ssim=True) holds the SSIM buffers"
+    assert targets.dtype == torch.float32 and targets.is_contiguous()
+    assert targets.shape[1:] == (frame.height, frame.width, 3)
+    u = u if u is not None else torch.empty((frame.S, 3), dtype=torch.float32, device=frame.beta.device)
+    assert u.dtype == torch.float32 and u.is_contiguous() and u.numel() == 3 * frame.S
+    if tile_loss is not None:
+        assert tile_loss.dtype == torch.float64 and tile_loss.numel() == frame.n_views * frame.T
+    fs = frame.struct()
+    _check(_lib.lmrs_ssim_residual(C.byref(fs), C.byref(opts), _ptr(targets), float(s), _ptr(u), _ptr(tile_loss),
+                                   _stream(stream)), "lmrs_ssim_residual")
+    return u
+
+
 def lmrs_sample(frame: Frame, sampler: int, seed: int, iter: int, scores: torch.Tensor | None = None,
                 stream=None):
     """Fills frame.pix / frame.w (frame must be sampled)."""
@@ -505,9 +535,9 @@ def view_batch(labels: "np.ndarray", batch: int, seed: int, iter: int) -> "np.nd
 
 def lm_params(iter: int, cg_iters: int, lam: float, seed: int = 0, eta_cap: float = 0.2,
               eta_warm: float = 0.05, warm_iters: int = 10, sampler: int = SAMPLER_UNIFORM,
-              cg_iters_late: int = 0, late_iter: int = 0) -> LmParams:
+              cg_iters_late: int = 0, late_iter: int = 0, ssim_weight: float = 0.0) -> LmParams:
     return LmParams(int(iter), int(cg_iters), float(lam), float(eta_cap), float(eta_warm), int(warm_iters),
-                    int(seed), int(sampler), int(cg_iters_late), int(late_iter))
+                    int(seed), int(sampler), int(cg_iters_late), int(late_iter), float(ssim_weight))
 
 
 EXPORTS = ("lmrs_status_str", "lmrs_last_error", "lmrs_report_status", "lmrs_workspace_bytes", "lmrs_project",
@@ -515,4 +545,5 @@ EXPORTS = ("lmrs_status_str", "lmrs_last_error", "lmrs_report_status", "lmrs_wor
            "lmrs_gn_product_timed", "lmrs_gn_product_noalloc", "lmrs_walk_counts", "lmrs_linearize",
            "lmrs_gn_diag", "lmrs_pcg", "lmrs_lm_step",
            "lmrs_residual_scores", "lmrs_contributor_counts", "lmrs_sample", "lmrs_lm_solve",
-           "lmrs_view_clusters", "lmrs_view_batch", "lmrs_lm_iterate", "lmrs_bin_tiles_async")
+           "lmrs_view_clusters", "lmrs_view_batch", "lmrs_lm_iterate", "lmrs_bin_tiles_async",
+           "lmrs_ssim_residual")

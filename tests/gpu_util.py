@@ -56,13 +56,13 @@ def lib():
     return lmrs
 
 
-def gpu_frame(n, deg, beta, cams, W, H, k=256, pix=None, wts=None, view_ids=None, render=True):
+def gpu_frame(n, deg, beta, cams, W, H, k=256, pix=None, wts=None, view_ids=None, render=True, ssim=False):
     L = lib()
     V = int(cams.shape[0]) if view_ids is None else len(view_ids)
     fr = L.Frame(n, deg, torch.tensor(np.asarray(beta, np.float32), device=DEV),
                  torch.tensor(np.asarray(cams, np.float32), device=DEV), W, H, V,
                  view_ids=None if view_ids is None else torch.tensor(np.asarray(view_ids, np.int32), device=DEV),
-                 k=k, sampled=pix is not None)
+                 k=k, sampled=pix is not None, ssim=ssim)
     L.lmrs_project(fr)
     L.lmrs_bin_tiles(fr)
     if pix is not None:
