@@ -67,6 +67,9 @@ class _Frame(C.Structure):
                 ("wc", C.c_void_p), ("image", C.c_void_p)]
 
 
+BLEND_BYTES_PER_PAIR = 44   # blend_k (2 x 16) + blend_m (2 x 4) + blend_run (4)
+
+
 def sched_ints(tiles: int) -> int:
     """int32 length of lmrs_frame.sched for `tiles` = V*T (LMRS_SCHED_INTS)."""
     return 2 * int(tiles) + 4
@@ -195,6 +198,11 @@ class Frame:
 
     def blend_built(self) -> bool:
         return bool(self.blend and int(self.tensors["blend_start"][self.n_views * self.T + 1].item()) == 1)
+
+    def set_blend_capacity(self, pairs: int):
+        """Reallocates the blend table for exactly `pairs` pairs (the table is then unbuilt)."""
+        if self.blend:
+            self._alloc_blend(pairs)
 
     def ensure_blend(self, needed: int | None = None, margin: float = 1.15) -> bool:
         """Grows the blend table to hold `needed` pairs (default: the last

@@ -22,6 +22,12 @@ iteration (weights 1), damping lambda.
   host. It is captured once per learning-rate branch into a HIP graph and
   replayed; the whole iteration budget of a fit is enqueued at admission, so
   the host only admits and retires;
+* each fit keeps a blend table (the linearization of its render, 44 bytes per
+  blending (pixel, Gaussian) pair; lmrs_frame), sized at admission from the
+  pair count of the target render with a 30 % margin and within what is left
+  of the HBM budget (at most TABLE_CAP_BYTES): an iteration whose pairs fit
+  takes its GN products from the table, one whose pairs do not walks the tile
+  lists (decided on the device, so graph replays need no host check);
 * a fit retires when its last iteration's event has completed: final PSNR
   over all views at full resolution, and its status: "ok", or "numeric" /
   "capacity" when any iteration flagged a numeric failure or an overflow of
@@ -31,7 +37,7 @@ iteration (weights 1), damping lambda.
 
 `run_sequential` is the plain baseline: the same requests one at a time in
 arrival order, eager lmrs_lm_step calls on one stream (which wait for each
-iteration's tile-list count), no graphs.
+iteration's tile-list count), no graphs, the same blend-table sizing.
 """
 from __future__ import annotations
 
@@ -44,6 +50,10 @@ import torch
 
 from . import lmrs as L
 from . import synth
+
+
+TABLE_CAP_BYTES = 48 << 30   # largest blend table of one fit
+TABLE_MARGIN = 1.3           # table pairs per pair of the target render
 
 
 @dataclass
@@ -161,7 +171,8 @@ def _image_index(fr: L.Frame, dev) -> torch.Tensor:
 class _Fit:
     """Device state of one resident fit."""
 
-    def __init__(self, prob: Problem, stream: torch.cuda.Stream, use_graphs: bool, dev, ws_op: int = L.OP_LM):
+    def __init__(self, prob: Problem, stream: torch.cuda.Stream, use_graphs: bool, dev, ws_op: int = L.OP_LM,
+                 table_bytes_max: int = TABLE_CAP_BYTES):
         req = prob.req
         self.prob, self.req, self.stream, self.use_graphs = prob, req, stream, use_graphs
         self.it = 0
@@ -171,7 +182,7 @@ class _Fit:
             self.cams = torch.tensor(prob.cams, device=dev)
             cap = int(prob.instances_bound * 1.05) + 1024
             self.fr = L.Frame(req.n, req.sh_degree, self.beta, self.cams, req.res, req.res, req.n_views, k=256,
-                              capacity=cap, blend=False)
+                              capacity=cap, blend=True)
             nbytes = max(L.workspace_bytes(L.OP_BIN, self.fr), L.workspace_bytes(ws_op, self.fr))
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
             self.rep = torch.zeros(L.REPORT_FLOATS, device=dev)
@@ -180,13 +191,18 @@ class _Fit:
             # targets: the ground truth rendered at every pixel
             self.targets = torch.empty((req.n_views, req.res, req.res, 3), dtype=torch.float32, device=dev)
             self._render_all(self.targets)
+            # the blend table, sized from the target render's pairs
+            want = int(self.fr.blend_pairs() * TABLE_MARGIN) + 4096
+            room = max(min(table_bytes_max, TABLE_CAP_BYTES), 0) // L.BLEND_BYTES_PER_PAIR
+            self.fr.set_blend_capacity(min(want, room))
+            self.table_bytes = self.fr.blend_capacity * L.BLEND_BYTES_PER_PAIR
             self.beta.copy_(torch.tensor(prob.beta_init, device=dev))
         self.done_event: torch.cuda.Event | None = None
 
     def _render_all(self, out: torch.Tensor):
         L.lmrs_project(self.fr, stream=self.stream)
         L.lmrs_bin_tiles(self.fr, stream=self.stream, ws=self.ws)
-        L.lmrs_render(self.fr, stream=self.stream)
+        L.lmrs_render(self.fr, stream=self.stream, grow_blend=False)
         out.view(-1, 3)[self.idx] = self.fr.color
 
     def params(self) -> L.LmParams:
@@ -247,6 +263,7 @@ class Server:
     _pending: list = field(default_factory=list)
     _results: dict = field(default_factory=dict)
     log: list = field(default_factory=list)
+    table_bytes: dict = field(default_factory=dict)   # blend-table bytes of each admitted fit
 
     def submit(self, req: FitRequest, problem: Problem | None = None) -> int:
         """Queue a request (host data prepared now, off the device). Returns its handle."""
@@ -276,8 +293,10 @@ class Server:
                    and used + pending[0].footprint <= self.hbm_budget_bytes):
                 prob = pending.pop(0)
                 si = free_streams.pop(0)
-                fit = _Fit(prob, streams[si], self.use_graphs, self.device)
-                used += prob.footprint
+                fit = _Fit(prob, streams[si], self.use_graphs, self.device,
+                           table_bytes_max=self.hbm_budget_bytes - used - prob.footprint)
+                used += prob.footprint + fit.table_bytes
+                self.table_bytes[prob.req.id] = fit.table_bytes
                 start = time.perf_counter() - t0
                 active.append((fit, si, start))
                 self.log.append(("admit", prob.req.id, start, used))
@@ -296,7 +315,7 @@ class Server:
                     end = time.perf_counter() - t0
                     req = fit.req
                     self._results[req.id] = FitResult(beta, psnr, end - req.arrival_t, fit.status(), start, end)
-                    used -= fit.prob.footprint
+                    used -= fit.prob.footprint + fit.table_bytes
                     free_streams.append(si)
                     self.log.append(("retire", req.id, end, used))
                     del fit
@@ -308,7 +327,8 @@ class Server:
         return self._results
 
 
-def run_sequential(problems: list[Problem], device: str = "cuda:0") -> dict[int, FitResult]:
+def run_sequential(problems: list[Problem], device: str = "cuda:0",
+                   hbm_budget_bytes: int = 200 << 30) -> dict[int, FitResult]:
     """Plain baseline: one request at a time in arrival order, eager
     lmrs_lm_step calls on the current stream, no graphs, no overlap."""
     out: dict[int, FitResult] = {}
@@ -322,9 +342,9 @@ def run_sequential(problems: list[Problem], device: str = "cuda:0") -> dict[int,
         if req.arrival_t > now:
             time.sleep(req.arrival_t - now)
         start = time.perf_counter() - t0
-        fit = _Fit(prob, stream, False, device, ws_op=L.OP_LM)
+        fit = _Fit(prob, stream, False, device, ws_op=L.OP_LM, table_bytes_max=hbm_budget_bytes - prob.footprint)
         for it in range(req.lm_iters):
-            L.lmrs_lm_step(fit.fr, fit.targets, L.lm_params(it, req.cg_iters, req.lam), report=fit.rep,
+            L.lmrs_lm_step(fit.fr, fit.targets, L.lm_params(it, req.cg_iters, req.lam), report=fit.rep, grow_blend=False,
                            ws=fit.ws, stream=stream)
             fit.fail.bitwise_or_(fit.rep[L.REP["status"]:L.REP["status"] + 1].to(torch.int32))
         beta, psnr = fit.finalize()

@@ -54,7 +54,10 @@ def test_graph_replays_match_eager_steps():
         worst = max(worst, e)
         assert e < 1e-4, (it, e)
     assert set(graph.graphs) == {True, False}
-    log(f"  14 LM iterations, graph vs eager step: worst rel {worst:.2e}")
+    # the GN products of both ran over the blend table sized at admission
+    assert eager.fr.blend_built() and graph.fr.blend_built()
+    log(f"  14 LM iterations, graph vs eager step: worst rel {worst:.2e}; blend table "
+        f"{graph.fr.blend_pairs()} of {graph.fr.blend_capacity} pairs")
 
 
 def test_same_alone_and_in_the_mix():
@@ -140,5 +143,6 @@ def test_admission_respects_budget_and_slots():
         else:
             resident.discard(rid)
         assert len(resident) <= 3
-        assert sum(fp[i] for i in resident) <= budget
-        assert u == sum(fp[i] for i in resident)
+        held = sum(fp[i] + srv.table_bytes[i] for i in resident)   # footprints and blend tables
+        assert held <= budget
+        assert u == held
