@@ -187,21 +187,33 @@ __device__ __forceinline__ void load_params(const float* beta, int n, int g, T* 
 //   f22 = 1 / sqrt(c),  f11 = c r,  f12 = -b r,  r = 1 / sqrt(c det),
 // with det = a c - b^2 formed without cancellation by the Cauchy-Binet
 // identity det = |k1 x k2|^2 + lowpass (|k1|^2 + |k2|^2) + lowpass^2.
+// The covariance factor M = R diag(s) of Sigma = M M^T (eq. 2), from the
+// quaternion (normalised here) and the log-scales; it does not depend on the
+// view.
 template <class T>
-__device__ __forceinline__ void proj_geom(const T* prm, const CamView& cv, float lowpass, T* rec,
-                                          double* a_out, double* b_out, double* c_out) {
-  const lmrs_camera& c = cv.c;
-  const T mx = prm[0], my = prm[1], mz = prm[2];
-  const T tx = T(c.R[0]) * mx + T(c.R[1]) * my + T(c.R[2]) * mz + T(c.t[0]);
-  const T ty = T(c.R[3]) * mx + T(c.R[4]) * my + T(c.R[5]) * mz + T(c.t[1]);
-  const T tz = T(c.R[6]) * mx + T(c.R[7]) * my + T(c.R[8]) * mz + T(c.t[2]);
-  const T iz = T(1.f) / tz;
+__device__ __forceinline__ void cov_factor(const T* prm, T* M) {
   const T inv = trsqrt(prm[6] * prm[6] + prm[7] * prm[7] + prm[8] * prm[8] + prm[9] * prm[9]);
   const T w = prm[6] * inv, x = prm[7] * inv, y = prm[8] * inv, z = prm[9] * inv;
   const T R[9] = {T(1.f) - T(2.f) * (y * y + z * z), T(2.f) * (x * y - w * z), T(2.f) * (x * z + w * y),
                   T(2.f) * (x * y + w * z), T(1.f) - T(2.f) * (x * x + z * z), T(2.f) * (y * z - w * x),
                   T(2.f) * (x * z - w * y), T(2.f) * (y * z + w * x), T(1.f) - T(2.f) * (x * x + y * y)};
   const T s[3] = {texp(prm[3]), texp(prm[4]), texp(prm[5])};
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[3 * l + j] = R[3 * l + j] * s[j];
+}
+
+// proj_geom with the covariance factor M given (cov_factor).
+template <class T>
+__device__ __forceinline__ void proj_geom_m(const T* prm, const T* M, const CamView& cv, float lowpass, T* rec,
+                                            double* a_out, double* b_out, double* c_out) {
+  const lmrs_camera& c = cv.c;
+  const T mx = prm[0], my = prm[1], mz = prm[2];
+  const T tx = T(c.R[0]) * mx + T(c.R[1]) * my + T(c.R[2]) * mz + T(c.t[0]);
+  const T ty = T(c.R[3]) * mx + T(c.R[4]) * my + T(c.R[5]) * mz + T(c.t[1]);
+  const T tz = T(c.R[6]) * mx + T(c.R[7]) * my + T(c.R[8]) * mz + T(c.t[2]);
+  const T iz = T(1.f) / tz;
   const T J00 = T(c.fx) * iz, J02 = -(T(c.fx) * tx * iz * iz);
   const T J11 = T(c.fy) * iz, J12 = -(T(c.fy) * ty * iz * iz);
   T Tm[6];
@@ -215,7 +227,7 @@ __device__ __forceinline__ void proj_geom(const T* prm, const CamView& cv, float
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      K[3 * i + j] = (Tm[3 * i + 0] * R[j] + Tm[3 * i + 1] * R[3 + j] + Tm[3 * i + 2] * R[6 + j]) * s[j];
+      K[3 * i + j] = Tm[3 * i + 0] * M[j] + Tm[3 * i + 1] * M[3 + j] + Tm[3 * i + 2] * M[6 + j];
   const T n1 = K[0] * K[0] + K[1] * K[1] + K[2] * K[2];
   const T n2 = K[3] * K[3] + K[4] * K[4] + K[5] * K[5];
   const T b = K[0] * K[3] + K[1] * K[4] + K[2] * K[5];
@@ -229,6 +241,14 @@ __device__ __forceinline__ void proj_geom(const T* prm, const CamView& cv, float
   rec[3] = -(b * r);
   rec[4] = trsqrt(cc);
   if (a_out) { *a_out = tval(n1 + T(lowpass)); *b_out = tval(b); *c_out = tval(cc); }
+}
+
+template <class T>
+__device__ __forceinline__ void proj_geom(const T* prm, const CamView& cv, float lowpass, T* rec,
+                                          double* a_out, double* b_out, double* c_out) {
+  T M[9];
+  cov_factor(prm, M);
+  proj_geom_m(prm, M, cv, lowpass, rec, a_out, b_out, c_out);
 }
 
 // Unit direction from the camera centre to the mean.
@@ -290,10 +310,55 @@ __device__ __forceinline__ void color_mean_jacobian(const float* prm, const CamV
   }
 }
 
-// Adjoint of proj_core: gp[j] += sum_q grec[q] d rec_q / d prm_j.
+// Adjoint of proj_core, split so that what does not depend on the view is
+// done once per Gaussian: GeoFactors holds the rotation, scales and
+// M = R diag(s) of the 3-D covariance factor; proj_vjp_view adds one view's
+// mean and SH-coefficient gradients to gp and its gradients of R, s and the
+// opacity to an accumulator (linear in them), and proj_vjp_finish takes the
+// accumulated ones back to the quaternion, log-scales and opacity logit.
+struct GeoFactors {
+  float w, x, y, z, inv;  // normalised quaternion and 1 / |q|
+  float R[9], s[3], M[9];
+};
+
+struct GeoGrad {
+  float gR[9], gs[3], go;
+};
+
+__device__ __forceinline__ GeoFactors geo_factors(const float* prm) {
+  GeoFactors f;
+  f.inv = 1.f / sqrtf(prm[6] * prm[6] + prm[7] * prm[7] + prm[8] * prm[8] + prm[9] * prm[9]);
+  const float w = prm[6] * f.inv, x = prm[7] * f.inv, y = prm[8] * f.inv, z = prm[9] * f.inv;
+  f.w = w;
+  f.x = x;
+  f.y = y;
+  f.z = z;
+  const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+                      2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+                      2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
+#pragma unroll
+  for (int q = 0; q < 9; ++q) f.R[q] = R[q];
+  f.s[0] = expf(prm[3]);
+  f.s[1] = expf(prm[4]);
+  f.s[2] = expf(prm[5]);
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) f.M[3 * l + j] = f.R[3 * l + j] * f.s[j];
+  return f;
+}
+
+__device__ __forceinline__ void geo_grad_zero(GeoGrad& a) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) a.gR[q] = 0.f;
+  a.gs[0] = a.gs[1] = a.gs[2] = 0.f;
+  a.go = 0.f;
+}
+
+// One view's share of gp[j] += sum_q grec[q] d rec_q / d prm_j.
 template <int DEG>
-__device__ __forceinline__ void proj_vjp(const float* prm, const CamView& cv, float lowpass, const float* gr,
-                                         float* gp) {
+__device__ __forceinline__ void proj_vjp_view(const float* prm, const GeoFactors& gf, const CamView& cv,
+                                              float lowpass, const float* gr, float* gp, GeoGrad& acc) {
   constexpr int K2 = ShDims<DEG>::K;
   const lmrs_camera& c = cv.c;
   const float mx = prm[0], my = prm[1], mz = prm[2];
@@ -301,12 +366,7 @@ __device__ __forceinline__ void proj_vjp(const float* prm, const CamView& cv, fl
   const float ty = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
   const float tz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
   const float iz = 1.f / tz, iz2 = iz * iz, iz3 = iz2 * iz;
-  const float inv = 1.f / sqrtf(prm[6] * prm[6] + prm[7] * prm[7] + prm[8] * prm[8] + prm[9] * prm[9]);
-  const float w = prm[6] * inv, x = prm[7] * inv, y = prm[8] * inv, z = prm[9] * inv;
-  const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
-                      2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
-                      2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
-  const float s[3] = {expf(prm[3]), expf(prm[4]), expf(prm[5])};
+  const float* M = gf.M;
   const float J00 = c.fx * iz, J02 = -c.fx * tx * iz2, J11 = c.fy * iz, J12 = -c.fy * ty * iz2;
   float Tm[6];
 #pragma unroll
@@ -314,11 +374,6 @@ __device__ __forceinline__ void proj_vjp(const float* prm, const CamView& cv, fl
     Tm[j] = J00 * c.R[j] + J02 * c.R[6 + j];
     Tm[3 + j] = J11 * c.R[3 + j] + J12 * c.R[6 + j];
   }
-  float M[9];
-#pragma unroll
-  for (int l = 0; l < 3; ++l)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) M[3 * l + j] = R[3 * l + j] * s[j];
   float K[6];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -332,7 +387,7 @@ __device__ __forceinline__ void proj_vjp(const float* prm, const CamView& cv, fl
   const float det = (cw[0] * cw[0] + cw[1] * cw[1] + cw[2] * cw[2]) + lowpass * (n1 + n2) + lowpass * lowpass;
   const float cc = n2 + lowpass;
   const float r = 1.f / sqrtf(cc * det), ic = 1.f / cc;
-  const float gu = gr[0], gv = gr[1], g11 = gr[2], g12 = gr[3], g22 = gr[4], go = gr[5];
+  const float gu = gr[0], gv = gr[1], g11 = gr[2], g12 = gr[3], g22 = gr[4];
   // F: f11 = c r, f12 = -b r, f22 = c^-1/2 with r = (c det)^-1/2
   const float g_r = g11 * cc - g12 * b;
   const float gc = g11 * r - 0.5f * g_r * r * ic - 0.5f * g22 * ic * sqrtf(ic);
@@ -355,17 +410,14 @@ __device__ __forceinline__ void proj_vjp(const float* prm, const CamView& cv, fl
 #pragma unroll
     for (int l = 0; l < 3; ++l)
       gTm[3 * i + l] = gK[3 * i] * M[3 * l] + gK[3 * i + 1] * M[3 * l + 1] + gK[3 * i + 2] * M[3 * l + 2];
-  float gR[9], gs[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int l = 0; l < 3; ++l)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const float gM = Tm[l] * gK[j] + Tm[3 + l] * gK[3 + j];
-      gR[3 * l + j] = gM * s[j];
-      gs[j] += gM * R[3 * l + j];
+      acc.gR[3 * l + j] += gM * gf.s[j];
+      acc.gs[j] += gM * gf.R[3 * l + j];
     }
-#pragma unroll
-  for (int j = 0; j < 3; ++j) gp[3 + j] += gs[j] * s[j];
   // Tm = J W
   float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
 #pragma unroll
@@ -382,22 +434,7 @@ __device__ __forceinline__ void proj_vjp(const float* prm, const CamView& cv, fl
   float gm[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) gm[i] = c.R[i] * gtx + c.R[3 + i] * gty + c.R[6 + i] * gtz;
-  // rotation of the normalised quaternion
-  const float gw = 2.f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
-  const float gx = 2.f * (y * gR[1] + z * gR[2] + y * gR[3] - 2.f * x * gR[4] - w * gR[5] + z * gR[6] +
-                          w * gR[7] - 2.f * x * gR[8]);
-  const float gy = 2.f * (-2.f * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
-                          z * gR[7] - 2.f * y * gR[8]);
-  const float gz = 2.f * (-2.f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.f * z * gR[4] +
-                          y * gR[5] + x * gR[6] + y * gR[7]);
-  const float dq = w * gw + x * gx + y * gy + z * gz;
-  gp[6] += (gw - w * dq) * inv;
-  gp[7] += (gx - x * dq) * inv;
-  gp[8] += (gy - y * dq) * inv;
-  gp[9] += (gz - z * dq) * inv;
-  // opacity
-  const float op = 1.f / (1.f + expf(-prm[10]));
-  gp[10] += go * op * (1.f - op);
+  acc.go += gr[5];
   // colour: d/d f_kc = Y_k(dir); d/d mean through the direction
   float d[3];
   view_dir(prm, cv, d);
@@ -416,6 +453,30 @@ __device__ __forceinline__ void proj_vjp(const float* prm, const CamView& cv, fl
   gp[0] += gm[0];
   gp[1] += gm[1];
   gp[2] += gm[2];
+}
+
+// The accumulated gradients of R, s and the opacity back to the quaternion
+// (through its normalisation), the log-scales and the opacity logit.
+__device__ __forceinline__ void proj_vjp_finish(const float* prm, const GeoFactors& gf, const GeoGrad& a,
+                                                float* gp) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) gp[3 + j] += a.gs[j] * gf.s[j];
+  const float w = gf.w, x = gf.x, y = gf.y, z = gf.z;
+  const float* gR = a.gR;
+  const float gw = 2.f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+  const float gx = 2.f * (y * gR[1] + z * gR[2] + y * gR[3] - 2.f * x * gR[4] - w * gR[5] + z * gR[6] +
+                          w * gR[7] - 2.f * x * gR[8]);
+  const float gy = 2.f * (-2.f * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
+                          z * gR[7] - 2.f * y * gR[8]);
+  const float gz = 2.f * (-2.f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.f * z * gR[4] +
+                          y * gR[5] + x * gR[6] + y * gR[7]);
+  const float dq = w * gw + x * gx + y * gy + z * gz;
+  gp[6] += (gw - w * dq) * gf.inv;
+  gp[7] += (gx - x * dq) * gf.inv;
+  gp[8] += (gy - y * dq) * gf.inv;
+  gp[9] += (gz - z * dq) * gf.inv;
+  const float op = 1.f / (1.f + expf(-prm[10]));
+  gp[10] += a.go * op * (1.f - op);
 }
 
 // --------------------------------------------------- per-pixel opacity test

@@ -89,17 +89,26 @@ __global__ __launch_bounds__(kBlock) void tangent_kernel(const float* __restrict
   dualf prm[PG];
 #pragma unroll
   for (int j = 0; j < PG; ++j) prm[j] = dualf(beta[(size_t)j * n + g], p[(size_t)j * n + g]);
+  // the view-independent parts: covariance factor and opacity
+  dualf M[9];
+  cov_factor(prm, M);
+  const dualf op = dualf(1.f) / (dualf(1.f) + texp(-prm[10]));
+  // the next view's rectangle is loaded while this view's tangent is formed
+  int4 rc_next = V > 0 ? rect[g] : make_int4(0, 0, 0, 0);
   for (int v = 0; v < V; ++v) {
     const size_t vg = (size_t)v * n + g;
     float4* out = reinterpret_cast<float4*>(tan + vg * LMRS_REC);
-    const int4 rc = rect[vg];
+    const int4 rc = rc_next;
+    if (v + 1 < V) rc_next = rect[vg + n];
     if (rc.x >= rc.z) {
       out[0] = out[1] = out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
       continue;
     }
     const CamView cv = load_cam(cams, view_ids, v);
     dualf r[9];
-    proj_core<DEG>(prm, cv, lowpass, r, nullptr, nullptr, nullptr);
+    proj_geom_m(prm, M, cv, lowpass, r, nullptr, nullptr, nullptr);
+    r[5] = op;
+    proj_color<DEG>(prm, cv, r + 6);
     out[0] = make_float4(r[0].d, r[1].d, r[2].d, r[3].d);
     out[1] = make_float4(r[4].d, r[5].d, r[6].d, r[7].d);
     out[2] = make_float4(r[8].d, 0.f, 0.f, 0.f);
@@ -125,14 +134,32 @@ __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
     load_params<PG>(beta, n, g, prm);
 #pragma unroll
     for (int j = 0; j < PG; ++j) gp[j] = 0.f;
+    const GeoFactors gf = geo_factors(prm);
+    GeoGrad acc;
+    geo_grad_zero(acc);
+    // the next view's row is loaded while this view's row is taken back
+    float4 a_next{}, b_next{};
+    float c_next = 0.f;
+    if (V > 0) {
+      const float* row0 = grad2d + (size_t)g * kGradRow;
+      a_next = reinterpret_cast<const float4*>(row0)[0];
+      b_next = reinterpret_cast<const float4*>(row0)[1];
+      c_next = row0[8];
+    }
     for (int v = 0; v < V; ++v) {
       float gr[9];
       bool any = false;
       float* row = grad2d + ((size_t)v * n + g) * kGradRow;
-      const float4 a = reinterpret_cast<const float4*>(row)[0], b = reinterpret_cast<const float4*>(row)[1];
+      const float4 a = a_next, b = b_next;
       gr[0] = a.x; gr[1] = a.y; gr[2] = a.z; gr[3] = a.w;
       gr[4] = b.x; gr[5] = b.y; gr[6] = b.z; gr[7] = b.w;
-      gr[8] = row[8];
+      gr[8] = c_next;
+      if (v + 1 < V) {
+        const float* nrow = row + (size_t)n * kGradRow;
+        a_next = reinterpret_cast<const float4*>(nrow)[0];
+        b_next = reinterpret_cast<const float4*>(nrow)[1];
+        c_next = nrow[8];
+      }
 #pragma unroll
       for (int q = 0; q < 9; ++q) any |= gr[q] != 0.f;
       if (!any) continue;
@@ -141,8 +168,9 @@ __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
         row[8] = 0.f;
       }
       const CamView cv = load_cam(cams, view_ids, v);
-      proj_vjp<DEG>(prm, cv, lowpass, gr, gp);
+      proj_vjp_view<DEG>(prm, gf, cv, lowpass, gr, gp, acc);
     }
+    proj_vjp_finish(prm, gf, acc, gp);
 #pragma unroll
     for (int j = 0; j < PG; ++j) {
       const size_t idx = (size_t)j * n + g;
