@@ -202,6 +202,32 @@ def copy_calibration(torch, dev, mib=1024, reps=3):
     del a, b
 
 
+def _working(rows):
+    """Counter values of the dispatches that did the splat's work: each splat
+    kernel is launched for every GN product and returns at once when the other
+    path is selected, so dispatches shorter than a quarter of the longest one
+    are left out. rows: (value, duration) pairs."""
+    if not rows:
+        return []
+    longest = max(d for _, d in rows)
+    return [v for v, d in rows if d >= 0.25 * longest]
+
+
+def _counter_rows(d: str):
+    """{(kernel name, counter): [(value, duration ns)]} from a --pmc output folder."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    out: dict = {}
+    for f in files:
+        for row in csv.DictReader(open(f)):
+            dur = float(row.get("End_Timestamp") or 0) - float(row.get("Start_Timestamp") or 0)
+            out.setdefault((row["Kernel_Name"], row["Counter_Name"]), []).append((float(row["Counter_Value"]), dur))
+    return out
+
+
 def summarize_traffic(fetch_dir: str, write_dir: str, copy_mib: int, command: str, copy_reps: int = 3) -> str:
     """Per-launch HBM bytes of the GN product's splat kernels (over the blend
     table and the fused list walk, each where the run launched it) from two
@@ -209,38 +235,25 @@ def summarize_traffic(fetch_dir: str, write_dir: str, copy_mib: int, command: st
     scaled by the ratio of the known copy size to what the same counter reads
     for the plain copy kernel of the same run. Writes one summary file per
     kernel found and returns their text."""
-    import csv
-    import glob
-
-    def per_kernel(d, counter):
-        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-        if not files:
-            raise SystemExit(f"no counter_collection.csv under {d}")
-        vals = {}
-        for f in files:
-            for row in csv.DictReader(open(f)):
-                if row.get("Counter_Name") != counter:
-                    continue
-                vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
-        return vals
-
-    runs = {c: per_kernel(d, c) for c, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir))}
+    runs = {c: _counter_rows(d) for c, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir))}
     copy = {}
-    for counter, vals in runs.items():
+    for counter, rows in runs.items():
         # the calibration copies are the largest dispatches of the runtime's
         # device-to-device copy kernel in the run (reps of the same size)
-        c = sorted(x for k, v in vals.items() if "copyBuffer" in k for x in v)[-copy_reps:]
+        c = sorted(v for (k, cn), xs in rows.items() if cn == counter and "copyBuffer" in k
+                   for v, _ in xs)[-copy_reps:]
         if not c:
-            raise SystemExit(f"{counter}: no copy kernel; kernels found: {sorted(vals)[:20]}")
+            raise SystemExit(f"{counter}: no copy kernel; kernels found: {sorted({k for k, _ in rows})[:20]}")
         copy[counter] = float(np.median(c))
     kernel_hash = hashlib.sha256(open(SPLAT_SOURCE, "rb").read()).hexdigest()
     texts = []
     for which, (match, title, path, _) in SPLAT_KERNELS.items():
-        out = {}
-        for counter, vals in runs.items():
-            xs = [x for k, v in vals.items() if match in k for x in v]
+        out, used = {}, 0
+        for counter, rows in runs.items():
+            xs = _working([r for (k, cn), v in rows.items() if cn == counter and match in k for r in v])
             if xs:
                 out[counter] = (float(np.median(xs)), copy[counter], copy_mib * 1024.0 / copy[counter])
+                used = len(xs)
         if len(out) < 2:
             continue
         fetch = out["FETCH_SIZE"][0] * out["FETCH_SIZE"][2] * 1024
@@ -249,7 +262,8 @@ def summarize_traffic(fetch_dir: str, write_dir: str, copy_mib: int, command: st
                 f"# 100k-Gaussian object-scale workload (8 views 800x800, 26 samples/tile).\n"
                 f"# Commands (one counter per run, from the repository root):\n"
                 f"#   {command}\n"
-                f"# Counter values are KiB per dispatch (median over the launches of the run);\n"
+                f"# Counter values are KiB per dispatch (median over the {used} launches of the run that did\n"
+                f"# the work; launches that found the other splat path selected return at once);\n"
                 f"# each is scaled by (known copy size / the same counter for a {copy_mib} MiB device copy).\n"
                 f"fetch_kib_splat: {out['FETCH_SIZE'][0]:.1f}\n"
                 f"fetch_kib_copy_{copy_mib}MiB: {out['FETCH_SIZE'][1]:.1f}\n"
@@ -325,7 +339,7 @@ def serving_leg(args, n_requests: int | None = None) -> dict:
     serving.run_sequential([serving.make_problem(serving.FitRequest(seed=999, n=2000, sh_degree=3, n_views=4,
                                                                     res=256, lm_iters=2))])
     log("[serve] sequential plain solves")
-    seq = serving.run_sequential(probs)
+    seq = serving.run_sequential(probs, hbm_budget_bytes=budget)
     s_seq = serving.summarize(seq, probs)
     log(f"[serve] sequential: {s_seq}")
     log(f"[serve] continuous batching, {args.slots} slots, budget {args.hbm_budget_gb} GiB")
@@ -374,20 +388,21 @@ def summarize_counters(dirs: list[str], command: str) -> str:
     """Median per dispatch of every counter found in rocprofv3 --pmc output
     folders, for each of the GN product's splat kernels the run launched;
     writes one summary file per kernel."""
-    import csv
-    import glob
+    rows_all = [_counter_rows(d) for d in dirs if os.path.isdir(d)]
     texts = []
     for which, (match, title, _, path) in SPLAT_KERNELS.items():
         vals: dict[str, list[float]] = {}
-        for d in dirs:
-            for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-                for row in csv.DictReader(open(f)):
-                    if match in row["Kernel_Name"]:
-                        vals.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+        for rows in rows_all:
+            for (k, cn), v in rows.items():
+                if match in k:
+                    vals.setdefault(cn, []).extend(v)
+        vals = {cn: _working(v) for cn, v in vals.items()}
         if not vals:
             continue
         lines = [f"# rocprofv3 counters of {title},",
-                 "# 100k-Gaussian object-scale workload (8 views 800x800, 26 samples/tile); median per dispatch.",
+                 "# 100k-Gaussian object-scale workload (8 views 800x800, 26 samples/tile); median per dispatch",
+                 "# over the launches that did the work (those that found the other splat path selected",
+                 "# return at once and are left out).",
                  "# Commands (one --pmc pass per counter group, from the repository root):",
                  f"#   {command}"]
         for k in sorted(vals):
