@@ -343,7 +343,7 @@ def serving_leg(args, n_requests: int | None = None) -> dict:
     s_seq = serving.summarize(seq, probs)
     log(f"[serve] sequential: {s_seq}")
     log(f"[serve] continuous batching, {args.slots} slots, budget {args.hbm_budget_gb} GiB")
-    srv = serving.Server(budget, max_slots=args.slots, use_graphs=not args.no_graphs)
+    srv = serving.Server(budget, max_slots=args.slots, use_graphs=not args.no_graphs, policy=args.policy)
     for p in probs:
         srv.submit(p.req, p)
     got = srv.run_until_idle()
@@ -357,6 +357,7 @@ def serving_leg(args, n_requests: int | None = None) -> dict:
                     f"Gaussians log-uniform 2k-200k, SH 0-3, 4-32 views of 256/512/800 px, every pixel)",
         "requests": len(reqs), "lm_iters": reqs[0].lm_iters, "cg_iters": reqs[0].cg_iters, "lambda": reqs[0].lam,
         "slots": args.slots, "hbm_budget_gib": args.hbm_budget_gb, "graphs": not args.no_graphs,
+        "policy": args.policy,
         "fits_per_s": round(s_srv["fits_per_s"], 4), "p50_latency_s": round(s_srv["p50_latency_s"], 3),
         "p99_latency_s": round(s_srv["p99_latency_s"], 3),
         "sequential": {k: round(v, 4) if isinstance(v, float) else v for k, v in s_seq.items()},
@@ -657,6 +658,7 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--lm-iters", type=int, default=0, help="override the requests' LM iterations")
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--policy", choices=["fifo", "sjf"], default="fifo", help="serving admission order")
     args = ap.parse_args()
     if args.serving:
         return serving_main(args)

@@ -36,3 +36,31 @@ def test_footprint_grows_with_request_size():
     assert small < more_views and small < more_sh and small < more_lists
     # targets alone: 4 views of 256^2 RGB floats
     assert small > 4 * 256 * 256 * 12
+
+
+def test_admission_order():
+    """Shortest estimated work first among the requests that have arrived and
+    fit the budget ("sjf"); arrival order without overtaking ("fifo")."""
+    serving = _serving()
+
+    def prob(i, n, views, res, t, fp):
+        req = serving.FitRequest(seed=i, n=n, sh_degree=0, n_views=views, res=res, arrival_t=t, id=i)
+        return serving.Problem(req, None, None, None, 0, fp)
+
+    big = prob(0, 100_000, 24, 800, 0.0, 10)
+    small = prob(1, 2_000, 4, 256, 0.1, 10)
+    mid = prob(2, 20_000, 8, 512, 0.2, 10)
+    late = prob(3, 1_000, 2, 128, 5.0, 10)
+    huge_fp = prob(4, 1_500, 2, 128, 0.0, 10 ** 9)
+    pending = [big, huge_fp, small, mid, late]
+    sjf = serving.Server(hbm_budget_bytes=100, policy="sjf")
+    assert serving.work_estimate(small.req) < serving.work_estimate(mid.req) < serving.work_estimate(big.req)
+    # at t = 1: late has not arrived and huge_fp does not fit, so the least work is small
+    assert sjf._pick(pending, 1.0, 0) == 2
+    assert sjf._pick(pending, 0.15, 0) == 2
+    assert sjf._pick(pending, 0.05, 0) == 0        # only big has arrived (and fits)
+    assert sjf._pick(pending, 6.0, 0) == 4          # late (the least work) has arrived
+    assert sjf._pick(pending, 6.0, 95) is None     # nothing fits next to 95 of 100
+    fifo = serving.Server(hbm_budget_bytes=100, policy="fifo")
+    assert fifo._pick(pending, 1.0, 0) == 0
+    assert fifo._pick(pending[1:], 1.0, 0) is None  # the head does not fit: no overtaking
