@@ -1203,7 +1203,7 @@ __global__ void blend_built_kernel(int64_t* __restrict__ start, int64_t m, int64
 // The opacity, exponent and their record derivatives are recomputed from the
 // screen record and the pixel centre (pair_alpha, the render's own
 // arithmetic), so a pair costs 20 bytes of table.
-constexpr int kBlendGnThreads = 256;
+constexpr int kBlendGnThreads = 512;
 constexpr int kBlendGnWaves = kBlendGnThreads / kWave;
 
 // Inclusive sums over each segment of consecutive lanes (dist = lane minus
