@@ -437,29 +437,48 @@ __global__ __launch_bounds__(kWave* W) void render_kernel(const float* __restric
 // (the table is stale until the reverse walk rebuilds it). One workgroup;
 // each thread scans a contiguous block of tiles.
 constexpr int kBlendScanThreads = 1024;
+constexpr int kBlendScanPer = 8;  // consecutive counts per thread and round
+// One workgroup: exclusive scan of the tiles' pair counts in place, in
+// rounds of kBlendScanThreads * kBlendScanPer counts (each thread reads its
+// counts as one coalesced block), with a running carry between rounds;
+// start[m] = total pairs, start[m + 1] = 0 (the table is not built yet).
 __global__ __launch_bounds__(kBlendScanThreads) void blend_scan_kernel(int64_t* __restrict__ start, int64_t m) {
-  __shared__ int64_t s_part[kBlendScanThreads];
-  const int tid = threadIdx.x;
-  const int64_t per = (m + kBlendScanThreads - 1) / kBlendScanThreads;
-  const int64_t a = min(m, tid * per), b = min(m, a + per);
-  int64_t acc = 0;
-  for (int64_t i = a; i < b; ++i) acc += start[i];
-  s_part[tid] = acc;
+  __shared__ int64_t s_wave[kBlendScanThreads / kWave];
+  __shared__ int64_t s_carry;
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+  if (tid == 0) s_carry = 0;
   __syncthreads();
-  for (int d = 1; d < kBlendScanThreads; d <<= 1) {
-    const int64_t y = tid >= d ? s_part[tid - d] : 0;
+  for (int64_t base = 0; base < m; base += (int64_t)kBlendScanThreads * kBlendScanPer) {
+    const int64_t a = base + (int64_t)tid * kBlendScanPer;
+    int64_t x[kBlendScanPer];
+    int64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < kBlendScanPer; ++q) {
+      x[q] = a + q < m ? start[a + q] : 0;
+      acc += x[q];
+    }
+    int64_t y = acc;  // inclusive scan over the wave
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int64_t z = __shfl_up(y, d, kWave);
+      if (lane >= d) y += z;
+    }
+    if (lane == kWave - 1) s_wave[wv] = y;
     __syncthreads();
-    s_part[tid] += y;
+    int64_t before = s_carry;
+    for (int w = 0; w < wv; ++w) before += s_wave[w];
+    int64_t run = before + (y - acc);
+#pragma unroll
+    for (int q = 0; q < kBlendScanPer; ++q) {
+      if (a + q < m) start[a + q] = run;
+      run += x[q];
+    }
+    __syncthreads();  // s_wave and s_carry have been read
+    if (tid == kBlendScanThreads - 1) s_carry = before + y;
     __syncthreads();
   }
-  int64_t run = s_part[tid] - acc;
-  for (int64_t i = a; i < b; ++i) {
-    const int64_t x = start[i];
-    start[i] = run;
-    run += x;
-  }
-  if (tid == kBlendScanThreads - 1) {
-    start[m] = s_part[tid];
+  if (tid == 0) {
+    start[m] = s_carry;
     start[m + 1] = 0;
   }
 }
