@@ -55,7 +55,7 @@ def _rng(seed: int, stream: int) -> np.random.Generator:
 def make_scene(n: int, sh_degree: int, seed: int, means: str = "cube", extent: float = 1.0,
                log_scale_mu: float = -3.0, log_scale_sd: float = 0.3,
                sh_rest_sd: float = 0.1) -> np.ndarray:
-    """Ground-truth scene with the priors of the spec workloads.
+    """Ground-truth scene with the priors shared by the synthetic workloads.
 
     means: 'cube' = uniform in [-extent, extent]^3; 'ball' = uniform in the ball of
     radius extent; 'logradius' = radius exp(U[ln 0.05, ln 10]) times a uniform
@@ -187,7 +187,7 @@ def config0(seed: int = 0) -> Workload:
     """1,000 Gaussians in [-1,1]^3, SH degree 0, 4 views 64x64, all pixels."""
     n, d = 1000, 0
     gt = make_scene(n, d, seed, means="cube")
-    return Workload("cfg0-1k-sh0-4x64", n, d, 64, 64,
+    return Workload("lm-run-1k-sh0-4x64", n, d, 64, 64,
                     sphere_cameras(4, 3.0, 64, 64, 60.0, seed), gt,
                     perturb_init(gt, n, d, seed), 4, 1.0, 10, 20, 1e-3, seed)
 
@@ -197,7 +197,7 @@ def config1(seed: int = 0, n: int = 100_000) -> Workload:
     10 % of pixels per LM step, 8 CG steps."""
     d = 3
     gt = make_scene(n, d, seed, means="ball")
-    return Workload("cfg1-100k-sh3-8of64x800", n, d, 800, 800,
+    return Workload("object-100k-sh3-8of64x800", n, d, 800, 800,
                     sphere_cameras(64, 4.0, 800, 800, 60.0, seed), gt,
                     perturb_init(gt, n, d, seed), 8, 0.10, 8, 20, 0.1, seed)
 
@@ -207,7 +207,7 @@ def config2(seed: int = 0, n: int = 1_500_000) -> Workload:
     and 5 % residual-weighted pixels per LM step, 10 CG steps."""
     d = 3
     gt = make_scene(n, d, seed, means="logradius")
-    return Workload("cfg2-1.5M-sh3-16of150x1264x832", n, d, 1264, 832,
+    return Workload("unbounded-1.5M-sh3-16of150x1264x832", n, d, 1264, 832,
                     ellipse_cameras(150, 1264, 832, 70.0, seed), gt,
                     perturb_init(gt, n, d, seed), 16, 0.05, 10, 20, 0.1, seed)
 
@@ -216,7 +216,7 @@ def config3(seed: int = 0, n: int = 200_000) -> Workload:
     """Differentiation check: 200k Gaussians, SH degree 3, 16 views 512x512."""
     d = 3
     gt = make_scene(n, d, seed, means="ball")
-    return Workload("cfg3-200k-sh3-16x512", n, d, 512, 512,
+    return Workload("autograd-200k-sh3-16x512", n, d, 512, 512,
                     sphere_cameras(16, 4.0, 512, 512, 60.0, seed), gt,
                     perturb_init(gt, n, d, seed), 16, 1.0, 8, 1, 0.1, seed)
 
