@@ -329,8 +329,9 @@ def serving_leg(args, n_requests: int | None = None) -> dict:
     count = n_requests or args.requests
     stream = synth.request_stream(256, args.rate, seed=0)[:count]
     reqs = [serving.FitRequest.from_stream(d) for d in stream]
-    if args.lm_iters:
-        for r in reqs:
+    for r in reqs:
+        r.deterministic = bool(args.deterministic)
+        if args.lm_iters:
             r.lm_iters = args.lm_iters
     log(f"[serve] preparing {len(reqs)} requests on the host")
     probs = [serving.make_problem(r) for r in reqs]
@@ -357,7 +358,7 @@ def serving_leg(args, n_requests: int | None = None) -> dict:
                     f"Gaussians log-uniform 2k-200k, SH 0-3, 4-32 views of 256/512/800 px, every pixel)",
         "requests": len(reqs), "lm_iters": reqs[0].lm_iters, "cg_iters": reqs[0].cg_iters, "lambda": reqs[0].lam,
         "slots": args.slots, "hbm_budget_gib": args.hbm_budget_gb, "graphs": not args.no_graphs,
-        "policy": args.policy,
+        "policy": args.policy, "deterministic": bool(args.deterministic),
         "fits_per_s": round(s_srv["fits_per_s"], 4), "p50_latency_s": round(s_srv["p50_latency_s"], 3),
         "p99_latency_s": round(s_srv["p99_latency_s"], 3),
         "sequential": {k: round(v, 4) if isinstance(v, float) else v for k, v in s_seq.items()},
@@ -441,7 +442,8 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
     V, k = w.views_per_step, w.samples_per_tile
     beta = torch.tensor(w.beta_init, device=dev)
     view_ids = torch.zeros(V, dtype=torch.int32, device=dev)
-    fr = L.Frame(w.n, w.sh_degree, beta, cams, w.width, w.height, V, view_ids=view_ids, k=k, sampled=True)
+    fr = L.Frame(w.n, w.sh_degree, beta, cams, w.width, w.height, V, view_ids=view_ids, k=k, sampled=True,
+                 deterministic=args.deterministic)
     rep = torch.zeros(L.REPORT_FLOATS, device=dev)
     rng = np.random.default_rng(w.seed)
     ws = None
@@ -543,6 +545,16 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
     e1.synchronize()
     unfused_ms = e0.elapsed_time(e1) / args.gn_reps
     out_gpu = out.double().cpu().numpy()
+    # the same product in the other accumulation mode (fixed-point sums when
+    # the run uses float atomics, and the reverse), phases median of gn_reps
+    fr.deterministic = not args.deterministic
+    other_ws = L.workspace(L.OP_GN, fr)
+    other_phases = np.median(np.array([L.lmrs_gn_product_timed(fr, p, w.lam, out=out, ws=other_ws)[1]
+                                       for _ in range(args.gn_reps)]), axis=0)
+    fr.deterministic = args.deterministic
+    del other_ws
+    log(f"[bench] GN product with {'float-atomic' if args.deterministic else 'deterministic'} accumulation: "
+        f"{other_phases.sum():.3f} ms (phases {', '.join(f'{x:.4f}' for x in other_phases)})")
     # the state of the timed product, for the oracle (the stage breakdown below re-samples)
     beta_h, pix_h, w_h, vids_h = (fr.beta.cpu().numpy(), fr.pix.cpu().numpy(), fr.w.cpu().numpy(),
                                   view_ids.cpu().numpy())
@@ -609,12 +621,15 @@ def run_workload(args, workload: str, steps: int, warmup: int, with_cpu: bool, n
         "config": {"workload": w.name, "gaussians": w.n, "sh_degree": w.sh_degree,
                    "views_per_step": V, "views_total": int(w.cams.shape[0]), "resolution": [w.width, w.height],
                    "samples_per_tile": k, "cg_iters": w.cg_iters, "lambda": w.lam,
+                   "deterministic": bool(args.deterministic),
                    "gn_product_ms_median": round(gn_ms, 4),
                    "gn_products_per_s_isolated": round(1e3 / gn_ms, 2),
                    "gn_phase_ms_median": [round(float(x), 4) for x in phase_ms],
                    "gn_phases": ["tangent", "fill", "blend-table splat", "fused walk", "chain"],
                    "gn_walk_ms_median": round(walk_ms, 4),
                    "gn_walk_phase_ms_median": [round(float(x), 4) for x in walk_phases],
+                   ("gn_float_atomic_phase_ms_median" if args.deterministic else
+                    "gn_deterministic_phase_ms_median"): [round(float(x), 4) for x in other_phases],
                    "linearize_ms": round(linearize_ms, 4),
                    "blend_table": {"built": table, "pairs": fr.blend_pairs(), "bytes_per_pair": 44},
                    "gn_unfused_jvp_vjp_ms": round(unfused_ms, 4),
@@ -659,6 +674,8 @@ def main():
     ap.add_argument("--lm-iters", type=int, default=0, help="override the requests' LM iterations")
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--policy", choices=["fifo", "sjf"], default="fifo", help="serving admission order")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="fixed-point accumulation (the same bits on every run) for the workload and the fits")
     args = ap.parse_args()
     if args.serving:
         return serving_main(args)

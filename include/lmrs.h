@@ -172,6 +172,18 @@ typedef struct lmrs_frame {
                              on every channel         (ssim, lm with SSIM: out) */
   float* image;           /* [V][height][width][3] full render of the batch
                              views                    (ssim, lm with SSIM: out) */
+  /* Deterministic accumulation: 0 = the sums over tiles (screen gradients of
+   * J^T u and b, Gram blocks of the diagonal) and the per-pixel sums of J p
+   * over the blend table are float atomics, whose order, and so the last
+   * bits of every result, changes from run to run; 1 = they are fixed-point
+   * integer sums (each float term split into two 64-bit integers in units of
+   * 2^-20 and 2^-60), so every call gives the same bits for the same inputs
+   * on the same GPU, whatever the order of the adds. Every other stage is
+   * deterministic either way. Mode 1 needs a larger workspace
+   * (lmrs_workspace_bytes reads this field) and holds per term: magnitudes
+   * below 2^30 (a term beyond that, or not finite, makes its whole row NaN),
+   * sums below 2^42, resolution 2^-60. */
+  int32_t deterministic;
 } lmrs_frame;
 
 /* Length in int32 of lmrs_frame.sched for a batch of `tiles` = V*T tiles. */

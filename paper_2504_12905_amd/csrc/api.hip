@@ -61,6 +61,11 @@ struct Scratch {
   BinScratch bin{};
 };
 
+// 32-bit words of the screen-gradient and Gram accumulators (float rows, or
+// the fixed-point rows of deterministic accumulation).
+int64_t grad_floats(const FrameDims& d) { return (int64_t)d.V * d.n * (d.det ? kFixGradFloats : kGradRow); }
+int64_t gram_floats(const FrameDims& d) { return (int64_t)d.V * d.n * (d.det ? kFixGramFloats : kGram); }
+
 // Workspace layout of each operation.
 Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
   Scratch s;
@@ -86,8 +91,8 @@ Scratch carve(int op, const FrameDims& d, int64_t capacity, Carver& c) {
     s.bin.col_part = c.take<int64_t>(((size_t)d.V * d.T + 255) / 256);
   }
   if (need_tan) s.tan = c.take<float>((size_t)VN * LMRS_REC);
-  if (need_grad) s.grad2d = c.take<float>((size_t)VN * kGradRow);
-  if (need_gram) s.gram = c.take<float>((size_t)VN * kGram);
+  if (need_grad) s.grad2d = c.take<float>((size_t)grad_floats(d));
+  if (need_gram) s.gram = c.take<float>((size_t)gram_floats(d));
   if (need_pcg) {
     s.diag = c.take<float>(P);
     s.r = c.take<float>(P);
@@ -125,6 +130,8 @@ lmrs_status check_frame(const lmrs_frame* f, bool need_samples_k = true) {
     if (!f->pix && f->k != 256) return fail(LMRS_EINVAL, "pix is NULL but k = %d != 256", f->k);
   }
   if (!f->beta) return fail(LMRS_EINVAL, "beta is NULL");
+  if (f->deterministic != 0 && f->deterministic != 1)
+    return fail(LMRS_EINVAL, "deterministic = %d must be 0 or 1", f->deterministic);
   if (f->blend_k) {
     if (!f->blend_m || !f->blend_run || !f->blend_runs || !f->blend_start)
       return fail(LMRS_EINVAL, "blend_k is set: blend_m, blend_run, blend_runs and blend_start are needed");
@@ -176,7 +183,7 @@ void gn_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts
                  float lambda, const float* dvec, float* out, const Scratch& s, hipStream_t st,
                  double* pu_part = nullptr, bool grad_zero = false) {
   launch_tangent(f, d, o, p, s.tan, st);
-  if (!grad_zero) launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
+  if (!grad_zero) launch_fill(s.grad2d, grad_floats(d), 0.f, st);
   // from the blend table when it is built for this render, else the fused walk
   launch_blend_gn(f, d, o, s.tan, s.grad2d, st);
   launch_deriv(3, f, d, o, s.tan, nullptr, nullptr, s.grad2d, st);
@@ -185,14 +192,14 @@ void gn_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts
 
 void vjp_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* u,
                   float* out, const Scratch& s, hipStream_t st) {
-  launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
+  launch_fill(s.grad2d, grad_floats(d), 0.f, st);
   launch_deriv(2, f, d, o, nullptr, u, nullptr, s.grad2d, st);
   launch_chain_vjp(f, d, o, s.grad2d, nullptr, 0.f, nullptr, out, st);
 }
 
 void diag_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, float* out,
                    const Scratch& s, hipStream_t st) {
-  launch_fill(s.gram, (int64_t)d.V * d.n * kGram, 0.f, st);
+  launch_fill(s.gram, gram_floats(d), 0.f, st);
   launch_gram(f, d, o, s.gram, nullptr, nullptr, st);
   launch_chain_diag(f, d, o, s.gram, out, st);
 }
@@ -200,8 +207,8 @@ void diag_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_op
 // b = J^T u and diag(J^T W J) from one reverse walk (the Gram pass with J^T u).
 void vjp_diag_sequence(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts& o, const float* u,
                        float* b, float* diag, const Scratch& s, hipStream_t st) {
-  launch_fill(s.gram, (int64_t)d.V * d.n * kGram, 0.f, st);
-  launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
+  launch_fill(s.gram, gram_floats(d), 0.f, st);
+  launch_fill(s.grad2d, grad_floats(d), 0.f, st);
   launch_gram(f, d, o, s.gram, u, s.grad2d, st);
   launch_chain_vjp(f, d, o, s.grad2d, nullptr, 0.f, nullptr, b, st, nullptr, true);  // leaves grad2d zero
   launch_chain_diag(f, d, o, s.gram, diag, st);
@@ -352,6 +359,7 @@ FrameDims dims_of(const lmrs_frame* f) {
   d.T = d.TX * d.TY;
   d.k = f->k;
   d.S = (int64_t)d.V * d.T * d.k;
+  d.det = f->deterministic != 0;
   return d;
 }
 
@@ -540,7 +548,7 @@ lmrs_status lmrs_gn_product_timed(const lmrs_frame* f, const lmrs_render_opts* o
   (void)hipEventRecord(ev[0], st);
   launch_tangent(f, d, *o, p, s.tan, st);
   (void)hipEventRecord(ev[1], st);
-  launch_fill(s.grad2d, (int64_t)d.V * d.n * kGradRow, 0.f, st);
+  launch_fill(s.grad2d, grad_floats(d), 0.f, st);
   (void)hipEventRecord(ev[2], st);
   launch_blend_gn(f, d, *o, s.tan, s.grad2d, st);
   (void)hipEventRecord(ev[3], st);
@@ -734,7 +742,8 @@ lmrs_status lmrs_gn_product_noalloc(const lmrs_frame* f, const lmrs_render_opts*
     return fail(LMRS_EWORKSPACE,
                 "lmrs_gn_product_noalloc: this frame needs %zu bytes of scratch, the static array holds %zu "
                 "(views x Gaussians up to about %zu); use lmrs_gn_product with a workspace",
-                need_bytes, kNoAllocBytes, kNoAllocBytes / ((LMRS_REC + kGradRow) * sizeof(float)));
+                need_bytes, kNoAllocBytes,
+                kNoAllocBytes / ((LMRS_REC + (f->deterministic ? kFixGradFloats : kGradRow)) * sizeof(float)));
   void* ws = nullptr;
   LMRS_TRY(noalloc_scratch(&ws));
   const FrameDims d = dims_of(f);

@@ -22,6 +22,58 @@ constexpr int kWave = 64;
 constexpr int kGram = 32;            // Gram entries kept per (view, Gaussian)
 constexpr int kGradRow = 16;         // floats per (view, Gaussian) row of screen gradients (9 used)
 
+// ---------------------------------------------------------------- fixed point
+// Deterministic accumulation (lmrs_frame.deterministic). A float term v goes
+// into an accumulator as two 64-bit integers: hi = floor(v 2^20) and lo = the
+// rest in units of 2^-60 (0 <= lo < 2^40), each added by an integer atomic.
+// Integer sums do not depend on the order of the adds, so the accumulated
+// value hi 2^-20 + lo 2^-60 has the same bits on every run. v 2^20 is exact
+// (a power-of-two scaling of a float, in FP64), so is its fractional part;
+// the split is exact for |v| >= 2^-37 and rounds only below 2^-60. Range:
+// |v| < 2^30 per term (a term beyond that, or not finite, sets the row's
+// poison word and the reader takes the row as NaN), |sum| < 2^42, at most
+// 2^23 terms per accumulator. A row holds the hi words of its components,
+// then (from word LO) their lo words, and a poison word P; the hi and the lo
+// words of a screen-gradient row each fill part of one 128-byte line, so an
+// atomic instruction over a row's components touches one line, as the float
+// rows do.
+constexpr int kFixGradRow = 32, kFixGradLo = 16, kFixGradPoison = 25;  // 256 B per row
+constexpr int kFixGramRow = 80, kFixGramLo = 32, kFixGramPoison = 64;  // 640 B per row
+constexpr int kFixGradFloats = 2 * kFixGradRow;  // the same rows counted in 32-bit words
+constexpr int kFixGramFloats = 2 * kFixGramRow;
+
+__device__ __forceinline__ void fix_split(float v, long long& hi, long long& lo) {
+  const double s = (double)v * 0x1p20;
+  const double h = floor(s);
+  hi = (long long)h;
+  lo = (long long)rint((s - h) * 0x1p40);
+}
+
+// Component q of a fixed-point row += v (hi word row[q], lo word row[LO + q],
+// poison word row[P]).
+template <int LO, int P>
+__device__ __forceinline__ void fix_add(unsigned long long* row, int q, float v) {
+  if (!(fabsf(v) < 0x1p30f)) {  // NaN fails the test too
+    atomicOr(row + P, 1ull);
+    return;
+  }
+  long long hi, lo;
+  fix_split(v, hi, lo);
+  if (hi) atomicAdd(row + q, (unsigned long long)hi);
+  if (lo) atomicAdd(row + LO + q, (unsigned long long)lo);
+}
+
+__device__ __forceinline__ float fix_value(unsigned long long hi, unsigned long long lo) {
+  return (float)((double)(long long)hi * 0x1p-20 + (double)(long long)lo * 0x1p-60);
+}
+
+// Screen-gradient row `row` (= view * n + Gaussian), component q < 9: a float
+// atomic into the kGradRow-float rows, or fixed point into kFixGradRow-word rows.
+__device__ __forceinline__ void grad_add(float* grad2d, bool fixed, size_t row, int q, float v) {
+  if (fixed) fix_add<kFixGradLo, kFixGradPoison>(reinterpret_cast<unsigned long long*>(grad2d) + row * kFixGradRow, q, v);
+  else atomicAdd(&grad2d[row * kGradRow + q], v);
+}
+
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon et al., SC 2011): 10 rounds of two 32x32->64
 // multiplies with key bumps by the Weyl constants. Host and device.

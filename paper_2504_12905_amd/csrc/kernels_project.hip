@@ -115,16 +115,54 @@ __global__ __launch_bounds__(kBlock) void tangent_kernel(const float* __restrict
   }
 }
 
+// A fixed-point row of NC components (hi words from word 0, lo words from
+// word LO, poison word P; see fix_add) read into floats; false when the row
+// is all zero (nothing accumulated), NaN components when it is poisoned.
+// With clear the row is zeroed after the read. Rows are 16-byte aligned and
+// their words past the components up to an even count are zero.
+template <int NC, int LO, int P>
+__device__ __forceinline__ bool fix_row(unsigned long long* row, float* out, bool clear) {
+  constexpr int kPairs = (NC + 1) / 2;
+  const ulonglong2* hp = reinterpret_cast<const ulonglong2*>(row);
+  const ulonglong2* lp = reinterpret_cast<const ulonglong2*>(row + LO);
+  unsigned long long hi[2 * kPairs], lo[2 * kPairs];
+#pragma unroll
+  for (int i = 0; i < kPairs; ++i) {
+    const ulonglong2 h = hp[i], l = lp[i];
+    hi[2 * i] = h.x;
+    hi[2 * i + 1] = h.y;
+    lo[2 * i] = l.x;
+    lo[2 * i + 1] = l.y;
+  }
+  const unsigned long long poison = row[P];
+  unsigned long long any = poison;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    any |= hi[q] | lo[q];
+    out[q] = poison ? NAN : fix_value(hi[q], lo[q]);
+  }
+  if (!any) return false;
+  if (clear) {
+    ulonglong2* hw = reinterpret_cast<ulonglong2*>(row);
+    ulonglong2* lw = reinterpret_cast<ulonglong2*>(row + LO);
+#pragma unroll
+    for (int i = 0; i < kPairs; ++i) hw[i] = lw[i] = make_ulonglong2(0ull, 0ull);
+    row[P] = 0ull;
+  }
+  return true;
+}
+
 // out[beta_g] = sum_v (d rec_vg / d beta_g)^T grad2d[v][g][0..9)  (+ lambda d p).
 // With pu_part, each workgroup also leaves its partial sum of p . out in
 // pu_part[blockIdx.x] (FP64; the PCG update reduces them), which saves the
 // operator product's separate pass over p and u. With zero_rows it clears
 // the non-zero rows it has read, so that grad2d is all zero again for the
-// next accumulation (instead of a fill of the whole buffer).
+// next accumulation (instead of a fill of the whole buffer). With fixed the
+// rows are the fixed-point rows of deterministic accumulation.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
     const float* __restrict__ beta, int n, int V, const lmrs_camera* __restrict__ cams,
-    const int32_t* __restrict__ view_ids, float lowpass, float* __restrict__ grad2d,
+    const int32_t* __restrict__ view_ids, float lowpass, float* __restrict__ grad2d, bool fixed,
     const float* __restrict__ p, float lambda, const float* __restrict__ dvec, float* __restrict__ out,
     double* __restrict__ pu_part, bool zero_rows) {
   constexpr int PG = ShDims<DEG>::PG;
@@ -137,16 +175,27 @@ __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
     const GeoFactors gf = geo_factors(prm);
     GeoGrad acc;
     geo_grad_zero(acc);
+    if (fixed) {
+      unsigned long long* rows = reinterpret_cast<unsigned long long*>(grad2d);
+      for (int v = 0; v < V; ++v) {
+        float gr[9];
+        if (!fix_row<9, kFixGradLo, kFixGradPoison>(rows + ((size_t)v * n + g) * kFixGradRow, gr, zero_rows))
+          continue;
+        const CamView cv = load_cam(cams, view_ids, v);
+        proj_vjp_view<DEG>(prm, gf, cv, lowpass, gr, gp, acc);
+      }
+    }
+    const int Vf = fixed ? 0 : V;  // views of float rows
     // the next view's row is loaded while this view's row is taken back
     float4 a_next{}, b_next{};
     float c_next = 0.f;
-    if (V > 0) {
+    if (Vf > 0) {
       const float* row0 = grad2d + (size_t)g * kGradRow;
       a_next = reinterpret_cast<const float4*>(row0)[0];
       b_next = reinterpret_cast<const float4*>(row0)[1];
       c_next = row0[8];
     }
-    for (int v = 0; v < V; ++v) {
+    for (int v = 0; v < Vf; ++v) {
       float gr[9];
       bool any = false;
       float* row = grad2d + ((size_t)v * n + g) * kGradRow;
@@ -154,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
       gr[0] = a.x; gr[1] = a.y; gr[2] = a.z; gr[3] = a.w;
       gr[4] = b.x; gr[5] = b.y; gr[6] = b.z; gr[7] = b.w;
       gr[8] = c_next;
-      if (v + 1 < V) {
+      if (v + 1 < Vf) {
         const float* nrow = row + (size_t)n * kGradRow;
         a_next = reinterpret_cast<const float4*>(nrow)[0];
         b_next = reinterpret_cast<const float4*>(nrow)[1];
@@ -200,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void chain_vjp_kernel(
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void chain_diag_kernel(
     const float* __restrict__ beta, int n, int V, const lmrs_camera* __restrict__ cams,
-    const int32_t* __restrict__ view_ids, float lowpass, const float* __restrict__ gram,
+    const int32_t* __restrict__ view_ids, float lowpass, const float* __restrict__ gram, bool fixed,
     float* __restrict__ out) {
   constexpr int K2 = ShDims<DEG>::K;
   constexpr int PG = ShDims<DEG>::PG;
@@ -215,17 +264,25 @@ __global__ __launch_bounds__(kBlock) void chain_diag_kernel(
   for (int v = 0; v < V; ++v) {
     float G[kGram];
     bool any = false;
-    const float4* row = reinterpret_cast<const float4*>(gram + ((size_t)v * n + g) * kGram);
+    if (fixed) {
+      // const_cast: fix_row clears nothing here
+      any = fix_row<kGram, kFixGramLo, kFixGramPoison>(
+          const_cast<unsigned long long*>(reinterpret_cast<const unsigned long long*>(gram)) +
+              ((size_t)v * n + g) * kFixGramRow,
+          G, false);
+    } else {
+      const float4* row = reinterpret_cast<const float4*>(gram + ((size_t)v * n + g) * kGram);
 #pragma unroll
-    for (int e4 = 0; e4 < kGram / 4; ++e4) {
-      const float4 x = row[e4];
-      G[4 * e4] = x.x;
-      G[4 * e4 + 1] = x.y;
-      G[4 * e4 + 2] = x.z;
-      G[4 * e4 + 3] = x.w;
+      for (int e4 = 0; e4 < kGram / 4; ++e4) {
+        const float4 x = row[e4];
+        G[4 * e4] = x.x;
+        G[4 * e4 + 1] = x.y;
+        G[4 * e4 + 2] = x.z;
+        G[4 * e4 + 3] = x.w;
+      }
+#pragma unroll
+      for (int e = 0; e < kGram; ++e) any |= G[e] != 0.f;
     }
-#pragma unroll
-    for (int e = 0; e < kGram; ++e) any |= G[e] != 0.f;
     if (!any) continue;
     const CamView cv = load_cam(cams, view_ids, v);
     float Jc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -313,10 +370,10 @@ void launch_chain_vjp(const lmrs_frame* f, const FrameDims& d, const lmrs_render
                       hipStream_t s, double* pu_part, bool zero_rows) {
   const unsigned grid = (unsigned)chain_vjp_blocks(d.n, pu_part != nullptr);
   switch (d.deg) {
-    case 0: chain_vjp_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part, zero_rows); break;
-    case 1: chain_vjp_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part, zero_rows); break;
-    case 2: chain_vjp_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part, zero_rows); break;
-    default: chain_vjp_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, p, lambda, dvec, out, pu_part, zero_rows); break;
+    case 0: chain_vjp_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, d.det, p, lambda, dvec, out, pu_part, zero_rows); break;
+    case 1: chain_vjp_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, d.det, p, lambda, dvec, out, pu_part, zero_rows); break;
+    case 2: chain_vjp_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, d.det, p, lambda, dvec, out, pu_part, zero_rows); break;
+    default: chain_vjp_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, grad2d, d.det, p, lambda, dvec, out, pu_part, zero_rows); break;
   }
 }
 
@@ -324,10 +381,10 @@ void launch_chain_diag(const lmrs_frame* f, const FrameDims& d, const lmrs_rende
                        const float* gram, float* out, hipStream_t s) {
   const unsigned grid = (d.n + kBlock - 1) / kBlock;
   switch (d.deg) {
-    case 0: chain_diag_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, out); break;
-    case 1: chain_diag_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, out); break;
-    case 2: chain_diag_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, out); break;
-    default: chain_diag_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, out); break;
+    case 0: chain_diag_kernel<0><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, d.det, out); break;
+    case 1: chain_diag_kernel<1><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, d.det, out); break;
+    case 2: chain_diag_kernel<2><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, d.det, out); break;
+    default: chain_diag_kernel<3><<<grid, kBlock, 0, s>>>(f->beta, d.n, d.V, f->cams, f->view_ids, o.lowpass, gram, d.det, out); break;
   }
 }
 

@@ -632,7 +632,7 @@ __device__ __forceinline__ void deriv_tile(
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
     const float* __restrict__ wc, const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n,
     int T, int TX, int k, const lmrs_render_opts& o, const float* __restrict__ u_in, float* __restrict__ jp_out,
-    float* __restrict__ grad2d, int64_t tile_lin, int wv, float* red) {
+    float* __restrict__ grad2d, bool fixed, int64_t tile_lin, int wv, float* red) {
   constexpr bool FWD = MODE != 2;
   constexpr bool REV = MODE != 1;
   constexpr bool DEALT = W > 1 && NS == 1 && MP > 1;
@@ -893,7 +893,7 @@ __device__ __forceinline__ void deriv_tile(
 #pragma unroll
           for (int w = 0; w < W; ++w) sum += buf[(w * 9 + q) * (kWave + 1) + ent];
         }
-        if (ide >= 0 && q < 9 && sum != 0.f) atomicAdd(&grad2d[((size_t)c.v * n + ide) * kGradRow + q], sum);
+        if (ide >= 0 && q < 9 && sum != 0.f) grad_add(grad2d, fixed, (size_t)c.v * n + ide, q, sum);
       }
       ++chunk;
     }
@@ -912,7 +912,8 @@ __global__ __launch_bounds__(kWave* W) void deriv_kernel(
     const int32_t* __restrict__ ids, const uint8_t* __restrict__ pix, const float* __restrict__ wts,
     const float* __restrict__ wc, const float* __restrict__ trans, const int32_t* __restrict__ lastv, int n,
     int T, int TX, int k, lmrs_render_opts o, const float* __restrict__ u_in, float* __restrict__ jp_out,
-    float* __restrict__ grad2d, int32_t* __restrict__ sched, int tiles, const int64_t* __restrict__ built) {
+    float* __restrict__ grad2d, bool fixed, int32_t* __restrict__ sched, int tiles,
+    const int64_t* __restrict__ built) {
   __shared__ int next_tile[2];
   __shared__ float red[MODE == 1 ? 1 : 2 * kRedBuf<W>];
   if (built && *built == 1) return;  // the blend table holds this render: blend_gn_kernel ran instead
@@ -928,7 +929,7 @@ __global__ __launch_bounds__(kWave* W) void deriv_kernel(
     if (tile == -1) break;
     if (tile >= 0)
       deriv_tile<MODE, NS, W, MP>(rec, tan, tile_start, ids, pix, wts, wc, trans, lastv, n, T, TX, k, o, u_in,
-                                  jp_out, grad2d, tile, wv, red);
+                                  jp_out, grad2d, fixed, tile, wv, red);
   }
   if (threadIdx.x == 0) sched_sign_off(sr);
 }
@@ -983,7 +984,8 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
                                           const int32_t* __restrict__ lastv, int n, int T, int TX, int k,
                                           const lmrs_render_opts& o, float* __restrict__ gram,
                                           const float* __restrict__ u_in, float* __restrict__ grad2d,
-                                          const BlendOut& bo, int64_t tile_lin, float* tr, int* tr_id) {
+                                          bool fixed, const BlendOut& bo, int64_t tile_lin, float* tr,
+                                          int* tr_id) {
   const int lane = lane_id();
   const TileCtx c = tile_ctx(tile_start, T, TX, tile_lin);
   PixelRegs<NS> pr;
@@ -1147,7 +1149,13 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
         const int e2 = 2 * t + half;
         const int ide = tr_id[e2];
         const float val = tr[q * (kWave + 1) + e2];
-        if (ide >= 0 && val != 0.f) atomicAdd(&gram[((size_t)c.v * n + ide) * kGram + q], val);
+        if (ide >= 0 && val != 0.f) {
+          const size_t row = (size_t)c.v * n + ide;
+          if (fixed)
+            fix_add<kFixGramLo, kFixGramPoison>(reinterpret_cast<unsigned long long*>(gram) + row * kFixGramRow, q,
+                                                val);
+          else atomicAdd(&gram[row * kGram + q], val);
+        }
       }
     }
     if (VJP) {  // J^T u, transposed the same way: 4 gradient rows per instruction
@@ -1158,7 +1166,7 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ rec, const i
         const int e2 = 4 * t + (lane >> 4);
         const int ide = tr_id[e2];
         const float val = q < 9 ? tr[q * (kWave + 1) + e2] : 0.f;
-        if (ide >= 0 && val != 0.f) atomicAdd(&grad2d[((size_t)c.v * n + ide) * kGradRow + q], val);
+        if (ide >= 0 && val != 0.f) grad_add(grad2d, fixed, (size_t)c.v * n + ide, q, val);
       }
     }
   }
@@ -1176,8 +1184,9 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
                                                      const int32_t* __restrict__ lastv, int n, int T,
                                                      int TX, int k, lmrs_render_opts o,
                                                      float* __restrict__ gram, const float* __restrict__ u_in,
-                                                     float* __restrict__ grad2d, int32_t* __restrict__ sched,
-                                                     int tiles, BlendOut bo, int64_t blend_capacity) {
+                                                     float* __restrict__ grad2d, bool fixed,
+                                                     int32_t* __restrict__ sched, int tiles, BlendOut bo,
+                                                     int64_t blend_capacity) {
   __shared__ float tr[kGram * (kWave + 1)];  // flush transposes (padded rows: no bank conflicts)
   __shared__ int tr_id[kWave];
   const SchedRef sr = sched_ref(sched, tiles);
@@ -1189,7 +1198,7 @@ __global__ __launch_bounds__(kWave) void gram_kernel(const float* __restrict__ r
     if (tile == -1) break;
     if (tile >= 0)
       gram_tile<NS, VJP, GRAM>(rec, tile_start, ids, pix, wts, wc, trans, lastv, n, T, TX, k, o, gram, u_in,
-                               grad2d, bo, tile, tr, tr_id);
+                               grad2d, fixed, bo, tile, tr, tr_id);
   }
   sched_finish(sr);
 }
@@ -1347,6 +1356,7 @@ __device__ __forceinline__ void seg_scan9(float (&g)[9], int dist) {
                : "v"(k31));
 }
 
+template <bool DET>
 __global__ __launch_bounds__(kBlendGnThreads) void blend_gn_kernel(
     const float* __restrict__ rec, const float* __restrict__ tan, const float4* __restrict__ bk,
     const uint32_t* __restrict__ bm, const int64_t* __restrict__ bstart, const uint8_t* __restrict__ pix,
@@ -1357,6 +1367,9 @@ __global__ __launch_bounds__(kBlendGnThreads) void blend_gn_kernel(
   __shared__ float2 s_xy[kMaxK];  // pixel centre of each sample slot
   __shared__ float s_tr[kBlendGnWaves][9 * (kWave + 1)];
   __shared__ int s_id[kBlendGnWaves][kWave];
+  // deterministic mode: J p of each sample slot in fixed point (3 hi words,
+  // 3 lo words, poison word, padding)
+  __shared__ unsigned long long s_fix[DET ? kMaxK * 8 : 1];
   if (bstart[tiles + 1] != 1) return;  // no table for this render: the list walk runs instead
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
   const uint64_t below = (1ull << lane) - 1ull;
@@ -1375,6 +1388,10 @@ __global__ __launch_bounds__(kBlendGnThreads) void blend_gn_kernel(
       const int p = pix ? (int)pix[(int64_t)tile * k + j] : j;
       s_xy[j] = make_float2(ox + (float)(p & 15) + 0.5f, oy + (float)(p >> 4) + 0.5f);
       s_u[j] = float4{};
+      if constexpr (DET) {
+#pragma unroll
+        for (int w = 0; w < 8; ++w) s_fix[8 * j + w] = 0ull;
+      }
     }
     __syncthreads();
     // 1. J p at the tile's sampled pixels, over the pixel-grouped copy of
@@ -1421,9 +1438,15 @@ __global__ __launch_bounds__(kBlendGnThreads) void blend_gn_kernel(
         seg_scan3(dc, dist);
         const bool is_end = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ull);
         if (is_end && j >= 0) {
-          atomicAdd(&s_u[j].x, dc[0]);
-          atomicAdd(&s_u[j].y, dc[1]);
-          atomicAdd(&s_u[j].z, dc[2]);
+          if constexpr (DET) {
+            fix_add<3, 6>(s_fix + 8 * j, 0, dc[0]);
+            fix_add<3, 6>(s_fix + 8 * j, 1, dc[1]);
+            fix_add<3, 6>(s_fix + 8 * j, 2, dc[2]);
+          } else {
+            atomicAdd(&s_u[j].x, dc[0]);
+            atomicAdd(&s_u[j].y, dc[1]);
+            atomicAdd(&s_u[j].z, dc[2]);
+          }
         }
       }
     }
@@ -1431,7 +1454,12 @@ __global__ __launch_bounds__(kBlendGnThreads) void blend_gn_kernel(
     // 2. u = w J p (per channel with operator weights wc)
     for (int j = tid; j < k; j += kBlendGnThreads) {
       const int64_t i = (int64_t)tile * k + j;
-      const float4 x = s_u[j];
+      float4 x = s_u[j];
+      if constexpr (DET) {
+        const unsigned long long* fx = s_fix + 8 * j;
+        x = fx[6] ? make_float4(NAN, NAN, NAN, 0.f)
+                  : make_float4(fix_value(fx[0], fx[3]), fix_value(fx[1], fx[4]), fix_value(fx[2], fx[5]), 0.f);
+      }
       if (wc) {
         s_u[j] = make_float4(x.x * wc[3 * i], x.y * wc[3 * i + 1], x.z * wc[3 * i + 2], 0.f);
       } else {
@@ -1507,7 +1535,7 @@ __global__ __launch_bounds__(kBlendGnThreads) void blend_gn_kernel(
         if (ent < nseg && q < 9) {
           const int ide = s_id[wv][ent];
           const float val = tr[q * (kWave + 1) + ent];
-          if (ide >= 0 && val != 0.f) atomicAdd(&grad2d[(vb + ide) * kGradRow + q], val);
+          if (ide >= 0 && val != 0.f) grad_add(grad2d, DET, vb + ide, q, val);
         }
       }
     }
@@ -1686,7 +1714,8 @@ void launch_deriv_mode(const lmrs_frame* f, const FrameDims& d, const lmrs_rende
   const int mp = W > 1 && small && d.k <= 8 * W ? (d.k + W - 1) / W : 1;
   auto go = [&](auto kern) {
     kern<<<grid, block, 0, s>>>(f->rec, tan, f->tile_start, f->ids, f->pix, f->w, MODE == 3 ? f->wc : nullptr,
-                                f->trans, f->last, d.n, d.T, d.TX, d.k, o, u, jp, grad2d, f->sched, tiles, built);
+                                f->trans, f->last, d.n, d.T, d.TX, d.k, o, u, jp, grad2d, d.det, f->sched, tiles,
+                                built);
   };
   if (!small) {
     go(deriv_kernel<MODE, 4, W, 1>);
@@ -1730,7 +1759,7 @@ void launch_gram(const lmrs_frame* f, const FrameDims& d, const lmrs_render_opts
               f->blend_k != nullptr, f->blend_capacity};
 #define LMRS_GRAM_ARGS                                                                                      \
   f->rec, f->tile_start, f->ids, f->pix, f->w, f->wc, f->trans, f->last, d.n, d.T, d.TX, d.k, o, gram, u, grad2d, \
-      f->sched, tiles, bo, f->blend_capacity
+      d.det, f->sched, tiles, bo, f->blend_capacity
   const bool wide = d.k > kWave;
   if (!gram_sums) {
     if (!wide) gram_kernel<1, false, false><<<grid, kWave, 0, s>>>(LMRS_GRAM_ARGS);
@@ -1750,9 +1779,13 @@ void launch_blend_gn(const lmrs_frame* f, const FrameDims& d, const lmrs_render_
                      float* grad2d, hipStream_t s) {
   if (!f->blend_k) return;
   const int tiles = d.V * d.T;
-  blend_gn_kernel<<<(unsigned)tiles, kBlendGnThreads, 0, s>>>(f->rec, tan, reinterpret_cast<const float4*>(f->blend_k),
-                                                   f->blend_m, f->blend_start, f->pix, f->w, f->wc, d.n, d.T, d.TX, d.k, o,
-                                                   grad2d, f->sched, tiles, f->blend_capacity);
+  auto go = [&](auto kern) {
+    kern<<<(unsigned)tiles, kBlendGnThreads, 0, s>>>(f->rec, tan, reinterpret_cast<const float4*>(f->blend_k),
+                                                     f->blend_m, f->blend_start, f->pix, f->w, f->wc, d.n, d.T, d.TX,
+                                                     d.k, o, grad2d, f->sched, tiles, f->blend_capacity);
+  };
+  if (d.det) go(blend_gn_kernel<true>);
+  else go(blend_gn_kernel<false>);
 }
 
 }  // namespace lmrs

@@ -12,6 +12,7 @@ namespace lmrs {
 struct FrameDims {
   int n, deg, pg, V, W, H, TX, TY, T, k;
   int64_t S;  // sampled pixels V*T*k
+  bool det;   // deterministic accumulation: grad2d and gram hold fixed-point rows
 };
 
 FrameDims dims_of(const lmrs_frame* f);

@@ -64,7 +64,7 @@ class _Frame(C.Structure):
                 ("trans", C.c_void_p), ("last", C.c_void_p), ("sched", C.c_void_p),
                 ("blend_k", C.c_void_p), ("blend_m", C.c_void_p), ("blend_run", C.c_void_p),
                 ("blend_runs", C.c_void_p), ("blend_start", C.c_void_p), ("blend_capacity", C.c_int64),
-                ("wc", C.c_void_p), ("image", C.c_void_p)]
+                ("wc", C.c_void_p), ("image", C.c_void_p), ("deterministic", C.c_int32)]
 
 
 BLEND_BYTES_PER_PAIR = 44   # blend_k (2 x 16) + blend_m (2 x 4) + blend_run (4)
@@ -156,6 +156,7 @@ class Frame:
     blend: bool = True             # keep the blend table (the render's linearization; see lmrs_frame)
     blend_capacity: int = 0        # pairs it can hold (grown by ensure_blend)
     ssim: bool = False             # allocate wc / image (the SSIM residual's buffers)
+    deterministic: bool = False    # fixed-point sums over tiles: the same bits on every run
     tensors: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -256,7 +257,8 @@ class Frame:
                       t["color"].data_ptr(), t["trans"].data_ptr(), t["last"].data_ptr(),
                       t["sched"].data_ptr(), *self._blend_fields(),
                       None if t["wc"] is None else t["wc"].data_ptr(),
-                      None if t["image"] is None else t["image"].data_ptr())
+                      None if t["image"] is None else t["image"].data_ptr(),
+                      1 if self.deterministic else 0)
 
     def _blend_fields(self):
         if not self.blend:

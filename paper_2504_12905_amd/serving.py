@@ -74,6 +74,7 @@ class FitRequest:
     lam: float = 0.1
     arrival_t: float = 0.0       # seconds after the start of the run
     id: int = 0
+    deterministic: bool = False  # fixed-point accumulation: the same bits alone, in a mix and on every run
 
     @staticmethod
     def from_stream(d: dict) -> "FitRequest":
@@ -134,9 +135,11 @@ def instances_bound(beta: np.ndarray, n: int, cams: np.ndarray, W: int, H: int) 
     return total
 
 
-def _frame_struct_bytes(op: int, n: int, deg: int, V: int, W: int, H: int, k: int, capacity: int) -> int:
+def _frame_struct_bytes(op: int, n: int, deg: int, V: int, W: int, H: int, k: int, capacity: int,
+                        deterministic: bool = False) -> int:
     fs = L._Frame(n, deg, V, W, H, k, None, None, None, None, None, None, None, capacity, None, None, None, None,
                   None, None)
+    fs.deterministic = 1 if deterministic else 0
     return int(L._lib.lmrs_workspace_bytes(op, L.C.byref(fs)))
 
 
@@ -160,7 +163,7 @@ def footprint_bytes(req: FitRequest, instances: int) -> int:
     frame = (V * n * (4 * L.LMRS_REC + 16) + 8 * (V * T + 1) + 4 * cap + S * (12 + 4 + 4)
              + 4 * L.sched_ints(V * T))
     ws = max(_frame_struct_bytes(L.OP_BIN, n, req.sh_degree, V, W, W, 256, cap),
-             _frame_struct_bytes(L.OP_LM, n, req.sh_degree, V, W, W, 256, cap))
+             _frame_struct_bytes(L.OP_LM, n, req.sh_degree, V, W, W, 256, cap, req.deterministic))
     return 4 * P + 16 * V * 4 + 12 * V * W * W + frame + ws + 64 * 4
 
 
@@ -197,7 +200,7 @@ class _Fit:
             self.cams = torch.tensor(prob.cams, device=dev)
             cap = int(prob.instances_bound * 1.05) + 1024
             self.fr = L.Frame(req.n, req.sh_degree, self.beta, self.cams, req.res, req.res, req.n_views, k=256,
-                              capacity=cap, blend=True)
+                              capacity=cap, blend=True, deterministic=req.deterministic)
             nbytes = max(L.workspace_bytes(L.OP_BIN, self.fr), L.workspace_bytes(ws_op, self.fr))
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
             self.rep = torch.zeros(L.REPORT_FLOATS, device=dev)

@@ -54,6 +54,24 @@ def test_workspace_sizes(M):
     assert M._lib.lmrs_workspace_bytes(M.OP_GN, None) == 0
 
 
+def test_deterministic_workspace_holds_fixed_point_rows(M):
+    """Deterministic accumulation keeps 32 64-bit words per screen-gradient
+    row (9 components as two integers each, a poison word, padding to whole
+    128-byte lines) instead of 16 floats, and 80 per Gram row instead of 32
+    floats."""
+    ws = lambda op, **kw: M._lib.lmrs_workspace_bytes(op, C.byref(frame(M, **kw)))
+    VN = 8 * 1000
+    grow_grad = VN * (32 * 8 - 16 * 4)
+    grow_gram = VN * (80 * 8 - 32 * 4)
+    for op, grow in ((M.OP_GN, grow_grad), (M.OP_DIAG, grow_gram), (M.OP_PCG, grow_grad + grow_gram),
+                     (M.OP_LM, grow_grad + grow_gram), (M.OP_JVP, 0)):
+        d = ws(op, deterministic=1) - ws(op)
+        assert abs(d - grow) <= 2 * 256, (op, d, grow)   # up to the 256-byte alignment of each buffer
+    f = frame(M, deterministic=2)
+    f.beta = 1
+    assert M._lib.lmrs_render(C.byref(f), C.byref(M.default_opts()), None) == M.LMRS_EINVAL
+
+
 @pytest.mark.parametrize("bad", [dict(n=0), dict(sh_degree=-1), dict(width=100), dict(n_views=0),
                                  dict(k=0), dict(k=300)])
 def test_invalid_frames_rejected_on_host(M, bad):

@@ -95,6 +95,51 @@ def test_same_alone_and_in_the_mix():
         assert a.status == b.status == "ok"
 
 
+def test_deterministic_graph_replays_equal_eager_bit_for_bit():
+    """With deterministic accumulation the graph replays and the eager solves
+    of the same fit stay bit-identical over 14 LM iterations, with no
+    re-synchronisation of the parameters."""
+    S = serving()
+    req = S.FitRequest(seed=3, n=6000, sh_degree=2, n_views=4, res=256, lm_iters=14, id=0, deterministic=True)
+    prob = S.make_problem(req)
+    eager = S._Fit(prob, torch.cuda.Stream(), False, DEV)
+    graph = S._Fit(prob, torch.cuda.Stream(), True, DEV)
+    for it in range(req.lm_iters):
+        eager.step()
+        graph.step()
+        torch.cuda.synchronize()
+        assert torch.equal(eager.beta.view(torch.int32), graph.beta.view(torch.int32)), it
+    assert set(graph.graphs) == {True, False}
+    assert eager.fr.blend_built() and graph.fr.blend_built()
+
+
+def test_deterministic_fits_same_bits_alone_and_in_the_mix():
+    """With deterministic accumulation six probe requests at lambda = 1e-3
+    (where the float-atomic noise grows about 3x per LM iteration) end with
+    the same parameters and PSNR, bit for bit, fitted alone by the sequential
+    solver and inside a served mix of twelve concurrent fits."""
+    S = serving()
+    probes = small_requests(range(6), lm_iters=6)
+    others = small_requests(range(6, 12), lm_iters=6)
+    for r in probes + others:
+        r.lam, r.deterministic = 1e-3, True
+    alone = S.run_sequential([S.make_problem(r) for r in probes])
+    srv = S.Server(hbm_budget_bytes=64 << 30, max_slots=6)
+    mix = sorted(probes + others, key=lambda r: r.id % 2)
+    for k, r in enumerate(mix):
+        r.arrival_t = 0.01 * k
+        srv.submit(r)
+    got = srv.run_until_idle()
+    assert len(got) == 12
+    for r in probes:
+        a, b = alone[r.id], got[r.id]
+        log(f"  request {r.id} (n={r.n}, SH {r.sh_degree}, {r.n_views} views {r.res}^2): identical "
+            f"{np.array_equal(a.beta, b.beta)}, PSNR {a.final_psnr:.6f} / {b.final_psnr:.6f} dB")
+        assert a.status == b.status == "ok"
+        assert np.array_equal(a.beta, b.beta)
+        assert a.final_psnr == b.final_psnr
+
+
 def test_failed_fit_is_isolated():
     """A request whose initial colours hold NaN retires with status "numeric"
     and its parameters untouched, while the three fits served beside it end
