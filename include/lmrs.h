@@ -316,7 +316,7 @@ lmrs_status lmrs_gn_product(const lmrs_frame* f, const lmrs_render_opts* o, cons
  * the same launches and result, with its scratch (tangent records and screen
  * gradients, lmrs_workspace_bytes(LMRS_OP_GN, f) bytes) taken from a static
  * device array of 64 MiB per GPU instead of a workspace argument (frames up to
- * about 599k views x Gaussians). The array is loaded with the library and held
+ * about 599k views x Gaussians, 220k with deterministic accumulation). The array is loaded with the library and held
  * until the process ends; the call allocates nothing. A frame that needs more
  * returns LMRS_EWORKSPACE. Every call on one GPU uses that GPU's array, so
  * calls that overlap on one GPU (other streams or threads) race: serialize
