@@ -319,7 +319,7 @@ def lm_breakdown(L, torch, fr, targets, w, sampler, it, gn_ms):
     return out
 
 
-def serving_leg(args, n_requests: int | None = None) -> dict:
+def serving_leg(args, n_requests: int | None = None, deterministic: bool | None = None) -> dict:
     """Served fits/s and p50/p99 latency on the first requests of the seeded
     Poisson stream of fit requests (256 requests at 20 req/s), against the
     plain sequential solver on the same requests and GPU."""
@@ -330,8 +330,9 @@ def serving_leg(args, n_requests: int | None = None) -> dict:
     count = n_requests or args.requests
     stream = synth.request_stream(256, args.rate, seed=0)[:count]
     reqs = [serving.FitRequest.from_stream(d) for d in stream]
+    det = bool(args.deterministic) if deterministic is None else deterministic
     for r in reqs:
-        r.deterministic = bool(args.deterministic)
+        r.deterministic = det
         if args.lm_iters:
             r.lm_iters = args.lm_iters
     log(f"[serve] preparing {len(reqs)} requests on the host")
@@ -359,7 +360,7 @@ def serving_leg(args, n_requests: int | None = None) -> dict:
                     f"Gaussians log-uniform 2k-200k, SH 0-3, 4-32 views of 256/512/800 px, every pixel)",
         "requests": len(reqs), "lm_iters": reqs[0].lm_iters, "cg_iters": reqs[0].cg_iters, "lambda": reqs[0].lam,
         "slots": args.slots, "hbm_budget_gib": args.hbm_budget_gb, "graphs": not args.no_graphs,
-        "policy": args.policy, "deterministic": bool(args.deterministic),
+        "policy": args.policy, "deterministic": det,
         "fits_per_s": round(s_srv["fits_per_s"], 4), "p50_latency_s": round(s_srv["p50_latency_s"], 3),
         "p99_latency_s": round(s_srv["p99_latency_s"], 3),
         "sequential": {k: round(v, 4) if isinstance(v, float) else v for k, v in s_seq.items()},
@@ -702,6 +703,14 @@ def main():
                                                 "roofline")}
         # served fits/s and latency against the sequential plain solver
         primary["serving"] = serving_leg(args)
+        if not args.deterministic:
+            # the same stream with deterministic accumulation: served and
+            # sequential fits then end with the same bits
+            try:
+                leg = serving_leg(args, deterministic=True)
+                primary["serving_deterministic"] = {k: v for k, v in leg.items() if k != "per_request"}
+            except Exception as e:  # reported, not fatal to the headline line
+                primary["serving_deterministic"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(primary), flush=True)
 
 

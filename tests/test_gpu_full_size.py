@@ -192,3 +192,32 @@ def test_full_size_adjoint_identity(full):
     rhs = float((p.double() * L.lmrs_vjp(fr, u).double()).sum())
     log(f"  <Jp,u>={lhs:.8e} <p,J^T u>={rhs:.8e}")
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_full_size_deterministic_products_repeat_bit_for_bit(full):
+    """Deterministic accumulation at the benchmark's size: the GN product over
+    the list walk and over the blend table, twice each, gives the same bits
+    and matches the FP64 oracle to the bar of the float-atomic product."""
+    w, fr, orc = full
+    L = lib()
+    p = np.random.default_rng(7).normal(size=orc.P).astype(np.float32)
+    pt = torch.tensor(p, device=DEV)
+    ref = orc.gn(p, w.lam)
+    try:
+        fr.deterministic = True
+        for path in ("walk", "table"):
+            if path == "walk":
+                L.lmrs_render(fr)          # leaves the table stale: the products walk the lists
+                assert not fr.blend_built()
+            else:
+                L.lmrs_linearize(fr)
+                assert fr.blend_built()
+            a = L.lmrs_gn_product(fr, pt, w.lam).clone()
+            b = L.lmrs_gn_product(fr, pt, w.lam).clone()
+            torch.cuda.synchronize()
+            same = torch.equal(a.view(torch.int32), b.view(torch.int32))
+            e = rel(np_(a), ref)
+            log(f"  deterministic GN product ({path}): repeats identical {same}, vs oracle {e:.2e}")
+            assert same and e < 1e-4
+    finally:
+        fr.deterministic = False
