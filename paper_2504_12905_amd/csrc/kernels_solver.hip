@@ -12,51 +12,64 @@ namespace lmrs {
 
 namespace {
 
-// One workgroup of 256 lanes per (view, tile): lane p draws the key of pixel p
-// from counter (p, tile, camera id, iteration); the k pixels with the smallest
-// (key, p) are taken, listed in ascending pixel order, each with weight 256/k.
-__global__ __launch_bounds__(256) void sample_kernel(const int32_t* __restrict__ view_ids, int T, int k,
-                                                     uint32_t seed_lo, uint32_t seed_hi, uint32_t iter,
-                                                     uint8_t* __restrict__ pix, float* __restrict__ w) {
-  __shared__ uint64_t s[256];
-  __shared__ int s_sel[256];
-  const int p = threadIdx.x;
-  const int64_t tile_lin = blockIdx.x;
+// One wave per (view, tile), four pixels per lane (pixel p = 64 j + lane in
+// register j): pixel p draws its key from counter (p, tile, camera id,
+// iteration); the k pixels with the smallest 40-bit (key, p) are taken,
+// listed in ascending pixel order, each with weight 256/k. The k-th smallest
+// key is found by a bitwise radix select over ballots (each step counts the
+// candidates whose next bit is 0), so a tile needs no LDS and no barrier.
+constexpr int kSampleWaves = 4;  // tiles per workgroup
+__global__ __launch_bounds__(kWave* kSampleWaves) void sample_kernel(const int32_t* __restrict__ view_ids, int T,
+                                                                     int k, int64_t tiles, uint32_t seed_lo,
+                                                                     uint32_t seed_hi, uint32_t iter,
+                                                                     uint8_t* __restrict__ pix,
+                                                                     float* __restrict__ w) {
+  const int lane = lane_id();
+  const int64_t tile_lin = (int64_t)blockIdx.x * kSampleWaves + threadIdx.x / kWave;
+  if (tile_lin >= tiles) return;  // the whole wave
   const int v = (int)(tile_lin / T), t = (int)(tile_lin % T);
   const uint32_t cam = (uint32_t)(view_ids ? view_ids[v] : v);
-  const uint4 r = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)t, cam, iter), seed_lo, seed_hi);
-  s[p] = ((uint64_t)r.x << 8) | (uint64_t)p;
-  __syncthreads();
-  for (int size = 2; size <= 256; size <<= 1)
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      if (p < 128) {
-        const int lo = 2 * stride * (p / stride) + (p % stride), hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint64_t x = s[lo], y = s[hi];
-        if ((x > y) == up) {
-          s[lo] = y;
-          s[hi] = x;
-        }
-      }
-      __syncthreads();
+  uint64_t c[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t p = (uint32_t)(j * kWave + lane);
+    const uint4 r = philox4x32_10(make_uint4(p, (uint32_t)t, cam, iter), seed_lo, seed_hi);
+    c[j] = ((uint64_t)r.x << 8) | (uint64_t)p;
+  }
+  // radix select, high bit first: `above` marks the decided bits, prefix
+  // their values in the k-th smallest key, cand counts the keys that match
+  // them and need how many of those are still to be taken. It stops when
+  // every candidate is taken (after about 8 of the 40 bits for distinct keys).
+  uint64_t prefix = 0, above = 0;
+  int need = k, cand = 256;
+  for (int b = 39; b >= 0 && cand > need; --b) {
+    const uint64_t bit = 1ull << b;
+    int zeros = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) zeros += __popcll(__ballot((c[j] & above) == prefix && (c[j] & bit) == 0));
+    above |= bit;
+    if (zeros >= need) {
+      cand = zeros;
+    } else {
+      need -= zeros;
+      cand -= zeros;
+      prefix |= bit;
     }
-  s_sel[p] = 0;
-  __syncthreads();
-  if (p < k) s_sel[(int)(s[p] & 0xff)] = 1;
-  __syncthreads();
-  // position of pixel p among the selected ones: selected lanes below it in
-  // its wave (ballot) plus the selected pixels of the waves before
-  const bool sel = s_sel[p] != 0;
-  const uint64_t selm = __ballot(sel);
-  const uint64_t below = selm & ((1ull << (p & (kWave - 1))) - 1ull);
-  __shared__ int s_wave[256 / kWave];
-  if ((p & (kWave - 1)) == 0) s_wave[p / kWave] = __popcll(selm);
-  __syncthreads();
-  if (sel) {
-    int pos = __popcll(below);
-    for (int q = 0; q < p / kWave; ++q) pos += s_wave[q];
-    pix[tile_lin * k + pos] = (uint8_t)p;
-    w[tile_lin * k + pos] = 256.f / (float)k;
+  }
+  // selected: the candidates and every key below them, written in
+  // ascending pixel order
+  const uint64_t below = (1ull << lane) - 1ull;
+  int base = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const bool sel = (c[j] & above) <= prefix;
+    const uint64_t m = __ballot(sel);
+    if (sel) {
+      const int64_t at = tile_lin * k + base + __popcll(m & below);
+      pix[at] = (uint8_t)(j * kWave + lane);
+      w[at] = 256.f / (float)k;
+    }
+    base += __popcll(m);
   }
 }
 
@@ -640,9 +653,10 @@ __global__ __launch_bounds__(256) void ssim_kernel(const float* __restrict__ ima
 }  // namespace
 
 void launch_sample_uniform(const lmrs_frame* f, const FrameDims& d, uint64_t seed, int iter, hipStream_t s) {
-  sample_kernel<<<(unsigned)((int64_t)d.V * d.T), 256, 0, s>>>(
-      f->view_ids, d.T, d.k, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)iter, f->pix,
-      f->w);
+  const int64_t tiles = (int64_t)d.V * d.T;
+  sample_kernel<<<(unsigned)((tiles + kSampleWaves - 1) / kSampleWaves), kWave * kSampleWaves, 0, s>>>(
+      f->view_ids, d.T, d.k, tiles, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)iter,
+      f->pix, f->w);
 }
 
 void launch_sample_residual(const lmrs_frame* f, const FrameDims& d, const float* scores, uint64_t seed,
