@@ -156,3 +156,33 @@ def test_out_of_range_terms_poison_their_rows(scene):
     # where the float mode accumulated something
     assert np.all(np.isnan(det[~ok])) and np.all(big[~ok] != 0)
     fr.deterministic = False
+
+
+def test_noalloc_and_ssim_products_repeat_bit_for_bit(scene):
+    """The no-workspace entry point gives the workspace entry point's bits in
+    deterministic mode (same kernels, same fixed-point rows, in its static
+    array); with the SSIM residual's per-channel operator weights the product
+    repeats bit for bit too."""
+    L = lib()
+    gt, beta, cams, pix, wts = scene
+    fr = gpu_frame(N, DEG, beta, cams, W, W, K, pix, wts)
+    L.lmrs_linearize(fr)
+    p = torch.tensor(np.random.default_rng(8).normal(size=fr.P).astype(np.float32), device=DEV)
+    fr.deterministic = True
+    a = L.lmrs_gn_product(fr, p, 0.05).clone()
+    b = L.lmrs_gn_product_noalloc(fr, p, 0.05, torch.empty_like(p)).clone()
+    torch.cuda.synchronize()
+    assert same_bits(a, b)
+    fs = gpu_frame(N, DEG, beta, cams, W, W, K, pix, wts, ssim=True)
+    L.lmrs_ssim_residual(fs, _targets(gt, cams), 0.2)   # sets the operator weights wc
+    L.lmrs_linearize(fs)
+    fs.deterministic = True
+    c = L.lmrs_gn_product(fs, p, 0.05).clone()
+    d = L.lmrs_gn_product(fs, p, 0.05).clone()
+    fs.deterministic = False
+    f = L.lmrs_gn_product(fs, p, 0.05).clone()
+    torch.cuda.synchronize()
+    e = rel(np_(c), np_(f))
+    log(f"  no-alloc = workspace bits: True; SSIM-weighted product repeats identical {same_bits(c, d)}, "
+        f"vs float atomics {e:.2e}, vs unweighted {rel(np_(c), np_(a)):.2e}")
+    assert same_bits(c, d) and e < 2e-5 and not same_bits(c, a)
