@@ -342,11 +342,12 @@ def serving_leg(args, n_requests: int | None = None, deterministic: bool | None 
     serving.run_sequential([serving.make_problem(serving.FitRequest(seed=999, n=2000, sh_degree=3, n_views=4,
                                                                     res=256, lm_iters=2))])
     log("[serve] sequential plain solves")
-    seq = serving.run_sequential(probs, hbm_budget_bytes=budget)
+    seq = serving.run_sequential(probs, hbm_budget_bytes=budget, progress=log)
     s_seq = serving.summarize(seq, probs)
     log(f"[serve] sequential: {s_seq}")
     log(f"[serve] continuous batching, {args.slots} slots, budget {args.hbm_budget_gb} GiB")
-    srv = serving.Server(budget, max_slots=args.slots, use_graphs=not args.no_graphs, policy=args.policy)
+    srv = serving.Server(budget, max_slots=args.slots, use_graphs=not args.no_graphs, policy=args.policy,
+                         progress=log)
     for p in probs:
         srv.submit(p.req, p)
     got = srv.run_until_idle()

@@ -283,6 +283,7 @@ class Server:
     _results: dict = field(default_factory=dict)
     log: list = field(default_factory=list)
     table_bytes: dict = field(default_factory=dict)   # blend-table bytes of each admitted fit
+    progress: object = None        # optional callable(str), called as each fit retires
 
     def submit(self, req: FitRequest, problem: Problem | None = None) -> int:
         """Queue a request (host data prepared now, off the device). Returns its handle."""
@@ -354,6 +355,9 @@ class Server:
                     used -= fit.prob.footprint + fit.table_bytes
                     free_streams.append(si)
                     self.log.append(("retire", req.id, end, used))
+                    if self.progress:
+                        self.progress(f"[serve] served fit {req.id} retired at {end:.1f} s "
+                                      f"({len(self._results)} done)")
                     del fit
                 else:
                     still.append((fit, si, start))
@@ -364,7 +368,7 @@ class Server:
 
 
 def run_sequential(problems: list[Problem], device: str = "cuda:0",
-                   hbm_budget_bytes: int = 200 << 30) -> dict[int, FitResult]:
+                   hbm_budget_bytes: int = 200 << 30, progress=None) -> dict[int, FitResult]:
     """Plain baseline: one request at a time in arrival order, eager
     lmrs_lm_step calls on the current stream, no graphs, no overlap."""
     out: dict[int, FitResult] = {}
@@ -386,6 +390,8 @@ def run_sequential(problems: list[Problem], device: str = "cuda:0",
         beta, psnr = fit.finalize()
         end = time.perf_counter() - t0
         out[req.id] = FitResult(beta, psnr, end - req.arrival_t, fit.status(), start, end)
+        if progress:
+            progress(f"[serve] sequential fit {req.id} done at {end:.1f} s ({len(out)} done)")
         del fit
     return out
 
