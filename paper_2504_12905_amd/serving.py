@@ -26,8 +26,15 @@ iteration (weights 1), damping lambda.
   b, preconditioner, the PCG loop's GN products and vector recurrences,
   learning rate, update: about a hundred launches), which never waits on the
   host. It is captured once per learning-rate branch into a HIP graph and
-  replayed; the whole iteration budget of a fit is enqueued at admission, so
-  the host only admits and retires;
+  replayed. A fit's iterations are enqueued CHUNK_ITERS at a time; when a
+  chunk has run, the host reads its failure bits. The host bound on the list
+  size holds for the parameters at admission, but a fit can grow its
+  Gaussians past it: an iteration whose lists overflow the id buffer leaves
+  the parameters alone and flags the overflow. The server then grows the id
+  buffer (and the binning workspace) to the largest count any iteration of
+  the chunk asked for, restores the parameters saved at the chunk's start and
+  runs the chunk again, so every iteration index runs once on complete
+  lists, as in the sequential solver;
 * each fit keeps a blend table (the linearization of its render, 44 bytes per
   blending (pixel, Gaussian) pair; lmrs_frame), sized at admission from the
   pair count of the target render with a 30 % margin and within what is left
@@ -60,6 +67,8 @@ from . import synth
 
 TABLE_CAP_BYTES = 48 << 30   # largest blend table of one fit
 TABLE_MARGIN = 1.3           # table pairs per pair of the target render
+CHUNK_ITERS = 5              # LM iterations a served fit enqueues between host checks
+MAX_REGROWTHS = 8            # list-buffer regrowths per fit before an overflow is reported
 
 
 @dataclass
@@ -194,7 +203,12 @@ class _Fit:
         req = prob.req
         self.prob, self.req, self.stream, self.use_graphs = prob, req, stream, use_graphs
         self.it = 0
+        self.dev, self.ws_op = dev, ws_op
         self.graphs: dict[bool, torch.cuda.CUDAGraph] = {}
+        self.chunk_start = 0
+        self.chunk_event: torch.cuda.Event | None = None
+        self.regrowths = 0
+        self.grown_bytes = 0          # id buffer and workspace added since admission
         with torch.cuda.stream(stream):
             self.beta = torch.tensor(prob.beta_gt, device=dev)
             self.cams = torch.tensor(prob.cams, device=dev)
@@ -205,6 +219,8 @@ class _Fit:
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
             self.rep = torch.zeros(L.REPORT_FLOATS, device=dev)
             self.fail = torch.zeros(1, dtype=torch.int32, device=dev)   # failure bits of every iteration, OR-ed
+            self.chunk_fail = torch.zeros(1, dtype=torch.int32, device=dev)  # ... of the current chunk
+            self.need = torch.zeros(1, dtype=torch.int64, device=dev)   # largest list count of the chunk
             self.idx = _image_index(self.fr, dev)
             # targets: the ground truth rendered at every pixel
             self.targets = torch.empty((req.n_views, req.res, req.res, 3), dtype=torch.float32, device=dev)
@@ -215,7 +231,7 @@ class _Fit:
             self.fr.set_blend_capacity(min(want, room))
             self.table_bytes = self.fr.blend_capacity * L.BLEND_BYTES_PER_PAIR
             self.beta.copy_(torch.tensor(prob.beta_init, device=dev))
-        self.done_event: torch.cuda.Event | None = None
+            self.snapshot = self.beta.clone()   # parameters at the start of the current chunk
 
     def _render_all(self, out: torch.Tensor):
         L.lmrs_project(self.fr, stream=self.stream)
@@ -228,7 +244,8 @@ class _Fit:
 
     def _iterate(self):
         L.lmrs_lm_iterate(self.fr, self.targets, self.params(), self.ws, report=self.rep, stream=self.stream)
-        self.fail.bitwise_or_(self.rep[L.REP["status"]:L.REP["status"] + 1].to(torch.int32))
+        self.chunk_fail.bitwise_or_(self.rep[L.REP["status"]:L.REP["status"] + 1].to(torch.int32))
+        torch.maximum(self.need, self.fr.n_instances, out=self.need)
 
     def step(self):
         """Enqueue one LM iteration on the fit's stream (never waits on the host)."""
@@ -246,12 +263,54 @@ class _Fit:
                     self.graphs[warm] = g
                 g.replay()
             self.it += 1
-            if self.it == req.lm_iters:
-                self.done_event = torch.cuda.Event()
-                self.done_event.record(self.stream)
 
-    def finished(self) -> bool:
-        return self.done_event is not None and self.done_event.query()
+    def _enqueue_chunk(self):
+        with torch.cuda.stream(self.stream):
+            self.snapshot.copy_(self.beta)
+            self.chunk_fail.zero_()
+            self.need.zero_()
+            self.chunk_start = self.it
+            end = min(self.it + CHUNK_ITERS, self.req.lm_iters)
+            while self.it < end:
+                self.step()
+            self.chunk_event = torch.cuda.Event()
+            self.chunk_event.record(self.stream)
+
+    def _grow(self, needed: int):
+        """Id buffer for `needed` list entries (with the binding's margin) and a
+        workspace to match; the graphs hold the old buffers and are dropped."""
+        old = 4 * self.fr.capacity + self.ws.numel()
+        self.graphs.clear()
+        with torch.cuda.stream(self.stream):
+            self.fr.grow_ids(needed)
+            nbytes = max(L.workspace_bytes(L.OP_BIN, self.fr), L.workspace_bytes(self.ws_op, self.fr))
+            if nbytes > self.ws.numel():
+                self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
+        self.grown_bytes += 4 * self.fr.capacity + self.ws.numel() - old
+        self.regrowths += 1
+
+    def poll(self) -> bool:
+        """Advance the fit without waiting: enqueue its next chunk when the last
+        one has run (again, after growing the lists, if it overflowed them).
+        True once every iteration has run."""
+        if self.chunk_event is not None:
+            if not self.chunk_event.query():
+                return False
+            with torch.cuda.stream(self.stream):   # the chunk has run: these reads do not wait
+                bits = int(self.chunk_fail.item())
+                need = int(self.need.item())
+            if bits & L.FAIL_CAPACITY and self.regrowths < MAX_REGROWTHS:
+                self._grow(need)
+                with torch.cuda.stream(self.stream):
+                    self.beta.copy_(self.snapshot)
+                self.it = self.chunk_start
+            else:
+                with torch.cuda.stream(self.stream):
+                    self.fail.bitwise_or_(self.chunk_fail)
+                if self.it >= self.req.lm_iters:
+                    return True
+        self._enqueue_chunk()
+        return False
 
     def status(self) -> str:
         bits = int(self.fail.item())
@@ -283,6 +342,7 @@ class Server:
     _results: dict = field(default_factory=dict)
     log: list = field(default_factory=list)
     table_bytes: dict = field(default_factory=dict)   # blend-table bytes of each admitted fit
+    regrowths: dict = field(default_factory=dict)     # list-buffer regrowths of each retired fit
     progress: object = None        # optional callable(str), called as each fit retires
 
     def submit(self, req: FitRequest, problem: Problem | None = None) -> int:
@@ -341,18 +401,18 @@ class Server:
                 if pending:
                     time.sleep(max(0.0, min(0.01, pending[0].req.arrival_t - (time.perf_counter() - t0))))
                 continue
-            # the whole iteration budget of each newly admitted fit is enqueued at once
-            for fit, _, _ in active:
-                while fit.it < fit.req.lm_iters:
-                    fit.step()
             still = []
             for fit, si, start in active:
-                if fit.it >= fit.req.lm_iters and fit.finished():
+                grown = fit.grown_bytes
+                done = fit.poll()
+                used += fit.grown_bytes - grown
+                if done:
                     beta, psnr = fit.finalize()
                     end = time.perf_counter() - t0
                     req = fit.req
                     self._results[req.id] = FitResult(beta, psnr, end - req.arrival_t, fit.status(), start, end)
-                    used -= fit.prob.footprint + fit.table_bytes
+                    self.regrowths[req.id] = fit.regrowths
+                    used -= fit.prob.footprint + fit.table_bytes + fit.grown_bytes
                     free_streams.append(si)
                     self.log.append(("retire", req.id, end, used))
                     if self.progress:

@@ -140,6 +140,31 @@ def test_deterministic_fits_same_bits_alone_and_in_the_mix():
         assert a.final_psnr == b.final_psnr
 
 
+def test_list_overflow_is_regrown_and_replayed():
+    """A fit whose Gaussians grow past the list bound taken at admission (request
+    68 of the seeded stream: 2,355 Gaussians, 11 views of 800x800) overflows its
+    id buffer mid-fit; the server grows the buffer, restores the parameters of
+    the chunk's start and runs the chunk again. With deterministic accumulation
+    the served fit then ends with the sequential solver's parameters, bit for
+    bit (the sequential solver grows the buffer inside each LM step)."""
+    S = serving()
+    from paper_2504_12905_amd import synth
+    d = synth.request_stream(256, 20.0, seed=0)[68]
+    req = S.FitRequest.from_stream(d)
+    req.arrival_t, req.deterministic = 0.0, True
+    prob = S.make_problem(req)
+    alone = S.run_sequential([prob])[req.id]
+    srv = S.Server(hbm_budget_bytes=64 << 30, max_slots=2)
+    srv.submit(req, prob)
+    got = srv.run_until_idle()[req.id]
+    log(f"  request 68 (n={req.n}, {req.n_views} views {req.res}^2): regrowths {srv.regrowths[req.id]}, "
+        f"status {got.status}, PSNR {alone.final_psnr:.4f} / {got.final_psnr:.4f} dB, identical "
+        f"{np.array_equal(alone.beta, got.beta)}")
+    assert srv.regrowths[req.id] >= 1
+    assert alone.status == got.status == "ok"
+    assert np.array_equal(alone.beta, got.beta) and alone.final_psnr == got.final_psnr
+
+
 def test_failed_fit_is_isolated():
     """A request whose initial colours hold NaN retires with status "numeric"
     and its parameters untouched, while the three fits served beside it end
