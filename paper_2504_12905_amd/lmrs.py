@@ -184,9 +184,11 @@ class Frame:
 
     def _alloc_blend(self, cap: int):
         dev = self.beta.device
+        t = self.tensors
+        for key in ("blend_k", "blend_m", "blend_run"):   # the old table goes before the new one comes
+            t.pop(key, None)
         self.blend_capacity = max(int(cap), 0)
         m = max(self.blend_capacity, 1)
-        t = self.tensors
         t["blend_k"] = torch.empty((2, m, 4), dtype=torch.float32, device=dev)   # two orders of the pairs
         t["blend_m"] = torch.empty((2, m), dtype=torch.int32, device=dev)
         t["blend_run"] = torch.empty(m, dtype=torch.int32, device=dev)

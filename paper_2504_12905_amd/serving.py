@@ -226,9 +226,10 @@ class _Fit:
             self.targets = torch.empty((req.n_views, req.res, req.res, 3), dtype=torch.float32, device=dev)
             self._render_all(self.targets)
             # the blend table, sized from the target render's pairs
-            want = int(self.fr.blend_pairs() * TABLE_MARGIN) + 4096
+            self.table_want = min(int(self.fr.blend_pairs() * TABLE_MARGIN) + 4096,
+                                  TABLE_CAP_BYTES // L.BLEND_BYTES_PER_PAIR)
             room = max(min(table_bytes_max, TABLE_CAP_BYTES), 0) // L.BLEND_BYTES_PER_PAIR
-            self.fr.set_blend_capacity(min(want, room))
+            self.fr.set_blend_capacity(min(self.table_want, room))
             self.table_bytes = self.fr.blend_capacity * L.BLEND_BYTES_PER_PAIR
             self.beta.copy_(torch.tensor(prob.beta_init, device=dev))
             self.snapshot = self.beta.clone()   # parameters at the start of the current chunk
@@ -263,6 +264,30 @@ class _Fit:
                     self.graphs[warm] = g
                 g.replay()
             self.it += 1
+
+    def table_short(self) -> int:
+        """Bytes the blend table lacks against its wanted size (the budget was short at admission)."""
+        return max(self.table_want - self.fr.blend_capacity, 0) * L.BLEND_BYTES_PER_PAIR
+
+    def grow_table(self) -> bool:
+        """The wanted blend table, before the first iteration; False (and the
+        table as it was) when the device cannot hold it after all."""
+        have = self.fr.blend_capacity
+        try:
+            with torch.cuda.stream(self.stream):
+                self.fr.set_blend_capacity(self.table_want)
+        except torch.OutOfMemoryError:
+            torch.cuda.empty_cache()   # cached blocks of retired fits
+            try:
+                with torch.cuda.stream(self.stream):
+                    self.fr.set_blend_capacity(self.table_want)
+            except torch.OutOfMemoryError:
+                with torch.cuda.stream(self.stream):
+                    self.fr.set_blend_capacity(have)
+                self.table_want = have
+                return False
+        self.table_bytes = self.fr.blend_capacity * L.BLEND_BYTES_PER_PAIR
+        return True
 
     def _enqueue_chunk(self):
         with torch.cuda.stream(self.stream):
@@ -402,7 +427,24 @@ class Server:
                     time.sleep(max(0.0, min(0.01, pending[0].req.arrival_t - (time.perf_counter() - t0))))
                 continue
             still = []
+            running = sum(1 for fit, _, _ in active if fit.chunk_event is not None)
             for fit, si, start in active:
+                if fit.chunk_event is None and fit.table_short():
+                    # a fit admitted while the budget was short of its blend table waits
+                    # for the room (its GN products would otherwise walk the lists where
+                    # alone they take the table, a different summation order), unless
+                    # nothing is running to free memory
+                    short = fit.table_short()
+                    if used + short <= self.hbm_budget_bytes:
+                        before = fit.table_bytes
+                        fit.grow_table()
+                        used += fit.table_bytes - before
+                        self.table_bytes[fit.req.id] = fit.table_bytes
+                    elif running:
+                        still.append((fit, si, start))
+                        continue
+                if fit.chunk_event is None:
+                    running += 1
                 grown = fit.grown_bytes
                 done = fit.poll()
                 used += fit.grown_bytes - grown
